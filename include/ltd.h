@@ -1,0 +1,235 @@
+/*
+ * ltd.h — LAPW+LO real-time TDDFT hot path on one AMD Instinct MI355X (gfx950).
+ *
+ * The library applies the velocity-gauge Hamiltonian and the overlap of an
+ * LAPW+LO basis to blocks of coefficient vectors without assembling either
+ * matrix, projects them onto an auxiliary subspace, and propagates the subspace
+ * coefficients (Pela & Draxl, "Speeding up all-electron real-time TDDFT
+ * demonstrated by the exciting package": Sec. 2.1 Eqs. (9)-(10), Sec. 2.2
+ * Eqs. (11)-(14), Sec. 2.3 Eqs. (15)-(19), App. A Eqs. (A.1)-(A.7)).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless marked (host).
+ *  - Complex numbers are complex128: interleaved (re, im) float64 pairs, 16-byte
+ *    aligned (the storage of a torch.complex128 tensor).
+ *  - Matrices are column-major with an explicit leading dimension (in
+ *    elements).  A contiguous C-order array of shape (cols, rows) is the
+ *    column-major rows x cols matrix with leading dimension rows.
+ *  - Real-space grids hold N = N1*N2*N3 float64 values, x fastest:
+ *    index j1 + N1*(j2 + N2*j3).
+ *  - A basis vector of k-point k has N_basis(k) = n_g[k] + N_LO rows: the
+ *    plane-wave (LAPW) block first, then the local orbitals of atom 0, atom 1, ...
+ *  - `stream` is a hipStream_t passed as void* (NULL: the null stream).
+ *    Every call only enqueues work on `stream` (except where it says it
+ *    synchronises) and returns before the work ends.
+ *  - Status: 0 ok; negative: the arguments were rejected on the host and
+ *    nothing was enqueued; positive: a HIP call failed, or the device latched
+ *    a failure (read it with ltd_sync_status).  No exception crosses the ABI
+ *    and nothing is printed.
+ *  - Ownership: the caller owns every buffer, including the workspace.  The
+ *    library keeps the device pointers of the system description and of the
+ *    bound auxiliary basis, which must stay valid while the system is used.
+ *  - Threading: one system is used by one host thread and one stream at a time.
+ */
+#ifndef LTD_H
+#define LTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ltd_system ltd_system;
+typedef int ltd_status;
+
+enum {
+  LTD_OK = 0,
+  LTD_EINVAL = -1,      /* null pointer, bad enum, non-finite scalar */
+  LTD_ESHAPE = -2,      /* sizes or leading dimensions inconsistent */
+  LTD_EALIGN = -3,      /* complex pointer not 16-byte aligned */
+  LTD_ESTATE = -4,      /* call out of order (no workspace / no subspace bound) */
+  LTD_EWORKSPACE = -5,  /* bound workspace smaller than ltd_create asked for */
+  LTD_EUNSUPPORTED = -6,/* grid length or mode this build does not handle */
+  LTD_EHIP = 1,         /* a HIP runtime call failed */
+  LTD_ENOTSPD = 2,      /* device: S_sub Cholesky met a pivot <= 0 */
+  LTD_ENONFINITE = 3,   /* device: non-finite current or energy */
+  LTD_ESPECTRUM = 4     /* device: subspace spectrum left the propagator's interval */
+};
+
+typedef enum { LTD_FP64 = 0, LTD_FP32_RESID = 1, LTD_BF16X3_RESID = 2 } ltd_precision;
+typedef enum { LTD_STEP_REBUILD = 0, LTD_STEP_AFFINE = 1 } ltd_step_mode;
+
+/* The system: one cell, one real-space grid, n_k k-points, n_atoms atoms.
+ * Muffin-tin channels of atom a: n_mt[a] (= n_rad (lmax+1)^2); local orbitals
+ * n_lo[a]; N_A = sum n_mt, N_LO = sum n_lo.  Sec. 2.1 Eqs. (6)-(9). */
+typedef struct {
+  int n_k;                 /* number of k-points, >= 1 */
+  const int *n_g;          /* (host) [n_k] plane waves per k-point */
+  const int32_t *g_int;    /* (host) [sum n_g][3] integer G triples, k-points concatenated;
+                              grid index of G is g mod (N1,N2,N3) and must be injective */
+  const double *gk_cart;   /* (host) [sum n_g][3] Cartesian G+k (bohr^-1) */
+  int grid[3];             /* N1, N2, N3 (each a product of 2, 3, 5; at most 192) */
+  const double *theta_r;   /* [N] step function: 1 interstitial, 0 in spheres (App. A, Eq. (A.2)) */
+  const double *v_r;       /* [N] reference Kohn-Sham potential (Ha) */
+  int n_atoms;
+  const int *n_mt;         /* (host) [n_atoms] */
+  const int *n_lo;         /* (host) [n_atoms] */
+  const void *amat;        /* per k: N_A x n_g[k] matching coefficients (ld N_A), k-points
+                              concatenated; rows = atom 0 channels, atom 1, ... */
+  const void *h;           /* per atom: s_a x s_a Hermitian block, s_a = n_mt[a]+n_lo[a], ld s_a,
+                              atoms concatenated: muffin-tin Hamiltonian (kinetic + potential) */
+  const void *o;           /* same layout: muffin-tin overlap block (positive definite) */
+  const void *pz;          /* same layout: muffin-tin momentum block, z component */
+  double omega;            /* cell volume (bohr^3) */
+  double c_light;          /* speed of light (a.u.) */
+  double occ;              /* occupation of every propagated state */
+  const double *k_weight;  /* (host) [n_k] k-point weights */
+  int n_aux;               /* auxiliary-subspace dimension N_aux (all k) */
+  int n_states;            /* propagated states N_states <= n_aux (all k) */
+  int max_cols;            /* most columns ever passed to ltd_apply_HS */
+} ltd_system_desc;
+
+/* Validates the description, copies its host arrays and plans every kernel;
+ * returns in *workspace_bytes the device workspace the caller must bind.
+ * precision: LTD_FP64, or a mixed mode for the per-step potential rebuild
+ * (LTD_FP32_RESID: FP32 rebuild of the potential difference on top of the FP64
+ * reference).  No device memory is allocated. */
+ltd_status ltd_create(const ltd_system_desc *desc, int precision, size_t *workspace_bytes,
+                      ltd_system **out);
+
+/* Binds a caller-allocated device workspace of at least the size ltd_create
+ * asked for, uploads the plan tables and clears the device status word.
+ * Synchronises `stream`. */
+ltd_status ltd_bind_workspace(ltd_system *sys, void *workspace, size_t bytes, void *stream);
+
+/* Frees the host-side state; the workspace stays the caller's. */
+ltd_status ltd_destroy(ltd_system *sys);
+
+const char *ltd_status_string(ltd_status status);
+
+/* Synchronises `stream`, returns the latched device status (LTD_OK if none)
+ * and clears it. */
+ltd_status ltd_sync_status(ltd_system *sys, void *stream);
+
+/* HC = H(t) C and SC = S C for the n columns of C at k-point k, with the
+ * velocity-gauge H(t) = H0 + (A_z/c) P_z + (A_z^2/2c^2) S (Sec. 2, Eq. (2)
+ * expanded as Eq. (15)); H0 = T + V.  The muffin-tin part goes through the
+ * matching coefficients and per-atom blocks (Eq. (19); App. A, Eqs.
+ * (A.4)-(A.6)), the interstitial part by FFT convolution with the step
+ * function (Sec. 2.3, second route; App. A, Eq. (A.7)).  a_vec (host) holds
+ * A(t) = (A_x, A_y, A_z); only A_z enters (the momentum block is z only).
+ * C, HC, SC: N_basis(k) x n, leading dimensions >= N_basis(k); outputs must
+ * not overlap C or each other.  n <= max_cols. */
+ltd_status ltd_apply_HS(ltd_system *sys, int k, const double a_vec[3], const void *C, int ldc,
+                        int n, void *HC, int ldhc, void *SC, int ldsc, void *stream);
+
+/* Binds the auxiliary basis Phi (N_basis(k) x n_aux, ld ldphi; caller-owned,
+ * must stay valid and unchanged while the system propagates k) and prepares
+ * the subspace (Sec. 2.2, Eq. (14); Sec. 2.3, Eqs. (15)-(16)): applies T, V,
+ * P_z and S to Phi, projects them (T_sub, V_sub, P_sub, S_sub, each made
+ * Hermitian), factors S_sub = L L^H, caches R = [A Phi_G; Phi_LO] and the
+ * plane-wave part of Phi on the real-space grid for the per-step rebuild, and
+ * computes the subspace spectrum.  Outputs, each optional (NULL skips):
+ * h0_sub, s_sub: n_aux x n_aux (ld n_aux); if C (N_basis x n_states, ld ldc)
+ * is given, theta = S_sub^{-1} Phi^H S C (n_aux x n_states, ld n_aux).
+ * n_aux must equal the description's.  Synchronises `stream` (the host reads
+ * back the spectrum bounds).  A non-positive-definite S_sub returns
+ * LTD_ENOTSPD. */
+ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldphi, int n_aux,
+                                void *h0_sub, void *s_sub, const void *C, int ldc, int n_states,
+                                void *theta, void *stream);
+
+/* Rotates the block X (N_basis(k) x n_aux, ld ldx, overwritten) into the
+ * Rayleigh-Ritz vectors of (H0, S) over span(X): X <- X W with W^H (X^H S X) W
+ * = I and W^H (X^H H0 X) W = diag(eps), eps ascending, written to eps (device,
+ * n_aux doubles) if non-NULL.  A stand-in for the ground-state orbitals that
+ * form the auxiliary basis (Sec. 2.2, Eq. (11)).  Synchronises `stream`. */
+ltd_status ltd_ritz_basis(ltd_system *sys, int k, void *x, int ldx, double *eps, void *stream);
+
+/* Host read-out of the bound subspace of k: extreme eigenvalues of (H0_sub,
+ * S_sub) and the critical time step f/(eps_max - eps_min) with f = 0.2
+ * (Sec. 3.1, Eq. (20)).  Any output may be NULL. */
+ltd_status ltd_subspace_info(ltd_system *sys, int k, double *eps_min, double *eps_max,
+                             double *dt_cr);
+
+typedef struct {
+  int mode;               /* LTD_STEP_REBUILD (the potential part is rebuilt from the
+                             potential handed in for the step) or LTD_STEP_AFFINE */
+  double dt;              /* time step (a.u.), may be negative */
+  const double *a_t;      /* [n_steps+1] A_z(t_n), t_n = n dt */
+  const double *a_mid;    /* [n_steps]   A_z(t_n + dt/2) */
+  int *step;              /* device int n: the step taken is n -> n+1; advanced on the device */
+  const double *v_r_t;    /* REBUILD: [N] potential for this step (NULL: the reference) */
+  const void *h_t;        /* REBUILD: per-atom Hamiltonian blocks for this step (NULL: reference) */
+  void *theta;            /* per k: n_aux x n_states (ld n_aux), k-points concatenated; in/out */
+  void *c_out;            /* optional: per k the map-back C = Phi theta, N_basis(k) x n_states
+                             (ld N_basis(k)), k-points concatenated; NULL skips */
+  double *j_out;          /* [n_steps+1] k-weighted current along z at t_n */
+  double *e_out;          /* [n_steps+1] energy at t_n */
+  double *dmu_out;        /* [n_steps+1] dipole change along z at t_n */
+} ltd_step_args;
+
+/* One time step n -> n+1 for every k-point (Sec. 2.2, Eqs. (12)-(13); Sec. 2.3
+ * text after Eq. (16): only the potential part is rebuilt): V_sub(t) =
+ * sum_a R_a^H h_a(t) R_a + Phi_G^H F[Theta V(t) F^{-1}(Phi_G)] (Eqs. (17)-(19),
+ * REBUILD) or the bound reference (AFFINE); H_sub = T_sub + V_sub + (A/c) P_sub
+ * + (A^2/2c^2) S_sub at A = a_mid[n] (Eq. (15)); theta <- exp(-i dt
+ * S_sub^{-1} H_sub) theta (exponential midpoint rule, FP64 Chebyshev series);
+ * optional map-back C = Phi theta (Eq. (12)); then at t_{n+1}: the current
+ * J = -(f/Omega) sum_k w_k sum_j Re theta_j^H (P_sub + (A/c) S_sub) theta_j,
+ * the energy, and the dipole change delta mu = Omega int J_ind dt (Eq. (4),
+ * trapezoid rule).  On the first step (n = 0) entry 0 of the series is
+ * written too.  Every k-point needs a bound subspace. */
+ltd_status ltd_propagate_step(ltd_system *sys, const ltd_step_args *args, void *stream);
+
+/* n_steps calls of ltd_propagate_step, recorded once into a hipGraph and
+ * replayed (the device step counter selects the pulse samples).  REBUILD
+ * re-reads v_r_t / h_t every step. */
+ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *args, int n_steps, void *stream);
+
+typedef struct {
+  const ltd_step_args *fwd; /* the step description (mode, dt, pulse, potential);
+                               fwd->theta holds theta_n; fwd->step is not used */
+  int n;                    /* (host) the step n -> n+1 to differentiate, 0 <= n < N;
+                               with terminal = 1, the last time point n = N */
+  int terminal;             /* 1: initialise at t_N: mu_N = dt w_N g_N, no propagator term */
+  int n_steps;              /* N, the length of the propagation (trapezoid weights) */
+  const void *mu_next;      /* per k: mu_{n+1}, n_aux x n_states (ld n_aux), concatenated */
+  void *mu_out;             /* per k: mu_n = U_n^H mu_{n+1} + dt w_n g_n (may equal mu_next) */
+  double *dl_da_mid;        /* [N]   entry n: dL/dA(t_n + dt/2) */
+  double *dl_da_t;          /* [N+1] entry n: explicit dL/dA(t_n) */
+} ltd_adjoint_args;
+
+/* One step of the discrete adjoint of ltd_propagate_step for the loss
+ * L = dt sum_n w_n (J_n - J_0) (trapezoid weights; L = delta mu(T)/Omega by
+ * Eq. (4)): mu_n = U_n^H mu_{n+1} + dt w_n g_n with g_n = -(2f/Omega) w_k
+ * (P_sub + (A_n/c) S_sub) theta_n, dL/dA(t_n+dt/2) = Re <mu_{n+1}, (dU_n/dA)
+ * theta_n> (derivative of the same Chebyshev series), and the explicit
+ * dL/dA(t_n) = dt w_n dJ_n/dA_n (minus T dJ_0/dA_0 at n = 0).  The caller
+ * recomputes theta_n (checkpointing).  Does not advance the step counter. */
+ltd_status ltd_propagate_step_adjoint(ltd_system *sys, const ltd_adjoint_args *args,
+                                      void *stream);
+
+/* Piecewise-linear pulse on n_knots uniform knots over [0, t_end] (both ends
+ * included): a_t[n] = A(n dt), n = 0..n_steps, a_mid[n] = A((n+1/2) dt).
+ * knots: [n_knots]. */
+ltd_status ltd_knot_samples(const double *knots, int n_knots, double t_end, double dt,
+                            int n_steps, double *a_t, double *a_mid, void *stream);
+
+/* Chain rule of ltd_knot_samples: dl_dq[k] = sum_n dl_da_t[n] phi_k(t_n) +
+ * sum_n dl_da_mid[n] phi_k(t_n + dt/2), phi_k the hat functions. */
+ltd_status ltd_knot_gradient(const double *dl_da_t, const double *dl_da_mid, int n_steps,
+                             double dt, int n_knots, double t_end, double *dl_dq, void *stream);
+
+/* Coefficients of the Chebyshev series exp(-i tau x) = sum_k c_k T_k(x) on
+ * [-1, 1]: c_k = (2 - delta_k0) (-i)^k J_k(tau) (host; Bessel functions by
+ * Miller's backward recurrence).  Writes kmax+1 complex values (interleaved
+ * re, im) to coef (host) and returns the truncation degree in *degree. */
+ltd_status ltd_chebyshev_coefficients(double tau, int kmax, double *coef, int *degree);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LTD_H */

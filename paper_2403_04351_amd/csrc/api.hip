@@ -1,0 +1,1119 @@
+// C-ABI of the ltd library: validation, workspace planning and the
+// orchestration of the kernels for the LAPW+LO operator applies, the subspace
+// set-up and the time step (Pela & Draxl, Secs. 2.1-2.3, App. A).
+#include "ltd.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "common.h"
+#include "subspace.h"
+
+using namespace ltd;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr long long PART_TILES = 2048;  // split-K partial budget (64x64 complex tiles)
+
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+struct Arena {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += up(bytes);
+    return o;
+  }
+};
+
+// One entry of the K2 (block-diagonal muffin-tin) problem tables.
+struct K2Table {
+  std::vector<ZProb> p1, p2;  // first pass (beta = 0), second pass (beta = 1)
+  int tiles1 = 0, tiles2 = 0;
+  size_t off1 = 0, off2 = 0;  // device offsets of the tables in the workspace
+  bool built = false;
+};
+
+struct KHost {
+  int n_g, n_basis, k_ext;
+  size_t g_off;            // first G of this k in the concatenated arrays
+  size_t amat_off;         // element offset of A_k
+  std::vector<int> plane_ptr, pts_g, pts_xy;
+  // workspace offsets
+  size_t o_gk, o_pptr, o_ptsg, o_ptsxy;
+  size_t o_subs;           // Tsub, Vsub, Psub, Ssub (4 n^2, Phi basis)
+  size_t o_tilde;          // Tt, Vt_ref, Pt (3 n^2), then H0t (n^2)
+  size_t o_L, o_Linv, o_vstep, o_work;
+  size_t o_phit, o_yext, o_cache;
+  // bound subspace
+  bool bound = false;
+  const double2 *phi = nullptr;
+  int ldphi = 0;
+  double lam_min = 0, lam_max = 0;
+};
+
+}  // namespace
+
+struct ltd_system {
+  // description
+  int n_k = 0;
+  std::vector<KHost> kh;
+  std::vector<int32_t> g_int;
+  std::vector<double> gk;
+  int n1 = 0, n2 = 0, n3 = 0;
+  long long ngrid = 0;
+  const double *theta = nullptr, *v_r = nullptr;
+  int n_atoms = 0;
+  std::vector<int> n_mt, n_lo, a_off, l_off, s_off;
+  int n_a = 0, n_lo_tot = 0, n_loc = 0;
+  long long blk_elems = 0;  // sum s_a^2
+  const double2 *amat = nullptr, *h = nullptr, *o = nullptr, *pz = nullptr;
+  double omega = 0, c_light = 0, occ = 0;
+  std::vector<double> kw;
+  int n_aux = 0, n_states = 0, max_cols = 0, precision = 0;
+  int nb_max = 0;
+  // grid plan
+  Grid grid{};
+  int chunk = 0;        // columns per apply pass
+  bool h_in_lds = false;
+  // workspace
+  char *ws = nullptr;
+  size_t ws_need = 0, ws_bound = 0;
+  size_t o_tw1, o_tw2, o_tw3, o_thv, o_thv_step, o_status, o_part, o_partials;
+  size_t o_slab_in, o_slab_out, o_W, o_Y, o_heff, o_tvps, o_proj, o_tmp3, o_eigA, o_eigV, o_eigw;
+  size_t o_stepslab, o_subdev, o_theta_sc, o_k6;
+  K2Table k2_hs, k2_tvps, k2_step;
+  size_t o_k2_hs1, o_k2_hs2, o_k2_tv1, o_k2_tv2, o_k2_st1, o_k2_st2;
+  std::vector<ZProb> vstep_tab;
+  int vstep_tiles = 0;
+  size_t o_vstep_tab;
+  const void *k2_step_h = nullptr;  // blocks the step table points at
+  // subspace / step state
+  std::vector<SubDev> sd;
+  double cheb_dt = NAN;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  ltd_step_args gargs{};
+  bool gvalid = false;
+
+  template <class T>
+  T *at(size_t off) const {
+    return reinterpret_cast<T *>(ws + off);
+  }
+};
+
+namespace {
+
+#define LTD_HIP(x)                      \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return LTD_EHIP; \
+  } while (0)
+
+#define LTD_TRY(x)                  \
+  do {                              \
+    ltd_status s_ = (x);            \
+    if (s_ != LTD_OK) return s_;    \
+  } while (0)
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------------------
+// Bessel functions J_0..J_nmax(x) by Miller's backward recurrence, normalised
+// with J_0 + 2 sum_k J_2k = 1.
+// ---------------------------------------------------------------------------
+void bessel_j(double x, int nmax, std::vector<double> &out) {
+  out.assign(nmax + 1, 0.0);
+  if (x == 0.0) {
+    out[0] = 1.0;
+    return;
+  }
+  const double ax = std::fabs(x);
+  const int top = std::max(nmax, (int)std::ceil(ax));
+  int m = top + 30 + (int)std::sqrt(40.0 * top);
+  if (m % 2) ++m;
+  std::vector<double> t(m + 2, 0.0);
+  t[m] = 1e-30;
+  for (int k = m; k >= 1; --k) {
+    t[k - 1] = (2.0 * k / ax) * t[k] - t[k + 1];
+    if (std::fabs(t[k - 1]) > 1e250)
+      for (int q = k - 1; q <= m; ++q) t[q] *= 1e-250;
+  }
+  double norm = t[0];
+  for (int k = 2; k <= m; k += 2) norm += 2.0 * t[k];
+  for (int k = 0; k <= nmax; ++k) {
+    double v = t[k] / norm;
+    if (x < 0 && (k % 2)) v = -v;  // J_k(-x) = (-1)^k J_k(x)
+    out[k] = v;
+  }
+}
+
+// exp(-i tau x) = sum_k c_k T_k(x); returns the degree (or -1 if kmax is too small).
+int cheb_coef(double tau, int kmax, std::vector<double2> &c) {
+  std::vector<double> j;
+  bessel_j(tau, kmax + 2, j);
+  c.assign(kmax + 1, make_double2(0.0, 0.0));
+  int deg = -1;
+  for (int k = 0; k <= kmax; ++k) {
+    const double a = (k == 0 ? 1.0 : 2.0) * j[k];
+    // (-i)^k
+    const int r = k % 4;
+    c[k] = (r == 0) ? make_double2(a, 0.0) : (r == 1) ? make_double2(0.0, -a) : (r == 2) ? make_double2(-a, 0.0)
+                                                                                      : make_double2(0.0, a);
+  }
+  for (int k = 1; k <= kmax; ++k) {
+    if (k > std::fabs(tau) && std::fabs(j[k]) + std::fabs(j[k + 1]) + std::fabs(j[k + 2]) < 1e-18) {
+      deg = k;
+      break;
+    }
+  }
+  return deg;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM helpers
+// ---------------------------------------------------------------------------
+ZProb zp(int m, int n, int k, const double2 *A, int lda, const double2 *B, int ldb, double2 *C, int ldc,
+         double2 alpha = make_double2(1.0, 0.0), double2 beta = make_double2(0.0, 0.0), int batch = 1,
+         long long sA = 0, long long sB = 0, long long sC = 0) {
+  ZProb p{};
+  p.A = A;
+  p.B = B;
+  p.C = C;
+  p.lda = lda;
+  p.ldb = ldb;
+  p.ldc = ldc;
+  p.m = m;
+  p.n = n;
+  p.k = k;
+  p.batch = batch;
+  p.sA = sA;
+  p.sB = sB;
+  p.sC = sC;
+  p.alpha = alpha;
+  p.beta = beta;
+  return p;
+}
+
+ltd_status gemm(ltd_system *sys, int opa, int opb, std::vector<ZProb> probs, hipStream_t s) {
+  for (size_t i0 = 0; i0 < probs.size(); i0 += GEMM_MAXP) {
+    ZBatch b{};
+    b.nprob = (int)std::min<size_t>(GEMM_MAXP, probs.size() - i0);
+    for (int i = 0; i < b.nprob; ++i) b.p[i] = probs[i0 + i];
+    gemm_plan(b.p, b.nprob, &b.total_tiles, 512, PART_TILES);
+    LTD_HIP(gemm_launch(opa, opb, b, sys->at<double2>(sys->o_partials), s));
+  }
+  return LTD_OK;
+}
+
+ltd_status gemm1(ltd_system *sys, int opa, int opb, const ZProb &p, hipStream_t s) {
+  return gemm(sys, opa, opb, std::vector<ZProb>{p}, s);
+}
+
+// K2 tables: Y_x = blockdiag(x_a) W for every atom a and matrix x in `xs`.
+void build_k2(const ltd_system *sys, const std::vector<const double2 *> &xs, const double2 *W, int ldw,
+              const std::vector<double2 *> &Ys, int ldy, int cols, std::vector<ZProb> &p1, std::vector<ZProb> &p2) {
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  for (size_t xi = 0; xi < xs.size(); ++xi) {
+    for (int a = 0; a < sys->n_atoms; ++a) {
+      const int m = sys->n_mt[a], l = sys->n_lo[a], s = m + l;
+      const double2 *x = xs[xi] + sys->s_off[a];
+      const double2 *wt = W + sys->a_off[a];
+      const double2 *wl = W + sys->n_a + sys->l_off[a];
+      double2 *yt = Ys[xi] + sys->a_off[a];
+      double2 *yl = Ys[xi] + sys->n_a + sys->l_off[a];
+      p1.push_back(zp(m, cols, m, x, s, wt, ldw, yt, ldy, one, zero));
+      if (l > 0) {
+        p1.push_back(zp(l, cols, m, x + m, s, wt, ldw, yl, ldy, one, zero));
+        p2.push_back(zp(m, cols, l, x + (long long)m * s, s, wl, ldw, yt, ldy, one, one));
+        p2.push_back(zp(l, cols, l, x + m + (long long)m * s, s, wl, ldw, yl, ldy, one, one));
+      }
+    }
+  }
+}
+
+ltd_status upload_k2(ltd_system *sys, std::vector<ZProb> &p1, std::vector<ZProb> &p2, K2Table &t, size_t off1,
+                     size_t off2, size_t cap) {
+  int tt = 0;
+  gemm_plan(p1.data(), (int)p1.size(), &tt, 1 << 30, 0);
+  t.tiles1 = tt;
+  tt = 0;
+  if (!p2.empty()) gemm_plan(p2.data(), (int)p2.size(), &tt, 1 << 30, 0);
+  t.tiles2 = tt;
+  if (p1.size() * sizeof(ZProb) > cap || p2.size() * sizeof(ZProb) > cap) return LTD_EUNSUPPORTED;
+  t.p1 = p1;
+  t.p2 = p2;
+  t.off1 = off1;
+  t.off2 = off2;
+  LTD_HIP(hipMemcpy(sys->ws + off1, p1.data(), p1.size() * sizeof(ZProb), hipMemcpyHostToDevice));
+  if (!p2.empty()) LTD_HIP(hipMemcpy(sys->ws + off2, p2.data(), p2.size() * sizeof(ZProb), hipMemcpyHostToDevice));
+  t.built = true;
+  return LTD_OK;
+}
+
+ltd_status run_k2(ltd_system *sys, const K2Table &t, int cols, hipStream_t s) {
+  if (!t.p1.empty())
+    LTD_HIP(gemm_launch_table(OP_N, OP_N, sys->at<ZProb>(t.off1), t.p1.data(), (int)t.p1.size(), t.tiles1,
+                              sys->at<double2>(sys->o_partials), cols, s));
+  if (!t.p2.empty())
+    LTD_HIP(gemm_launch_table(OP_N, OP_N, sys->at<ZProb>(t.off2), t.p2.data(), (int)t.p2.size(), t.tiles2,
+                              sys->at<double2>(sys->o_partials), cols, s));
+  return LTD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FFT argument helpers
+// ---------------------------------------------------------------------------
+KSphere sphere_of(const ltd_system *sys, int k) {
+  const KHost &h = sys->kh[k];
+  KSphere sp{};
+  sp.gk = sys->at<double>(h.o_gk);
+  sp.plane_ptr = sys->at<int>(h.o_pptr);
+  sp.pts_g = sys->at<int>(h.o_ptsg);
+  sp.pts_xy = sys->at<int>(h.o_ptsxy);
+  sp.n_g = h.n_g;
+  return sp;
+}
+
+Grid grid_of(const ltd_system *sys) {
+  Grid g = sys->grid;
+  g.tw1 = sys->at<double2>(sys->o_tw1);
+  g.tw2 = sys->at<double2>(sys->o_tw2);
+  g.tw3 = sys->at<double2>(sys->o_tw3);
+  g.theta = sys->theta;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// Operator apply on a column chunk of one k-point.
+//   mode FFT_MODE_HS:   out[0] = H(A) C, out[1] = S C
+//   mode FFT_MODE_TVPS: out[0..3] = T C, V C, P_z C, S C
+// ---------------------------------------------------------------------------
+ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const double2 *C, int ldc, int cols,
+                       double2 *const out[4], const int ldo[4], hipStream_t s) {
+  if (cols <= 0) return LTD_OK;
+  const KHost &kh = sys->kh[k];
+  const Grid g = grid_of(sys);
+  const double al = a_z / sys->c_light, be = a_z * a_z / (2.0 * sys->c_light * sys->c_light);
+  // interstitial
+  FftKArgs ka{};
+  ka.sph[0] = sphere_of(sys, k);
+  ka.in[0].c = C;
+  ka.in[0].ldc = ldc;
+  ka.slab_out[0] = sys->at<double2>(sys->o_slab_in);
+  LTD_HIP(fft_inverse_planes(g, ka, 1, cols, 4, s));
+  ka.slab_in[0] = sys->at<double2>(sys->o_slab_in);
+  ka.slab_out[0] = sys->at<double2>(sys->o_slab_out);
+  LTD_HIP(fft_lines(g, ka, 1, cols, FFT_MODE_HS, sys->at<double>(sys->o_thv), s));
+  ka.slab_in[0] = sys->at<double2>(sys->o_slab_out);
+  FwdOut fo{};
+  fo.o0 = out[0];
+  fo.o1 = out[1];
+  fo.ld0 = ldo[0];
+  fo.ld1 = ldo[1];
+  if (mode == FFT_MODE_TVPS) {
+    fo.o2 = out[2];
+    fo.o3 = out[3];
+    fo.ld2 = ldo[2];
+    fo.ld3 = ldo[3];
+  }
+  ka.out[0] = fo;
+  LTD_HIP(fft_forward_planes(g, ka, 1, cols, mode, al, be, s));
+  // muffin-tin chain: W = [A C_G; C_LO]
+  double2 *W = sys->at<double2>(sys->o_W);
+  double2 *Y = sys->at<double2>(sys->o_Y);
+  const int nl = sys->n_loc, chunk = sys->chunk;
+  const double2 *Ak = sys->amat + kh.amat_off;
+  LTD_TRY(gemm1(sys, OP_N, OP_N, zp(sys->n_a, cols, kh.n_g, Ak, sys->n_a, C, ldc, W, nl), s));
+  if (sys->n_lo_tot > 0) LTD_HIP(launch_copy_rows(W + sys->n_a, nl, C + kh.n_g, ldc, sys->n_lo_tot, cols, false, s));
+  const double2 one = make_double2(1.0, 0.0);
+  std::vector<ZProb> k3;
+  if (mode == FFT_MODE_HS) {
+    LTD_HIP(launch_heff(sys->at<double2>(sys->o_heff), sys->h, sys->pz, sys->o, al, be, sys->blk_elems, s));
+    LTD_TRY(run_k2(sys, sys->k2_hs, cols, s));
+    // Y layout: [Y_heff | Y_o], each n_loc x chunk
+    for (int x = 0; x < 2; ++x) {
+      double2 *Yx = Y + (long long)x * nl * chunk;
+      k3.push_back(zp(kh.n_g, cols, sys->n_a, Ak, sys->n_a, Yx, nl, out[x], ldo[x], one, one));
+    }
+    LTD_TRY(gemm(sys, OP_C, OP_N, k3, s));
+    for (int x = 0; x < 2; ++x)
+      if (sys->n_lo_tot > 0)
+        LTD_HIP(launch_copy_rows(out[x] + kh.n_g, ldo[x], Y + (long long)x * nl * chunk + sys->n_a, nl,
+                                 sys->n_lo_tot, cols, false, s));
+  } else {
+    LTD_TRY(run_k2(sys, sys->k2_tvps, cols, s));
+    // Y layout: [Y_h | Y_p | Y_o] -> V, P, S
+    for (int x = 0; x < 3; ++x) {
+      double2 *Yx = Y + (long long)x * nl * chunk;
+      k3.push_back(zp(kh.n_g, cols, sys->n_a, Ak, sys->n_a, Yx, nl, out[x + 1], ldo[x + 1], one, one));
+    }
+    LTD_TRY(gemm(sys, OP_C, OP_N, k3, s));
+    if (sys->n_lo_tot > 0) {
+      LTD_HIP(launch_copy_rows(out[0] + kh.n_g, ldo[0], nullptr, 0, sys->n_lo_tot, cols, true, s));
+      for (int x = 0; x < 3; ++x)
+        LTD_HIP(launch_copy_rows(out[x + 1] + kh.n_g, ldo[x + 1], Y + (long long)x * nl * chunk + sys->n_a, nl,
+                                 sys->n_lo_tot, cols, false, s));
+    }
+  }
+  return LTD_OK;
+}
+
+ltd_status apply_cols(ltd_system *sys, int k, int mode, double a_z, const double2 *C, int ldc, int n,
+                      double2 *const out[4], const int ldo[4], hipStream_t s) {
+  for (int j0 = 0; j0 < n; j0 += sys->chunk) {
+    const int cols = std::min(sys->chunk, n - j0);
+    double2 *o[4];
+    for (int i = 0; i < 4; ++i) o[i] = out[i] ? out[i] + (long long)j0 * ldo[i] : nullptr;
+    LTD_TRY(apply_chunk(sys, k, mode, a_z, C + (long long)j0 * ldc, ldc, cols, o, ldo, s));
+  }
+  return LTD_OK;
+}
+
+ltd_status read_status(ltd_system *sys, hipStream_t s, int *st) {
+  LTD_HIP(hipStreamSynchronize(s));
+  LTD_HIP(hipMemcpy(st, sys->ws + sys->o_status, sizeof(int), hipMemcpyDeviceToHost));
+  return LTD_OK;
+}
+
+// Subspace matrices of a block X (N_basis x n): X^H T X, ..., made Hermitian, then
+// S = L L^H, L^{-1}, and the S-orthonormal-basis T~, V~, P~, H~0 of the k-point's slots.
+ltd_status setup_sub(ltd_system *sys, int k, const double2 *X, int ldx, hipStream_t s) {
+  KHost &kh = sys->kh[k];
+  const int n = sys->n_aux, nb = kh.n_basis;
+  double2 *tv = sys->at<double2>(sys->o_tvps);  // 4 blocks N_basis x n, ld nb_max
+  const int ldt = sys->nb_max;
+  double2 *outs[4] = {tv, tv + (long long)ldt * n, tv + 2LL * ldt * n, tv + 3LL * ldt * n};
+  const int lds[4] = {ldt, ldt, ldt, ldt};
+  LTD_TRY(apply_cols(sys, k, FFT_MODE_TVPS, 0.0, X, ldx, n, outs, lds, s));
+  // projection: X^H [TX | VX | PX | SX] -> n x 4n
+  double2 *pr = sys->at<double2>(sys->o_proj);
+  std::vector<ZProb> pp;
+  for (int b = 0; b < 4; ++b) pp.push_back(zp(n, n, nb, X, ldx, outs[b], ldt, pr + (long long)b * n * n, n));
+  LTD_TRY(gemm(sys, OP_C, OP_N, pp, s));
+  double2 *subs = sys->at<double2>(kh.o_subs);
+  LTD_HIP(launch_herm_split(pr, n, n, 4, subs, s));
+  double2 *L = sys->at<double2>(kh.o_L), *Li = sys->at<double2>(kh.o_Linv);
+  int *fail = sys->at<int>(sys->o_status) + 1;
+  LTD_HIP(launch_cholesky(subs + 3LL * n * n, L, n, sys->at<int>(sys->o_status), fail, s));
+  LTD_HIP(launch_trtri(L, Li, n, s));
+  // tilde matrices: M~ = Li M Li^H for M in T, V, P
+  double2 *tmp = sys->at<double2>(sys->o_tmp3);
+  double2 *til = sys->at<double2>(kh.o_tilde);
+  const long long n2 = (long long)n * n;
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  LTD_TRY(gemm1(sys, OP_N, OP_C, zp(n, n, n, subs, n, Li, n, tmp, n, one, zero, 3, n2, 0, n2), s));
+  LTD_TRY(gemm1(sys, OP_N, OP_N, zp(n, n, n, Li, n, tmp, n, pr, n, one, zero, 3, 0, n2, n2), s));
+  LTD_HIP(launch_herm_split(pr, n, n, 3, til, s));
+  LTD_HIP(launch_axpby(til + 3 * n2, til, til + n2, 1.0, 1.0, n2, s));  // H~0 = T~ + V~_ref
+  return LTD_OK;
+}
+
+ltd_status eig_bounds(ltd_system *sys, int k, hipStream_t s, double *lmin, double *lmax) {
+  KHost &kh = sys->kh[k];
+  const int n = sys->n_aux;
+  const long long n2 = (long long)n * n;
+  double2 *A = sys->at<double2>(sys->o_eigA);
+  double *w = sys->at<double>(sys->o_eigw);
+  LTD_HIP(hipMemcpyAsync(A, sys->at<double2>(kh.o_tilde) + 3 * n2, n2 * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  LTD_HIP(launch_jacobi(A, nullptr, w, n, s));
+  std::vector<double> hw(n);
+  LTD_HIP(hipStreamSynchronize(s));
+  LTD_HIP(hipMemcpy(hw.data(), w, n * sizeof(double), hipMemcpyDeviceToHost));
+  *lmin = hw[0];
+  *lmax = hw[n - 1];
+  return LTD_OK;
+}
+
+ltd_status upload_subdev(ltd_system *sys) {
+  LTD_HIP(hipMemcpy(sys->ws + sys->o_subdev, sys->sd.data(), sys->sd.size() * sizeof(SubDev), hipMemcpyHostToDevice));
+  return LTD_OK;
+}
+
+ltd_status prepare_dt(ltd_system *sys, double dt) {
+  if (sys->cheb_dt == dt) return LTD_OK;
+  std::vector<double2> c;
+  for (int k = 0; k < sys->n_k; ++k) {
+    if (!sys->kh[k].bound) continue;
+    SubDev &d = sys->sd[k];
+    const int deg = cheb_coef(d.r * dt, CHEB_KMAX, c);
+    if (deg < 0) return LTD_EUNSUPPORTED;  // dt too large for the subspace spectrum
+    d.K = std::max(deg, 1);
+    for (int q = 0; q <= CHEB_KMAX; ++q) d.coef[q] = c[q];
+    d.phase = make_double2(std::cos(dt * d.c0), -std::sin(dt * d.c0));
+  }
+  LTD_TRY(upload_subdev(sys));
+  sys->cheb_dt = dt;
+  return LTD_OK;
+}
+
+ltd_status build_step_tables(ltd_system *sys) {
+  // K2 (muffin-tin rebuild) and the V~ projection GEMM over every bound k
+  std::vector<ZProb> p1, p2, pv;
+  const double2 *hx = sys->k2_step_h ? reinterpret_cast<const double2 *>(sys->k2_step_h) : sys->h;
+  const int n = sys->n_aux;
+  for (int k = 0; k < sys->n_k; ++k) {
+    KHost &kh = sys->kh[k];
+    if (!kh.bound) continue;
+    double2 *ph = sys->at<double2>(kh.o_phit), *ye = sys->at<double2>(kh.o_yext);
+    build_k2(sys, {hx}, ph + kh.n_g, kh.k_ext, {ye + kh.n_g}, kh.k_ext, n, p1, p2);
+    pv.push_back(zp(n, n, kh.k_ext, ph, kh.k_ext, ye, kh.k_ext, sys->at<double2>(kh.o_vstep), n));
+  }
+  const size_t cap = (size_t)4 * sys->n_atoms * sys->n_k * sizeof(ZProb) + 1024;
+  LTD_TRY(upload_k2(sys, p1, p2, sys->k2_step, sys->o_k2_st1, sys->o_k2_st2, cap));
+  int tt = 0;
+  gemm_plan(pv.data(), (int)pv.size(), &tt, 512, PART_TILES);
+  sys->vstep_tab = pv;
+  sys->vstep_tiles = tt;
+  LTD_HIP(hipMemcpy(sys->ws + sys->o_vstep_tab, pv.data(), pv.size() * sizeof(ZProb), hipMemcpyHostToDevice));
+  return LTD_OK;
+}
+
+StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
+  StepCtx c{};
+  c.sub = sys->at<SubDev>(sys->o_subdev);
+  c.n_aux = sys->n_aux;
+  c.n_states = sys->n_states;
+  c.n_k = sys->n_k;
+  c.h_in_lds = sys->h_in_lds ? 1 : 0;
+  c.rebuild = (a->mode == LTD_STEP_REBUILD) ? 1 : 0;
+  c.step = a->step;
+  c.step_rw = a->step;
+  c.a_t = a->a_t;
+  c.a_mid = a->a_mid;
+  c.c_light = sys->c_light;
+  c.occ = sys->occ;
+  c.omega = sys->omega;
+  c.dt = a->dt;
+  c.theta = reinterpret_cast<double2 *>(a->theta);
+  c.part = sys->at<double>(sys->o_part);
+  c.status = sys->at<int>(sys->o_status);
+  c.j_out = a->j_out;
+  c.e_out = a->e_out;
+  c.dmu_out = a->dmu_out;
+  return c;
+}
+
+// Rebuild V~(t) of every k for the potential of this step (v_r_t, h_t).
+ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
+  const Grid g = grid_of(sys);
+  const int n = sys->n_aux;
+  const double *thv = sys->at<double>(sys->o_thv);
+  if (a->v_r_t) {
+    LTD_HIP(launch_thv(sys->at<double>(sys->o_thv_step), sys->theta, a->v_r_t, sys->ngrid, s));
+    thv = sys->at<double>(sys->o_thv_step);
+  }
+  const long long slab = (long long)g.nbz * sys->n1 * sys->n2 * n;
+  for (int k0 = 0; k0 < sys->n_k; k0 += FFT_MAXK) {
+    const int nk = std::min(FFT_MAXK, sys->n_k - k0);
+    FftKArgs ka{};
+    for (int i = 0; i < nk; ++i) {
+      const KHost &kh = sys->kh[k0 + i];
+      ka.sph[i] = sphere_of(sys, k0 + i);
+      ka.slab_in[i] = sys->at<double2>(kh.o_cache);
+      ka.slab_out[i] = sys->at<double2>(sys->o_stepslab) + (long long)i * slab;
+      ka.out[i].o0 = sys->at<double2>(kh.o_yext);
+      ka.out[i].ld0 = kh.k_ext;
+    }
+    LTD_HIP(fft_lines(g, ka, nk, n, FFT_MODE_V, thv, s));
+    for (int i = 0; i < nk; ++i) ka.slab_in[i] = ka.slab_out[i];
+    LTD_HIP(fft_forward_planes(g, ka, nk, n, FFT_MODE_V, 0.0, 0.0, s));
+  }
+  const void *hx = a->h_t ? a->h_t : nullptr;
+  if (hx != sys->k2_step_h) {
+    sys->k2_step_h = hx;
+    LTD_TRY(build_step_tables(sys));
+  }
+  LTD_TRY(run_k2(sys, sys->k2_step, n, s));
+  LTD_HIP(gemm_launch_table(OP_C, OP_N, sys->at<ZProb>(sys->o_vstep_tab), sys->vstep_tab.data(),
+                            (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_partials), 0, s));
+  return LTD_OK;
+}
+
+ltd_status map_back(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
+  if (!a->c_out) return LTD_OK;
+  std::vector<ZProb> pp;
+  long long coff = 0;
+  const int n = sys->n_aux, ns = sys->n_states;
+  for (int k = 0; k < sys->n_k; ++k) {
+    const KHost &kh = sys->kh[k];
+    pp.push_back(zp(kh.n_basis, ns, n, kh.phi, kh.ldphi, reinterpret_cast<double2 *>(a->theta) + (long long)k * n * ns,
+                    n, reinterpret_cast<double2 *>(a->c_out) + coff, kh.n_basis));
+    coff += (long long)kh.n_basis * ns;
+  }
+  return gemm(sys, OP_N, OP_N, pp, s);
+}
+
+ltd_status check_step_args(ltd_system *sys, const ltd_step_args *a) {
+  if (!sys || !a) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  for (int k = 0; k < sys->n_k; ++k)
+    if (!sys->kh[k].bound) return LTD_ESTATE;
+  if (a->mode != LTD_STEP_REBUILD && a->mode != LTD_STEP_AFFINE) return LTD_EINVAL;
+  if (!(std::isfinite(a->dt)) || a->dt == 0.0) return LTD_EINVAL;
+  if (!a->a_t || !a->a_mid || !a->step || !a->theta || !a->j_out || !a->e_out || !a->dmu_out) return LTD_EINVAL;
+  if (!aligned16(a->theta) || (a->c_out && !aligned16(a->c_out))) return LTD_EALIGN;
+  if (a->h_t && !aligned16(a->h_t)) return LTD_EALIGN;
+  return LTD_OK;
+}
+
+ltd_status step_once(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
+  if (a->mode == LTD_STEP_REBUILD) LTD_TRY(rebuild_v(sys, a, s));
+  LTD_HIP(launch_step(step_ctx(sys, a), s));
+  LTD_TRY(map_back(sys, a, s));
+  return LTD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *ltd_status_string(ltd_status st) {
+  switch (st) {
+    case LTD_OK: return "ok";
+    case LTD_EINVAL: return "invalid argument";
+    case LTD_ESHAPE: return "inconsistent sizes or leading dimensions";
+    case LTD_EALIGN: return "complex pointer not 16-byte aligned";
+    case LTD_ESTATE: return "call out of order (workspace or subspace not bound)";
+    case LTD_EWORKSPACE: return "workspace too small";
+    case LTD_EUNSUPPORTED: return "size or mode not supported by this build";
+    case LTD_EHIP: return "HIP runtime error";
+    case LTD_ENOTSPD: return "subspace overlap not positive definite";
+    case LTD_ENONFINITE: return "non-finite current or energy";
+    case LTD_ESPECTRUM: return "subspace spectrum left the propagator interval";
+    default: return "unknown status";
+  }
+}
+
+ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes, ltd_system **out) {
+  if (!d || !ws_bytes || !out) return LTD_EINVAL;
+  *out = nullptr;
+  if (precision != LTD_FP64) return LTD_EUNSUPPORTED;
+  if (d->n_k < 1 || d->n_atoms < 0 || d->n_aux < 1 || d->n_states < 1 || d->n_states > d->n_aux ||
+      d->max_cols < 1)
+    return LTD_ESHAPE;
+  if (!d->n_g || !d->g_int || !d->gk_cart || !d->theta_r || !d->v_r || !d->amat || !d->k_weight) return LTD_EINVAL;
+  if (d->n_atoms > 0 && (!d->n_mt || !d->n_lo || !d->h || !d->o || !d->pz)) return LTD_EINVAL;
+  if (!(d->omega > 0.0) || !(d->c_light > 0.0) || !std::isfinite(d->occ)) return LTD_EINVAL;
+  if (!aligned16(d->amat) || (d->n_atoms > 0 && (!aligned16(d->h) || !aligned16(d->o) || !aligned16(d->pz))))
+    return LTD_EALIGN;
+  if (d->n_aux > 320) return LTD_EUNSUPPORTED;
+  auto *sys = new ltd_system();
+  sys->n_k = d->n_k;
+  sys->n1 = d->grid[0];
+  sys->n2 = d->grid[1];
+  sys->n3 = d->grid[2];
+  sys->ngrid = (long long)sys->n1 * sys->n2 * sys->n3;
+  Grid &g = sys->grid;
+  g.n1 = sys->n1;
+  g.n2 = sys->n2;
+  g.n3 = sys->n3;
+  if (!fft_plan_length(g.n1, &g.p1) || !fft_plan_length(g.n2, &g.p2) || !fft_plan_length(g.n3, &g.p3)) {
+    delete sys;
+    return LTD_EUNSUPPORTED;
+  }
+  sys->theta = d->theta_r;
+  sys->v_r = d->v_r;
+  sys->n_atoms = d->n_atoms;
+  int ao = 0, lo = 0;
+  long long so = 0;
+  for (int a = 0; a < d->n_atoms; ++a) {
+    if (d->n_mt[a] < 1 || d->n_lo[a] < 0) {
+      delete sys;
+      return LTD_ESHAPE;
+    }
+    sys->n_mt.push_back(d->n_mt[a]);
+    sys->n_lo.push_back(d->n_lo[a]);
+    sys->a_off.push_back(ao);
+    sys->l_off.push_back(lo);
+    sys->s_off.push_back((int)so);
+    const int s = d->n_mt[a] + d->n_lo[a];
+    ao += d->n_mt[a];
+    lo += d->n_lo[a];
+    so += (long long)s * s;
+  }
+  sys->n_a = ao;
+  sys->n_lo_tot = lo;
+  sys->n_loc = ao + lo;
+  sys->blk_elems = so;
+  sys->amat = reinterpret_cast<const double2 *>(d->amat);
+  sys->h = reinterpret_cast<const double2 *>(d->h);
+  sys->o = reinterpret_cast<const double2 *>(d->o);
+  sys->pz = reinterpret_cast<const double2 *>(d->pz);
+  sys->omega = d->omega;
+  sys->c_light = d->c_light;
+  sys->occ = d->occ;
+  sys->n_aux = d->n_aux;
+  sys->n_states = d->n_states;
+  sys->max_cols = d->max_cols;
+  sys->precision = precision;
+  // G sets, box, sphere tables
+  long long gtot = 0;
+  int bx = 0, by = 0, bz = 0;
+  for (int k = 0; k < d->n_k; ++k) {
+    if (d->n_g[k] < 1) {
+      delete sys;
+      return LTD_ESHAPE;
+    }
+    gtot += d->n_g[k];
+  }
+  sys->g_int.assign(d->g_int, d->g_int + 3 * gtot);
+  sys->gk.assign(d->gk_cart, d->gk_cart + 3 * gtot);
+  for (long long i = 0; i < gtot; ++i) {
+    bx = std::max(bx, std::abs(sys->g_int[3 * i]));
+    by = std::max(by, std::abs(sys->g_int[3 * i + 1]));
+    bz = std::max(bz, std::abs(sys->g_int[3 * i + 2]));
+  }
+  if (2 * bx >= g.n1 || 2 * by >= g.n2 || 2 * bz >= g.n3) {
+    delete sys;
+    return LTD_ESHAPE;
+  }
+  g.bx = bx;
+  g.by = by;
+  g.bz = bz;
+  g.nbx = 2 * bx + 1;
+  g.nby = 2 * by + 1;
+  g.nbz = 2 * bz + 1;
+  if (fft_plane_lds_bytes(g) > 160 * 1024 || fft_line_lds_bytes(g) > 160 * 1024) {
+    delete sys;
+    return LTD_EUNSUPPORTED;
+  }
+  long long goff = 0;
+  size_t aoff = 0;
+  sys->nb_max = 0;
+  for (int k = 0; k < d->n_k; ++k) {
+    KHost kh{};
+    kh.n_g = d->n_g[k];
+    kh.n_basis = kh.n_g + sys->n_lo_tot;
+    kh.k_ext = kh.n_g + sys->n_loc;
+    kh.g_off = goff;
+    kh.amat_off = aoff;
+    sys->nb_max = std::max(sys->nb_max, kh.n_basis);
+    // CSR of sphere points by kz plane; injectivity of g mod N
+    std::vector<std::vector<int>> byplane(g.nbz);
+    std::vector<char> seen((size_t)g.n1 * g.n2 * g.n3, 0);
+    for (int i = 0; i < kh.n_g; ++i) {
+      const int *gi = &sys->g_int[3 * (goff + i)];
+      const int x = (gi[0] % g.n1 + g.n1) % g.n1, y = (gi[1] % g.n2 + g.n2) % g.n2, z = (gi[2] % g.n3 + g.n3) % g.n3;
+      const size_t lin = (size_t)x + (size_t)g.n1 * (y + (size_t)g.n2 * z);
+      if (seen[lin]) {
+        delete sys;
+        return LTD_ESHAPE;
+      }
+      seen[lin] = 1;
+      byplane[gi[2] + bz].push_back(i);
+    }
+    kh.plane_ptr.push_back(0);
+    for (int p = 0; p < g.nbz; ++p) {
+      for (int i : byplane[p]) {
+        const int *gi = &sys->g_int[3 * (goff + i)];
+        const int x = (gi[0] % g.n1 + g.n1) % g.n1, y = (gi[1] % g.n2 + g.n2) % g.n2;
+        kh.pts_g.push_back(i);
+        kh.pts_xy.push_back(y * g.n1 + x);
+      }
+      kh.plane_ptr.push_back((int)kh.pts_g.size());
+    }
+    sys->kh.push_back(kh);
+    goff += kh.n_g;
+    aoff += (size_t)sys->n_a * kh.n_g;
+    sys->kw.push_back(d->k_weight[k]);
+  }
+  // columns per apply pass: FFT slabs (4 in + 5 out fields) within ~3 GB
+  const long long per_col = 9LL * g.nbz * g.n1 * g.n2 * (long long)sizeof(double2);
+  const int cmax = std::max(sys->max_cols, sys->n_aux);
+  sys->chunk = (int)std::max(1LL, std::min<long long>(cmax, (3LL << 30) / per_col));
+  const int n = sys->n_aux;
+  const long long n2 = (long long)n * n;
+  sys->h_in_lds = step_lds_bytes(n, true, true) <= 150 * 1024;
+  // workspace plan
+  Arena ar;
+  sys->o_tw1 = ar.take(g.n1 * sizeof(double2));
+  sys->o_tw2 = ar.take(g.n2 * sizeof(double2));
+  sys->o_tw3 = ar.take(g.n3 * sizeof(double2));
+  sys->o_thv = ar.take(sys->ngrid * sizeof(double));
+  sys->o_thv_step = ar.take(sys->ngrid * sizeof(double));
+  sys->o_status = ar.take(64);
+  sys->o_part = ar.take((size_t)4 * sys->n_k * sys->n_states * sizeof(double));
+  sys->o_partials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
+  const long long slab_f = (long long)g.nbz * g.n1 * g.n2 * sys->chunk;
+  sys->o_slab_in = ar.take(4 * slab_f * sizeof(double2));
+  sys->o_slab_out = ar.take(5 * slab_f * sizeof(double2));
+  sys->o_W = ar.take((size_t)sys->n_loc * sys->chunk * sizeof(double2));
+  sys->o_Y = ar.take((size_t)3 * sys->n_loc * sys->chunk * sizeof(double2));
+  sys->o_heff = ar.take((size_t)std::max<long long>(1, sys->blk_elems) * sizeof(double2));
+  sys->o_tvps = ar.take((size_t)4 * sys->nb_max * std::max(n, sys->n_states) * sizeof(double2));
+  sys->o_theta_sc = ar.take((size_t)2 * sys->nb_max * std::max(sys->n_states, 1) * sizeof(double2));
+  sys->o_proj = ar.take((size_t)4 * n2 * sizeof(double2));
+  sys->o_tmp3 = ar.take((size_t)3 * n2 * sizeof(double2));
+  sys->o_eigA = ar.take((size_t)n2 * sizeof(double2));
+  sys->o_eigV = ar.take((size_t)n2 * sizeof(double2));
+  sys->o_eigw = ar.take((size_t)n * sizeof(double));
+  sys->o_k6 = ar.take((size_t)sys->nb_max * n * sizeof(double2));
+  sys->o_stepslab = ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * g.nbz * g.n1 * g.n2 * n * sizeof(double2));
+  sys->o_subdev = ar.take(sys->n_k * sizeof(SubDev));
+  const size_t k2cap_apply = (size_t)4 * sys->n_atoms * 3 * sizeof(ZProb) + 1024;
+  sys->o_k2_hs1 = ar.take(k2cap_apply);
+  sys->o_k2_hs2 = ar.take(k2cap_apply);
+  sys->o_k2_tv1 = ar.take(k2cap_apply);
+  sys->o_k2_tv2 = ar.take(k2cap_apply);
+  const size_t k2cap_step = (size_t)4 * sys->n_atoms * sys->n_k * sizeof(ZProb) + 1024;
+  sys->o_k2_st1 = ar.take(k2cap_step);
+  sys->o_k2_st2 = ar.take(k2cap_step);
+  sys->o_vstep_tab = ar.take(sys->n_k * sizeof(ZProb) + 256);
+  for (int k = 0; k < sys->n_k; ++k) {
+    KHost &kh = sys->kh[k];
+    kh.o_gk = ar.take((size_t)3 * kh.n_g * sizeof(double));
+    kh.o_pptr = ar.take((size_t)(g.nbz + 1) * sizeof(int));
+    kh.o_ptsg = ar.take((size_t)kh.n_g * sizeof(int));
+    kh.o_ptsxy = ar.take((size_t)kh.n_g * sizeof(int));
+    kh.o_subs = ar.take((size_t)4 * n2 * sizeof(double2));
+    kh.o_tilde = ar.take((size_t)4 * n2 * sizeof(double2));
+    kh.o_L = ar.take((size_t)n2 * sizeof(double2));
+    kh.o_Linv = ar.take((size_t)n2 * sizeof(double2));
+    kh.o_vstep = ar.take((size_t)n2 * sizeof(double2));
+    kh.o_work = sys->h_in_lds ? 0 : ar.take((size_t)sys->n_states * n2 * sizeof(double2));
+    kh.o_phit = ar.take((size_t)kh.k_ext * n * sizeof(double2));
+    kh.o_yext = ar.take((size_t)kh.k_ext * n * sizeof(double2));
+    kh.o_cache = ar.take((size_t)g.nbz * g.n1 * g.n2 * n * sizeof(double2));
+  }
+  sys->ws_need = ar.off;
+  sys->sd.assign(sys->n_k, SubDev{});
+  *ws_bytes = sys->ws_need;
+  *out = sys;
+  return LTD_OK;
+}
+
+ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *stream) {
+  if (!sys || !ws) return LTD_EINVAL;
+  if (bytes < sys->ws_need) return LTD_EWORKSPACE;
+  if (((uintptr_t)ws % ALIGN) != 0) return LTD_EALIGN;
+  sys->ws = reinterpret_cast<char *>(ws);
+  sys->ws_bound = bytes;
+  hipStream_t s = S(stream);
+  fft_init_attrs();
+  subspace_init_attrs();
+  // twiddles exp(-2 pi i m / L)
+  auto tw = [&](int L, size_t off) -> ltd_status {
+    std::vector<double2> t(L);
+    for (int m = 0; m < L; ++m) {
+      const double ang = -2.0 * M_PI * (double)m / (double)L;
+      t[m] = make_double2(std::cos(ang), std::sin(ang));
+    }
+    LTD_HIP(hipMemcpy(sys->ws + off, t.data(), L * sizeof(double2), hipMemcpyHostToDevice));
+    return LTD_OK;
+  };
+  LTD_TRY(tw(sys->n1, sys->o_tw1));
+  LTD_TRY(tw(sys->n2, sys->o_tw2));
+  LTD_TRY(tw(sys->n3, sys->o_tw3));
+  for (int k = 0; k < sys->n_k; ++k) {
+    KHost &kh = sys->kh[k];
+    LTD_HIP(hipMemcpy(sys->ws + kh.o_gk, &sys->gk[3 * kh.g_off], 3 * kh.n_g * sizeof(double), hipMemcpyHostToDevice));
+    LTD_HIP(hipMemcpy(sys->ws + kh.o_pptr, kh.plane_ptr.data(), kh.plane_ptr.size() * sizeof(int), hipMemcpyHostToDevice));
+    LTD_HIP(hipMemcpy(sys->ws + kh.o_ptsg, kh.pts_g.data(), kh.n_g * sizeof(int), hipMemcpyHostToDevice));
+    LTD_HIP(hipMemcpy(sys->ws + kh.o_ptsxy, kh.pts_xy.data(), kh.n_g * sizeof(int), hipMemcpyHostToDevice));
+    kh.bound = false;
+  }
+  std::vector<int> zero(16, 0);
+  LTD_HIP(hipMemcpy(sys->ws + sys->o_status, zero.data(), 16 * sizeof(int), hipMemcpyHostToDevice));
+  LTD_HIP(launch_thv(sys->at<double>(sys->o_thv), sys->theta, sys->v_r, sys->ngrid, s));
+  // K2 tables of the apply chunk
+  double2 *W = sys->at<double2>(sys->o_W), *Y = sys->at<double2>(sys->o_Y);
+  const long long yst = (long long)sys->n_loc * sys->chunk;
+  {
+    std::vector<ZProb> p1, p2;
+    build_k2(sys, {sys->at<double2>(sys->o_heff), sys->o}, W, sys->n_loc, {Y, Y + yst}, sys->n_loc, sys->chunk, p1, p2);
+    LTD_TRY(upload_k2(sys, p1, p2, sys->k2_hs, sys->o_k2_hs1, sys->o_k2_hs2, (size_t)4 * sys->n_atoms * 3 * sizeof(ZProb) + 1024));
+  }
+  {
+    std::vector<ZProb> p1, p2;
+    build_k2(sys, {sys->h, sys->pz, sys->o}, W, sys->n_loc, {Y, Y + yst, Y + 2 * yst}, sys->n_loc, sys->chunk, p1, p2);
+    LTD_TRY(upload_k2(sys, p1, p2, sys->k2_tvps, sys->o_k2_tv1, sys->o_k2_tv2, (size_t)4 * sys->n_atoms * 3 * sizeof(ZProb) + 1024));
+  }
+  for (int k = 0; k < sys->n_k; ++k) {
+    SubDev &d = sys->sd[k];
+    d = SubDev{};
+    d.kw = sys->kw[k];
+  }
+  sys->cheb_dt = NAN;
+  sys->gvalid = false;
+  LTD_HIP(hipStreamSynchronize(s));
+  return LTD_OK;
+}
+
+ltd_status ltd_destroy(ltd_system *sys) {
+  if (!sys) return LTD_EINVAL;
+  if (sys->gexec) (void)hipGraphExecDestroy(sys->gexec);
+  if (sys->graph) (void)hipGraphDestroy(sys->graph);
+  if (sys->cap_stream) (void)hipStreamDestroy(sys->cap_stream);
+  delete sys;
+  return LTD_OK;
+}
+
+ltd_status ltd_sync_status(ltd_system *sys, void *stream) {
+  if (!sys) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  int st = 0;
+  LTD_TRY(read_status(sys, S(stream), &st));
+  int zero[2] = {0, 0};
+  LTD_HIP(hipMemcpy(sys->ws + sys->o_status, zero, sizeof(zero), hipMemcpyHostToDevice));
+  return st;
+}
+
+ltd_status ltd_apply_HS(ltd_system *sys, int k, const double a_vec[3], const void *C, int ldc, int n, void *HC,
+                        int ldhc, void *SC, int ldsc, void *stream) {
+  if (!sys || !a_vec) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  if (k < 0 || k >= sys->n_k || n < 0 || n > sys->max_cols) return LTD_ESHAPE;
+  if (n == 0) return LTD_OK;
+  if (!C || !HC || !SC) return LTD_EINVAL;
+  if (!std::isfinite(a_vec[0]) || !std::isfinite(a_vec[1]) || !std::isfinite(a_vec[2])) return LTD_EINVAL;
+  const int nb = sys->kh[k].n_basis;
+  if (ldc < nb || ldhc < nb || ldsc < nb) return LTD_ESHAPE;
+  if (!aligned16(C) || !aligned16(HC) || !aligned16(SC)) return LTD_EALIGN;
+  if (HC == C || SC == C || HC == SC) return LTD_EINVAL;
+  double2 *outs[4] = {reinterpret_cast<double2 *>(HC), reinterpret_cast<double2 *>(SC), nullptr, nullptr};
+  const int ldo[4] = {ldhc, ldsc, 0, 0};
+  return apply_cols(sys, k, FFT_MODE_HS, a_vec[2], reinterpret_cast<const double2 *>(C), ldc, n, outs, ldo, S(stream));
+}
+
+ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldphi, int n_aux, void *h0_sub,
+                                void *s_sub, const void *C, int ldc, int n_states, void *theta, void *stream) {
+  if (!sys || !phi) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  if (k < 0 || k >= sys->n_k || n_aux != sys->n_aux) return LTD_ESHAPE;
+  KHost &kh = sys->kh[k];
+  if (ldphi < kh.n_basis) return LTD_ESHAPE;
+  if (C && (ldc < kh.n_basis || n_states != sys->n_states || !theta)) return LTD_ESHAPE;
+  if (!aligned16(phi) || (h0_sub && !aligned16(h0_sub)) || (s_sub && !aligned16(s_sub)) || (C && !aligned16(C)) ||
+      (theta && !aligned16(theta)))
+    return LTD_EALIGN;
+  hipStream_t s = S(stream);
+  const int n = sys->n_aux;
+  const long long n2 = (long long)n * n;
+  const double2 *Phi = reinterpret_cast<const double2 *>(phi);
+  LTD_TRY(setup_sub(sys, k, Phi, ldphi, s));
+  int fail = 0;
+  LTD_HIP(hipStreamSynchronize(s));
+  LTD_HIP(hipMemcpy(&fail, sys->ws + sys->o_status + sizeof(int), sizeof(int), hipMemcpyDeviceToHost));
+  if (fail) return LTD_ENOTSPD;
+  double2 *subs = sys->at<double2>(kh.o_subs);
+  double2 *L = sys->at<double2>(kh.o_L), *Li = sys->at<double2>(kh.o_Linv);
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  // Phi~ = Phi L^{-H}; Phi~_ext = [Phi~_G; A Phi~_G; Phi~_LO]
+  double2 *pt = sys->at<double2>(sys->o_k6);
+  LTD_TRY(gemm1(sys, OP_N, OP_C, zp(kh.n_basis, n, n, Phi, ldphi, Li, n, pt, sys->nb_max), s));
+  double2 *pe = sys->at<double2>(kh.o_phit);
+  LTD_HIP(launch_copy_rows(pe, kh.k_ext, pt, sys->nb_max, kh.n_g, n, false, s));
+  LTD_TRY(gemm1(sys, OP_N, OP_N, zp(sys->n_a, n, kh.n_g, sys->amat + kh.amat_off, sys->n_a, pt, sys->nb_max,
+                                    pe + kh.n_g, kh.k_ext), s));
+  if (sys->n_lo_tot > 0)
+    LTD_HIP(launch_copy_rows(pe + kh.n_g + sys->n_a, kh.k_ext, pt + kh.n_g, sys->nb_max, sys->n_lo_tot, n, false, s));
+  // cached plane-wave part of Phi~ on the grid (first passes of the inverse transform)
+  {
+    FftKArgs ka{};
+    ka.sph[0] = sphere_of(sys, k);
+    ka.in[0].c = pe;
+    ka.in[0].ldc = kh.k_ext;
+    ka.slab_out[0] = sys->at<double2>(kh.o_cache);
+    LTD_HIP(fft_inverse_planes(grid_of(sys), ka, 1, n, 1, s));
+  }
+  // outputs in the Phi basis
+  if (h0_sub) LTD_HIP(launch_axpby(reinterpret_cast<double2 *>(h0_sub), subs, subs + n2, 1.0, 1.0, n2, s));
+  if (s_sub)
+    LTD_HIP(hipMemcpyAsync(s_sub, subs + 3 * n2, n2 * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  if (C) {
+    // theta = S^{-1} Phi^H (S C) = L^{-H} L^{-1} Phi^H (S C)
+    double2 *hsc = sys->at<double2>(sys->o_theta_sc);
+    double2 *outs[4] = {hsc, hsc + (long long)sys->nb_max * n_states, nullptr, nullptr};
+    const int ldo[4] = {sys->nb_max, sys->nb_max, 0, 0};
+    LTD_TRY(apply_cols(sys, k, FFT_MODE_HS, 0.0, reinterpret_cast<const double2 *>(C), ldc, n_states, outs, ldo, s));
+    double2 *t1 = sys->at<double2>(sys->o_tmp3);
+    double2 *t2 = t1 + (long long)n * n_states;
+    LTD_TRY(gemm1(sys, OP_C, OP_N, zp(n, n_states, kh.n_basis, Phi, ldphi, outs[1], sys->nb_max, t1, n), s));
+    LTD_TRY(gemm1(sys, OP_N, OP_N, zp(n, n_states, n, Li, n, t1, n, t2, n), s));
+    LTD_TRY(gemm1(sys, OP_C, OP_N, zp(n, n_states, n, Li, n, t2, n, reinterpret_cast<double2 *>(theta), n), s));
+  }
+  (void)one;
+  (void)zero;
+  // spectrum of H~0 -> Chebyshev interval and critical time step
+  double lmin = 0, lmax = 0;
+  LTD_TRY(eig_bounds(sys, k, s, &lmin, &lmax));
+  kh.lam_min = lmin;
+  kh.lam_max = lmax;
+  kh.phi = Phi;
+  kh.ldphi = ldphi;
+  SubDev &d = sys->sd[k];
+  const double half = 0.5 * (lmax - lmin);
+  d.tt = sys->at<double2>(kh.o_tilde);
+  d.vt_ref = d.tt + n2;
+  d.pt = d.tt + 2 * n2;
+  d.h0t = d.tt + 3 * n2;
+  d.vt_step = sys->at<double2>(kh.o_vstep);
+  d.L = L;
+  d.Linv = Li;
+  d.work = sys->h_in_lds ? nullptr : sys->at<double2>(kh.o_work);
+  d.kw = sys->kw[k];
+  d.c0 = 0.5 * (lmax + lmin);
+  d.margin = 0.25 * half + 0.2;
+  d.r = half + d.margin;
+  kh.bound = true;
+  sys->cheb_dt = NAN;
+  sys->gvalid = false;
+  LTD_TRY(build_step_tables(sys));
+  LTD_TRY(upload_subdev(sys));
+  LTD_HIP(hipStreamSynchronize(s));
+  return LTD_OK;
+}
+
+ltd_status ltd_ritz_basis(ltd_system *sys, int k, void *x, int ldx, double *eps, void *stream) {
+  if (!sys || !x) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  if (k < 0 || k >= sys->n_k) return LTD_ESHAPE;
+  KHost &kh = sys->kh[k];
+  if (ldx < kh.n_basis) return LTD_ESHAPE;
+  if (!aligned16(x)) return LTD_EALIGN;
+  hipStream_t s = S(stream);
+  const int n = sys->n_aux;
+  const long long n2 = (long long)n * n;
+  double2 *X = reinterpret_cast<double2 *>(x);
+  const bool was_bound = kh.bound;
+  LTD_TRY(setup_sub(sys, k, X, ldx, s));
+  int fail = 0;
+  LTD_HIP(hipStreamSynchronize(s));
+  LTD_HIP(hipMemcpy(&fail, sys->ws + sys->o_status + sizeof(int), sizeof(int), hipMemcpyDeviceToHost));
+  if (fail) return LTD_ENOTSPD;
+  double2 *A = sys->at<double2>(sys->o_eigA), *V = sys->at<double2>(sys->o_eigV);
+  double *w = sys->at<double>(sys->o_eigw);
+  LTD_HIP(hipMemcpyAsync(A, sys->at<double2>(kh.o_tilde) + 3 * n2, n2 * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  LTD_HIP(launch_jacobi(A, V, w, n, s));
+  // X <- X L^{-H} W
+  double2 *t = sys->at<double2>(sys->o_k6);
+  LTD_TRY(gemm1(sys, OP_N, OP_C, zp(kh.n_basis, n, n, X, ldx, sys->at<double2>(kh.o_Linv), n, t, sys->nb_max), s));
+  LTD_TRY(gemm1(sys, OP_N, OP_N, zp(kh.n_basis, n, n, t, sys->nb_max, V, n, X, ldx), s));
+  if (eps) LTD_HIP(hipMemcpyAsync(eps, w, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  LTD_HIP(hipStreamSynchronize(s));
+  // the k-point's slots were overwritten: the previous binding (if any) is gone
+  if (was_bound) kh.bound = false;
+  sys->gvalid = false;
+  return LTD_OK;
+}
+
+ltd_status ltd_subspace_info(ltd_system *sys, int k, double *eps_min, double *eps_max, double *dt_cr) {
+  if (!sys) return LTD_EINVAL;
+  if (k < 0 || k >= sys->n_k) return LTD_ESHAPE;
+  const KHost &kh = sys->kh[k];
+  if (!kh.bound) return LTD_ESTATE;
+  if (eps_min) *eps_min = kh.lam_min;
+  if (eps_max) *eps_max = kh.lam_max;
+  if (dt_cr) *dt_cr = 0.2 / (kh.lam_max - kh.lam_min);
+  return LTD_OK;
+}
+
+ltd_status ltd_propagate_step(ltd_system *sys, const ltd_step_args *a, void *stream) {
+  LTD_TRY(check_step_args(sys, a));
+  LTD_TRY(prepare_dt(sys, a->dt));
+  return step_once(sys, a, S(stream));
+}
+
+ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, void *stream) {
+  LTD_TRY(check_step_args(sys, a));
+  if (n_steps < 0) return LTD_ESHAPE;
+  if (n_steps == 0) return LTD_OK;
+  LTD_TRY(prepare_dt(sys, a->dt));
+  hipStream_t s = S(stream);
+  // tables that a rebuild step would refresh on the host must be current before capture
+  if (a->mode == LTD_STEP_REBUILD && (a->h_t ? a->h_t : nullptr) != sys->k2_step_h) {
+    sys->k2_step_h = a->h_t;
+    LTD_TRY(build_step_tables(sys));
+  }
+  const bool same = sys->gvalid && std::memcmp(&sys->gargs, a, sizeof(ltd_step_args)) == 0;
+  if (!same) {
+    if (sys->gexec) {
+      (void)hipGraphExecDestroy(sys->gexec);
+      sys->gexec = nullptr;
+    }
+    if (sys->graph) {
+      (void)hipGraphDestroy(sys->graph);
+      sys->graph = nullptr;
+    }
+    if (!sys->cap_stream) LTD_HIP(hipStreamCreateWithFlags(&sys->cap_stream, hipStreamNonBlocking));
+    LTD_HIP(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeThreadLocal));
+    const ltd_status st = step_once(sys, a, sys->cap_stream);
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(sys->cap_stream, &gr);
+    if (st != LTD_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return st;
+    }
+    if (ec != hipSuccess) return LTD_EHIP;
+    sys->graph = gr;
+    LTD_HIP(hipGraphInstantiate(&sys->gexec, gr, nullptr, nullptr, 0));
+    sys->gargs = *a;
+    sys->gvalid = true;
+  }
+  for (int i = 0; i < n_steps; ++i) LTD_HIP(hipGraphLaunch(sys->gexec, s));
+  return LTD_OK;
+}
+
+ltd_status ltd_propagate_step_adjoint(ltd_system *sys, const ltd_adjoint_args *aa, void *stream) {
+  if (!aa) return LTD_EINVAL;
+  const ltd_step_args *a = aa->fwd;
+  LTD_TRY(check_step_args(sys, a));
+  if (!aa->mu_out || (!aa->terminal && (!aa->mu_next || !aa->dl_da_mid)) || !aa->dl_da_t) return LTD_EINVAL;
+  if (aa->n_steps < 1 || aa->n < 0 || aa->n > aa->n_steps || (!aa->terminal && aa->n == aa->n_steps))
+    return LTD_ESHAPE;
+  if (!aligned16(aa->mu_out) || (aa->mu_next && !aligned16(aa->mu_next))) return LTD_EALIGN;
+  LTD_TRY(prepare_dt(sys, a->dt));
+  hipStream_t s = S(stream);
+  if (a->mode == LTD_STEP_REBUILD && !aa->terminal) LTD_TRY(rebuild_v(sys, a, s));
+  AdjCtx ac{};
+  ac.n = aa->n;
+  ac.terminal = aa->terminal;
+  ac.n_steps = aa->n_steps;
+  ac.mu_next = reinterpret_cast<const double2 *>(aa->mu_next);
+  ac.mu_out = reinterpret_cast<double2 *>(aa->mu_out);
+  ac.dl_da_mid = aa->dl_da_mid;
+  ac.dl_da_t = aa->dl_da_t;
+  LTD_HIP(launch_adjoint(step_ctx(sys, a), ac, s));
+  return LTD_OK;
+}
+
+ltd_status ltd_knot_samples(const double *knots, int n_knots, double t_end, double dt, int n_steps, double *a_t,
+                            double *a_mid, void *stream) {
+  if (!knots || !a_t || !a_mid) return LTD_EINVAL;
+  if (n_knots < 2 || n_steps < 1 || !(t_end > 0.0) || !(dt > 0.0)) return LTD_ESHAPE;
+  LTD_HIP(launch_knot_samples(knots, n_knots, t_end, dt, n_steps, a_t, a_mid, S(stream)));
+  return LTD_OK;
+}
+
+ltd_status ltd_knot_gradient(const double *dl_da_t, const double *dl_da_mid, int n_steps, double dt, int n_knots,
+                             double t_end, double *dl_dq, void *stream) {
+  if (!dl_da_t || !dl_da_mid || !dl_dq) return LTD_EINVAL;
+  if (n_knots < 2 || n_steps < 1 || !(t_end > 0.0) || !(dt > 0.0)) return LTD_ESHAPE;
+  LTD_HIP(launch_knot_gradient(dl_da_t, dl_da_mid, n_steps, dt, n_knots, t_end, dl_dq, S(stream)));
+  return LTD_OK;
+}
+
+ltd_status ltd_chebyshev_coefficients(double tau, int kmax, double *coef, int *degree) {
+  if (!coef || !degree || !std::isfinite(tau)) return LTD_EINVAL;
+  if (kmax < 1 || kmax > 4096) return LTD_ESHAPE;
+  std::vector<double2> c;
+  *degree = cheb_coef(tau, kmax, c);
+  for (int k = 0; k <= kmax; ++k) {
+    coef[2 * k] = c[k].x;
+    coef[2 * k + 1] = c[k].y;
+  }
+  return LTD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Internal declarations shared by the HIP sources of the ltd library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ltd {
+
+// ----------------------------------------------------------------------------
+// Complex helpers (interleaved re/im in double2 / float2)
+// ----------------------------------------------------------------------------
+__host__ __device__ inline double2 cmake(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double2 cfma(double2 a, double2 b, double2 c) {  // a*b + c
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+
+// ----------------------------------------------------------------------------
+// GEMM: C = alpha op(A) op(B) + beta C, complex128, column-major.
+// ----------------------------------------------------------------------------
+enum Op { OP_N = 0, OP_C = 1 };
+
+struct ZProb {
+  const double2 *A;
+  const double2 *B;
+  double2 *C;
+  long long sA, sB, sC;  // batch strides (elements)
+  int lda, ldb, ldc;
+  int m, n, k, batch;
+  double2 alpha, beta;
+  // planner-filled
+  int tiles_m, tiles_n, ksplit, kchunk;  // kchunk: K per split, multiple of the K tile
+  int tile_begin;                        // first logical tile of this problem
+  int rtile_begin;                       // first output tile (reduction pass)
+  long long part_off;                    // offset (tiles) into the split-K partial buffer
+};
+
+constexpr int GEMM_MAXP = 8;  // problems passed by value in one launch
+
+struct ZBatch {
+  ZProb p[GEMM_MAXP];
+  int nprob;
+  int total_tiles;
+};
+
+// Plans (tiles, split-K) a batch in place; returns the partial-buffer size (bytes).
+// `target_blocks` is the launch size below which K is split.
+// Split-K partial tiles never exceed `max_part_tiles` (64x64 complex each).
+size_t gemm_plan(ZProb *probs, int nprob, int *total_tiles, int target_blocks = 512,
+                 long long max_part_tiles = 2048);
+// Launches a planned batch held by value (nprob <= GEMM_MAXP).
+hipError_t gemm_launch(int opa, int opb, const ZBatch &b, double2 *partials, hipStream_t s);
+// Launches a planned batch whose problem table lives in device memory (any size);
+// `host` is the same table on the host (for the reduction pass).
+// n_limit > 0 caps every problem's column count (tiles beyond it exit at once).
+hipError_t gemm_launch_table(int opa, int opb, const ZProb *dev_table, const ZProb *host, int nprob,
+                             int total_tiles, double2 *partials, int n_limit, hipStream_t s);
+
+// ----------------------------------------------------------------------------
+// Interstitial FFT pipeline.
+// ----------------------------------------------------------------------------
+constexpr int FFT_MAXST = 8;
+constexpr int FFT_MAXLEN = 192;
+
+struct FftPlan {
+  int L;
+  int nst;
+  int radix[FFT_MAXST];
+};
+
+struct Grid {
+  int n1, n2, n3;
+  int bx, by, bz;  // box half-widths |g_i| <= b_i
+  int nbx, nby, nbz;
+  FftPlan p1, p2, p3;
+  const double2 *tw1, *tw2, *tw3;  // device twiddles exp(-2 pi i m / L)
+  const double *theta;             // [N]
+};
+
+// Per-k sphere tables (device).
+struct KSphere {
+  const double *gk;       // [n_g][3]
+  const int *plane_ptr;   // [nbz+1] CSR over kz planes
+  const int *pts_g;       // [n_g] G index, sorted by plane
+  const int *pts_xy;      // [n_g] position y*N1 + x of the point in its plane
+  int n_g;
+};
+
+enum FftMode { FFT_MODE_V = 0, FFT_MODE_HS = 1, FFT_MODE_TVPS = 2 };
+
+// Output descriptor of the forward plane pass (one per k).
+struct FwdOut {
+  double2 *o0;  // MODE_V: Y;  MODE_HS: HC;  MODE_TVPS: T
+  double2 *o1;  // MODE_HS: SC;  MODE_TVPS: V
+  double2 *o2;  // MODE_TVPS: P
+  double2 *o3;  // MODE_TVPS: S
+  int ld0, ld1, ld2, ld3;
+};
+
+// Input descriptor of the inverse plane pass (one per k): plane-wave block of C.
+struct InvIn {
+  const double2 *c;
+  int ldc;
+};
+
+constexpr int FFT_MAXK = 16;  // k-points handled by one batched FFT launch
+
+struct FftKArgs {
+  KSphere sph[FFT_MAXK];
+  InvIn in[FFT_MAXK];
+  FwdOut out[FFT_MAXK];
+  double2 *slab_in[FFT_MAXK];   // per k base of the input slabs
+  double2 *slab_out[FFT_MAXK];  // per k base of the output slabs
+};
+
+// slab layout per k: [field][col][pz][y][x]; field stride = ncols * nbz * N1 * N2.
+hipError_t fft_inverse_planes(const Grid &g, const FftKArgs &ka, int nk, int ncols, int nfields,
+                              hipStream_t s);
+hipError_t fft_lines(const Grid &g, const FftKArgs &ka, int nk, int ncols, int mode,
+                     const double *v_r, hipStream_t s);
+hipError_t fft_forward_planes(const Grid &g, const FftKArgs &ka, int nk, int ncols, int mode,
+                              double alpha_a, double beta_a, hipStream_t s);
+
+bool fft_plan_length(int L, FftPlan *p);
+size_t fft_plane_lds_bytes(const Grid &g);
+void fft_init_attrs();  // LDS limits of the FFT kernels (call outside graph capture)
+size_t fft_line_lds_bytes(const Grid &g);
+
+}  // namespace ltd

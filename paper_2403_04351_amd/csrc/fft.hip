@@ -1,0 +1,531 @@
+// Interstitial part of the LAPW+LO operators by FFT convolution (Pela & Draxl,
+// Sec. 2.3, second route; App. A, Eqs. (A.2), (A.4), (A.7)).
+//
+// For a block of plane-wave coefficient vectors the interstitial operators act
+// as: transform to the real-space grid, multiply by the step function Theta
+// (and by Theta V), transform back and read off at the G vectors:
+//   S C  = F(Theta psi),  V C = F(Theta V psi),
+//   T C  = 1/2 sum_i (G+k)_i F(Theta pi_i psi),  pi_i psi = F^{-1}((G+k)_i C),
+//   Pz C = 1/2 [(G+k)_z F(Theta psi) + F(Theta pi_z psi)],
+// with F f(q) = (1/N) sum_j f_j exp(-2 pi i q.j/N) and F^{-1} c = sum_q c_q
+// exp(+2 pi i q.j/N).
+//
+// The coefficients live on a sphere that fills a few per cent of the grid, so
+// each 3D transform is split into passes that only touch the box
+// |g_i| <= b_i around it:
+//   plane pass  (per kz in the box): 2D transform over (x, y) held whole in
+//                LDS; only the box columns are transformed along y;
+//   line pass   (per tile of (x, y) positions): full-length z transforms in
+//                LDS, fused with the pointwise products, so real-space fields
+//                never reach HBM;
+// and intermediate "slabs" hold nbz x N2 x N1 values per field and column.
+//
+// The 1D transforms are mixed-radix (8, 4, 5, 3, 2) Stockham autosort passes.
+// Each wavefront owns whole lines, so a pass needs no block barrier: a
+// wavefront reads all its butterfly inputs into registers, then writes the
+// outputs (LDS operations of one wavefront complete in order).
+#include "common.h"
+
+#include <cmath>
+
+namespace ltd {
+
+namespace {
+
+constexpr int FFT_NT = 256;
+constexpr double SQ1_2 = 0.70710678118654752440;  // 1/sqrt(2)
+constexpr double SQ3_2 = 0.86602540378443864676;  // sqrt(3)/2
+constexpr double C5_1 = 0.30901699437494742410;   // cos(2 pi/5)
+constexpr double C5_2 = -0.80901699437494742410;  // cos(4 pi/5)
+constexpr double S5_1 = 0.95105651629515357212;   // sin(2 pi/5)
+constexpr double S5_2 = 0.58778525229247312917;   // sin(4 pi/5)
+
+template <int DIR>
+__device__ inline double2 mul_i(double2 a) {  // (DIR i) * a
+  return DIR > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// In-place DFT of length R: y_p = sum_q v_q exp(DIR 2 pi i p q / R).
+template <int R, int DIR>
+__device__ inline void dft_small(double2 *v);
+
+template <>
+__device__ inline void dft_small<2, -1>(double2 *v) {
+  const double2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <>
+__device__ inline void dft_small<2, 1>(double2 *v) {
+  dft_small<2, -1>(v);
+}
+
+template <int DIR>
+__device__ inline void dft4(double2 &v0, double2 &v1, double2 &v2, double2 &v3) {
+  const double2 a = cadd(v0, v2), b = csub(v0, v2), c = cadd(v1, v3), d = mul_i<DIR>(csub(v1, v3));
+  v0 = cadd(a, c);
+  v2 = csub(a, c);
+  v1 = cadd(b, d);
+  v3 = csub(b, d);
+}
+template <>
+__device__ inline void dft_small<4, -1>(double2 *v) {
+  dft4<-1>(v[0], v[1], v[2], v[3]);
+}
+template <>
+__device__ inline void dft_small<4, 1>(double2 *v) {
+  dft4<1>(v[0], v[1], v[2], v[3]);
+}
+
+template <int DIR>
+__device__ inline void dft8(double2 *v) {
+  double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  // twiddles w8^p, w8 = exp(DIR i pi/4)
+  const double2 t1 = make_double2(SQ1_2 * (o1.x - DIR * o1.y), SQ1_2 * (o1.y + DIR * o1.x));
+  const double2 t2 = mul_i<DIR>(o2);
+  const double2 t3 = make_double2(SQ1_2 * (-o3.x - DIR * o3.y), SQ1_2 * (-o3.y + DIR * o3.x));
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+template <>
+__device__ inline void dft_small<8, -1>(double2 *v) {
+  dft8<-1>(v);
+}
+template <>
+__device__ inline void dft_small<8, 1>(double2 *v) {
+  dft8<1>(v);
+}
+
+template <int DIR>
+__device__ inline void dft3(double2 *v) {
+  const double2 t = cadd(v[1], v[2]);
+  const double2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
+  const double2 u = cscale(mul_i<DIR>(csub(v[1], v[2])), SQ3_2);
+  v[0] = cadd(v[0], t);
+  v[1] = cadd(m, u);
+  v[2] = csub(m, u);
+}
+template <>
+__device__ inline void dft_small<3, -1>(double2 *v) {
+  dft3<-1>(v);
+}
+template <>
+__device__ inline void dft_small<3, 1>(double2 *v) {
+  dft3<1>(v);
+}
+
+template <int DIR>
+__device__ inline void dft5(double2 *v) {
+  const double2 a1 = cadd(v[1], v[4]), a2 = cadd(v[2], v[3]);
+  const double2 b1 = csub(v[1], v[4]), b2 = csub(v[2], v[3]);
+  const double2 y0 = cadd(v[0], cadd(a1, a2));
+  const double2 m1 = make_double2(v[0].x + C5_1 * a1.x + C5_2 * a2.x, v[0].y + C5_1 * a1.y + C5_2 * a2.y);
+  const double2 m2 = make_double2(v[0].x + C5_2 * a1.x + C5_1 * a2.x, v[0].y + C5_2 * a1.y + C5_1 * a2.y);
+  const double2 n1 = mul_i<DIR>(make_double2(S5_1 * b1.x + S5_2 * b2.x, S5_1 * b1.y + S5_2 * b2.y));
+  const double2 n2 = mul_i<DIR>(make_double2(S5_2 * b1.x - S5_1 * b2.x, S5_2 * b1.y - S5_1 * b2.y));
+  v[0] = y0;
+  v[1] = cadd(m1, n1);
+  v[4] = csub(m1, n1);
+  v[2] = cadd(m2, n2);
+  v[3] = csub(m2, n2);
+}
+template <>
+__device__ inline void dft_small<5, -1>(double2 *v) {
+  dft5<-1>(v);
+}
+template <>
+__device__ inline void dft_small<5, 1>(double2 *v) {
+  dft5<1>(v);
+}
+
+template <int R>
+struct Tpl {  // butterflies per lane and stage (register budget)
+  static constexpr int value = (R == 8) ? 1 : (R == 5) ? 1 : (R == 4) ? 2 : (R == 3) ? 2 : 4;
+};
+
+__host__ __device__ inline int tpl_of(int r) { return r == 8 ? 1 : r == 5 ? 1 : r == 4 ? 2 : r == 3 ? 2 : 4; }
+
+// Largest number of lines one wavefront can transform per pass.
+__host__ __device__ inline int lines_per_wave(const FftPlan &p) {
+  int best = 1 << 20;
+  for (int s = 0; s < p.nst; ++s) {
+    const int r = p.radix[s];
+    const int v = (64 * tpl_of(r)) / (p.L / r);
+    best = v < best ? v : best;
+  }
+  return best < 1 ? 1 : best;
+}
+
+// Line addressing: element e of line l sits at buf[map(l) + e * es].
+struct LinesUniform {
+  int base, ls;
+  __device__ int operator()(int l) const { return base + l * ls; }
+};
+struct LinesBox {  // box columns of a plane: line l is column (l - b) mod n
+  int b, n;
+  __device__ int operator()(int l) const {
+    const int x = l - b;
+    return x < 0 ? x + n : x;
+  }
+};
+struct LinesTwo {  // lines [0, h) at a0 + l, lines [h, 2h) at a1 + (l - h)
+  int a0, a1, h;
+  __device__ int operator()(int l) const { return l < h ? a0 + l : a1 + (l - h); }
+};
+
+template <int R, int DIR, class LM>
+__device__ inline void fft_stage(double2 *buf, const LM &lm, int l0, int nl, int es, int L, int Ns,
+                                 const double2 *tw, int lane) {
+  constexpr int TPL = Tpl<R>::value;
+  const int nb = L / R;
+  const int ntask = nl * nb;
+  const int twm = L / (Ns * R);
+  double2 v[TPL][R];
+  int ob[TPL];
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) {
+    const int task = lane + 64 * t;
+    ob[t] = -1;
+    if (task < ntask) {
+      const int line = task / nb;
+      const int j = task - line * nb;
+      const int k = j % Ns;
+      const int base = lm(l0 + line);
+      const int tws = twm * k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        double2 x = buf[base + (j + q * nb) * es];
+        if (q > 0) {
+          double2 w = tw[(tws * q) % L];
+          if (DIR > 0) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[t][q] = x;
+      }
+      ob[t] = base + ((j / Ns) * Ns * R + k) * es;
+    }
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) {
+    if (ob[t] >= 0) {
+      dft_small<R, DIR>(v[t]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) buf[ob[t] + q * Ns * es] = v[t][q];
+    }
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <int DIR, class LM>
+__device__ void fft_wave(double2 *buf, const LM &lm, int l0, int nl, int es, const FftPlan &p, const double2 *tw,
+                         int lane) {
+  int ns = 1;
+  for (int s = 0; s < p.nst; ++s) {
+    const int r = p.radix[s];
+    switch (r) {
+      case 8: fft_stage<8, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+      case 4: fft_stage<4, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+      case 5: fft_stage<5, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+      case 3: fft_stage<3, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+      default: fft_stage<2, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+    }
+    ns *= r;
+  }
+}
+
+// All waves of the block transform `nlines` lines; ends with a block barrier.
+template <int DIR, class LM>
+__device__ void fft_block(double2 *buf, const LM &lm, int nlines, int es, const FftPlan &p, const double2 *tw) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lpw = lines_per_wave(p);
+  for (int l0 = wave * lpw; l0 < nlines; l0 += nw * lpw) {
+    const int nl = (nlines - l0) < lpw ? (nlines - l0) : lpw;
+    fft_wave<DIR>(buf, lm, l0, nl, es, p, tw, lane);
+  }
+  __syncthreads();
+}
+
+__device__ inline void load_tw(double2 *dst, const double2 *src, int L) {
+  for (int i = threadIdx.x; i < L; i += blockDim.x) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Inverse plane pass: sphere coefficients (times 1 or (G+k)_i) -> slab planes.
+// grid (nbz, ncols, nk); fields: 0 psi, 1..3 pi_x, pi_y, pi_z.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FFT_NT) void k_inv_plane(const Grid g, const FftKArgs ka, int ncols, int nfields) {
+  extern __shared__ double2 sm[];
+  const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
+  const int n1 = g.n1, n2 = g.n2, pitch = n1 + 1;
+  double2 *plane = sm;
+  double2 *tw1 = sm + n2 * pitch;
+  double2 *tw2 = tw1 + n1;
+  load_tw(tw1, g.tw1, n1);
+  load_tw(tw2, g.tw2, n2);
+  const KSphere &sp = ka.sph[kk];
+  const InvIn in = ka.in[kk];
+  const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
+  const long long plane_sz = (long long)n1 * n2;
+  const long long fstride = (long long)ncols * g.nbz * plane_sz;
+  double2 *out = ka.slab_out[kk] + ((long long)col * g.nbz + pz) * plane_sz;
+  for (int f = 0; f < nfields; ++f) {
+    for (int i = threadIdx.x; i < n2 * pitch; i += blockDim.x) plane[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+      const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+      double2 c = in.c[(long long)gi + (long long)col * in.ldc];
+      if (f > 0) c = cscale(c, sp.gk[3 * gi + (f - 1)]);
+      plane[(xy / n1) * pitch + (xy % n1)] = c;
+    }
+    __syncthreads();
+    fft_block<1>(plane, LinesBox{g.bx, n1}, g.nbx, pitch, g.p2, tw2);  // along y, box columns
+    fft_block<1>(plane, LinesUniform{0, pitch}, n2, 1, g.p1, tw1);      // along x, all rows
+    double2 *o = out + f * fstride;
+    for (int i = threadIdx.x; i < n1 * n2; i += blockDim.x) o[i] = plane[(i / n1) * pitch + (i % n1)];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Line pass along z for a tile of T consecutive (x, y) positions.
+// MODE_V:    in field 0 (psi)                 -> out field 0 (Theta V psi)
+// otherwise: in fields psi, pi_x, pi_y, pi_z -> out Theta psi, Theta V psi,
+//            Theta pi_x psi, Theta pi_y psi, Theta pi_z psi
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FFT_NT) void k_lines(const Grid g, const FftKArgs ka, int ncols, int mode, int T,
+                                                  const double *__restrict__ thv) {
+  extern __shared__ double2 sm[];
+  const int tile = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
+  const int n3 = g.n3, nbz = g.nbz, bz = g.bz;
+  const long long plane_sz = (long long)g.n1 * g.n2;
+  const int pos0 = tile * T;
+  const int tp = T + 1;
+  double2 *A = sm;
+  double2 *B = sm + n3 * tp;
+  double2 *tw3 = B + n3 * tp;
+  load_tw(tw3, g.tw3, n3);
+  const long long fstride = (long long)ncols * nbz * plane_sz;
+  const double2 *in = ka.slab_in[kk] + (long long)col * nbz * plane_sz;
+  double2 *out = ka.slab_out[kk] + (long long)col * nbz * plane_sz;
+  const int ntot = nbz * T;
+
+  auto load_field = [&](const double2 *src) {
+    for (int i = threadIdx.x; i < n3 * tp; i += blockDim.x) A[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
+      const int p = i / T, t = i - p * T;
+      const int kz = p - bz;
+      const int z = kz < 0 ? kz + n3 : kz;
+      if (pos0 + t < plane_sz) A[z * tp + t] = src[(long long)p * plane_sz + pos0 + t];
+    }
+    __syncthreads();
+  };
+  auto store_field = [&](const double2 *buf, double2 *dst) {
+    for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
+      const int p = i / T, t = i - p * T;
+      const int kz = p - bz;
+      const int z = kz < 0 ? kz + n3 : kz;
+      if (pos0 + t < plane_sz) dst[(long long)p * plane_sz + pos0 + t] = buf[z * tp + t];
+    }
+  };
+
+  if (mode == FFT_MODE_V) {
+    load_field(in);
+    fft_block<1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+    for (int i = threadIdx.x; i < n3 * T; i += blockDim.x) {
+      const int z = i / T, t = i - z * T;
+      if (pos0 + t < plane_sz) A[z * tp + t] = cscale(A[z * tp + t], thv[(long long)z * plane_sz + pos0 + t]);
+    }
+    __syncthreads();
+    fft_block<-1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+    store_field(A, out);
+    return;
+  }
+  // psi -> Theta psi, Theta V psi
+  load_field(in);
+  fft_block<1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+  for (int i = threadIdx.x; i < n3 * T; i += blockDim.x) {
+    const int z = i / T, t = i - z * T;
+    double th = 0.0, tv = 0.0;
+    if (pos0 + t < plane_sz) {
+      const long long gidx = (long long)z * plane_sz + pos0 + t;
+      th = g.theta[gidx];
+      tv = thv[gidx];
+    }
+    const double2 a = A[z * tp + t];
+    B[z * tp + t] = cscale(a, tv);
+    A[z * tp + t] = cscale(a, th);
+  }
+  __syncthreads();
+  fft_block<-1>(A, LinesTwo{0, n3 * tp, T}, 2 * T, tp, g.p3, tw3);
+  store_field(A, out);
+  store_field(B, out + fstride);
+  __syncthreads();
+  for (int f = 1; f <= 3; ++f) {
+    load_field(in + f * fstride);
+    fft_block<1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+    for (int i = threadIdx.x; i < n3 * T; i += blockDim.x) {
+      const int z = i / T, t = i - z * T;
+      const double th = (pos0 + t < plane_sz) ? g.theta[(long long)z * plane_sz + pos0 + t] : 0.0;
+      A[z * tp + t] = cscale(A[z * tp + t], th);
+    }
+    __syncthreads();
+    fft_block<-1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+    store_field(A, out + (f + 1) * fstride);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward plane pass: slab planes -> values at the sphere, combined per mode.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKArgs ka, int ncols, int mode,
+                                                      double alpha_a, double beta_a) {
+  extern __shared__ double2 sm[];
+  const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
+  const int n1 = g.n1, n2 = g.n2, pitch = n1 + 1;
+  double2 *plane = sm;
+  double2 *tw1 = sm + n2 * pitch;
+  double2 *tw2 = tw1 + n1;
+  load_tw(tw1, g.tw1, n1);
+  load_tw(tw2, g.tw2, n2);
+  const KSphere &sp = ka.sph[kk];
+  const FwdOut &fo = ka.out[kk];
+  const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
+  const long long plane_sz = (long long)n1 * n2;
+  const long long fstride = (long long)ncols * g.nbz * plane_sz;
+  const double2 *src0 = ka.slab_in[kk] + ((long long)col * g.nbz + pz) * plane_sz;
+  const double inv_n = 1.0 / ((double)n1 * n2 * g.n3);
+  const int nf = (mode == FFT_MODE_V) ? 1 : 5;
+  for (int f = 0; f < nf; ++f) {
+    const double2 *src = src0 + f * fstride;
+    for (int i = threadIdx.x; i < n1 * n2; i += blockDim.x) plane[(i / n1) * pitch + (i % n1)] = src[i];
+    __syncthreads();
+    fft_block<-1>(plane, LinesUniform{0, pitch}, n2, 1, g.p1, tw1);      // along x, all rows
+    fft_block<-1>(plane, LinesBox{g.bx, n1}, g.nbx, pitch, g.p2, tw2);  // along y, box columns
+    for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+      const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+      const double2 val = cscale(plane[(xy / n1) * pitch + (xy % n1)], inv_n);
+      const long long c = (long long)col;
+      if (mode == FFT_MODE_V) {
+        fo.o0[gi + c * fo.ld0] = val;
+      } else if (mode == FFT_MODE_HS) {
+        double2 *hc = fo.o0 + gi + c * fo.ld0;
+        const double gz = sp.gk[3 * gi + 2];
+        if (f == 0) {
+          fo.o1[gi + c * fo.ld1] = val;                                    // S C
+          *hc = cscale(val, alpha_a * 0.5 * gz + beta_a);                  // (A/c) 1/2 gz F(Th psi) + (A^2/2c^2) F(Th psi)
+        } else if (f == 1) {
+          *hc = cadd(*hc, val);                                            // F(Th V psi)
+        } else {
+          const double gi_c = sp.gk[3 * gi + (f - 2)];
+          double w = 0.5 * gi_c;                                           // 1/2 (G+k)_i F(Th pi_i psi)
+          if (f == 4) w += 0.5 * alpha_a;                                  // (A/c) 1/2 F(Th pi_z psi)
+          *hc = cadd(*hc, cscale(val, w));
+        }
+      } else {  // TVPS
+        const double gz = sp.gk[3 * gi + 2];
+        if (f == 0) {
+          fo.o3[gi + c * fo.ld3] = val;                      // S
+          fo.o2[gi + c * fo.ld2] = cscale(val, 0.5 * gz);    // P part
+        } else if (f == 1) {
+          fo.o1[gi + c * fo.ld1] = val;                      // V
+        } else {
+          const double w = 0.5 * sp.gk[3 * gi + (f - 2)];
+          double2 *t = fo.o0 + gi + c * fo.ld0;
+          *t = (f == 2) ? cscale(val, w) : cadd(*t, cscale(val, w));
+          if (f == 4) {
+            double2 *p = fo.o2 + gi + c * fo.ld2;
+            *p = cadd(*p, cscale(val, 0.5));
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+size_t plane_lds(const Grid &g) { return ((size_t)g.n2 * (g.n1 + 1) + g.n1 + g.n2) * sizeof(double2); }
+
+int line_tile(const Grid &g) {
+  const long long plane_sz = (long long)g.n1 * g.n2;
+  int t = 64;
+  while (t > 8 && (size_t)(2 * g.n3 * (t + 1) + g.n3) * sizeof(double2) > 80 * 1024) t /= 2;
+  while (t > 8 && t / 2 >= plane_sz) t /= 2;
+  return t;
+}
+
+size_t line_lds(const Grid &g, int t) { return (size_t)(2 * g.n3 * (t + 1) + g.n3) * sizeof(double2); }
+
+bool attrs_set = false;
+void set_attrs() {
+  if (attrs_set) return;
+  (void)hipFuncSetAttribute((const void *)k_inv_plane, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipFuncSetAttribute((const void *)k_fwd_plane, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipFuncSetAttribute((const void *)k_lines, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  attrs_set = true;
+}
+
+}  // namespace
+
+bool fft_plan_length(int L, FftPlan *p) {
+  if (L < 2 || L > FFT_MAXLEN) return false;
+  p->L = L;
+  p->nst = 0;
+  int r = L;
+  const int order[5] = {8, 4, 5, 3, 2};
+  for (int oi = 0; oi < 5; ++oi) {
+    while (r % order[oi] == 0 && r > 1) {
+      if (p->nst >= FFT_MAXST) return false;
+      p->radix[p->nst++] = order[oi];
+      r /= order[oi];
+    }
+  }
+  if (r != 1) return false;
+  // one wavefront must hold at least one line in every pass
+  for (int s = 0; s < p->nst; ++s)
+    if (L / p->radix[s] > 64 * tpl_of(p->radix[s])) return false;
+  return true;
+}
+
+void fft_init_attrs() { set_attrs(); }
+
+size_t fft_plane_lds_bytes(const Grid &g) { return plane_lds(g); }
+size_t fft_line_lds_bytes(const Grid &g) { return line_lds(g, line_tile(g)); }
+
+hipError_t fft_inverse_planes(const Grid &g, const FftKArgs &ka, int nk, int ncols, int nfields, hipStream_t s) {
+  set_attrs();
+  hipLaunchKernelGGL(k_inv_plane, dim3(g.nbz, ncols, nk), dim3(FFT_NT), plane_lds(g), s, g, ka, ncols, nfields);
+  return hipGetLastError();
+}
+
+hipError_t fft_lines(const Grid &g, const FftKArgs &ka, int nk, int ncols, int mode, const double *thv,
+                     hipStream_t s) {
+  set_attrs();
+  const int t = line_tile(g);
+  const long long plane_sz = (long long)g.n1 * g.n2;
+  const int ntile = (int)((plane_sz + t - 1) / t);
+  hipLaunchKernelGGL(k_lines, dim3(ntile, ncols, nk), dim3(FFT_NT), line_lds(g, t), s, g, ka, ncols, mode, t,
+                     thv);
+  return hipGetLastError();
+}
+
+hipError_t fft_forward_planes(const Grid &g, const FftKArgs &ka, int nk, int ncols, int mode, double alpha_a,
+                              double beta_a, hipStream_t s) {
+  set_attrs();
+  hipLaunchKernelGGL(k_fwd_plane, dim3(g.nbz, ncols, nk), dim3(FFT_NT), plane_lds(g), s, g, ka, ncols, mode,
+                     alpha_a, beta_a);
+  return hipGetLastError();
+}
+
+}  // namespace ltd

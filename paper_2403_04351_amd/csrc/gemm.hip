@@ -1,0 +1,353 @@
+// Complex FP64 GEMM on the CDNA4 matrix cores.
+//
+// C = alpha op(A) op(B) + beta C with complex128 operands, column-major, as a
+// grouped launch over independent problems (each optionally strided-batched)
+// and an optional split of the K dimension whose partial tiles are summed in a
+// fixed order by a second pass (deterministic, no atomics).
+//
+// Work decomposition: 64x64 output tiles, 256 threads = 4 wavefronts in a 2x2
+// arrangement, each wavefront owning a 32x32 block = 2x2 MFMA blocks of 16x16.
+// A complex multiply-add is four real v_mfma_f64_16x16x4_f64: re += ar br,
+// re += (-ai) bi, im += ar bi, im += ai br.  Operand tiles (64 x 16 complex)
+// are staged through LDS as separate real and imaginary planes, double
+// buffered, with the conjugation of op = C folded into the staging store.
+// Logical tiles are remapped so that each XCD (blocks are dealt round-robin
+// to the 8 XCDs) runs a contiguous range of them: tiles that share an operand
+// panel share an L2.
+#include "common.h"
+
+namespace ltd {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256, LP = 2;  // LP: LDS row padding (doubles)
+
+struct Frag {
+  double2 v[4];
+};
+
+__device__ inline int xcd_logical(int b, int g) {
+  const int q = g / 8, rem = g % 8, x = b % 8, r = b / 8;
+  return (x < rem) ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
+}
+
+template <int OPA>
+__device__ inline void load_a(const ZProb &P, const double2 *A, int m0, int k0, int kend, int t,
+                              Frag &f) {
+  if (OPA == OP_N) {  // A is m x k: tile column kk is contiguous in i
+    const int kk = t >> 4, i = (t & 15) * 4;
+    const int kg = k0 + kk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ig = m0 + i + q;
+      f.v[q] = (ig < P.m && kg < kend) ? A[(long long)ig + (long long)kg * P.lda] : make_double2(0.0, 0.0);
+    }
+  } else {  // A is k x m, op = conj-transpose: tile row i is contiguous in kk
+    const int i = t >> 2, kk = (t & 3) * 4;
+    const int ig = m0 + i;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kg = k0 + kk + q;
+      f.v[q] = (ig < P.m && kg < kend) ? A[(long long)kg + (long long)ig * P.lda] : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+template <int OPB>
+__device__ inline void load_b(const ZProb &P, const double2 *B, int n0, int k0, int kend, int t,
+                              Frag &f, int nlim) {
+  if (OPB == OP_N) {  // B is k x n: tile column j is contiguous in kk
+    const int j = t >> 2, kk = (t & 3) * 4;
+    const int jg = n0 + j;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kg = k0 + kk + q;
+      f.v[q] = (jg < nlim && kg < kend) ? B[(long long)kg + (long long)jg * P.ldb] : make_double2(0.0, 0.0);
+    }
+  } else {  // B is n x k, op = conj-transpose: tile row kk is contiguous in j
+    const int kk = t >> 4, j = (t & 15) * 4;
+    const int kg = k0 + kk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jg = n0 + j + q;
+      f.v[q] = (jg < nlim && kg < kend) ? B[(long long)jg + (long long)kg * P.ldb] : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+template <int OPA>
+__device__ inline void store_a(double (*As)[BK][BM + LP], int t, const Frag &f) {
+  const double sg = (OPA == OP_C) ? -1.0 : 1.0;
+  if (OPA == OP_N) {
+    const int kk = t >> 4, i = (t & 15) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[0][kk][i + q] = f.v[q].x;
+      As[1][kk][i + q] = f.v[q].y;
+    }
+  } else {
+    const int i = t >> 2, kk = (t & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[0][kk + q][i] = f.v[q].x;
+      As[1][kk + q][i] = sg * f.v[q].y;
+    }
+  }
+}
+
+template <int OPB>
+__device__ inline void store_b(double (*Bs)[BK][BN + LP], int t, const Frag &f) {
+  const double sg = (OPB == OP_C) ? -1.0 : 1.0;
+  if (OPB == OP_N) {
+    const int j = t >> 2, kk = (t & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Bs[0][kk + q][j] = f.v[q].x;
+      Bs[1][kk + q][j] = f.v[q].y;
+    }
+  } else {
+    const int kk = t >> 4, j = (t & 15) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Bs[0][kk][j + q] = f.v[q].x;
+      Bs[1][kk][j + q] = sg * f.v[q].y;
+    }
+  }
+}
+
+template <int OPA, int OPB, bool TABLE>
+__global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZProb *__restrict__ table,
+                                                   int nprob, double2 *__restrict__ partials, int n_limit) {
+  __shared__ double As[2][2][BK][BM + LP];
+  __shared__ double Bs[2][2][BK][BN + LP];
+
+  const ZProb *probs = TABLE ? table : batch.p;
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  int pi = 0;
+  while (pi + 1 < nprob && probs[pi + 1].tile_begin <= logical) ++pi;
+  const ZProb &P = probs[pi];
+
+  int t = logical - P.tile_begin;
+  const int tm = t % P.tiles_m;
+  t /= P.tiles_m;
+  const int tn = t % P.tiles_n;
+  t /= P.tiles_n;
+  const int bi = t % P.batch;
+  const int ks = t / P.batch;
+
+  const double2 *A = P.A + (long long)bi * P.sA;
+  const double2 *B = P.B + (long long)bi * P.sB;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int nlim = (n_limit > 0 && n_limit < P.n) ? n_limit : P.n;
+  if (n0 >= nlim) return;  // whole block: columns beyond the limit
+  const int kbeg = ks * P.kchunk;
+  const int kend = min(P.k, kbeg + P.kchunk);
+  const int nkt = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  d4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      ci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  Frag fa, fb;
+  if (nkt > 0) {
+    load_a<OPA>(P, A, m0, kbeg, kend, tid, fa);
+    load_b<OPB>(P, B, n0, kbeg, kend, tid, fb, nlim);
+    store_a<OPA>(As[0], tid, fa);
+    store_b<OPB>(Bs[0], tid, fb);
+  }
+  __syncthreads();
+
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int cur = kt & 1;
+    const bool more = (kt + 1) < nkt;
+    if (more) {
+      const int k0 = kbeg + (kt + 1) * BK;
+      load_a<OPA>(P, A, m0, k0, kend, tid, fa);
+      load_b<OPB>(P, B, n0, k0, kend, tid, fb, nlim);
+    }
+#pragma unroll
+    for (int kq = 0; kq < BK; kq += 4) {
+      const int kk = kq + (lane >> 4);
+      double ar[2], ai[2], br[2], bi2[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = wm * 32 + a * 16 + (lane & 15);
+        ar[a] = As[cur][0][kk][i];
+        ai[a] = As[cur][1][kk][i];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = wn * 32 + b * 16 + (lane & 15);
+        br[b] = Bs[cur][0][kk][j];
+        bi2[b] = Bs[cur][1][kk][j];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
+          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], bi2[b], cr[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi2[b], ci[a][b], 0, 0, 0);
+          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], ci[a][b], 0, 0, 0);
+        }
+    }
+    if (more) {
+      store_a<OPA>(As[cur ^ 1], tid, fa);
+      store_b<OPB>(Bs[cur ^ 1], tid, fb);
+    }
+    __syncthreads();
+  }
+
+  // Output element of accumulator register r of v_mfma_f64_16x16x4f64: row 4*r + lane/16,
+  // column lane%16 (measured; the FP32 16x16 variant differs).
+  if (P.ksplit == 1) {
+    double2 *C = P.C + (long long)bi * P.sC;
+    const bool rd = (P.beta.x != 0.0 || P.beta.y != 0.0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = m0 + wm * 32 + a * 16 + 4 * r + (lane >> 4);
+          const int j = n0 + wn * 32 + b * 16 + (lane & 15);
+          if (i < P.m && j < nlim) {
+            const double2 acc = make_double2(cr[a][b][r], ci[a][b][r]);
+            double2 v = cmul(P.alpha, acc);
+            double2 *dst = C + (long long)i + (long long)j * P.ldc;
+            if (rd) v = cfma(P.beta, *dst, v);
+            *dst = v;
+          }
+        }
+  } else {
+    const long long tile_lin = ((long long)bi * P.tiles_n + tn) * P.tiles_m + tm;
+    double2 *dst = partials + (P.part_off + tile_lin * P.ksplit + ks) * (long long)(BM * BN);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int il = wm * 32 + a * 16 + 4 * r + (lane >> 4);
+          const int jl = wn * 32 + b * 16 + (lane & 15);
+          dst[jl * BM + il] = make_double2(cr[a][b][r], ci[a][b][r]);
+        }
+  }
+}
+
+// Sums the split-K partials of every output tile in split order, then
+// C = alpha * sum + beta * C.  One thread per output element.
+template <bool TABLE>
+__global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZProb *__restrict__ table,
+                                                    int nprob, const double2 *__restrict__ partials, int n_limit) {
+  const ZProb *probs = TABLE ? table : batch.p;
+  const int per_tile = (BM * BN) / 256;  // blocks per tile
+  const int rt = blockIdx.x / per_tile;
+  const int sub = blockIdx.x % per_tile;
+  int pi = 0;
+  while (pi + 1 < nprob && probs[pi + 1].rtile_begin <= rt) ++pi;
+  const ZProb &P = probs[pi];
+  if (P.ksplit == 1) return;
+  const int tl = rt - P.rtile_begin;
+  const int tm = tl % P.tiles_m;
+  const int tn = (tl / P.tiles_m) % P.tiles_n;
+  const int bi = tl / (P.tiles_m * P.tiles_n);
+  const int e = sub * 256 + threadIdx.x;
+  const int il = e % BM, jl = e / BM;
+  const int i = tm * BM + il, j = tn * BN + jl;
+  const int nlim = (n_limit > 0 && n_limit < P.n) ? n_limit : P.n;
+  if (i >= P.m || j >= nlim) return;
+  const double2 *src = partials + (P.part_off + (long long)tl * P.ksplit) * (long long)(BM * BN) + e;
+  double2 s = make_double2(0.0, 0.0);
+  for (int q = 0; q < P.ksplit; ++q) s = cadd(s, src[(long long)q * BM * BN]);
+  double2 *C = P.C + (long long)bi * P.sC + (long long)i + (long long)j * P.ldc;
+  double2 v = cmul(P.alpha, s);
+  if (P.beta.x != 0.0 || P.beta.y != 0.0) v = cfma(P.beta, *C, v);
+  *C = v;
+}
+
+template <bool TABLE>
+hipError_t launch_impl(int opa, int opb, const ZBatch &b, const ZProb *table, const ZProb *host, int nprob,
+                       int total_tiles, double2 *partials, int n_limit, hipStream_t s) {
+  if (total_tiles <= 0) return hipSuccess;
+  dim3 grid(total_tiles), block(NT);
+#define LTD_ZG(OA, OB) \
+  hipLaunchKernelGGL((zgemm_kernel<OA, OB, TABLE>), grid, block, 0, s, b, table, nprob, partials, n_limit)
+  if (opa == OP_N && opb == OP_N) LTD_ZG(OP_N, OP_N);
+  else if (opa == OP_C && opb == OP_N) LTD_ZG(OP_C, OP_N);
+  else if (opa == OP_N && opb == OP_C) LTD_ZG(OP_N, OP_C);
+  else LTD_ZG(OP_C, OP_C);
+#undef LTD_ZG
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  bool split = false;
+  int rtiles = 0;
+  for (int i = 0; i < nprob; ++i) {
+    split = split || host[i].ksplit > 1;
+    rtiles = host[i].rtile_begin + host[i].tiles_m * host[i].tiles_n * host[i].batch;
+  }
+  if (!split) return hipSuccess;
+  hipLaunchKernelGGL((zgemm_reduce<TABLE>), dim3(rtiles * ((BM * BN) / 256)), dim3(256), 0, s, b, table, nprob,
+                     partials, n_limit);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t gemm_plan(ZProb *probs, int nprob, int *total_tiles, int target_blocks, long long max_part_tiles) {
+  int tb = 0, rb = 0;
+  long long part = 0;
+  for (int i = 0; i < nprob; ++i) {
+    ZProb &P = probs[i];
+    P.tiles_m = (P.m + BM - 1) / BM;
+    P.tiles_n = (P.n + BN - 1) / BN;
+    if (P.batch < 1) P.batch = 1;
+    const int base = P.tiles_m * P.tiles_n * P.batch;
+    const int kt = (P.k + BK - 1) / BK;
+    int ks = 1;
+    if (base < target_blocks && kt >= 16) {
+      ks = (target_blocks + base - 1) / base;
+      ks = ks < kt / 8 ? ks : kt / 8;
+      if (ks < 1) ks = 1;
+    }
+    if (ks > 1 && part + (long long)base * ks > max_part_tiles) {
+      const long long room = (max_part_tiles - part) / base;
+      ks = room > 1 ? (int)room : 1;
+    }
+    const int kt_per = (kt + ks - 1) / (ks > 0 ? ks : 1);
+    P.kchunk = (kt_per > 0 ? kt_per : 1) * BK;
+    P.ksplit = (P.k + P.kchunk - 1) / P.kchunk;
+    if (P.ksplit < 1) P.ksplit = 1;
+    P.tile_begin = tb;
+    P.rtile_begin = rb;
+    P.part_off = part;
+    tb += base * P.ksplit;
+    rb += base;
+    if (P.ksplit > 1) part += (long long)base * P.ksplit;
+  }
+  *total_tiles = tb;
+  return (size_t)part * BM * BN * sizeof(double2);
+}
+
+hipError_t gemm_launch(int opa, int opb, const ZBatch &b, double2 *partials, hipStream_t s) {
+  return launch_impl<false>(opa, opb, b, nullptr, b.p, b.nprob, b.total_tiles, partials, 0, s);
+}
+
+hipError_t gemm_launch_table(int opa, int opb, const ZProb *dev_table, const ZProb *host, int nprob,
+                             int total_tiles, double2 *partials, int n_limit, hipStream_t s) {
+  static const ZBatch empty{};
+  return launch_impl<true>(opa, opb, empty, dev_table, host, nprob, total_tiles, partials, n_limit, s);
+}
+
+}  // namespace ltd

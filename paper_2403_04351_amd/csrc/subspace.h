@@ -1,0 +1,74 @@
+// Device-side state of a bound auxiliary subspace and the launch contexts of
+// the per-step kernels.
+#pragma once
+
+#include "common.h"
+
+namespace ltd {
+
+constexpr int CHEB_KMAX = 96;  // largest Chebyshev degree of the step exponential
+
+// Per k-point subspace state (lives in the workspace; matrices n_aux x n_aux,
+// column-major, in the S-orthonormal basis Phi~ = Phi L^{-H} unless noted).
+struct SubDev {
+  const double2 *tt;       // T~ (interstitial kinetic)
+  const double2 *pt;       // P~ (momentum, z)
+  const double2 *vt_ref;   // V~ of the reference potential
+  const double2 *h0t;      // H~0 = T~ + V~_ref
+  double2 *vt_step;        // V~ rebuilt for the current step (raw, made Hermitian on use)
+  const double2 *L;        // Cholesky factor of S_sub (Phi basis), lower
+  const double2 *Linv;     // L^{-1}
+  double2 *work;           // n_states x n_aux^2 scratch when H~ does not fit in LDS
+  double kw;               // k-point weight
+  double c0, r;            // Chebyshev interval [c0 - r, c0 + r]
+  double margin;           // largest ||H~(t) - H~0||_F the interval covers
+  int K;                   // series degree for the current dt
+  double2 phase;           // exp(-i dt c0)
+  double2 coef[CHEB_KMAX + 1];
+};
+
+struct StepCtx {
+  const SubDev *sub;       // device array [n_k]
+  int n_aux, n_states, n_k;
+  int h_in_lds;
+  int rebuild;
+  const int *step;         // device step counter n
+  int *step_rw;            // same pointer, advanced by the finaliser
+  const double *a_t, *a_mid;
+  double c_light, occ, omega, dt;
+  double2 *theta;          // [n_k][n_states][n_aux]
+  double *part;            // [n_k * n_states][4] partial sums
+  int *status;
+  double *j_out, *e_out, *dmu_out;
+};
+
+struct AdjCtx {
+  int n;                   // step index (forward step n -> n+1), or N when terminal
+  int terminal;
+  int n_steps;
+  const double2 *mu_next;
+  double2 *mu_out;
+  double *dl_da_mid, *dl_da_t;
+};
+
+hipError_t launch_copy_rows(double2 *dst, int ldd, const double2 *src, int lds, int rows, int cols, bool zero,
+                            hipStream_t s);
+hipError_t launch_herm_split(const double2 *x, int ldx, int n, int nb, double2 *out, hipStream_t s);
+hipError_t launch_axpby(double2 *out, const double2 *a, const double2 *b, double sa, double sb, long long n,
+                        hipStream_t s);
+hipError_t launch_heff(double2 *out, const double2 *h, const double2 *p, const double2 *o, double al, double be,
+                       long long n, hipStream_t s);
+hipError_t launch_thv(double *out, const double *th, const double *v, long long n, hipStream_t s);
+hipError_t launch_cholesky(const double2 *S, double2 *L, int n, int *status, int *fail, hipStream_t s);
+hipError_t launch_trtri(const double2 *L, double2 *Li, int n, hipStream_t s);
+hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s);
+size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint);
+void subspace_init_attrs();  // LDS limits of the step kernels (call outside graph capture)
+hipError_t launch_step(const StepCtx &c, hipStream_t s);
+hipError_t launch_adjoint(const StepCtx &c, const AdjCtx &a, hipStream_t s);
+hipError_t launch_knot_samples(const double *q, int nk, double t_end, double dt, int ns, double *a_t,
+                               double *a_mid, hipStream_t s);
+hipError_t launch_knot_gradient(const double *g_t, const double *g_mid, int ns, double dt, int nk, double t_end,
+                                double *g_q, hipStream_t s);
+
+}  // namespace ltd

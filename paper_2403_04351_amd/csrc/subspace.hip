@@ -1,0 +1,744 @@
+// Subspace kernels: small dense FP64 linear algebra (Cholesky, triangular
+// inverse, Hermitian Jacobi eigensolver), the per-step propagation of the
+// subspace coefficients with observables, the adjoint step, and helpers of
+// the muffin-tin chain.
+//
+// The propagation works in the S-orthonormal basis Phi~ = Phi L^{-H}
+// (S_sub = L L^H): there H~ = L^{-1} H_sub L^{-H} is Hermitian, the step
+// propagator of the exponential midpoint rule is exp(-i dt H~(t_n + dt/2))
+// (Pela & Draxl, Sec. 2.2, Eq. (13); Sec. 2.1, Eq. (10)), and theta~ = L^H
+// theta.  The exponential is applied to each state as a Chebyshev series,
+// exp(-i dt H~) = exp(-i dt c0) sum_k c_k T_k(X), X = (H~ - c0)/r, with the
+// spectrum of H~ inside [c0 - r, c0 + r] and c_k = (2 - delta_k0) (-i)^k
+// J_k(r dt).  One workgroup propagates one state of one k-point; H~ stays in
+// LDS for the whole series.
+#include "common.h"
+#include "subspace.h"
+
+#include <cmath>
+
+namespace ltd {
+
+namespace {
+
+__device__ inline void latch(int *status, int code) {
+  if (status) atomicCAS(status, 0, code);
+}
+
+// Block-wide y = op(A) v, A n x n column-major with leading dimension lda
+// (LDS or global); v, y in LDS (y must not alias v); red: blockDim doubles2.
+template <bool CONJT>
+__device__ void matvec(const double2 *A, int lda, const double2 *v, double2 *y, int n, double2 *red) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (n <= nt) {
+    const int np = nt / n;
+    const int i = t % n, part = t / n;
+    double2 s = make_double2(0.0, 0.0);
+    if (part < np) {
+      const int k0 = (part * n) / np, k1 = ((part + 1) * n) / np;
+      for (int k = k0; k < k1; ++k) {
+        if (CONJT) s = cfma(cconj(A[(long long)k + (long long)i * lda]), v[k], s);
+        else s = cfma(A[(long long)i + (long long)k * lda], v[k], s);
+      }
+    }
+    red[t] = s;
+    __syncthreads();
+    if (t < n) {
+      double2 acc = red[t];
+      for (int p = 1; p < np; ++p) acc = cadd(acc, red[p * n + t]);
+      y[t] = acc;
+    }
+    __syncthreads();
+  } else {
+    for (int i = t; i < n; i += nt) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int k = 0; k < n; ++k) {
+        if (CONJT) s = cfma(cconj(A[(long long)k + (long long)i * lda]), v[k], s);
+        else s = cfma(A[(long long)i + (long long)k * lda], v[k], s);
+      }
+      y[i] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Block-wide sum of one double per thread (fixed order); result valid in all threads.
+__device__ double block_sum(double x, double *sred) {
+  const int t = threadIdx.x;
+  sred[t] = x;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sred[t] += sred[t + s];
+    __syncthreads();
+  }
+  const double r = sred[0];
+  __syncthreads();
+  return r;
+}
+
+// Re sum_i conj(a_i) b_i over n entries in LDS (block-wide, fixed order).
+__device__ double dot_re(const double2 *a, const double2 *b, int n, double *sred) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += a[i].x * b[i].x + a[i].y * b[i].y;
+  return block_sum(s, sred);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers
+// ---------------------------------------------------------------------------
+__global__ void k_copy_rows(double2 *dst, int ldd, const double2 *src, int lds, int rows, int cols, int zero) {
+  const long long tot = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % rows), j = (int)(e / rows);
+    dst[r + (long long)j * ldd] = zero ? make_double2(0.0, 0.0) : src[r + (long long)j * lds];
+  }
+}
+
+__global__ void k_herm_split(const double2 *x, int ldx, int n, int nb, double2 *out) {
+  // out[b] (n x n, contiguous) = (X_b + X_b^H)/2 with X_b = x[:, b*n:(b+1)*n]
+  const long long tot = (long long)nb * n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(e / ((long long)n * n));
+    const int r = (int)(e % ((long long)n * n));
+    const int i = r % n, j = r / n;
+    const double2 a = x[i + (long long)(b * n + j) * ldx];
+    const double2 c = x[j + (long long)(b * n + i) * ldx];
+    out[e] = make_double2(0.5 * (a.x + c.x), 0.5 * (a.y - c.y));
+  }
+}
+
+__global__ void k_axpby_n2(double2 *out, const double2 *a, const double2 *b, double sa, double sb, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    out[e] = make_double2(sa * a[e].x + sb * b[e].x, sa * a[e].y + sb * b[e].y);
+}
+
+__global__ void k_heff(double2 *out, const double2 *h, const double2 *p, const double2 *o, double al, double be,
+                       long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    out[e] = make_double2(h[e].x + al * p[e].x + be * o[e].x, h[e].y + al * p[e].y + be * o[e].y);
+}
+
+__global__ void k_thv(double *out, const double *th, const double *v, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    out[e] = th[e] * v[e];
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky S = L L^H (lower), one workgroup, left-looking by columns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_cholesky(const double2 *S, double2 *L, int n, int *status, int *fail) {
+  __shared__ double2 col[320];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  for (long long e = t; e < (long long)n * n; e += blockDim.x) L[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    for (int i = j + t; i < n; i += blockDim.x) {
+      double2 s = S[i + (long long)j * n];
+      for (int k = 0; k < j; ++k) s = csub(s, cmul(L[i + (long long)k * n], cconj(L[j + (long long)k * n])));
+      col[i] = s;
+    }
+    __syncthreads();
+    const double d = col[j].x;
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (t == 0) bad = 1;
+      __syncthreads();
+      break;
+    }
+    const double sd = sqrt(d);
+    for (int i = j + t; i < n; i += blockDim.x)
+      L[i + (long long)j * n] = (i == j) ? make_double2(sd, 0.0) : cscale(col[i], 1.0 / sd);
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (bad) latch(status, 2);
+    if (fail) *fail = bad;
+  }
+}
+
+// Inverse of a lower-triangular matrix, one thread per column (forward substitution).
+__global__ void k_trtri(const double2 *L, double2 *Li, int n) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  for (int i = 0; i < c; ++i) Li[i + (long long)c * n] = make_double2(0.0, 0.0);
+  for (int i = c; i < n; ++i) {
+    double2 s = (i == c) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+    for (int k = c; k < i; ++k) s = csub(s, cmul(L[i + (long long)k * n], Li[k + (long long)c * n]));
+    const double2 d = L[i + (long long)i * n];
+    const double den = d.x * d.x + d.y * d.y;
+    Li[i + (long long)c * n] = make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hermitian eigensolver: cyclic two-sided Jacobi with round-robin parallel
+// ordering (disjoint rotations applied together), one workgroup.  A (n x n,
+// column-major, global) is overwritten; V (if non-null) receives the
+// eigenvectors as columns; w the eigenvalues, ascending (V sorted along).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_jacobi(double2 *A, double2 *V, double *w, int n, int max_sweeps) {
+  __shared__ double sc[160], ss[160];
+  __shared__ double2 se[160];
+  __shared__ int sp[160], sq[160];
+  __shared__ double sred[1024];
+  __shared__ int perm[320];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int m = (n + 1) & ~1;  // players (one dummy if n is odd)
+  const int half = m / 2;
+  if (V)
+    for (long long e = t; e < (long long)n * n; e += nt) {
+      const int i = (int)(e % n), j = (int)(e / n);
+      V[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (long long e = t; e < (long long)n * n; e += nt) {
+      const int i = (int)(e % n), j = (int)(e / n);
+      const double a2 = A[e].x * A[e].x + A[e].y * A[e].y;
+      tot += a2;
+      if (i != j) off += a2;
+    }
+    off = block_sum(off, sred);
+    tot = block_sum(tot, sred);
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int round = 0; round < m - 1; ++round) {
+      for (int s = t; s < half; s += nt) {
+        // circle method: position 0 fixed, others rotate
+        auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (m - 1); };
+        int p = player(s), q = player(m - 1 - s);
+        if (p > q) {
+          const int x = p;
+          p = q;
+          q = x;
+        }
+        sp[s] = p;
+        sq[s] = q;
+        double c = 1.0, sn = 0.0;
+        double2 e = make_double2(1.0, 0.0);
+        if (q < n) {
+          const double2 apq = A[p + (long long)q * n];
+          const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+          const double app = A[p + (long long)p * n].x, aqq = A[q + (long long)q * n].x;
+          if (mag > 0.0) {
+            e = make_double2(apq.x / mag, apq.y / mag);
+            const double zeta = (aqq - app) / (2.0 * mag);
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            sn = tt * c;
+          }
+        }
+        sc[s] = c;
+        ss[s] = sn;
+        se[s] = e;
+      }
+      __syncthreads();
+      // columns: A[:,p], A[:,q] <- c A_p - s conj(e) A_q,  s A_p + c conj(e) A_q ; same for V
+      for (long long e2 = t; e2 < (long long)half * n; e2 += nt) {
+        const int s = (int)(e2 / n), i = (int)(e2 % n);
+        const int p = sp[s], q = sq[s];
+        if (q >= n || ss[s] == 0.0) continue;
+        const double c = sc[s], sn = ss[s];
+        const double2 ec = cconj(se[s]);
+        double2 *ap = A + i + (long long)p * n, *aq = A + i + (long long)q * n;
+        const double2 x = *ap, y = cmul(ec, *aq);
+        *ap = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+        *aq = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+        if (V) {
+          double2 *vp = V + i + (long long)p * n, *vq = V + i + (long long)q * n;
+          const double2 vx = *vp, vy = cmul(ec, *vq);
+          *vp = make_double2(c * vx.x - sn * vy.x, c * vx.y - sn * vy.y);
+          *vq = make_double2(sn * vx.x + c * vy.x, sn * vx.y + c * vy.y);
+        }
+      }
+      __syncthreads();
+      // rows: A[p,:], A[q,:] <- c A_p - s e A_q,  s A_p + c e A_q
+      for (long long e2 = t; e2 < (long long)half * n; e2 += nt) {
+        const int s = (int)(e2 / n), j = (int)(e2 % n);
+        const int p = sp[s], q = sq[s];
+        if (q >= n || ss[s] == 0.0) continue;
+        const double c = sc[s], sn = ss[s];
+        const double2 ev = se[s];
+        double2 *ap = A + p + (long long)j * n, *aq = A + q + (long long)j * n;
+        const double2 x = *ap, y = cmul(ev, *aq);
+        *ap = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+        *aq = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+      }
+      __syncthreads();
+    }
+  }
+  // sort ascending (selection by rank, ties by index)
+  for (int i = t; i < n; i += nt) {
+    const double di = A[i + (long long)i * n].x;
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double dj = A[j + (long long)j * n].x;
+      rank += (dj < di) || (dj == di && j < i);
+    }
+    perm[rank] = i;
+  }
+  __syncthreads();
+  for (int r = t; r < n; r += nt) w[r] = A[perm[r] + (long long)perm[r] * n].x;
+  if (V) {
+    // permute columns through A's strictly-lower part is not possible in place; use A as scratch
+    __syncthreads();
+    for (long long e = t; e < (long long)n * n; e += nt) A[e] = V[e];
+    __syncthreads();
+    for (long long e = t; e < (long long)n * n; e += nt) {
+      const int i = (int)(e % n), r = (int)(e / n);
+      V[e] = A[i + (long long)perm[r] * n];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-step propagation of one state (blockIdx.x) of one k-point (blockIdx.y).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_step(const StepCtx c) {
+  extern __shared__ double2 sm[];
+  const int j = blockIdx.x, k = blockIdx.y;
+  const SubDev &S = c.sub[k];
+  const int n = c.n_aux;
+  const bool hl = c.h_in_lds;
+  double2 *Hm = hl ? sm : S.work + (long long)j * n * n;  // (H~(mid) - c0)/r
+  double2 *vec = hl ? sm + (long long)n * n : sm;
+  double2 *v = vec, *t0 = vec + n, *t1 = vec + 2 * n, *acc = vec + 3 * n, *tmp = vec + 4 * n, *w = vec + 5 * n;
+  double2 *red = vec + 6 * n;
+  double *sred = reinterpret_cast<double *>(red + blockDim.x);
+  const int step = *c.step;
+  const double am = c.a_mid[step], a1 = c.a_t[step + 1];
+  const double cl = c.c_light;
+  const double al = am / cl, be = am * am / (2.0 * cl * cl);
+  const double ir = 1.0 / S.r;
+
+  // 1. H~(mid) = T~ + V~ + (A/c) P~ + (A^2/2c^2) I, shifted and scaled; spectral check
+  double dev2 = 0.0;
+  const double2 *Vs = c.rebuild ? S.vt_step : S.vt_ref;
+  for (long long e = threadIdx.x; e < (long long)n * n; e += blockDim.x) {
+    const int a = (int)(e % n), b = (int)(e / n);
+    double2 vv;
+    if (c.rebuild) {  // Hermitian part of the rebuilt matrix
+      const double2 x = Vs[e], y = Vs[b + (long long)a * n];
+      vv = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    } else {
+      vv = Vs[e];
+    }
+    double2 h = cadd(S.tt[e], vv);
+    h = cadd(h, cscale(S.pt[e], al));
+    if (a == b) h.x += be;
+    const double2 d = csub(h, S.h0t[e]);
+    dev2 += d.x * d.x + d.y * d.y;
+    if (a == b) h.x -= S.c0;
+    Hm[e] = cscale(h, ir);
+  }
+  dev2 = block_sum(dev2, sred);
+  if (j == 0 && threadIdx.x == 0 && !(sqrt(dev2) <= S.margin)) latch(c.status, 4);
+
+  // 2. theta~ = L^H theta
+  double2 *th = c.theta + (long long)k * n * c.n_states + (long long)j * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tmp[i] = th[i];
+  __syncthreads();
+  matvec<true>(S.L, n, tmp, v, n, red);
+
+  // observables of theta~ in v at A = a (H~(a) v built from M v):
+  //   J = -(f/Omega) w_k Re(v^H P~ v + (a/c) v^H v),  E = f w_k Re v^H H~(a) v
+  auto observe = [&](double a, double *jo, double *eo) {
+    matvec<false>(Hm, n, v, t0, n, red);      // t0 = M v
+    matvec<false>(S.pt, n, v, t1, n, red);    // t1 = P~ v
+    const double vv = dot_re(v, v, n, sred);
+    const double vp = dot_re(v, t1, n, sred);
+    const double vm = dot_re(v, t0, n, sred);
+    // v^H H~(a) v = r vm + c0 vv + ((a - am)/c) vp + ((a^2 - am^2)/2c^2) vv
+    const double vh = S.r * vm + S.c0 * vv + ((a - am) / cl) * vp + ((a * a - am * am) / (2.0 * cl * cl)) * vv;
+    if (threadIdx.x == 0) {
+      *jo = -(c.occ / c.omega) * S.kw * (vp + (a / cl) * vv);
+      *eo = c.occ * S.kw * vh;
+    }
+    __syncthreads();
+  };
+  double *part = c.part + 4 * ((long long)k * c.n_states + j);
+  if (step == 0) observe(c.a_t[0], part + 2, part + 3);
+
+  // 3. Chebyshev series
+  const int K = S.K;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) t0[i] = v[i];
+  __syncthreads();
+  matvec<false>(Hm, n, v, t1, n, red);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc[i] = cadd(cmul(S.coef[0], t0[i]), cmul(S.coef[1], t1[i]));
+  __syncthreads();
+  double2 *pa = t0, *pb = t1;  // T_{k-2}, T_{k-1}
+  for (int q = 2; q <= K; ++q) {
+    matvec<false>(Hm, n, pb, tmp, n, red);
+    const double2 cq = S.coef[q];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double2 tn = make_double2(2.0 * tmp[i].x - pa[i].x, 2.0 * tmp[i].y - pa[i].y);
+      pa[i] = tn;  // becomes T_q
+      acc[i] = cfma(cq, tn, acc[i]);
+    }
+    __syncthreads();
+    double2 *x = pa;
+    pa = pb;
+    pb = x;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = cmul(S.phase, acc[i]);
+  __syncthreads();
+
+  // 4. theta = L^{-H} theta~
+  matvec<true>(S.Linv, n, v, w, n, red);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) th[i] = w[i];
+
+  // 5. observables at t_{n+1}
+  observe(a1, part + 0, part + 1);
+}
+
+// Sums the per-state partials in a fixed order, writes the series, advances the step.
+__global__ void k_finalize(const StepCtx c) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int step = *c.step;
+  const int np = c.n_k * c.n_states;
+  double j1 = 0.0, e1 = 0.0, j0 = 0.0, e0 = 0.0;
+  for (int p = 0; p < np; ++p) {
+    j1 += c.part[4 * p + 0];
+    e1 += c.part[4 * p + 1];
+    j0 += c.part[4 * p + 2];
+    e0 += c.part[4 * p + 3];
+  }
+  if (step == 0) {
+    c.j_out[0] = j0;
+    c.e_out[0] = e0;
+    c.dmu_out[0] = 0.0;
+  }
+  const double jz = c.j_out[0];
+  c.j_out[step + 1] = j1;
+  c.e_out[step + 1] = e1;
+  c.dmu_out[step + 1] = c.dmu_out[step] + c.omega * c.dt * 0.5 * ((c.j_out[step] - jz) + (j1 - jz));
+  if (!isfinite(j1) || !isfinite(e1)) latch(c.status, 3);
+  *c.step_rw = step + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint step for one state (blockIdx.x) of one k-point (blockIdx.y).
+// In the S-orthonormal basis (theta~ = L^H theta, mu~ = L^{-1} mu, so that
+// Re <mu, d theta> = Re <mu~, d theta~>):
+//   mu~_n = U~^H mu~_{n+1} + dt w_n g~_n,  g~_n = -(2f/Omega) w_k (P~ + A_n/c) theta~_n
+//   dL/dA_mid = Re <mu~_{n+1}, (dU~/dA) theta~_n>,
+// where dU~/dA is the derivative of the same Chebyshev series:
+//   T'_0 = 0, T'_1 = E, T'_q = 2 E T_{q-1} + 2 X T'_{q-1} - T'_{q-2},
+//   E = dX/dA = (P~/c + (A/c^2) I)/r,
+// and U~^H = conj(phase) sum conj(c_q) T_q(X) (X Hermitian).
+// Per-state partials: part[4p+0] midpoint term, part[4p+1] dt w_n dJ_n/dA_n,
+// part[4p+2] dJ_n/dA_n.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adjoint(const StepCtx c, const AdjCtx ac) {
+  extern __shared__ double2 sm[];
+  const int j = blockIdx.x, k = blockIdx.y;
+  const SubDev &S = c.sub[k];
+  const int n = c.n_aux;
+  const bool hl = c.h_in_lds;
+  double2 *Hm = hl ? sm : S.work + (long long)j * n * n;
+  double2 *vec = hl ? sm + (long long)n * n : sm;
+  double2 *v = vec, *mu = vec + n, *ta = vec + 2 * n, *tb = vec + 3 * n, *da = vec + 4 * n;
+  double2 *db = vec + 5 * n, *tmp = vec + 6 * n, *tmp2 = vec + 7 * n, *xdt = vec + 8 * n;
+  double2 *acc = vec + 9 * n, *dacc = vec + 10 * n;
+  double2 *red = vec + 11 * n;
+  double *sred = reinterpret_cast<double *>(red + blockDim.x);
+  const int step = ac.n;
+  const double cl = c.c_light;
+  const double an = c.a_t[step];
+  const double wn = (step == 0 || step == ac.n_steps) ? 0.5 : 1.0;
+  const double ir = 1.0 / S.r;
+  const double gs = -(2.0 * c.occ / c.omega) * S.kw;
+  double *part = c.part + 4 * ((long long)k * c.n_states + j);
+  double2 *mo = ac.mu_out + (long long)k * n * c.n_states + (long long)j * n;
+
+  const double2 *th = c.theta + (long long)k * n * c.n_states + (long long)j * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tmp[i] = th[i];
+  __syncthreads();
+  matvec<true>(S.L, n, tmp, v, n, red);  // theta~_n
+  const double vv = dot_re(v, v, n, sred);
+  const double djda = -(c.occ / (c.omega * cl)) * S.kw * vv;
+  matvec<false>(S.pt, n, v, tmp2, n, red);  // P~ theta~_n (for the source term)
+
+  if (ac.terminal) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      tmp[i] = cscale(cadd(tmp2[i], cscale(v[i], an / cl)), gs * c.dt * wn);
+    __syncthreads();
+    matvec<false>(S.L, n, tmp, acc, n, red);  // mu_N = L mu~_N
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mo[i] = acc[i];
+    if (threadIdx.x == 0) {
+      part[0] = 0.0;
+      part[1] = c.dt * wn * djda;
+      part[2] = djda;
+    }
+    return;
+  }
+  // keep the source term: xdt <- dt w_n g~_n (zero at n = 0: the initial state is fixed)
+  const double sw = (step >= 1) ? gs * c.dt * wn : 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) xdt[i] = cscale(cadd(tmp2[i], cscale(v[i], an / cl)), sw);
+
+  const double am = c.a_mid[step];
+  const double al = am / cl, be = am * am / (2.0 * cl * cl);
+  for (long long e = threadIdx.x; e < (long long)n * n; e += blockDim.x) {
+    const int a = (int)(e % n), b = (int)(e / n);
+    double2 vv2;
+    if (c.rebuild) {
+      const double2 x = S.vt_step[e], y = S.vt_step[b + (long long)a * n];
+      vv2 = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    } else {
+      vv2 = S.vt_ref[e];
+    }
+    double2 h = cadd(S.tt[e], vv2);
+    h = cadd(h, cscale(S.pt[e], al));
+    if (a == b) h.x += be - S.c0;
+    Hm[e] = cscale(h, ir);
+  }
+  // mu~_{n+1} = L^{-1} mu_{n+1}
+  const double2 *mn = ac.mu_next + (long long)k * n * c.n_states + (long long)j * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tmp[i] = mn[i];
+  __syncthreads();
+  matvec<false>(S.Linv, n, tmp, mu, n, red);
+
+  // derivative of the series applied to theta~_n
+  auto apply_e = [&](const double2 *y, double2 *out) {  // out = E y
+    matvec<false>(S.pt, n, y, tmp2, n, red);
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      out[i] = cscale(cadd(cscale(tmp2[i], 1.0 / cl), cscale(y[i], am / (cl * cl))), ir);
+    __syncthreads();
+  };
+  const int K = S.K;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    ta[i] = v[i];
+    da[i] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  matvec<false>(Hm, n, v, tb, n, red);  // T_1 v
+  apply_e(v, db);                        // T'_1 v
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dacc[i] = cmul(S.coef[1], db[i]);
+  __syncthreads();
+  for (int q = 2; q <= K; ++q) {
+    double2 *et = acc;                    // scratch: E T_{q-1} v
+    apply_e(tb, et);
+    matvec<false>(Hm, n, db, tmp, n, red);  // X T'_{q-1} v
+    double2 *xt = tmp2;
+    matvec<false>(Hm, n, tb, xt, n, red);  // X T_{q-1} v
+    const double2 cq = S.coef[q];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double2 tn = make_double2(2.0 * xt[i].x - ta[i].x, 2.0 * xt[i].y - ta[i].y);
+      const double2 dn = make_double2(2.0 * et[i].x + 2.0 * tmp[i].x - da[i].x,
+                                      2.0 * et[i].y + 2.0 * tmp[i].y - da[i].y);
+      ta[i] = tn;
+      da[i] = dn;
+      dacc[i] = cfma(cq, dn, dacc[i]);
+    }
+    __syncthreads();
+    double2 *x = ta;
+    ta = tb;
+    tb = x;
+    x = da;
+    da = db;
+    db = x;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dacc[i] = cmul(S.phase, dacc[i]);
+  __syncthreads();
+  const double dmid = dot_re(mu, dacc, n, sred);
+
+  // U~^H mu~_{n+1}
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ta[i] = mu[i];
+  __syncthreads();
+  matvec<false>(Hm, n, mu, tb, n, red);
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    acc[i] = cadd(cmul(cconj(S.coef[0]), ta[i]), cmul(cconj(S.coef[1]), tb[i]));
+  __syncthreads();
+  for (int q = 2; q <= K; ++q) {
+    matvec<false>(Hm, n, tb, tmp, n, red);
+    const double2 cq = cconj(S.coef[q]);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double2 tn = make_double2(2.0 * tmp[i].x - ta[i].x, 2.0 * tmp[i].y - ta[i].y);
+      ta[i] = tn;
+      acc[i] = cfma(cq, tn, acc[i]);
+    }
+    __syncthreads();
+    double2 *x = ta;
+    ta = tb;
+    tb = x;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tmp[i] = cadd(cmul(cconj(S.phase), acc[i]), xdt[i]);
+  __syncthreads();
+  matvec<false>(S.L, n, tmp, ta, n, red);  // mu_n = L mu~_n
+  for (int i = threadIdx.x; i < n; i += blockDim.x) mo[i] = ta[i];
+  if (threadIdx.x == 0) {
+    part[0] = dmid;
+    part[1] = c.dt * wn * djda;
+    part[2] = djda;
+  }
+}
+
+// Sums the adjoint partials in a fixed order.
+__global__ void k_adjoint_finalize(const StepCtx c, const AdjCtx ac) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int np = c.n_k * c.n_states;
+  double dm = 0.0, dt_ = 0.0, dj = 0.0;
+  for (int p = 0; p < np; ++p) {
+    dm += c.part[4 * p + 0];
+    dt_ += c.part[4 * p + 1];
+    dj += c.part[4 * p + 2];
+  }
+  if (!ac.terminal) ac.dl_da_mid[ac.n] = dm;
+  // the J_0 subtracted in J_ind: L contains -T J_0, T = N dt
+  if (ac.n == 0) dt_ -= ac.n_steps * c.dt * dj;
+  ac.dl_da_t[ac.n] = dt_;
+}
+
+// ---------------------------------------------------------------------------
+// Piecewise-linear pulse on uniform knots and its chain rule.
+// ---------------------------------------------------------------------------
+__device__ inline void hat_pair(double t, int nk, double h, int *i0, double *w1) {
+  int i = (int)floor(t / h);
+  if (i < 0) i = 0;
+  if (i > nk - 2) i = nk - 2;
+  *i0 = i;
+  *w1 = (t - i * h) / h;
+}
+
+__global__ void k_knot_samples(const double *q, int nk, double t_end, double dt, int ns, double *a_t,
+                               double *a_mid) {
+  const double h = t_end / (nk - 1);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * ns + 1; e += gridDim.x * blockDim.x) {
+    const bool mid = e > ns;
+    const int n = mid ? e - ns - 1 : e;
+    const double t = (n + (mid ? 0.5 : 0.0)) * dt;
+    int i0;
+    double w1;
+    hat_pair(t, nk, h, &i0, &w1);
+    const double v = (1.0 - w1) * q[i0] + w1 * q[i0 + 1];
+    if (mid) a_mid[n] = v;
+    else a_t[n] = v;
+  }
+}
+
+// One thread per knot sums its support in time order (deterministic).
+__global__ void k_knot_gradient(const double *g_t, const double *g_mid, int ns, double dt, int nk, double t_end,
+                                double *g_q) {
+  const int kq = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kq >= nk) return;
+  const double h = t_end / (nk - 1);
+  double s = 0.0;
+  for (int e = 0; e < 2 * ns + 1; ++e) {
+    const bool mid = e > ns;
+    const int n = mid ? e - ns - 1 : e;
+    const double t = (n + (mid ? 0.5 : 0.0)) * dt;
+    int i0;
+    double w1;
+    hat_pair(t, nk, h, &i0, &w1);
+    const double g = mid ? g_mid[n] : g_t[n];
+    if (i0 == kq) s += (1.0 - w1) * g;
+    if (i0 + 1 == kq) s += w1 * g;
+  }
+  g_q[kq] = s;
+}
+
+}  // namespace
+
+hipError_t launch_copy_rows(double2 *dst, int ldd, const double2 *src, int lds, int rows, int cols, bool zero,
+                            hipStream_t s) {
+  const long long tot = (long long)rows * cols;
+  if (tot <= 0) return hipSuccess;
+  const int nb = (int)((tot + 255) / 256 < 4096 ? (tot + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_copy_rows, dim3(nb), dim3(256), 0, s, dst, ldd, src, lds, rows, cols, zero ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_herm_split(const double2 *x, int ldx, int n, int nb, double2 *out, hipStream_t s) {
+  const long long tot = (long long)nb * n * n;
+  if (tot <= 0) return hipSuccess;
+  const int g = (int)((tot + 255) / 256 < 4096 ? (tot + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_herm_split, dim3(g), dim3(256), 0, s, x, ldx, n, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double2 *out, const double2 *a, const double2 *b, double sa, double sb, long long n,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int g = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_axpby_n2, dim3(g), dim3(256), 0, s, out, a, b, sa, sb, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_heff(double2 *out, const double2 *h, const double2 *p, const double2 *o, double al, double be,
+                       long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int g = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_heff, dim3(g), dim3(256), 0, s, out, h, p, o, al, be, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_thv(double *out, const double *th, const double *v, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int g = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_thv, dim3(g), dim3(256), 0, s, out, th, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky(const double2 *S, double2 *L, int n, int *status, int *fail, hipStream_t s) {
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, S, L, n, status, fail);
+  return hipGetLastError();
+}
+
+hipError_t launch_trtri(const double2 *L, double2 *Li, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_trtri, dim3((n + 63) / 64), dim3(64), 0, s, L, Li, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, A, V, w, n, 40);
+  return hipGetLastError();
+}
+
+size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint) {
+  const size_t vecs = adjoint ? 11 : 6;
+  return ((h_in_lds ? (size_t)n * n : 0) + vecs * n + 256) * sizeof(double2) + 256 * sizeof(double);
+}
+
+static bool g_step_attr = false;
+
+void subspace_init_attrs() {
+  if (g_step_attr) return;
+  (void)hipFuncSetAttribute((const void *)k_step, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipFuncSetAttribute((const void *)k_adjoint, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  g_step_attr = true;
+}
+
+hipError_t launch_step(const StepCtx &c, hipStream_t s) {
+  subspace_init_attrs();
+  hipLaunchKernelGGL(k_step, dim3(c.n_states, c.n_k), dim3(256), step_lds_bytes(c.n_aux, c.h_in_lds, false), s, c);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const StepCtx &c, const AdjCtx &a, hipStream_t s) {
+  subspace_init_attrs();
+  hipLaunchKernelGGL(k_adjoint, dim3(c.n_states, c.n_k), dim3(256), step_lds_bytes(c.n_aux, c.h_in_lds, true), s,
+                     c, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adjoint_finalize, dim3(1), dim3(64), 0, s, c, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_knot_samples(const double *q, int nk, double t_end, double dt, int ns, double *a_t,
+                               double *a_mid, hipStream_t s) {
+  const int tot = 2 * ns + 1;
+  hipLaunchKernelGGL(k_knot_samples, dim3((tot + 255) / 256), dim3(256), 0, s, q, nk, t_end, dt, ns, a_t, a_mid);
+  return hipGetLastError();
+}
+
+hipError_t launch_knot_gradient(const double *g_t, const double *g_mid, int ns, double dt, int nk, double t_end,
+                                double *g_q, hipStream_t s) {
+  hipLaunchKernelGGL(k_knot_gradient, dim3((nk + 63) / 64), dim3(64), 0, s, g_t, g_mid, ns, dt, nk, t_end, g_q);
+  return hipGetLastError();
+}
+
+}  // namespace ltd

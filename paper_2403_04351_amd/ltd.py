@@ -1,0 +1,299 @@
+"""Python binding of the ltd library: argument marshalling between torch
+tensors and the C ABI of include/ltd.h.  Every computation runs in the HIP
+library; torch only provides device memory and the stream.
+
+Matrix convention: a column-major rows x cols matrix is a contiguous torch
+tensor of shape (cols, rows) (``colmajor``/``to_numpy`` convert from/to a
+numpy (rows, cols) array).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import AdjointArgs, StepArgs, SystemDesc, check
+
+LTD_STEP_REBUILD = _lib.LTD_STEP_REBUILD
+LTD_STEP_AFFINE = _lib.LTD_STEP_AFFINE
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def colmajor(a: np.ndarray, device) -> "torch.Tensor":
+    """numpy (rows, cols) -> device tensor (cols, rows) holding the column-major matrix."""
+    t = _torch()
+    return t.from_numpy(np.ascontiguousarray(np.asarray(a).T)).to(device)
+
+
+def to_numpy(x) -> np.ndarray:
+    """device tensor (cols, rows) -> numpy (rows, cols)."""
+    return x.detach().cpu().numpy().T
+
+
+def _ptr(x) -> int:
+    return 0 if x is None else int(x.data_ptr())
+
+
+class Ltd:
+    """One ltd system bound to a device workspace."""
+
+    def __init__(self, sys, device="cuda", max_cols=None, precision=_lib.LTD_FP64):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.sysdef = sys
+        self.device = torch.device(device)
+        dev = self.device
+        kp = sys.kpts
+        self.n_k = len(kp)
+        self.n_aux = sys.n_aux
+        self.n_states = sys.n_states
+        self.n_basis = [sys.n_basis(k) for k in range(self.n_k)]
+        # host arrays (kept alive: the library copies them at create)
+        self._n_g = np.array([k.n_g for k in kp], dtype=np.int32)
+        self._g_int = np.ascontiguousarray(np.concatenate([k.g_int for k in kp]).astype(np.int32))
+        self._gk = np.ascontiguousarray(np.concatenate([k.gk for k in kp]).astype(np.float64))
+        self._n_mt = np.array([a.n_mt for a in sys.atoms], dtype=np.int32)
+        self._n_lo = np.array([a.n_lo for a in sys.atoms], dtype=np.int32)
+        self._kw = np.array([k.weight for k in kp], dtype=np.float64)
+        # device arrays (kept alive: the library keeps their pointers)
+        self.theta_r = torch.from_numpy(np.ascontiguousarray(sys.theta.ravel())).to(dev)
+        self.v_r = torch.from_numpy(np.ascontiguousarray(sys.vr.ravel())).to(dev)
+        amats = [np.ascontiguousarray(k.A.T).ravel() for k in kp]
+        if sum(a.size for a in amats) == 0:
+            amats = [np.zeros(1, dtype=np.complex128)]
+        self.amat = torch.from_numpy(np.concatenate(amats)).to(dev)
+        def blk(xs):
+            if not xs:  # no atoms: a placeholder the library never reads
+                return torch.zeros(1, dtype=torch.complex128, device=dev)
+            return torch.from_numpy(np.concatenate([np.ascontiguousarray(x.T).ravel() for x in xs])).to(dev)
+
+        self.h = blk(sys.h)
+        self.o = blk(sys.o)
+        self.pz = blk(sys.pz)
+        self.max_cols = max(sys.n_aux, sys.n_states) if max_cols is None else max_cols
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int))
+        self._desc = SystemDesc(
+            n_k=self.n_k, n_g=ip(self._n_g), g_int=self._g_int.ctypes.data_as(C.POINTER(C.c_int32)),
+            gk_cart=self._gk.ctypes.data_as(C.POINTER(C.c_double)), grid=(C.c_int * 3)(*sys.grid),
+            theta_r=_ptr(self.theta_r), v_r=_ptr(self.v_r), n_atoms=sys.n_atoms, n_mt=ip(self._n_mt),
+            n_lo=ip(self._n_lo), amat=_ptr(self.amat), h=_ptr(self.h), o=_ptr(self.o), pz=_ptr(self.pz),
+            omega=sys.omega, c_light=sys.c_light, occ=sys.occ,
+            k_weight=self._kw.ctypes.data_as(C.POINTER(C.c_double)), n_aux=sys.n_aux,
+            n_states=sys.n_states, max_cols=self.max_cols)
+        wsb = C.c_size_t(0)
+        handle = C.c_void_p(0)
+        check(self.lib.ltd_create(C.byref(self._desc), precision, C.byref(wsb), C.byref(handle)), "ltd_create")
+        self.handle = handle
+        self.ws_bytes = wsb.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        check(self.lib.ltd_bind_workspace(self.handle, _ptr(self.ws), self.ws_bytes, self.stream()),
+              "ltd_bind_workspace")
+        self._phis = {}
+
+    # ------------------------------------------------------------------
+    def stream(self) -> int:
+        return int(_torch().cuda.current_stream(self.device).cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.ltd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync_status(self) -> int:
+        return int(self.lib.ltd_sync_status(self.handle, self.stream()))
+
+    # ------------------------------------------------------------------
+    def apply_hs(self, k: int, c, a_z: float = 0.0):
+        """H(A) C and S C; c: tensor (n, N_basis) (column-major N_basis x n)."""
+        torch = _torch()
+        n, nb = c.shape
+        hc = torch.empty_like(c)
+        sc = torch.empty_like(c)
+        a = (C.c_double * 3)(0.0, 0.0, float(a_z))
+        check(self.lib.ltd_apply_HS(self.handle, k, a, _ptr(c), nb, n, _ptr(hc), nb, _ptr(sc), nb, self.stream()),
+              "ltd_apply_HS")
+        return hc, sc
+
+    def project_subspace(self, k: int, phi, c=None):
+        """Binds phi (tensor (n_aux, N_basis)); returns H0_sub, S_sub (tensors (n, n),
+        column-major) and, if c is given, theta (tensor (n_states, n_aux))."""
+        torch = _torch()
+        n = self.n_aux
+        h0 = torch.empty((n, n), dtype=torch.complex128, device=self.device)
+        s = torch.empty_like(h0)
+        th = None
+        if c is not None:
+            th = torch.empty((c.shape[0], n), dtype=torch.complex128, device=self.device)
+        self._phis[k] = phi
+        check(self.lib.ltd_project_subspace(self.handle, k, _ptr(phi), phi.shape[1], n, _ptr(h0), _ptr(s),
+                                            _ptr(c), c.shape[1] if c is not None else 0,
+                                            c.shape[0] if c is not None else 0, _ptr(th), self.stream()),
+              "ltd_project_subspace")
+        return h0, s, th
+
+    def ritz_basis(self, k: int, x):
+        """Rotates x (tensor (n_aux, N_basis)) in place into Ritz vectors; returns eps."""
+        torch = _torch()
+        eps = torch.empty(self.n_aux, dtype=torch.float64, device=self.device)
+        check(self.lib.ltd_ritz_basis(self.handle, k, _ptr(x), x.shape[1], _ptr(eps), self.stream()),
+              "ltd_ritz_basis")
+        return eps
+
+    def subspace_info(self, k: int):
+        a, b, d = C.c_double(), C.c_double(), C.c_double()
+        check(self.lib.ltd_subspace_info(self.handle, k, C.byref(a), C.byref(b), C.byref(d)), "ltd_subspace_info")
+        return a.value, b.value, d.value
+
+    # ------------------------------------------------------------------
+    def make_step_args(self, mode, dt, a_t, a_mid, theta, n_steps, c_out=None, v_r_t=None, h_t=None):
+        """Device buffers and the StepArgs for a run of n_steps; theta (n_k, n_states, n_aux)."""
+        torch = _torch()
+        dev = self.device
+        st = dict(
+            step=torch.zeros(1, dtype=torch.int32, device=dev),
+            j=torch.zeros(n_steps + 1, dtype=torch.float64, device=dev),
+            e=torch.zeros(n_steps + 1, dtype=torch.float64, device=dev),
+            dmu=torch.zeros(n_steps + 1, dtype=torch.float64, device=dev),
+            a_t=a_t, a_mid=a_mid, theta=theta, c_out=c_out, v_r_t=v_r_t, h_t=h_t,
+        )
+        st["args"] = StepArgs(mode=mode, dt=dt, a_t=_ptr(a_t), a_mid=_ptr(a_mid), step=_ptr(st["step"]),
+                              v_r_t=_ptr(v_r_t), h_t=_ptr(h_t), theta=_ptr(theta), c_out=_ptr(c_out),
+                              j_out=_ptr(st["j"]), e_out=_ptr(st["e"]), dmu_out=_ptr(st["dmu"]))
+        return st
+
+    def step(self, st):
+        check(self.lib.ltd_propagate_step(self.handle, C.byref(st["args"]), self.stream()), "ltd_propagate_step")
+
+    def run(self, st, n_steps: int):
+        check(self.lib.ltd_propagate(self.handle, C.byref(st["args"]), n_steps, self.stream()), "ltd_propagate")
+
+    def propagate(self, mode, dt, a_t, a_mid, theta, n_steps, graph=True, c_out=None, v_r_t=None, h_t=None):
+        st = self.make_step_args(mode, dt, a_t, a_mid, theta, n_steps, c_out, v_r_t, h_t)
+        if graph:
+            self.run(st, n_steps)
+        else:
+            for _ in range(n_steps):
+                self.step(st)
+        return st
+
+    def adjoint_step(self, st, n, n_steps, mu_next, mu_out, dl_da_mid, dl_da_t, terminal=False):
+        a = AdjointArgs(fwd=C.pointer(st["args"]), n=n, terminal=1 if terminal else 0, n_steps=n_steps,
+                        mu_next=_ptr(mu_next), mu_out=_ptr(mu_out), dl_da_mid=_ptr(dl_da_mid),
+                        dl_da_t=_ptr(dl_da_t))
+        check(self.lib.ltd_propagate_step_adjoint(self.handle, C.byref(a), self.stream()),
+              "ltd_propagate_step_adjoint")
+
+    def knot_samples(self, q, t_end, dt, n_steps):
+        torch = _torch()
+        a_t = torch.empty(n_steps + 1, dtype=torch.float64, device=self.device)
+        a_mid = torch.empty(n_steps, dtype=torch.float64, device=self.device)
+        check(self.lib.ltd_knot_samples(_ptr(q), q.numel(), t_end, dt, n_steps, _ptr(a_t), _ptr(a_mid),
+                                        self.stream()), "ltd_knot_samples")
+        return a_t, a_mid
+
+    def knot_gradient(self, g_t, g_mid, dt, n_knots, t_end):
+        torch = _torch()
+        g = torch.empty(n_knots, dtype=torch.float64, device=self.device)
+        check(self.lib.ltd_knot_gradient(_ptr(g_t), _ptr(g_mid), g_mid.numel(), dt, n_knots, t_end, _ptr(g),
+                                         self.stream()), "ltd_knot_gradient")
+        return g
+
+
+def chebyshev_coefficients(tau: float, kmax: int):
+    lib = _lib.load()
+    buf = (C.c_double * (2 * (kmax + 1)))()
+    deg = C.c_int(0)
+    check(lib.ltd_chebyshev_coefficients(tau, kmax, buf, C.byref(deg)), "ltd_chebyshev_coefficients")
+    a = np.frombuffer(buf, dtype=np.float64).copy()
+    return a[0::2] + 1j * a[1::2], deg.value
+
+
+# ----------------------------------------------------------------------
+# Pulse gradients: forward propagation with theta checkpoints, backward by
+# recomputing each segment and running the adjoint steps in reverse.
+# ----------------------------------------------------------------------
+def pulse_forward(lt: Ltd, mode, dt, q, t_end, n_steps, theta0, checkpoint=50):
+    """Propagates theta0 (n_k, n_states, n_aux) under the piecewise-linear pulse
+    with knots q; returns (loss, state) with loss = dt sum_n w_n (J_n - J_0)."""
+    torch = _torch()
+    a_t, a_mid = lt.knot_samples(q, t_end, dt, n_steps)
+    theta = theta0.clone()
+    st = lt.make_step_args(mode, dt, a_t, a_mid, theta, n_steps)
+    ckpt = {0: theta.clone()}
+    done = 0
+    while done < n_steps:
+        m = min(checkpoint, n_steps - done)
+        lt.run(st, m) if m > 1 else lt.step(st)
+        done += m
+        ckpt[done] = theta.clone()
+    w = torch.ones(n_steps + 1, dtype=torch.float64, device=lt.device)
+    w[0] = w[-1] = 0.5
+    j = st["j"]
+    loss = dt * torch.sum(w * (j - j[0]))
+    return loss, dict(st=st, ckpt=ckpt, a_t=a_t, a_mid=a_mid, checkpoint=checkpoint)
+
+
+def pulse_backward(lt: Ltd, mode, dt, q, t_end, n_steps, fw):
+    """dL/dq for the forward run ``fw`` (checkpointed adjoint)."""
+    torch = _torch()
+    dev = lt.device
+    shape = (lt.n_k, lt.n_states, lt.n_aux)
+    mu = torch.zeros(shape, dtype=torch.complex128, device=dev)
+    g_mid = torch.zeros(n_steps, dtype=torch.float64, device=dev)
+    g_t = torch.zeros(n_steps + 1, dtype=torch.float64, device=dev)
+    ck = fw["checkpoint"]
+    # terminal point
+    th_n = fw["ckpt"][n_steps]
+    sa = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], th_n, n_steps)
+    lt.adjoint_step(sa, n_steps, n_steps, None, mu, None, g_t, terminal=True)
+    seg_starts = sorted(s for s in fw["ckpt"] if s < n_steps)
+    for s0 in reversed(seg_starts):
+        s1 = min(s0 + ck, n_steps)
+        theta = fw["ckpt"][s0].clone()
+        rec = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], theta, n_steps)
+        rec["step"].fill_(s0)
+        thetas = []
+        for _ in range(s0, s1):
+            thetas.append(theta.clone())
+            lt.step(rec)
+        for n in range(s1 - 1, s0 - 1, -1):
+            sa = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], thetas[n - s0], n_steps)
+            lt.adjoint_step(sa, n, n_steps, mu, mu, g_mid, g_t)
+    return lt.knot_gradient(g_t, g_mid, dt, q.numel(), t_end), g_t, g_mid
+
+
+class PulseLoss:
+    """torch.autograd.Function: L(q) = delta mu_z(T)/Omega for knot amplitudes q."""
+
+    @staticmethod
+    def apply(lt, q, mode, dt, t_end, n_steps, theta0, checkpoint=50):
+        torch = _torch()
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, qq):
+                loss, fw = pulse_forward(lt, mode, dt, qq.detach(), t_end, n_steps, theta0, checkpoint)
+                ctx.fw = fw
+                ctx.save_for_backward(qq.detach())
+                return loss
+
+            @staticmethod
+            def backward(ctx, g):
+                (qq,) = ctx.saved_tensors
+                grad, _, _ = pulse_backward(lt, mode, dt, qq, t_end, n_steps, ctx.fw)
+                return g * grad
+
+        return _F.apply(q)

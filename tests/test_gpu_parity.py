@@ -1,0 +1,277 @@
+"""GPU parity: every entry point of the HIP library against the CPU FP64 oracle
+on the same seeded inputs (tiny workload: several tiles and a ragged tail).
+
+Bar: 1e-10 relative (FP64), element-wise maxima reported relative to the
+largest reference element.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import adjoint as ad
+from oracle import operators as op
+from oracle import propagate as pr
+from oracle import subspace as ss
+from synth import make_system, pulse_samples
+from synth.lapw_inputs import knot_times, knot_values
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def rel_max(x, ref):
+    return float(np.abs(np.asarray(x) - np.asarray(ref)).max() / np.abs(np.asarray(ref)).max())
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    return t
+
+
+@pytest.fixture(scope="module")
+def cfg0(torch):
+    from paper_2403_04351_amd import ltd
+
+    sys = make_system(0)
+    phi, eps = ss.ground_state(sys, 0)
+    sub = ss.project(sys, 0, phi)
+    lt = ltd.Ltd(sys, max_cols=70)
+    return dict(sys=sys, phi=phi, eps=eps, sub=sub, lt=lt, ltd=ltd)
+
+
+def test_apply_hs_matches_oracle(cfg0, torch):
+    sys, lt, ltd = cfg0["sys"], cfg0["lt"], cfg0["ltd"]
+    nb = sys.n_basis(0)
+    rng = np.random.default_rng(1)
+    for n, a_z in ((1, 0.0), (5, 0.37), (16, -1.1), (70, 0.2)):
+        c = rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))
+        hc, sc = lt.apply_hs(0, ltd.colmajor(c, lt.device), a_z)
+        torch.cuda.synchronize()
+        hr, sr = op.apply_hs(sys, 0, c, a_z)
+        print(f"apply n={n} a={a_z}: H {rel_max(ltd.to_numpy(hc), hr):.2e} S {rel_max(ltd.to_numpy(sc), sr):.2e}",
+              flush=True)
+        assert rel_max(ltd.to_numpy(hc), hr) < TOL
+        assert rel_max(ltd.to_numpy(sc), sr) < TOL
+    assert lt.sync_status() == 0
+
+
+def test_interstitial_fft_identity(torch):
+    """No atoms, Theta = 1, V = 0: S C = C and H(A) C = 1/2 |G+k+(A/c) z|^2 C
+    exactly (the interstitial pipeline alone)."""
+    from paper_2403_04351_amd import ltd
+
+    sys = make_system(0, atoms=("explicit", []))
+    assert np.all(sys.theta == 1.0) and np.all(sys.vr == 0.0)
+    lt = ltd.Ltd(sys, max_cols=8)
+    nb = sys.n_basis(0)
+    rng = np.random.default_rng(7)
+    c = rng.standard_normal((nb, 5)) + 1j * rng.standard_normal((nb, 5))
+    a = 0.9
+    hc, sc = lt.apply_hs(0, ltd.colmajor(c, lt.device), a)
+    torch.cuda.synchronize()
+    gk = sys.kpts[0].gk + np.array([0.0, 0.0, a / sys.c_light])
+    print(f"identity: S {rel_max(ltd.to_numpy(sc), c):.2e} H "
+          f"{rel_max(ltd.to_numpy(hc), 0.5 * (gk * gk).sum(1)[:, None] * c):.2e}", flush=True)
+    assert rel_max(ltd.to_numpy(sc), c) < 1e-13
+    assert rel_max(ltd.to_numpy(hc), 0.5 * (gk * gk).sum(1)[:, None] * c) < 1e-12
+
+
+def test_muffin_tin_chain_alone(torch):
+    """Theta = 0 (no interstitial): only the matching-coefficient chain acts."""
+    from paper_2403_04351_amd import ltd
+
+    sys = make_system(0)
+    sys.theta[:] = 0.0
+    lt = ltd.Ltd(sys, max_cols=8)
+    nb = sys.n_basis(0)
+    rng = np.random.default_rng(8)
+    c = rng.standard_normal((nb, 3)) + 1j * rng.standard_normal((nb, 3))
+    hc, sc = lt.apply_hs(0, ltd.colmajor(c, lt.device), 0.4)
+    torch.cuda.synchronize()
+    hr, sr = op.apply_hs(sys, 0, c, 0.4)
+    print(f"mt only: H {rel_max(ltd.to_numpy(hc), hr):.2e} S {rel_max(ltd.to_numpy(sc), sr):.2e}", flush=True)
+    assert rel_max(ltd.to_numpy(sc), sr) < TOL
+    assert rel_max(ltd.to_numpy(hc), hr) < TOL
+
+
+def test_project_subspace_matches_oracle(cfg0, torch):
+    sys, lt, ltd, phi, sub = cfg0["sys"], cfg0["lt"], cfg0["ltd"], cfg0["phi"], cfg0["sub"]
+    rng = np.random.default_rng(2)
+    th_ref = rng.standard_normal((16, 4)) + 1j * rng.standard_normal((16, 4))
+    c = phi @ th_ref
+    phid = ltd.colmajor(phi, lt.device)
+    h0, s, th = lt.project_subspace(0, phid, ltd.colmajor(c, lt.device))
+    torch.cuda.synchronize()
+    assert rel_max(ltd.to_numpy(h0), sub["H0"]) < TOL
+    assert rel_max(ltd.to_numpy(s), sub["S"]) < TOL
+    assert rel_max(ltd.to_numpy(th), th_ref) < TOL
+    emin, emax, dtcr = lt.subspace_info(0)
+    assert abs(emin - cfg0["eps"][0]) < 1e-11 and abs(emax - cfg0["eps"][-1]) < 1e-11
+    assert abs(dtcr - pr.critical_timestep(sub["H0"], sub["S"])) < 1e-10 * dtcr
+
+
+def test_ritz_basis_matches_oracle(cfg0, torch):
+    sys, ltd = cfg0["sys"], cfg0["ltd"]
+    lt2 = ltd.Ltd(sys)
+    x = sys.kpts[0].start[:, :16]
+    phi_ref, eps_ref = ss.ritz(sys, 0, x)
+    xd = ltd.colmajor(x, lt2.device)
+    eps = lt2.ritz_basis(0, xd)
+    torch.cuda.synchronize()
+    assert np.abs(eps.cpu().numpy() - eps_ref).max() < 1e-11 * np.abs(eps_ref).max()
+    phi = ltd.to_numpy(xd)
+    sub = ss.project(sys, 0, phi)
+    assert np.abs(sub["S"] - np.eye(16)).max() < 1e-11
+    assert np.abs(sub["H0"] - np.diag(eps_ref)).max() < 1e-11
+    # same subspace: projector onto span(X) in the S metric agrees
+    d = op.dense_operators(sys, 0)
+    p_gpu = phi @ phi.conj().T @ d["S"]
+    p_ref = phi_ref @ phi_ref.conj().T @ d["S"]
+    assert np.abs(p_gpu - p_ref).max() < 1e-10
+
+
+def _gpu_propagate(cfg, mode, n_steps, scale=1.0, graph=True, c_out=False):
+    torch = __import__("torch")
+    sys, lt, ltd = cfg["sys"], cfg["lt"], cfg["ltd"]
+    phid = ltd.colmajor(cfg["phi"], lt.device)
+    lt.project_subspace(0, phid)
+    a_t, a_mid = pulse_samples(sys, n_steps)
+    at = torch.from_numpy(scale * a_t).to(lt.device)
+    am = torch.from_numpy(scale * a_mid).to(lt.device)
+    th0 = pr.initial_theta(sys.n_aux, sys.n_states)
+    theta = torch.from_numpy(np.ascontiguousarray(th0.T)[None]).to(lt.device)
+    cout = None
+    if c_out:
+        cout = torch.zeros((sys.n_states, sys.n_basis(0)), dtype=torch.complex128, device=lt.device)
+    st = lt.propagate(mode, sys.dt, at, am, theta, n_steps, graph=graph, c_out=cout)
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+    return st, (scale * a_t, scale * a_mid), cout
+
+
+@pytest.mark.parametrize("mode", ["affine", "rebuild"])
+def test_propagation_matches_oracle(cfg0, mode):
+    ltd = cfg0["ltd"]
+    m = ltd.LTD_STEP_AFFINE if mode == "affine" else ltd.LTD_STEP_REBUILD
+    sys, sub = cfg0["sys"], cfg0["sub"]
+    st, (a_t, a_mid), _ = _gpu_propagate(cfg0, m, sys.n_steps)
+    vfn = None
+    if mode == "rebuild":
+        vfn = lambda n: ss.rebuild_v_sub(sys, 0, cfg0["phi"])
+    ref = pr.propagate(sub, pr.initial_theta(16, 4), a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light,
+                       v_sub_fn=vfn)
+    j, e, dmu = st["j"].cpu().numpy(), st["e"].cpu().numpy(), st["dmu"].cpu().numpy()
+    th = st["theta"][0].cpu().numpy().T
+    print(f"{mode}: J {rel_max(j, ref['J']):.2e} E {rel_max(e, ref['E']):.2e} "
+          f"dmu {rel_max(dmu, ref['dmu']):.2e} theta {rel_max(th, ref['theta']):.2e}", flush=True)
+    assert rel_max(j, ref["J"]) < TOL
+    assert rel_max(e, ref["E"]) < TOL
+    assert rel_max(dmu, ref["dmu"]) < 1e-9  # dmu is a small difference of large currents
+    assert rel_max(th, ref["theta"]) < TOL
+    # the induced current itself (J - J0) relative to its own size
+    ji, jr = j - j[0], ref["J"] - ref["J"][0]
+    assert np.abs(ji - jr).max() < 1e-8 * np.abs(jr).max()
+
+
+def test_graph_replay_equals_stepwise(cfg0):
+    ltd = cfg0["ltd"]
+    st_g, _, _ = _gpu_propagate(cfg0, ltd.LTD_STEP_REBUILD, 30, graph=True)
+    st_s, _, _ = _gpu_propagate(cfg0, ltd.LTD_STEP_REBUILD, 30, graph=False)
+    assert np.array_equal(st_g["j"].cpu().numpy(), st_s["j"].cpu().numpy())
+    assert np.array_equal(st_g["theta"].cpu().numpy(), st_s["theta"].cpu().numpy())
+
+
+def test_rebuild_equals_affine_for_static_potential(cfg0):
+    ltd = cfg0["ltd"]
+    a, _, _ = _gpu_propagate(cfg0, ltd.LTD_STEP_AFFINE, 100)
+    b, _, _ = _gpu_propagate(cfg0, ltd.LTD_STEP_REBUILD, 100)
+    assert rel_max(b["j"].cpu().numpy(), a["j"].cpu().numpy()) < 1e-12
+    assert rel_max(b["theta"].cpu().numpy(), a["theta"].cpu().numpy()) < 1e-12
+
+
+def test_stationary_states_phase_on_gpu(cfg0):
+    ltd = cfg0["ltd"]
+    st, _, _ = _gpu_propagate(cfg0, ltd.LTD_STEP_REBUILD, 200, scale=0.0)
+    th = st["theta"][0].cpu().numpy().T
+    t = 200 * cfg0["sys"].dt
+    expect = pr.initial_theta(16, 4) * np.exp(-1j * cfg0["eps"][:4] * t)[None, :]
+    assert np.abs(th - expect).max() < 1e-11
+    e = st["e"].cpu().numpy()
+    assert np.abs(e - e[0]).max() < 1e-12 * abs(e[0])
+
+
+def test_map_back(cfg0):
+    ltd = cfg0["ltd"]
+    st, _, cout = _gpu_propagate(cfg0, ltd.LTD_STEP_AFFINE, 20, c_out=True)
+    th = st["theta"][0].cpu().numpy().T
+    c = ltd.to_numpy(cout)
+    assert rel_max(c, ss.map_back(cfg0["phi"], th)) < TOL
+
+
+def test_knot_samples_and_chain_rule(cfg0, torch):
+    lt = cfg0["lt"]
+    q = np.random.default_rng(3).standard_normal(9)
+    qd = torch.from_numpy(q).to(lt.device)
+    a_t, a_mid = lt.knot_samples(qd, 7.0, 0.1, 70)
+    tau = knot_times(9, 7.0)
+    t = np.arange(71) * 0.1
+    tm = (np.arange(70) + 0.5) * 0.1
+    assert np.abs(a_t.cpu().numpy() - np.interp(t, tau, q)).max() < 1e-14
+    assert np.abs(a_mid.cpu().numpy() - np.interp(tm, tau, q)).max() < 1e-14
+    gt = np.random.default_rng(4).standard_normal(71)
+    gm = np.random.default_rng(5).standard_normal(70)
+    g = lt.knot_gradient(torch.from_numpy(gt).to(lt.device), torch.from_numpy(gm).to(lt.device), 0.1, 9, 7.0)
+    ref = ad.hat_matrix(t, tau).T @ gt + ad.hat_matrix(tm, tau).T @ gm
+    assert np.abs(g.cpu().numpy() - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("mode", ["affine", "rebuild"])
+def test_adjoint_matches_oracle(cfg0, torch, mode):
+    ltd = cfg0["ltd"]
+    sys0 = cfg0["sys"]
+    n_steps, n_knots = 60, 8
+    sys = make_system(0, n_steps=n_steps, pulse=dict(kind="knots", n_knots=n_knots, base=dict(
+        kind="gauss_sin", amp=0.01, omega=0.3, t0=3.0, width=1.5)))
+    t_end = n_steps * sys.dt
+    q = knot_values(sys.pulse, t_end)
+    a_t, a_mid = pulse_samples(sys, knots=q)
+    sub = cfg0["sub"]
+    g = ad.gradients(sub, pr.initial_theta(16, 4), a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light)
+    gq = ad.knot_gradient(g, knot_times(n_knots, t_end), sys.dt)
+    lt = cfg0["lt"]
+    lt.project_subspace(0, ltd.colmajor(cfg0["phi"], lt.device))
+    m = ltd.LTD_STEP_AFFINE if mode == "affine" else ltd.LTD_STEP_REBUILD
+    th0 = torch.from_numpy(np.ascontiguousarray(pr.initial_theta(16, 4).T)[None]).to(lt.device)
+    qd = torch.from_numpy(q).to(lt.device)
+    loss, fw = ltd.pulse_forward(lt, m, sys.dt, qd, t_end, n_steps, th0, checkpoint=7)
+    grad, g_t, g_mid = ltd.pulse_backward(lt, m, sys.dt, qd, t_end, n_steps, fw)
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+    assert abs(loss.item() - g["loss"]) < 1e-10 * abs(g["loss"])
+    print(f"adjoint {mode}: mid {rel_max(g_mid.cpu().numpy(), g['mid']):.2e} "
+          f"t {rel_max(g_t.cpu().numpy(), g['at']):.2e} q {rel_max(grad.cpu().numpy(), gq):.2e}", flush=True)
+    assert rel_max(g_mid.cpu().numpy(), g["mid"]) < 1e-9
+    assert rel_max(g_t.cpu().numpy(), g["at"]) < 1e-9
+    assert rel_max(grad.cpu().numpy(), gq) < 1e-9
+    # torch.autograd entry point
+    qv = qd.clone().requires_grad_(True)
+    lv = ltd.PulseLoss.apply(lt, qv, m, sys.dt, t_end, n_steps, th0, 7)
+    lv.backward()
+    assert rel_max(qv.grad.cpu().numpy(), gq) < 1e-9
+    del sys0
+
+
+def test_singular_overlap_is_reported(cfg0, torch):
+    ltd = cfg0["ltd"]
+    from paper_2403_04351_amd import _lib
+
+    sys = cfg0["sys"]
+    lt2 = ltd.Ltd(sys)
+    phi = cfg0["phi"].copy()
+    phi[:, 5] = 0.0  # rank deficient: S_sub has an exactly zero pivot
+    with pytest.raises(_lib.LtdError) as ei:
+        lt2.project_subspace(0, ltd.colmajor(phi, lt2.device))
+    assert ei.value.code == _lib.LTD_ENOTSPD
