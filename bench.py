@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Throughput of the subspace time propagation on one MI355X.
+
+Workload: the molecule-in-large-cell system (1 k-point, N_G = 12000 plane
+waves, 2 atoms at lmax = 8 with 2 radial functions and 10 local orbitals each,
+FFT grid 72^3, N_aux = 64, N_states = 5, dt = 0.2 a.u.), seeded synthetic
+inputs.  One bench "step" is one time step of every state: the per-step
+rebuild of the potential part of the subspace Hamiltonian from the potential
+handed in for the step (interstitial FFT passes, muffin-tin block products,
+projection), the FP64 Chebyshev exponential of the midpoint Hamiltonian and
+the current/energy/dipole observables, replayed from a hipGraph.
+
+Prints one JSON line: state-steps/s (whole job), the roofline of the dominant
+kernel stage from HIP events, the FP64 MFMA rate of the H-apply GEMMs, and the
+CPU FP64 oracle on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "KS state-steps/s + H-apply MFMA util, FP64 vs mixed/batched at stated dipole err"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+STAGES = ["theta_v", "z_lines", "planes", "mt_blocks", "v_projection", "subspace_step", "map_back"]
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--mode", choices=["rebuild", "affine"], default="rebuild")
+    p.add_argument("--profile-steps", type=int, default=20)
+    p.add_argument("--cpu-steps", type=int, default=6)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def stage_bytes(sysd, n, nbz, n1, n2, n3):
+    """Algorithmic bytes of one launch of each step stage (read + write of its own
+    inputs and outputs once)."""
+    c16 = 16
+    slab = nbz * n1 * n2 * n * c16
+    ngrid = n1 * n2 * n3
+    ng = sysd.kpts[0].n_g
+    k_ext = ng + sysd.n_a + sysd.n_lo
+    return {
+        "theta_v": 3 * ngrid * 8,
+        "z_lines": 2 * slab + ngrid * 8,
+        "planes": slab + ng * n * c16 + ng * 16,
+        "v_projection": 2 * k_ext * n * c16 + n * n * c16,
+    }
+
+
+def traffic_from_profiles(kernel_file):
+    """HBM traffic of the dominant kernel from committed rocprofv3 counter runs,
+    valid only while the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2403_04351_amd", "csrc", kernel_file), "rb").read()
+        if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(sysd, n_steps, mode):
+    """The FP64 oracle, timed on the host cores over a bounded number of steps."""
+    import threadpoolctl
+
+    from oracle import operators as op
+    from oracle import propagate as pr
+    from oracle import subspace as ss
+    from synth import pulse_samples
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    op._WORKERS = cores
+    with threadpoolctl.threadpool_limits(cores):
+        phi, _ = ss.ground_state(sysd, 0)
+        sub = ss.project(sysd, 0, phi)
+        a_t, a_mid = pulse_samples(sysd, n_steps)
+        vfn = (lambda n: ss.rebuild_v_sub(sysd, 0, phi)) if mode == "rebuild" else None
+        t0 = time.perf_counter()
+        pr.propagate(sub, pr.initial_theta(sysd.n_aux, sysd.n_states), a_t, a_mid, sysd.dt, sysd.occ,
+                     sysd.omega, sysd.c_light, v_sub_fn=vfn, n_steps=n_steps)
+        t = time.perf_counter() - t0
+    return dict(value=sysd.n_states * n_steps / t, unit="state-steps/s", cores=cores, kind="oracle",
+                sample=f"first {n_steps} time steps ({mode}) of the same workload, setup excluded; "
+                       f"{t:.2f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the k-point and column "
+              "sharding across GPUs is described in the design notes but not run.", file=sys.stderr)
+        return 2
+    import torch
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    from paper_2403_04351_amd import ltd
+    from synth import make_system, pulse_samples
+
+    dev = torch.device("cuda:0")
+    sysd = make_system(1)
+    lt = ltd.Ltd(sysd, device=dev)
+    # auxiliary basis: Rayleigh-Ritz vectors of the seeded start block, on the GPU
+    phi = ltd.colmajor(sysd.kpts[0].start[:, :sysd.n_aux], dev)
+    lt.ritz_basis(0, phi)
+    lt.project_subspace(0, phi)
+    emin, emax, dtcr = lt.subspace_info(0)
+    mode = ltd.LTD_STEP_REBUILD if args.mode == "rebuild" else ltd.LTD_STEP_AFFINE
+    total = args.warmup + args.steps + args.profile_steps
+    a_t, a_mid = pulse_samples(sysd, total)
+    at = torch.from_numpy(a_t).to(dev)
+    am = torch.from_numpy(a_mid).to(dev)
+    th0 = np.zeros((1, sysd.n_states, sysd.n_aux), dtype=np.complex128)
+    for j in range(sysd.n_states):
+        th0[0, j, j] = 1.0
+    theta = torch.from_numpy(th0).to(dev)
+    st = lt.make_step_args(mode, sysd.dt, at, am, theta, total)
+    s = torch.cuda.current_stream(dev)
+    if args.warmup:
+        lt.run(st, args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    lt.run(st, args.steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    status = lt.sync_status()
+    if status != 0:
+        print(f"device status {status} after the timed run", file=sys.stderr)
+        return 1
+    value = sysd.n_states * args.steps / (ms / 1e3)
+
+    # stage profile (HIP events between stages, eager)
+    stage_ms = lt.profile_steps(st, max(1, args.profile_steps))
+    prof = {STAGES[i]: round(stage_ms[i] * 1e3, 3) for i in range(len(STAGES))}
+    n1, n2, n3 = sysd.grid
+    bz = int(np.abs(sysd.kpts[0].g_int[:, 2]).max())
+    nbz = 2 * bz + 1
+    sb = stage_bytes(sysd, sysd.n_aux, nbz, n1, n2, n3)
+    hbm_stages = {k: v for k, v in prof.items() if k in sb}
+    dom = max(hbm_stages, key=hbm_stages.get)
+    dom_us = hbm_stages[dom]
+    achieved = sb[dom] / (dom_us * 1e-6) / 1e9
+    kernel_file = "fft.hip" if dom in ("z_lines", "planes") else "api.hip"
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(kernel_file),
+                    bytes_per_launch=sb[dom], avg_launch_us=dom_us)
+
+    # H-apply MFMA rate: the muffin-tin GEMMs of one apply at n = N_aux
+    apms, _, _ = lt.profile_apply(0, phi)
+    n = sysd.n_aux
+    ng = sysd.kpts[0].n_g
+    f_k1 = 8.0 * sysd.n_a * ng * n
+    f_k3 = 8.0 * ng * sysd.n_a * 2 * n
+    t_k = (apms[3] + apms[5]) * 1e-3
+    tfs = (f_k1 + f_k3) / t_k / 1e12
+    h_apply = dict(gemm_tflops=round(tfs, 2), peak_tflops=FP64_PEAK_TFS, frac=round(tfs / FP64_PEAK_TFS, 4),
+                   k1_us=round(apms[3] * 1e3, 1), k3_us=round(apms[5] * 1e3, 1),
+                   apply_total_us=round(sum(apms[:6]) * 1e3, 1))
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "state-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "molecule in large cell: 1 k-point, N_G=12000, 2 atoms lmax 8 (162 MT channels + "
+                        "10 LO each), FFT grid 72^3, N_aux=64, N_states=5, dt=0.2, "
+                        f"{args.mode} mode, FP64",
+            "n_g": ng, "n_aux": n, "n_states": sysd.n_states, "grid": list(sysd.grid),
+            "mode": args.mode, "precision": "fp64",
+        },
+        "wall_s": round(wall, 4),
+        "stage_us": prof,
+        "roofline": roofline,
+        "h_apply": h_apply,
+        "subspace": dict(eps_min=emin, eps_max=emax, dt_cr=dtcr),
+        "dmu_final": float(st["dmu"][args.warmup + args.steps].item()),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sysd, args.cpu_steps, args.mode)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -212,6 +212,26 @@ typedef struct {
 ltd_status ltd_propagate_step_adjoint(ltd_system *sys, const ltd_adjoint_args *args,
                                       void *stream);
 
+/* Diagnostics (profiling).  Stage durations come from HIP events recorded on
+ * `stream` between the stages of an eager (not graph-replayed) run; the host
+ * synchronises after every step.  stage_ms: (host) LTD_PROFILE_STAGES doubles.
+ *
+ * ltd_profile_steps: n_steps calls of ltd_propagate_step (advancing the step
+ * counter); stage_ms[i] is the mean per step of stage i: 0 Theta V(t) on the
+ * grid, 1 z-line transforms and product, 2 plane transforms and sphere read-out,
+ * 3 muffin-tin block products, 4 projection of V~ (Phi~^H Y), 5 subspace
+ * exponential and observables, 6 map-back.
+ *
+ * ltd_profile_apply: one ltd_apply_HS at A = 0 (HC, SC: N_basis(k) x n, ld ldo);
+ * stage_ms[i] is the total of: 0 inverse plane transforms, 1 z lines and
+ * products, 2 forward plane transforms, 3 A C (muffin-tin gather GEMM), 4 block
+ * products, 5 A^H Y (scatter GEMM) and local-orbital rows. */
+#define LTD_PROFILE_STAGES 8
+ltd_status ltd_profile_steps(ltd_system *sys, const ltd_step_args *args, int n_steps, double *stage_ms,
+                             void *stream);
+ltd_status ltd_profile_apply(ltd_system *sys, int k, const void *C, int ldc, int n, void *HC, void *SC,
+                             int ldo, double *stage_ms, void *stream);
+
 /* Piecewise-linear pulse on n_knots uniform knots over [0, t_end] (both ends
  * included): a_t[n] = A(n dt), n = 0..n_steps, a_mid[n] = A((n+1/2) dt).
  * knots: [n_knots]. */

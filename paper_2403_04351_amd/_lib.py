@@ -30,8 +30,9 @@ EXPORTED = [
     "ltd_create", "ltd_bind_workspace", "ltd_destroy", "ltd_status_string", "ltd_sync_status",
     "ltd_apply_HS", "ltd_project_subspace", "ltd_ritz_basis", "ltd_subspace_info",
     "ltd_propagate_step", "ltd_propagate", "ltd_propagate_step_adjoint", "ltd_knot_samples",
-    "ltd_knot_gradient", "ltd_chebyshev_coefficients",
+    "ltd_knot_gradient", "ltd_chebyshev_coefficients", "ltd_profile_steps", "ltd_profile_apply",
 ]
+LTD_PROFILE_STAGES = 8
 
 
 class SystemDesc(C.Structure):
@@ -119,6 +120,8 @@ def load(path: str = LIB_PATH):
     lib.ltd_knot_samples.argtypes = [vp, ip, C.c_double, C.c_double, ip, vp, vp, vp]
     lib.ltd_knot_gradient.argtypes = [vp, vp, ip, C.c_double, ip, C.c_double, vp, vp]
     lib.ltd_chebyshev_coefficients.argtypes = [C.c_double, ip, dp, C.POINTER(ip)]
+    lib.ltd_profile_steps.argtypes = [vp, C.POINTER(StepArgs), ip, dp, vp]
+    lib.ltd_profile_apply.argtypes = [vp, ip, vp, ip, ip, vp, vp, ip, dp, vp]
     for name in EXPORTED:
         getattr(lib, name).restype = getattr(lib, name).restype if name == "ltd_status_string" else C.c_int
     _lib = lib

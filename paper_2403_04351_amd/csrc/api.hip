@@ -125,6 +125,48 @@ namespace {
 
 hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Stage timer: records an event after each stage on the stream (eager runs only).
+struct Prof {
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> tag;
+  ltd_status begin(hipStream_t st) {
+    s = st;
+    hipEvent_t e;
+    LTD_HIP(hipEventCreate(&e));
+    LTD_HIP(hipEventRecord(e, s));
+    ev.push_back(e);
+    tag.push_back(-1);
+    return LTD_OK;
+  }
+  ltd_status mark(int stage) {
+    hipEvent_t e;
+    LTD_HIP(hipEventCreate(&e));
+    LTD_HIP(hipEventRecord(e, s));
+    ev.push_back(e);
+    tag.push_back(stage);
+    return LTD_OK;
+  }
+  // adds elapsed ms per stage into acc; destroys the events
+  ltd_status collect(double *acc, int nstage) {
+    LTD_HIP(hipEventSynchronize(ev.back()));
+    for (size_t i = 1; i < ev.size(); ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i - 1], ev[i]) != hipSuccess) ms = 0.f;
+      if (tag[i] >= 0 && tag[i] < nstage) acc[tag[i]] += ms;
+    }
+    for (auto e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    tag.clear();
+    return LTD_OK;
+  }
+};
+
+#define LTD_MARK(p, st)                 \
+  do {                                  \
+    if (p) LTD_TRY((p)->mark(st));      \
+  } while (0)
+
 // ---------------------------------------------------------------------------
 // Bessel functions J_0..J_nmax(x) by Miller's backward recurrence, normalised
 // with J_0 + 2 sum_k J_2k = 1.
@@ -217,10 +259,13 @@ ltd_status gemm1(ltd_system *sys, int opa, int opb, const ZProb &p, hipStream_t 
   return gemm(sys, opa, opb, std::vector<ZProb>{p}, s);
 }
 
-// K2 tables: Y_x = blockdiag(x_a) W for every atom a and matrix x in `xs`.
+// K2 tables: Y_x = blockdiag(x_a) W for every atom a and matrix x in `xs`.  The
+// local vector of atom a is [W rows of its channels; W rows of its LOs] (two row
+// segments of W), so each output block is one GEMM over a two-segment K.
 void build_k2(const ltd_system *sys, const std::vector<const double2 *> &xs, const double2 *W, int ldw,
               const std::vector<double2 *> &Ys, int ldy, int cols, std::vector<ZProb> &p1, std::vector<ZProb> &p2) {
   const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  (void)p2;
   for (size_t xi = 0; xi < xs.size(); ++xi) {
     for (int a = 0; a < sys->n_atoms; ++a) {
       const int m = sys->n_mt[a], l = sys->n_lo[a], s = m + l;
@@ -229,11 +274,15 @@ void build_k2(const ltd_system *sys, const std::vector<const double2 *> &xs, con
       const double2 *wl = W + sys->n_a + sys->l_off[a];
       double2 *yt = Ys[xi] + sys->a_off[a];
       double2 *yl = Ys[xi] + sys->n_a + sys->l_off[a];
-      p1.push_back(zp(m, cols, m, x, s, wt, ldw, yt, ldy, one, zero));
+      ZProb top = zp(m, cols, s, x, s, wt, ldw, yt, ldy, one, zero);
+      top.B2 = wl;
+      top.kseg = l > 0 ? m : 0;
+      p1.push_back(top);
       if (l > 0) {
-        p1.push_back(zp(l, cols, m, x + m, s, wt, ldw, yl, ldy, one, zero));
-        p2.push_back(zp(m, cols, l, x + (long long)m * s, s, wl, ldw, yt, ldy, one, one));
-        p2.push_back(zp(l, cols, l, x + m + (long long)m * s, s, wl, ldw, yl, ldy, one, one));
+        ZProb bot = zp(l, cols, s, x + m, s, wt, ldw, yl, ldy, one, zero);
+        bot.B2 = wl;
+        bot.kseg = m;
+        p1.push_back(bot);
       }
     }
   }
@@ -242,10 +291,10 @@ void build_k2(const ltd_system *sys, const std::vector<const double2 *> &xs, con
 ltd_status upload_k2(ltd_system *sys, std::vector<ZProb> &p1, std::vector<ZProb> &p2, K2Table &t, size_t off1,
                      size_t off2, size_t cap) {
   int tt = 0;
-  gemm_plan(p1.data(), (int)p1.size(), &tt, 1 << 30, 0);
+  gemm_plan(p1.data(), (int)p1.size(), &tt, 512, PART_TILES);
   t.tiles1 = tt;
   tt = 0;
-  if (!p2.empty()) gemm_plan(p2.data(), (int)p2.size(), &tt, 1 << 30, 0);
+  if (!p2.empty()) gemm_plan(p2.data(), (int)p2.size(), &tt, 512, PART_TILES);
   t.tiles2 = tt;
   if (p1.size() * sizeof(ZProb) > cap || p2.size() * sizeof(ZProb) > cap) return LTD_EUNSUPPORTED;
   t.p1 = p1;
@@ -296,8 +345,10 @@ Grid grid_of(const ltd_system *sys) {
 //   mode FFT_MODE_HS:   out[0] = H(A) C, out[1] = S C
 //   mode FFT_MODE_TVPS: out[0..3] = T C, V C, P_z C, S C
 // ---------------------------------------------------------------------------
+// Apply stages (profiling tags): 0 inverse planes, 1 z lines, 2 forward planes,
+// 3 A C (K1), 4 block-diagonal muffin-tin products (K2), 5 A^H Y (K3) and LO rows.
 ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const double2 *C, int ldc, int cols,
-                       double2 *const out[4], const int ldo[4], hipStream_t s) {
+                       double2 *const out[4], const int ldo[4], hipStream_t s, Prof *pf = nullptr) {
   if (cols <= 0) return LTD_OK;
   const KHost &kh = sys->kh[k];
   const Grid g = grid_of(sys);
@@ -309,9 +360,11 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   ka.in[0].ldc = ldc;
   ka.slab_out[0] = sys->at<double2>(sys->o_slab_in);
   LTD_HIP(fft_inverse_planes(g, ka, 1, cols, 4, s));
+  LTD_MARK(pf, 0);
   ka.slab_in[0] = sys->at<double2>(sys->o_slab_in);
   ka.slab_out[0] = sys->at<double2>(sys->o_slab_out);
   LTD_HIP(fft_lines(g, ka, 1, cols, FFT_MODE_HS, sys->at<double>(sys->o_thv), s));
+  LTD_MARK(pf, 1);
   ka.slab_in[0] = sys->at<double2>(sys->o_slab_out);
   FwdOut fo{};
   fo.o0 = out[0];
@@ -326,6 +379,7 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   }
   ka.out[0] = fo;
   LTD_HIP(fft_forward_planes(g, ka, 1, cols, mode, al, be, s));
+  LTD_MARK(pf, 2);
   // muffin-tin chain: W = [A C_G; C_LO]
   double2 *W = sys->at<double2>(sys->o_W);
   double2 *Y = sys->at<double2>(sys->o_Y);
@@ -333,11 +387,13 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   const double2 *Ak = sys->amat + kh.amat_off;
   LTD_TRY(gemm1(sys, OP_N, OP_N, zp(sys->n_a, cols, kh.n_g, Ak, sys->n_a, C, ldc, W, nl), s));
   if (sys->n_lo_tot > 0) LTD_HIP(launch_copy_rows(W + sys->n_a, nl, C + kh.n_g, ldc, sys->n_lo_tot, cols, false, s));
+  LTD_MARK(pf, 3);
   const double2 one = make_double2(1.0, 0.0);
   std::vector<ZProb> k3;
   if (mode == FFT_MODE_HS) {
     LTD_HIP(launch_heff(sys->at<double2>(sys->o_heff), sys->h, sys->pz, sys->o, al, be, sys->blk_elems, s));
     LTD_TRY(run_k2(sys, sys->k2_hs, cols, s));
+    LTD_MARK(pf, 4);
     // Y layout: [Y_heff | Y_o], each n_loc x chunk
     for (int x = 0; x < 2; ++x) {
       double2 *Yx = Y + (long long)x * nl * chunk;
@@ -350,6 +406,7 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
                                  sys->n_lo_tot, cols, false, s));
   } else {
     LTD_TRY(run_k2(sys, sys->k2_tvps, cols, s));
+    LTD_MARK(pf, 4);
     // Y layout: [Y_h | Y_p | Y_o] -> V, P, S
     for (int x = 0; x < 3; ++x) {
       double2 *Yx = Y + (long long)x * nl * chunk;
@@ -363,6 +420,7 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
                                  sys->n_lo_tot, cols, false, s));
     }
   }
+  LTD_MARK(pf, 5);
   return LTD_OK;
 }
 
@@ -501,8 +559,10 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
   return c;
 }
 
+// Step stages (profiling tags): 0 Theta V(t), 1 z lines, 2 forward planes, 3 muffin-tin
+// blocks (K2), 4 projection of V~ (GEMM), 5 subspace step and observables, 6 map-back.
 // Rebuild V~(t) of every k for the potential of this step (v_r_t, h_t).
-ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
+ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Prof *pf = nullptr) {
   const Grid g = grid_of(sys);
   const int n = sys->n_aux;
   const double *thv = sys->at<double>(sys->o_thv);
@@ -510,6 +570,7 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
     LTD_HIP(launch_thv(sys->at<double>(sys->o_thv_step), sys->theta, a->v_r_t, sys->ngrid, s));
     thv = sys->at<double>(sys->o_thv_step);
   }
+  LTD_MARK(pf, 0);
   const long long slab = (long long)g.nbz * sys->n1 * sys->n2 * n;
   for (int k0 = 0; k0 < sys->n_k; k0 += FFT_MAXK) {
     const int nk = std::min(FFT_MAXK, sys->n_k - k0);
@@ -523,8 +584,10 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
       ka.out[i].ld0 = kh.k_ext;
     }
     LTD_HIP(fft_lines(g, ka, nk, n, FFT_MODE_V, thv, s));
+    LTD_MARK(pf, 1);
     for (int i = 0; i < nk; ++i) ka.slab_in[i] = ka.slab_out[i];
     LTD_HIP(fft_forward_planes(g, ka, nk, n, FFT_MODE_V, 0.0, 0.0, s));
+    LTD_MARK(pf, 2);
   }
   const void *hx = a->h_t ? a->h_t : nullptr;
   if (hx != sys->k2_step_h) {
@@ -532,8 +595,10 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
     LTD_TRY(build_step_tables(sys));
   }
   LTD_TRY(run_k2(sys, sys->k2_step, n, s));
+  LTD_MARK(pf, 3);
   LTD_HIP(gemm_launch_table(OP_C, OP_N, sys->at<ZProb>(sys->o_vstep_tab), sys->vstep_tab.data(),
                             (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_partials), 0, s));
+  LTD_MARK(pf, 4);
   return LTD_OK;
 }
 
@@ -564,10 +629,12 @@ ltd_status check_step_args(ltd_system *sys, const ltd_step_args *a) {
   return LTD_OK;
 }
 
-ltd_status step_once(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
-  if (a->mode == LTD_STEP_REBUILD) LTD_TRY(rebuild_v(sys, a, s));
+ltd_status step_once(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Prof *pf = nullptr) {
+  if (a->mode == LTD_STEP_REBUILD) LTD_TRY(rebuild_v(sys, a, s, pf));
   LTD_HIP(launch_step(step_ctx(sys, a), s));
+  LTD_MARK(pf, 5);
   LTD_TRY(map_back(sys, a, s));
+  LTD_MARK(pf, 6);
   return LTD_OK;
 }
 
@@ -1085,6 +1152,48 @@ ltd_status ltd_propagate_step_adjoint(ltd_system *sys, const ltd_adjoint_args *a
   ac.dl_da_mid = aa->dl_da_mid;
   ac.dl_da_t = aa->dl_da_t;
   LTD_HIP(launch_adjoint(step_ctx(sys, a), ac, s));
+  return LTD_OK;
+}
+
+ltd_status ltd_profile_steps(ltd_system *sys, const ltd_step_args *a, int n_steps, double *stage_ms,
+                             void *stream) {
+  LTD_TRY(check_step_args(sys, a));
+  if (!stage_ms) return LTD_EINVAL;
+  if (n_steps < 1) return LTD_ESHAPE;
+  LTD_TRY(prepare_dt(sys, a->dt));
+  hipStream_t s = S(stream);
+  for (int i = 0; i < LTD_PROFILE_STAGES; ++i) stage_ms[i] = 0.0;
+  for (int it = 0; it < n_steps; ++it) {
+    Prof pf;
+    LTD_TRY(pf.begin(s));
+    LTD_TRY(step_once(sys, a, s, &pf));
+    LTD_TRY(pf.collect(stage_ms, LTD_PROFILE_STAGES));
+  }
+  for (int i = 0; i < LTD_PROFILE_STAGES; ++i) stage_ms[i] /= n_steps;
+  return LTD_OK;
+}
+
+ltd_status ltd_profile_apply(ltd_system *sys, int k, const void *C, int ldc, int n, void *HC, void *SC, int ldo,
+                             double *stage_ms, void *stream) {
+  if (!sys || !C || !HC || !SC || !stage_ms) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  if (k < 0 || k >= sys->n_k || n < 1 || n > sys->max_cols) return LTD_ESHAPE;
+  const int nb = sys->kh[k].n_basis;
+  if (ldc < nb || ldo < nb) return LTD_ESHAPE;
+  if (!aligned16(C) || !aligned16(HC) || !aligned16(SC)) return LTD_EALIGN;
+  hipStream_t s = S(stream);
+  for (int i = 0; i < LTD_PROFILE_STAGES; ++i) stage_ms[i] = 0.0;
+  double2 *outs[4] = {reinterpret_cast<double2 *>(HC), reinterpret_cast<double2 *>(SC), nullptr, nullptr};
+  const int lo[4] = {ldo, ldo, 0, 0};
+  const double2 *c = reinterpret_cast<const double2 *>(C);
+  for (int j0 = 0; j0 < n; j0 += sys->chunk) {
+    const int cols = std::min(sys->chunk, n - j0);
+    double2 *o[4] = {outs[0] + (long long)j0 * ldo, outs[1] + (long long)j0 * ldo, nullptr, nullptr};
+    Prof pf;
+    LTD_TRY(pf.begin(s));
+    LTD_TRY(apply_chunk(sys, k, FFT_MODE_HS, 0.0, c + (long long)j0 * ldc, ldc, cols, o, lo, s, &pf));
+    LTD_TRY(pf.collect(stage_ms, LTD_PROFILE_STAGES));
+  }
   return LTD_OK;
 }
 

@@ -35,6 +35,10 @@ struct ZProb {
   const double2 *A;
   const double2 *B;
   double2 *C;
+  // optional two-segment K for op(B) = N: rows k < kseg of B come from B, rows
+  // k >= kseg from B2 (row k - kseg); kseg = 0 disables
+  const double2 *B2;
+  int kseg;
   long long sA, sB, sC;  // batch strides (elements)
   int lda, ldb, ldc;
   int m, n, k, batch;

@@ -13,8 +13,9 @@
 // The coefficients live on a sphere that fills a few per cent of the grid, so
 // each 3D transform is split into passes that only touch the box
 // |g_i| <= b_i around it:
-//   plane pass  (per kz in the box): 2D transform over (x, y) held whole in
-//                LDS; only the box columns are transformed along y;
+//   plane pass  (per kz in the box): 2D transform over (x, y); rows stream
+//                through LDS in chunks, only the box columns stay in LDS
+//                and only they are transformed along y;
 //   line pass   (per tile of (x, y) positions): full-length z transforms in
 //                LDS, fused with the pointwise products, so real-space fields
 //                never reach HBM;
@@ -23,7 +24,10 @@
 // The 1D transforms are mixed-radix (8, 4, 5, 3, 2) Stockham autosort passes.
 // Each wavefront owns whole lines, so a pass needs no block barrier: a
 // wavefront reads all its butterfly inputs into registers, then writes the
-// outputs (LDS operations of one wavefront complete in order).
+// outputs (LDS operations of one wavefront complete in order).  The grid
+// lengths of the workloads (16, 64, 72, 96, 160) are compile-time constants
+// of their kernels, so all index arithmetic is strength-reduced; other lengths
+// take a runtime-length path.
 #include "common.h"
 
 #include <cmath>
@@ -152,9 +156,36 @@ struct Tpl {  // butterflies per lane and stage (register budget)
   static constexpr int value = (R == 8) ? 1 : (R == 5) ? 1 : (R == 4) ? 2 : (R == 3) ? 2 : 4;
 };
 
-__host__ __device__ inline int tpl_of(int r) { return r == 8 ? 1 : r == 5 ? 1 : r == 4 ? 2 : r == 3 ? 2 : 4; }
+__host__ __device__ constexpr int tpl_of(int r) { return r == 8 ? 1 : r == 5 ? 1 : r == 4 ? 2 : r == 3 ? 2 : 4; }
+
+struct Radices {
+  int n;
+  int r[FFT_MAXST];
+};
+
+__host__ __device__ constexpr Radices factor_len(int L) {
+  Radices f{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+  const int order[5] = {8, 4, 5, 3, 2};
+  int x = L;
+  for (int oi = 0; oi < 5; ++oi)
+    while (x > 1 && x % order[oi] == 0 && f.n < FFT_MAXST) {
+      f.r[f.n++] = order[oi];
+      x /= order[oi];
+    }
+  return f;
+}
 
 // Largest number of lines one wavefront can transform per pass.
+__host__ __device__ constexpr int lpw_len(int L) {
+  const Radices f = factor_len(L);
+  int best = 1 << 20;
+  for (int s = 0; s < f.n; ++s) {
+    const int v = (64 * tpl_of(f.r[s])) / (L / f.r[s]);
+    best = v < best ? v : best;
+  }
+  return best < 1 ? 1 : best;
+}
+
 __host__ __device__ inline int lines_per_wave(const FftPlan &p) {
   int best = 1 << 20;
   for (int s = 0; s < p.nst; ++s) {
@@ -170,25 +201,22 @@ struct LinesUniform {
   int base, ls;
   __device__ int operator()(int l) const { return base + l * ls; }
 };
-struct LinesBox {  // box columns of a plane: line l is column (l - b) mod n
-  int b, n;
-  __device__ int operator()(int l) const {
-    const int x = l - b;
-    return x < 0 ? x + n : x;
-  }
-};
 struct LinesTwo {  // lines [0, h) at a0 + l, lines [h, 2h) at a1 + (l - h)
   int a0, a1, h;
   __device__ int operator()(int l) const { return l < h ? a0 + l : a1 + (l - h); }
 };
 
-template <int R, int DIR, class LM>
-__device__ inline void fft_stage(double2 *buf, const LM &lm, int l0, int nl, int es, int L, int Ns,
+// One Stockham pass of radix R on the lines [l0, l0 + nl) of this wavefront.
+// L, NS: compile-time line length and sub-transform size when L > 0.
+template <int R, int DIR, int L, int NS, class LM>
+__device__ __forceinline__ void fft_stage(double2 *buf, const LM &lm, int l0, int nl, int es, int Lr, int NSr,
                                  const double2 *tw, int lane) {
   constexpr int TPL = Tpl<R>::value;
-  const int nb = L / R;
+  const int len = (L > 0) ? L : Lr;
+  const int ns = (L > 0) ? NS : NSr;
+  const int nb = len / R;
   const int ntask = nl * nb;
-  const int twm = L / (Ns * R);
+  const int twm = len / (ns * R);
   double2 v[TPL][R];
   int ob[TPL];
 #pragma unroll
@@ -198,20 +226,20 @@ __device__ inline void fft_stage(double2 *buf, const LM &lm, int l0, int nl, int
     if (task < ntask) {
       const int line = task / nb;
       const int j = task - line * nb;
-      const int k = j % Ns;
+      const int k = j % ns;
       const int base = lm(l0 + line);
-      const int tws = twm * k;
+      const int tws = twm * k;  // tws * q < len for q < R
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         double2 x = buf[base + (j + q * nb) * es];
         if (q > 0) {
-          double2 w = tw[(tws * q) % L];
+          double2 w = tw[tws * q];
           if (DIR > 0) w.y = -w.y;
           x = cmul(x, w);
         }
         v[t][q] = x;
       }
-      ob[t] = base + ((j / Ns) * Ns * R + k) * es;
+      ob[t] = base + ((j / ns) * ns * R + k) * es;
     }
   }
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -220,37 +248,57 @@ __device__ inline void fft_stage(double2 *buf, const LM &lm, int l0, int nl, int
     if (ob[t] >= 0) {
       dft_small<R, DIR>(v[t]);
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[ob[t] + q * Ns * es] = v[t][q];
+      for (int q = 0; q < R; ++q) buf[ob[t] + q * ns * es] = v[t][q];
     }
   }
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+template <int DIR, int L, int S, int NS, class LM>
+__device__ __forceinline__ void fft_stages_ct(double2 *buf, const LM &lm, int l0, int nl, int es, const double2 *tw,
+                                     int lane) {
+  constexpr Radices f = factor_len(L);
+  if constexpr (S < f.n) {
+    constexpr int R = f.r[S];
+    fft_stage<R, DIR, L, NS>(buf, lm, l0, nl, es, L, NS, tw, lane);
+    fft_stages_ct<DIR, L, S + 1, NS * R>(buf, lm, l0, nl, es, tw, lane);
+  }
+}
+
 template <int DIR, class LM>
-__device__ void fft_wave(double2 *buf, const LM &lm, int l0, int nl, int es, const FftPlan &p, const double2 *tw,
-                         int lane) {
+__device__ __forceinline__ void fft_stages_rt(double2 *buf, const LM &lm, int l0, int nl, int es, const FftPlan &p,
+                              const double2 *tw, int lane) {
   int ns = 1;
   for (int s = 0; s < p.nst; ++s) {
     const int r = p.radix[s];
     switch (r) {
-      case 8: fft_stage<8, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
-      case 4: fft_stage<4, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
-      case 5: fft_stage<5, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
-      case 3: fft_stage<3, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
-      default: fft_stage<2, DIR>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+      case 8: fft_stage<8, DIR, 0, 0>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+      case 4: fft_stage<4, DIR, 0, 0>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+      case 5: fft_stage<5, DIR, 0, 0>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+      case 3: fft_stage<3, DIR, 0, 0>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
+      default: fft_stage<2, DIR, 0, 0>(buf, lm, l0, nl, es, p.L, ns, tw, lane); break;
     }
     ns *= r;
   }
 }
 
-// All waves of the block transform `nlines` lines; ends with a block barrier.
-template <int DIR, class LM>
-__device__ void fft_block(double2 *buf, const LM &lm, int nlines, int es, const FftPlan &p, const double2 *tw) {
+// All waves of the block transform `nlines` lines (length L, or p.L when L == 0);
+// ends with a block barrier.
+template <int DIR, int L, class LM>
+__device__ __forceinline__ void fft_block(double2 *buf, const LM &lm, int nlines, int es, const FftPlan &p, const double2 *tw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int lpw = lines_per_wave(p);
-  for (int l0 = wave * lpw; l0 < nlines; l0 += nw * lpw) {
-    const int nl = (nlines - l0) < lpw ? (nlines - l0) : lpw;
-    fft_wave<DIR>(buf, lm, l0, nl, es, p, tw, lane);
+  if constexpr (L > 0) {
+    constexpr int lpw = lpw_len(L);
+    for (int l0 = wave * lpw; l0 < nlines; l0 += nw * lpw) {
+      const int nl = (nlines - l0) < lpw ? (nlines - l0) : lpw;
+      fft_stages_ct<DIR, L, 0, 1>(buf, lm, l0, nl, es, tw, lane);
+    }
+  } else {
+    const int lpw = lines_per_wave(p);
+    for (int l0 = wave * lpw; l0 < nlines; l0 += nw * lpw) {
+      const int nl = (nlines - l0) < lpw ? (nlines - l0) : lpw;
+      fft_stages_rt<DIR>(buf, lm, l0, nl, es, p, tw, lane);
+    }
   }
   __syncthreads();
 }
@@ -259,16 +307,27 @@ __device__ inline void load_tw(double2 *dst, const double2 *src, int L) {
   for (int i = threadIdx.x; i < L; i += blockDim.x) dst[i] = src[i];
 }
 
+// box index of a kx column (x = kx mod n1): kx + bx, or -1 outside the box
+__device__ inline int box_of(int x, int n1, int bx) {
+  return x <= bx ? x + bx : (x >= n1 - bx ? x - n1 + bx : -1);
+}
+
 // ---------------------------------------------------------------------------
 // Inverse plane pass: sphere coefficients (times 1 or (G+k)_i) -> slab planes.
 // grid (nbz, ncols, nk); fields: 0 psi, 1..3 pi_x, pi_y, pi_z.
+// LDS: box columns bx_[nbx][n2+1], a chunk of rows rw[ch][n1+1], twiddles.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FFT_NT) void k_inv_plane(const Grid g, const FftKArgs ka, int ncols, int nfields) {
+template <int L1, int L2>
+__global__ __launch_bounds__(FFT_NT) void k_inv_plane(const Grid g, const FftKArgs ka, int ncols, int nfields,
+                                                      int ch) {
   extern __shared__ double2 sm[];
   const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
-  const int n1 = g.n1, n2 = g.n2, pitch = n1 + 1;
-  double2 *plane = sm;
-  double2 *tw1 = sm + n2 * pitch;
+  const int n1 = L1 > 0 ? L1 : g.n1, n2 = L2 > 0 ? L2 : g.n2;
+  const int bx = g.bx, nbx = g.nbx;
+  const int bp = n2 + 1, rp = n1 + 1;
+  double2 *bxc = sm;
+  double2 *rw = bxc + nbx * bp;
+  double2 *tw1 = rw + ch * rp;
   double2 *tw2 = tw1 + n1;
   load_tw(tw1, g.tw1, n1);
   load_tw(tw2, g.tw2, n2);
@@ -279,20 +338,33 @@ __global__ __launch_bounds__(FFT_NT) void k_inv_plane(const Grid g, const FftKAr
   const long long fstride = (long long)ncols * g.nbz * plane_sz;
   double2 *out = ka.slab_out[kk] + ((long long)col * g.nbz + pz) * plane_sz;
   for (int f = 0; f < nfields; ++f) {
-    for (int i = threadIdx.x; i < n2 * pitch; i += blockDim.x) plane[i] = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < nbx * bp; i += blockDim.x) bxc[i] = make_double2(0.0, 0.0);
     __syncthreads();
     for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
       const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
       double2 c = in.c[(long long)gi + (long long)col * in.ldc];
       if (f > 0) c = cscale(c, sp.gk[3 * gi + (f - 1)]);
-      plane[(xy / n1) * pitch + (xy % n1)] = c;
+      const int y = xy / n1, x = xy - y * n1;
+      bxc[box_of(x, n1, bx) * bp + y] = c;
     }
     __syncthreads();
-    fft_block<1>(plane, LinesBox{g.bx, n1}, g.nbx, pitch, g.p2, tw2);  // along y, box columns
-    fft_block<1>(plane, LinesUniform{0, pitch}, n2, 1, g.p1, tw1);      // along x, all rows
+    fft_block<1, L2>(bxc, LinesUniform{0, bp}, nbx, 1, g.p2, tw2);  // along y, box columns
     double2 *o = out + f * fstride;
-    for (int i = threadIdx.x; i < n1 * n2; i += blockDim.x) o[i] = plane[(i / n1) * pitch + (i % n1)];
-    __syncthreads();
+    for (int y0 = 0; y0 < n2; y0 += ch) {
+      const int nr = (n2 - y0) < ch ? (n2 - y0) : ch;
+      for (int i = threadIdx.x; i < nr * n1; i += blockDim.x) {
+        const int r = i / n1, x = i - r * n1;
+        const int b = box_of(x, n1, bx);
+        rw[r * rp + x] = (b >= 0) ? bxc[b * bp + y0 + r] : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      fft_block<1, L1>(rw, LinesUniform{0, rp}, nr, 1, g.p1, tw1);  // along x
+      for (int i = threadIdx.x; i < nr * n1; i += blockDim.x) {
+        const int r = i / n1, x = i - r * n1;
+        o[(long long)(y0 + r) * n1 + x] = rw[r * rp + x];
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -301,32 +373,36 @@ __global__ __launch_bounds__(FFT_NT) void k_inv_plane(const Grid g, const FftKAr
 // MODE_V:    in field 0 (psi)                 -> out field 0 (Theta V psi)
 // otherwise: in fields psi, pi_x, pi_y, pi_z -> out Theta psi, Theta V psi,
 //            Theta pi_x psi, Theta pi_y psi, Theta pi_z psi
+// LDS: A [n3][T+1] (and B [n3][T+1] unless MODE_V), twiddles.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FFT_NT) void k_lines(const Grid g, const FftKArgs ka, int ncols, int mode, int T,
+template <int L3, bool VMODE>
+__global__ __launch_bounds__(FFT_NT) void k_lines(const Grid g, const FftKArgs ka, int ncols, int T,
                                                   const double *__restrict__ thv) {
   extern __shared__ double2 sm[];
   const int tile = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
-  const int n3 = g.n3, nbz = g.nbz, bz = g.bz;
+  const int n3 = L3 > 0 ? L3 : g.n3;
+  const int nbz = g.nbz, bz = g.bz;
   const long long plane_sz = (long long)g.n1 * g.n2;
   const int pos0 = tile * T;
   const int tp = T + 1;
+  constexpr bool vmode = VMODE;
   double2 *A = sm;
   double2 *B = sm + n3 * tp;
-  double2 *tw3 = B + n3 * tp;
+  double2 *tw3 = vmode ? B : B + n3 * tp;
   load_tw(tw3, g.tw3, n3);
   const long long fstride = (long long)ncols * nbz * plane_sz;
   const double2 *in = ka.slab_in[kk] + (long long)col * nbz * plane_sz;
   double2 *out = ka.slab_out[kk] + (long long)col * nbz * plane_sz;
   const int ntot = nbz * T;
 
+  // zero-fills the line buffer and places the box of kz values at z = kz mod n3
   auto load_field = [&](const double2 *src) {
-    for (int i = threadIdx.x; i < n3 * tp; i += blockDim.x) A[i] = make_double2(0.0, 0.0);
-    __syncthreads();
-    for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
-      const int p = i / T, t = i - p * T;
-      const int kz = p - bz;
-      const int z = kz < 0 ? kz + n3 : kz;
-      if (pos0 + t < plane_sz) A[z * tp + t] = src[(long long)p * plane_sz + pos0 + t];
+    for (int i = threadIdx.x; i < n3 * T; i += blockDim.x) {
+      const int z = i / T, t = i - z * T;
+      const int kz = z <= bz ? z : z - n3;
+      double2 v = make_double2(0.0, 0.0);
+      if ((kz >= -bz && kz <= bz) && pos0 + t < plane_sz) v = src[(long long)(kz + bz) * plane_sz + pos0 + t];
+      A[z * tp + t] = v;
     }
     __syncthreads();
   };
@@ -339,21 +415,21 @@ __global__ __launch_bounds__(FFT_NT) void k_lines(const Grid g, const FftKArgs k
     }
   };
 
-  if (mode == FFT_MODE_V) {
+  if constexpr (VMODE) {
     load_field(in);
-    fft_block<1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+    fft_block<1, L3>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
     for (int i = threadIdx.x; i < n3 * T; i += blockDim.x) {
       const int z = i / T, t = i - z * T;
       if (pos0 + t < plane_sz) A[z * tp + t] = cscale(A[z * tp + t], thv[(long long)z * plane_sz + pos0 + t]);
     }
     __syncthreads();
-    fft_block<-1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+    fft_block<-1, L3>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
     store_field(A, out);
     return;
-  }
+  } else {
   // psi -> Theta psi, Theta V psi
   load_field(in);
-  fft_block<1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+  fft_block<1, L3>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
   for (int i = threadIdx.x; i < n3 * T; i += blockDim.x) {
     const int z = i / T, t = i - z * T;
     double th = 0.0, tv = 0.0;
@@ -367,35 +443,40 @@ __global__ __launch_bounds__(FFT_NT) void k_lines(const Grid g, const FftKArgs k
     A[z * tp + t] = cscale(a, th);
   }
   __syncthreads();
-  fft_block<-1>(A, LinesTwo{0, n3 * tp, T}, 2 * T, tp, g.p3, tw3);
+  fft_block<-1, L3>(A, LinesTwo{0, n3 * tp, T}, 2 * T, tp, g.p3, tw3);
   store_field(A, out);
   store_field(B, out + fstride);
   __syncthreads();
   for (int f = 1; f <= 3; ++f) {
     load_field(in + f * fstride);
-    fft_block<1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+    fft_block<1, L3>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
     for (int i = threadIdx.x; i < n3 * T; i += blockDim.x) {
       const int z = i / T, t = i - z * T;
       const double th = (pos0 + t < plane_sz) ? g.theta[(long long)z * plane_sz + pos0 + t] : 0.0;
       A[z * tp + t] = cscale(A[z * tp + t], th);
     }
     __syncthreads();
-    fft_block<-1>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
+    fft_block<-1, L3>(A, LinesUniform{0, 1}, T, tp, g.p3, tw3);
     store_field(A, out + (f + 1) * fstride);
     __syncthreads();
+  }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Forward plane pass: slab planes -> values at the sphere, combined per mode.
 // ---------------------------------------------------------------------------
+template <int L1, int L2>
 __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKArgs ka, int ncols, int mode,
-                                                      double alpha_a, double beta_a) {
+                                                      double alpha_a, double beta_a, int ch) {
   extern __shared__ double2 sm[];
   const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
-  const int n1 = g.n1, n2 = g.n2, pitch = n1 + 1;
-  double2 *plane = sm;
-  double2 *tw1 = sm + n2 * pitch;
+  const int n1 = L1 > 0 ? L1 : g.n1, n2 = L2 > 0 ? L2 : g.n2;
+  const int bx = g.bx, nbx = g.nbx;
+  const int bp = n2 + 1, rp = n1 + 1;
+  double2 *bxc = sm;
+  double2 *rw = bxc + nbx * bp;
+  double2 *tw1 = rw + ch * rp;
   double2 *tw2 = tw1 + n1;
   load_tw(tw1, g.tw1, n1);
   load_tw(tw2, g.tw2, n2);
@@ -407,15 +488,29 @@ __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKAr
   const double2 *src0 = ka.slab_in[kk] + ((long long)col * g.nbz + pz) * plane_sz;
   const double inv_n = 1.0 / ((double)n1 * n2 * g.n3);
   const int nf = (mode == FFT_MODE_V) ? 1 : 5;
+  __syncthreads();
   for (int f = 0; f < nf; ++f) {
     const double2 *src = src0 + f * fstride;
-    for (int i = threadIdx.x; i < n1 * n2; i += blockDim.x) plane[(i / n1) * pitch + (i % n1)] = src[i];
-    __syncthreads();
-    fft_block<-1>(plane, LinesUniform{0, pitch}, n2, 1, g.p1, tw1);      // along x, all rows
-    fft_block<-1>(plane, LinesBox{g.bx, n1}, g.nbx, pitch, g.p2, tw2);  // along y, box columns
+    for (int y0 = 0; y0 < n2; y0 += ch) {
+      const int nr = (n2 - y0) < ch ? (n2 - y0) : ch;
+      for (int i = threadIdx.x; i < nr * n1; i += blockDim.x) {
+        const int r = i / n1, x = i - r * n1;
+        rw[r * rp + x] = src[(long long)(y0 + r) * n1 + x];
+      }
+      __syncthreads();
+      fft_block<-1, L1>(rw, LinesUniform{0, rp}, nr, 1, g.p1, tw1);  // along x
+      for (int i = threadIdx.x; i < nr * nbx; i += blockDim.x) {
+        const int r = i / nbx, b = i - r * nbx;
+        const int kx = b - bx;
+        bxc[b * bp + y0 + r] = rw[r * rp + (kx < 0 ? kx + n1 : kx)];
+      }
+      __syncthreads();
+    }
+    fft_block<-1, L2>(bxc, LinesUniform{0, bp}, nbx, 1, g.p2, tw2);  // along y, box columns
     for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
       const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
-      const double2 val = cscale(plane[(xy / n1) * pitch + (xy % n1)], inv_n);
+      const int y = xy / n1, x = xy - y * n1;
+      const double2 val = cscale(bxc[box_of(x, n1, bx) * bp + y], inv_n);
       const long long c = (long long)col;
       if (mode == FFT_MODE_V) {
         fo.o0[gi + c * fo.ld0] = val;
@@ -423,23 +518,22 @@ __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKAr
         double2 *hc = fo.o0 + gi + c * fo.ld0;
         const double gz = sp.gk[3 * gi + 2];
         if (f == 0) {
-          fo.o1[gi + c * fo.ld1] = val;                                    // S C
-          *hc = cscale(val, alpha_a * 0.5 * gz + beta_a);                  // (A/c) 1/2 gz F(Th psi) + (A^2/2c^2) F(Th psi)
+          fo.o1[gi + c * fo.ld1] = val;                    // S C
+          *hc = cscale(val, alpha_a * 0.5 * gz + beta_a);  // (A/c) 1/2 gz F(Th psi) + (A^2/2c^2) F(Th psi)
         } else if (f == 1) {
-          *hc = cadd(*hc, val);                                            // F(Th V psi)
+          *hc = cadd(*hc, val);                            // F(Th V psi)
         } else {
-          const double gi_c = sp.gk[3 * gi + (f - 2)];
-          double w = 0.5 * gi_c;                                           // 1/2 (G+k)_i F(Th pi_i psi)
-          if (f == 4) w += 0.5 * alpha_a;                                  // (A/c) 1/2 F(Th pi_z psi)
+          double w = 0.5 * sp.gk[3 * gi + (f - 2)];        // 1/2 (G+k)_i F(Th pi_i psi)
+          if (f == 4) w += 0.5 * alpha_a;                  // (A/c) 1/2 F(Th pi_z psi)
           *hc = cadd(*hc, cscale(val, w));
         }
       } else {  // TVPS
         const double gz = sp.gk[3 * gi + 2];
         if (f == 0) {
-          fo.o3[gi + c * fo.ld3] = val;                      // S
-          fo.o2[gi + c * fo.ld2] = cscale(val, 0.5 * gz);    // P part
+          fo.o3[gi + c * fo.ld3] = val;                    // S
+          fo.o2[gi + c * fo.ld2] = cscale(val, 0.5 * gz);  // P part
         } else if (f == 1) {
-          fo.o1[gi + c * fo.ld1] = val;                      // V
+          fo.o1[gi + c * fo.ld1] = val;                    // V
         } else {
           const double w = 0.5 * sp.gk[3 * gi + (f - 2)];
           double2 *t = fo.o0 + gi + c * fo.ld0;
@@ -455,24 +549,51 @@ __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKAr
   }
 }
 
-size_t plane_lds(const Grid &g) { return ((size_t)g.n2 * (g.n1 + 1) + g.n1 + g.n2) * sizeof(double2); }
+// ---------------------------------------------------------------------------
+// Launch configuration
+// ---------------------------------------------------------------------------
+constexpr int PLANE_CH = 8;  // rows per chunk of the plane passes
 
-int line_tile(const Grid &g) {
+size_t plane_lds(const Grid &g) {
+  return ((size_t)g.nbx * (g.n2 + 1) + (size_t)PLANE_CH * (g.n1 + 1) + g.n1 + g.n2) * sizeof(double2);
+}
+
+int line_tile(const Grid &g, bool vmode) {
   const long long plane_sz = (long long)g.n1 * g.n2;
+  const int nbuf = vmode ? 1 : 2;
+  const size_t budget = vmode ? 40 * 1024 : 52 * 1024;
   int t = 64;
-  while (t > 8 && (size_t)(2 * g.n3 * (t + 1) + g.n3) * sizeof(double2) > 80 * 1024) t /= 2;
+  while (t > 8 && (size_t)(nbuf * g.n3 * (t + 1) + g.n3) * sizeof(double2) > budget) t /= 2;
   while (t > 8 && t / 2 >= plane_sz) t /= 2;
   return t;
 }
 
-size_t line_lds(const Grid &g, int t) { return (size_t)(2 * g.n3 * (t + 1) + g.n3) * sizeof(double2); }
+size_t line_lds(const Grid &g, int t, bool vmode) {
+  return (size_t)((vmode ? 1 : 2) * g.n3 * (t + 1) + g.n3) * sizeof(double2);
+}
+
+template <class F>
+void each_plane_kernel(F &&f) {
+  f((const void *)k_inv_plane<0, 0>);
+  f((const void *)k_fwd_plane<0, 0>);
+#define LTD_PL(a, b)                            \
+  f((const void *)k_inv_plane<a, b>);           \
+  f((const void *)k_fwd_plane<a, b>);
+  LTD_PL(16, 16) LTD_PL(64, 64) LTD_PL(72, 72) LTD_PL(96, 96)
+#undef LTD_PL
+#define LTD_LK(a)                               \
+  f((const void *)k_lines<a, true>);            \
+  f((const void *)k_lines<a, false>);
+  LTD_LK(0) LTD_LK(16) LTD_LK(64) LTD_LK(72) LTD_LK(160)
+#undef LTD_LK
+}
 
 bool attrs_set = false;
 void set_attrs() {
   if (attrs_set) return;
-  (void)hipFuncSetAttribute((const void *)k_inv_plane, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  (void)hipFuncSetAttribute((const void *)k_fwd_plane, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  (void)hipFuncSetAttribute((const void *)k_lines, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  each_plane_kernel([](const void *k) {
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  });
   attrs_set = true;
 }
 
@@ -480,18 +601,13 @@ void set_attrs() {
 
 bool fft_plan_length(int L, FftPlan *p) {
   if (L < 2 || L > FFT_MAXLEN) return false;
+  const Radices f = factor_len(L);
+  int prod = 1;
+  for (int s = 0; s < f.n; ++s) prod *= f.r[s];
+  if (prod != L) return false;
   p->L = L;
-  p->nst = 0;
-  int r = L;
-  const int order[5] = {8, 4, 5, 3, 2};
-  for (int oi = 0; oi < 5; ++oi) {
-    while (r % order[oi] == 0 && r > 1) {
-      if (p->nst >= FFT_MAXST) return false;
-      p->radix[p->nst++] = order[oi];
-      r /= order[oi];
-    }
-  }
-  if (r != 1) return false;
+  p->nst = f.n;
+  for (int s = 0; s < f.n; ++s) p->radix[s] = f.r[s];
   // one wavefront must hold at least one line in every pass
   for (int s = 0; s < p->nst; ++s)
     if (L / p->radix[s] > 64 * tpl_of(p->radix[s])) return false;
@@ -501,30 +617,62 @@ bool fft_plan_length(int L, FftPlan *p) {
 void fft_init_attrs() { set_attrs(); }
 
 size_t fft_plane_lds_bytes(const Grid &g) { return plane_lds(g); }
-size_t fft_line_lds_bytes(const Grid &g) { return line_lds(g, line_tile(g)); }
+size_t fft_line_lds_bytes(const Grid &g) { return line_lds(g, line_tile(g, false), false); }
 
 hipError_t fft_inverse_planes(const Grid &g, const FftKArgs &ka, int nk, int ncols, int nfields, hipStream_t s) {
   set_attrs();
-  hipLaunchKernelGGL(k_inv_plane, dim3(g.nbz, ncols, nk), dim3(FFT_NT), plane_lds(g), s, g, ka, ncols, nfields);
+  const dim3 grid(g.nbz, ncols, nk), block(FFT_NT);
+  const size_t lds = plane_lds(g);
+#define LTD_INV(a, b) hipLaunchKernelGGL((k_inv_plane<a, b>), grid, block, lds, s, g, ka, ncols, nfields, PLANE_CH)
+  if (g.n1 == 16 && g.n2 == 16) LTD_INV(16, 16);
+  else if (g.n1 == 64 && g.n2 == 64) LTD_INV(64, 64);
+  else if (g.n1 == 72 && g.n2 == 72) LTD_INV(72, 72);
+  else if (g.n1 == 96 && g.n2 == 96) LTD_INV(96, 96);
+  else LTD_INV(0, 0);
+#undef LTD_INV
   return hipGetLastError();
 }
 
 hipError_t fft_lines(const Grid &g, const FftKArgs &ka, int nk, int ncols, int mode, const double *thv,
                      hipStream_t s) {
   set_attrs();
-  const int t = line_tile(g);
+  const bool vmode = (mode == FFT_MODE_V);
+  const int t = line_tile(g, vmode);
   const long long plane_sz = (long long)g.n1 * g.n2;
   const int ntile = (int)((plane_sz + t - 1) / t);
-  hipLaunchKernelGGL(k_lines, dim3(ntile, ncols, nk), dim3(FFT_NT), line_lds(g, t), s, g, ka, ncols, mode, t,
-                     thv);
+  const dim3 grid(ntile, ncols, nk), block(FFT_NT);
+  const size_t lds = line_lds(g, t, vmode);
+#define LTD_LN(a)                                                                               \
+  if (vmode) hipLaunchKernelGGL((k_lines<a, true>), grid, block, lds, s, g, ka, ncols, t, thv); \
+  else hipLaunchKernelGGL((k_lines<a, false>), grid, block, lds, s, g, ka, ncols, t, thv)
+  if (g.n3 == 16) {
+    LTD_LN(16);
+  } else if (g.n3 == 64) {
+    LTD_LN(64);
+  } else if (g.n3 == 72) {
+    LTD_LN(72);
+  } else if (g.n3 == 160) {
+    LTD_LN(160);
+  } else {
+    LTD_LN(0);
+  }
+#undef LTD_LN
   return hipGetLastError();
 }
 
 hipError_t fft_forward_planes(const Grid &g, const FftKArgs &ka, int nk, int ncols, int mode, double alpha_a,
                               double beta_a, hipStream_t s) {
   set_attrs();
-  hipLaunchKernelGGL(k_fwd_plane, dim3(g.nbz, ncols, nk), dim3(FFT_NT), plane_lds(g), s, g, ka, ncols, mode,
-                     alpha_a, beta_a);
+  const dim3 grid(g.nbz, ncols, nk), block(FFT_NT);
+  const size_t lds = plane_lds(g);
+#define LTD_FW(a, b) \
+  hipLaunchKernelGGL((k_fwd_plane<a, b>), grid, block, lds, s, g, ka, ncols, mode, alpha_a, beta_a, PLANE_CH)
+  if (g.n1 == 16 && g.n2 == 16) LTD_FW(16, 16);
+  else if (g.n1 == 64 && g.n2 == 64) LTD_FW(64, 64);
+  else if (g.n1 == 72 && g.n2 == 72) LTD_FW(72, 72);
+  else if (g.n1 == 96 && g.n2 == 96) LTD_FW(96, 96);
+  else LTD_FW(0, 0);
+#undef LTD_FW
   return hipGetLastError();
 }
 

@@ -56,7 +56,7 @@ __device__ inline void load_a(const ZProb &P, const double2 *A, int m0, int k0, 
 }
 
 template <int OPB>
-__device__ inline void load_b(const ZProb &P, const double2 *B, int n0, int k0, int kend, int t,
+__device__ inline void load_b(const ZProb &P, const double2 *B, const double2 *B2, int n0, int k0, int kend, int t,
                               Frag &f, int nlim) {
   if (OPB == OP_N) {  // B is k x n: tile column j is contiguous in kk
     const int j = t >> 2, kk = (t & 3) * 4;
@@ -64,7 +64,12 @@ __device__ inline void load_b(const ZProb &P, const double2 *B, int n0, int k0, 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kg = k0 + kk + q;
-      f.v[q] = (jg < nlim && kg < kend) ? B[(long long)kg + (long long)jg * P.ldb] : make_double2(0.0, 0.0);
+      double2 v = make_double2(0.0, 0.0);
+      if (jg < nlim && kg < kend) {
+        if (P.kseg > 0 && kg >= P.kseg) v = B2[(long long)(kg - P.kseg) + (long long)jg * P.ldb];
+        else v = B[(long long)kg + (long long)jg * P.ldb];
+      }
+      f.v[q] = v;
     }
   } else {  // B is n x k, op = conj-transpose: tile row kk is contiguous in j
     const int kk = t >> 4, j = (t & 15) * 4;
@@ -139,6 +144,7 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
 
   const double2 *A = P.A + (long long)bi * P.sA;
   const double2 *B = P.B + (long long)bi * P.sB;
+  const double2 *B2 = P.B2 ? P.B2 + (long long)bi * P.sB : nullptr;
   const int m0 = tm * BM, n0 = tn * BN;
   const int nlim = (n_limit > 0 && n_limit < P.n) ? n_limit : P.n;
   if (n0 >= nlim) return;  // whole block: columns beyond the limit
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
   Frag fa, fb;
   if (nkt > 0) {
     load_a<OPA>(P, A, m0, kbeg, kend, tid, fa);
-    load_b<OPB>(P, B, n0, kbeg, kend, tid, fb, nlim);
+    load_b<OPB>(P, B, B2, n0, kbeg, kend, tid, fb, nlim);
     store_a<OPA>(As[0], tid, fa);
     store_b<OPB>(Bs[0], tid, fb);
   }
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
     if (more) {
       const int k0 = kbeg + (kt + 1) * BK;
       load_a<OPA>(P, A, m0, k0, kend, tid, fa);
-      load_b<OPB>(P, B, n0, k0, kend, tid, fb, nlim);
+      load_b<OPB>(P, B, B2, n0, k0, kend, tid, fb, nlim);
     }
 #pragma unroll
     for (int kq = 0; kq < BK; kq += 4) {
@@ -246,13 +252,18 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
   }
 }
 
-// Sums the split-K partials of every output tile in split order, then
-// C = alpha * sum + beta * C.  One thread per output element.
+// Sums the split-K partials of every output tile in a fixed order, then
+// C = alpha * sum + beta * C.  A block covers 32 output elements of one tile;
+// its 256 threads are 32 elements x 8 groups, group g summing splits
+// g, g + 8, g + 16, ... in order, then the 8 group sums are added in order.
+constexpr int RED_E = 32, RED_G = 8;
+
 template <bool TABLE>
 __global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZProb *__restrict__ table,
                                                     int nprob, const double2 *__restrict__ partials, int n_limit) {
+  __shared__ double2 part[RED_G][RED_E];
   const ZProb *probs = TABLE ? table : batch.p;
-  const int per_tile = (BM * BN) / 256;  // blocks per tile
+  const int per_tile = (BM * BN) / RED_E;  // blocks per tile
   const int rt = blockIdx.x / per_tile;
   const int sub = blockIdx.x % per_tile;
   int pi = 0;
@@ -263,18 +274,27 @@ __global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZP
   const int tm = tl % P.tiles_m;
   const int tn = (tl / P.tiles_m) % P.tiles_n;
   const int bi = tl / (P.tiles_m * P.tiles_n);
-  const int e = sub * 256 + threadIdx.x;
+  const int el = threadIdx.x % RED_E, grp = threadIdx.x / RED_E;
+  const int e = sub * RED_E + el;
   const int il = e % BM, jl = e / BM;
   const int i = tm * BM + il, j = tn * BN + jl;
   const int nlim = (n_limit > 0 && n_limit < P.n) ? n_limit : P.n;
-  if (i >= P.m || j >= nlim) return;
-  const double2 *src = partials + (P.part_off + (long long)tl * P.ksplit) * (long long)(BM * BN) + e;
+  const bool live = (i < P.m && j < nlim);
   double2 s = make_double2(0.0, 0.0);
-  for (int q = 0; q < P.ksplit; ++q) s = cadd(s, src[(long long)q * BM * BN]);
-  double2 *C = P.C + (long long)bi * P.sC + (long long)i + (long long)j * P.ldc;
-  double2 v = cmul(P.alpha, s);
-  if (P.beta.x != 0.0 || P.beta.y != 0.0) v = cfma(P.beta, *C, v);
-  *C = v;
+  if (live) {
+    const double2 *src = partials + (P.part_off + (long long)tl * P.ksplit) * (long long)(BM * BN) + e;
+    for (int q = grp; q < P.ksplit; q += RED_G) s = cadd(s, src[(long long)q * BM * BN]);
+  }
+  part[grp][el] = s;
+  __syncthreads();
+  if (grp == 0 && live) {
+    double2 acc = part[0][el];
+    for (int g2 = 1; g2 < RED_G; ++g2) acc = cadd(acc, part[g2][el]);
+    double2 *C = P.C + (long long)bi * P.sC + (long long)i + (long long)j * P.ldc;
+    double2 v = cmul(P.alpha, acc);
+    if (P.beta.x != 0.0 || P.beta.y != 0.0) v = cfma(P.beta, *C, v);
+    *C = v;
+  }
 }
 
 template <bool TABLE>
@@ -298,7 +318,7 @@ hipError_t launch_impl(int opa, int opb, const ZBatch &b, const ZProb *table, co
     rtiles = host[i].rtile_begin + host[i].tiles_m * host[i].tiles_n * host[i].batch;
   }
   if (!split) return hipSuccess;
-  hipLaunchKernelGGL((zgemm_reduce<TABLE>), dim3(rtiles * ((BM * BN) / 256)), dim3(256), 0, s, b, table, nprob,
+  hipLaunchKernelGGL((zgemm_reduce<TABLE>), dim3(rtiles * ((BM * BN) / RED_E)), dim3(256), 0, s, b, table, nprob,
                      partials, n_limit);
   return hipGetLastError();
 }
@@ -316,12 +336,14 @@ size_t gemm_plan(ZProb *probs, int nprob, int *total_tiles, int target_blocks, l
     const int base = P.tiles_m * P.tiles_n * P.batch;
     const int kt = (P.k + BK - 1) / BK;
     int ks = 1;
-    if (base < target_blocks && kt >= 16) {
+    if (base > 0 && base < target_blocks && kt >= 4) {
+      // K-tiles per split: 8 when K is deep, fewer for shallow K (latency)
+      const int per = kt >= 64 ? 8 : (kt >= 16 ? 4 : 2);
       ks = (target_blocks + base - 1) / base;
-      ks = ks < kt / 8 ? ks : kt / 8;
+      ks = ks < kt / per ? ks : kt / per;
       if (ks < 1) ks = 1;
     }
-    if (ks > 1 && part + (long long)base * ks > max_part_tiles) {
+    if (ks > 1 && base > 0 && part + (long long)base * ks > max_part_tiles) {
       const long long room = (max_part_tiles - part) / base;
       ks = room > 1 ? (int)room : 1;
     }

@@ -189,6 +189,24 @@ class Ltd:
                 self.step(st)
         return st
 
+    def profile_steps(self, st, n_steps: int):
+        """Mean per-step duration (ms) of each stage over n_steps eager steps."""
+        buf = (C.c_double * _lib.LTD_PROFILE_STAGES)()
+        check(self.lib.ltd_profile_steps(self.handle, C.byref(st["args"]), n_steps, buf, self.stream()),
+              "ltd_profile_steps")
+        return list(buf)
+
+    def profile_apply(self, k: int, c):
+        """Stage durations (ms) of one H/S apply of the block c at A = 0."""
+        torch = _torch()
+        n, nb = c.shape
+        hc = torch.empty_like(c)
+        sc = torch.empty_like(c)
+        buf = (C.c_double * _lib.LTD_PROFILE_STAGES)()
+        check(self.lib.ltd_profile_apply(self.handle, k, _ptr(c), nb, n, _ptr(hc), _ptr(sc), nb, buf,
+                                         self.stream()), "ltd_profile_apply")
+        return list(buf), hc, sc
+
     def adjoint_step(self, st, n, n_steps, mu_next, mu_out, dl_da_mid, dl_da_t, terminal=False):
         a = AdjointArgs(fwd=C.pointer(st["args"]), n=n, terminal=1 if terminal else 0, n_steps=n_steps,
                         mu_next=_ptr(mu_next), mu_out=_ptr(mu_out), dl_da_mid=_ptr(dl_da_mid),
