@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--profile-steps", type=int, default=20)
     p.add_argument("--cpu-steps", type=int, default=6)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="only run 5 plain device-to-device copies of MIB MiB (counter calibration)")
     return p.parse_args()
 
 
@@ -116,6 +118,15 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         return 1
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "reads_plus_writes_per_copy": 2 * nbytes}))
+        return 0
     from paper_2403_04351_amd import ltd
     from synth import make_system, pulse_samples
 

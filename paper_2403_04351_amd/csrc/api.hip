@@ -49,7 +49,7 @@ struct KHost {
   size_t o_gk, o_pptr, o_ptsg, o_ptsxy;
   size_t o_subs;           // Tsub, Vsub, Psub, Ssub (4 n^2, Phi basis)
   size_t o_tilde;          // Tt, Vt_ref, Pt (3 n^2), then H0t (n^2)
-  size_t o_L, o_Linv, o_vstep, o_work;
+  size_t o_L, o_Linv, o_LH, o_LinvH, o_vstep, o_work, o_hm, o_dev;
   size_t o_phit, o_yext, o_cache;
   // bound subspace
   bool bound = false;
@@ -82,6 +82,7 @@ struct ltd_system {
   Grid grid{};
   int chunk = 0;        // columns per apply pass
   bool h_in_lds = false;
+  bool p_in_lds = false;
   // workspace
   char *ws = nullptr;
   size_t ws_need = 0, ws_bound = 0;
@@ -541,6 +542,7 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
   c.n_states = sys->n_states;
   c.n_k = sys->n_k;
   c.h_in_lds = sys->h_in_lds ? 1 : 0;
+  c.p_in_lds = sys->p_in_lds ? 1 : 0;
   c.rebuild = (a->mode == LTD_STEP_REBUILD) ? 1 : 0;
   c.step = a->step;
   c.step_rw = a->step;
@@ -802,6 +804,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   const int n = sys->n_aux;
   const long long n2 = (long long)n * n;
   sys->h_in_lds = step_lds_bytes(n, true, true) <= 150 * 1024;
+  sys->p_in_lds = sys->h_in_lds && step_lds_bytes(n, true, false, true) <= 150 * 1024;
   // workspace plan
   Arena ar;
   sys->o_tw1 = ar.take(g.n1 * sizeof(double2));
@@ -847,7 +850,11 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     kh.o_tilde = ar.take((size_t)4 * n2 * sizeof(double2));
     kh.o_L = ar.take((size_t)n2 * sizeof(double2));
     kh.o_Linv = ar.take((size_t)n2 * sizeof(double2));
+    kh.o_LH = ar.take((size_t)n2 * sizeof(double2));
+    kh.o_LinvH = ar.take((size_t)n2 * sizeof(double2));
     kh.o_vstep = ar.take((size_t)n2 * sizeof(double2));
+    kh.o_hm = ar.take((size_t)n2 * sizeof(double2));
+    kh.o_dev = ar.take((size_t)assemble_blocks(n) * sizeof(double));
     kh.o_work = sys->h_in_lds ? 0 : ar.take((size_t)sys->n_states * n2 * sizeof(double2));
     kh.o_phit = ar.take((size_t)kh.k_ext * n * sizeof(double2));
     kh.o_yext = ar.take((size_t)kh.k_ext * n * sizeof(double2));
@@ -1028,7 +1035,13 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
   d.vt_step = sys->at<double2>(kh.o_vstep);
   d.L = L;
   d.Linv = Li;
+  d.LH = sys->at<double2>(kh.o_LH);
+  d.LinvH = sys->at<double2>(kh.o_LinvH);
+  LTD_HIP(launch_conj_transpose(L, sys->at<double2>(kh.o_LH), n, s));
+  LTD_HIP(launch_conj_transpose(Li, sys->at<double2>(kh.o_LinvH), n, s));
   d.work = sys->h_in_lds ? nullptr : sys->at<double2>(kh.o_work);
+  d.hm = sys->at<double2>(kh.o_hm);
+  d.dev = sys->at<double>(kh.o_dev);
   d.kw = sys->kw[k];
   d.c0 = 0.5 * (lmax + lmin);
   d.margin = 0.25 * half + 0.2;

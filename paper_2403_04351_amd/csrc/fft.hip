@@ -552,10 +552,14 @@ __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKAr
 // ---------------------------------------------------------------------------
 // Launch configuration
 // ---------------------------------------------------------------------------
-constexpr int PLANE_CH = 8;  // rows per chunk of the plane passes
+// rows per chunk of the plane passes: every wavefront transforms its full share of lines
+int plane_ch(const Grid &g) {
+  const int ch = (FFT_NT / 64) * lines_per_wave(g.p1);
+  return ch < g.n2 ? ch : g.n2;
+}
 
 size_t plane_lds(const Grid &g) {
-  return ((size_t)g.nbx * (g.n2 + 1) + (size_t)PLANE_CH * (g.n1 + 1) + g.n1 + g.n2) * sizeof(double2);
+  return ((size_t)g.nbx * (g.n2 + 1) + (size_t)plane_ch(g) * (g.n1 + 1) + g.n1 + g.n2) * sizeof(double2);
 }
 
 int line_tile(const Grid &g, bool vmode) {
@@ -623,7 +627,7 @@ hipError_t fft_inverse_planes(const Grid &g, const FftKArgs &ka, int nk, int nco
   set_attrs();
   const dim3 grid(g.nbz, ncols, nk), block(FFT_NT);
   const size_t lds = plane_lds(g);
-#define LTD_INV(a, b) hipLaunchKernelGGL((k_inv_plane<a, b>), grid, block, lds, s, g, ka, ncols, nfields, PLANE_CH)
+#define LTD_INV(a, b) hipLaunchKernelGGL((k_inv_plane<a, b>), grid, block, lds, s, g, ka, ncols, nfields, plane_ch(g))
   if (g.n1 == 16 && g.n2 == 16) LTD_INV(16, 16);
   else if (g.n1 == 64 && g.n2 == 64) LTD_INV(64, 64);
   else if (g.n1 == 72 && g.n2 == 72) LTD_INV(72, 72);
@@ -666,7 +670,7 @@ hipError_t fft_forward_planes(const Grid &g, const FftKArgs &ka, int nk, int nco
   const dim3 grid(g.nbz, ncols, nk), block(FFT_NT);
   const size_t lds = plane_lds(g);
 #define LTD_FW(a, b) \
-  hipLaunchKernelGGL((k_fwd_plane<a, b>), grid, block, lds, s, g, ka, ncols, mode, alpha_a, beta_a, PLANE_CH)
+  hipLaunchKernelGGL((k_fwd_plane<a, b>), grid, block, lds, s, g, ka, ncols, mode, alpha_a, beta_a, plane_ch(g))
   if (g.n1 == 16 && g.n2 == 16) LTD_FW(16, 16);
   else if (g.n1 == 64 && g.n2 == 64) LTD_FW(64, 64);
   else if (g.n1 == 72 && g.n2 == 72) LTD_FW(72, 72);

@@ -18,7 +18,11 @@ struct SubDev {
   double2 *vt_step;        // V~ rebuilt for the current step (raw, made Hermitian on use)
   const double2 *L;        // Cholesky factor of S_sub (Phi basis), lower
   const double2 *Linv;     // L^{-1}
+  const double2 *LH;       // L^H (explicit, for coalesced products)
+  const double2 *LinvH;    // L^{-H}
   double2 *work;           // n_states x n_aux^2 scratch when H~ does not fit in LDS
+  double2 *hm;             // (H~(t_n + dt/2) - c0)/r of the current step (n_aux^2)
+  double *dev;             // per-block partial sums of ||H~(t) - H~0||_F^2
   double kw;               // k-point weight
   double c0, r;            // Chebyshev interval [c0 - r, c0 + r]
   double margin;           // largest ||H~(t) - H~0||_F the interval covers
@@ -31,6 +35,7 @@ struct StepCtx {
   const SubDev *sub;       // device array [n_k]
   int n_aux, n_states, n_k;
   int h_in_lds;
+  int p_in_lds;            // P~ also resident in LDS
   int rebuild;
   const int *step;         // device step counter n
   int *step_rw;            // same pointer, advanced by the finaliser
@@ -62,9 +67,11 @@ hipError_t launch_thv(double *out, const double *th, const double *v, long long 
 hipError_t launch_cholesky(const double2 *S, double2 *L, int n, int *status, int *fail, hipStream_t s);
 hipError_t launch_trtri(const double2 *L, double2 *Li, int n, hipStream_t s);
 hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s);
-size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint);
+size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint, bool p_in_lds = false);
+hipError_t launch_conj_transpose(const double2 *a, double2 *out, int n, hipStream_t s);
 void subspace_init_attrs();  // LDS limits of the step kernels (call outside graph capture)
 hipError_t launch_step(const StepCtx &c, hipStream_t s);
+int assemble_blocks(int n);
 hipError_t launch_adjoint(const StepCtx &c, const AdjCtx &a, hipStream_t s);
 hipError_t launch_knot_samples(const double *q, int nk, double t_end, double dt, int ns, double *a_t,
                                double *a_mid, hipStream_t s);

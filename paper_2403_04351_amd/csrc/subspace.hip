@@ -36,6 +36,7 @@ __device__ void matvec(const double2 *A, int lda, const double2 *v, double2 *y, 
     double2 s = make_double2(0.0, 0.0);
     if (part < np) {
       const int k0 = (part * n) / np, k1 = ((part + 1) * n) / np;
+#pragma unroll 8
       for (int k = k0; k < k1; ++k) {
         if (CONJT) s = cfma(cconj(A[(long long)k + (long long)i * lda]), v[k], s);
         else s = cfma(A[(long long)i + (long long)k * lda], v[k], s);
@@ -74,6 +75,40 @@ __device__ double block_sum(double x, double *sred) {
   const double r = sred[0];
   __syncthreads();
   return r;
+}
+
+// Sums of three doubles over the block: butterfly within each wavefront, then
+// the per-wave sums in wave order (deterministic).  sred: >= 3 * (blockDim/64).
+__device__ inline double wave_sum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ void block_sum3(double &a, double &b, double &c, double *sred) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  if (lane == 0) {
+    sred[3 * wv] = a;
+    sred[3 * wv + 1] = b;
+    sred[3 * wv + 2] = c;
+  }
+  __syncthreads();
+  a = b = c = 0.0;
+  for (int q = 0; q < nw; ++q) {
+    a += sred[3 * q];
+    b += sred[3 * q + 1];
+    c += sred[3 * q + 2];
+  }
+  __syncthreads();
+}
+
+__global__ void k_conj_transpose(const double2 *a, double2 *out, int n) {
+  const long long tot = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    out[e] = cconj(a[j + (long long)i * n]);
+  }
 }
 
 // Re sum_i conj(a_i) b_i over n entries in LDS (block-wide, fixed order).
@@ -295,75 +330,127 @@ __global__ __launch_bounds__(1024) void k_jacobi(double2 *A, double2 *V, double 
 // ---------------------------------------------------------------------------
 // Per-step propagation of one state (blockIdx.x) of one k-point (blockIdx.y).
 // ---------------------------------------------------------------------------
+// (H~(mid) - c0)/r for every k-point, one thread per element, and per-block
+// partial sums of ||H~(mid) - H~0||_F^2 for the spectral-interval check.
+// grid (assemble_blocks(n), n_k).
+__global__ __launch_bounds__(256) void k_assemble(const StepCtx c) {
+  __shared__ double sred[16];
+  const int k = blockIdx.y;
+  const SubDev &S = c.sub[k];
+  const int n = c.n_aux;
+  const long long n2 = (long long)n * n;
+  const int step = *c.step;
+  const double am = c.a_mid[step];
+  const double cl = c.c_light;
+  const double al = am / cl, be = am * am / (2.0 * cl * cl);
+  const double ir = 1.0 / S.r;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double dev2 = 0.0;
+  if (e < n2) {
+    const int a = (int)(e % n), b = (int)(e / n);
+    double2 vv;
+    if (c.rebuild) {  // Hermitian part of the rebuilt matrix
+      const double2 x = S.vt_step[e], y = S.vt_step[b + (long long)a * n];
+      vv = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    } else {
+      vv = S.vt_ref[e];
+    }
+    double2 h = cadd(S.tt[e], vv);
+    h = cadd(h, cscale(S.pt[e], al));
+    if (a == b) h.x += be;
+    const double2 d = csub(h, S.h0t[e]);
+    dev2 = d.x * d.x + d.y * d.y;
+    if (a == b) h.x -= S.c0;
+    S.hm[e] = cscale(h, ir);
+  }
+  dev2 = wave_sum(dev2);
+  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = dev2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sred[q];
+    S.dev[blockIdx.x] = t;
+  }
+}
+
+// Copies n elements global -> LDS, eight loads in flight per thread.
+__device__ inline void stage_to_lds(double2 *dst, const double2 *src, long long n) {
+  const long long nt = blockDim.x;
+  long long e = threadIdx.x;
+  for (; e + 7 * nt < n; e += 8 * nt) {
+    double2 r[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = src[e + q * nt];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dst[e + q * nt] = r[q];
+  }
+  for (; e < n; e += nt) dst[e] = src[e];
+}
+
 __global__ __launch_bounds__(256) void k_step(const StepCtx c) {
   extern __shared__ double2 sm[];
   const int j = blockIdx.x, k = blockIdx.y;
   const SubDev &S = c.sub[k];
   const int n = c.n_aux;
-  const bool hl = c.h_in_lds;
-  double2 *Hm = hl ? sm : S.work + (long long)j * n * n;  // (H~(mid) - c0)/r
-  double2 *vec = hl ? sm + (long long)n * n : sm;
+  const long long n2 = (long long)n * n;
+  const bool hl = c.h_in_lds, pl = c.p_in_lds;
+  double2 *Hm = hl ? sm : S.hm;  // (H~(mid) - c0)/r
+  double2 *Pl = pl ? sm + n2 : nullptr;
+  double2 *vec = sm + (hl ? n2 : 0) + (pl ? n2 : 0);
+  const double2 *P = pl ? Pl : S.pt;
   double2 *v = vec, *t0 = vec + n, *t1 = vec + 2 * n, *acc = vec + 3 * n, *tmp = vec + 4 * n, *w = vec + 5 * n;
   double2 *red = vec + 6 * n;
   double *sred = reinterpret_cast<double *>(red + blockDim.x);
   const int step = *c.step;
   const double am = c.a_mid[step], a1 = c.a_t[step + 1];
   const double cl = c.c_light;
-  const double al = am / cl, be = am * am / (2.0 * cl * cl);
-  const double ir = 1.0 / S.r;
 
-  // 1. H~(mid) = T~ + V~ + (A/c) P~ + (A^2/2c^2) I, shifted and scaled; spectral check
-  double dev2 = 0.0;
-  const double2 *Vs = c.rebuild ? S.vt_step : S.vt_ref;
-  for (long long e = threadIdx.x; e < (long long)n * n; e += blockDim.x) {
-    const int a = (int)(e % n), b = (int)(e / n);
-    double2 vv;
-    if (c.rebuild) {  // Hermitian part of the rebuilt matrix
-      const double2 x = Vs[e], y = Vs[b + (long long)a * n];
-      vv = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
-    } else {
-      vv = Vs[e];
-    }
-    double2 h = cadd(S.tt[e], vv);
-    h = cadd(h, cscale(S.pt[e], al));
-    if (a == b) h.x += be;
-    const double2 d = csub(h, S.h0t[e]);
-    dev2 += d.x * d.x + d.y * d.y;
-    if (a == b) h.x -= S.c0;
-    Hm[e] = cscale(h, ir);
+  // 1. the assembled (H~(mid) - c0)/r (k_assemble) into LDS; spectral check
+  if (hl) stage_to_lds(Hm, S.hm, n2);
+  if (pl) stage_to_lds(Pl, S.pt, n2);
+  if (j == 0 && threadIdx.x == 0) {
+    double dev2 = 0.0;
+    const int nb = (int)((n2 + 255) / 256);
+    for (int q = 0; q < nb; ++q) dev2 += S.dev[q];
+    if (!(sqrt(dev2) <= S.margin)) latch(c.status, 4);
   }
-  dev2 = block_sum(dev2, sred);
-  if (j == 0 && threadIdx.x == 0 && !(sqrt(dev2) <= S.margin)) latch(c.status, 4);
+  __syncthreads();
 
   // 2. theta~ = L^H theta
   double2 *th = c.theta + (long long)k * n * c.n_states + (long long)j * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) tmp[i] = th[i];
   __syncthreads();
-  matvec<true>(S.L, n, tmp, v, n, red);
+  matvec<false>(S.LH, n, tmp, v, n, red);
 
   // observables of theta~ in v at A = a (H~(a) v built from M v):
   //   J = -(f/Omega) w_k Re(v^H P~ v + (a/c) v^H v),  E = f w_k Re v^H H~(a) v
-  auto observe = [&](double a, double *jo, double *eo) {
-    matvec<false>(Hm, n, v, t0, n, red);      // t0 = M v
-    matvec<false>(S.pt, n, v, t1, n, red);    // t1 = P~ v
-    const double vv = dot_re(v, v, n, sred);
-    const double vp = dot_re(v, t1, n, sred);
-    const double vm = dot_re(v, t0, n, sred);
-    // v^H H~(a) v = r vm + c0 vv + ((a - am)/c) vp + ((a^2 - am^2)/2c^2) vv
-    const double vh = S.r * vm + S.c0 * vv + ((a - am) / cl) * vp + ((a * a - am * am) / (2.0 * cl * cl)) * vv;
+  // ref = false: H~(a) v from the step's M = (H~(mid) - c0)/r;
+  // ref = true:  H~(a) v from H~0 (the reference potential, the only one known at t_0)
+  auto observe = [&](double a, double *jo, double *eo, bool ref) {
+    matvec<false>(ref ? S.h0t : Hm, n, v, t0, n, red);  // t0 = M v  or  H~0 v
+    matvec<false>(P, n, v, t1, n, red);                  // t1 = P~ v
+    double vv = 0.0, vp = 0.0, vm = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      vv += v[i].x * v[i].x + v[i].y * v[i].y;
+      vp += v[i].x * t1[i].x + v[i].y * t1[i].y;
+      vm += v[i].x * t0[i].x + v[i].y * t0[i].y;
+    }
+    block_sum3(vv, vp, vm, sred);
+    // v^H H~(a) v = r vm + c0 vv + ((a - am)/c) vp + ((a^2 - am^2)/2c^2) vv   (step matrix)
+    //             = vm + (a/c) vp + (a^2/2c^2) vv                              (reference)
+    const double vh = ref ? vm + (a / cl) * vp + (a * a / (2.0 * cl * cl)) * vv
+                          : S.r * vm + S.c0 * vv + ((a - am) / cl) * vp + ((a * a - am * am) / (2.0 * cl * cl)) * vv;
     if (threadIdx.x == 0) {
       *jo = -(c.occ / c.omega) * S.kw * (vp + (a / cl) * vv);
       *eo = c.occ * S.kw * vh;
     }
-    __syncthreads();
   };
   double *part = c.part + 4 * ((long long)k * c.n_states + j);
-  if (step == 0) observe(c.a_t[0], part + 2, part + 3);
+  if (step == 0) observe(c.a_t[0], part + 2, part + 3, true);
 
   // 3. Chebyshev series
   const int K = S.K;
   for (int i = threadIdx.x; i < n; i += blockDim.x) t0[i] = v[i];
-  __syncthreads();
   matvec<false>(Hm, n, v, t1, n, red);
   for (int i = threadIdx.x; i < n; i += blockDim.x) acc[i] = cadd(cmul(S.coef[0], t0[i]), cmul(S.coef[1], t1[i]));
   __syncthreads();
@@ -385,11 +472,11 @@ __global__ __launch_bounds__(256) void k_step(const StepCtx c) {
   __syncthreads();
 
   // 4. theta = L^{-H} theta~
-  matvec<true>(S.Linv, n, v, w, n, red);
+  matvec<false>(S.LinvH, n, v, w, n, red);
   for (int i = threadIdx.x; i < n; i += blockDim.x) th[i] = w[i];
 
   // 5. observables at t_{n+1}
-  observe(a1, part + 0, part + 1);
+  observe(a1, part + 0, part + 1, false);
 }
 
 // Sums the per-state partials in a fixed order, writes the series, advances the step.
@@ -455,7 +542,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepCtx c, const AdjCtx a
   const double2 *th = c.theta + (long long)k * n * c.n_states + (long long)j * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) tmp[i] = th[i];
   __syncthreads();
-  matvec<true>(S.L, n, tmp, v, n, red);  // theta~_n
+  matvec<false>(S.LH, n, tmp, v, n, red);  // theta~_n
   const double vv = dot_re(v, v, n, sred);
   const double djda = -(c.occ / (c.omega * cl)) * S.kw * vv;
   matvec<false>(S.pt, n, v, tmp2, n, red);  // P~ theta~_n (for the source term)
@@ -695,12 +782,22 @@ hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s
   return hipGetLastError();
 }
 
-size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint) {
+size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint, bool p_in_lds) {
   const size_t vecs = adjoint ? 11 : 6;
-  return ((h_in_lds ? (size_t)n * n : 0) + vecs * n + 256) * sizeof(double2) + 256 * sizeof(double);
+  const size_t mats = (h_in_lds ? (size_t)n * n : 0) + ((!adjoint && p_in_lds) ? (size_t)n * n : 0);
+  return (mats + vecs * n + 256) * sizeof(double2) + 256 * sizeof(double);
+}
+
+hipError_t launch_conj_transpose(const double2 *a, double2 *out, int n, hipStream_t s) {
+  const long long tot = (long long)n * n;
+  const int g = (int)((tot + 255) / 256 < 4096 ? (tot + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_conj_transpose, dim3(g), dim3(256), 0, s, a, out, n);
+  return hipGetLastError();
 }
 
 static bool g_step_attr = false;
+
+int assemble_blocks(int n) { return (int)(((long long)n * n + 255) / 256); }
 
 void subspace_init_attrs() {
   if (g_step_attr) return;
@@ -711,7 +808,11 @@ void subspace_init_attrs() {
 
 hipError_t launch_step(const StepCtx &c, hipStream_t s) {
   subspace_init_attrs();
-  hipLaunchKernelGGL(k_step, dim3(c.n_states, c.n_k), dim3(256), step_lds_bytes(c.n_aux, c.h_in_lds, false), s, c);
+  hipLaunchKernelGGL(k_assemble, dim3(assemble_blocks(c.n_aux), c.n_k), dim3(256), 0, s, c);
+  hipError_t e0 = hipGetLastError();
+  if (e0 != hipSuccess) return e0;
+  hipLaunchKernelGGL(k_step, dim3(c.n_states, c.n_k), dim3(256),
+                     step_lds_bytes(c.n_aux, c.h_in_lds, false, c.p_in_lds), s, c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, c);

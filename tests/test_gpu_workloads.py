@@ -1,0 +1,182 @@
+"""GPU parity at the benchmark's size and launch configuration (72^3 grid,
+N_G = 12000, N_aux = 64, 1000 graph-replayed REBUILD steps) and with a
+potential that really changes every step.
+
+Sampled outputs where the oracle must compute them one by one (applies on a
+few columns, the first REBUILD steps); the full 1000-step series against the
+oracle's AFFINE propagation, which is exact for the static potential (REBUILD
+= AFFINE to rounding, tested on the tiny workload).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import operators as op
+from oracle import propagate as pr
+from oracle import subspace as ss
+from synth import make_system, pulse_samples, td_potential
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def rel_max(x, ref):
+    return float(np.abs(np.asarray(x) - np.asarray(ref)).max() / np.abs(np.asarray(ref)).max())
+
+
+@pytest.fixture(scope="module")
+def w1():
+    import torch
+
+    from paper_2403_04351_amd import ltd
+
+    sys = make_system(1)
+    phi, eps = ss.ground_state(sys, 0)  # oracle Rayleigh-Ritz of the start block
+    sub = ss.project(sys, 0, phi)
+    lt = ltd.Ltd(sys, max_cols=64)
+    phid = ltd.colmajor(phi, lt.device)
+    lt.project_subspace(0, phid)
+    torch.cuda.synchronize()
+    return dict(sys=sys, phi=phi, eps=eps, sub=sub, lt=lt, ltd=ltd, phid=phid, torch=torch)
+
+
+def test_full_size_apply_sampled_columns(w1):
+    sys, lt, ltd, phi = w1["sys"], w1["lt"], w1["ltd"], w1["phi"]
+    rng = np.random.default_rng(11)
+    c = np.hstack([phi[:, [0, 31, 63]],
+                   rng.standard_normal((sys.n_basis(0), 2)) + 1j * rng.standard_normal((sys.n_basis(0), 2))])
+    hc, sc = lt.apply_hs(0, ltd.colmajor(c, lt.device), 0.0041)
+    w1["torch"].cuda.synchronize()
+    hr, sr = op.apply_hs(sys, 0, c, 0.0041)
+    print(f"full-size apply: H {rel_max(ltd.to_numpy(hc), hr):.2e} S {rel_max(ltd.to_numpy(sc), sr):.2e}",
+          flush=True)
+    assert rel_max(ltd.to_numpy(hc), hr) < TOL
+    assert rel_max(ltd.to_numpy(sc), sr) < TOL
+
+
+def test_full_size_projection_and_spectrum(w1):
+    lt, sub, eps = w1["lt"], w1["sub"], w1["eps"]
+    ltd = w1["ltd"]
+    h0, s, _ = lt.project_subspace(0, w1["phid"])
+    w1["torch"].cuda.synchronize()
+    assert rel_max(ltd.to_numpy(h0), sub["H0"]) < TOL
+    assert rel_max(ltd.to_numpy(s), sub["S"]) < TOL
+    emin, emax, dtcr = lt.subspace_info(0)
+    assert abs(emin - eps[0]) < 1e-10 * abs(eps[0]) and abs(emax - eps[-1]) < 1e-10 * abs(eps[-1])
+
+
+def test_full_size_ritz_on_gpu(w1):
+    sys, ltd, torch = w1["sys"], w1["ltd"], w1["torch"]
+    lt2 = ltd.Ltd(sys, max_cols=64)
+    x = ltd.colmajor(sys.kpts[0].start[:, :64], lt2.device)
+    e = lt2.ritz_basis(0, x)
+    torch.cuda.synchronize()
+    assert rel_max(e.cpu().numpy(), w1["eps"]) < TOL
+
+
+def test_bench_configuration_1000_steps(w1):
+    """REBUILD, hipGraph replay, 1000 steps of dt = 0.2 (the benchmark's launch)."""
+    sys, lt, ltd, torch, sub, phi = w1["sys"], w1["lt"], w1["ltd"], w1["torch"], w1["sub"], w1["phi"]
+    lt.project_subspace(0, w1["phid"])
+    a_t, a_mid = pulse_samples(sys)
+    th0 = pr.initial_theta(64, 5)
+    theta = torch.from_numpy(np.ascontiguousarray(th0.T)[None]).to(lt.device)
+    st = lt.propagate(ltd.LTD_STEP_REBUILD, sys.dt, torch.from_numpy(a_t).to(lt.device),
+                      torch.from_numpy(a_mid).to(lt.device), theta, sys.n_steps)
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+    ref = pr.propagate(sub, th0, a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light)
+    j, e, dmu = st["j"].cpu().numpy(), st["e"].cpu().numpy(), st["dmu"].cpu().numpy()
+    th = st["theta"][0].cpu().numpy().T
+    print(f"1000 steps: J {rel_max(j, ref['J']):.2e} E {rel_max(e, ref['E']):.2e} "
+          f"dmu {rel_max(dmu, ref['dmu']):.2e} theta {rel_max(th, ref['theta']):.2e}", flush=True)
+    assert rel_max(j, ref["J"]) < TOL
+    assert rel_max(e, ref["E"]) < TOL
+    assert rel_max(th, ref["theta"]) < TOL
+    jr = ref["J"] - ref["J"][0]
+    assert np.abs((j - j[0]) - jr).max() < 1e-8 * np.abs(jr).max()
+    assert rel_max(dmu, ref["dmu"]) < 1e-8
+    # the first steps against the oracle's own per-step rebuild
+    n3 = 3
+    vfn = lambda n: ss.rebuild_v_sub(sys, 0, phi)
+    ref3 = pr.propagate(sub, th0, a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light, v_sub_fn=vfn,
+                        n_steps=n3)
+    assert rel_max(j[: n3 + 1], ref3["J"]) < TOL
+
+
+def _td_run(cfg_sys, phi, sub, lt, ltd, torch, n_steps, eps_v=1e-2):
+    """REBUILD with V(t) = V + eps s(t) W and h(t) = h + eps s(t) w, s = A/max|A|,
+    handed to the library step by step; oracle rebuilds the same potential."""
+    sys = cfg_sys
+    eps, wfield, wblk = td_potential(sys, eps_v)
+    a_t, a_mid = pulse_samples(sys, n_steps)
+    amax = np.abs(a_mid).max()
+    s_n = a_mid / amax
+    dev = lt.device
+    v_t = torch.zeros(sys.n_grid, dtype=torch.float64, device=dev)
+    h_t = torch.zeros_like(lt.h)
+    v0 = torch.from_numpy(np.ascontiguousarray(sys.vr.ravel())).to(dev)
+    w0 = torch.from_numpy(np.ascontiguousarray(wfield.ravel())).to(dev)
+    wb = torch.from_numpy(np.concatenate([np.ascontiguousarray(x.T).ravel() for x in wblk])).to(dev)
+    th0 = pr.initial_theta(sys.n_aux, sys.n_states)
+    theta = torch.from_numpy(np.ascontiguousarray(th0.T)[None]).to(dev)
+    lt.project_subspace(0, ltd.colmajor(phi, dev))
+    st = lt.make_step_args(ltd.LTD_STEP_REBUILD, sys.dt, torch.from_numpy(a_t).to(dev),
+                           torch.from_numpy(a_mid).to(dev), theta, n_steps, v_r_t=v_t, h_t=h_t)
+    for n in range(n_steps):
+        v_t.copy_(v0 + eps * s_n[n] * w0)
+        h_t.copy_(lt.h + eps * s_n[n] * wb)
+        lt.step(st)
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+
+    def vfn(n):
+        return ss.rebuild_v_sub(sys, 0, phi, vr=sys.vr + eps * s_n[n] * wfield,
+                                h=[h + eps * s_n[n] * w for h, w in zip(sys.h, wblk)])
+
+    ref = pr.propagate(sub, th0, a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light, v_sub_fn=vfn)
+    return st, ref
+
+
+def test_time_dependent_potential_tiny():
+    import torch
+
+    from paper_2403_04351_amd import ltd
+
+    sys = make_system(0)
+    phi, _ = ss.ground_state(sys, 0)
+    sub = ss.project(sys, 0, phi)
+    lt = ltd.Ltd(sys)
+    st, ref = _td_run(sys, phi, sub, lt, ltd, torch, 60)
+    j = st["j"].cpu().numpy()
+    jr = ref["J"] - ref["J"][0]
+    print(f"td potential (tiny): J {rel_max(j, ref['J']):.2e} J_ind {rel_max(j - j[0], jr):.2e}", flush=True)
+    assert rel_max(j, ref["J"]) < TOL
+    assert rel_max(st["e"].cpu().numpy(), ref["E"]) < TOL
+    assert rel_max(st["theta"][0].cpu().numpy().T, ref["theta"]) < TOL
+
+
+def test_time_dependent_potential_full_size(w1):
+    st, ref = _td_run(w1["sys"], w1["phi"], w1["sub"], w1["lt"], w1["ltd"], w1["torch"], 4)
+    j = st["j"].cpu().numpy()
+    assert rel_max(j, ref["J"]) < TOL
+    assert rel_max(st["theta"][0].cpu().numpy().T, ref["theta"]) < TOL
+
+
+def test_edge_cases(w1):
+    """Zero columns, maximum columns, A = 0, a non-finite A is rejected."""
+    from paper_2403_04351_amd import _lib
+
+    sys, lt, ltd, torch = w1["sys"], w1["lt"], w1["ltd"], w1["torch"]
+    nb = sys.n_basis(0)
+    empty = torch.zeros((0, nb), dtype=torch.complex128, device=lt.device)
+    hc, sc = lt.apply_hs(0, empty, 0.0)
+    assert hc.numel() == 0
+    big = torch.zeros((65, nb), dtype=torch.complex128, device=lt.device)
+    with pytest.raises(_lib.LtdError) as ei:
+        lt.apply_hs(0, big, 0.0)
+    assert ei.value.code == _lib.LTD_ESHAPE
+    with pytest.raises(_lib.LtdError) as ei:
+        lt.apply_hs(0, w1["phid"][:2].contiguous(), float("nan"))
+    assert ei.value.code == _lib.LTD_EINVAL
