@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "KS state-steps/s + H-apply MFMA util, FP64 vs mixed/batched at stated dipole err"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
-STAGES = ["theta_v", "z_lines", "planes", "mt_blocks", "v_projection", "subspace_step", "map_back"]
+STAGES = ["theta_v", "xz_planes", "y_lines", "mt_blocks", "v_projection", "subspace_step", "map_back"]
 
 
 def parse():
@@ -49,18 +49,19 @@ def parse():
     return p.parse_args()
 
 
-def stage_bytes(sysd, n, nbz, n1, n2, n3):
+def stage_bytes(sysd, n, nbx, nbz, n1, n2, n3):
     """Algorithmic bytes of one launch of each step stage (read + write of its own
-    inputs and outputs once)."""
+    inputs and outputs once).  The cached grid image of one column is the box
+    array c[kz][y][kx]: nbz * N2 * nbx complex values."""
     c16 = 16
-    slab = nbz * n1 * n2 * n * c16
+    slab = nbz * n2 * nbx * n * c16
     ngrid = n1 * n2 * n3
     ng = sysd.kpts[0].n_g
     k_ext = ng + sysd.n_a + sysd.n_lo
     return {
         "theta_v": 3 * ngrid * 8,
-        "z_lines": 2 * slab + ngrid * 8,
-        "planes": slab + ng * n * c16 + ng * 16,
+        "xz_planes": 2 * slab + ngrid * 8,
+        "y_lines": slab + ng * n * c16 + ng * 8,
         "v_projection": 2 * k_ext * n * c16 + n * n * c16,
     }
 
@@ -170,14 +171,14 @@ def main():
     stage_ms = lt.profile_steps(st, max(1, args.profile_steps))
     prof = {STAGES[i]: round(stage_ms[i] * 1e3, 3) for i in range(len(STAGES))}
     n1, n2, n3 = sysd.grid
-    bz = int(np.abs(sysd.kpts[0].g_int[:, 2]).max())
-    nbz = 2 * bz + 1
-    sb = stage_bytes(sysd, sysd.n_aux, nbz, n1, n2, n3)
+    nbx = 2 * int(np.abs(sysd.kpts[0].g_int[:, 0]).max()) + 1
+    nbz = 2 * int(np.abs(sysd.kpts[0].g_int[:, 2]).max()) + 1
+    sb = stage_bytes(sysd, sysd.n_aux, nbx, nbz, n1, n2, n3)
     hbm_stages = {k: v for k, v in prof.items() if k in sb}
     dom = max(hbm_stages, key=hbm_stages.get)
     dom_us = hbm_stages[dom]
     achieved = sb[dom] / (dom_us * 1e-6) / 1e9
-    kernel_file = "fft.hip" if dom in ("z_lines", "planes") else "api.hip"
+    kernel_file = "fft.hip" if dom in ("xz_planes", "y_lines") else "api.hip"
     roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(kernel_file),
                     bytes_per_launch=sb[dom], avg_launch_us=dom_us)

@@ -218,8 +218,8 @@ ltd_status ltd_propagate_step_adjoint(ltd_system *sys, const ltd_adjoint_args *a
  *
  * ltd_profile_steps: n_steps calls of ltd_propagate_step (advancing the step
  * counter); stage_ms[i] is the mean per step of stage i: 0 Theta V(t) on the
- * grid, 1 z-line transforms and product, 2 plane transforms and sphere read-out,
- * 3 muffin-tin block products, 4 projection of V~ (Phi~^H Y), 5 subspace
+ * grid, 1 x/z transforms and Theta V product per y plane, 2 y transforms and
+ * sphere read-out, 3 muffin-tin block products, 4 projection of V~ (Phi~^H Y), 5 subspace
  * exponential and observables, 6 map-back.
  *
  * ltd_profile_apply: one ltd_apply_HS at A = 0 (HC, SC: N_basis(k) x n, ld ldo);

@@ -86,7 +86,7 @@ struct ltd_system {
   // workspace
   char *ws = nullptr;
   size_t ws_need = 0, ws_bound = 0;
-  size_t o_tw1, o_tw2, o_tw3, o_thv, o_thv_step, o_status, o_part, o_partials;
+  size_t o_tw1, o_tw2, o_tw3, o_thv, o_thv_rb, o_thv_step, o_status, o_part, o_partials;
   size_t o_slab_in, o_slab_out, o_W, o_Y, o_heff, o_tvps, o_proj, o_tmp3, o_eigA, o_eigV, o_eigw;
   size_t o_stepslab, o_subdev, o_theta_sc, o_k6;
   K2Table k2_hs, k2_tvps, k2_step;
@@ -561,19 +561,19 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
   return c;
 }
 
-// Step stages (profiling tags): 0 Theta V(t), 1 z lines, 2 forward planes, 3 muffin-tin
+// Step stages (profiling tags): 0 Theta V(t), 1 x/z planes, 2 y lines, 3 muffin-tin
 // blocks (K2), 4 projection of V~ (GEMM), 5 subspace step and observables, 6 map-back.
 // Rebuild V~(t) of every k for the potential of this step (v_r_t, h_t).
 ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Prof *pf = nullptr) {
   const Grid g = grid_of(sys);
   const int n = sys->n_aux;
-  const double *thv = sys->at<double>(sys->o_thv);
+  const double *thv = sys->at<double>(sys->o_thv_rb);
   if (a->v_r_t) {
-    LTD_HIP(launch_thv(sys->at<double>(sys->o_thv_step), sys->theta, a->v_r_t, sys->ngrid, s));
+    LTD_HIP(fft_rb_thv(g, sys->theta, a->v_r_t, sys->at<double>(sys->o_thv_step), s));
     thv = sys->at<double>(sys->o_thv_step);
   }
   LTD_MARK(pf, 0);
-  const long long slab = (long long)g.nbz * sys->n1 * sys->n2 * n;
+  const long long slab = (long long)fft_rb_slab_values(g) * n;
   for (int k0 = 0; k0 < sys->n_k; k0 += FFT_MAXK) {
     const int nk = std::min(FFT_MAXK, sys->n_k - k0);
     FftKArgs ka{};
@@ -585,10 +585,11 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
       ka.out[i].o0 = sys->at<double2>(kh.o_yext);
       ka.out[i].ld0 = kh.k_ext;
     }
-    LTD_HIP(fft_lines(g, ka, nk, n, FFT_MODE_V, thv, s));
+    // x/z transforms and the Theta V product per y plane, then y transforms per kz plane
+    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0));
     LTD_MARK(pf, 1);
     for (int i = 0; i < nk; ++i) ka.slab_in[i] = ka.slab_out[i];
-    LTD_HIP(fft_forward_planes(g, ka, nk, n, FFT_MODE_V, 0.0, 0.0, s));
+    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1));
     LTD_MARK(pf, 2);
   }
   const void *hx = a->h_t ? a->h_t : nullptr;
@@ -811,6 +812,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_tw2 = ar.take(g.n2 * sizeof(double2));
   sys->o_tw3 = ar.take(g.n3 * sizeof(double2));
   sys->o_thv = ar.take(sys->ngrid * sizeof(double));
+  sys->o_thv_rb = ar.take(sys->ngrid * sizeof(double));
   sys->o_thv_step = ar.take(sys->ngrid * sizeof(double));
   sys->o_status = ar.take(64);
   sys->o_part = ar.take((size_t)4 * sys->n_k * sys->n_states * sizeof(double));
@@ -829,7 +831,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_eigV = ar.take((size_t)n2 * sizeof(double2));
   sys->o_eigw = ar.take((size_t)n * sizeof(double));
   sys->o_k6 = ar.take((size_t)sys->nb_max * n * sizeof(double2));
-  sys->o_stepslab = ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * g.nbz * g.n1 * g.n2 * n * sizeof(double2));
+  sys->o_stepslab = ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * fft_rb_slab_values(g) * n * sizeof(double2));
   sys->o_subdev = ar.take(sys->n_k * sizeof(SubDev));
   const size_t k2cap_apply = (size_t)4 * sys->n_atoms * 3 * sizeof(ZProb) + 1024;
   sys->o_k2_hs1 = ar.take(k2cap_apply);
@@ -858,7 +860,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     kh.o_work = sys->h_in_lds ? 0 : ar.take((size_t)sys->n_states * n2 * sizeof(double2));
     kh.o_phit = ar.take((size_t)kh.k_ext * n * sizeof(double2));
     kh.o_yext = ar.take((size_t)kh.k_ext * n * sizeof(double2));
-    kh.o_cache = ar.take((size_t)g.nbz * g.n1 * g.n2 * n * sizeof(double2));
+    kh.o_cache = ar.take(fft_rb_slab_values(g) * n * sizeof(double2));
   }
   sys->ws_need = ar.off;
   sys->sd.assign(sys->n_k, SubDev{});
@@ -900,6 +902,7 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
   std::vector<int> zero(16, 0);
   LTD_HIP(hipMemcpy(sys->ws + sys->o_status, zero.data(), 16 * sizeof(int), hipMemcpyHostToDevice));
   LTD_HIP(launch_thv(sys->at<double>(sys->o_thv), sys->theta, sys->v_r, sys->ngrid, s));
+  LTD_HIP(fft_rb_thv(grid_of(sys), sys->theta, sys->v_r, sys->at<double>(sys->o_thv_rb), s));
   // K2 tables of the apply chunk
   double2 *W = sys->at<double2>(sys->o_W), *Y = sys->at<double2>(sys->o_Y);
   const long long yst = (long long)sys->n_loc * sys->chunk;
@@ -992,14 +995,14 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
                                     pe + kh.n_g, kh.k_ext), s));
   if (sys->n_lo_tot > 0)
     LTD_HIP(launch_copy_rows(pe + kh.n_g + sys->n_a, kh.k_ext, pt + kh.n_g, sys->nb_max, sys->n_lo_tot, n, false, s));
-  // cached plane-wave part of Phi~ on the grid (first passes of the inverse transform)
+  // cached plane-wave part of Phi~, transformed along y only (box in x and z)
   {
     FftKArgs ka{};
     ka.sph[0] = sphere_of(sys, k);
     ka.in[0].c = pe;
     ka.in[0].ldc = kh.k_ext;
     ka.slab_out[0] = sys->at<double2>(kh.o_cache);
-    LTD_HIP(fft_inverse_planes(grid_of(sys), ka, 1, n, 1, s));
+    LTD_HIP(fft_rb_cache(grid_of(sys), ka, 1, n, s));
   }
   // outputs in the Phi basis
   if (h0_sub) LTD_HIP(launch_axpby(reinterpret_cast<double2 *>(h0_sub), subs, subs + n2, 1.0, 1.0, n2, s));

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <algorithm>
 
 namespace ltd {
 
@@ -139,6 +140,17 @@ hipError_t fft_forward_planes(const Grid &g, const FftKArgs &ka, int nk, int nco
 bool fft_plan_length(int L, FftPlan *p);
 size_t fft_plane_lds_bytes(const Grid &g);
 void fft_init_attrs();  // LDS limits of the FFT kernels (call outside graph capture)
+// Per-step rebuild path: the cached grid image is c[kz][y][kx] per column
+// (fft_rb_slab_values per column); fft_rb_cache builds it from sphere
+// coefficients (ka.in -> ka.slab_out); fft_rb_step part 0 maps slab_in -> slab_out
+// through the x/z transforms and the Theta V product, part 1 reads slab_in out to
+// the sphere (ka.out[k].o0).
+size_t fft_rb_slab_values(const Grid &g);
+hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hipStream_t s);
+hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const double *thv, hipStream_t s,
+                       int part);
+// Theta V of a step in the layout fft_rb_step part 0 reads (ngrid doubles).
+hipError_t fft_rb_thv(const Grid &g, const double *theta, const double *v, double *out, hipStream_t s);
 size_t fft_line_lds_bytes(const Grid &g);
 
 }  // namespace ltd

@@ -151,6 +151,47 @@ __device__ inline void dft_small<5, 1>(double2 *v) {
   dft5<1>(v);
 }
 
+constexpr double C9_1 = 0.76604444311897803520;   // cos(2 pi/9)
+constexpr double S9_1 = 0.64278760968653932632;   // sin(2 pi/9)
+constexpr double C9_2 = 0.17364817766693034885;   // cos(4 pi/9)
+constexpr double S9_2 = 0.98480775301220805937;   // sin(4 pi/9)
+constexpr double C9_4 = -0.93969262078590838405;  // cos(8 pi/9)
+constexpr double S9_4 = 0.34202014332566873304;   // sin(8 pi/9)
+
+// Length 9 as 3 x 3: input q = 3 q1 + q2, output p = p1 + 3 p2.
+template <int DIR>
+__device__ inline void dft9(double2 *v) {
+  double2 a[3][3];
+#pragma unroll
+  for (int q2 = 0; q2 < 3; ++q2) {
+    double2 t[3] = {v[q2], v[3 + q2], v[6 + q2]};
+    dft3<DIR>(t);
+    a[q2][0] = t[0];
+    a[q2][1] = t[1];
+    a[q2][2] = t[2];
+  }
+  a[1][1] = cmul(a[1][1], make_double2(C9_1, DIR * S9_1));
+  a[1][2] = cmul(a[1][2], make_double2(C9_2, DIR * S9_2));
+  a[2][1] = cmul(a[2][1], make_double2(C9_2, DIR * S9_2));
+  a[2][2] = cmul(a[2][2], make_double2(C9_4, DIR * S9_4));
+#pragma unroll
+  for (int p1 = 0; p1 < 3; ++p1) {
+    double2 t[3] = {a[0][p1], a[1][p1], a[2][p1]};
+    dft3<DIR>(t);
+    v[p1] = t[0];
+    v[p1 + 3] = t[1];
+    v[p1 + 6] = t[2];
+  }
+}
+
+// In-register DFT of the lengths the two-factor transforms use.
+template <int R, int DIR>
+__device__ __forceinline__ void dft_reg(double2 *v) {
+  if constexpr (R == 9) dft9<DIR>(v);
+  else if constexpr (R == 1) (void)v;
+  else dft_small<R, DIR>(v);
+}
+
 template <int R>
 struct Tpl {  // butterflies per lane and stage (register budget)
   static constexpr int value = (R == 8) ? 1 : (R == 5) ? 1 : (R == 4) ? 2 : (R == 3) ? 2 : 4;
@@ -550,6 +591,348 @@ __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKAr
 }
 
 // ---------------------------------------------------------------------------
+// Per-step rebuild path.  The cached grid image of the auxiliary basis is kept
+// transformed along y only: per column the box array c[kz][y][kx] (kz, kx in the
+// G box, y over the grid).  A step then runs
+//   k_rb_xz (per y plane): inverse x transforms of the nbz rows, inverse z
+//     transforms of the x columns, product with Theta V, forward z and x
+//     transforms, box read-out -> d[kz][y][kx];
+//   k_rb_y (per kz plane): forward y transforms of the box columns and the
+//     sphere read-out,
+// so a column moves 3 box arrays (nbz*N2*nbx values) through HBM per step.
+// ---------------------------------------------------------------------------
+
+// Setup: sphere coefficients of one kz plane -> inverse y transforms of the box
+// columns -> c[kz][y][kx].  grid (nbz, ncols, nk).
+template <int L2>
+__global__ __launch_bounds__(FFT_NT) void k_rb_cache(const Grid g, const FftKArgs ka, int ncols) {
+  extern __shared__ double2 sm[];
+  const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
+  const int n1 = g.n1, n2 = L2 > 0 ? L2 : g.n2;
+  const int bx = g.bx, nbx = g.nbx;
+  const int bp = n2 + 1;
+  double2 *bxc = sm;
+  double2 *tw2 = bxc + nbx * bp;
+  load_tw(tw2, g.tw2, n2);
+  const KSphere &sp = ka.sph[kk];
+  const InvIn in = ka.in[kk];
+  const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
+  for (int i = threadIdx.x; i < nbx * bp; i += blockDim.x) bxc[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+    const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+    const int y = xy / n1, x = xy - y * n1;
+    bxc[box_of(x, n1, bx) * bp + y] = in.c[(long long)gi + (long long)col * in.ldc];
+  }
+  __syncthreads();
+  fft_block<1, L2>(bxc, LinesUniform{0, bp}, nbx, 1, g.p2, tw2);
+  const long long csz = (long long)g.nbz * n2 * nbx;
+  double2 *out = ka.slab_out[kk] + (long long)col * csz + (long long)pz * n2 * nbx;
+  for (int i = threadIdx.x; i < n2 * nbx; i += blockDim.x) {
+    const int y = i / nbx, b = i - y * nbx;
+    out[i] = bxc[b * bp + y];
+  }
+}
+
+// Step: one y plane of one column.  grid (ncols, N2, nk): the blocks resident
+// together share the y plane of Theta V in L2.
+// LDS: X [nbz][n1+1] (kz rows, x), Z [n3][xc+1] (a chunk of xc x columns), twiddles.
+template <int L1, int L3>
+__global__ __launch_bounds__(FFT_NT) void k_rb_xz(const Grid g, const FftKArgs ka, int ncols, int xc,
+                                                  const double *__restrict__ thv) {
+  extern __shared__ double2 sm[];
+  const int col = blockIdx.x, y = blockIdx.y, kk = blockIdx.z;
+  const int n1 = L1 > 0 ? L1 : g.n1, n2 = g.n2, n3 = L3 > 0 ? L3 : g.n3;
+  const int bx = g.bx, nbx = g.nbx, bz = g.bz, nbz = g.nbz;
+  const int xp = n1 + 1, zp = xc + 1;
+  double2 *X = sm;
+  double2 *Z = X + nbz * xp;
+  double2 *tw1 = Z + n3 * zp;
+  double2 *tw3 = tw1 + n1;
+  load_tw(tw1, g.tw1, n1);
+  load_tw(tw3, g.tw3, n3);
+  const long long csz = (long long)nbz * n2 * nbx;
+  const double2 *in = ka.slab_in[kk] + (long long)col * csz + (long long)y * nbx;
+  double2 *out = ka.slab_out[kk] + (long long)col * csz + (long long)y * nbx;
+  const long long rs = (long long)n2 * nbx;  // kz stride of the box arrays
+  for (int i = threadIdx.x; i < nbz * n1; i += blockDim.x) {
+    const int p = i / n1, x = i - p * n1;
+    const int b = box_of(x, n1, bx);
+    X[p * xp + x] = (b >= 0) ? in[p * rs + b] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  fft_block<1, L1>(X, LinesUniform{0, xp}, nbz, 1, g.p1, tw1);  // inverse along x
+  const long long plane = (long long)n1 * n2;
+  for (int x0 = 0; x0 < n1; x0 += xc) {
+    const int nc = (n1 - x0) < xc ? (n1 - x0) : xc;
+    for (int i = threadIdx.x; i < n3 * xc; i += blockDim.x) {
+      const int z = i / xc, cc = i - z * xc;
+      const int kz = z <= bz ? z : z - n3;
+      Z[z * zp + cc] = (cc < nc && kz >= -bz && kz <= bz) ? X[(kz + bz) * xp + x0 + cc] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    fft_block<1, L3>(Z, LinesUniform{0, 1}, nc, zp, g.p3, tw3);  // inverse along z
+    for (int i = threadIdx.x; i < n3 * nc; i += blockDim.x) {
+      const int z = i / nc, cc = i - z * nc;
+      Z[z * zp + cc] = cscale(Z[z * zp + cc], thv[(long long)z * plane + (long long)y * n1 + x0 + cc]);
+    }
+    __syncthreads();
+    fft_block<-1, L3>(Z, LinesUniform{0, 1}, nc, zp, g.p3, tw3);  // forward along z
+    for (int i = threadIdx.x; i < nbz * nc; i += blockDim.x) {
+      const int p = i / nc, cc = i - p * nc;
+      const int kz = p - bz;
+      X[p * xp + x0 + cc] = Z[(kz < 0 ? kz + n3 : kz) * zp + cc];
+    }
+    __syncthreads();
+  }
+  fft_block<-1, L1>(X, LinesUniform{0, xp}, nbz, 1, g.p1, tw1);  // forward along x
+  for (int i = threadIdx.x; i < nbz * nbx; i += blockDim.x) {
+    const int p = i / nbx, b = i - p * nbx;
+    const int kx = b - bx;
+    out[p * rs + b] = X[p * xp + (kx < 0 ? kx + n1 : kx)];
+  }
+}
+
+// Step: forward y transforms of one kz plane of the box array and the sphere
+// read-out Y[g, col] = (1/N) value.  grid (nbz, ncols, nk).
+template <int L2>
+__global__ __launch_bounds__(FFT_NT) void k_rb_y(const Grid g, const FftKArgs ka, int ncols) {
+  extern __shared__ double2 sm[];
+  const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
+  const int n1 = g.n1, n2 = L2 > 0 ? L2 : g.n2;
+  const int bx = g.bx, nbx = g.nbx;
+  const int bp = n2 + 1;
+  double2 *bxc = sm;
+  double2 *tw2 = bxc + nbx * bp;
+  load_tw(tw2, g.tw2, n2);
+  const KSphere &sp = ka.sph[kk];
+  const FwdOut &fo = ka.out[kk];
+  const long long csz = (long long)g.nbz * n2 * nbx;
+  const double2 *src = ka.slab_in[kk] + (long long)col * csz + (long long)pz * n2 * nbx;
+  for (int i = threadIdx.x; i < n2 * nbx; i += blockDim.x) {
+    const int y = i / nbx, b = i - y * nbx;
+    bxc[b * bp + y] = src[i];
+  }
+  __syncthreads();
+  fft_block<-1, L2>(bxc, LinesUniform{0, bp}, nbx, 1, g.p2, tw2);
+  const double inv_n = 1.0 / ((double)n1 * n2 * g.n3);
+  const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
+  for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+    const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+    const int yy = xy / n1, x = xy - yy * n1;
+    fo.o0[gi + (long long)col * fo.ld0] = cscale(bxc[box_of(x, n1, bx) * bp + yy], inv_n);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rebuild path, two-factor register transforms.  A line of length N = F1 * F2
+// is transformed by F2 lanes holding F1 values each, one exchange through a
+// per-wave LDS scratch, then F1 lanes holding F2 values each (w_M = exp(DIR 2 pi i/M)):
+//   inverse, input n = F2 n1 + n2, output k = k1 + F1 k2:
+//     X[k1 + F1 k2] = sum_n2 w_F2^(n2 k2) w_N^(n2 k1) sum_n1 w_F1^(n1 k1) x[F2 n1 + n2]
+//   forward, input z = a + F1 b, output m = F2 c + d:
+//     Q[F2 c + d] = sum_a w_F1^(a c) w_N^(a d) sum_b w_F2^(b d) P[a + F1 b]
+// The inverse's output layout (lane k1 holds k1 + F1 k2) is the forward's input
+// layout, so a z column stays in registers from its inverse transform through
+// the Theta V product to its forward transform.  Lines live inside one wave
+// (G = max(F1, F2) lanes each); the exchange needs no block barrier.
+// ---------------------------------------------------------------------------
+template <int N, int F1, int F2>
+struct Two {
+  static_assert(F1 * F2 == N, "two-factor length");
+  static constexpr int G = F1 > F2 ? F1 : F2;             // lanes per line
+  static constexpr int LPW = 64 / G;                      // lines per wave
+  static constexpr int P = (G % 2) ? G : G + 1;           // odd pitch of the exchange rows
+  static constexpr int LS = G * P + ((9 - (G * P) % 8) % 8);  // line stride, = 1 mod 8
+  static constexpr int SCR = LPW * LS;                    // exchange values per wave
+};
+
+constexpr int rb_pitch(int n) { return n + ((9 - n % 8) % 8); }  // >= n, = 1 mod 8
+
+__device__ __forceinline__ void wave_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+// base twiddle w_N^role (inverse sign) of this lane
+__device__ __forceinline__ double2 role_twiddle(int role, int n) {
+  double sv, cv;
+  sincospi(2.0 * role / n, &sv, &cv);
+  return make_double2(cv, sv);
+}
+
+// v[j] *= w^j, j = 1 .. R-1 (powers by repeated products)
+template <int R>
+__device__ __forceinline__ void twiddle_powers(double2 *v, double2 w) {
+  double2 p = w;
+#pragma unroll
+  for (int j = 1; j < R; ++j) {
+    v[j] = cmul(v[j], p);
+    if (j + 1 < R) p = cmul(p, w);
+  }
+}
+
+// One y plane of one column.  grid (ncols, N2, nk).  LDS: R [nbz][RX] (inverse
+// x transforms of the kz box rows), then the per-wave exchange scratch.
+//   phase 1: box rows -> x transforms -> R
+//   phase 2: per x column: inverse z (box rows of R) -> * Theta V -> forward z
+//            -> box rows of R
+//   phase 3: R rows -> forward x transforms -> box columns -> slab_out
+// thp: Theta V of this step in the order [y][k2][x][k1], z = k1 + Z1 k2.
+template <int NX, int X1, int X2, int NZ, int Z1, int Z2>
+__global__ __launch_bounds__(FFT_NT) void k_rb_xz2(const Grid g, const FftKArgs ka, int ncols,
+                                                   const double *__restrict__ thp) {
+  using TX = Two<NX, X1, X2>;
+  using TZ = Two<NZ, Z1, Z2>;
+  constexpr int RX = rb_pitch(NX);
+  constexpr int SCR = TX::SCR > TZ::SCR ? TX::SCR : TZ::SCR;
+  extern __shared__ double2 sm[];
+  const int col = blockIdx.x, y = blockIdx.y, kk = blockIdx.z;
+  const int n2 = g.n2, bx = g.bx, nbx = g.nbx, bz = g.bz, nbz = g.nbz;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double2 *R = sm;
+  double2 *scr = sm + nbz * RX + wave * SCR;
+  const long long csz = (long long)nbz * n2 * nbx;
+  const long long rs = (long long)n2 * nbx;  // kz stride of the box arrays
+  const double2 *in = ka.slab_in[kk] + (long long)col * csz + (long long)y * nbx;
+  double2 *out = ka.slab_out[kk] + (long long)col * csz + (long long)y * nbx;
+  const double2 zero = make_double2(0.0, 0.0);
+  const int lx = lane / TX::G, rx = lane - lx * TX::G;
+  const int lz = lane / TZ::G, rz = lane - lz * TZ::G;
+  const double2 wx = role_twiddle(rx, NX), wz = role_twiddle(rz, NZ);
+
+  // phase 1: inverse x transforms of the box rows
+  for (int r0 = wave * TX::LPW; r0 < nbz; r0 += nw * TX::LPW) {
+    const int r = r0 + lx;
+    const bool on = lx < TX::LPW && r < nbz;
+    double2 *sl = scr + lx * TX::LS;
+    if (on && rx < X2) {
+      double2 v[X1];
+#pragma unroll
+      for (int n1 = 0; n1 < X1; ++n1) {
+        const int n = X2 * n1 + rx;
+        const int kx = n <= bx ? n : n - NX;
+        v[n1] = (n <= bx || n >= NX - bx) ? in[r * rs + kx + bx] : zero;
+      }
+      dft_reg<X1, 1>(v);
+      twiddle_powers<X1>(v, wx);
+#pragma unroll
+      for (int k1 = 0; k1 < X1; ++k1) sl[rx * TX::P + k1] = v[k1];
+    }
+    wave_fence();
+    if (on && rx < X1) {
+      double2 u[X2];
+#pragma unroll
+      for (int q = 0; q < X2; ++q) u[q] = sl[q * TX::P + rx];
+      dft_reg<X2, 1>(u);
+#pragma unroll
+      for (int k2 = 0; k2 < X2; ++k2) R[r * RX + rx + X1 * k2] = u[k2];
+    }
+    wave_fence();
+  }
+  __syncthreads();
+
+  // phase 2: z columns, inverse -> product -> forward, in place in R
+  const double2 wzc = cconj(wz);
+  for (int x0 = wave * TZ::LPW; x0 < NX; x0 += nw * TZ::LPW) {
+    const int x = x0 + lz;
+    const bool on = lz < TZ::LPW && x < NX;
+    double2 *sl = scr + lz * TZ::LS;
+    double t[Z2];
+    if (on && rz < Z1) {
+#pragma unroll
+      for (int k2 = 0; k2 < Z2; ++k2) t[k2] = thp[(((long long)y * Z2 + k2) * NX + x) * Z1 + rz];
+    }
+    if (on && rz < Z2) {
+      double2 v[Z1];
+#pragma unroll
+      for (int n1 = 0; n1 < Z1; ++n1) {
+        const int n = Z2 * n1 + rz;
+        const int row = n <= bz ? n + bz : n - NZ + bz;
+        v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : zero;
+      }
+      dft_reg<Z1, 1>(v);
+      twiddle_powers<Z1>(v, wz);
+#pragma unroll
+      for (int k1 = 0; k1 < Z1; ++k1) sl[rz * TZ::P + k1] = v[k1];
+    }
+    wave_fence();
+    if (on && rz < Z1) {
+      double2 u[Z2];
+#pragma unroll
+      for (int q = 0; q < Z2; ++q) u[q] = sl[q * TZ::P + rz];
+      dft_reg<Z2, 1>(u);
+#pragma unroll
+      for (int k2 = 0; k2 < Z2; ++k2) u[k2] = cscale(u[k2], t[k2]);
+      dft_reg<Z2, -1>(u);
+      twiddle_powers<Z2>(u, wzc);
+      wave_fence();
+#pragma unroll
+      for (int d = 0; d < Z2; ++d) sl[rz * TZ::P + d] = u[d];
+    }
+    wave_fence();
+    if (on && rz < Z2) {
+      double2 v[Z1];
+#pragma unroll
+      for (int a = 0; a < Z1; ++a) v[a] = sl[a * TZ::P + rz];
+      dft_reg<Z1, -1>(v);
+#pragma unroll
+      for (int c = 0; c < Z1; ++c) {
+        const int m = Z2 * c + rz;
+        if (m <= bz || m >= NZ - bz) R[(m <= bz ? m + bz : m - NZ + bz) * RX + x] = v[c];
+      }
+    }
+    wave_fence();
+  }
+  __syncthreads();
+
+  // phase 3: forward x transforms of the box rows, box columns out
+  const double2 wxc = cconj(wx);
+  for (int r0 = wave * TX::LPW; r0 < nbz; r0 += nw * TX::LPW) {
+    const int r = r0 + lx;
+    const bool on = lx < TX::LPW && r < nbz;
+    double2 *sl = scr + lx * TX::LS;
+    if (on && rx < X1) {
+      double2 u[X2];
+#pragma unroll
+      for (int b = 0; b < X2; ++b) u[b] = R[r * RX + rx + X1 * b];
+      dft_reg<X2, -1>(u);
+      twiddle_powers<X2>(u, wxc);
+#pragma unroll
+      for (int d = 0; d < X2; ++d) sl[rx * TX::P + d] = u[d];
+    }
+    wave_fence();
+    if (on && rx < X2) {
+      double2 v[X1];
+#pragma unroll
+      for (int a = 0; a < X1; ++a) v[a] = sl[a * TX::P + rx];
+      dft_reg<X1, -1>(v);
+#pragma unroll
+      for (int c = 0; c < X1; ++c) {
+        const int m = X2 * c + rx;
+        if (m <= bx || m >= NX - bx) out[r * rs + (m <= bx ? m : m - NX) + bx] = v[c];
+      }
+    }
+    wave_fence();
+  }
+}
+
+// Theta V in the order k_rb_xz2 reads it: out[((y Z2 + k2) N1 + x) Z1 + k1] for
+// the grid point (z = k1 + Z1 k2, y, x); z1 == 0: the grid order itself.
+__global__ void k_rb_thv(double *__restrict__ out, const double *__restrict__ th, const double *__restrict__ v,
+                         int n1, int n2, int n3, int z1, int z2) {
+  const long long ng = (long long)n1 * n2 * n3;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < ng; i += (long long)gridDim.x * blockDim.x) {
+    if (z1 == 0) {
+      out[i] = th[i] * v[i];
+      continue;
+    }
+    const int x = (int)(i % n1);
+    const long long t = i / n1;
+    const int y = (int)(t % n2), z = (int)(t / n2);
+    const int k1 = z % z1, k2 = z / z1;
+    out[(((long long)y * z2 + k2) * n1 + x) * z1 + k1] = th[i] * v[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launch configuration
 // ---------------------------------------------------------------------------
 // rows per chunk of the plane passes: every wavefront transforms its full share of lines
@@ -576,8 +959,38 @@ size_t line_lds(const Grid &g, int t, bool vmode) {
   return (size_t)((vmode ? 1 : 2) * g.n3 * (t + 1) + g.n3) * sizeof(double2);
 }
 
+size_t rb_cache_lds(const Grid &g) { return ((size_t)g.nbx * (g.n2 + 1) + g.n2) * sizeof(double2); }
+
+// x columns per z chunk of k_rb_xz: the fewest equal chunks that keep the block
+// within 80 KB of LDS (two blocks per CU), else within the 160 KB of one CU
+int rb_xc(const Grid &g) {
+  const size_t fixed = ((size_t)g.nbz * (g.n1 + 1) + g.n1 + g.n3) * sizeof(double2);
+  for (size_t budget : {(size_t)80 * 1024, (size_t)160 * 1024})
+    for (int nch = 1; nch <= g.n1; ++nch) {
+      const int xc = (g.n1 + nch - 1) / nch;
+      if (fixed + (size_t)g.n3 * (xc + 1) * sizeof(double2) <= budget) return xc;
+    }
+  return 1;
+}
+
+size_t rb_xz_lds(const Grid &g) {
+  return ((size_t)g.nbz * (g.n1 + 1) + (size_t)g.n3 * (rb_xc(g) + 1) + g.n1 + g.n3) * sizeof(double2);
+}
+
 template <class F>
 void each_plane_kernel(F &&f) {
+  f((const void *)k_rb_cache<0>);
+  f((const void *)k_rb_y<0>);
+  f((const void *)k_rb_xz<0, 0>);
+#define LTD_RB(a, c)                            \
+  f((const void *)k_rb_cache<a>);               \
+  f((const void *)k_rb_y<a>);                   \
+  f((const void *)k_rb_xz<a, c>);
+  LTD_RB(16, 16) LTD_RB(64, 64) LTD_RB(72, 72) LTD_RB(96, 160)
+#undef LTD_RB
+  f((const void *)k_rb_xz2<72, 8, 9, 72, 8, 9>);
+  f((const void *)k_rb_xz2<64, 8, 8, 64, 8, 8>);
+  f((const void *)k_rb_xz2<16, 4, 4, 16, 4, 4>);
   f((const void *)k_inv_plane<0, 0>);
   f((const void *)k_fwd_plane<0, 0>);
 #define LTD_PL(a, b)                            \
@@ -619,6 +1032,83 @@ bool fft_plan_length(int L, FftPlan *p) {
 }
 
 void fft_init_attrs() { set_attrs(); }
+
+size_t fft_rb_slab_values(const Grid &g) { return (size_t)g.nbz * g.n2 * g.nbx; }
+
+// Two-factor splits of the x and z lengths with a register path (0 if none).
+int rb_split(int n) { return n == 72 ? 8 : n == 64 ? 8 : n == 16 ? 4 : 0; }
+bool rb_fast(const Grid &g) { return rb_split(g.n1) > 0 && rb_split(g.n3) > 0; }
+
+size_t rb_xz2_lds(const Grid &g) {
+  const auto scr = [](int n) {
+    const int f1 = rb_split(n), f2 = n / f1, gl = f1 > f2 ? f1 : f2, p = (gl % 2) ? gl : gl + 1;
+    const int ls = gl * p + ((9 - (gl * p) % 8) % 8);
+    return (64 / gl) * ls;
+  };
+  const int rx = g.n1 + ((9 - g.n1 % 8) % 8);
+  return ((size_t)g.nbz * rx + (size_t)(FFT_NT / 64) * std::max(scr(g.n1), scr(g.n3))) * sizeof(double2);
+}
+
+hipError_t fft_rb_thv(const Grid &g, const double *th, const double *v, double *out, hipStream_t s) {
+  const int z1 = rb_fast(g) ? rb_split(g.n3) : 0, z2 = z1 ? g.n3 / z1 : 0;
+  const long long ng = (long long)g.n1 * g.n2 * g.n3;
+  const int blocks = (int)std::min<long long>((ng + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_rb_thv, dim3(blocks), dim3(256), 0, s, out, th, v, g.n1, g.n2, g.n3, z1, z2);
+  return hipGetLastError();
+}
+
+hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hipStream_t s) {
+  set_attrs();
+  const dim3 grid(g.nbz, ncols, nk), block(FFT_NT);
+  const size_t lds = rb_cache_lds(g);
+#define LTD_RC(a) hipLaunchKernelGGL((k_rb_cache<a>), grid, block, lds, s, g, ka, ncols)
+  if (g.n2 == 16) LTD_RC(16);
+  else if (g.n2 == 64) LTD_RC(64);
+  else if (g.n2 == 72) LTD_RC(72);
+  else if (g.n2 == 96) LTD_RC(96);
+  else LTD_RC(0);
+#undef LTD_RC
+  return hipGetLastError();
+}
+
+hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const double *thv, hipStream_t s,
+                       int part) {
+  set_attrs();
+  const dim3 block(FFT_NT);
+  if (part == 0 && rb_fast(g)) {
+    const dim3 grid(ncols, g.n2, nk);
+    const size_t lds = rb_xz2_lds(g);
+#define LTD_XZ2(a, a1, c, c1) \
+  hipLaunchKernelGGL((k_rb_xz2<a, a1, a / a1, c, c1, c / c1>), grid, block, lds, s, g, ka, ncols, thv)
+    if (g.n1 == 72 && g.n3 == 72) LTD_XZ2(72, 8, 72, 8);
+    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ2(64, 8, 64, 8);
+    else if (g.n1 == 16 && g.n3 == 16) LTD_XZ2(16, 4, 16, 4);
+    else return hipErrorInvalidValue;
+#undef LTD_XZ2
+  } else if (part == 0) {
+    const dim3 grid(ncols, g.n2, nk);
+    const size_t lds = rb_xz_lds(g);
+    const int xc = rb_xc(g);
+#define LTD_XZ(a, c) hipLaunchKernelGGL((k_rb_xz<a, c>), grid, block, lds, s, g, ka, ncols, xc, thv)
+    if (g.n1 == 16 && g.n3 == 16) LTD_XZ(16, 16);
+    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ(64, 64);
+    else if (g.n1 == 72 && g.n3 == 72) LTD_XZ(72, 72);
+    else if (g.n1 == 96 && g.n3 == 160) LTD_XZ(96, 160);
+    else LTD_XZ(0, 0);
+#undef LTD_XZ
+  } else {
+    const dim3 grid(g.nbz, ncols, nk);
+    const size_t lds = rb_cache_lds(g);
+#define LTD_RY(a) hipLaunchKernelGGL((k_rb_y<a>), grid, block, lds, s, g, ka, ncols)
+    if (g.n2 == 16) LTD_RY(16);
+    else if (g.n2 == 64) LTD_RY(64);
+    else if (g.n2 == 72) LTD_RY(72);
+    else if (g.n2 == 96) LTD_RY(96);
+    else LTD_RY(0);
+#undef LTD_RY
+  }
+  return hipGetLastError();
+}
 
 size_t fft_plane_lds_bytes(const Grid &g) { return plane_lds(g); }
 size_t fft_line_lds_bytes(const Grid &g) { return line_lds(g, line_tile(g, false), false); }
