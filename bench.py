@@ -6,7 +6,9 @@ waves, 2 atoms at lmax = 8 with 2 radial functions and 10 local orbitals each,
 FFT grid 72^3, N_aux = 64, N_states = 5, dt = 0.2 a.u.), seeded synthetic
 inputs.  One bench "step" is one time step of every state: the per-step
 rebuild of the potential part of the subspace Hamiltonian from the potential
-handed in for the step (interstitial FFT passes, muffin-tin block products,
+handed in for the step (a different V(r) and set of muffin-tin blocks every
+step, V_n = V + eps s_n W, h_n = h + eps s_n w, resident in HBM: Theta V_n on
+the rebuild grid, interstitial FFT passes, muffin-tin block products,
 projection), the FP64 Chebyshev exponential of the midpoint Hamiltonian and
 the current/energy/dipole observables, replayed from a hipGraph.
 
@@ -32,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "KS state-steps/s + H-apply MFMA util, FP64 vs mixed/batched at stated dipole err"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
-STAGES = ["theta_v", "xz_planes", "y_lines", "mt_blocks", "v_projection", "subspace_step", "map_back"]
+STAGES = ["potential", "xz_planes", "y_lines", "mt_blocks", "v_projection", "subspace_step", "map_back"]
 
 
 def parse():
@@ -41,6 +43,8 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--mode", choices=["rebuild", "affine"], default="rebuild")
+    p.add_argument("--potential", choices=["series", "static"], default="series",
+                   help="rebuild from a per-step potential series (default) or from one potential")
     p.add_argument("--profile-steps", type=int, default=20)
     p.add_argument("--cpu-steps", type=int, default=6)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -49,17 +53,19 @@ def parse():
     return p.parse_args()
 
 
-def stage_bytes(sysd, n, nbx, nbz, n1, n2, n3):
+def stage_bytes(sysd, n, nbx, nbz, rgrid):
     """Algorithmic bytes of one launch of each step stage (read + write of its own
     inputs and outputs once).  The cached grid image of one column is the box
-    array c[kz][y][kx]: nbz * N2 * nbx complex values."""
+    array c[kz][y][kx]: nbz * N2' * nbx complex values on the rebuild grid
+    (N1', N2', N3')."""
     c16 = 16
+    n1, n2, n3 = rgrid
     slab = nbz * n2 * nbx * n * c16
     ngrid = n1 * n2 * n3
     ng = sysd.kpts[0].n_g
     k_ext = ng + sysd.n_a + sysd.n_lo
     return {
-        "theta_v": 3 * ngrid * 8,
+        "potential": 2 * sysd.n_grid * 8 + ngrid * 8,
         "xz_planes": 2 * slab + ngrid * 8,
         "y_lines": slab + ng * n * c16 + ng * 8,
         "v_projection": 2 * k_ext * n * c16 + n * n * c16,
@@ -82,7 +88,12 @@ def traffic_from_profiles(kernel_file):
         return None
 
 
-def cpu_baseline(sysd, n_steps, mode):
+def potential_series(sysd, n_total):
+    """s_n, the per-step potential scale of the series V_n = V + eps s_n W."""
+    return np.sin(0.05 * np.arange(n_total))
+
+
+def cpu_baseline(sysd, n_steps, mode, series):
     """The FP64 oracle, timed on the host cores over a bounded number of steps."""
     import threadpoolctl
 
@@ -98,14 +109,26 @@ def cpu_baseline(sysd, n_steps, mode):
         phi, _ = ss.ground_state(sysd, 0)
         sub = ss.project(sysd, 0, phi)
         a_t, a_mid = pulse_samples(sysd, n_steps)
-        vfn = (lambda n: ss.rebuild_v_sub(sysd, 0, phi)) if mode == "rebuild" else None
+        vfn = None
+        if mode == "rebuild" and series:
+            from synth import td_potential
+
+            eps, wfield, wblk = td_potential(sysd)
+            s_n = potential_series(sysd, n_steps)
+
+            def vfn(n):
+                return ss.rebuild_v_sub(sysd, 0, phi, vr=sysd.vr + eps * s_n[n] * wfield,
+                                        h=[h + eps * s_n[n] * w for h, w in zip(sysd.h, wblk)])
+        elif mode == "rebuild":
+            def vfn(n):
+                return ss.rebuild_v_sub(sysd, 0, phi)
         t0 = time.perf_counter()
         pr.propagate(sub, pr.initial_theta(sysd.n_aux, sysd.n_states), a_t, a_mid, sysd.dt, sysd.occ,
                      sysd.omega, sysd.c_light, v_sub_fn=vfn, n_steps=n_steps)
         t = time.perf_counter() - t0
     return dict(value=sysd.n_states * n_steps / t, unit="state-steps/s", cores=cores, kind="oracle",
-                sample=f"first {n_steps} time steps ({mode}) of the same workload, setup excluded; "
-                       f"{t:.2f} s")
+                sample=f"first {n_steps} time steps ({mode}, {'per-step potential' if series else 'one potential'}) "
+                       f"of the same workload, setup excluded; {t:.2f} s")
 
 
 def main():
@@ -148,7 +171,20 @@ def main():
     for j in range(sysd.n_states):
         th0[0, j, j] = 1.0
     theta = torch.from_numpy(th0).to(dev)
-    st = lt.make_step_args(mode, sysd.dt, at, am, theta, total)
+    pot = {}
+    series = args.mode == "rebuild" and args.potential == "series"
+    if series:
+        from synth import td_potential
+
+        eps, wfield, wblk = td_potential(sysd)
+        sd = torch.from_numpy(potential_series(sysd, total)).to(dev)[:, None]
+        v0 = torch.from_numpy(np.ascontiguousarray(sysd.vr.ravel())).to(dev)
+        w0 = torch.from_numpy(np.ascontiguousarray(wfield.ravel())).to(dev)
+        wb = torch.from_numpy(np.concatenate([np.ascontiguousarray(x.T).ravel() for x in wblk])).to(dev)
+        vs = (v0[None, :] + eps * sd * w0[None, :]).contiguous()
+        hs = (lt.h[None, :] + eps * sd * wb[None, :]).contiguous()
+        pot = dict(v_r_t=vs, h_t=hs, v_stride=vs.shape[1], h_stride=hs.shape[1])
+    st = lt.make_step_args(mode, sysd.dt, at, am, theta, total, **pot)
     s = torch.cuda.current_stream(dev)
     if args.warmup:
         lt.run(st, args.warmup)
@@ -170,15 +206,15 @@ def main():
     # stage profile (HIP events between stages, eager)
     stage_ms = lt.profile_steps(st, max(1, args.profile_steps))
     prof = {STAGES[i]: round(stage_ms[i] * 1e3, 3) for i in range(len(STAGES))}
-    n1, n2, n3 = sysd.grid
+    rgrid = lt.rebuild_grid()
     nbx = 2 * int(np.abs(sysd.kpts[0].g_int[:, 0]).max()) + 1
     nbz = 2 * int(np.abs(sysd.kpts[0].g_int[:, 2]).max()) + 1
-    sb = stage_bytes(sysd, sysd.n_aux, nbx, nbz, n1, n2, n3)
+    sb = stage_bytes(sysd, sysd.n_aux, nbx, nbz, rgrid)
     hbm_stages = {k: v for k, v in prof.items() if k in sb}
     dom = max(hbm_stages, key=hbm_stages.get)
     dom_us = hbm_stages[dom]
     achieved = sb[dom] / (dom_us * 1e-6) / 1e9
-    kernel_file = "fft.hip" if dom in ("xz_planes", "y_lines") else "api.hip"
+    kernel_file = "fft.hip" if dom in ("potential", "xz_planes", "y_lines") else "api.hip"
     roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(kernel_file),
                     bytes_per_launch=sb[dom], avg_launch_us=dom_us)
@@ -211,9 +247,10 @@ def main():
         "config": {
             "workload": "molecule in large cell: 1 k-point, N_G=12000, 2 atoms lmax 8 (162 MT channels + "
                         "10 LO each), FFT grid 72^3, N_aux=64, N_states=5, dt=0.2, "
-                        f"{args.mode} mode, FP64",
+                        f"{args.mode} mode" + (", potential handed in per step" if series else "") + ", FP64",
             "n_g": ng, "n_aux": n, "n_states": sysd.n_states, "grid": list(sysd.grid),
-            "mode": args.mode, "precision": "fp64",
+            "rebuild_grid": list(rgrid), "mode": args.mode, "potential": args.potential if
+            args.mode == "rebuild" else None, "precision": "fp64",
         },
         "wall_s": round(wall, 4),
         "stage_us": prof,
@@ -223,7 +260,7 @@ def main():
         "dmu_final": float(st["dmu"][args.warmup + args.steps].item()),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sysd, args.cpu_steps, args.mode)
+        out["cpu_baseline"] = cpu_baseline(sysd, args.cpu_steps, args.mode, series)
     print(json.dumps(out), flush=True)
     return 0
 

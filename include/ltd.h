@@ -148,6 +148,13 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
  * form the auxiliary basis (Sec. 2.2, Eq. (11)).  Synchronises `stream`. */
 ltd_status ltd_ritz_basis(ltd_system *sys, int k, void *x, int ldx, double *eps, void *stream);
 
+/* Host read-out of the FFT lengths of the per-step rebuild (lengths[3], host):
+ * the smallest supported lengths >= 4 b_i + 1 (b_i the largest |g_i| of the
+ * G+k sets) and <= the grid's, so that every difference of two G-box
+ * frequencies stays distinct and the convolution with Theta V(t) (Sec. 2.3,
+ * Eq. (17)) is exact on them; the grid's own lengths when none is smaller. */
+ltd_status ltd_rebuild_grid(const ltd_system *sys, int *lengths);
+
 /* Host read-out of the bound subspace of k: extreme eigenvalues of (H0_sub,
  * S_sub) and the critical time step f/(eps_max - eps_min) with f = 0.2
  * (Sec. 3.1, Eq. (20)).  Any output may be NULL. */
@@ -169,6 +176,10 @@ typedef struct {
   double *j_out;          /* [n_steps+1] k-weighted current along z at t_n */
   double *e_out;          /* [n_steps+1] energy at t_n */
   double *dmu_out;        /* [n_steps+1] dipole change along z at t_n */
+  long long v_stride;     /* REBUILD: doubles between the potentials of consecutive steps in
+                             v_r_t: step n reads v_r_t + n v_stride (0: one potential) */
+  long long h_stride;     /* REBUILD: complex elements between the blocks of consecutive steps
+                             in h_t: step n reads h_t + n h_stride (0: one set of blocks) */
 } ltd_step_args;
 
 /* One time step n -> n+1 for every k-point (Sec. 2.2, Eqs. (12)-(13); Sec. 2.3
@@ -185,8 +196,9 @@ typedef struct {
 ltd_status ltd_propagate_step(ltd_system *sys, const ltd_step_args *args, void *stream);
 
 /* n_steps calls of ltd_propagate_step, recorded once into a hipGraph and
- * replayed (the device step counter selects the pulse samples).  REBUILD
- * re-reads v_r_t / h_t every step. */
+ * replayed (the device step counter selects the pulse samples and, with
+ * nonzero strides, the potential of the step).  REBUILD re-reads v_r_t / h_t
+ * every step. */
 ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *args, int n_steps, void *stream);
 
 typedef struct {

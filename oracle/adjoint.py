@@ -48,8 +48,12 @@ def propagator_derivative(h_sub, s_sub, dh, dt):
     return linv.conj().T @ w @ (f * d) @ w.conj().T @ l.conj().T
 
 
-def gradients(sub: dict, theta0, a_t, a_mid, dt, occ, omega, c_light) -> dict:
+def gradients(sub: dict, theta0, a_t, a_mid, dt, occ, omega, c_light, v_sub_fn=None) -> dict:
     """dL/dA(t_n + dt/2) for every step and dL/dA(t_n) for every time point.
+
+    v_sub_fn(n): V_sub of step n -> n+1 when the potential part is rebuilt every
+    step (Sec. 2.3, text after Eq. (16)); it enters the step propagators only,
+    not dH/dA.
 
     Adjoint recursion (real loss, gradient convention dL = Re <mu, d theta>):
     mu_N = dt w_N g_N, mu_n = U_n^H mu_{n+1} + dt w_n g_n with the current's
@@ -58,7 +62,7 @@ def gradients(sub: dict, theta0, a_t, a_mid, dt, occ, omega, c_light) -> dict:
     dJ_n/dA_n = -(f/(Omega c)) sum_j theta_j^H S_sub theta_j, and the J_0 that
     is subtracted in J_ind contributes -T dJ_0/dA_0 (T = N dt)."""
     n_steps = len(a_mid)
-    fw = propagate(sub, theta0, a_t, a_mid, dt, occ, omega, c_light, keep_theta=True)
+    fw = propagate(sub, theta0, a_t, a_mid, dt, occ, omega, c_light, v_sub_fn=v_sub_fn, keep_theta=True)
     th = fw["thetas"]
     w = trapezoid_weights(n_steps)
     p, s = sub["P"], sub["S"]
@@ -73,7 +77,7 @@ def gradients(sub: dict, theta0, a_t, a_mid, dt, occ, omega, c_light) -> dict:
     d_at = np.zeros(n_steps + 1)
     mu = dt * w[n_steps] * g_j(n_steps)
     for n in range(n_steps - 1, -1, -1):
-        hm = h_sub_at(sub, a_mid[n], c_light)
+        hm = h_sub_at(sub, a_mid[n], c_light, None if v_sub_fn is None else v_sub_fn(n))
         dh = p / c_light + (a_mid[n] / c_light ** 2) * s
         du = propagator_derivative(hm, s, dh, dt)
         d_mid[n] = float(np.real(np.sum(mu.conj() * (du @ th[n]))))

@@ -31,6 +31,7 @@ EXPORTED = [
     "ltd_apply_HS", "ltd_project_subspace", "ltd_ritz_basis", "ltd_subspace_info",
     "ltd_propagate_step", "ltd_propagate", "ltd_propagate_step_adjoint", "ltd_knot_samples",
     "ltd_knot_gradient", "ltd_chebyshev_coefficients", "ltd_profile_steps", "ltd_profile_apply",
+    "ltd_rebuild_grid",
 ]
 LTD_PROFILE_STAGES = 8
 
@@ -75,6 +76,8 @@ class StepArgs(C.Structure):
         ("j_out", C.c_void_p),
         ("e_out", C.c_void_p),
         ("dmu_out", C.c_void_p),
+        ("v_stride", C.c_longlong),
+        ("h_stride", C.c_longlong),
     ]
 
 
@@ -114,6 +117,7 @@ def load(path: str = LIB_PATH):
     lib.ltd_project_subspace.argtypes = [vp, ip, vp, ip, ip, vp, vp, vp, ip, ip, vp, vp]
     lib.ltd_ritz_basis.argtypes = [vp, ip, vp, ip, vp, vp]
     lib.ltd_subspace_info.argtypes = [vp, ip, dp, dp, dp]
+    lib.ltd_rebuild_grid.argtypes = [vp, C.POINTER(ip)]
     lib.ltd_propagate_step.argtypes = [vp, C.POINTER(StepArgs), vp]
     lib.ltd_propagate.argtypes = [vp, C.POINTER(StepArgs), ip, vp]
     lib.ltd_propagate_step_adjoint.argtypes = [vp, C.POINTER(AdjointArgs), vp]

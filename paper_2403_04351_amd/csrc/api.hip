@@ -78,8 +78,12 @@ struct ltd_system {
   std::vector<double> kw;
   int n_aux = 0, n_states = 0, max_cols = 0, precision = 0;
   int nb_max = 0;
-  // grid plan
+  // grid plan; rgrid: the grid of the per-step rebuild (same box, lengths
+  // >= 4 b + 1), with W synthesised from Theta V when it is smaller
   Grid grid{};
+  Grid rgrid{};
+  bool rb_synth = false;
+  size_t o_rtw1 = 0, o_rtw2 = 0, o_rtw3 = 0, o_M1 = 0, o_M2 = 0, o_M3 = 0, o_syn1 = 0, o_syn2 = 0;
   int chunk = 0;        // columns per apply pass
   bool h_in_lds = false;
   bool p_in_lds = false;
@@ -88,7 +92,7 @@ struct ltd_system {
   size_t ws_need = 0, ws_bound = 0;
   size_t o_tw1, o_tw2, o_tw3, o_thv, o_thv_rb, o_thv_step, o_status, o_part, o_partials;
   size_t o_slab_in, o_slab_out, o_W, o_Y, o_heff, o_tvps, o_proj, o_tmp3, o_eigA, o_eigV, o_eigw;
-  size_t o_stepslab, o_subdev, o_theta_sc, o_k6;
+  size_t o_stepslab, o_subdev, o_theta_sc, o_k6, o_hstep;
   K2Table k2_hs, k2_tvps, k2_step;
   size_t o_k2_hs1, o_k2_hs2, o_k2_tv1, o_k2_tv2, o_k2_st1, o_k2_st2;
   std::vector<ZProb> vstep_tab;
@@ -341,6 +345,38 @@ Grid grid_of(const ltd_system *sys) {
   return g;
 }
 
+// grid of the per-step rebuild
+Grid rgrid_of(const ltd_system *sys) {
+  if (!sys->rb_synth) return grid_of(sys);
+  Grid g = sys->rgrid;
+  g.tw1 = sys->at<double2>(sys->o_rtw1);
+  g.tw2 = sys->at<double2>(sys->o_rtw2);
+  g.tw3 = sys->at<double2>(sys->o_rtw3);
+  g.theta = sys->theta;
+  return g;
+}
+
+// Theta v in the layout of the rebuild step (W on the rebuild grid when it is
+// smaller); v read at v + (*step) * stride when step is not NULL
+ltd_status rebuild_potential(ltd_system *sys, const double *v, const int *step, long long stride, double *out,
+                             hipStream_t s) {
+  if (sys->rb_synth) {
+    LTD_HIP(fft_rb_synth(rgrid_of(sys), sys->n1, sys->n2, sys->n3, sys->theta, v, step, stride,
+                         sys->at<double>(sys->o_M1), sys->at<double>(sys->o_M2), sys->at<double>(sys->o_M3),
+                         sys->at<double>(sys->o_syn1), sys->at<double>(sys->o_syn2), out, s));
+  } else {
+    LTD_HIP(fft_rb_thv(grid_of(sys), sys->theta, v, step, stride, out, s));
+  }
+  return LTD_OK;
+}
+
+// the blocks the muffin-tin step table reads: a per-step series goes through
+// a fixed copy buffer, one set of blocks is read in place (NULL: the reference)
+const void *k2_source(const ltd_system *sys, const ltd_step_args *a) {
+  if (!a->h_t) return nullptr;
+  return a->h_stride ? static_cast<const void *>(sys->at<double2>(sys->o_hstep)) : a->h_t;
+}
+
 // ---------------------------------------------------------------------------
 // Operator apply on a column chunk of one k-point.
 //   mode FFT_MODE_HS:   out[0] = H(A) C, out[1] = S C
@@ -564,14 +600,27 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
 // Step stages (profiling tags): 0 Theta V(t), 1 x/z planes, 2 y lines, 3 muffin-tin
 // blocks (K2), 4 projection of V~ (GEMM), 5 subspace step and observables, 6 map-back.
 // Rebuild V~(t) of every k for the potential of this step (v_r_t, h_t).
-ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Prof *pf = nullptr) {
-  const Grid g = grid_of(sys);
+// host_step >= 0: the step index is known on the host (adjoint); otherwise the
+// series are indexed by the device step counter.
+ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Prof *pf = nullptr,
+                     int host_step = -1) {
+  const Grid g = rgrid_of(sys);
   const int n = sys->n_aux;
   const double *thv = sys->at<double>(sys->o_thv_rb);
   if (a->v_r_t) {
-    LTD_HIP(fft_rb_thv(g, sys->theta, a->v_r_t, sys->at<double>(sys->o_thv_step), s));
+    const double *v = a->v_r_t;
+    const int *dstep = nullptr;
+    if (a->v_stride) {
+      if (host_step >= 0) v += (long long)host_step * a->v_stride;
+      else dstep = a->step;
+    }
+    LTD_TRY(rebuild_potential(sys, v, dstep, a->v_stride, sys->at<double>(sys->o_thv_step), s));
     thv = sys->at<double>(sys->o_thv_step);
   }
+  if (a->h_t && a->h_stride)
+    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), reinterpret_cast<const double2 *>(a->h_t),
+                             sys->blk_elems, host_step >= 0 ? nullptr : a->step, a->h_stride,
+                             host_step >= 0 ? (long long)host_step * a->h_stride : 0, s));
   LTD_MARK(pf, 0);
   const long long slab = (long long)fft_rb_slab_values(g) * n;
   for (int k0 = 0; k0 < sys->n_k; k0 += FFT_MAXK) {
@@ -592,7 +641,7 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
     LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1));
     LTD_MARK(pf, 2);
   }
-  const void *hx = a->h_t ? a->h_t : nullptr;
+  const void *hx = k2_source(sys, a);
   if (hx != sys->k2_step_h) {
     sys->k2_step_h = hx;
     LTD_TRY(build_step_tables(sys));
@@ -629,6 +678,9 @@ ltd_status check_step_args(ltd_system *sys, const ltd_step_args *a) {
   if (!a->a_t || !a->a_mid || !a->step || !a->theta || !a->j_out || !a->e_out || !a->dmu_out) return LTD_EINVAL;
   if (!aligned16(a->theta) || (a->c_out && !aligned16(a->c_out))) return LTD_EALIGN;
   if (a->h_t && !aligned16(a->h_t)) return LTD_EALIGN;
+  if (a->v_stride < 0 || a->h_stride < 0) return LTD_EINVAL;
+  if (a->v_stride && a->v_stride < sys->ngrid) return LTD_ESHAPE;
+  if (a->h_stride && a->h_stride < sys->blk_elems) return LTD_ESHAPE;
   return LTD_OK;
 }
 
@@ -754,6 +806,22 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   g.nbx = 2 * bx + 1;
   g.nby = 2 * by + 1;
   g.nbz = 2 * bz + 1;
+  g.d1 = g.n1;
+  g.d2 = g.n2;
+  {
+    Grid r = g;
+    r.n1 = fft_rb_length(g.n1, bx);
+    r.n2 = fft_rb_length(g.n2, by);
+    r.n3 = fft_rb_length(g.n3, bz);
+    const bool smaller = r.n1 != g.n1 || r.n2 != g.n2 || r.n3 != g.n3;
+    if (smaller && fft_rb_fast(r) && fft_plan_length(r.n1, &r.p1) && fft_plan_length(r.n2, &r.p2) &&
+        fft_plan_length(r.n3, &r.p3)) {
+      sys->rgrid = r;
+      sys->rb_synth = true;
+    } else {
+      sys->rgrid = g;
+    }
+  }
   if (fft_plane_lds_bytes(g) > 160 * 1024 || fft_line_lds_bytes(g) > 160 * 1024) {
     delete sys;
     return LTD_EUNSUPPORTED;
@@ -831,8 +899,21 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_eigV = ar.take((size_t)n2 * sizeof(double2));
   sys->o_eigw = ar.take((size_t)n * sizeof(double));
   sys->o_k6 = ar.take((size_t)sys->nb_max * n * sizeof(double2));
-  sys->o_stepslab = ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * fft_rb_slab_values(g) * n * sizeof(double2));
+  sys->o_stepslab =
+      ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * fft_rb_slab_values(sys->rgrid) * n * sizeof(double2));
+  if (sys->rb_synth) {
+    const Grid &r = sys->rgrid;
+    sys->o_rtw1 = ar.take(r.n1 * sizeof(double2));
+    sys->o_rtw2 = ar.take(r.n2 * sizeof(double2));
+    sys->o_rtw3 = ar.take(r.n3 * sizeof(double2));
+    sys->o_M1 = ar.take((size_t)r.n1 * g.n1 * sizeof(double));
+    sys->o_M2 = ar.take((size_t)r.n2 * g.n2 * sizeof(double));
+    sys->o_M3 = ar.take((size_t)r.n3 * g.n3 * sizeof(double));
+    sys->o_syn1 = ar.take((size_t)g.n3 * g.n2 * r.n1 * sizeof(double));
+    sys->o_syn2 = ar.take((size_t)g.n3 * r.n2 * r.n1 * sizeof(double));
+  }
   sys->o_subdev = ar.take(sys->n_k * sizeof(SubDev));
+  sys->o_hstep = ar.take((size_t)std::max<long long>(1, sys->blk_elems) * sizeof(double2));
   const size_t k2cap_apply = (size_t)4 * sys->n_atoms * 3 * sizeof(ZProb) + 1024;
   sys->o_k2_hs1 = ar.take(k2cap_apply);
   sys->o_k2_hs2 = ar.take(k2cap_apply);
@@ -860,7 +941,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     kh.o_work = sys->h_in_lds ? 0 : ar.take((size_t)sys->n_states * n2 * sizeof(double2));
     kh.o_phit = ar.take((size_t)kh.k_ext * n * sizeof(double2));
     kh.o_yext = ar.take((size_t)kh.k_ext * n * sizeof(double2));
-    kh.o_cache = ar.take(fft_rb_slab_values(g) * n * sizeof(double2));
+    kh.o_cache = ar.take(fft_rb_slab_values(sys->rgrid) * n * sizeof(double2));
   }
   sys->ws_need = ar.off;
   sys->sd.assign(sys->n_k, SubDev{});
@@ -891,6 +972,28 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
   LTD_TRY(tw(sys->n1, sys->o_tw1));
   LTD_TRY(tw(sys->n2, sys->o_tw2));
   LTD_TRY(tw(sys->n3, sys->o_tw3));
+  if (sys->rb_synth) {
+    const Grid &r = sys->rgrid;
+    LTD_TRY(tw(r.n1, sys->o_rtw1));
+    LTD_TRY(tw(r.n2, sys->o_rtw2));
+    LTD_TRY(tw(r.n3, sys->o_rtw3));
+    // M[j'][j] = (1/N) sum_{|q| <= 2b} exp(2 pi i q j'/N') exp(-2 pi i q j/N), real
+    auto mat = [&](int np, int nn, int b, size_t off) -> ltd_status {
+      std::vector<double> m((size_t)np * nn);
+      for (int jp = 0; jp < np; ++jp)
+        for (int j = 0; j < nn; ++j) {
+          double acc = 1.0;
+          for (int q = 1; q <= 2 * b; ++q)
+            acc += 2.0 * std::cos(2.0 * M_PI * q * ((double)jp / np - (double)j / nn));
+          m[(size_t)jp * nn + j] = acc / nn;
+        }
+      LTD_HIP(hipMemcpy(sys->ws + off, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice));
+      return LTD_OK;
+    };
+    LTD_TRY(mat(r.n1, sys->n1, r.bx, sys->o_M1));
+    LTD_TRY(mat(r.n2, sys->n2, r.by, sys->o_M2));
+    LTD_TRY(mat(r.n3, sys->n3, r.bz, sys->o_M3));
+  }
   for (int k = 0; k < sys->n_k; ++k) {
     KHost &kh = sys->kh[k];
     LTD_HIP(hipMemcpy(sys->ws + kh.o_gk, &sys->gk[3 * kh.g_off], 3 * kh.n_g * sizeof(double), hipMemcpyHostToDevice));
@@ -902,7 +1005,7 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
   std::vector<int> zero(16, 0);
   LTD_HIP(hipMemcpy(sys->ws + sys->o_status, zero.data(), 16 * sizeof(int), hipMemcpyHostToDevice));
   LTD_HIP(launch_thv(sys->at<double>(sys->o_thv), sys->theta, sys->v_r, sys->ngrid, s));
-  LTD_HIP(fft_rb_thv(grid_of(sys), sys->theta, sys->v_r, sys->at<double>(sys->o_thv_rb), s));
+  LTD_TRY(rebuild_potential(sys, sys->v_r, nullptr, 0, sys->at<double>(sys->o_thv_rb), s));
   // K2 tables of the apply chunk
   double2 *W = sys->at<double2>(sys->o_W), *Y = sys->at<double2>(sys->o_Y);
   const long long yst = (long long)sys->n_loc * sys->chunk;
@@ -1002,7 +1105,7 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
     ka.in[0].c = pe;
     ka.in[0].ldc = kh.k_ext;
     ka.slab_out[0] = sys->at<double2>(kh.o_cache);
-    LTD_HIP(fft_rb_cache(grid_of(sys), ka, 1, n, s));
+    LTD_HIP(fft_rb_cache(rgrid_of(sys), ka, 1, n, s));
   }
   // outputs in the Phi basis
   if (h0_sub) LTD_HIP(launch_axpby(reinterpret_cast<double2 *>(h0_sub), subs, subs + n2, 1.0, 1.0, n2, s));
@@ -1091,6 +1194,14 @@ ltd_status ltd_ritz_basis(ltd_system *sys, int k, void *x, int ldx, double *eps,
   return LTD_OK;
 }
 
+ltd_status ltd_rebuild_grid(const ltd_system *sys, int *lengths) {
+  if (!sys || !lengths) return LTD_EINVAL;
+  lengths[0] = sys->rgrid.n1;
+  lengths[1] = sys->rgrid.n2;
+  lengths[2] = sys->rgrid.n3;
+  return LTD_OK;
+}
+
 ltd_status ltd_subspace_info(ltd_system *sys, int k, double *eps_min, double *eps_max, double *dt_cr) {
   if (!sys) return LTD_EINVAL;
   if (k < 0 || k >= sys->n_k) return LTD_ESHAPE;
@@ -1115,8 +1226,8 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
   LTD_TRY(prepare_dt(sys, a->dt));
   hipStream_t s = S(stream);
   // tables that a rebuild step would refresh on the host must be current before capture
-  if (a->mode == LTD_STEP_REBUILD && (a->h_t ? a->h_t : nullptr) != sys->k2_step_h) {
-    sys->k2_step_h = a->h_t;
+  if (a->mode == LTD_STEP_REBUILD && k2_source(sys, a) != sys->k2_step_h) {
+    sys->k2_step_h = k2_source(sys, a);
     LTD_TRY(build_step_tables(sys));
   }
   const bool same = sys->gvalid && std::memcmp(&sys->gargs, a, sizeof(ltd_step_args)) == 0;
@@ -1158,7 +1269,7 @@ ltd_status ltd_propagate_step_adjoint(ltd_system *sys, const ltd_adjoint_args *a
   if (!aligned16(aa->mu_out) || (aa->mu_next && !aligned16(aa->mu_next))) return LTD_EALIGN;
   LTD_TRY(prepare_dt(sys, a->dt));
   hipStream_t s = S(stream);
-  if (a->mode == LTD_STEP_REBUILD && !aa->terminal) LTD_TRY(rebuild_v(sys, a, s));
+  if (a->mode == LTD_STEP_REBUILD && !aa->terminal) LTD_TRY(rebuild_v(sys, a, s, nullptr, aa->n));
   AdjCtx ac{};
   ac.n = aa->n;
   ac.terminal = aa->terminal;

@@ -91,6 +91,7 @@ struct Grid {
   FftPlan p1, p2, p3;
   const double2 *tw1, *tw2, *tw3;  // device twiddles exp(-2 pi i m / L)
   const double *theta;             // [N]
+  int d1, d2;                      // grid of the sphere tables' positions y * d1 + x
 };
 
 // Per-k sphere tables (device).
@@ -150,7 +151,22 @@ hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hi
 hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const double *thv, hipStream_t s,
                        int part);
 // Theta V of a step in the layout fft_rb_step part 0 reads (ngrid doubles).
-hipError_t fft_rb_thv(const Grid &g, const double *theta, const double *v, double *out, hipStream_t s);
+// v is read at v + (*step) * stride when step is not NULL.
+hipError_t fft_rb_thv(const Grid &g, const double *theta, const double *v, const int *step, long long stride,
+                      double *out, hipStream_t s);
+// Rebuild length of one axis of length n with box half-width b: the smallest
+// length with a register path that is >= 4 b + 1 (every difference of two box
+// frequencies is then distinct modulo it) and <= n; n itself otherwise.
+int fft_rb_length(int n, int b);
+// True when fft_rb_step has a register path for this grid (x and z lengths).
+bool fft_rb_fast(const Grid &g);
+// W on the rebuild grid gr from Theta V on the original grid (n1, n2, n3):
+// W = IDFT_gr(keep |q_d| <= 2 b_d (DFT(Theta V))), one real matrix M_d
+// (gr.n_d x n_d) per axis, passes z, y, x; written in the layout fft_rb_step
+// part 0 reads.  t1: n3 * n2 * gr.n1 doubles, t2: n3 * gr.n2 * gr.n1 doubles.
+hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *theta, const double *v,
+                        const int *step, long long stride, const double *m1, const double *m2,
+                        const double *m3, double *t1, double *t2, double *out, hipStream_t s);
 size_t fft_line_lds_bytes(const Grid &g);
 
 }  // namespace ltd

@@ -621,8 +621,9 @@ __global__ __launch_bounds__(FFT_NT) void k_rb_cache(const Grid g, const FftKArg
   __syncthreads();
   for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
     const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
-    const int y = xy / n1, x = xy - y * n1;
-    bxc[box_of(x, n1, bx) * bp + y] = in.c[(long long)gi + (long long)col * in.ldc];
+    const int y = xy / g.d1, x = xy - y * g.d1;
+    const int yr = y <= g.by ? y : y - g.d2 + n2;  // k_y mod n2
+    bxc[box_of(x, g.d1, bx) * bp + yr] = in.c[(long long)gi + (long long)col * in.ldc];
   }
   __syncthreads();
   fft_block<1, L2>(bxc, LinesUniform{0, bp}, nbx, 1, g.p2, tw2);
@@ -719,8 +720,9 @@ __global__ __launch_bounds__(FFT_NT) void k_rb_y(const Grid g, const FftKArgs ka
   const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
   for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
     const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
-    const int yy = xy / n1, x = xy - yy * n1;
-    fo.o0[gi + (long long)col * fo.ld0] = cscale(bxc[box_of(x, n1, bx) * bp + yy], inv_n);
+    const int yy = xy / g.d1, x = xy - yy * g.d1;
+    const int yr = yy <= g.by ? yy : yy - g.d2 + n2;
+    fo.o0[gi + (long long)col * fo.ld0] = cscale(bxc[box_of(x, g.d1, bx) * bp + yr], inv_n);
   }
 }
 
@@ -744,9 +746,10 @@ struct Two {
   static constexpr int LPW = 64 / G;                      // lines per wave
   static constexpr int P = (G % 2) ? G : G + 1;           // odd pitch of the exchange rows
   static constexpr int LS = G * P + ((9 - (G * P) % 8) % 8);  // line stride, = 1 mod 8
-  static constexpr int SCR = LPW * LS;                    // exchange values per wave
 };
 
+constexpr int RB_NW = 6;  // waves per block of k_rb_xz4
+constexpr int RB_LZ = 6;  // z columns per wave and pass of k_rb_xz4
 constexpr int rb_pitch(int n) { return n + ((9 - n % 8) % 8); }  // >= n, = 1 mod 8
 
 __device__ __forceinline__ void wave_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
@@ -769,156 +772,222 @@ __device__ __forceinline__ void twiddle_powers(double2 *v, double2 w) {
   }
 }
 
-// One y plane of one column.  grid (ncols, N2, nk).  LDS: R [nbz][RX] (inverse
-// x transforms of the kz box rows), then the per-wave exchange scratch.
-//   phase 1: box rows -> x transforms -> R
-//   phase 2: per x column: inverse z (box rows of R) -> * Theta V -> forward z
-//            -> box rows of R
-//   phase 3: R rows -> forward x transforms -> box columns -> slab_out
-// thp: Theta V of this step in the order [y][k2][x][k1], z = k1 + Z1 k2.
-template <int NX, int X1, int X2, int NZ, int Z1, int Z2>
-__global__ __launch_bounds__(FFT_NT) void k_rb_xz2(const Grid g, const FftKArgs ka, int ncols,
+// Same transforms with NW waves per block: an x row exchanges in place through
+// its own RX slots (value (k1, n2) at slot k1 F2 + n2, odd stride across lanes);
+// the z columns exchange through a per-wave scratch of LZ lines.
+template <int NX, int X1, int X2, int NZ, int Z1, int Z2, int NW, int LZ>
+__global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs ka, int ncols,
                                                    const double *__restrict__ thp) {
   using TX = Two<NX, X1, X2>;
   using TZ = Two<NZ, Z1, Z2>;
+  static_assert(LZ <= TZ::LPW, "z lines per wave");
   constexpr int RX = rb_pitch(NX);
-  constexpr int SCR = TX::SCR > TZ::SCR ? TX::SCR : TZ::SCR;
   extern __shared__ double2 sm[];
   const int col = blockIdx.x, y = blockIdx.y, kk = blockIdx.z;
   const int n2 = g.n2, bx = g.bx, nbx = g.nbx, bz = g.bz, nbz = g.nbz;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double2 *R = sm;
-  double2 *scr = sm + nbz * RX + wave * SCR;
+  double2 *scr = sm + nbz * RX + wave * (LZ * TZ::LS);
   const long long csz = (long long)nbz * n2 * nbx;
   const long long rs = (long long)n2 * nbx;  // kz stride of the box arrays
   const double2 *in = ka.slab_in[kk] + (long long)col * csz + (long long)y * nbx;
   double2 *out = ka.slab_out[kk] + (long long)col * csz + (long long)y * nbx;
-  const double2 zero = make_double2(0.0, 0.0);
   const int lx = lane / TX::G, rx = lane - lx * TX::G;
   const int lz = lane / TZ::G, rz = lane - lz * TZ::G;
-  const double2 wx = role_twiddle(rx, NX), wz = role_twiddle(rz, NZ);
 
-  // phase 1: inverse x transforms of the box rows
-  for (int r0 = wave * TX::LPW; r0 < nbz; r0 += nw * TX::LPW) {
-    const int r = r0 + lx;
-    const bool on = lx < TX::LPW && r < nbz;
-    double2 *sl = scr + lx * TX::LS;
-    if (on && rx < X2) {
-      double2 v[X1];
+  // phase 1: inverse x transforms of the box rows, in place in R
+  {
+    const double2 w = cconj(g.tw1[rx < NX ? rx : 0]);
+    for (int r0 = wave * TX::LPW; r0 < nbz; r0 += NW * TX::LPW) {
+      const int r = r0 + lx;
+      const bool on = lx < TX::LPW && r < nbz;
+      double2 *row = R + r * RX;
+      if (on && rx < X2) {
+        double2 v[X1];
 #pragma unroll
-      for (int n1 = 0; n1 < X1; ++n1) {
-        const int n = X2 * n1 + rx;
-        const int kx = n <= bx ? n : n - NX;
-        v[n1] = (n <= bx || n >= NX - bx) ? in[r * rs + kx + bx] : zero;
+        for (int n1 = 0; n1 < X1; ++n1) {
+          const int n = X2 * n1 + rx;
+          const int kx = n <= bx ? n : n - NX;
+          v[n1] = (n <= bx || n >= NX - bx) ? in[r * rs + kx + bx] : make_double2(0.0, 0.0);
+        }
+        dft_reg<X1, 1>(v);
+        twiddle_powers<X1>(v, w);
+#pragma unroll
+        for (int k1 = 0; k1 < X1; ++k1) row[k1 * X2 + rx] = v[k1];
       }
-      dft_reg<X1, 1>(v);
-      twiddle_powers<X1>(v, wx);
+      wave_fence();
+      if (on && rx < X1) {
+        double2 u[X2];
 #pragma unroll
-      for (int k1 = 0; k1 < X1; ++k1) sl[rx * TX::P + k1] = v[k1];
+        for (int q = 0; q < X2; ++q) u[q] = row[rx * X2 + q];
+        dft_reg<X2, 1>(u);
+        wave_fence();
+#pragma unroll
+        for (int k2 = 0; k2 < X2; ++k2) row[rx + X1 * k2] = u[k2];
+      }
+      wave_fence();
     }
-    wave_fence();
-    if (on && rx < X1) {
-      double2 u[X2];
-#pragma unroll
-      for (int q = 0; q < X2; ++q) u[q] = sl[q * TX::P + rx];
-      dft_reg<X2, 1>(u);
-#pragma unroll
-      for (int k2 = 0; k2 < X2; ++k2) R[r * RX + rx + X1 * k2] = u[k2];
-    }
-    wave_fence();
   }
   __syncthreads();
 
-  // phase 2: z columns, inverse -> product -> forward, in place in R
-  const double2 wzc = cconj(wz);
-  for (int x0 = wave * TZ::LPW; x0 < NX; x0 += nw * TZ::LPW) {
-    const int x = x0 + lz;
-    const bool on = lz < TZ::LPW && x < NX;
-    double2 *sl = scr + lz * TZ::LS;
-    double t[Z2];
-    if (on && rz < Z1) {
+  // phase 2: z columns, inverse -> product -> forward, in place in the box rows
+  {
+    const double2 w = cconj(g.tw3[rz < NZ ? rz : 0]), wc = cconj(w);
+    for (int x0 = wave * LZ; x0 < NX; x0 += NW * LZ) {
+      const int x = x0 + lz;
+      const bool on = lz < LZ && x < NX;
+      double2 *sl = scr + lz * TZ::LS;
+      if (on && rz < Z2) {
+        double2 v[Z1];
 #pragma unroll
-      for (int k2 = 0; k2 < Z2; ++k2) t[k2] = thp[(((long long)y * Z2 + k2) * NX + x) * Z1 + rz];
-    }
-    if (on && rz < Z2) {
-      double2 v[Z1];
+        for (int n1 = 0; n1 < Z1; ++n1) {
+          const int n = Z2 * n1 + rz;
+          const int row = n <= bz ? n + bz : n - NZ + bz;
+          v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : make_double2(0.0, 0.0);
+        }
+        dft_reg<Z1, 1>(v);
+        twiddle_powers<Z1>(v, w);
 #pragma unroll
-      for (int n1 = 0; n1 < Z1; ++n1) {
-        const int n = Z2 * n1 + rz;
-        const int row = n <= bz ? n + bz : n - NZ + bz;
-        v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : zero;
+        for (int k1 = 0; k1 < Z1; ++k1) sl[rz * TZ::P + k1] = v[k1];
       }
-      dft_reg<Z1, 1>(v);
-      twiddle_powers<Z1>(v, wz);
-#pragma unroll
-      for (int k1 = 0; k1 < Z1; ++k1) sl[rz * TZ::P + k1] = v[k1];
-    }
-    wave_fence();
-    if (on && rz < Z1) {
-      double2 u[Z2];
-#pragma unroll
-      for (int q = 0; q < Z2; ++q) u[q] = sl[q * TZ::P + rz];
-      dft_reg<Z2, 1>(u);
-#pragma unroll
-      for (int k2 = 0; k2 < Z2; ++k2) u[k2] = cscale(u[k2], t[k2]);
-      dft_reg<Z2, -1>(u);
-      twiddle_powers<Z2>(u, wzc);
       wave_fence();
+      if (on && rz < Z1) {
+        double t[Z2];
 #pragma unroll
-      for (int d = 0; d < Z2; ++d) sl[rz * TZ::P + d] = u[d];
-    }
-    wave_fence();
-    if (on && rz < Z2) {
-      double2 v[Z1];
+        for (int k2 = 0; k2 < Z2; ++k2) t[k2] = thp[(((long long)y * Z2 + k2) * NX + x) * Z1 + rz];
+        double2 u[Z2];
 #pragma unroll
-      for (int a = 0; a < Z1; ++a) v[a] = sl[a * TZ::P + rz];
-      dft_reg<Z1, -1>(v);
+        for (int q = 0; q < Z2; ++q) u[q] = sl[q * TZ::P + rz];
+        dft_reg<Z2, 1>(u);
 #pragma unroll
-      for (int c = 0; c < Z1; ++c) {
-        const int m = Z2 * c + rz;
-        if (m <= bz || m >= NZ - bz) R[(m <= bz ? m + bz : m - NZ + bz) * RX + x] = v[c];
+        for (int k2 = 0; k2 < Z2; ++k2) u[k2] = cscale(u[k2], t[k2]);
+        dft_reg<Z2, -1>(u);
+        twiddle_powers<Z2>(u, wc);
+        wave_fence();
+#pragma unroll
+        for (int d = 0; d < Z2; ++d) sl[rz * TZ::P + d] = u[d];
       }
+      wave_fence();
+      if (on && rz < Z2) {
+        double2 v[Z1];
+#pragma unroll
+        for (int a = 0; a < Z1; ++a) v[a] = sl[a * TZ::P + rz];
+        dft_reg<Z1, -1>(v);
+#pragma unroll
+        for (int c = 0; c < Z1; ++c) {
+          const int m = Z2 * c + rz;
+          if (m <= bz || m >= NZ - bz) R[(m <= bz ? m + bz : m - NZ + bz) * RX + x] = v[c];
+        }
+      }
+      wave_fence();
     }
-    wave_fence();
   }
   __syncthreads();
 
   // phase 3: forward x transforms of the box rows, box columns out
-  const double2 wxc = cconj(wx);
-  for (int r0 = wave * TX::LPW; r0 < nbz; r0 += nw * TX::LPW) {
-    const int r = r0 + lx;
-    const bool on = lx < TX::LPW && r < nbz;
-    double2 *sl = scr + lx * TX::LS;
-    if (on && rx < X1) {
-      double2 u[X2];
+  {
+    const double2 wc = g.tw1[rx < NX ? rx : 0];
+    for (int r0 = wave * TX::LPW; r0 < nbz; r0 += NW * TX::LPW) {
+      const int r = r0 + lx;
+      const bool on = lx < TX::LPW && r < nbz;
+      double2 *row = R + r * RX;
+      if (on && rx < X1) {
+        double2 u[X2];
 #pragma unroll
-      for (int b = 0; b < X2; ++b) u[b] = R[r * RX + rx + X1 * b];
-      dft_reg<X2, -1>(u);
-      twiddle_powers<X2>(u, wxc);
+        for (int b = 0; b < X2; ++b) u[b] = row[rx + X1 * b];
+        dft_reg<X2, -1>(u);
+        twiddle_powers<X2>(u, wc);
+        wave_fence();
 #pragma unroll
-      for (int d = 0; d < X2; ++d) sl[rx * TX::P + d] = u[d];
-    }
-    wave_fence();
-    if (on && rx < X2) {
-      double2 v[X1];
-#pragma unroll
-      for (int a = 0; a < X1; ++a) v[a] = sl[a * TX::P + rx];
-      dft_reg<X1, -1>(v);
-#pragma unroll
-      for (int c = 0; c < X1; ++c) {
-        const int m = X2 * c + rx;
-        if (m <= bx || m >= NX - bx) out[r * rs + (m <= bx ? m : m - NX) + bx] = v[c];
+        for (int d = 0; d < X2; ++d) row[rx * X2 + d] = u[d];
       }
+      wave_fence();
+      if (on && rx < X2) {
+        double2 v[X1];
+#pragma unroll
+        for (int a = 0; a < X1; ++a) v[a] = row[a * X2 + rx];
+        dft_reg<X1, -1>(v);
+#pragma unroll
+        for (int c = 0; c < X1; ++c) {
+          const int m = X2 * c + rx;
+          if (m <= bx || m >= NX - bx) out[r * rs + (m <= bx ? m : m - NX) + bx] = v[c];
+        }
+      }
+      wave_fence();
     }
-    wave_fence();
   }
 }
 
-// Theta V in the order k_rb_xz2 reads it: out[((y Z2 + k2) N1 + x) Z1 + k1] for
+// One pass of the W synthesis: out[o][j'][i] = sum_j M[j'][j] f[o][j][i] for
+// o < O, j' < Np, i < I (i fastest), f = in, or th * in when th is given.
+// perm > 0: the output is the z pass into the k_rb_xz4 order with O = 1 and
+// I = n2 n1 (perm = n1, z1, z2 the x length and the z split).  A block takes
+// 16 positions p = o I + i and all j'; LDS: M [Np][N], the tile [N][16].
+__global__ __launch_bounds__(256) void k_axis_mat(const double *__restrict__ in, const double *__restrict__ th,
+                                                  const int *step, long long stride, double *__restrict__ out,
+                                                  const double *__restrict__ M, int O, int N, int I, int Np,
+                                                  int perm_n1, int perm_z1, int perm_z2) {
+  extern __shared__ double sd[];
+  constexpr int TP = 16;
+  double *Ms = sd;
+  double *T = sd + (size_t)Np * N;
+  const long long P = (long long)O * I;
+  const long long p0 = (long long)blockIdx.x * TP;
+  if (step) in += (long long)(*step) * stride;
+  for (int t = threadIdx.x; t < Np * N; t += blockDim.x) Ms[t] = M[t];
+  for (int t = threadIdx.x; t < TP * N; t += blockDim.x) {
+    int j, pl;
+    if (I == 1) {
+      pl = t / N;
+      j = t - pl * N;
+    } else {
+      j = t / TP;
+      pl = t - j * TP;
+    }
+    const long long p = p0 + pl;
+    double f = 0.0;
+    if (p < P) {
+      const long long o = p / I, i = p - o * I;
+      const long long src = (o * N + j) * I + i;
+      f = th ? th[src] * in[src] : in[src];
+    }
+    T[j * TP + pl] = f;
+  }
+  __syncthreads();
+  const int q = threadIdx.x & 3;  // positions 4 q .. 4 q + 3
+  for (int jp = threadIdx.x >> 2; jp < Np; jp += blockDim.x >> 2) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const double *mr = Ms + (size_t)jp * N;
+    for (int j = 0; j < N; ++j) {
+      const double m = mr[j];
+      const double *tr = T + j * TP + 4 * q;
+      a0 = fma(m, tr[0], a0);
+      a1 = fma(m, tr[1], a1);
+      a2 = fma(m, tr[2], a2);
+      a3 = fma(m, tr[3], a3);
+    }
+    const double acc[4] = {a0, a1, a2, a3};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const long long p = p0 + 4 * q + e;
+      if (p >= P) continue;
+      const long long o = p / I, i = p - o * I;
+      if (perm_n1 > 0) {  // z pass: (z' = jp, y, x) from i = y n1 + x
+        const long long y = i / perm_n1, x = i - y * perm_n1;
+        out[((y * perm_z2 + jp / perm_z1) * perm_n1 + x) * perm_z1 + jp % perm_z1] = acc[e];
+      } else {
+        out[(o * Np + jp) * I + i] = acc[e];
+      }
+    }
+  }
+}
+
+// Theta V in the order k_rb_xz4 reads it: out[((y Z2 + k2) N1 + x) Z1 + k1] for
 // the grid point (z = k1 + Z1 k2, y, x); z1 == 0: the grid order itself.
 __global__ void k_rb_thv(double *__restrict__ out, const double *__restrict__ th, const double *__restrict__ v,
-                         int n1, int n2, int n3, int z1, int z2) {
+                         const int *step, long long stride, int n1, int n2, int n3, int z1, int z2) {
   const long long ng = (long long)n1 * n2 * n3;
+  if (step) v += (long long)(*step) * stride;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < ng; i += (long long)gridDim.x * blockDim.x) {
     if (z1 == 0) {
       out[i] = th[i] * v[i];
@@ -988,9 +1057,9 @@ void each_plane_kernel(F &&f) {
   f((const void *)k_rb_xz<a, c>);
   LTD_RB(16, 16) LTD_RB(64, 64) LTD_RB(72, 72) LTD_RB(96, 160)
 #undef LTD_RB
-  f((const void *)k_rb_xz2<72, 8, 9, 72, 8, 9>);
-  f((const void *)k_rb_xz2<64, 8, 8, 64, 8, 8>);
-  f((const void *)k_rb_xz2<16, 4, 4, 16, 4, 4>);
+  f((const void *)k_rb_xz4<72, 8, 9, 72, 8, 9, RB_NW, RB_LZ>);
+  f((const void *)k_rb_xz4<64, 8, 8, 64, 8, 8, RB_NW, RB_LZ>);
+  f((const void *)k_rb_xz4<16, 4, 4, 16, 4, 4, RB_NW, RB_LZ>);
   f((const void *)k_inv_plane<0, 0>);
   f((const void *)k_fwd_plane<0, 0>);
 #define LTD_PL(a, b)                            \
@@ -1039,21 +1108,52 @@ size_t fft_rb_slab_values(const Grid &g) { return (size_t)g.nbz * g.n2 * g.nbx; 
 int rb_split(int n) { return n == 72 ? 8 : n == 64 ? 8 : n == 16 ? 4 : 0; }
 bool rb_fast(const Grid &g) { return rb_split(g.n1) > 0 && rb_split(g.n3) > 0; }
 
-size_t rb_xz2_lds(const Grid &g) {
-  const auto scr = [](int n) {
-    const int f1 = rb_split(n), f2 = n / f1, gl = f1 > f2 ? f1 : f2, p = (gl % 2) ? gl : gl + 1;
-    const int ls = gl * p + ((9 - (gl * p) % 8) % 8);
-    return (64 / gl) * ls;
-  };
+size_t rb_xz4_lds(const Grid &g) {
+  const int f1 = rb_split(g.n3), f2 = g.n3 / f1, gl = f1 > f2 ? f1 : f2, p = (gl % 2) ? gl : gl + 1;
+  const int ls = gl * p + ((9 - (gl * p) % 8) % 8);
   const int rx = g.n1 + ((9 - g.n1 % 8) % 8);
-  return ((size_t)g.nbz * rx + (size_t)(FFT_NT / 64) * std::max(scr(g.n1), scr(g.n3))) * sizeof(double2);
+  return ((size_t)g.nbz * rx + (size_t)RB_NW * RB_LZ * ls) * sizeof(double2);
 }
 
-hipError_t fft_rb_thv(const Grid &g, const double *th, const double *v, double *out, hipStream_t s) {
+bool fft_rb_fast(const Grid &g) { return rb_fast(g); }
+
+int fft_rb_length(int n, int b) {
+  for (int c : {16, 64, 72})
+    if (c >= 4 * b + 1 && c <= n) return c;
+  return n;
+}
+
+hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th, const double *v,
+                        const int *step, long long stride, const double *m1, const double *m2,
+                        const double *m3, double *t1, double *t2, double *out, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_axis_mat, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  const int z1 = rb_split(gr.n3), z2 = gr.n3 / z1;
+  const auto launch = [&](const double *in, const double *thp, const int *st, double *o, const double *M, int O,
+                          int N, int I, int Np, int pn1) {
+    const long long P = (long long)O * I;
+    const size_t lds = ((size_t)Np * N + 16 * (size_t)N) * sizeof(double);
+    hipLaunchKernelGGL(k_axis_mat, dim3((unsigned)((P + 15) / 16)), dim3(256), lds, s, in, thp, st, stride, o, M, O,
+                       N, I, Np, pn1, z1, z2);
+  };
+  // x pass: [n3][n2][n1] -> [n3][n2][n1'] (Theta V formed on the fly)
+  launch(v, th, step, t1, m1, n3 * n2, n1, 1, gr.n1, 0);
+  // y pass: [n3][n2][n1'] -> [n3][n2'][n1']
+  launch(t1, nullptr, nullptr, t2, m2, n3, n2, gr.n1, gr.n2, 0);
+  // z pass: [n3][n2' n1'] -> permuted [n2'][k2][n1'][k1]
+  launch(t2, nullptr, nullptr, out, m3, 1, n3, gr.n2 * gr.n1, gr.n3, gr.n1);
+  return hipGetLastError();
+}
+
+hipError_t fft_rb_thv(const Grid &g, const double *th, const double *v, const int *step, long long stride,
+                      double *out, hipStream_t s) {
   const int z1 = rb_fast(g) ? rb_split(g.n3) : 0, z2 = z1 ? g.n3 / z1 : 0;
   const long long ng = (long long)g.n1 * g.n2 * g.n3;
   const int blocks = (int)std::min<long long>((ng + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_rb_thv, dim3(blocks), dim3(256), 0, s, out, th, v, g.n1, g.n2, g.n3, z1, z2);
+  hipLaunchKernelGGL(k_rb_thv, dim3(blocks), dim3(256), 0, s, out, th, v, step, stride, g.n1, g.n2, g.n3, z1, z2);
   return hipGetLastError();
 }
 
@@ -1076,15 +1176,15 @@ hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, con
   set_attrs();
   const dim3 block(FFT_NT);
   if (part == 0 && rb_fast(g)) {
-    const dim3 grid(ncols, g.n2, nk);
-    const size_t lds = rb_xz2_lds(g);
-#define LTD_XZ2(a, a1, c, c1) \
-  hipLaunchKernelGGL((k_rb_xz2<a, a1, a / a1, c, c1, c / c1>), grid, block, lds, s, g, ka, ncols, thv)
-    if (g.n1 == 72 && g.n3 == 72) LTD_XZ2(72, 8, 72, 8);
-    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ2(64, 8, 64, 8);
-    else if (g.n1 == 16 && g.n3 == 16) LTD_XZ2(16, 4, 16, 4);
+    const dim3 grid(ncols, g.n2, nk), blk(RB_NW * 64);
+    const size_t lds = rb_xz4_lds(g);
+#define LTD_XZ4(a, a1, c, c1) \
+  hipLaunchKernelGGL((k_rb_xz4<a, a1, a / a1, c, c1, c / c1, RB_NW, RB_LZ>), grid, blk, lds, s, g, ka, ncols, thv)
+    if (g.n1 == 72 && g.n3 == 72) LTD_XZ4(72, 8, 72, 8);
+    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ4(64, 8, 64, 8);
+    else if (g.n1 == 16 && g.n3 == 16) LTD_XZ4(16, 4, 16, 4);
     else return hipErrorInvalidValue;
-#undef LTD_XZ2
+#undef LTD_XZ4
   } else if (part == 0) {
     const dim3 grid(ncols, g.n2, nk);
     const size_t lds = rb_xz_lds(g);

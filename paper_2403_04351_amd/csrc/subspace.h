@@ -56,6 +56,10 @@ struct AdjCtx {
   double *dl_da_mid, *dl_da_t;
 };
 
+// dst[i] = src[off + i], i < n, off = (*step) * stride (step on the device) or
+// host_off when step is NULL.
+hipError_t launch_copy_step(double2 *dst, const double2 *src, long long n, const int *step, long long stride,
+                            long long host_off, hipStream_t s);
 hipError_t launch_copy_rows(double2 *dst, int ldd, const double2 *src, int lds, int rows, int cols, bool zero,
                             hipStream_t s);
 hipError_t launch_herm_split(const double2 *x, int ldx, int n, int nb, double2 *out, hipStream_t s);

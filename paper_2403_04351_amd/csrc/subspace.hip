@@ -153,6 +153,13 @@ __global__ void k_heff(double2 *out, const double2 *h, const double2 *p, const d
     out[e] = make_double2(h[e].x + al * p[e].x + be * o[e].x, h[e].y + al * p[e].y + be * o[e].y);
 }
 
+__global__ void k_copy_step(double2 *__restrict__ dst, const double2 *__restrict__ src, long long n,
+                            const int *step, long long stride, long long host_off) {
+  const long long off = step ? (long long)(*step) * stride : host_off;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[off + i];
+}
+
 __global__ void k_thv(double *out, const double *th, const double *v, long long n) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
     out[e] = th[e] * v[e];
@@ -757,6 +764,14 @@ hipError_t launch_heff(double2 *out, const double2 *h, const double2 *p, const d
   if (n <= 0) return hipSuccess;
   const int g = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
   hipLaunchKernelGGL(k_heff, dim3(g), dim3(256), 0, s, out, h, p, o, al, be, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_step(double2 *dst, const double2 *src, long long n, const int *step, long long stride,
+                            long long host_off, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_copy_step, dim3(blocks), dim3(256), 0, s, dst, src, n, step, stride, host_off);
   return hipGetLastError();
 }
 

@@ -158,8 +158,17 @@ class Ltd:
         return a.value, b.value, d.value
 
     # ------------------------------------------------------------------
-    def make_step_args(self, mode, dt, a_t, a_mid, theta, n_steps, c_out=None, v_r_t=None, h_t=None):
-        """Device buffers and the StepArgs for a run of n_steps; theta (n_k, n_states, n_aux)."""
+    def rebuild_grid(self):
+        """FFT lengths (N1, N2, N3) of the per-step rebuild."""
+        out = (C.c_int * 3)()
+        check(self.lib.ltd_rebuild_grid(self.handle, out), "ltd_rebuild_grid")
+        return tuple(out)
+
+    def make_step_args(self, mode, dt, a_t, a_mid, theta, n_steps, c_out=None, v_r_t=None, h_t=None,
+                       v_stride=0, h_stride=0):
+        """Device buffers and the StepArgs for a run of n_steps; theta (n_k, n_states, n_aux).
+        v_stride / h_stride: elements between the potentials / blocks of consecutive
+        steps when v_r_t / h_t hold one per step (0: one for every step)."""
         torch = _torch()
         dev = self.device
         st = dict(
@@ -171,7 +180,8 @@ class Ltd:
         )
         st["args"] = StepArgs(mode=mode, dt=dt, a_t=_ptr(a_t), a_mid=_ptr(a_mid), step=_ptr(st["step"]),
                               v_r_t=_ptr(v_r_t), h_t=_ptr(h_t), theta=_ptr(theta), c_out=_ptr(c_out),
-                              j_out=_ptr(st["j"]), e_out=_ptr(st["e"]), dmu_out=_ptr(st["dmu"]))
+                              j_out=_ptr(st["j"]), e_out=_ptr(st["e"]), dmu_out=_ptr(st["dmu"]),
+                              v_stride=v_stride, h_stride=h_stride)
         return st
 
     def step(self, st):
@@ -180,8 +190,9 @@ class Ltd:
     def run(self, st, n_steps: int):
         check(self.lib.ltd_propagate(self.handle, C.byref(st["args"]), n_steps, self.stream()), "ltd_propagate")
 
-    def propagate(self, mode, dt, a_t, a_mid, theta, n_steps, graph=True, c_out=None, v_r_t=None, h_t=None):
-        st = self.make_step_args(mode, dt, a_t, a_mid, theta, n_steps, c_out, v_r_t, h_t)
+    def propagate(self, mode, dt, a_t, a_mid, theta, n_steps, graph=True, c_out=None, v_r_t=None, h_t=None,
+                  v_stride=0, h_stride=0):
+        st = self.make_step_args(mode, dt, a_t, a_mid, theta, n_steps, c_out, v_r_t, h_t, v_stride, h_stride)
         if graph:
             self.run(st, n_steps)
         else:
@@ -243,13 +254,16 @@ def chebyshev_coefficients(tau: float, kmax: int):
 # Pulse gradients: forward propagation with theta checkpoints, backward by
 # recomputing each segment and running the adjoint steps in reverse.
 # ----------------------------------------------------------------------
-def pulse_forward(lt: Ltd, mode, dt, q, t_end, n_steps, theta0, checkpoint=50):
+def pulse_forward(lt: Ltd, mode, dt, q, t_end, n_steps, theta0, checkpoint=50, potential=None):
     """Propagates theta0 (n_k, n_states, n_aux) under the piecewise-linear pulse
-    with knots q; returns (loss, state) with loss = dt sum_n w_n (J_n - J_0)."""
+    with knots q; returns (loss, state) with loss = dt sum_n w_n (J_n - J_0).
+    potential: optional dict of make_step_args keywords (v_r_t, h_t, v_stride,
+    h_stride) for REBUILD with a potential handed in per step."""
     torch = _torch()
+    pot = dict(potential or {})
     a_t, a_mid = lt.knot_samples(q, t_end, dt, n_steps)
     theta = theta0.clone()
-    st = lt.make_step_args(mode, dt, a_t, a_mid, theta, n_steps)
+    st = lt.make_step_args(mode, dt, a_t, a_mid, theta, n_steps, **pot)
     ckpt = {0: theta.clone()}
     done = 0
     while done < n_steps:
@@ -261,7 +275,7 @@ def pulse_forward(lt: Ltd, mode, dt, q, t_end, n_steps, theta0, checkpoint=50):
     w[0] = w[-1] = 0.5
     j = st["j"]
     loss = dt * torch.sum(w * (j - j[0]))
-    return loss, dict(st=st, ckpt=ckpt, a_t=a_t, a_mid=a_mid, checkpoint=checkpoint)
+    return loss, dict(st=st, ckpt=ckpt, a_t=a_t, a_mid=a_mid, checkpoint=checkpoint, pot=pot)
 
 
 def pulse_backward(lt: Ltd, mode, dt, q, t_end, n_steps, fw):
@@ -273,22 +287,23 @@ def pulse_backward(lt: Ltd, mode, dt, q, t_end, n_steps, fw):
     g_mid = torch.zeros(n_steps, dtype=torch.float64, device=dev)
     g_t = torch.zeros(n_steps + 1, dtype=torch.float64, device=dev)
     ck = fw["checkpoint"]
+    pot = fw["pot"]
     # terminal point
     th_n = fw["ckpt"][n_steps]
-    sa = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], th_n, n_steps)
+    sa = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], th_n, n_steps, **pot)
     lt.adjoint_step(sa, n_steps, n_steps, None, mu, None, g_t, terminal=True)
     seg_starts = sorted(s for s in fw["ckpt"] if s < n_steps)
     for s0 in reversed(seg_starts):
         s1 = min(s0 + ck, n_steps)
         theta = fw["ckpt"][s0].clone()
-        rec = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], theta, n_steps)
+        rec = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], theta, n_steps, **pot)
         rec["step"].fill_(s0)
         thetas = []
         for _ in range(s0, s1):
             thetas.append(theta.clone())
             lt.step(rec)
         for n in range(s1 - 1, s0 - 1, -1):
-            sa = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], thetas[n - s0], n_steps)
+            sa = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], thetas[n - s0], n_steps, **pot)
             lt.adjoint_step(sa, n, n_steps, mu, mu, g_mid, g_t)
     return lt.knot_gradient(g_t, g_mid, dt, q.numel(), t_end), g_t, g_mid
 
@@ -297,13 +312,13 @@ class PulseLoss:
     """torch.autograd.Function: L(q) = delta mu_z(T)/Omega for knot amplitudes q."""
 
     @staticmethod
-    def apply(lt, q, mode, dt, t_end, n_steps, theta0, checkpoint=50):
+    def apply(lt, q, mode, dt, t_end, n_steps, theta0, checkpoint=50, potential=None):
         torch = _torch()
 
         class _F(torch.autograd.Function):
             @staticmethod
             def forward(ctx, qq):
-                loss, fw = pulse_forward(lt, mode, dt, qq.detach(), t_end, n_steps, theta0, checkpoint)
+                loss, fw = pulse_forward(lt, mode, dt, qq.detach(), t_end, n_steps, theta0, checkpoint, potential)
                 ctx.fw = fw
                 ctx.save_for_backward(qq.detach())
                 return loss
