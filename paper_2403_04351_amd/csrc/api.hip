@@ -83,6 +83,9 @@ struct ltd_system {
   Grid grid{};
   Grid rgrid{};
   bool rb_synth = false;
+  // side stream of the rebuild: the muffin-tin branch runs beside the FFT chain
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t o_rtw1 = 0, o_rtw2 = 0, o_rtw3 = 0, o_M1 = 0, o_M2 = 0, o_M3 = 0, o_syn1 = 0, o_syn2 = 0;
   int chunk = 0;        // columns per apply pass
   bool h_in_lds = false;
@@ -606,6 +609,28 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
                      int host_step = -1) {
   const Grid g = rgrid_of(sys);
   const int n = sys->n_aux;
+  const void *hx = k2_source(sys, a);
+  if (hx != sys->k2_step_h) {  // host tables before any launch of the step
+    sys->k2_step_h = hx;
+    LTD_TRY(build_step_tables(sys));
+  }
+  // muffin-tin branch (blocks of the step, K2 into the Y rows past the G block)
+  // on the side stream, beside the FFT chain; serial when stages are timed
+  const bool fork = pf == nullptr && sys->side != nullptr;
+  hipStream_t sb = s;
+  if (fork) {
+    LTD_HIP(hipEventRecord(sys->ev_fork, s));
+    LTD_HIP(hipStreamWaitEvent(sys->side, sys->ev_fork, 0));
+    sb = sys->side;
+  }
+  if (a->h_t && a->h_stride)
+    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), reinterpret_cast<const double2 *>(a->h_t),
+                             sys->blk_elems, host_step >= 0 ? nullptr : a->step, a->h_stride,
+                             host_step >= 0 ? (long long)host_step * a->h_stride : 0, sb));
+  if (fork) {
+    LTD_TRY(run_k2(sys, sys->k2_step, n, sb));
+    LTD_HIP(hipEventRecord(sys->ev_join, sb));
+  }
   const double *thv = sys->at<double>(sys->o_thv_rb);
   if (a->v_r_t) {
     const double *v = a->v_r_t;
@@ -617,10 +642,6 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
     LTD_TRY(rebuild_potential(sys, v, dstep, a->v_stride, sys->at<double>(sys->o_thv_step), s));
     thv = sys->at<double>(sys->o_thv_step);
   }
-  if (a->h_t && a->h_stride)
-    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), reinterpret_cast<const double2 *>(a->h_t),
-                             sys->blk_elems, host_step >= 0 ? nullptr : a->step, a->h_stride,
-                             host_step >= 0 ? (long long)host_step * a->h_stride : 0, s));
   LTD_MARK(pf, 0);
   const long long slab = (long long)fft_rb_slab_values(g) * n;
   for (int k0 = 0; k0 < sys->n_k; k0 += FFT_MAXK) {
@@ -641,12 +662,8 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
     LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1));
     LTD_MARK(pf, 2);
   }
-  const void *hx = k2_source(sys, a);
-  if (hx != sys->k2_step_h) {
-    sys->k2_step_h = hx;
-    LTD_TRY(build_step_tables(sys));
-  }
-  LTD_TRY(run_k2(sys, sys->k2_step, n, s));
+  if (fork) LTD_HIP(hipStreamWaitEvent(s, sys->ev_join, 0));
+  else LTD_TRY(run_k2(sys, sys->k2_step, n, s));
   LTD_MARK(pf, 3);
   LTD_HIP(gemm_launch_table(OP_C, OP_N, sys->at<ZProb>(sys->o_vstep_tab), sys->vstep_tab.data(),
                             (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_partials), 0, s));
@@ -906,9 +923,9 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     sys->o_rtw1 = ar.take(r.n1 * sizeof(double2));
     sys->o_rtw2 = ar.take(r.n2 * sizeof(double2));
     sys->o_rtw3 = ar.take(r.n3 * sizeof(double2));
-    sys->o_M1 = ar.take((size_t)r.n1 * g.n1 * sizeof(double));
-    sys->o_M2 = ar.take((size_t)r.n2 * g.n2 * sizeof(double));
-    sys->o_M3 = ar.take((size_t)r.n3 * g.n3 * sizeof(double));
+    sys->o_M1 = ar.take((size_t)fft_rb_table_len(g.n1, r.n1) * sizeof(double));
+    sys->o_M2 = ar.take((size_t)fft_rb_table_len(g.n2, r.n2) * sizeof(double));
+    sys->o_M3 = ar.take((size_t)fft_rb_table_len(g.n3, r.n3) * sizeof(double));
     sys->o_syn1 = ar.take((size_t)g.n3 * g.n2 * r.n1 * sizeof(double));
     sys->o_syn2 = ar.take((size_t)g.n3 * r.n2 * r.n1 * sizeof(double));
   }
@@ -959,6 +976,11 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
   hipStream_t s = S(stream);
   fft_init_attrs();
   subspace_init_attrs();
+  if (!sys->side) {
+    LTD_HIP(hipStreamCreateWithFlags(&sys->side, hipStreamNonBlocking));
+    LTD_HIP(hipEventCreateWithFlags(&sys->ev_fork, hipEventDisableTiming));
+    LTD_HIP(hipEventCreateWithFlags(&sys->ev_join, hipEventDisableTiming));
+  }
   // twiddles exp(-2 pi i m / L)
   auto tw = [&](int L, size_t off) -> ltd_status {
     std::vector<double2> t(L);
@@ -977,16 +999,17 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
     LTD_TRY(tw(r.n1, sys->o_rtw1));
     LTD_TRY(tw(r.n2, sys->o_rtw2));
     LTD_TRY(tw(r.n3, sys->o_rtw3));
-    // M[j'][j] = (1/N) sum_{|q| <= 2b} exp(2 pi i q j'/N') exp(-2 pi i q j/N), real
+    // tab[m] = (1/N) sum_{|q| <= 2b} exp(2 pi i q m / L): the axis matrix
+    // M[j'][j] = (1/N) sum_{|q| <= 2b} exp(2 pi i q j'/N') exp(-2 pi i q j/N) (real)
+    // at j'/N' - j/N = m/L, L = lcm(N, N')
     auto mat = [&](int np, int nn, int b, size_t off) -> ltd_status {
-      std::vector<double> m((size_t)np * nn);
-      for (int jp = 0; jp < np; ++jp)
-        for (int j = 0; j < nn; ++j) {
-          double acc = 1.0;
-          for (int q = 1; q <= 2 * b; ++q)
-            acc += 2.0 * std::cos(2.0 * M_PI * q * ((double)jp / np - (double)j / nn));
-          m[(size_t)jp * nn + j] = acc / nn;
-        }
+      const int L = fft_rb_table_len(nn, np);
+      std::vector<double> m(L);
+      for (int e = 0; e < L; ++e) {
+        double acc = 1.0;
+        for (int q = 1; q <= 2 * b; ++q) acc += 2.0 * std::cos(2.0 * M_PI * (double)((long long)q * e % L) / L);
+        m[e] = acc / nn;
+      }
       LTD_HIP(hipMemcpy(sys->ws + off, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice));
       return LTD_OK;
     };
@@ -1035,6 +1058,9 @@ ltd_status ltd_destroy(ltd_system *sys) {
   if (sys->gexec) (void)hipGraphExecDestroy(sys->gexec);
   if (sys->graph) (void)hipGraphDestroy(sys->graph);
   if (sys->cap_stream) (void)hipStreamDestroy(sys->cap_stream);
+  if (sys->side) (void)hipStreamDestroy(sys->side);
+  if (sys->ev_fork) (void)hipEventDestroy(sys->ev_fork);
+  if (sys->ev_join) (void)hipEventDestroy(sys->ev_join);
   delete sys;
   return LTD_OK;
 }

@@ -94,6 +94,27 @@ struct Grid {
   int d1, d2;                      // grid of the sphere tables' positions y * d1 + x
 };
 
+// Block-wide staging of e < n: store(e, load(e)), each thread issuing eight
+// loads (at clamped, always valid indices) before it stores their values, so
+// that the loads are in flight together.
+template <class T, class LD, class ST>
+__device__ __forceinline__ void stage8(int n, LD load, ST store) {
+  const int nt = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < n; e0 += 8 * nt) {
+    T r[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + q * nt;
+      r[q] = load(e < n ? e : n - 1);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + q * nt;
+      if (e < n) store(e, r[q]);
+    }
+  }
+}
+
 // Per-k sphere tables (device).
 struct KSphere {
   const double *gk;       // [n_g][3]
@@ -161,12 +182,15 @@ int fft_rb_length(int n, int b);
 // True when fft_rb_step has a register path for this grid (x and z lengths).
 bool fft_rb_fast(const Grid &g);
 // W on the rebuild grid gr from Theta V on the original grid (n1, n2, n3):
-// W = IDFT_gr(keep |q_d| <= 2 b_d (DFT(Theta V))), one real matrix M_d
-// (gr.n_d x n_d) per axis, passes z, y, x; written in the layout fft_rb_step
-// part 0 reads.  t1: n3 * n2 * gr.n1 doubles, t2: n3 * gr.n2 * gr.n1 doubles.
+// W = IDFT_gr(keep |q_d| <= 2 b_d (DFT(Theta V))), one real matrix per axis,
+// M_d[j'][j] = (1/n_d) sum_{|q| <= 2 b_d} exp(2 pi i q (j'/n'_d - j/n_d)), given by
+// its table tab_d[m] = M at j'/n'_d - j/n_d = m / L_d (L_d = fft_rb_table_len);
+// passes x, y, z, written in the layout fft_rb_step part 0 reads.
+// t1: n3 * n2 * gr.n1 doubles, t2: n3 * gr.n2 * gr.n1 doubles.
+int fft_rb_table_len(int n, int np);
 hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *theta, const double *v,
-                        const int *step, long long stride, const double *m1, const double *m2,
-                        const double *m3, double *t1, double *t2, double *out, hipStream_t s);
+                        const int *step, long long stride, const double *tab1, const double *tab2,
+                        const double *tab3, double *t1, double *t2, double *out, hipStream_t s);
 size_t fft_line_lds_bytes(const Grid &g);
 
 }  // namespace ltd

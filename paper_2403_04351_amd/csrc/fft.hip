@@ -31,6 +31,8 @@
 #include "common.h"
 
 #include <cmath>
+#include <numeric>
+#include <type_traits>
 
 namespace ltd {
 
@@ -710,10 +712,8 @@ __global__ __launch_bounds__(FFT_NT) void k_rb_y(const Grid g, const FftKArgs ka
   const FwdOut &fo = ka.out[kk];
   const long long csz = (long long)g.nbz * n2 * nbx;
   const double2 *src = ka.slab_in[kk] + (long long)col * csz + (long long)pz * n2 * nbx;
-  for (int i = threadIdx.x; i < n2 * nbx; i += blockDim.x) {
-    const int y = i / nbx, b = i - y * nbx;
-    bxc[b * bp + y] = src[i];
-  }
+  stage8<double2>(
+      n2 * nbx, [&](int i) { return src[i]; }, [&](int i, double2 x) { bxc[(i % nbx) * bp + i / nbx] = x; });
   __syncthreads();
   fft_block<-1, L2>(bxc, LinesUniform{0, bp}, nbx, 1, g.p2, tw2);
   const double inv_n = 1.0 / ((double)n1 * n2 * g.n3);
@@ -748,8 +748,9 @@ struct Two {
   static constexpr int LS = G * P + ((9 - (G * P) % 8) % 8);  // line stride, = 1 mod 8
 };
 
-constexpr int RB_NW = 6;  // waves per block of k_rb_xz4
-constexpr int RB_LZ = 6;  // z columns per wave and pass of k_rb_xz4
+constexpr int RB_NW = 4;  // waves per block of k_rb_xz4
+// z columns per wave and pass of k_rb_xz4: up to 8, as many lines as fit a wave
+constexpr int rb_lz(int lpw) { return lpw < 8 ? lpw : 8; }
 constexpr int rb_pitch(int n) { return n + ((9 - n % 8) % 8); }  // >= n, = 1 mod 8
 
 __device__ __forceinline__ void wave_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
@@ -918,69 +919,95 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
   }
 }
 
-// One pass of the W synthesis: out[o][j'][i] = sum_j M[j'][j] f[o][j][i] for
-// o < O, j' < Np, i < I (i fastest), f = in, or th * in when th is given.
-// perm > 0: the output is the z pass into the k_rb_xz4 order with O = 1 and
-// I = n2 n1 (perm = n1, z1, z2 the x length and the z split).  A block takes
-// 16 positions p = o I + i and all j'; LDS: M [Np][N], the tile [N][16].
-__global__ __launch_bounds__(256) void k_axis_mat(const double *__restrict__ in, const double *__restrict__ th,
+// One axis pass of the W synthesis with the axis matrix given by its Dirichlet
+// table: M[j'][j] = tab[(c1 j' - c2 j) mod L] (c1 = N/g, c2 = N'/g, L = N N'/g,
+// g = gcd(N, N')), so that the block stages L values instead of N' N.
+//   out(o, j', i) = sum_j M[j'][j] f(o, j, i),  f(o, j, i) = in[(o N + j) I + i]
+//   (times th[...] when th is given), o < O, j' < Np, i < I.
+// A block takes TP positions p = o I + i (i fastest) and all j'.  perm_n1 > 0:
+// the z pass into the k_rb_xz4 order (O = 1, i = y' N1' + x').
+// LDS: table [L], tile [N][TP+1].
+template <int TP, bool TH>
+__global__ __launch_bounds__(256) void k_syn_pass(const double *__restrict__ in, const double *__restrict__ th,
                                                   const int *step, long long stride, double *__restrict__ out,
-                                                  const double *__restrict__ M, int O, int N, int I, int Np,
-                                                  int perm_n1, int perm_z1, int perm_z2) {
+                                                  const double *__restrict__ tab, int L, int c1, int c2, int O,
+                                                  int N, int I, int Np, int perm_n1, int perm_z1, int perm_z2) {
   extern __shared__ double sd[];
-  constexpr int TP = 16;
-  double *Ms = sd;
-  double *T = sd + (size_t)Np * N;
-  const long long P = (long long)O * I;
-  const long long p0 = (long long)blockIdx.x * TP;
+  double *tb = sd;
+  double *T = sd + L;
+  const int P = O * I;
+  const int p0 = blockIdx.x * TP;
+  const int np = (P - p0) < TP ? (P - p0) : TP;
   if (step) in += (long long)(*step) * stride;
-  for (int t = threadIdx.x; t < Np * N; t += blockDim.x) Ms[t] = M[t];
-  for (int t = threadIdx.x; t < TP * N; t += blockDim.x) {
-    int j, pl;
-    if (I == 1) {
-      pl = t / N;
-      j = t - pl * N;
-    } else {
-      j = t / TP;
-      pl = t - j * TP;
-    }
-    const long long p = p0 + pl;
-    double f = 0.0;
-    if (p < P) {
-      const long long o = p / I, i = p - o * I;
-      const long long src = (o * N + j) * I + i;
-      f = th ? th[src] * in[src] : in[src];
-    }
-    T[j * TP + pl] = f;
+  stage8<double>(
+      L, [&](int e) { return tab[e]; }, [&](int e, double x) { tb[e] = x; });
+  if (I == 1) {  // rows o = p, contiguous in j
+    stage8<double>(
+        np * N,
+        [&](int e) {
+          const long long src = (long long)p0 * N + e;
+          if constexpr (TH) return th[src] * in[src];
+          else return in[src];
+        },
+        [&](int e, double x) { T[(e % N) * (TP + 1) + e / N] = x; });
+  } else {  // positions contiguous in i (at most one row boundary: TP <= I)
+    const int o0 = p0 / I, i0 = p0 - o0 * I;
+    stage8<double>(
+        N * TP,
+        [&](int e) {
+          const int j = e / TP, pl = e % TP;
+          int i = i0 + (pl < np ? pl : np - 1), o = o0;
+          if (i >= I) {
+            i -= I;
+            ++o;
+          }
+          const long long src = ((long long)o * N + j) * I + i;
+          if constexpr (TH) return th[src] * in[src];
+          else return in[src];
+        },
+        [&](int e, double x) { T[(e / TP) * (TP + 1) + e % TP] = x; });
   }
   __syncthreads();
-  const int q = threadIdx.x & 3;  // positions 4 q .. 4 q + 3
-  for (int jp = threadIdx.x >> 2; jp < Np; jp += blockDim.x >> 2) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    const double *mr = Ms + (size_t)jp * N;
+  // 2 x 2 output tiles (j', position); the table index of row j' at j is
+  // (c1 j' - c2 j) mod L, stepped by -c2 (mod L) along j
+  const int tn = (np + 1) / 2, tiles = ((Np + 1) / 2) * tn;
+  for (int tile = threadIdx.x; tile < tiles; tile += blockDim.x) {
+    const int i0 = (tile / tn) * 2, q0 = (tile % tn) * 2;
+    const int ra = i0, rb = (i0 + 1 < Np) ? i0 + 1 : Np - 1;
+    const int qa = q0, qb = (q0 + 1 < np) ? q0 + 1 : np - 1;
+    int xa = (int)(((long long)c1 * ra) % L), xb = (int)(((long long)c1 * rb) % L);
+    double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+#pragma unroll 8
     for (int j = 0; j < N; ++j) {
-      const double m = mr[j];
-      const double *tr = T + j * TP + 4 * q;
-      a0 = fma(m, tr[0], a0);
-      a1 = fma(m, tr[1], a1);
-      a2 = fma(m, tr[2], a2);
-      a3 = fma(m, tr[3], a3);
+      const double ma = tb[xa], mb = tb[xb];
+      const double ta = T[j * (TP + 1) + qa], tq = T[j * (TP + 1) + qb];
+      s00 = fma(ma, ta, s00);
+      s01 = fma(ma, tq, s01);
+      s10 = fma(mb, ta, s10);
+      s11 = fma(mb, tq, s11);
+      xa -= c2;
+      xa += xa < 0 ? L : 0;
+      xb -= c2;
+      xb += xb < 0 ? L : 0;
     }
-    const double acc[4] = {a0, a1, a2, a3};
+    const double acc[2][2] = {{s00, s01}, {s10, s11}};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const long long p = p0 + 4 * q + e;
-      if (p >= P) continue;
-      const long long o = p / I, i = p - o * I;
-      if (perm_n1 > 0) {  // z pass: (z' = jp, y, x) from i = y n1 + x
-        const long long y = i / perm_n1, x = i - y * perm_n1;
-        out[((y * perm_z2 + jp / perm_z1) * perm_n1 + x) * perm_z1 + jp % perm_z1] = acc[e];
-      } else {
-        out[(o * Np + jp) * I + i] = acc[e];
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int jp = i0 + r, q = q0 + c;
+        if (jp >= Np || q >= np) continue;
+        const int p = p0 + q, o = p / I, i = p - o * I;
+        if (perm_n1 > 0) {
+          const int y = i / perm_n1, x = i - y * perm_n1;
+          out[(((long long)y * perm_z2 + jp / perm_z1) * perm_n1 + x) * perm_z1 + jp % perm_z1] = acc[r][c];
+        } else {
+          out[((long long)o * Np + jp) * I + i] = acc[r][c];
+        }
       }
-    }
   }
 }
+
 
 // Theta V in the order k_rb_xz4 reads it: out[((y Z2 + k2) N1 + x) Z1 + k1] for
 // the grid point (z = k1 + Z1 k2, y, x); z1 == 0: the grid order itself.
@@ -1057,9 +1084,9 @@ void each_plane_kernel(F &&f) {
   f((const void *)k_rb_xz<a, c>);
   LTD_RB(16, 16) LTD_RB(64, 64) LTD_RB(72, 72) LTD_RB(96, 160)
 #undef LTD_RB
-  f((const void *)k_rb_xz4<72, 8, 9, 72, 8, 9, RB_NW, RB_LZ>);
-  f((const void *)k_rb_xz4<64, 8, 8, 64, 8, 8, RB_NW, RB_LZ>);
-  f((const void *)k_rb_xz4<16, 4, 4, 16, 4, 4, RB_NW, RB_LZ>);
+  f((const void *)k_rb_xz4<72, 8, 9, 72, 8, 9, RB_NW, rb_lz(Two<72, 8, 9>::LPW)>);
+  f((const void *)k_rb_xz4<64, 8, 8, 64, 8, 8, RB_NW, rb_lz(Two<64, 8, 8>::LPW)>);
+  f((const void *)k_rb_xz4<16, 4, 4, 16, 4, 4, RB_NW, rb_lz(Two<16, 4, 4>::LPW)>);
   f((const void *)k_inv_plane<0, 0>);
   f((const void *)k_fwd_plane<0, 0>);
 #define LTD_PL(a, b)                            \
@@ -1112,7 +1139,7 @@ size_t rb_xz4_lds(const Grid &g) {
   const int f1 = rb_split(g.n3), f2 = g.n3 / f1, gl = f1 > f2 ? f1 : f2, p = (gl % 2) ? gl : gl + 1;
   const int ls = gl * p + ((9 - (gl * p) % 8) % 8);
   const int rx = g.n1 + ((9 - g.n1 % 8) % 8);
-  return ((size_t)g.nbz * rx + (size_t)RB_NW * RB_LZ * ls) * sizeof(double2);
+  return ((size_t)g.nbz * rx + (size_t)RB_NW * rb_lz(64 / gl) * ls) * sizeof(double2);
 }
 
 bool fft_rb_fast(const Grid &g) { return rb_fast(g); }
@@ -1123,28 +1150,32 @@ int fft_rb_length(int n, int b) {
   return n;
 }
 
+int fft_rb_table_len(int n, int np) { return n / std::gcd(n, np) * np; }
+
 hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th, const double *v,
-                        const int *step, long long stride, const double *m1, const double *m2,
-                        const double *m3, double *t1, double *t2, double *out, hipStream_t s) {
+                        const int *step, long long stride, const double *tab1, const double *tab2,
+                        const double *tab3, double *t1, double *t2, double *out, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_axis_mat, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    for (const void *k : {(const void *)k_syn_pass<32, true>, (const void *)k_syn_pass<16, false>})
+      (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
   const int z1 = rb_split(gr.n3), z2 = gr.n3 / z1;
-  const auto launch = [&](const double *in, const double *thp, const int *st, double *o, const double *M, int O,
-                          int N, int I, int Np, int pn1) {
-    const long long P = (long long)O * I;
-    const size_t lds = ((size_t)Np * N + 16 * (size_t)N) * sizeof(double);
-    hipLaunchKernelGGL(k_axis_mat, dim3((unsigned)((P + 15) / 16)), dim3(256), lds, s, in, thp, st, stride, o, M, O,
-                       N, I, Np, pn1, z1, z2);
+  const auto pass = [&](auto kern, int tp, const double *in, const double *thp, const int *st, double *o,
+                        const double *tab, int n, int np, int O, int I, int pn1) {
+    const int g = std::gcd(n, np), L = n / g * np;
+    const size_t lds = ((size_t)L + (size_t)n * (tp + 1)) * sizeof(double);
+    const int P = O * I;
+    hipLaunchKernelGGL(kern, dim3((P + tp - 1) / tp), dim3(256), lds, s, in, thp, st, stride, o, tab, L, n / g,
+                       np / g, O, n, I, np, pn1, z1, z2);
   };
-  // x pass: [n3][n2][n1] -> [n3][n2][n1'] (Theta V formed on the fly)
-  launch(v, th, step, t1, m1, n3 * n2, n1, 1, gr.n1, 0);
-  // y pass: [n3][n2][n1'] -> [n3][n2'][n1']
-  launch(t1, nullptr, nullptr, t2, m2, n3, n2, gr.n1, gr.n2, 0);
-  // z pass: [n3][n2' n1'] -> permuted [n2'][k2][n1'][k1]
-  launch(t2, nullptr, nullptr, out, m3, 1, n3, gr.n2 * gr.n1, gr.n3, gr.n1);
+  // x: [n3 n2][n1] -> [n3 n2][n1']  (Theta V formed on the fly)
+  pass(k_syn_pass<32, true>, 32, v, th, step, t1, tab1, n1, gr.n1, n3 * n2, 1, 0);
+  // y: [n3][n2][n1'] -> [n3][n2'][n1']  (16 <= n1': one row boundary at most per block)
+  pass(k_syn_pass<16, false>, 16, t1, nullptr, nullptr, t2, tab2, n2, gr.n2, n3, gr.n1, 0);
+  // z: [n3][n2' n1'] -> the k_rb_xz4 order
+  pass(k_syn_pass<16, false>, 16, t2, nullptr, nullptr, out, tab3, n3, gr.n3, 1, gr.n2 * gr.n1, gr.n1);
   return hipGetLastError();
 }
 
@@ -1179,7 +1210,8 @@ hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, con
     const dim3 grid(ncols, g.n2, nk), blk(RB_NW * 64);
     const size_t lds = rb_xz4_lds(g);
 #define LTD_XZ4(a, a1, c, c1) \
-  hipLaunchKernelGGL((k_rb_xz4<a, a1, a / a1, c, c1, c / c1, RB_NW, RB_LZ>), grid, blk, lds, s, g, ka, ncols, thv)
+  hipLaunchKernelGGL((k_rb_xz4<a, a1, a / a1, c, c1, c / c1, RB_NW, rb_lz(Two<c, c1, c / c1>::LPW)>), grid, blk, lds, \
+                     s, g, ka, ncols, thv)
     if (g.n1 == 72 && g.n3 == 72) LTD_XZ4(72, 8, 72, 8);
     else if (g.n1 == 64 && g.n3 == 64) LTD_XZ4(64, 8, 64, 8);
     else if (g.n1 == 16 && g.n3 == 16) LTD_XZ4(16, 4, 16, 4);

@@ -381,26 +381,20 @@ __global__ __launch_bounds__(256) void k_assemble(const StepCtx c) {
 }
 
 // Copies n elements global -> LDS, eight loads in flight per thread.
-__device__ inline void stage_to_lds(double2 *dst, const double2 *src, long long n) {
-  const long long nt = blockDim.x;
-  long long e = threadIdx.x;
-  for (; e + 7 * nt < n; e += 8 * nt) {
-    double2 r[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) r[q] = src[e + q * nt];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) dst[e + q * nt] = r[q];
-  }
-  for (; e < n; e += nt) dst[e] = src[e];
+__device__ __forceinline__ void stage_to_lds(double2 *dst, const double2 *src, long long n) {
+  stage8<double2>((int)n, [&](int e) { return src[e]; }, [&](int e, double2 x) { dst[e] = x; });
 }
 
+// HL / PL: H~(mid) / P~ staged in LDS (compile-time, so that their reads are
+// LDS reads rather than generic ones).
+template <bool HL, bool PL>
 __global__ __launch_bounds__(256) void k_step(const StepCtx c) {
   extern __shared__ double2 sm[];
   const int j = blockIdx.x, k = blockIdx.y;
   const SubDev &S = c.sub[k];
   const int n = c.n_aux;
   const long long n2 = (long long)n * n;
-  const bool hl = c.h_in_lds, pl = c.p_in_lds;
+  constexpr bool hl = HL, pl = PL;
   double2 *Hm = hl ? sm : S.hm;  // (H~(mid) - c0)/r
   double2 *Pl = pl ? sm + n2 : nullptr;
   double2 *vec = sm + (hl ? n2 : 0) + (pl ? n2 : 0);
@@ -413,13 +407,14 @@ __global__ __launch_bounds__(256) void k_step(const StepCtx c) {
   const double cl = c.c_light;
 
   // 1. the assembled (H~(mid) - c0)/r (k_assemble) into LDS; spectral check
-  if (hl) stage_to_lds(Hm, S.hm, n2);
-  if (pl) stage_to_lds(Pl, S.pt, n2);
-  if (j == 0 && threadIdx.x == 0) {
+  if constexpr (HL) stage_to_lds(sm, S.hm, n2);
+  if constexpr (PL) stage_to_lds(sm + n2, S.pt, n2);
+  if (j == 0 && threadIdx.x < 64) {  // one wave: the partials load in parallel, fixed-order sum
     double dev2 = 0.0;
     const int nb = (int)((n2 + 255) / 256);
-    for (int q = 0; q < nb; ++q) dev2 += S.dev[q];
-    if (!(sqrt(dev2) <= S.margin)) latch(c.status, 4);
+    for (int q = threadIdx.x; q < nb; q += 64) dev2 += S.dev[q];
+    dev2 = wave_sum(dev2);
+    if (threadIdx.x == 0 && !(sqrt(dev2) <= S.margin)) latch(c.status, 4);
   }
   __syncthreads();
 
@@ -488,15 +483,23 @@ __global__ __launch_bounds__(256) void k_step(const StepCtx c) {
 
 // Sums the per-state partials in a fixed order, writes the series, advances the step.
 __global__ void k_finalize(const StepCtx c) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int step = *c.step;
+  constexpr int CAP = 2048;
+  __shared__ double sp[CAP];
+  if (blockIdx.x != 0) return;
   const int np = c.n_k * c.n_states;
+  const bool staged = 4 * np <= CAP;
+  if (staged)  // the partials load in parallel; thread 0 sums them in a fixed order
+    for (int e = threadIdx.x; e < 4 * np; e += blockDim.x) sp[e] = c.part[e];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double *pp = staged ? sp : c.part;
+  const int step = *c.step;
   double j1 = 0.0, e1 = 0.0, j0 = 0.0, e0 = 0.0;
   for (int p = 0; p < np; ++p) {
-    j1 += c.part[4 * p + 0];
-    e1 += c.part[4 * p + 1];
-    j0 += c.part[4 * p + 2];
-    e0 += c.part[4 * p + 3];
+    j1 += pp[4 * p + 0];
+    e1 += pp[4 * p + 1];
+    j0 += pp[4 * p + 2];
+    e0 += pp[4 * p + 3];
   }
   if (step == 0) {
     c.j_out[0] = j0;
@@ -524,12 +527,13 @@ __global__ void k_finalize(const StepCtx c) {
 // Per-state partials: part[4p+0] midpoint term, part[4p+1] dt w_n dJ_n/dA_n,
 // part[4p+2] dJ_n/dA_n.
 // ---------------------------------------------------------------------------
+template <bool HL>
 __global__ __launch_bounds__(256) void k_adjoint(const StepCtx c, const AdjCtx ac) {
   extern __shared__ double2 sm[];
   const int j = blockIdx.x, k = blockIdx.y;
   const SubDev &S = c.sub[k];
   const int n = c.n_aux;
-  const bool hl = c.h_in_lds;
+  constexpr bool hl = HL;
   double2 *Hm = hl ? sm : S.work + (long long)j * n * n;
   double2 *vec = hl ? sm + (long long)n * n : sm;
   double2 *v = vec, *mu = vec + n, *ta = vec + 2 * n, *tb = vec + 3 * n, *da = vec + 4 * n;
@@ -816,8 +820,10 @@ int assemble_blocks(int n) { return (int)(((long long)n * n + 255) / 256); }
 
 void subspace_init_attrs() {
   if (g_step_attr) return;
-  (void)hipFuncSetAttribute((const void *)k_step, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  (void)hipFuncSetAttribute((const void *)k_adjoint, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  for (const void *k : {(const void *)k_step<true, true>, (const void *)k_step<true, false>,
+                        (const void *)k_step<false, false>, (const void *)k_adjoint<true>,
+                        (const void *)k_adjoint<false>})
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   g_step_attr = true;
 }
 
@@ -826,8 +832,13 @@ hipError_t launch_step(const StepCtx &c, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble, dim3(assemble_blocks(c.n_aux), c.n_k), dim3(256), 0, s, c);
   hipError_t e0 = hipGetLastError();
   if (e0 != hipSuccess) return e0;
-  hipLaunchKernelGGL(k_step, dim3(c.n_states, c.n_k), dim3(256),
-                     step_lds_bytes(c.n_aux, c.h_in_lds, false, c.p_in_lds), s, c);
+  const size_t lds = step_lds_bytes(c.n_aux, c.h_in_lds, false, c.p_in_lds);
+  if (c.h_in_lds && c.p_in_lds)
+    hipLaunchKernelGGL((k_step<true, true>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c);
+  else if (c.h_in_lds)
+    hipLaunchKernelGGL((k_step<true, false>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c);
+  else
+    hipLaunchKernelGGL((k_step<false, false>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, c);
@@ -836,8 +847,11 @@ hipError_t launch_step(const StepCtx &c, hipStream_t s) {
 
 hipError_t launch_adjoint(const StepCtx &c, const AdjCtx &a, hipStream_t s) {
   subspace_init_attrs();
-  hipLaunchKernelGGL(k_adjoint, dim3(c.n_states, c.n_k), dim3(256), step_lds_bytes(c.n_aux, c.h_in_lds, true), s,
-                     c, a);
+  const size_t lds = step_lds_bytes(c.n_aux, c.h_in_lds, true);
+  if (c.h_in_lds)
+    hipLaunchKernelGGL((k_adjoint<true>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c, a);
+  else
+    hipLaunchKernelGGL((k_adjoint<false>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adjoint_finalize, dim3(1), dim3(64), 0, s, c, a);
