@@ -32,6 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "KS state-steps/s + H-apply MFMA util, FP64 vs mixed/batched at stated dipole err"
+WORKLOADS = {
+    1: "molecule in large cell: 1 k-point, N_G=12000, 2 atoms lmax 8 (162 MT channels + 10 LO each), "
+       "FFT grid 72^3, N_aux=64, N_states=5, dt=0.2",
+    3: "batched k-points: 16 k (4x4x1), N_G 8000..9500 per k, 3 atoms lmax 7 (128 MT channels + 6 LO each), "
+       "FFT grid 64^3, N_aux=80, N_states=20 per k, dt=0.2, all k in one launch per stage",
+}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 STAGES = ["potential", "xz_planes", "y_lines", "mt_blocks", "v_projection", "subspace_step", "map_back"]
@@ -40,6 +46,8 @@ STAGES = ["potential", "xz_planes", "y_lines", "mt_blocks", "v_projection", "sub
 def parse():
     p = argparse.ArgumentParser(description=__doc__)
     p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--config", type=int, choices=[1, 3], default=1,
+                   help="1: the molecule in a large cell (headline); 3: 16 batched k-points")
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--mode", choices=["rebuild", "affine"], default="rebuild")
@@ -55,20 +63,21 @@ def parse():
 
 def stage_bytes(sysd, n, nbx, nbz, rgrid):
     """Algorithmic bytes of one launch of each step stage (read + write of its own
-    inputs and outputs once).  The cached grid image of one column is the box
-    array c[kz][y][kx]: nbz * N2' * nbx complex values on the rebuild grid
-    (N1', N2', N3')."""
+    inputs and outputs once), summed over the k-points.  The cached grid image of
+    one column is the box array c[kz][y][kx]: nbz * N2' * nbx complex values on
+    the rebuild grid (N1', N2', N3')."""
     c16 = 16
     n1, n2, n3 = rgrid
-    slab = nbz * n2 * nbx * n * c16
+    nk = len(sysd.kpts)
+    slab = nbz * n2 * nbx * n * c16 * nk
     ngrid = n1 * n2 * n3
-    ng = sysd.kpts[0].n_g
-    k_ext = ng + sysd.n_a + sysd.n_lo
+    ng = sum(kp.n_g for kp in sysd.kpts)
+    k_ext = ng + nk * (sysd.n_a + sysd.n_lo)
     return {
         "potential": 2 * sysd.n_grid * 8 + ngrid * 8,
         "xz_planes": 2 * slab + ngrid * 8,
         "y_lines": slab + ng * n * c16 + ng * 8,
-        "v_projection": 2 * k_ext * n * c16 + n * n * c16,
+        "v_projection": 2 * k_ext * n * c16 + nk * n * n * c16,
     }
 
 
@@ -93,8 +102,9 @@ def potential_series(sysd, n_total):
     return np.sin(0.05 * np.arange(n_total))
 
 
-def cpu_baseline(sysd, n_steps, mode, series):
-    """The FP64 oracle, timed on the host cores over a bounded number of steps."""
+def cpu_baseline(sysd, n_steps, mode, series, ks):
+    """The FP64 oracle, timed on the host cores over a bounded number of steps of
+    the k-points ks (setup excluded)."""
     import threadpoolctl
 
     from oracle import operators as op
@@ -105,30 +115,33 @@ def cpu_baseline(sysd, n_steps, mode, series):
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cores = max(1, min(cores, 16))
     op._WORKERS = cores
+    t = 0.0
     with threadpoolctl.threadpool_limits(cores):
-        phi, _ = ss.ground_state(sysd, 0)
-        sub = ss.project(sysd, 0, phi)
         a_t, a_mid = pulse_samples(sysd, n_steps)
-        vfn = None
         if mode == "rebuild" and series:
             from synth import td_potential
 
             eps, wfield, wblk = td_potential(sysd)
             s_n = potential_series(sysd, n_steps)
-
-            def vfn(n):
-                return ss.rebuild_v_sub(sysd, 0, phi, vr=sysd.vr + eps * s_n[n] * wfield,
-                                        h=[h + eps * s_n[n] * w for h, w in zip(sysd.h, wblk)])
-        elif mode == "rebuild":
-            def vfn(n):
-                return ss.rebuild_v_sub(sysd, 0, phi)
-        t0 = time.perf_counter()
-        pr.propagate(sub, pr.initial_theta(sysd.n_aux, sysd.n_states), a_t, a_mid, sysd.dt, sysd.occ,
-                     sysd.omega, sysd.c_light, v_sub_fn=vfn, n_steps=n_steps)
-        t = time.perf_counter() - t0
-    return dict(value=sysd.n_states * n_steps / t, unit="state-steps/s", cores=cores, kind="oracle",
+        for k in ks:
+            phi, _ = ss.ground_state(sysd, k)
+            sub = ss.project(sysd, k, phi)
+            vfn = None
+            if mode == "rebuild" and series:
+                def vfn(n, k=k, phi=phi):
+                    return ss.rebuild_v_sub(sysd, k, phi, vr=sysd.vr + eps * s_n[n] * wfield,
+                                            h=[h + eps * s_n[n] * w for h, w in zip(sysd.h, wblk)])
+            elif mode == "rebuild":
+                def vfn(n, k=k, phi=phi):
+                    return ss.rebuild_v_sub(sysd, k, phi)
+            t0 = time.perf_counter()
+            pr.propagate(sub, pr.initial_theta(sysd.n_aux, sysd.n_states), a_t, a_mid, sysd.dt, sysd.occ,
+                         sysd.omega, sysd.c_light, v_sub_fn=vfn, n_steps=n_steps)
+            t += time.perf_counter() - t0
+    kdesc = "the k-point" if len(sysd.kpts) == 1 else f"{len(ks)} of the {len(sysd.kpts)} k-points"
+    return dict(value=len(ks) * sysd.n_states * n_steps / t, unit="state-steps/s", cores=cores, kind="oracle",
                 sample=f"first {n_steps} time steps ({mode}, {'per-step potential' if series else 'one potential'}) "
-                       f"of the same workload, setup excluded; {t:.2f} s")
+                       f"of {kdesc} of the same workload, setup excluded; {t:.2f} s")
 
 
 def main():
@@ -155,21 +168,26 @@ def main():
     from synth import make_system, pulse_samples
 
     dev = torch.device("cuda:0")
-    sysd = make_system(1)
+    sysd = make_system(args.config)
+    nk = len(sysd.kpts)
     lt = ltd.Ltd(sysd, device=dev)
-    # auxiliary basis: Rayleigh-Ritz vectors of the seeded start block, on the GPU
-    phi = ltd.colmajor(sysd.kpts[0].start[:, :sysd.n_aux], dev)
-    lt.ritz_basis(0, phi)
-    lt.project_subspace(0, phi)
+    # auxiliary basis per k: Rayleigh-Ritz vectors of the seeded start block, on the GPU
+    phis = []
+    for k in range(nk):
+        phi = ltd.colmajor(sysd.kpts[k].start[:, :sysd.n_aux], dev)
+        lt.ritz_basis(k, phi)
+        lt.project_subspace(k, phi)
+        phis.append(phi)
+    phi = phis[0]
     emin, emax, dtcr = lt.subspace_info(0)
     mode = ltd.LTD_STEP_REBUILD if args.mode == "rebuild" else ltd.LTD_STEP_AFFINE
     total = args.warmup + args.steps + args.profile_steps
     a_t, a_mid = pulse_samples(sysd, total)
     at = torch.from_numpy(a_t).to(dev)
     am = torch.from_numpy(a_mid).to(dev)
-    th0 = np.zeros((1, sysd.n_states, sysd.n_aux), dtype=np.complex128)
+    th0 = np.zeros((nk, sysd.n_states, sysd.n_aux), dtype=np.complex128)
     for j in range(sysd.n_states):
-        th0[0, j, j] = 1.0
+        th0[:, j, j] = 1.0
     theta = torch.from_numpy(th0).to(dev)
     pot = {}
     series = args.mode == "rebuild" and args.potential == "series"
@@ -201,7 +219,7 @@ def main():
     if status != 0:
         print(f"device status {status} after the timed run", file=sys.stderr)
         return 1
-    value = sysd.n_states * args.steps / (ms / 1e3)
+    value = nk * sysd.n_states * args.steps / (ms / 1e3)
 
     # stage profile (HIP events between stages, eager)
     stage_ms = lt.profile_steps(st, max(1, args.profile_steps))
@@ -245,10 +263,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "molecule in large cell: 1 k-point, N_G=12000, 2 atoms lmax 8 (162 MT channels + "
-                        "10 LO each), FFT grid 72^3, N_aux=64, N_states=5, dt=0.2, "
-                        f"{args.mode} mode" + (", potential handed in per step" if series else "") + ", FP64",
-            "n_g": ng, "n_aux": n, "n_states": sysd.n_states, "grid": list(sysd.grid),
+            "workload": (WORKLOADS[args.config] + f", {args.mode} mode"
+                         + (", potential handed in per step" if series else "") + ", FP64"),
+            "n_k": nk, "n_g": [kp.n_g for kp in sysd.kpts] if nk > 1 else ng, "n_aux": n,
+            "n_states": sysd.n_states, "grid": list(sysd.grid),
             "rebuild_grid": list(rgrid), "mode": args.mode, "potential": args.potential if
             args.mode == "rebuild" else None, "precision": "fp64",
         },
@@ -260,7 +278,8 @@ def main():
         "dmu_final": float(st["dmu"][args.warmup + args.steps].item()),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sysd, args.cpu_steps, args.mode, series)
+        ks = [0] if nk == 1 else [0, 1]
+        out["cpu_baseline"] = cpu_baseline(sysd, args.cpu_steps if nk == 1 else 3, args.mode, series, ks)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -326,26 +326,42 @@ hipError_t launch_impl(int opa, int opb, const ZBatch &b, const ZProb *table, co
 }  // namespace
 
 size_t gemm_plan(ZProb *probs, int nprob, int *total_tiles, int target_blocks, long long max_part_tiles) {
-  int tb = 0, rb = 0;
-  long long part = 0;
+  // Output tiles of every problem; the K split is chosen for the launch as a
+  // whole: the problems whose tiles alone leave the GPU short of target_blocks
+  // split their K dimension by a common factor (at most K-tiles / per of each),
+  // within the partial-tile budget.
+  long long base_all = 0, base_split = 0;
   for (int i = 0; i < nprob; ++i) {
     ZProb &P = probs[i];
     P.tiles_m = (P.m + BM - 1) / BM;
     P.tiles_n = (P.n + BN - 1) / BN;
     if (P.batch < 1) P.batch = 1;
+    base_all += (long long)P.tiles_m * P.tiles_n * P.batch;
+  }
+  const auto per_of = [](int kt) { return kt >= 64 ? 4 : (kt >= 16 ? 4 : 2); };
+  int ks_common = 1;
+  if (base_all > 0 && base_all < target_blocks) {
+    for (int i = 0; i < nprob; ++i) {
+      const ZProb &P = probs[i];
+      const int kt = (P.k + BK - 1) / BK;
+      if (kt >= 4) base_split += (long long)P.tiles_m * P.tiles_n * P.batch;
+    }
+    if (base_split > 0) {
+      ks_common = (int)((target_blocks + base_all - 1) / base_all);
+      const long long cap = max_part_tiles / base_split;
+      if (ks_common > cap) ks_common = (int)(cap > 1 ? cap : 1);
+    }
+  }
+  int tb = 0, rb = 0;
+  long long part = 0;
+  for (int i = 0; i < nprob; ++i) {
+    ZProb &P = probs[i];
     const int base = P.tiles_m * P.tiles_n * P.batch;
     const int kt = (P.k + BK - 1) / BK;
     int ks = 1;
-    if (base > 0 && base < target_blocks && kt >= 4) {
-      // K-tiles per split: 8 when K is deep, fewer for shallow K (latency)
-      const int per = kt >= 64 ? 8 : (kt >= 16 ? 4 : 2);
-      ks = (target_blocks + base - 1) / base;
-      ks = ks < kt / per ? ks : kt / per;
+    if (ks_common > 1 && base > 0 && kt >= 4) {
+      ks = ks_common < kt / per_of(kt) ? ks_common : kt / per_of(kt);
       if (ks < 1) ks = 1;
-    }
-    if (ks > 1 && base > 0 && part + (long long)base * ks > max_part_tiles) {
-      const long long room = (max_part_tiles - part) / base;
-      ks = room > 1 ? (int)room : 1;
     }
     const int kt_per = (kt + ks - 1) / (ks > 0 ? ks : 1);
     P.kchunk = (kt_per > 0 ? kt_per : 1) * BK;

@@ -1,0 +1,130 @@
+"""Batched k-points at the batched workload's size: 16 k-points of a 4x4x1 set
+with ragged N_G (8000..9500), 3 atoms at lmax = 7 with 6 local orbitals each,
+64^3 grid, N_aux = 80, 20 states per k.  Every k is bound in one system, so
+each step stage runs all k in one launch (FFT passes, muffin-tin tables, the
+projection table, the subspace step over (state, k)).
+
+* Projection of every k against the oracle.
+* 60 graph-replayed REBUILD steps (static potential) against the oracle's AFFINE
+  propagation of each k, combined with the k weights (J, E, delta mu, theta).
+* One REBUILD step with a potential that differs from the bound one against the
+  oracle's per-k rebuild of V_sub.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from oracle import propagate as pr
+from oracle import subspace as ss
+from synth import make_system, pulse_samples, td_potential
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def rel_max(x, ref):
+    return float(np.abs(np.asarray(x) - np.asarray(ref)).max() / np.abs(np.asarray(ref)).max())
+
+
+@pytest.fixture(scope="module")
+def w3():
+    import torch
+
+    from paper_2403_04351_amd import ltd
+
+    t0 = time.perf_counter()
+    sys = make_system(3)
+    n = sys.n_aux
+    phis = [np.ascontiguousarray(kp.start[:, :n]) for kp in sys.kpts]
+    subs = []
+    for k in range(len(sys.kpts)):
+        subs.append(ss.project(sys, k, phis[k]))
+        print(f"[w3] oracle projection k={k} ({time.perf_counter() - t0:.1f} s)", flush=True)
+    lt = ltd.Ltd(sys, max_cols=n)
+    for k in range(len(sys.kpts)):
+        lt.project_subspace(k, ltd.colmajor(phis[k], lt.device))
+    torch.cuda.synchronize()
+    print(f"[w3] library bound and projected ({time.perf_counter() - t0:.1f} s)", flush=True)
+    return dict(sys=sys, phis=phis, subs=subs, lt=lt, ltd=ltd, torch=torch)
+
+
+def test_batched_projection_matches_oracle(w3):
+    sys, lt, ltd, subs = w3["sys"], w3["lt"], w3["ltd"], w3["subs"]
+    for k in range(len(sys.kpts)):
+        h0, s, _ = lt.project_subspace(k, ltd.colmajor(w3["phis"][k], lt.device))
+        w3["torch"].cuda.synchronize()
+        assert rel_max(ltd.to_numpy(h0), subs[k]["H0"]) < TOL
+        assert rel_max(ltd.to_numpy(s), subs[k]["S"]) < TOL
+
+
+def _theta0(sys, torch, dev):
+    th0 = pr.initial_theta(sys.n_aux, sys.n_states)
+    nk = len(sys.kpts)
+    return th0, torch.from_numpy(np.ascontiguousarray(np.stack([th0.T] * nk))).to(dev)
+
+
+def test_batched_propagation_matches_oracle(w3):
+    sys, lt, ltd, torch, subs = w3["sys"], w3["lt"], w3["ltd"], w3["torch"], w3["subs"]
+    n_steps = 60
+    a_t, a_mid = pulse_samples(sys, n_steps)
+    th0, theta = _theta0(sys, torch, lt.device)
+    for k in range(len(sys.kpts)):  # rebind (the previous test rebinds every k)
+        lt.project_subspace(k, ltd.colmajor(w3["phis"][k], lt.device))
+    st = lt.propagate(ltd.LTD_STEP_REBUILD, sys.dt, torch.from_numpy(a_t).to(lt.device),
+                      torch.from_numpy(a_mid).to(lt.device), theta, n_steps)
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+    j = np.zeros(n_steps + 1)
+    e = np.zeros(n_steps + 1)
+    th = st["theta"].cpu().numpy()
+    worst = 0.0
+    for k, kp in enumerate(sys.kpts):
+        ref = pr.propagate(subs[k], th0, a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light)
+        j += kp.weight * ref["J"]
+        e += kp.weight * ref["E"]
+        worst = max(worst, rel_max(th[k].T, ref["theta"]))
+    dmu = pr.dipole_change(j, sys.dt, sys.omega)
+    gj, ge, gd = st["j"].cpu().numpy(), st["e"].cpu().numpy(), st["dmu"].cpu().numpy()
+    print(f"batched 16 k, {n_steps} steps: J {rel_max(gj, j):.2e} E {rel_max(ge, e):.2e} "
+          f"dmu {rel_max(gd, dmu):.2e} theta (worst k) {worst:.2e}", flush=True)
+    assert rel_max(gj, j) < TOL
+    assert rel_max(ge, e) < TOL
+    assert worst < TOL
+    assert rel_max(gd, dmu) < 1e-8
+
+
+def test_batched_rebuild_with_new_potential(w3):
+    sys, lt, ltd, torch, subs, phis = w3["sys"], w3["lt"], w3["ltd"], w3["torch"], w3["subs"], w3["phis"]
+    eps, wfield, wblk = td_potential(sys, 1e-2)
+    a_t, a_mid = pulse_samples(sys, 1)
+    th0, theta = _theta0(sys, torch, lt.device)
+    for k in range(len(sys.kpts)):
+        lt.project_subspace(k, ltd.colmajor(phis[k], lt.device))
+    dev = lt.device
+    v1 = torch.from_numpy(np.ascontiguousarray((sys.vr + eps * wfield).ravel())).to(dev)
+    wb = torch.from_numpy(np.concatenate([np.ascontiguousarray(x.T).ravel() for x in wblk])).to(dev)
+    h1 = (lt.h + eps * wb).contiguous()
+    st = lt.propagate(ltd.LTD_STEP_REBUILD, sys.dt, torch.from_numpy(a_t).to(dev), torch.from_numpy(a_mid).to(dev),
+                      theta, 1, v_r_t=v1, h_t=h1)
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+    th = st["theta"].cpu().numpy()
+    j1 = 0.0
+    worst = 0.0
+    t0 = time.perf_counter()
+    for k, kp in enumerate(sys.kpts):
+        vk = ss.rebuild_v_sub(sys, k, phis[k], vr=sys.vr + eps * wfield,
+                              h=[h + eps * w for h, w in zip(sys.h, wblk)])
+        ref = pr.propagate(subs[k], th0, a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light,
+                           v_sub_fn=lambda n, vk=vk: vk, n_steps=1)
+        j1 += kp.weight * ref["J"][1]
+        worst = max(worst, rel_max(th[k].T, ref["theta"]))
+        print(f"[rebuild] oracle k={k} ({time.perf_counter() - t0:.1f} s)", flush=True)
+    gj = st["j"].cpu().numpy()
+    print(f"batched rebuild, new potential: J1 {abs(gj[1] - j1) / abs(j1):.2e} theta (worst k) {worst:.2e}",
+          flush=True)
+    assert abs(gj[1] - j1) < TOL * abs(j1)
+    assert worst < TOL
