@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--mode", choices=["rebuild", "affine"], default="rebuild")
+    p.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                   help="fp32: the per-step rebuild of the potential difference in FP32 (mixed mode)")
     p.add_argument("--potential", choices=["series", "static"], default="series",
                    help="rebuild from a per-step potential series (default) or from one potential")
     p.add_argument("--profile-steps", type=int, default=20)
@@ -61,21 +63,22 @@ def parse():
     return p.parse_args()
 
 
-def stage_bytes(sysd, n, nbx, nbz, rgrid):
+def stage_bytes(sysd, n, nbx, nbz, rgrid, es=16):
     """Algorithmic bytes of one launch of each step stage (read + write of its own
     inputs and outputs once), summed over the k-points.  The cached grid image of
     one column is the box array c[kz][y][kx]: nbz * N2' * nbx complex values on
-    the rebuild grid (N1', N2', N3')."""
+    the rebuild grid (N1', N2', N3'); es bytes per complex value of the slabs
+    (8 for the FP32 residual, whose Theta V is float)."""
     c16 = 16
     n1, n2, n3 = rgrid
     nk = len(sysd.kpts)
-    slab = nbz * n2 * nbx * n * c16 * nk
+    slab = nbz * n2 * nbx * n * es * nk
     ngrid = n1 * n2 * n3
     ng = sum(kp.n_g for kp in sysd.kpts)
     k_ext = ng + nk * (sysd.n_a + sysd.n_lo)
     return {
-        "potential": 2 * sysd.n_grid * 8 + ngrid * 8,
-        "xz_planes": 2 * slab + ngrid * 8,
+        "potential": 2 * sysd.n_grid * 8 + ngrid * es // 2,
+        "xz_planes": 2 * slab + ngrid * es // 2,
         "y_lines": slab + ng * n * c16 + ng * 8,
         "v_projection": 2 * k_ext * n * c16 + nk * n * n * c16,
     }
@@ -100,6 +103,33 @@ def traffic_from_profiles(kernel_file):
 def potential_series(sysd, n_total):
     """s_n, the per-step potential scale of the series V_n = V + eps s_n W."""
     return np.sin(0.05 * np.arange(n_total))
+
+
+def mixed_error(sysd, st, n_steps):
+    """Relative errors of J, J_ind and delta mu of the run (first n_steps) against
+    the FP64 oracle with the same per-step potential (the oracle's V_sub is linear
+    in the potential: V_ref + s_n D, D its rebuild of the perturbation)."""
+    from oracle import propagate as pr
+    from oracle import subspace as ss
+    from synth import pulse_samples, td_potential
+
+    phi, _ = ss.ground_state(sysd, 0)
+    sub = ss.project(sysd, 0, phi)
+    eps, wfield, wblk = td_potential(sysd)
+    v_ref = ss.rebuild_v_sub(sysd, 0, phi)
+    d = ss.rebuild_v_sub(sysd, 0, phi, vr=sysd.vr + eps * wfield,
+                         h=[h + eps * w for h, w in zip(sysd.h, wblk)]) - v_ref
+    s_n = potential_series(sysd, n_steps)
+    a_t, a_mid = pulse_samples(sysd, n_steps)
+    # the GPU run starts from the Ritz basis of the library; the oracle uses its own
+    # Ritz basis of the same start block (the same subspace and states to rounding)
+    ref = pr.propagate(sub, pr.initial_theta(sysd.n_aux, sysd.n_states), a_t, a_mid, sysd.dt, sysd.occ,
+                       sysd.omega, sysd.c_light, v_sub_fn=lambda k: v_ref + s_n[k] * d, n_steps=n_steps)
+    j = st["j"][: n_steps + 1].cpu().numpy()
+    dmu = st["dmu"][: n_steps + 1].cpu().numpy()
+    rel = lambda x, r: float(np.abs(x - r).max() / np.abs(r).max())
+    return dict(steps=n_steps, j=rel(j, ref["J"]), j_ind=rel(j - j[0], ref["J"] - ref["J"][0]),
+                dmu=rel(dmu, ref["dmu"]), against="FP64 oracle, same per-step potential")
 
 
 def cpu_baseline(sysd, n_steps, mode, series, ks):
@@ -170,7 +200,10 @@ def main():
     dev = torch.device("cuda:0")
     sysd = make_system(args.config)
     nk = len(sysd.kpts)
-    lt = ltd.Ltd(sysd, device=dev)
+    from paper_2403_04351_amd import _lib
+
+    prec = _lib.LTD_FP64 if args.precision == "fp64" else _lib.LTD_FP32_RESID
+    lt = ltd.Ltd(sysd, device=dev, precision=prec)
     # auxiliary basis per k: Rayleigh-Ritz vectors of the seeded start block, on the GPU
     phis = []
     for k in range(nk):
@@ -227,7 +260,7 @@ def main():
     rgrid = lt.rebuild_grid()
     nbx = 2 * int(np.abs(sysd.kpts[0].g_int[:, 0]).max()) + 1
     nbz = 2 * int(np.abs(sysd.kpts[0].g_int[:, 2]).max()) + 1
-    sb = stage_bytes(sysd, sysd.n_aux, nbx, nbz, rgrid)
+    sb = stage_bytes(sysd, sysd.n_aux, nbx, nbz, rgrid, 16 if args.precision == "fp64" else 8)
     hbm_stages = {k: v for k, v in prof.items() if k in sb}
     dom = max(hbm_stages, key=hbm_stages.get)
     dom_us = hbm_stages[dom]
@@ -260,15 +293,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": (WORKLOADS[args.config] + f", {args.mode} mode"
-                         + (", potential handed in per step" if series else "") + ", FP64"),
+                         + (", potential handed in per step" if series else "")
+                         + (", FP64" if args.precision == "fp64" else ", FP32 residual rebuild on FP64")),
             "n_k": nk, "n_g": [kp.n_g for kp in sysd.kpts] if nk > 1 else ng, "n_aux": n,
             "n_states": sysd.n_states, "grid": list(sysd.grid),
             "rebuild_grid": list(rgrid), "mode": args.mode, "potential": args.potential if
-            args.mode == "rebuild" else None, "precision": "fp64",
+            args.mode == "rebuild" else None, "precision": args.precision,
         },
         "wall_s": round(wall, 4),
         "stage_us": prof,
@@ -277,6 +311,8 @@ def main():
         "subspace": dict(eps_min=emin, eps_max=emax, dt_cr=dtcr),
         "dmu_final": float(st["dmu"][args.warmup + args.steps].item()),
     }
+    if args.precision == "fp32" and series and nk == 1:
+        out["mixed_error"] = mixed_error(sysd, st, args.warmup + args.steps)
     if not args.no_cpu_baseline:
         ks = [0] if nk == 1 else [0, 1]
         out["cpu_baseline"] = cpu_baseline(sysd, args.cpu_steps if nk == 1 else 3, args.mode, series, ks)

@@ -95,7 +95,7 @@ struct ltd_system {
   size_t ws_need = 0, ws_bound = 0;
   size_t o_tw1, o_tw2, o_tw3, o_thv, o_thv_rb, o_thv_step, o_status, o_part, o_partials;
   size_t o_slab_in, o_slab_out, o_W, o_Y, o_heff, o_tvps, o_proj, o_tmp3, o_eigA, o_eigV, o_eigw;
-  size_t o_stepslab, o_subdev, o_theta_sc, o_k6, o_hstep;
+  size_t o_stepslab, o_subdev, o_theta_sc, o_k6, o_hstep, o_zero32;
   K2Table k2_hs, k2_tvps, k2_step;
   size_t o_k2_hs1, o_k2_hs2, o_k2_tv1, o_k2_tv2, o_k2_st1, o_k2_st2;
   std::vector<ZProb> vstep_tab;
@@ -339,6 +339,11 @@ KSphere sphere_of(const ltd_system *sys, int k) {
   return sp;
 }
 
+// bytes per value of the rebuild cache and step slabs (complex64 for the FP32 residual)
+size_t rb_elem(const ltd_system *sys) {
+  return sys->precision == LTD_FP32_RESID ? sizeof(float2) : sizeof(double2);
+}
+
 Grid grid_of(const ltd_system *sys) {
   Grid g = sys->grid;
   g.tw1 = sys->at<double2>(sys->o_tw1);
@@ -359,16 +364,20 @@ Grid rgrid_of(const ltd_system *sys) {
   return g;
 }
 
+bool resid32(const ltd_system *sys) { return sys->precision == LTD_FP32_RESID; }
+
 // Theta v in the layout of the rebuild step (W on the rebuild grid when it is
-// smaller); v read at v + (*step) * stride when step is not NULL
-ltd_status rebuild_potential(ltd_system *sys, const double *v, const int *step, long long stride, double *out,
-                             hipStream_t s) {
+// smaller); v read at v + (*step) * stride when step is not NULL.  resid: the
+// difference from the reference, W(t) - W_ref or Theta (v - v_ref), in FP32.
+ltd_status rebuild_potential(ltd_system *sys, const double *v, const int *step, long long stride, void *out,
+                             bool resid, hipStream_t s) {
   if (sys->rb_synth) {
     LTD_HIP(fft_rb_synth(rgrid_of(sys), sys->n1, sys->n2, sys->n3, sys->theta, v, step, stride,
                          sys->at<double>(sys->o_M1), sys->at<double>(sys->o_M2), sys->at<double>(sys->o_M3),
-                         sys->at<double>(sys->o_syn1), sys->at<double>(sys->o_syn2), out, s));
+                         sys->at<double>(sys->o_syn1), sys->at<double>(sys->o_syn2), out,
+                         resid ? sys->at<double>(sys->o_thv_rb) : nullptr, resid, s));
   } else {
-    LTD_HIP(fft_rb_thv(grid_of(sys), sys->theta, v, step, stride, out, s));
+    LTD_HIP(fft_rb_thv(grid_of(sys), sys->theta, v, step, stride, out, resid ? sys->v_r : nullptr, resid, s));
   }
   return LTD_OK;
 }
@@ -376,6 +385,7 @@ ltd_status rebuild_potential(ltd_system *sys, const double *v, const int *step, 
 // the blocks the muffin-tin step table reads: a per-step series goes through
 // a fixed copy buffer, one set of blocks is read in place (NULL: the reference)
 const void *k2_source(const ltd_system *sys, const ltd_step_args *a) {
+  if (resid32(sys)) return sys->at<double2>(sys->o_hstep);  // the block difference h(t) - h
   if (!a->h_t) return nullptr;
   return a->h_stride ? static_cast<const void *>(sys->at<double2>(sys->o_hstep)) : a->h_t;
 }
@@ -583,6 +593,7 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
   c.h_in_lds = sys->h_in_lds ? 1 : 0;
   c.p_in_lds = sys->p_in_lds ? 1 : 0;
   c.rebuild = (a->mode == LTD_STEP_REBUILD) ? 1 : 0;
+  c.resid = (c.rebuild && resid32(sys)) ? 1 : 0;
   c.step = a->step;
   c.step_rw = a->step;
   c.a_t = a->a_t;
@@ -623,15 +634,19 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
     LTD_HIP(hipStreamWaitEvent(sys->side, sys->ev_fork, 0));
     sb = sys->side;
   }
-  if (a->h_t && a->h_stride)
+  const bool r32 = resid32(sys);
+  if (a->h_t && (a->h_stride || r32))
     LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), reinterpret_cast<const double2 *>(a->h_t),
-                             sys->blk_elems, host_step >= 0 ? nullptr : a->step, a->h_stride,
-                             host_step >= 0 ? (long long)host_step * a->h_stride : 0, sb));
+                             sys->blk_elems, host_step >= 0 || !a->h_stride ? nullptr : a->step, a->h_stride,
+                             host_step >= 0 ? (long long)host_step * a->h_stride : 0, r32 ? sys->h : nullptr, sb));
+  else if (r32)  // the reference blocks: a zero difference (h - h)
+    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), sys->h, sys->blk_elems, nullptr, 0, 0, sys->h, sb));
   if (fork) {
     LTD_TRY(run_k2(sys, sys->k2_step, n, sb));
     LTD_HIP(hipEventRecord(sys->ev_join, sb));
   }
-  const double *thv = sys->at<double>(sys->o_thv_rb);
+  const void *thv = r32 ? static_cast<const void *>(sys->at<float>(sys->o_zero32))
+                        : static_cast<const void *>(sys->at<double>(sys->o_thv_rb));
   if (a->v_r_t) {
     const double *v = a->v_r_t;
     const int *dstep = nullptr;
@@ -639,7 +654,7 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
       if (host_step >= 0) v += (long long)host_step * a->v_stride;
       else dstep = a->step;
     }
-    LTD_TRY(rebuild_potential(sys, v, dstep, a->v_stride, sys->at<double>(sys->o_thv_step), s));
+    LTD_TRY(rebuild_potential(sys, v, dstep, a->v_stride, sys->at<double>(sys->o_thv_step), r32, s));
     thv = sys->at<double>(sys->o_thv_step);
   }
   LTD_MARK(pf, 0);
@@ -651,15 +666,15 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
       const KHost &kh = sys->kh[k0 + i];
       ka.sph[i] = sphere_of(sys, k0 + i);
       ka.slab_in[i] = sys->at<double2>(kh.o_cache);
-      ka.slab_out[i] = sys->at<double2>(sys->o_stepslab) + (long long)i * slab;
+      ka.slab_out[i] = reinterpret_cast<double2 *>(sys->ws + sys->o_stepslab + (size_t)i * slab * rb_elem(sys));
       ka.out[i].o0 = sys->at<double2>(kh.o_yext);
       ka.out[i].ld0 = kh.k_ext;
     }
     // x/z transforms and the Theta V product per y plane, then y transforms per kz plane
-    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0));
+    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0, r32));
     LTD_MARK(pf, 1);
     for (int i = 0; i < nk; ++i) ka.slab_in[i] = ka.slab_out[i];
-    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1));
+    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1, r32));
     LTD_MARK(pf, 2);
   }
   if (fork) LTD_HIP(hipStreamWaitEvent(s, sys->ev_join, 0));
@@ -737,7 +752,7 @@ const char *ltd_status_string(ltd_status st) {
 ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes, ltd_system **out) {
   if (!d || !ws_bytes || !out) return LTD_EINVAL;
   *out = nullptr;
-  if (precision != LTD_FP64) return LTD_EUNSUPPORTED;
+  if (precision != LTD_FP64 && precision != LTD_FP32_RESID) return LTD_EUNSUPPORTED;
   if (d->n_k < 1 || d->n_atoms < 0 || d->n_aux < 1 || d->n_states < 1 || d->n_states > d->n_aux ||
       d->max_cols < 1)
     return LTD_ESHAPE;
@@ -838,6 +853,11 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     } else {
       sys->rgrid = g;
     }
+    // the FP32 residual runs on the register transforms only
+    if (precision == LTD_FP32_RESID && !fft_rb_fast(sys->rgrid)) {
+      delete sys;
+      return LTD_EUNSUPPORTED;
+    }
   }
   if (fft_plane_lds_bytes(g) > 160 * 1024 || fft_line_lds_bytes(g) > 160 * 1024) {
     delete sys;
@@ -916,8 +936,8 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_eigV = ar.take((size_t)n2 * sizeof(double2));
   sys->o_eigw = ar.take((size_t)n * sizeof(double));
   sys->o_k6 = ar.take((size_t)sys->nb_max * n * sizeof(double2));
-  sys->o_stepslab =
-      ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * fft_rb_slab_values(sys->rgrid) * n * sizeof(double2));
+  sys->o_stepslab = ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * fft_rb_slab_values(sys->rgrid) * n * rb_elem(sys));
+  sys->o_zero32 = resid32(sys) ? ar.take((size_t)sys->ngrid * sizeof(float)) : 0;
   if (sys->rb_synth) {
     const Grid &r = sys->rgrid;
     sys->o_rtw1 = ar.take(r.n1 * sizeof(double2));
@@ -958,7 +978,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     kh.o_work = sys->h_in_lds ? 0 : ar.take((size_t)sys->n_states * n2 * sizeof(double2));
     kh.o_phit = ar.take((size_t)kh.k_ext * n * sizeof(double2));
     kh.o_yext = ar.take((size_t)kh.k_ext * n * sizeof(double2));
-    kh.o_cache = ar.take(fft_rb_slab_values(sys->rgrid) * n * sizeof(double2));
+    kh.o_cache = ar.take(fft_rb_slab_values(sys->rgrid) * n * rb_elem(sys));
   }
   sys->ws_need = ar.off;
   sys->sd.assign(sys->n_k, SubDev{});
@@ -1028,7 +1048,8 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
   std::vector<int> zero(16, 0);
   LTD_HIP(hipMemcpy(sys->ws + sys->o_status, zero.data(), 16 * sizeof(int), hipMemcpyHostToDevice));
   LTD_HIP(launch_thv(sys->at<double>(sys->o_thv), sys->theta, sys->v_r, sys->ngrid, s));
-  LTD_TRY(rebuild_potential(sys, sys->v_r, nullptr, 0, sys->at<double>(sys->o_thv_rb), s));
+  LTD_TRY(rebuild_potential(sys, sys->v_r, nullptr, 0, sys->at<double>(sys->o_thv_rb), false, s));
+  if (resid32(sys)) LTD_HIP(hipMemsetAsync(sys->ws + sys->o_zero32, 0, sys->ngrid * sizeof(float), s));
   // K2 tables of the apply chunk
   double2 *W = sys->at<double2>(sys->o_W), *Y = sys->at<double2>(sys->o_Y);
   const long long yst = (long long)sys->n_loc * sys->chunk;
@@ -1131,7 +1152,7 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
     ka.in[0].c = pe;
     ka.in[0].ldc = kh.k_ext;
     ka.slab_out[0] = sys->at<double2>(kh.o_cache);
-    LTD_HIP(fft_rb_cache(rgrid_of(sys), ka, 1, n, s));
+    LTD_HIP(fft_rb_cache(rgrid_of(sys), ka, 1, n, s, resid32(sys)));
   }
   // outputs in the Phi basis
   if (h0_sub) LTD_HIP(launch_axpby(reinterpret_cast<double2 *>(h0_sub), subs, subs + n2, 1.0, 1.0, n2, s));

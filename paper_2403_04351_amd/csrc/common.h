@@ -26,6 +26,31 @@ __host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -
 __host__ __device__ inline double2 cfma(double2 a, double2 b, double2 c) {  // a*b + c
   return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// Complex element types of the transforms: double2 (FP64) and float2 (FP32).
+template <class T>
+struct CT;
+template <>
+struct CT<double2> {
+  using R = double;
+  __host__ __device__ static double2 mk(double x, double y) { return make_double2(x, y); }
+  __host__ __device__ static double2 from(double2 a) { return a; }
+};
+template <>
+struct CT<float2> {
+  using R = float;
+  __host__ __device__ static float2 mk(float x, float y) { return make_float2(x, y); }
+  __host__ __device__ static float2 from(double2 a) { return make_float2((float)a.x, (float)a.y); }
+};
+__host__ __device__ inline double2 to_d2(double2 a) { return a; }
+__host__ __device__ inline double2 to_d2(float2 a) { return make_double2(a.x, a.y); }
 
 // ----------------------------------------------------------------------------
 // GEMM: C = alpha op(A) op(B) + beta C, complex128, column-major.
@@ -168,13 +193,16 @@ void fft_init_attrs();  // LDS limits of the FFT kernels (call outside graph cap
 // through the x/z transforms and the Theta V product, part 1 reads slab_in out to
 // the sphere (ka.out[k].o0).
 size_t fft_rb_slab_values(const Grid &g);
-hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hipStream_t s);
-hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const double *thv, hipStream_t s,
-                       int part);
+// fp32: the cache and step slabs hold float2 (the FP32 residual); thv is then
+// float, else double; Y is written in FP64 either way.
+hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hipStream_t s, bool fp32);
+hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s,
+                       int part, bool fp32);
 // Theta V of a step in the layout fft_rb_step part 0 reads (ngrid doubles).
-// v is read at v + (*step) * stride when step is not NULL.
+// v is read at v + (*step) * stride when step is not NULL; vref != NULL gives
+// Theta (v - vref); fp32: out is float, else double.
 hipError_t fft_rb_thv(const Grid &g, const double *theta, const double *v, const int *step, long long stride,
-                      double *out, hipStream_t s);
+                      void *out, const double *vref, bool fp32, hipStream_t s);
 // Rebuild length of one axis of length n with box half-width b: the smallest
 // length with a register path that is >= 4 b + 1 (every difference of two box
 // frequencies is then distinct modulo it) and <= n; n itself otherwise.
@@ -188,9 +216,11 @@ bool fft_rb_fast(const Grid &g);
 // passes x, y, z, written in the layout fft_rb_step part 0 reads.
 // t1: n3 * n2 * gr.n1 doubles, t2: n3 * gr.n2 * gr.n1 doubles.
 int fft_rb_table_len(int n, int np);
+// sub != NULL: out = W - sub (same layout); fp32: out is float, else double.
 hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *theta, const double *v,
                         const int *step, long long stride, const double *tab1, const double *tab2,
-                        const double *tab3, double *t1, double *t2, double *out, hipStream_t s);
+                        const double *tab3, double *t1, double *t2, void *out, const double *sub, bool fp32,
+                        hipStream_t s);
 size_t fft_line_lds_bytes(const Grid &g);
 
 }  // namespace ltd

@@ -46,53 +46,32 @@ constexpr double C5_2 = -0.80901699437494742410;  // cos(4 pi/5)
 constexpr double S5_1 = 0.95105651629515357212;   // sin(2 pi/5)
 constexpr double S5_2 = 0.58778525229247312917;   // sin(4 pi/5)
 
-template <int DIR>
-__device__ inline double2 mul_i(double2 a) {  // (DIR i) * a
-  return DIR > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+template <int DIR, class T>
+__device__ inline T mul_i(T a) {  // (DIR i) * a
+  return DIR > 0 ? CT<T>::mk(-a.y, a.x) : CT<T>::mk(a.y, -a.x);
 }
 
-// In-place DFT of length R: y_p = sum_q v_q exp(DIR 2 pi i p q / R).
-template <int R, int DIR>
-__device__ inline void dft_small(double2 *v);
-
-template <>
-__device__ inline void dft_small<2, -1>(double2 *v) {
-  const double2 a = v[0], b = v[1];
-  v[0] = cadd(a, b);
-  v[1] = csub(a, b);
-}
-template <>
-__device__ inline void dft_small<2, 1>(double2 *v) {
-  dft_small<2, -1>(v);
-}
-
-template <int DIR>
-__device__ inline void dft4(double2 &v0, double2 &v1, double2 &v2, double2 &v3) {
-  const double2 a = cadd(v0, v2), b = csub(v0, v2), c = cadd(v1, v3), d = mul_i<DIR>(csub(v1, v3));
+template <int DIR, class T>
+__device__ inline void dft4(T &v0, T &v1, T &v2, T &v3) {
+  const T a = cadd(v0, v2), b = csub(v0, v2), c = cadd(v1, v3), d = mul_i<DIR>(csub(v1, v3));
   v0 = cadd(a, c);
   v2 = csub(a, c);
   v1 = cadd(b, d);
   v3 = csub(b, d);
 }
-template <>
-__device__ inline void dft_small<4, -1>(double2 *v) {
-  dft4<-1>(v[0], v[1], v[2], v[3]);
-}
-template <>
-__device__ inline void dft_small<4, 1>(double2 *v) {
-  dft4<1>(v[0], v[1], v[2], v[3]);
-}
 
-template <int DIR>
-__device__ inline void dft8(double2 *v) {
-  double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-  double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+template <int DIR, class T>
+__device__ inline void dft8(T *v) {
+  using R = typename CT<T>::R;
+  const R h = (R)SQ1_2;
+  T e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  T o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
   dft4<DIR>(e0, e1, e2, e3);
   dft4<DIR>(o0, o1, o2, o3);
   // twiddles w8^p, w8 = exp(DIR i pi/4)
-  const double2 t1 = make_double2(SQ1_2 * (o1.x - DIR * o1.y), SQ1_2 * (o1.y + DIR * o1.x));
-  const double2 t2 = mul_i<DIR>(o2);
-  const double2 t3 = make_double2(SQ1_2 * (-o3.x - DIR * o3.y), SQ1_2 * (-o3.y + DIR * o3.x));
+  const T t1 = CT<T>::mk(h * (o1.x - DIR * o1.y), h * (o1.y + DIR * o1.x));
+  const T t2 = mul_i<DIR>(o2);
+  const T t3 = CT<T>::mk(h * (-o3.x - DIR * o3.y), h * (-o3.y + DIR * o3.x));
   v[0] = cadd(e0, o0);
   v[4] = csub(e0, o0);
   v[1] = cadd(e1, t1);
@@ -102,55 +81,53 @@ __device__ inline void dft8(double2 *v) {
   v[3] = cadd(e3, t3);
   v[7] = csub(e3, t3);
 }
-template <>
-__device__ inline void dft_small<8, -1>(double2 *v) {
-  dft8<-1>(v);
-}
-template <>
-__device__ inline void dft_small<8, 1>(double2 *v) {
-  dft8<1>(v);
-}
 
-template <int DIR>
-__device__ inline void dft3(double2 *v) {
-  const double2 t = cadd(v[1], v[2]);
-  const double2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
-  const double2 u = cscale(mul_i<DIR>(csub(v[1], v[2])), SQ3_2);
+template <int DIR, class T>
+__device__ inline void dft3(T *v) {
+  using R = typename CT<T>::R;
+  const T t = cadd(v[1], v[2]);
+  const T m = CT<T>::mk(v[0].x - (R)0.5 * t.x, v[0].y - (R)0.5 * t.y);
+  const T u = cscale(mul_i<DIR>(csub(v[1], v[2])), (R)SQ3_2);
   v[0] = cadd(v[0], t);
   v[1] = cadd(m, u);
   v[2] = csub(m, u);
 }
-template <>
-__device__ inline void dft_small<3, -1>(double2 *v) {
-  dft3<-1>(v);
-}
-template <>
-__device__ inline void dft_small<3, 1>(double2 *v) {
-  dft3<1>(v);
-}
 
-template <int DIR>
-__device__ inline void dft5(double2 *v) {
-  const double2 a1 = cadd(v[1], v[4]), a2 = cadd(v[2], v[3]);
-  const double2 b1 = csub(v[1], v[4]), b2 = csub(v[2], v[3]);
-  const double2 y0 = cadd(v[0], cadd(a1, a2));
-  const double2 m1 = make_double2(v[0].x + C5_1 * a1.x + C5_2 * a2.x, v[0].y + C5_1 * a1.y + C5_2 * a2.y);
-  const double2 m2 = make_double2(v[0].x + C5_2 * a1.x + C5_1 * a2.x, v[0].y + C5_2 * a1.y + C5_1 * a2.y);
-  const double2 n1 = mul_i<DIR>(make_double2(S5_1 * b1.x + S5_2 * b2.x, S5_1 * b1.y + S5_2 * b2.y));
-  const double2 n2 = mul_i<DIR>(make_double2(S5_2 * b1.x - S5_1 * b2.x, S5_2 * b1.y - S5_1 * b2.y));
+template <int DIR, class T>
+__device__ inline void dft5(T *v) {
+  using R = typename CT<T>::R;
+  const R c1 = (R)C5_1, c2 = (R)C5_2, s1 = (R)S5_1, s2 = (R)S5_2;
+  const T a1 = cadd(v[1], v[4]), a2 = cadd(v[2], v[3]);
+  const T b1 = csub(v[1], v[4]), b2 = csub(v[2], v[3]);
+  const T y0 = cadd(v[0], cadd(a1, a2));
+  const T m1 = CT<T>::mk(v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y);
+  const T m2 = CT<T>::mk(v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y);
+  const T n1 = mul_i<DIR>(CT<T>::mk(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+  const T n2 = mul_i<DIR>(CT<T>::mk(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
   v[0] = y0;
   v[1] = cadd(m1, n1);
   v[4] = csub(m1, n1);
   v[2] = cadd(m2, n2);
   v[3] = csub(m2, n2);
 }
-template <>
-__device__ inline void dft_small<5, -1>(double2 *v) {
-  dft5<-1>(v);
-}
-template <>
-__device__ inline void dft_small<5, 1>(double2 *v) {
-  dft5<1>(v);
+
+// In-place DFT of length R: y_p = sum_q v_q exp(DIR 2 pi i p q / R).
+template <int R, int DIR, class T>
+__device__ inline void dft_small(T *v) {
+  if constexpr (R == 2) {
+    const T a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 3) {
+    dft3<DIR>(v);
+  } else if constexpr (R == 4) {
+    dft4<DIR>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 5) {
+    dft5<DIR>(v);
+  } else {
+    static_assert(R == 8, "radix");
+    dft8<DIR>(v);
+  }
 }
 
 constexpr double C9_1 = 0.76604444311897803520;   // cos(2 pi/9)
@@ -161,24 +138,25 @@ constexpr double C9_4 = -0.93969262078590838405;  // cos(8 pi/9)
 constexpr double S9_4 = 0.34202014332566873304;   // sin(8 pi/9)
 
 // Length 9 as 3 x 3: input q = 3 q1 + q2, output p = p1 + 3 p2.
-template <int DIR>
-__device__ inline void dft9(double2 *v) {
-  double2 a[3][3];
+template <int DIR, class T>
+__device__ inline void dft9(T *v) {
+  using R = typename CT<T>::R;
+  T a[3][3];
 #pragma unroll
   for (int q2 = 0; q2 < 3; ++q2) {
-    double2 t[3] = {v[q2], v[3 + q2], v[6 + q2]};
+    T t[3] = {v[q2], v[3 + q2], v[6 + q2]};
     dft3<DIR>(t);
     a[q2][0] = t[0];
     a[q2][1] = t[1];
     a[q2][2] = t[2];
   }
-  a[1][1] = cmul(a[1][1], make_double2(C9_1, DIR * S9_1));
-  a[1][2] = cmul(a[1][2], make_double2(C9_2, DIR * S9_2));
-  a[2][1] = cmul(a[2][1], make_double2(C9_2, DIR * S9_2));
-  a[2][2] = cmul(a[2][2], make_double2(C9_4, DIR * S9_4));
+  a[1][1] = cmul(a[1][1], CT<T>::mk((R)C9_1, (R)(DIR * S9_1)));
+  a[1][2] = cmul(a[1][2], CT<T>::mk((R)C9_2, (R)(DIR * S9_2)));
+  a[2][1] = cmul(a[2][1], CT<T>::mk((R)C9_2, (R)(DIR * S9_2)));
+  a[2][2] = cmul(a[2][2], CT<T>::mk((R)C9_4, (R)(DIR * S9_4)));
 #pragma unroll
   for (int p1 = 0; p1 < 3; ++p1) {
-    double2 t[3] = {a[0][p1], a[1][p1], a[2][p1]};
+    T t[3] = {a[0][p1], a[1][p1], a[2][p1]};
     dft3<DIR>(t);
     v[p1] = t[0];
     v[p1 + 3] = t[1];
@@ -187,8 +165,8 @@ __device__ inline void dft9(double2 *v) {
 }
 
 // In-register DFT of the lengths the two-factor transforms use.
-template <int R, int DIR>
-__device__ __forceinline__ void dft_reg(double2 *v) {
+template <int R, int DIR, class T>
+__device__ __forceinline__ void dft_reg(T *v) {
   if constexpr (R == 9) dft9<DIR>(v);
   else if constexpr (R == 1) (void)v;
   else dft_small<R, DIR>(v);
@@ -251,16 +229,16 @@ struct LinesTwo {  // lines [0, h) at a0 + l, lines [h, 2h) at a1 + (l - h)
 
 // One Stockham pass of radix R on the lines [l0, l0 + nl) of this wavefront.
 // L, NS: compile-time line length and sub-transform size when L > 0.
-template <int R, int DIR, int L, int NS, class LM>
-__device__ __forceinline__ void fft_stage(double2 *buf, const LM &lm, int l0, int nl, int es, int Lr, int NSr,
-                                 const double2 *tw, int lane) {
+template <int R, int DIR, int L, int NS, class LM, class T>
+__device__ __forceinline__ void fft_stage(T *buf, const LM &lm, int l0, int nl, int es, int Lr, int NSr,
+                                 const T *tw, int lane) {
   constexpr int TPL = Tpl<R>::value;
   const int len = (L > 0) ? L : Lr;
   const int ns = (L > 0) ? NS : NSr;
   const int nb = len / R;
   const int ntask = nl * nb;
   const int twm = len / (ns * R);
-  double2 v[TPL][R];
+  T v[TPL][R];
   int ob[TPL];
 #pragma unroll
   for (int t = 0; t < TPL; ++t) {
@@ -274,9 +252,9 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const LM &lm, int l0, in
       const int tws = twm * k;  // tws * q < len for q < R
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        double2 x = buf[base + (j + q * nb) * es];
+        T x = buf[base + (j + q * nb) * es];
         if (q > 0) {
-          double2 w = tw[tws * q];
+          T w = tw[tws * q];
           if (DIR > 0) w.y = -w.y;
           x = cmul(x, w);
         }
@@ -297,8 +275,8 @@ __device__ __forceinline__ void fft_stage(double2 *buf, const LM &lm, int l0, in
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <int DIR, int L, int S, int NS, class LM>
-__device__ __forceinline__ void fft_stages_ct(double2 *buf, const LM &lm, int l0, int nl, int es, const double2 *tw,
+template <int DIR, int L, int S, int NS, class LM, class T>
+__device__ __forceinline__ void fft_stages_ct(T *buf, const LM &lm, int l0, int nl, int es, const T *tw,
                                      int lane) {
   constexpr Radices f = factor_len(L);
   if constexpr (S < f.n) {
@@ -308,9 +286,9 @@ __device__ __forceinline__ void fft_stages_ct(double2 *buf, const LM &lm, int l0
   }
 }
 
-template <int DIR, class LM>
-__device__ __forceinline__ void fft_stages_rt(double2 *buf, const LM &lm, int l0, int nl, int es, const FftPlan &p,
-                              const double2 *tw, int lane) {
+template <int DIR, class LM, class T>
+__device__ __forceinline__ void fft_stages_rt(T *buf, const LM &lm, int l0, int nl, int es, const FftPlan &p,
+                              const T *tw, int lane) {
   int ns = 1;
   for (int s = 0; s < p.nst; ++s) {
     const int r = p.radix[s];
@@ -327,8 +305,8 @@ __device__ __forceinline__ void fft_stages_rt(double2 *buf, const LM &lm, int l0
 
 // All waves of the block transform `nlines` lines (length L, or p.L when L == 0);
 // ends with a block barrier.
-template <int DIR, int L, class LM>
-__device__ __forceinline__ void fft_block(double2 *buf, const LM &lm, int nlines, int es, const FftPlan &p, const double2 *tw) {
+template <int DIR, int L, class LM, class T>
+__device__ __forceinline__ void fft_block(T *buf, const LM &lm, int nlines, int es, const FftPlan &p, const T *tw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if constexpr (L > 0) {
     constexpr int lpw = lpw_len(L);
@@ -346,8 +324,9 @@ __device__ __forceinline__ void fft_block(double2 *buf, const LM &lm, int nlines
   __syncthreads();
 }
 
-__device__ inline void load_tw(double2 *dst, const double2 *src, int L) {
-  for (int i = threadIdx.x; i < L; i += blockDim.x) dst[i] = src[i];
+template <class T>
+__device__ inline void load_tw(T *dst, const double2 *src, int L) {
+  for (int i = threadIdx.x; i < L; i += blockDim.x) dst[i] = CT<T>::from(src[i]);
 }
 
 // box index of a kx column (x = kx mod n1): kx + bx, or -1 outside the box
@@ -606,31 +585,33 @@ __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKAr
 
 // Setup: sphere coefficients of one kz plane -> inverse y transforms of the box
 // columns -> c[kz][y][kx].  grid (nbz, ncols, nk).
-template <int L2>
+// T: element type of the cache (double2, or float2 for the FP32 residual).
+template <int L2, class T>
 __global__ __launch_bounds__(FFT_NT) void k_rb_cache(const Grid g, const FftKArgs ka, int ncols) {
-  extern __shared__ double2 sm[];
+  extern __shared__ double2 sm_raw[];
+  T *sm = reinterpret_cast<T *>(sm_raw);
   const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
-  const int n1 = g.n1, n2 = L2 > 0 ? L2 : g.n2;
+  const int n2 = L2 > 0 ? L2 : g.n2;
   const int bx = g.bx, nbx = g.nbx;
   const int bp = n2 + 1;
-  double2 *bxc = sm;
-  double2 *tw2 = bxc + nbx * bp;
+  T *bxc = sm;
+  T *tw2 = bxc + nbx * bp;
   load_tw(tw2, g.tw2, n2);
   const KSphere &sp = ka.sph[kk];
   const InvIn in = ka.in[kk];
   const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
-  for (int i = threadIdx.x; i < nbx * bp; i += blockDim.x) bxc[i] = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < nbx * bp; i += blockDim.x) bxc[i] = CT<T>::mk(0, 0);
   __syncthreads();
   for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
     const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
     const int y = xy / g.d1, x = xy - y * g.d1;
     const int yr = y <= g.by ? y : y - g.d2 + n2;  // k_y mod n2
-    bxc[box_of(x, g.d1, bx) * bp + yr] = in.c[(long long)gi + (long long)col * in.ldc];
+    bxc[box_of(x, g.d1, bx) * bp + yr] = CT<T>::from(in.c[(long long)gi + (long long)col * in.ldc]);
   }
   __syncthreads();
   fft_block<1, L2>(bxc, LinesUniform{0, bp}, nbx, 1, g.p2, tw2);
   const long long csz = (long long)g.nbz * n2 * nbx;
-  double2 *out = ka.slab_out[kk] + (long long)col * csz + (long long)pz * n2 * nbx;
+  T *out = reinterpret_cast<T *>(ka.slab_out[kk]) + (long long)col * csz + (long long)pz * n2 * nbx;
   for (int i = threadIdx.x; i < n2 * nbx; i += blockDim.x) {
     const int y = i / nbx, b = i - y * nbx;
     out[i] = bxc[b * bp + y];
@@ -698,22 +679,23 @@ __global__ __launch_bounds__(FFT_NT) void k_rb_xz(const Grid g, const FftKArgs k
 
 // Step: forward y transforms of one kz plane of the box array and the sphere
 // read-out Y[g, col] = (1/N) value.  grid (nbz, ncols, nk).
-template <int L2>
+template <int L2, class T>
 __global__ __launch_bounds__(FFT_NT) void k_rb_y(const Grid g, const FftKArgs ka, int ncols) {
-  extern __shared__ double2 sm[];
+  extern __shared__ double2 sm_raw[];
+  T *sm = reinterpret_cast<T *>(sm_raw);
   const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
   const int n1 = g.n1, n2 = L2 > 0 ? L2 : g.n2;
   const int bx = g.bx, nbx = g.nbx;
   const int bp = n2 + 1;
-  double2 *bxc = sm;
-  double2 *tw2 = bxc + nbx * bp;
+  T *bxc = sm;
+  T *tw2 = bxc + nbx * bp;
   load_tw(tw2, g.tw2, n2);
   const KSphere &sp = ka.sph[kk];
   const FwdOut &fo = ka.out[kk];
   const long long csz = (long long)g.nbz * n2 * nbx;
-  const double2 *src = ka.slab_in[kk] + (long long)col * csz + (long long)pz * n2 * nbx;
-  stage8<double2>(
-      n2 * nbx, [&](int i) { return src[i]; }, [&](int i, double2 x) { bxc[(i % nbx) * bp + i / nbx] = x; });
+  const T *src = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)pz * n2 * nbx;
+  stage8<T>(
+      n2 * nbx, [&](int i) { return src[i]; }, [&](int i, T x) { bxc[(i % nbx) * bp + i / nbx] = x; });
   __syncthreads();
   fft_block<-1, L2>(bxc, LinesUniform{0, bp}, nbx, 1, g.p2, tw2);
   const double inv_n = 1.0 / ((double)n1 * n2 * g.n3);
@@ -722,7 +704,7 @@ __global__ __launch_bounds__(FFT_NT) void k_rb_y(const Grid g, const FftKArgs ka
     const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
     const int yy = xy / g.d1, x = xy - yy * g.d1;
     const int yr = yy <= g.by ? yy : yy - g.d2 + n2;
-    fo.o0[gi + (long long)col * fo.ld0] = cscale(bxc[box_of(x, g.d1, bx) * bp + yr], inv_n);
+    fo.o0[gi + (long long)col * fo.ld0] = cscale(to_d2(bxc[box_of(x, g.d1, bx) * bp + yr]), inv_n);
   }
 }
 
@@ -763,9 +745,9 @@ __device__ __forceinline__ double2 role_twiddle(int role, int n) {
 }
 
 // v[j] *= w^j, j = 1 .. R-1 (powers by repeated products)
-template <int R>
-__device__ __forceinline__ void twiddle_powers(double2 *v, double2 w) {
-  double2 p = w;
+template <int R, class T>
+__device__ __forceinline__ void twiddle_powers(T *v, T w) {
+  T p = w;
 #pragma unroll
   for (int j = 1; j < R; ++j) {
     v[j] = cmul(v[j], p);
@@ -776,40 +758,43 @@ __device__ __forceinline__ void twiddle_powers(double2 *v, double2 w) {
 // Same transforms with NW waves per block: an x row exchanges in place through
 // its own RX slots (value (k1, n2) at slot k1 F2 + n2, odd stride across lanes);
 // the z columns exchange through a per-wave scratch of LZ lines.
-template <int NX, int X1, int X2, int NZ, int Z1, int Z2, int NW, int LZ>
+// T: element type (double2, or float2 for the FP32 residual); thp in its real type.
+template <int NX, int X1, int X2, int NZ, int Z1, int Z2, int NW, int LZ, class T>
 __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs ka, int ncols,
-                                                   const double *__restrict__ thp) {
+                                                   const typename CT<T>::R *__restrict__ thp) {
+  using RT = typename CT<T>::R;
   using TX = Two<NX, X1, X2>;
   using TZ = Two<NZ, Z1, Z2>;
   static_assert(LZ <= TZ::LPW, "z lines per wave");
   constexpr int RX = rb_pitch(NX);
-  extern __shared__ double2 sm[];
+  extern __shared__ double2 sm_raw[];
+  T *sm = reinterpret_cast<T *>(sm_raw);
   const int col = blockIdx.x, y = blockIdx.y, kk = blockIdx.z;
   const int n2 = g.n2, bx = g.bx, nbx = g.nbx, bz = g.bz, nbz = g.nbz;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double2 *R = sm;
-  double2 *scr = sm + nbz * RX + wave * (LZ * TZ::LS);
+  T *R = sm;
+  T *scr = sm + nbz * RX + wave * (LZ * TZ::LS);
   const long long csz = (long long)nbz * n2 * nbx;
   const long long rs = (long long)n2 * nbx;  // kz stride of the box arrays
-  const double2 *in = ka.slab_in[kk] + (long long)col * csz + (long long)y * nbx;
-  double2 *out = ka.slab_out[kk] + (long long)col * csz + (long long)y * nbx;
+  const T *in = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)y * nbx;
+  T *out = reinterpret_cast<T *>(ka.slab_out[kk]) + (long long)col * csz + (long long)y * nbx;
   const int lx = lane / TX::G, rx = lane - lx * TX::G;
   const int lz = lane / TZ::G, rz = lane - lz * TZ::G;
 
   // phase 1: inverse x transforms of the box rows, in place in R
   {
-    const double2 w = cconj(g.tw1[rx < NX ? rx : 0]);
+    const T w = CT<T>::from(cconj(g.tw1[rx < NX ? rx : 0]));
     for (int r0 = wave * TX::LPW; r0 < nbz; r0 += NW * TX::LPW) {
       const int r = r0 + lx;
       const bool on = lx < TX::LPW && r < nbz;
-      double2 *row = R + r * RX;
+      T *row = R + r * RX;
       if (on && rx < X2) {
-        double2 v[X1];
+        T v[X1];
 #pragma unroll
         for (int n1 = 0; n1 < X1; ++n1) {
           const int n = X2 * n1 + rx;
           const int kx = n <= bx ? n : n - NX;
-          v[n1] = (n <= bx || n >= NX - bx) ? in[r * rs + kx + bx] : make_double2(0.0, 0.0);
+          v[n1] = (n <= bx || n >= NX - bx) ? in[r * rs + kx + bx] : CT<T>::mk(0, 0);
         }
         dft_reg<X1, 1>(v);
         twiddle_powers<X1>(v, w);
@@ -818,7 +803,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
       }
       wave_fence();
       if (on && rx < X1) {
-        double2 u[X2];
+        T u[X2];
 #pragma unroll
         for (int q = 0; q < X2; ++q) u[q] = row[rx * X2 + q];
         dft_reg<X2, 1>(u);
@@ -833,18 +818,18 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
 
   // phase 2: z columns, inverse -> product -> forward, in place in the box rows
   {
-    const double2 w = cconj(g.tw3[rz < NZ ? rz : 0]), wc = cconj(w);
+    const T w = CT<T>::from(cconj(g.tw3[rz < NZ ? rz : 0])), wc = cconj(w);
     for (int x0 = wave * LZ; x0 < NX; x0 += NW * LZ) {
       const int x = x0 + lz;
       const bool on = lz < LZ && x < NX;
-      double2 *sl = scr + lz * TZ::LS;
+      T *sl = scr + lz * TZ::LS;
       if (on && rz < Z2) {
-        double2 v[Z1];
+        T v[Z1];
 #pragma unroll
         for (int n1 = 0; n1 < Z1; ++n1) {
           const int n = Z2 * n1 + rz;
           const int row = n <= bz ? n + bz : n - NZ + bz;
-          v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : make_double2(0.0, 0.0);
+          v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : CT<T>::mk(0, 0);
         }
         dft_reg<Z1, 1>(v);
         twiddle_powers<Z1>(v, w);
@@ -853,10 +838,10 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
       }
       wave_fence();
       if (on && rz < Z1) {
-        double t[Z2];
+        RT t[Z2];
 #pragma unroll
         for (int k2 = 0; k2 < Z2; ++k2) t[k2] = thp[(((long long)y * Z2 + k2) * NX + x) * Z1 + rz];
-        double2 u[Z2];
+        T u[Z2];
 #pragma unroll
         for (int q = 0; q < Z2; ++q) u[q] = sl[q * TZ::P + rz];
         dft_reg<Z2, 1>(u);
@@ -870,7 +855,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
       }
       wave_fence();
       if (on && rz < Z2) {
-        double2 v[Z1];
+        T v[Z1];
 #pragma unroll
         for (int a = 0; a < Z1; ++a) v[a] = sl[a * TZ::P + rz];
         dft_reg<Z1, -1>(v);
@@ -887,13 +872,13 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
 
   // phase 3: forward x transforms of the box rows, box columns out
   {
-    const double2 wc = g.tw1[rx < NX ? rx : 0];
+    const T wc = CT<T>::from(g.tw1[rx < NX ? rx : 0]);
     for (int r0 = wave * TX::LPW; r0 < nbz; r0 += NW * TX::LPW) {
       const int r = r0 + lx;
       const bool on = lx < TX::LPW && r < nbz;
-      double2 *row = R + r * RX;
+      T *row = R + r * RX;
       if (on && rx < X1) {
-        double2 u[X2];
+        T u[X2];
 #pragma unroll
         for (int b = 0; b < X2; ++b) u[b] = row[rx + X1 * b];
         dft_reg<X2, -1>(u);
@@ -904,7 +889,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
       }
       wave_fence();
       if (on && rx < X2) {
-        double2 v[X1];
+        T v[X1];
 #pragma unroll
         for (int a = 0; a < X1; ++a) v[a] = row[a * X2 + rx];
         dft_reg<X1, -1>(v);
@@ -927,9 +912,12 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
 // A block takes TP positions p = o I + i (i fastest) and all j'.  perm_n1 > 0:
 // the z pass into the k_rb_xz4 order (O = 1, i = y' N1' + x').
 // LDS: table [L], tile [N][TP+1].
-template <int TP, bool TH>
+// TO: output type (float for the FP32 residual); sub != NULL (z pass): the
+// output is acc - sub[same index] (W(t) - W_ref).
+template <int TP, bool TH, class TO>
 __global__ __launch_bounds__(256) void k_syn_pass(const double *__restrict__ in, const double *__restrict__ th,
-                                                  const int *step, long long stride, double *__restrict__ out,
+                                                  const int *step, long long stride, TO *__restrict__ out,
+                                                  const double *__restrict__ sub,
                                                   const double *__restrict__ tab, int L, int c1, int c2, int O,
                                                   int N, int I, int Np, int perm_n1, int perm_z1, int perm_z2) {
   extern __shared__ double sd[];
@@ -1000,9 +988,10 @@ __global__ __launch_bounds__(256) void k_syn_pass(const double *__restrict__ in,
         const int p = p0 + q, o = p / I, i = p - o * I;
         if (perm_n1 > 0) {
           const int y = i / perm_n1, x = i - y * perm_n1;
-          out[(((long long)y * perm_z2 + jp / perm_z1) * perm_n1 + x) * perm_z1 + jp % perm_z1] = acc[r][c];
+          const long long oi = (((long long)y * perm_z2 + jp / perm_z1) * perm_n1 + x) * perm_z1 + jp % perm_z1;
+          out[oi] = (TO)(sub ? acc[r][c] - sub[oi] : acc[r][c]);
         } else {
-          out[((long long)o * Np + jp) * I + i] = acc[r][c];
+          out[((long long)o * Np + jp) * I + i] = (TO)acc[r][c];
         }
       }
   }
@@ -1011,20 +1000,23 @@ __global__ __launch_bounds__(256) void k_syn_pass(const double *__restrict__ in,
 
 // Theta V in the order k_rb_xz4 reads it: out[((y Z2 + k2) N1 + x) Z1 + k1] for
 // the grid point (z = k1 + Z1 k2, y, x); z1 == 0: the grid order itself.
-__global__ void k_rb_thv(double *__restrict__ out, const double *__restrict__ th, const double *__restrict__ v,
-                         const int *step, long long stride, int n1, int n2, int n3, int z1, int z2) {
+// vref != NULL: Theta (v - vref) (the residual, in TO = float).
+template <class TO>
+__global__ void k_rb_thv(TO *__restrict__ out, const double *__restrict__ th, const double *__restrict__ v,
+                         const double *__restrict__ vref, const int *step, long long stride, int n1, int n2, int n3,
+                         int z1, int z2) {
   const long long ng = (long long)n1 * n2 * n3;
   if (step) v += (long long)(*step) * stride;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < ng; i += (long long)gridDim.x * blockDim.x) {
     if (z1 == 0) {
-      out[i] = th[i] * v[i];
+      out[i] = (TO)(th[i] * (vref ? v[i] - vref[i] : v[i]));
       continue;
     }
     const int x = (int)(i % n1);
     const long long t = i / n1;
     const int y = (int)(t % n2), z = (int)(t / n2);
     const int k1 = z % z1, k2 = z / z1;
-    out[(((long long)y * z2 + k2) * n1 + x) * z1 + k1] = th[i] * v[i];
+    out[(((long long)y * z2 + k2) * n1 + x) * z1 + k1] = (TO)(th[i] * (vref ? v[i] - vref[i] : v[i]));
   }
 }
 
@@ -1055,7 +1047,7 @@ size_t line_lds(const Grid &g, int t, bool vmode) {
   return (size_t)((vmode ? 1 : 2) * g.n3 * (t + 1) + g.n3) * sizeof(double2);
 }
 
-size_t rb_cache_lds(const Grid &g) { return ((size_t)g.nbx * (g.n2 + 1) + g.n2) * sizeof(double2); }
+size_t rb_cache_lds(const Grid &g, size_t es = sizeof(double2)) { return ((size_t)g.nbx * (g.n2 + 1) + g.n2) * es; }
 
 // x columns per z chunk of k_rb_xz: the fewest equal chunks that keep the block
 // within 80 KB of LDS (two blocks per CU), else within the 160 KB of one CU
@@ -1075,18 +1067,19 @@ size_t rb_xz_lds(const Grid &g) {
 
 template <class F>
 void each_plane_kernel(F &&f) {
-  f((const void *)k_rb_cache<0>);
-  f((const void *)k_rb_y<0>);
   f((const void *)k_rb_xz<0, 0>);
 #define LTD_RB(a, c)                            \
-  f((const void *)k_rb_cache<a>);               \
-  f((const void *)k_rb_y<a>);                   \
+  f((const void *)k_rb_cache<a, double2>);      \
+  f((const void *)k_rb_cache<a, float2>);       \
+  f((const void *)k_rb_y<a, double2>);          \
+  f((const void *)k_rb_y<a, float2>);           \
   f((const void *)k_rb_xz<a, c>);
-  LTD_RB(16, 16) LTD_RB(64, 64) LTD_RB(72, 72) LTD_RB(96, 160)
+  LTD_RB(0, 0) LTD_RB(16, 16) LTD_RB(64, 64) LTD_RB(72, 72) LTD_RB(96, 160)
 #undef LTD_RB
-  f((const void *)k_rb_xz4<72, 8, 9, 72, 8, 9, RB_NW, rb_lz(Two<72, 8, 9>::LPW)>);
-  f((const void *)k_rb_xz4<64, 8, 8, 64, 8, 8, RB_NW, rb_lz(Two<64, 8, 8>::LPW)>);
-  f((const void *)k_rb_xz4<16, 4, 4, 16, 4, 4, RB_NW, rb_lz(Two<16, 4, 4>::LPW)>);
+#define LTD_X4(n, f1, T) f((const void *)k_rb_xz4<n, f1, n / f1, n, f1, n / f1, RB_NW, rb_lz(Two<n, f1, n / f1>::LPW), T>);
+  LTD_X4(72, 8, double2) LTD_X4(64, 8, double2) LTD_X4(16, 4, double2)
+  LTD_X4(72, 8, float2) LTD_X4(64, 8, float2) LTD_X4(16, 4, float2)
+#undef LTD_X4
   f((const void *)k_inv_plane<0, 0>);
   f((const void *)k_fwd_plane<0, 0>);
 #define LTD_PL(a, b)                            \
@@ -1135,11 +1128,11 @@ size_t fft_rb_slab_values(const Grid &g) { return (size_t)g.nbz * g.n2 * g.nbx; 
 int rb_split(int n) { return n == 72 ? 8 : n == 64 ? 8 : n == 16 ? 4 : 0; }
 bool rb_fast(const Grid &g) { return rb_split(g.n1) > 0 && rb_split(g.n3) > 0; }
 
-size_t rb_xz4_lds(const Grid &g) {
+size_t rb_xz4_lds(const Grid &g, size_t es = sizeof(double2)) {
   const int f1 = rb_split(g.n3), f2 = g.n3 / f1, gl = f1 > f2 ? f1 : f2, p = (gl % 2) ? gl : gl + 1;
   const int ls = gl * p + ((9 - (gl * p) % 8) % 8);
   const int rx = g.n1 + ((9 - g.n1 % 8) % 8);
-  return ((size_t)g.nbz * rx + (size_t)RB_NW * rb_lz(64 / gl) * ls) * sizeof(double2);
+  return ((size_t)g.nbz * rx + (size_t)RB_NW * rb_lz(64 / gl) * ls) * es;
 }
 
 bool fft_rb_fast(const Grid &g) { return rb_fast(g); }
@@ -1154,45 +1147,61 @@ int fft_rb_table_len(int n, int np) { return n / std::gcd(n, np) * np; }
 
 hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th, const double *v,
                         const int *step, long long stride, const double *tab1, const double *tab2,
-                        const double *tab3, double *t1, double *t2, double *out, hipStream_t s) {
+                        const double *tab3, double *t1, double *t2, void *out, const double *sub, bool fp32,
+                        hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    for (const void *k : {(const void *)k_syn_pass<32, true>, (const void *)k_syn_pass<16, false>})
+    for (const void *k : {(const void *)k_syn_pass<32, true, double>, (const void *)k_syn_pass<16, false, double>,
+                          (const void *)k_syn_pass<16, false, float>})
       (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
   const int z1 = rb_split(gr.n3), z2 = gr.n3 / z1;
-  const auto pass = [&](auto kern, int tp, const double *in, const double *thp, const int *st, double *o,
-                        const double *tab, int n, int np, int O, int I, int pn1) {
+  const auto pass = [&](auto kern, int tp, const double *in, const double *thp, const int *st, auto *o,
+                        const double *sb, const double *tab, int n, int np, int O, int I, int pn1) {
     const int g = std::gcd(n, np), L = n / g * np;
     const size_t lds = ((size_t)L + (size_t)n * (tp + 1)) * sizeof(double);
     const int P = O * I;
-    hipLaunchKernelGGL(kern, dim3((P + tp - 1) / tp), dim3(256), lds, s, in, thp, st, stride, o, tab, L, n / g,
+    hipLaunchKernelGGL(kern, dim3((P + tp - 1) / tp), dim3(256), lds, s, in, thp, st, stride, o, sb, tab, L, n / g,
                        np / g, O, n, I, np, pn1, z1, z2);
   };
   // x: [n3 n2][n1] -> [n3 n2][n1']  (Theta V formed on the fly)
-  pass(k_syn_pass<32, true>, 32, v, th, step, t1, tab1, n1, gr.n1, n3 * n2, 1, 0);
+  pass(k_syn_pass<32, true, double>, 32, v, th, step, t1, nullptr, tab1, n1, gr.n1, n3 * n2, 1, 0);
   // y: [n3][n2][n1'] -> [n3][n2'][n1']  (16 <= n1': one row boundary at most per block)
-  pass(k_syn_pass<16, false>, 16, t1, nullptr, nullptr, t2, tab2, n2, gr.n2, n3, gr.n1, 0);
-  // z: [n3][n2' n1'] -> the k_rb_xz4 order
-  pass(k_syn_pass<16, false>, 16, t2, nullptr, nullptr, out, tab3, n3, gr.n3, 1, gr.n2 * gr.n1, gr.n1);
+  pass(k_syn_pass<16, false, double>, 16, t1, nullptr, nullptr, t2, nullptr, tab2, n2, gr.n2, n3, gr.n1, 0);
+  // z: [n3][n2' n1'] -> the k_rb_xz4 order (minus sub, in FP32 for the residual)
+  if (fp32)
+    pass(k_syn_pass<16, false, float>, 16, t2, nullptr, nullptr, static_cast<float *>(out), sub, tab3, n3, gr.n3, 1,
+         gr.n2 * gr.n1, gr.n1);
+  else
+    pass(k_syn_pass<16, false, double>, 16, t2, nullptr, nullptr, static_cast<double *>(out), sub, tab3, n3, gr.n3, 1,
+         gr.n2 * gr.n1, gr.n1);
   return hipGetLastError();
 }
 
 hipError_t fft_rb_thv(const Grid &g, const double *th, const double *v, const int *step, long long stride,
-                      double *out, hipStream_t s) {
+                      void *out, const double *vref, bool fp32, hipStream_t s) {
   const int z1 = rb_fast(g) ? rb_split(g.n3) : 0, z2 = z1 ? g.n3 / z1 : 0;
   const long long ng = (long long)g.n1 * g.n2 * g.n3;
   const int blocks = (int)std::min<long long>((ng + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_rb_thv, dim3(blocks), dim3(256), 0, s, out, th, v, step, stride, g.n1, g.n2, g.n3, z1, z2);
+  if (fp32)
+    hipLaunchKernelGGL(k_rb_thv<float>, dim3(blocks), dim3(256), 0, s, static_cast<float *>(out), th, v, vref, step,
+                       stride, g.n1, g.n2, g.n3, z1, z2);
+  else
+    hipLaunchKernelGGL(k_rb_thv<double>, dim3(blocks), dim3(256), 0, s, static_cast<double *>(out), th, v, vref, step,
+                       stride, g.n1, g.n2, g.n3, z1, z2);
   return hipGetLastError();
 }
 
-hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hipStream_t s) {
+hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hipStream_t s, bool fp32) {
   set_attrs();
   const dim3 grid(g.nbz, ncols, nk), block(FFT_NT);
-  const size_t lds = rb_cache_lds(g);
-#define LTD_RC(a) hipLaunchKernelGGL((k_rb_cache<a>), grid, block, lds, s, g, ka, ncols)
+  const size_t lds = rb_cache_lds(g, fp32 ? sizeof(float2) : sizeof(double2));
+#define LTD_RC(a)                                                                    \
+  do {                                                                               \
+    if (fp32) hipLaunchKernelGGL((k_rb_cache<a, float2>), grid, block, lds, s, g, ka, ncols); \
+    else hipLaunchKernelGGL((k_rb_cache<a, double2>), grid, block, lds, s, g, ka, ncols);     \
+  } while (0)
   if (g.n2 == 16) LTD_RC(16);
   else if (g.n2 == 64) LTD_RC(64);
   else if (g.n2 == 72) LTD_RC(72);
@@ -1202,26 +1211,34 @@ hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hi
   return hipGetLastError();
 }
 
-hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const double *thv, hipStream_t s,
-                       int part) {
+hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s,
+                       int part, bool fp32) {
   set_attrs();
   const dim3 block(FFT_NT);
   if (part == 0 && rb_fast(g)) {
     const dim3 grid(ncols, g.n2, nk), blk(RB_NW * 64);
-    const size_t lds = rb_xz4_lds(g);
-#define LTD_XZ4(a, a1, c, c1) \
-  hipLaunchKernelGGL((k_rb_xz4<a, a1, a / a1, c, c1, c / c1, RB_NW, rb_lz(Two<c, c1, c / c1>::LPW)>), grid, blk, lds, \
-                     s, g, ka, ncols, thv)
-    if (g.n1 == 72 && g.n3 == 72) LTD_XZ4(72, 8, 72, 8);
-    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ4(64, 8, 64, 8);
-    else if (g.n1 == 16 && g.n3 == 16) LTD_XZ4(16, 4, 16, 4);
+    const size_t lds = rb_xz4_lds(g, fp32 ? sizeof(float2) : sizeof(double2));
+#define LTD_XZ4(a, a1, c, c1, T, RT)                                                                            \
+  hipLaunchKernelGGL((k_rb_xz4<a, a1, a / a1, c, c1, c / c1, RB_NW, rb_lz(Two<c, c1, c / c1>::LPW), T>), grid, blk, \
+                     lds, s, g, ka, ncols, static_cast<const RT *>(thv))
+#define LTD_XZ4P(a, a1, c, c1)                            \
+  do {                                                     \
+    if (fp32) LTD_XZ4(a, a1, c, c1, float2, float);        \
+    else LTD_XZ4(a, a1, c, c1, double2, double);           \
+  } while (0)
+    if (g.n1 == 72 && g.n3 == 72) LTD_XZ4P(72, 8, 72, 8);
+    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ4P(64, 8, 64, 8);
+    else if (g.n1 == 16 && g.n3 == 16) LTD_XZ4P(16, 4, 16, 4);
     else return hipErrorInvalidValue;
+#undef LTD_XZ4P
 #undef LTD_XZ4
   } else if (part == 0) {
+    if (fp32) return hipErrorInvalidValue;  // the FP32 residual needs the register path
     const dim3 grid(ncols, g.n2, nk);
     const size_t lds = rb_xz_lds(g);
     const int xc = rb_xc(g);
-#define LTD_XZ(a, c) hipLaunchKernelGGL((k_rb_xz<a, c>), grid, block, lds, s, g, ka, ncols, xc, thv)
+    const double *thd = static_cast<const double *>(thv);
+#define LTD_XZ(a, c) hipLaunchKernelGGL((k_rb_xz<a, c>), grid, block, lds, s, g, ka, ncols, xc, thd)
     if (g.n1 == 16 && g.n3 == 16) LTD_XZ(16, 16);
     else if (g.n1 == 64 && g.n3 == 64) LTD_XZ(64, 64);
     else if (g.n1 == 72 && g.n3 == 72) LTD_XZ(72, 72);
@@ -1230,8 +1247,12 @@ hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, con
 #undef LTD_XZ
   } else {
     const dim3 grid(g.nbz, ncols, nk);
-    const size_t lds = rb_cache_lds(g);
-#define LTD_RY(a) hipLaunchKernelGGL((k_rb_y<a>), grid, block, lds, s, g, ka, ncols)
+    const size_t lds = rb_cache_lds(g, fp32 ? sizeof(float2) : sizeof(double2));
+#define LTD_RY(a)                                                                 \
+  do {                                                                            \
+    if (fp32) hipLaunchKernelGGL((k_rb_y<a, float2>), grid, block, lds, s, g, ka, ncols); \
+    else hipLaunchKernelGGL((k_rb_y<a, double2>), grid, block, lds, s, g, ka, ncols);     \
+  } while (0)
     if (g.n2 == 16) LTD_RY(16);
     else if (g.n2 == 64) LTD_RY(64);
     else if (g.n2 == 72) LTD_RY(72);

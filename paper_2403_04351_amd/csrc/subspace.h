@@ -37,6 +37,7 @@ struct StepCtx {
   int h_in_lds;
   int p_in_lds;            // P~ also resident in LDS
   int rebuild;
+  int resid;               // rebuilt matrix is the residual V~(t) - V~_ref (FP32 rebuild)
   const int *step;         // device step counter n
   int *step_rw;            // same pointer, advanced by the finaliser
   const double *a_t, *a_mid;
@@ -58,8 +59,9 @@ struct AdjCtx {
 
 // dst[i] = src[off + i], i < n, off = (*step) * stride (step on the device) or
 // host_off when step is NULL.
+// sub != NULL: dst[i] = src[off + i] - sub[i].
 hipError_t launch_copy_step(double2 *dst, const double2 *src, long long n, const int *step, long long stride,
-                            long long host_off, hipStream_t s);
+                            long long host_off, const double2 *sub, hipStream_t s);
 hipError_t launch_copy_rows(double2 *dst, int ldd, const double2 *src, int lds, int rows, int cols, bool zero,
                             hipStream_t s);
 hipError_t launch_herm_split(const double2 *x, int ldx, int n, int nb, double2 *out, hipStream_t s);

@@ -154,10 +154,10 @@ __global__ void k_heff(double2 *out, const double2 *h, const double2 *p, const d
 }
 
 __global__ void k_copy_step(double2 *__restrict__ dst, const double2 *__restrict__ src, long long n,
-                            const int *step, long long stride, long long host_off) {
+                            const int *step, long long stride, long long host_off, const double2 *__restrict__ sub) {
   const long long off = step ? (long long)(*step) * stride : host_off;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    dst[i] = src[off + i];
+    dst[i] = sub ? csub(src[off + i], sub[i]) : src[off + i];
 }
 
 __global__ void k_thv(double *out, const double *th, const double *v, long long n) {
@@ -356,9 +356,10 @@ __global__ __launch_bounds__(256) void k_assemble(const StepCtx c) {
   if (e < n2) {
     const int a = (int)(e % n), b = (int)(e / n);
     double2 vv;
-    if (c.rebuild) {  // Hermitian part of the rebuilt matrix
+    if (c.rebuild) {  // Hermitian part of the rebuilt matrix (plus the reference for a residual)
       const double2 x = S.vt_step[e], y = S.vt_step[b + (long long)a * n];
       vv = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+      if (c.resid) vv = cadd(vv, S.vt_ref[e]);
     } else {
       vv = S.vt_ref[e];
     }
@@ -583,6 +584,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepCtx c, const AdjCtx a
     if (c.rebuild) {
       const double2 x = S.vt_step[e], y = S.vt_step[b + (long long)a * n];
       vv2 = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+      if (c.resid) vv2 = cadd(vv2, S.vt_ref[e]);
     } else {
       vv2 = S.vt_ref[e];
     }
@@ -772,10 +774,10 @@ hipError_t launch_heff(double2 *out, const double2 *h, const double2 *p, const d
 }
 
 hipError_t launch_copy_step(double2 *dst, const double2 *src, long long n, const int *step, long long stride,
-                            long long host_off, hipStream_t s) {
+                            long long host_off, const double2 *sub, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int blocks = (int)std::min<long long>((n + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_copy_step, dim3(blocks), dim3(256), 0, s, dst, src, n, step, stride, host_off);
+  hipLaunchKernelGGL(k_copy_step, dim3(blocks), dim3(256), 0, s, dst, src, n, step, stride, host_off, sub);
   return hipGetLastError();
 }
 

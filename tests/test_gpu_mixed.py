@@ -1,0 +1,133 @@
+"""Mixed precision (FP32 residual) against the FP64 oracle.
+
+The FP32 mode rebuilds only the difference of the step's potential from the
+bound reference, V_sub(t) = V_sub,ref + V_sub[V(t) - V_ref, h(t) - h_ref], with
+the interstitial transforms of the difference in complex64; the reference part,
+the projection, the Cholesky factor, the exponential and the observables stay
+FP64.  The errors are stated per output and bounded by the 1e-6 relative
+dipole/current target.
+
+* Static potential: the residual is exactly zero, so FP32 mode equals the FP64
+  oracle to 1e-10.
+* A potential that changes every step (V + eps s_n W, h + eps s_n w), tiny
+  system on its own grid and on a larger grid rebuilt on a smaller one.
+* The molecule workload at full size, 1000 graph-replayed steps.  The oracle's
+  V_sub is linear in the potential, so V_sub(t) = V_ref + s_n D with D its own
+  rebuild of the perturbation.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import propagate as pr
+from oracle import subspace as ss
+from synth import make_system, pulse_samples, td_potential
+
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = 1e-6
+
+
+def rel_max(x, ref):
+    return float(np.abs(np.asarray(x) - np.asarray(ref)).max() / np.abs(np.asarray(ref)).max())
+
+
+def _bind(sys, phi, precision, max_cols=None):
+    import torch
+
+    from paper_2403_04351_amd import _lib, ltd
+
+    lt = ltd.Ltd(sys, max_cols=max_cols, precision=getattr(_lib, precision))
+    lt.project_subspace(0, ltd.colmajor(phi, lt.device))
+    return lt, ltd, torch
+
+
+def _series(sys, lt, torch, s_n, eps_v=1e-2):
+    eps, wfield, wblk = td_potential(sys, eps_v)
+    dev = lt.device
+    v0 = torch.from_numpy(np.ascontiguousarray(sys.vr.ravel())).to(dev)
+    w0 = torch.from_numpy(np.ascontiguousarray(wfield.ravel())).to(dev)
+    wb = torch.from_numpy(np.concatenate([np.ascontiguousarray(x.T).ravel() for x in wblk])).to(dev)
+    sd = torch.from_numpy(np.asarray(s_n, dtype=np.float64)).to(dev)[:, None]
+    vs = (v0[None, :] + eps * sd * w0[None, :]).contiguous()
+    hs = (lt.h[None, :] + eps * sd * wb[None, :]).contiguous()
+    return dict(v_r_t=vs, h_t=hs, v_stride=vs.shape[1], h_stride=hs.shape[1]), (eps, wfield, wblk)
+
+
+def _run(lt, ltd, torch, sys, a_t, a_mid, n, pot):
+    th0 = pr.initial_theta(sys.n_aux, sys.n_states)
+    theta = torch.from_numpy(np.ascontiguousarray(th0.T)[None]).to(lt.device)
+    st = lt.propagate(ltd.LTD_STEP_REBUILD, sys.dt, torch.from_numpy(a_t).to(lt.device),
+                      torch.from_numpy(a_mid).to(lt.device), theta, n, **pot)
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+    return st, th0
+
+
+def test_fp32_residual_static_potential_equals_fp64_oracle():
+    sys = make_system(0)
+    phi, _ = ss.ground_state(sys, 0)
+    sub = ss.project(sys, 0, phi)
+    lt, ltd, torch = _bind(sys, phi, "LTD_FP32_RESID")
+    n = 40
+    a_t, a_mid = pulse_samples(sys, n)
+    st, th0 = _run(lt, ltd, torch, sys, a_t, a_mid, n, {})
+    ref = pr.propagate(sub, th0, a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light)
+    assert rel_max(st["j"].cpu().numpy(), ref["J"]) < 1e-10
+    assert rel_max(st["theta"][0].cpu().numpy().T, ref["theta"]) < 1e-10
+
+
+@pytest.mark.parametrize("grid", [None, (64, 64, 64)], ids=["grid16", "grid64_rebuilt_on_16"])
+def test_fp32_residual_potential_series(grid):
+    sys = make_system(0, **({} if grid is None else dict(grid=grid)))
+    phi, _ = ss.ground_state(sys, 0)
+    sub = ss.project(sys, 0, phi)
+    lt, ltd, torch = _bind(sys, phi, "LTD_FP32_RESID")
+    n = 100
+    a_t, a_mid = pulse_samples(sys, n)
+    s_n = a_mid / np.abs(a_mid).max()
+    pot, (eps, wfield, wblk) = _series(sys, lt, torch, s_n)
+    st, th0 = _run(lt, ltd, torch, sys, a_t, a_mid, n, pot)
+
+    def vfn(k):
+        return ss.rebuild_v_sub(sys, 0, phi, vr=sys.vr + eps * s_n[k] * wfield,
+                                h=[h + eps * s_n[k] * w for h, w in zip(sys.h, wblk)])
+
+    ref = pr.propagate(sub, th0, a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light, v_sub_fn=vfn)
+    j, dmu = st["j"].cpu().numpy(), st["dmu"].cpu().numpy()
+    ej, ed = rel_max(j, ref["J"]), rel_max(dmu, ref["dmu"])
+    ee = rel_max(st["e"].cpu().numpy(), ref["E"])
+    jr = ref["J"] - ref["J"][0]
+    eji = rel_max(j - j[0], jr)
+    print(f"FP32 residual {grid}: J {ej:.2e} J_ind {eji:.2e} E {ee:.2e} dmu {ed:.2e}", flush=True)
+    assert ed < MIXED_TOL and eji < MIXED_TOL and ej < MIXED_TOL and ee < MIXED_TOL
+
+
+def test_fp32_residual_full_size_1000_steps():
+    sys = make_system(1)
+    phi, _ = ss.ground_state(sys, 0)
+    sub = ss.project(sys, 0, phi)
+    eps, wfield, wblk = td_potential(sys, 1e-2)
+    v_ref = ss.rebuild_v_sub(sys, 0, phi)
+    d = ss.rebuild_v_sub(sys, 0, phi, vr=sys.vr + eps * wfield, h=[h + eps * w for h, w in zip(sys.h, wblk)]) - v_ref
+    print("[mixed full size] oracle subspace and perturbation rebuilt", flush=True)
+    n = sys.n_steps
+    a_t, a_mid = pulse_samples(sys, n)
+    s_n = np.sin(0.05 * np.arange(n))
+    ref = pr.propagate(sub, pr.initial_theta(sys.n_aux, sys.n_states), a_t, a_mid, sys.dt, sys.occ, sys.omega,
+                       sys.c_light, v_sub_fn=lambda k: v_ref + s_n[k] * d)
+    jr = ref["J"] - ref["J"][0]
+    errs = {}
+    for prec in ("LTD_FP64", "LTD_FP32_RESID"):
+        lt, ltd, torch = _bind(sys, phi, prec, max_cols=64)
+        pot, _ = _series(sys, lt, torch, s_n)
+        st, _ = _run(lt, ltd, torch, sys, a_t, a_mid, n, pot)
+        j, dmu = st["j"].cpu().numpy(), st["dmu"].cpu().numpy()
+        errs[prec] = (rel_max(j, ref["J"]), rel_max(j - j[0], jr), rel_max(dmu, ref["dmu"]),
+                      rel_max(st["theta"][0].cpu().numpy().T, ref["theta"]))
+        print(f"[mixed full size] {prec}: J {errs[prec][0]:.2e} J_ind {errs[prec][1]:.2e} "
+              f"dmu {errs[prec][2]:.2e} theta {errs[prec][3]:.2e}", flush=True)
+        del lt
+    assert errs["LTD_FP64"][0] < 1e-10 and errs["LTD_FP64"][3] < 1e-10
+    assert errs["LTD_FP64"][2] < 1e-8
+    assert max(errs["LTD_FP32_RESID"][:3]) < MIXED_TOL
