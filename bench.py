@@ -84,9 +84,9 @@ def stage_bytes(sysd, n, nbx, nbz, rgrid, es=16):
     }
 
 
-def traffic_from_profiles(kernel_file):
+def traffic_from_profiles(kernel_file, stage, precision):
     """HBM traffic of the dominant kernel from committed rocprofv3 counter runs,
-    valid only while the kernel source is unchanged."""
+    valid only for the same stage and precision while the kernel source is unchanged."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -94,6 +94,8 @@ def traffic_from_profiles(kernel_file):
         rec = json.load(open(path))
         src = open(os.path.join(ROOT, "paper_2403_04351_amd", "csrc", kernel_file), "rb").read()
         if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        if rec.get("stage") != stage or rec.get("precision", "fp64") != precision:
             return None
         return rec.get("bytes_per_launch")
     except Exception:
@@ -267,7 +269,7 @@ def main():
     achieved = sb[dom] / (dom_us * 1e-6) / 1e9
     kernel_file = "fft.hip" if dom in ("potential", "xz_planes", "y_lines") else "api.hip"
     roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(kernel_file),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(kernel_file, dom, args.precision),
                     bytes_per_launch=sb[dom], avg_launch_us=dom_us)
 
     # H-apply MFMA rate: the muffin-tin GEMMs of one apply at n = N_aux
