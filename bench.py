@@ -215,6 +215,7 @@ def main():
         phis.append(phi)
     phi = phis[0]
     emin, emax, dtcr = lt.subspace_info(0)
+    tuned = lt.autotune() if args.mode == "rebuild" else None
     mode = ltd.LTD_STEP_REBUILD if args.mode == "rebuild" else ltd.LTD_STEP_AFFINE
     total = args.warmup + args.steps + args.profile_steps
     a_t, a_mid = pulse_samples(sysd, total)
@@ -309,6 +310,7 @@ def main():
         "wall_s": round(wall, 4),
         "stage_us": prof,
         "roofline": roofline,
+        "tuning": tuned,
         "h_apply": h_apply,
         "subspace": dict(eps_min=emin, eps_max=emax, dt_cr=dtcr),
         "dmu_final": float(st["dmu"][args.warmup + args.steps].item()),

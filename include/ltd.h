@@ -148,6 +148,23 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
  * form the auxiliary basis (Sec. 2.2, Eq. (11)).  Synchronises `stream`. */
 ltd_status ltd_ritz_basis(ltd_system *sys, int k, void *x, int ldx, double *eps, void *stream);
 
+/* Tuner of the per-step rebuild's launch shapes (batched k-points: tiles from
+ * an autotuner, the survey's extension 2): times, on the bound subspaces, every
+ * launch shape of the x/z transform kernel (waves per block, z columns per wave)
+ * and four block targets (256, 512, 1024, 2048) of the K split of the
+ * projection GEMM, and keeps the fastest of each for the following steps
+ * (results do not depend on the shape; the split changes the summation order
+ * only).  choice (host, 2 ints): the shape index and the block target chosen;
+ * times_us (host, optional): the timings, shapes first.  Every k-point must be
+ * bound.  Synchronises `stream`; invalidates a captured step graph. */
+ltd_status ltd_autotune(ltd_system *sys, int *choice, double *times_us, void *stream);
+
+/* Sets the two tuned choices directly (host, 2 ints: x/z launch-shape index in
+ * [0, number of shapes), projection block target in [64, 8192]), e.g. to reuse
+ * a tuning result saved from an earlier run.  LTD_EINVAL for values outside
+ * those ranges.  Invalidates a captured step graph. */
+ltd_status ltd_set_tuning(ltd_system *sys, const int *choice);
+
 /* Host read-out of the FFT lengths of the per-step rebuild (lengths[3], host):
  * the smallest supported lengths >= 4 b_i + 1 (b_i the largest |g_i| of the
  * G+k sets) and <= the grid's, so that every difference of two G-box

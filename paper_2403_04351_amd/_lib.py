@@ -31,7 +31,7 @@ EXPORTED = [
     "ltd_apply_HS", "ltd_project_subspace", "ltd_ritz_basis", "ltd_subspace_info",
     "ltd_propagate_step", "ltd_propagate", "ltd_propagate_step_adjoint", "ltd_knot_samples",
     "ltd_knot_gradient", "ltd_chebyshev_coefficients", "ltd_profile_steps", "ltd_profile_apply",
-    "ltd_rebuild_grid",
+    "ltd_rebuild_grid", "ltd_autotune", "ltd_set_tuning",
 ]
 LTD_PROFILE_STAGES = 8
 
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
     lib.ltd_ritz_basis.argtypes = [vp, ip, vp, ip, vp, vp]
     lib.ltd_subspace_info.argtypes = [vp, ip, dp, dp, dp]
     lib.ltd_rebuild_grid.argtypes = [vp, C.POINTER(ip)]
+    lib.ltd_autotune.argtypes = [vp, C.POINTER(ip), dp, vp]
+    lib.ltd_set_tuning.argtypes = [vp, C.POINTER(ip)]
     lib.ltd_propagate_step.argtypes = [vp, C.POINTER(StepArgs), vp]
     lib.ltd_propagate.argtypes = [vp, C.POINTER(StepArgs), ip, vp]
     lib.ltd_propagate_step_adjoint.argtypes = [vp, C.POINTER(AdjointArgs), vp]

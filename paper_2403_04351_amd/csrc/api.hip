@@ -83,6 +83,8 @@ struct ltd_system {
   Grid grid{};
   Grid rgrid{};
   bool rb_synth = false;
+  int rb_variant = 0;      // launch shape of the x/z rebuild kernel (tuned)
+  int vproj_target = 512;  // block target of the projection GEMM's K split (tuned)
   // side stream of the rebuild: the muffin-tin branch runs beside the FFT chain
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -577,7 +579,7 @@ ltd_status build_step_tables(ltd_system *sys) {
   const size_t cap = (size_t)4 * sys->n_atoms * sys->n_k * sizeof(ZProb) + 1024;
   LTD_TRY(upload_k2(sys, p1, p2, sys->k2_step, sys->o_k2_st1, sys->o_k2_st2, cap));
   int tt = 0;
-  gemm_plan(pv.data(), (int)pv.size(), &tt, 512, PART_TILES);
+  gemm_plan(pv.data(), (int)pv.size(), &tt, sys->vproj_target, PART_TILES);
   sys->vstep_tab = pv;
   sys->vstep_tiles = tt;
   LTD_HIP(hipMemcpy(sys->ws + sys->o_vstep_tab, pv.data(), pv.size() * sizeof(ZProb), hipMemcpyHostToDevice));
@@ -671,10 +673,10 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
       ka.out[i].ld0 = kh.k_ext;
     }
     // x/z transforms and the Theta V product per y plane, then y transforms per kz plane
-    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0, r32));
+    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0, r32, sys->rb_variant));
     LTD_MARK(pf, 1);
     for (int i = 0; i < nk; ++i) ka.slab_in[i] = ka.slab_out[i];
-    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1, r32));
+    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1, r32, 0));
     LTD_MARK(pf, 2);
   }
   if (fork) LTD_HIP(hipStreamWaitEvent(s, sys->ev_join, 0));
@@ -1237,6 +1239,97 @@ ltd_status ltd_ritz_basis(ltd_system *sys, int k, void *x, int ldx, double *eps,
   LTD_HIP(hipStreamSynchronize(s));
   // the k-point's slots were overwritten: the previous binding (if any) is gone
   if (was_bound) kh.bound = false;
+  sys->gvalid = false;
+  return LTD_OK;
+}
+
+ltd_status ltd_autotune(ltd_system *sys, int *choice, double *times_us, void *stream) {
+  if (!sys || !choice) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  for (int k = 0; k < sys->n_k; ++k)
+    if (!sys->kh[k].bound) return LTD_ESTATE;
+  hipStream_t s = S(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  LTD_HIP(hipEventCreate(&e0));
+  LTD_HIP(hipEventCreate(&e1));
+  constexpr int REPS = 5;
+  const auto timed = [&](auto &&launch, double *us) -> ltd_status {
+    LTD_TRY(launch());  // warm-up
+    LTD_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < REPS; ++r) LTD_TRY(launch());
+    LTD_HIP(hipEventRecord(e1, s));
+    LTD_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    LTD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *us = 1e3 * ms / REPS;
+    return LTD_OK;
+  };
+  ltd_status st = LTD_OK;
+  int ti = 0;
+  // 1. launch shape of the x/z rebuild kernel, on the cached grid images of the
+  //    first k-points and the reference potential
+  const Grid g = rgrid_of(sys);
+  const bool r32 = resid32(sys);
+  const int n = sys->n_aux, nk = std::min(FFT_MAXK, sys->n_k);
+  FftKArgs ka{};
+  for (int i = 0; i < nk; ++i) {
+    ka.sph[i] = sphere_of(sys, i);
+    ka.slab_in[i] = sys->at<double2>(sys->kh[i].o_cache);
+    ka.slab_out[i] = reinterpret_cast<double2 *>(sys->ws + sys->o_stepslab +
+                                                 (size_t)i * fft_rb_slab_values(g) * n * rb_elem(sys));
+  }
+  const void *thv = r32 ? static_cast<const void *>(sys->at<float>(sys->o_zero32))
+                        : static_cast<const void *>(sys->at<double>(sys->o_thv_rb));
+  int best_v = 0;
+  double best_t = 1e300;
+  for (int v = 0; v < fft_rb_variants() && st == LTD_OK; ++v) {
+    double us = 0.0;
+    st = timed([&]() -> ltd_status {
+      LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0, r32, v));
+      return LTD_OK;
+    }, &us);
+    if (times_us) times_us[ti++] = us;
+    if (us < best_t) best_t = us, best_v = v;
+  }
+  // 2. block target of the projection GEMM's K split
+  const int targets[4] = {256, 512, 1024, 2048};
+  int best_g = sys->vproj_target;
+  best_t = 1e300;
+  for (int q = 0; q < 4 && st == LTD_OK; ++q) {
+    sys->vproj_target = targets[q];
+    st = build_step_tables(sys);
+    if (st != LTD_OK) break;
+    double us = 0.0;
+    st = timed([&]() -> ltd_status {
+      LTD_HIP(gemm_launch_table(OP_C, OP_N, sys->at<ZProb>(sys->o_vstep_tab), sys->vstep_tab.data(),
+                                (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_partials), 0,
+                                s));
+      return LTD_OK;
+    }, &us);
+    if (times_us) times_us[ti++] = us;
+    if (us < best_t) best_t = us, best_g = targets[q];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  LTD_TRY(st);
+  sys->vproj_target = best_g;
+  LTD_TRY(build_step_tables(sys));
+  sys->rb_variant = best_v;
+  sys->gvalid = false;  // a captured step graph holds the previous shapes
+  choice[0] = best_v;
+  choice[1] = best_g;
+  return LTD_OK;
+}
+
+ltd_status ltd_set_tuning(ltd_system *sys, const int *choice) {
+  if (!sys || !choice) return LTD_EINVAL;
+  if (choice[0] < 0 || choice[0] >= fft_rb_variants()) return LTD_EINVAL;
+  if (choice[1] < 64 || choice[1] > 8192) return LTD_EINVAL;
+  sys->rb_variant = choice[0];
+  if (choice[1] != sys->vproj_target) {
+    sys->vproj_target = choice[1];
+    if (sys->ws) LTD_TRY(build_step_tables(sys));
+  }
   sys->gvalid = false;
   return LTD_OK;
 }

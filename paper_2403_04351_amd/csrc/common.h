@@ -196,8 +196,11 @@ size_t fft_rb_slab_values(const Grid &g);
 // fp32: the cache and step slabs hold float2 (the FP32 residual); thv is then
 // float, else double; Y is written in FP64 either way.
 hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hipStream_t s, bool fp32);
+// variant: launch shape of the part-0 kernel, 0 .. fft_rb_variants() - 1 (the
+// arithmetic per value is the same for every shape).
 hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s,
-                       int part, bool fp32);
+                       int part, bool fp32, int variant);
+int fft_rb_variants();
 // Theta V of a step in the layout fft_rb_step part 0 reads (ngrid doubles).
 // v is read at v + (*step) * stride when step is not NULL; vref != NULL gives
 // Theta (v - vref); fp32: out is float, else double.

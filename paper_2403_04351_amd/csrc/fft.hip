@@ -730,7 +730,6 @@ struct Two {
   static constexpr int LS = G * P + ((9 - (G * P) % 8) % 8);  // line stride, = 1 mod 8
 };
 
-constexpr int RB_NW = 4;  // waves per block of k_rb_xz4
 // z columns per wave and pass of k_rb_xz4: up to 8, as many lines as fit a wave
 constexpr int rb_lz(int lpw) { return lpw < 8 ? lpw : 8; }
 constexpr int rb_pitch(int n) { return n + ((9 - n % 8) % 8); }  // >= n, = 1 mod 8
@@ -1065,6 +1064,42 @@ size_t rb_xz_lds(const Grid &g) {
   return ((size_t)g.nbz * (g.n1 + 1) + (size_t)g.n3 * (rb_xc(g) + 1) + g.n1 + g.n3) * sizeof(double2);
 }
 
+// Launch shapes of k_rb_xz4 (waves per block, z columns per wave), the
+// candidates of the tuner: 0 = (4, LZ), 1 = (2, LZ), 2 = (4, LZ / 2), LZ as rb_lz.
+constexpr int RB_VARIANTS = 3;
+constexpr int rb_nw_of(int v) { return v == 1 ? 2 : 4; }
+template <int N, int F1>
+constexpr int rb_lz_of(int v) {
+  return v == 2 ? (rb_lz(Two<N, F1, N / F1>::LPW) / 2 > 0 ? rb_lz(Two<N, F1, N / F1>::LPW) / 2 : 1)
+                : rb_lz(Two<N, F1, N / F1>::LPW);
+}
+
+template <int N, int F1, class T, class F>
+void reg_xz4(F &&f) {
+  f((const void *)k_rb_xz4<N, F1, N / F1, N, F1, N / F1, rb_nw_of(0), rb_lz_of<N, F1>(0), T>);
+  f((const void *)k_rb_xz4<N, F1, N / F1, N, F1, N / F1, rb_nw_of(1), rb_lz_of<N, F1>(1), T>);
+  f((const void *)k_rb_xz4<N, F1, N / F1, N, F1, N / F1, rb_nw_of(2), rb_lz_of<N, F1>(2), T>);
+}
+
+template <int N, int F1, class T>
+void launch_xz4(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s, int v) {
+  using TZ = Two<N, F1, N / F1>;
+  const auto *th = static_cast<const typename CT<T>::R *>(thv);
+  const size_t fixed = (size_t)g.nbz * rb_pitch(N);
+  const dim3 grid(ncols, g.n2, nk);
+#define LTD_V(V)                                                                                                \
+  do {                                                                                                          \
+    constexpr int NW = rb_nw_of(V), LZ = rb_lz_of<N, F1>(V);                                                    \
+    const size_t lds = (fixed + (size_t)NW * LZ * TZ::LS) * sizeof(T);                                          \
+    hipLaunchKernelGGL((k_rb_xz4<N, F1, N / F1, N, F1, N / F1, NW, LZ, T>), grid, dim3(NW * 64), lds, s, g, ka, \
+                       ncols, th);                                                                              \
+  } while (0)
+  if (v == 1) LTD_V(1);
+  else if (v == 2) LTD_V(2);
+  else LTD_V(0);
+#undef LTD_V
+}
+
 template <class F>
 void each_plane_kernel(F &&f) {
   f((const void *)k_rb_xz<0, 0>);
@@ -1076,10 +1111,12 @@ void each_plane_kernel(F &&f) {
   f((const void *)k_rb_xz<a, c>);
   LTD_RB(0, 0) LTD_RB(16, 16) LTD_RB(64, 64) LTD_RB(72, 72) LTD_RB(96, 160)
 #undef LTD_RB
-#define LTD_X4(n, f1, T) f((const void *)k_rb_xz4<n, f1, n / f1, n, f1, n / f1, RB_NW, rb_lz(Two<n, f1, n / f1>::LPW), T>);
-  LTD_X4(72, 8, double2) LTD_X4(64, 8, double2) LTD_X4(16, 4, double2)
-  LTD_X4(72, 8, float2) LTD_X4(64, 8, float2) LTD_X4(16, 4, float2)
-#undef LTD_X4
+  reg_xz4<72, 8, double2>(f);
+  reg_xz4<64, 8, double2>(f);
+  reg_xz4<16, 4, double2>(f);
+  reg_xz4<72, 8, float2>(f);
+  reg_xz4<64, 8, float2>(f);
+  reg_xz4<16, 4, float2>(f);
   f((const void *)k_inv_plane<0, 0>);
   f((const void *)k_fwd_plane<0, 0>);
 #define LTD_PL(a, b)                            \
@@ -1128,12 +1165,6 @@ size_t fft_rb_slab_values(const Grid &g) { return (size_t)g.nbz * g.n2 * g.nbx; 
 int rb_split(int n) { return n == 72 ? 8 : n == 64 ? 8 : n == 16 ? 4 : 0; }
 bool rb_fast(const Grid &g) { return rb_split(g.n1) > 0 && rb_split(g.n3) > 0; }
 
-size_t rb_xz4_lds(const Grid &g, size_t es = sizeof(double2)) {
-  const int f1 = rb_split(g.n3), f2 = g.n3 / f1, gl = f1 > f2 ? f1 : f2, p = (gl % 2) ? gl : gl + 1;
-  const int ls = gl * p + ((9 - (gl * p) % 8) % 8);
-  const int rx = g.n1 + ((9 - g.n1 % 8) % 8);
-  return ((size_t)g.nbz * rx + (size_t)RB_NW * rb_lz(64 / gl) * ls) * es;
-}
 
 bool fft_rb_fast(const Grid &g) { return rb_fast(g); }
 
@@ -1211,27 +1242,24 @@ hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hi
   return hipGetLastError();
 }
 
+int fft_rb_variants() { return RB_VARIANTS; }
+
 hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s,
-                       int part, bool fp32) {
+                       int part, bool fp32, int variant) {
   set_attrs();
   const dim3 block(FFT_NT);
+  if (variant < 0 || variant >= RB_VARIANTS) return hipErrorInvalidValue;
   if (part == 0 && rb_fast(g)) {
-    const dim3 grid(ncols, g.n2, nk), blk(RB_NW * 64);
-    const size_t lds = rb_xz4_lds(g, fp32 ? sizeof(float2) : sizeof(double2));
-#define LTD_XZ4(a, a1, c, c1, T, RT)                                                                            \
-  hipLaunchKernelGGL((k_rb_xz4<a, a1, a / a1, c, c1, c / c1, RB_NW, rb_lz(Two<c, c1, c / c1>::LPW), T>), grid, blk, \
-                     lds, s, g, ka, ncols, static_cast<const RT *>(thv))
-#define LTD_XZ4P(a, a1, c, c1)                            \
-  do {                                                     \
-    if (fp32) LTD_XZ4(a, a1, c, c1, float2, float);        \
-    else LTD_XZ4(a, a1, c, c1, double2, double);           \
+#define LTD_XZ4P(n, f1)                                                  \
+  do {                                                                   \
+    if (fp32) launch_xz4<n, f1, float2>(g, ka, nk, ncols, thv, s, variant);  \
+    else launch_xz4<n, f1, double2>(g, ka, nk, ncols, thv, s, variant);      \
   } while (0)
-    if (g.n1 == 72 && g.n3 == 72) LTD_XZ4P(72, 8, 72, 8);
-    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ4P(64, 8, 64, 8);
-    else if (g.n1 == 16 && g.n3 == 16) LTD_XZ4P(16, 4, 16, 4);
+    if (g.n1 == 72 && g.n3 == 72) LTD_XZ4P(72, 8);
+    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ4P(64, 8);
+    else if (g.n1 == 16 && g.n3 == 16) LTD_XZ4P(16, 4);
     else return hipErrorInvalidValue;
 #undef LTD_XZ4P
-#undef LTD_XZ4
   } else if (part == 0) {
     if (fp32) return hipErrorInvalidValue;  // the FP32 residual needs the register path
     const dim3 grid(ncols, g.n2, nk);

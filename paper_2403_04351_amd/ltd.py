@@ -158,6 +158,19 @@ class Ltd:
         return a.value, b.value, d.value
 
     # ------------------------------------------------------------------
+    def autotune(self):
+        """Times the rebuild's launch shapes and projection split targets on the
+        bound subspaces and keeps the fastest; returns the choice and the timings."""
+        choice = (C.c_int * 2)()
+        times = (C.c_double * 16)()
+        check(self.lib.ltd_autotune(self.handle, choice, times, self.stream()), "ltd_autotune")
+        return dict(xz_shape=choice[0], projection_blocks=choice[1], times_us=list(times[:7]))
+
+    def set_tuning(self, xz_shape, projection_blocks):
+        """Sets the rebuild's launch shape and the projection split target."""
+        choice = (C.c_int * 2)(xz_shape, projection_blocks)
+        check(self.lib.ltd_set_tuning(self.handle, choice), "ltd_set_tuning")
+
     def rebuild_grid(self):
         """FFT lengths (N1, N2, N3) of the per-step rebuild."""
         out = (C.c_int * 3)()
