@@ -89,6 +89,7 @@ struct ltd_system {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t o_rtw1 = 0, o_rtw2 = 0, o_rtw3 = 0, o_M1 = 0, o_M2 = 0, o_M3 = 0, o_syn1 = 0, o_syn2 = 0;
+  size_t o_F1 = 0, o_F2 = 0, o_F3 = 0;  // MFMA fragments of the synthesis axis matrices
   int chunk = 0;        // columns per apply pass
   bool h_in_lds = false;
   bool p_in_lds = false;
@@ -376,6 +377,7 @@ ltd_status rebuild_potential(ltd_system *sys, const double *v, const int *step, 
   if (sys->rb_synth) {
     LTD_HIP(fft_rb_synth(rgrid_of(sys), sys->n1, sys->n2, sys->n3, sys->theta, v, step, stride,
                          sys->at<double>(sys->o_M1), sys->at<double>(sys->o_M2), sys->at<double>(sys->o_M3),
+                         sys->at<double>(sys->o_F1), sys->at<double>(sys->o_F2), sys->at<double>(sys->o_F3),
                          sys->at<double>(sys->o_syn1), sys->at<double>(sys->o_syn2), out,
                          resid ? sys->at<double>(sys->o_thv_rb) : nullptr, resid, s));
   } else {
@@ -948,6 +950,9 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     sys->o_M1 = ar.take((size_t)fft_rb_table_len(g.n1, r.n1) * sizeof(double));
     sys->o_M2 = ar.take((size_t)fft_rb_table_len(g.n2, r.n2) * sizeof(double));
     sys->o_M3 = ar.take((size_t)fft_rb_table_len(g.n3, r.n3) * sizeof(double));
+    sys->o_F1 = ar.take((size_t)fft_rb_frag_len(g.n1, r.n1) * sizeof(double));
+    sys->o_F2 = ar.take((size_t)fft_rb_frag_len(g.n2, r.n2) * sizeof(double));
+    sys->o_F3 = ar.take((size_t)fft_rb_frag_len(g.n3, r.n3) * sizeof(double));
     sys->o_syn1 = ar.take((size_t)g.n3 * g.n2 * r.n1 * sizeof(double));
     sys->o_syn2 = ar.take((size_t)g.n3 * r.n2 * r.n1 * sizeof(double));
   }
@@ -1024,7 +1029,7 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
     // tab[m] = (1/N) sum_{|q| <= 2b} exp(2 pi i q m / L): the axis matrix
     // M[j'][j] = (1/N) sum_{|q| <= 2b} exp(2 pi i q j'/N') exp(-2 pi i q j/N) (real)
     // at j'/N' - j/N = m/L, L = lcm(N, N')
-    auto mat = [&](int np, int nn, int b, size_t off) -> ltd_status {
+    auto mat = [&](int np, int nn, int b, size_t off, size_t off_f) -> ltd_status {
       const int L = fft_rb_table_len(nn, np);
       std::vector<double> m(L);
       for (int e = 0; e < L; ++e) {
@@ -1033,11 +1038,14 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
         m[e] = acc / nn;
       }
       LTD_HIP(hipMemcpy(sys->ws + off, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice));
+      std::vector<double> f(fft_rb_frag_len(nn, np));
+      fft_rb_frag(nn, np, m.data(), f.data());
+      LTD_HIP(hipMemcpy(sys->ws + off_f, f.data(), f.size() * sizeof(double), hipMemcpyHostToDevice));
       return LTD_OK;
     };
-    LTD_TRY(mat(r.n1, sys->n1, r.bx, sys->o_M1));
-    LTD_TRY(mat(r.n2, sys->n2, r.by, sys->o_M2));
-    LTD_TRY(mat(r.n3, sys->n3, r.bz, sys->o_M3));
+    LTD_TRY(mat(r.n1, sys->n1, r.bx, sys->o_M1, sys->o_F1));
+    LTD_TRY(mat(r.n2, sys->n2, r.by, sys->o_M2, sys->o_F2));
+    LTD_TRY(mat(r.n3, sys->n3, r.bz, sys->o_M3, sys->o_F3));
   }
   for (int k = 0; k < sys->n_k; ++k) {
     KHost &kh = sys->kh[k];

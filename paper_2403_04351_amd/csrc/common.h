@@ -219,11 +219,17 @@ bool fft_rb_fast(const Grid &g);
 // passes x, y, z, written in the layout fft_rb_step part 0 reads.
 // t1: n3 * n2 * gr.n1 doubles, t2: n3 * gr.n2 * gr.n1 doubles.
 int fft_rb_table_len(int n, int np);
-// sub != NULL: out = W - sub (same layout); fp32: out is float, else double.
-hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *theta, const double *v,
+// MFMA fragments of the synthesis axis matrix (n original points, np rebuild
+// points) from its Dirichlet table: fft_rb_frag_len(n, np) doubles, host side.
+int fft_rb_frag_len(int n, int np);
+void fft_rb_frag(int n, int np, const double *tab, double *mf);
+// mf_d: the fragments of M_d (device), used where n_d is 16, 64, 72 or 96; the
+// tables otherwise.  sub != NULL: out = W - sub (same layout); fp32: out is
+// float, else double.
+hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th, const double *v,
                         const int *step, long long stride, const double *tab1, const double *tab2,
-                        const double *tab3, double *t1, double *t2, void *out, const double *sub, bool fp32,
-                        hipStream_t s);
+                        const double *tab3, const double *mf1, const double *mf2, const double *mf3, double *t1,
+                        double *t2, void *out, const double *sub, bool fp32, hipStream_t s);
 size_t fft_line_lds_bytes(const Grid &g);
 
 }  // namespace ltd

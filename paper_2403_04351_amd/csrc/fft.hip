@@ -997,6 +997,84 @@ __global__ __launch_bounds__(256) void k_syn_pass(const double *__restrict__ in,
 }
 
 
+// The same axis pass on the matrix cores (v_mfma_f64_16x16x4f64), for N a
+// multiple of 4 (KS = N / 4 steps of K = 4).  The axis matrix comes as MFMA
+// fragments mf[(s RB + a) 64 + lane] = M[16 a + lane % 16][4 s + lane / 16]
+// (zero outside Np x N, RB = ceil(Np / 16)).  A wave computes one 16 x 16
+// output block:
+//  ROWS (I == 1, the positions are the rows o, contiguous in j): the data rows
+//    are the A operand and M^T the B operand, D[p][j'] = sum_j F[p][j] M[j'][j],
+//    so the 16 lanes of an output register write 16 consecutive j';
+//  otherwise (I a multiple of 16, a block of 16 consecutive i within one o): M
+//    is the A operand and the data the B operand, D[j'][p] = sum_j M[j'][j] F[j][p],
+//    read and written 16 consecutive i at a time.
+// Output element of accumulator register r: row 4 r + lane / 16, column lane % 16.
+template <int KS, bool ROWS, bool TH, class TO>
+__global__ __launch_bounds__(256) void k_syn_mfma(const double *__restrict__ in, const double *__restrict__ th,
+                                                  const int *step, long long stride, TO *__restrict__ out,
+                                                  const double *__restrict__ sub, const double *__restrict__ mf,
+                                                  int RB, int O, int N, int I, int Np, int perm_n1, int perm_z1,
+                                                  int perm_z2) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  const long long task = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long long P = (long long)O * I;
+  const long long ntile = (P + 15) / 16;
+  if (task >= ntile * RB) return;  // the whole wave (task is uniform across it)
+  const int a = (int)(task % RB);
+  const long long p0 = (task / RB) * 16;
+  if (step) in += (long long)(*step) * stride;
+  const int lr = lane & 15, lk = lane >> 4;
+  double fa[KS], fb[KS];
+  if constexpr (ROWS) {
+    const long long p = p0 + lr < P ? p0 + lr : P - 1;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const long long src = p * N + 4 * s + lk;
+      if constexpr (TH) fa[s] = th[src] * in[src];
+      else fa[s] = in[src];
+      fb[s] = mf[(s * RB + a) * 64 + lane];
+    }
+  } else {
+    const long long o = p0 / I;
+    const long long i = p0 - o * I + lr;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const long long src = (o * N + 4 * s + lk) * I + i;
+      if constexpr (TH) fb[s] = th[src] * in[src];
+      else fb[s] = in[src];
+      fa[s] = mf[(s * RB + a) * 64 + lane];
+    }
+  }
+  d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < KS; s += 2) {
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s], fb[s], acc0, 0, 0, 0);
+    if (s + 1 < KS) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s + 1], fb[s + 1], acc1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double v = acc0[r] + acc1[r];
+    if constexpr (ROWS) {
+      const long long p = p0 + 4 * r + lk;
+      const int jp = 16 * a + lr;
+      if (p < P && jp < Np) out[p * Np + jp] = (TO)v;
+    } else {
+      const int jp = 16 * a + 4 * r + lk;
+      const long long o = p0 / I;
+      const long long i = p0 - o * I + lr;
+      if (jp >= Np) continue;
+      if (perm_n1 > 0) {
+        const long long y = i / perm_n1, x = i - y * perm_n1;
+        const long long oi = ((y * perm_z2 + jp / perm_z1) * perm_n1 + x) * perm_z1 + jp % perm_z1;
+        out[oi] = (TO)(sub ? v - sub[oi] : v);
+      } else {
+        out[(o * Np + jp) * I + i] = (TO)v;
+      }
+    }
+  }
+}
+
 // Theta V in the order k_rb_xz4 reads it: out[((y Z2 + k2) N1 + x) Z1 + k1] for
 // the grid point (z = k1 + Z1 k2, y, x); z1 == 0: the grid order itself.
 // vref != NULL: Theta (v - vref) (the residual, in TO = float).
@@ -1176,10 +1254,50 @@ int fft_rb_length(int n, int b) {
 
 int fft_rb_table_len(int n, int np) { return n / std::gcd(n, np) * np; }
 
+int fft_rb_frag_len(int n, int np) { return ((np + 15) / 16) * ((n + 3) / 4) * 64; }
+
+void fft_rb_frag(int n, int np, const double *tab, double *mf) {
+  const int g = std::gcd(n, np), L = n / g * np, c1 = n / g, c2 = np / g;
+  const int rb = (np + 15) / 16, ks = (n + 3) / 4;
+  for (int s = 0; s < ks; ++s)
+    for (int a = 0; a < rb; ++a)
+      for (int l = 0; l < 64; ++l) {
+        const int jp = 16 * a + l % 16, j = 4 * s + l / 16;
+        double v = 0.0;
+        if (jp < np && j < n) {
+          long long m = ((long long)c1 * jp - (long long)c2 * j) % L;
+          if (m < 0) m += L;
+          v = tab[m];
+        }
+        mf[((size_t)s * rb + a) * 64 + l] = v;
+      }
+}
+
+namespace {
+// MFMA pass for N in {16, 64, 72, 96} (and I a multiple of 16 unless ROWS);
+// false when the shape has no instantiation
+template <bool ROWS, bool TH, class TO>
+bool syn_mfma(int N, dim3 grid, hipStream_t s, const double *in, const double *th, const int *step, long long stride,
+              TO *out, const double *sub, const double *mf, int RB, int O, int I, int Np, int pn1, int z1, int z2) {
+  if (ROWS ? I != 1 : I % 16 != 0) return false;
+#define LTD_SM(KS) \
+  hipLaunchKernelGGL((k_syn_mfma<KS, ROWS, TH, TO>), grid, dim3(256), 0, s, in, th, step, stride, out, sub, mf, RB, O, \
+                     N, I, Np, pn1, z1, z2)
+  switch (N) {
+    case 16: LTD_SM(4); return true;
+    case 64: LTD_SM(16); return true;
+    case 72: LTD_SM(18); return true;
+    case 96: LTD_SM(24); return true;
+    default: return false;
+  }
+#undef LTD_SM
+}
+}  // namespace
+
 hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th, const double *v,
                         const int *step, long long stride, const double *tab1, const double *tab2,
-                        const double *tab3, double *t1, double *t2, void *out, const double *sub, bool fp32,
-                        hipStream_t s) {
+                        const double *tab3, const double *mf1, const double *mf2, const double *mf3, double *t1,
+                        double *t2, void *out, const double *sub, bool fp32, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     for (const void *k : {(const void *)k_syn_pass<32, true, double>, (const void *)k_syn_pass<16, false, double>,
@@ -1196,17 +1314,33 @@ hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th
     hipLaunchKernelGGL(kern, dim3((P + tp - 1) / tp), dim3(256), lds, s, in, thp, st, stride, o, sb, tab, L, n / g,
                        np / g, O, n, I, np, pn1, z1, z2);
   };
+  const auto grid_of = [](int np, long long P) {
+    const long long tasks = ((np + 15) / 16) * ((P + 15) / 16);
+    return dim3((unsigned)((tasks + 3) / 4));
+  };
+  const auto rb = [](int np) { return (np + 15) / 16; };
   // x: [n3 n2][n1] -> [n3 n2][n1']  (Theta V formed on the fly)
-  pass(k_syn_pass<32, true, double>, 32, v, th, step, t1, nullptr, tab1, n1, gr.n1, n3 * n2, 1, 0);
+  if (!syn_mfma<true, true, double>(n1, grid_of(gr.n1, (long long)n3 * n2), s, v, th, step, stride, t1, nullptr, mf1,
+                                    rb(gr.n1), n3 * n2, 1, gr.n1, 0, z1, z2))
+    pass(k_syn_pass<32, true, double>, 32, v, th, step, t1, nullptr, tab1, n1, gr.n1, n3 * n2, 1, 0);
   // y: [n3][n2][n1'] -> [n3][n2'][n1']  (16 <= n1': one row boundary at most per block)
-  pass(k_syn_pass<16, false, double>, 16, t1, nullptr, nullptr, t2, nullptr, tab2, n2, gr.n2, n3, gr.n1, 0);
+  if (!syn_mfma<false, false, double>(n2, grid_of(gr.n2, (long long)n3 * gr.n1), s, t1, nullptr, nullptr, 0, t2,
+                                      nullptr, mf2, rb(gr.n2), n3, gr.n1, gr.n2, 0, z1, z2))
+    pass(k_syn_pass<16, false, double>, 16, t1, nullptr, nullptr, t2, nullptr, tab2, n2, gr.n2, n3, gr.n1, 0);
   // z: [n3][n2' n1'] -> the k_rb_xz4 order (minus sub, in FP32 for the residual)
-  if (fp32)
-    pass(k_syn_pass<16, false, float>, 16, t2, nullptr, nullptr, static_cast<float *>(out), sub, tab3, n3, gr.n3, 1,
-         gr.n2 * gr.n1, gr.n1);
-  else
-    pass(k_syn_pass<16, false, double>, 16, t2, nullptr, nullptr, static_cast<double *>(out), sub, tab3, n3, gr.n3, 1,
-         gr.n2 * gr.n1, gr.n1);
+  const long long pz = (long long)gr.n2 * gr.n1;
+  if (fp32) {
+    if (!syn_mfma<false, false, float>(n3, grid_of(gr.n3, pz), s, t2, nullptr, nullptr, 0, static_cast<float *>(out),
+                                       sub, mf3, rb(gr.n3), 1, (int)pz, gr.n3, gr.n1, z1, z2))
+      pass(k_syn_pass<16, false, float>, 16, t2, nullptr, nullptr, static_cast<float *>(out), sub, tab3, n3, gr.n3, 1,
+           gr.n2 * gr.n1, gr.n1);
+  } else {
+    if (!syn_mfma<false, false, double>(n3, grid_of(gr.n3, pz), s, t2, nullptr, nullptr, 0,
+                                        static_cast<double *>(out), sub, mf3, rb(gr.n3), 1, (int)pz, gr.n3, gr.n1, z1,
+                                        z2))
+      pass(k_syn_pass<16, false, double>, 16, t2, nullptr, nullptr, static_cast<double *>(out), sub, tab3, n3, gr.n3,
+           1, gr.n2 * gr.n1, gr.n1);
+  }
   return hipGetLastError();
 }
 

@@ -7,8 +7,8 @@
 //
 // Work decomposition: 64x64 output tiles, 256 threads = 4 wavefronts in a 2x2
 // arrangement, each wavefront owning a 32x32 block = 2x2 MFMA blocks of 16x16.
-// A complex multiply-add is four real v_mfma_f64_16x16x4_f64: re += ar br,
-// re += (-ai) bi, im += ar bi, im += ai br.  Operand tiles (64 x 16 complex)
+// A complex multiply-add is three real v_mfma_f64_16x16x4_f64 (the Gauss form
+// below).  Operand tiles (64 x 16 complex)
 // are staged through LDS as separate real and imaginary planes, double
 // buffered, with the conjugation of op = C folded into the staging store.
 // Logical tiles are remapped so that each XCD (blocks are dealt round-robin
@@ -33,51 +33,71 @@ __device__ inline int xcd_logical(int b, int g) {
   return (x < rem) ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
 }
 
+// Global-memory operand pointer (address space 1: global loads, not flat ones).
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef const d2v __attribute__((address_space(1))) *gptr;
+__device__ inline double2 ldg(gptr p) {
+  const d2v v = *p;
+  return make_double2(v.x, v.y);
+}
+
+// Per-block copy of the problem fields the K loop uses (registers, not the table).
+struct Ops {
+  gptr A, B, B2;
+  int lda, ldb, m, nlim, kseg, kend;
+};
+
+// Operand loads at clamped (in-bounds) indices, zeroed by value outside the
+// problem: no branch around a load, so the loads of a tile are all in flight
+// together.
 template <int OPA>
-__device__ inline void load_a(const ZProb &P, const double2 *A, int m0, int k0, int kend, int t,
-                              Frag &f) {
+__device__ inline void load_a(const Ops &o, int m0, int k0, int t, Frag &f) {
   if (OPA == OP_N) {  // A is m x k: tile column kk is contiguous in i
     const int kk = t >> 4, i = (t & 15) * 4;
     const int kg = k0 + kk;
+    const int kc = kg < o.kend ? kg : o.kend - 1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int ig = m0 + i + q;
-      f.v[q] = (ig < P.m && kg < kend) ? A[(long long)ig + (long long)kg * P.lda] : make_double2(0.0, 0.0);
+      const double2 v = ldg(o.A + (long long)(ig < o.m ? ig : o.m - 1) + (long long)kc * o.lda);
+      f.v[q] = (ig < o.m && kg < o.kend) ? v : make_double2(0.0, 0.0);
     }
   } else {  // A is k x m, op = conj-transpose: tile row i is contiguous in kk
     const int i = t >> 2, kk = (t & 3) * 4;
     const int ig = m0 + i;
+    const int ic = ig < o.m ? ig : o.m - 1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kg = k0 + kk + q;
-      f.v[q] = (ig < P.m && kg < kend) ? A[(long long)kg + (long long)ig * P.lda] : make_double2(0.0, 0.0);
+      const double2 v = ldg(o.A + (long long)(kg < o.kend ? kg : o.kend - 1) + (long long)ic * o.lda);
+      f.v[q] = (ig < o.m && kg < o.kend) ? v : make_double2(0.0, 0.0);
     }
   }
 }
 
 template <int OPB>
-__device__ inline void load_b(const ZProb &P, const double2 *B, const double2 *B2, int n0, int k0, int kend, int t,
-                              Frag &f, int nlim) {
+__device__ inline void load_b(const Ops &o, int n0, int k0, int t, Frag &f) {
   if (OPB == OP_N) {  // B is k x n: tile column j is contiguous in kk
     const int j = t >> 2, kk = (t & 3) * 4;
     const int jg = n0 + j;
+    const int jc = jg < o.nlim ? jg : o.nlim - 1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kg = k0 + kk + q;
-      double2 v = make_double2(0.0, 0.0);
-      if (jg < nlim && kg < kend) {
-        if (P.kseg > 0 && kg >= P.kseg) v = B2[(long long)(kg - P.kseg) + (long long)jg * P.ldb];
-        else v = B[(long long)kg + (long long)jg * P.ldb];
-      }
-      f.v[q] = v;
+      const int kc = kg < o.kend ? kg : o.kend - 1;
+      const gptr src = (o.kseg > 0 && kc >= o.kseg) ? o.B2 + (kc - o.kseg) : o.B + kc;
+      const double2 v = ldg(src + (long long)jc * o.ldb);
+      f.v[q] = (jg < o.nlim && kg < o.kend) ? v : make_double2(0.0, 0.0);
     }
   } else {  // B is n x k, op = conj-transpose: tile row kk is contiguous in j
     const int kk = t >> 4, j = (t & 15) * 4;
     const int kg = k0 + kk;
+    const int kc = kg < o.kend ? kg : o.kend - 1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int jg = n0 + j + q;
-      f.v[q] = (jg < nlim && kg < kend) ? B[(long long)jg + (long long)kg * P.ldb] : make_double2(0.0, 0.0);
+      const double2 v = ldg(o.B + (long long)(jg < o.nlim ? jg : o.nlim - 1) + (long long)kc * o.ldb);
+      f.v[q] = (jg < o.nlim && kg < o.kend) ? v : make_double2(0.0, 0.0);
     }
   }
 }
@@ -122,6 +142,12 @@ __device__ inline void store_b(double (*Bs)[BK][BN + LP], int t, const Frag &f) 
   }
 }
 
+// Complex products by the three-multiplication (Gauss) form: for a = ar + i ai,
+// b = br + i bi, t1 = ar br, t2 = ai bi, t3 = (ar + ai)(br + bi), and
+// ab = (t1 - t2) + i (t3 - t1 - t2).  Each 16x16 output block keeps t1, t2, t3
+// as three MFMA accumulators summed over K, so a complex multiply-add costs
+// three real MFMAs instead of four; the sums ar + ai, br + bi are formed after
+// the LDS reads.
 template <int OPA, int OPB, bool TABLE>
 __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZProb *__restrict__ table,
                                                    int nprob, double2 *__restrict__ partials, int n_limit) {
@@ -142,33 +168,39 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
   const int bi = t % P.batch;
   const int ks = t / P.batch;
 
-  const double2 *A = P.A + (long long)bi * P.sA;
-  const double2 *B = P.B + (long long)bi * P.sB;
-  const double2 *B2 = P.B2 ? P.B2 + (long long)bi * P.sB : nullptr;
   const int m0 = tm * BM, n0 = tn * BN;
-  const int nlim = (n_limit > 0 && n_limit < P.n) ? n_limit : P.n;
-  if (n0 >= nlim) return;  // whole block: columns beyond the limit
+  Ops o;
+  o.nlim = (n_limit > 0 && n_limit < P.n) ? n_limit : P.n;
+  if (n0 >= o.nlim) return;  // whole block: columns beyond the limit
+  o.A = (gptr)(const void *)(P.A + (long long)bi * P.sA);
+  o.B = (gptr)(const void *)(P.B + (long long)bi * P.sB);
+  o.B2 = (gptr)(const void *)(P.B2 ? P.B2 + (long long)bi * P.sB : P.B);
+  o.lda = P.lda;
+  o.ldb = P.ldb;
+  o.m = P.m;
+  o.kseg = P.B2 ? P.kseg : 0;
   const int kbeg = ks * P.kchunk;
-  const int kend = min(P.k, kbeg + P.kchunk);
-  const int nkt = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+  o.kend = min(P.k, kbeg + P.kchunk);
+  const int nkt = (o.kend > kbeg) ? (o.kend - kbeg + BK - 1) / BK : 0;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  d4 cr[2][2], ci[2][2];
+  d4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      cr[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-      ci[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      t1[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      t2[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      t3[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
   Frag fa, fb;
   if (nkt > 0) {
-    load_a<OPA>(P, A, m0, kbeg, kend, tid, fa);
-    load_b<OPB>(P, B, B2, n0, kbeg, kend, tid, fb, nlim);
+    load_a<OPA>(o, m0, kbeg, tid, fa);
+    load_b<OPB>(o, n0, kbeg, tid, fb);
     store_a<OPA>(As[0], tid, fa);
     store_b<OPB>(Bs[0], tid, fb);
   }
@@ -176,39 +208,43 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
 
   for (int kt = 0; kt < nkt; ++kt) {
     const int cur = kt & 1;
-    const bool more = (kt + 1) < nkt;
-    if (more) {
-      const int k0 = kbeg + (kt + 1) * BK;
-      load_a<OPA>(P, A, m0, k0, kend, tid, fa);
-      load_b<OPB>(P, B, B2, n0, k0, kend, tid, fb, nlim);
-    }
+    // next tile's loads (clamped: the last iteration reloads the last tile, unused)
+    const int k0 = kbeg + (kt + 1 < nkt ? kt + 1 : kt) * BK;
+    load_a<OPA>(o, m0, k0, tid, fa);
+    load_b<OPB>(o, n0, k0, tid, fb);
+    __builtin_amdgcn_sched_barrier(0);  // the loads issue before the MFMAs of this tile
 #pragma unroll
     for (int kq = 0; kq < BK; kq += 4) {
       const int kk = kq + (lane >> 4);
-      double ar[2], ai[2], br[2], bi2[2];
+      double ar[2], ai[2], as[2], br[2], bi2[2], bs[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int i = wm * 32 + a * 16 + (lane & 15);
         ar[a] = As[cur][0][kk][i];
         ai[a] = As[cur][1][kk][i];
+        as[a] = ar[a] + ai[a];
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const int j = wn * 32 + b * 16 + (lane & 15);
         br[b] = Bs[cur][0][kk][j];
         bi2[b] = Bs[cur][1][kk][j];
+        bs[b] = br[b] + bi2[b];
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
-          cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], bi2[b], cr[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi2[b], ci[a][b], 0, 0, 0);
-          ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], ci[a][b], 0, 0, 0);
-        }
+        for (int b = 0; b < 2; ++b) t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], t1[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi2[b], t2[a][b], 0, 0, 0);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[a], bs[b], t3[a][b], 0, 0, 0);
     }
-    if (more) {
+    if (kt + 1 < nkt) {
       store_a<OPA>(As[cur ^ 1], tid, fa);
       store_b<OPB>(Bs[cur ^ 1], tid, fb);
     }
@@ -217,6 +253,9 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
 
   // Output element of accumulator register r of v_mfma_f64_16x16x4f64: row 4*r + lane/16,
   // column lane%16 (measured; the FP32 16x16 variant differs).
+  const auto acc_of = [&](int a, int b, int r) {
+    return make_double2(t1[a][b][r] - t2[a][b][r], t3[a][b][r] - t1[a][b][r] - t2[a][b][r]);
+  };
   if (P.ksplit == 1) {
     double2 *C = P.C + (long long)bi * P.sC;
     const bool rd = (P.beta.x != 0.0 || P.beta.y != 0.0);
@@ -228,9 +267,8 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
         for (int r = 0; r < 4; ++r) {
           const int i = m0 + wm * 32 + a * 16 + 4 * r + (lane >> 4);
           const int j = n0 + wn * 32 + b * 16 + (lane & 15);
-          if (i < P.m && j < nlim) {
-            const double2 acc = make_double2(cr[a][b][r], ci[a][b][r]);
-            double2 v = cmul(P.alpha, acc);
+          if (i < P.m && j < o.nlim) {
+            double2 v = cmul(P.alpha, acc_of(a, b, r));
             double2 *dst = C + (long long)i + (long long)j * P.ldc;
             if (rd) v = cfma(P.beta, *dst, v);
             *dst = v;
@@ -247,7 +285,7 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
         for (int r = 0; r < 4; ++r) {
           const int il = wm * 32 + a * 16 + 4 * r + (lane >> 4);
           const int jl = wn * 32 + b * 16 + (lane & 15);
-          dst[jl * BM + il] = make_double2(cr[a][b][r], ci[a][b][r]);
+          dst[jl * BM + il] = acc_of(a, b, r);
         }
   }
 }
@@ -347,7 +385,8 @@ size_t gemm_plan(ZProb *probs, int nprob, int *total_tiles, int target_blocks, l
       if (kt >= 4) base_split += (long long)P.tiles_m * P.tiles_n * P.batch;
     }
     if (base_split > 0) {
-      ks_common = (int)((target_blocks + base_all - 1) / base_all);
+      // rounded down: a launch of at most target_blocks leaves no tail round
+      ks_common = (int)(target_blocks / base_all > 1 ? target_blocks / base_all : 1);
       const long long cap = max_part_tiles / base_split;
       if (ks_common > cap) ks_common = (int)(cap > 1 ? cap : 1);
     }
