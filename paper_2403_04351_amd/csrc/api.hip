@@ -609,6 +609,7 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
   c.theta = reinterpret_cast<double2 *>(a->theta);
   c.part = sys->at<double>(sys->o_part);
   c.status = sys->at<int>(sys->o_status);
+  c.done = sys->at<int>(sys->o_status) + 8;  // zeroed at bind, reset by the step kernel's last block
   c.j_out = a->j_out;
   c.e_out = a->e_out;
   c.dmu_out = a->dmu_out;

@@ -1002,9 +1002,10 @@ __global__ __launch_bounds__(256) void k_syn_pass(const double *__restrict__ in,
 // fragments mf[(s RB + a) 64 + lane] = M[16 a + lane % 16][4 s + lane / 16]
 // (zero outside Np x N, RB = ceil(Np / 16)).  A wave computes one 16 x 16
 // output block:
-//  ROWS (I == 1, the positions are the rows o, contiguous in j): the data rows
-//    are the A operand and M^T the B operand, D[p][j'] = sum_j F[p][j] M[j'][j],
-//    so the 16 lanes of an output register write 16 consecutive j';
+//  ROWS (I == 1, the positions are the rows o, contiguous in j): a block of
+//    RB waves takes 16 rows, staged through LDS; the data rows are the A
+//    operand and M^T the B operand, D[p][j'] = sum_j F[p][j] M[j'][j], so the 16
+//    lanes of an output register write 16 consecutive j';
 //  otherwise (I a multiple of 16, a block of 16 consecutive i within one o): M
 //    is the A operand and the data the B operand, D[j'][p] = sum_j M[j'][j] F[j][p],
 //    read and written 16 consecutive i at a time.
@@ -1016,26 +1017,44 @@ __global__ __launch_bounds__(256) void k_syn_mfma(const double *__restrict__ in,
                                                   int RB, int O, int N, int I, int Np, int perm_n1, int perm_z1,
                                                   int perm_z2) {
   typedef double d4 __attribute__((ext_vector_type(4)));
-  const int lane = threadIdx.x & 63;
-  const long long task = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  constexpr int RP = 4 * KS + 1;  // LDS row pitch of the ROWS tile (odd: no bank conflicts)
+  __shared__ double tile[ROWS ? 16 * RP : 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long P = (long long)O * I;
-  const long long ntile = (P + 15) / 16;
-  if (task >= ntile * RB) return;  // the whole wave (task is uniform across it)
-  const int a = (int)(task % RB);
-  const long long p0 = (task / RB) * 16;
-  if (step) in += (long long)(*step) * stride;
   const int lr = lane & 15, lk = lane >> 4;
+  if (step) in += (long long)(*step) * stride;
   double fa[KS], fb[KS];
+  int a;
+  long long p0;
   if constexpr (ROWS) {
-    const long long p = p0 + lr < P ? p0 + lr : P - 1;
+    // a block is 16 consecutive rows (contiguous in memory), staged once through
+    // LDS with coalesced loads; its RB waves are the 16-column blocks of j'
+    p0 = (long long)blockIdx.x * 16;
+    a = wave;
+    const int nr = P - p0 < 16 ? (int)(P - p0) : 16;
+    const double *src = in + p0 * N;
+    const double *ths = TH ? th + p0 * N : nullptr;
+    stage8<double>(
+        nr * N,
+        [&](int e) {
+          if constexpr (TH) return ths[e] * src[e];
+          else return src[e];
+        },
+        [&](int e, double x) { tile[(e / N) * RP + e % N] = x; });
+    __syncthreads();
+    if (a >= RB) return;
+    const int rr = lr < nr ? lr : nr - 1;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const long long src = p * N + 4 * s + lk;
-      if constexpr (TH) fa[s] = th[src] * in[src];
-      else fa[s] = in[src];
+      fa[s] = tile[rr * RP + 4 * s + lk];
       fb[s] = mf[(s * RB + a) * 64 + lane];
     }
   } else {
+    const long long task = (long long)blockIdx.x * 4 + wave;
+    const long long ntile = (P + 15) / 16;
+    if (task >= ntile * RB) return;  // the whole wave (task is uniform across it)
+    a = (int)(task % RB);
+    p0 = (task / RB) * 16;
     const long long o = p0 / I;
     const long long i = p0 - o * I + lr;
 #pragma unroll
@@ -1279,7 +1298,8 @@ namespace {
 template <bool ROWS, bool TH, class TO>
 bool syn_mfma(int N, dim3 grid, hipStream_t s, const double *in, const double *th, const int *step, long long stride,
               TO *out, const double *sub, const double *mf, int RB, int O, int I, int Np, int pn1, int z1, int z2) {
-  if (ROWS ? I != 1 : I % 16 != 0) return false;
+  if (ROWS ? (I != 1 || RB > 4) : I % 16 != 0) return false;
+  if (ROWS) grid = dim3((unsigned)(((long long)O + 15) / 16));
 #define LTD_SM(KS) \
   hipLaunchKernelGGL((k_syn_mfma<KS, ROWS, TH, TO>), grid, dim3(256), 0, s, in, th, step, stride, out, sub, mf, RB, O, \
                      N, I, Np, pn1, z1, z2)

@@ -291,10 +291,11 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
 }
 
 // Sums the split-K partials of every output tile in a fixed order, then
-// C = alpha * sum + beta * C.  A block covers 32 output elements of one tile;
-// its 256 threads are 32 elements x 8 groups, group g summing splits
-// g, g + 8, g + 16, ... in order, then the 8 group sums are added in order.
-constexpr int RED_E = 32, RED_G = 8;
+// C = alpha * sum + beta * C.  A block covers RED_E output elements of one
+// tile; its 256 threads are RED_E elements x RED_G groups, group g summing
+// splits g, g + RED_G, g + 2 RED_G, ... in order (eight loads in flight per
+// thread), then the RED_G group sums are added in order.
+constexpr int RED_E = 8, RED_G = 32;
 
 template <bool TABLE>
 __global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZProb *__restrict__ table,
@@ -321,7 +322,18 @@ __global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZP
   double2 s = make_double2(0.0, 0.0);
   if (live) {
     const double2 *src = partials + (P.part_off + (long long)tl * P.ksplit) * (long long)(BM * BN) + e;
-    for (int q = grp; q < P.ksplit; q += RED_G) s = cadd(s, src[(long long)q * BM * BN]);
+    const int ks = P.ksplit;
+    for (int q0 = grp; q0 < ks; q0 += 8 * RED_G) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * RED_G;
+        v[u] = src[(long long)(q < ks ? q : ks - 1) * BM * BN];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u * RED_G < ks) s = cadd(s, v[u]);
+    }
   }
   part[grp][el] = s;
   __syncthreads();

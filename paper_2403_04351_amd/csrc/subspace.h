@@ -45,6 +45,7 @@ struct StepCtx {
   double2 *theta;          // [n_k][n_states][n_aux]
   double *part;            // [n_k * n_states][4] partial sums
   int *status;
+  int *done;               // blocks of the step kernel finished (zero between launches)
   double *j_out, *e_out, *dmu_out;
 };
 

@@ -386,8 +386,33 @@ __device__ __forceinline__ void stage_to_lds(double2 *dst, const double2 *src, l
   stage8<double2>((int)n, [&](int e) { return src[e]; }, [&](int e, double2 x) { dst[e] = x; });
 }
 
+// Sums the per-state partials in a fixed order, writes the series, advances
+// the step (one thread, after every state of the step has written its partials).
+__device__ void finalize_step(const StepCtx &c, int step) {
+  const int np = c.n_k * c.n_states;
+  double j1 = 0.0, e1 = 0.0, j0 = 0.0, e0 = 0.0;
+  for (int p = 0; p < np; ++p) {
+    j1 += c.part[4 * p + 0];
+    e1 += c.part[4 * p + 1];
+    j0 += c.part[4 * p + 2];
+    e0 += c.part[4 * p + 3];
+  }
+  if (step == 0) {
+    c.j_out[0] = j0;
+    c.e_out[0] = e0;
+    c.dmu_out[0] = 0.0;
+  }
+  const double jz = c.j_out[0];
+  c.j_out[step + 1] = j1;
+  c.e_out[step + 1] = e1;
+  c.dmu_out[step + 1] = c.dmu_out[step] + c.omega * c.dt * 0.5 * ((c.j_out[step] - jz) + (j1 - jz));
+  if (!isfinite(j1) || !isfinite(e1)) latch(c.status, 3);
+  *c.step_rw = step + 1;
+}
+
 // HL / PL: H~(mid) / P~ staged in LDS (compile-time, so that their reads are
-// LDS reads rather than generic ones).
+// LDS reads rather than generic ones).  The block that finishes last sums the
+// partials of every state (finalize_step).
 template <bool HL, bool PL>
 __global__ __launch_bounds__(256) void k_step(const StepCtx c) {
   extern __shared__ double2 sm[];
@@ -480,39 +505,19 @@ __global__ __launch_bounds__(256) void k_step(const StepCtx c) {
 
   // 5. observables at t_{n+1}
   observe(a1, part + 0, part + 1, false);
-}
 
-// Sums the per-state partials in a fixed order, writes the series, advances the step.
-__global__ void k_finalize(const StepCtx c) {
-  constexpr int CAP = 2048;
-  __shared__ double sp[CAP];
-  if (blockIdx.x != 0) return;
-  const int np = c.n_k * c.n_states;
-  const bool staged = 4 * np <= CAP;
-  if (staged)  // the partials load in parallel; thread 0 sums them in a fixed order
-    for (int e = threadIdx.x; e < 4 * np; e += blockDim.x) sp[e] = c.part[e];
+  // 6. the last block to finish: fixed-order sum, series, step counter
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  const double *pp = staged ? sp : c.part;
-  const int step = *c.step;
-  double j1 = 0.0, e1 = 0.0, j0 = 0.0, e0 = 0.0;
-  for (int p = 0; p < np; ++p) {
-    j1 += pp[4 * p + 0];
-    e1 += pp[4 * p + 1];
-    j0 += pp[4 * p + 2];
-    e0 += pp[4 * p + 3];
+  int *last = reinterpret_cast<int *>(sred);
+  if (threadIdx.x == 0) {
+    __threadfence();
+    *last = atomicAdd(c.done, 1) == (int)(gridDim.x * gridDim.y) - 1;
   }
-  if (step == 0) {
-    c.j_out[0] = j0;
-    c.e_out[0] = e0;
-    c.dmu_out[0] = 0.0;
-  }
-  const double jz = c.j_out[0];
-  c.j_out[step + 1] = j1;
-  c.e_out[step + 1] = e1;
-  c.dmu_out[step + 1] = c.dmu_out[step] + c.omega * c.dt * 0.5 * ((c.j_out[step] - jz) + (j1 - jz));
-  if (!isfinite(j1) || !isfinite(e1)) latch(c.status, 3);
-  *c.step_rw = step + 1;
+  __syncthreads();
+  if (!*last || threadIdx.x != 0) return;
+  __threadfence();
+  finalize_step(c, step);
+  *c.done = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -841,9 +846,6 @@ hipError_t launch_step(const StepCtx &c, hipStream_t s) {
     hipLaunchKernelGGL((k_step<true, false>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c);
   else
     hipLaunchKernelGGL((k_step<false, false>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, c);
   return hipGetLastError();
 }
 
