@@ -150,17 +150,20 @@ ltd_status ltd_ritz_basis(ltd_system *sys, int k, void *x, int ldx, double *eps,
 
 /* Tuner of the per-step rebuild's launch shapes (batched k-points: tiles from
  * an autotuner, the survey's extension 2): times, on the bound subspaces, every
- * launch shape of the x/z transform kernel (waves per block, z columns per wave)
- * and four block targets (256, 512, 1024, 2048) of the K split of the
- * projection GEMM, and keeps the fastest of each for the following steps
- * (results do not depend on the shape; the split changes the summation order
- * only).  choice (host, 2 ints): the shape index and the block target chosen;
- * times_us (host, optional): the timings, shapes first.  Every k-point must be
- * bound.  Synchronises `stream`; invalidates a captured step graph. */
+ * launch shape of the x/z transform kernel (three shapes of the two-factor
+ * kernel, whose results do not depend on the shape, and for the FP32 residual
+ * on a 64-point rebuild grid a fourth, register-resident kernel: the same
+ * transforms in another summation order) and four block targets (256, 512,
+ * 1024, 2048) of the K split of the projection GEMM (another summation order),
+ * and keeps the fastest of each for the following steps.  choice (host, 3
+ * ints): the shape index and the block target chosen, and the number of shapes
+ * timed; times_us (host, optional, 8 doubles): the timings, shapes first.
+ * Every k-point must be bound.  Synchronises `stream`; invalidates a captured
+ * step graph. */
 ltd_status ltd_autotune(ltd_system *sys, int *choice, double *times_us, void *stream);
 
 /* Sets the two tuned choices directly (host, 2 ints: x/z launch-shape index in
- * [0, number of shapes), projection block target in [64, 8192]), e.g. to reuse
+ * [0, number of shapes of this system), projection block target in [64, 8192]), e.g. to reuse
  * a tuning result saved from an earlier run.  LTD_EINVAL for values outside
  * those ranges.  Invalidates a captured step graph. */
 ltd_status ltd_set_tuning(ltd_system *sys, const int *choice);

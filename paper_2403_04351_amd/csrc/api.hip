@@ -1291,7 +1291,7 @@ ltd_status ltd_autotune(ltd_system *sys, int *choice, double *times_us, void *st
                         : static_cast<const void *>(sys->at<double>(sys->o_thv_rb));
   int best_v = 0;
   double best_t = 1e300;
-  for (int v = 0; v < fft_rb_variants() && st == LTD_OK; ++v) {
+  for (int v = 0; v < fft_rb_variants(g, r32) && st == LTD_OK; ++v) {
     double us = 0.0;
     st = timed([&]() -> ltd_status {
       LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0, r32, v));
@@ -1327,12 +1327,13 @@ ltd_status ltd_autotune(ltd_system *sys, int *choice, double *times_us, void *st
   sys->gvalid = false;  // a captured step graph holds the previous shapes
   choice[0] = best_v;
   choice[1] = best_g;
+  choice[2] = fft_rb_variants(g, r32);
   return LTD_OK;
 }
 
 ltd_status ltd_set_tuning(ltd_system *sys, const int *choice) {
   if (!sys || !choice) return LTD_EINVAL;
-  if (choice[0] < 0 || choice[0] >= fft_rb_variants()) return LTD_EINVAL;
+  if (choice[0] < 0 || choice[0] >= fft_rb_variants(rgrid_of(sys), resid32(sys))) return LTD_EINVAL;
   if (choice[1] < 64 || choice[1] > 8192) return LTD_EINVAL;
   sys->rb_variant = choice[0];
   if (choice[1] != sys->vproj_target) {

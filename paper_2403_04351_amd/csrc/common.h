@@ -196,11 +196,13 @@ size_t fft_rb_slab_values(const Grid &g);
 // fp32: the cache and step slabs hold float2 (the FP32 residual); thv is then
 // float, else double; Y is written in FP64 either way.
 hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hipStream_t s, bool fp32);
-// variant: launch shape of the part-0 kernel, 0 .. fft_rb_variants() - 1 (the
-// arithmetic per value is the same for every shape).
+// variant: launch shape of the part-0 kernel, 0 .. fft_rb_variants(g, fp32) - 1:
+// the first three are shapes of one two-factor kernel (the same arithmetic per
+// value, bit-identical results); for complex64 slabs on 64-point grids a fourth
+// is the register-resident kernel (the same transforms, another summation order).
 hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s,
                        int part, bool fp32, int variant);
-int fft_rb_variants();
+int fft_rb_variants(const Grid &g, bool fp32);
 // Theta V of a step in the layout fft_rb_step part 0 reads (ngrid doubles).
 // v is read at v + (*step) * stride when step is not NULL; vref != NULL gives
 // Theta (v - vref); fp32: out is float, else double.

@@ -903,6 +903,271 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident x/z transforms for N1' = N3' = 64 (box half-widths b <= 15,
+// which the rebuild grid guarantees: 4 b + 1 <= 64).  One wavefront per
+// (column, y') plane; each lane holds one whole 64-point transform in registers
+// as 8 x 8: input n = 8 n1 + n2, output k = k1 + 8 k2, a first pass of length-8
+// DFTs over n1, twiddles w^(n2 k1) (w = exp(DIR 2 pi i / 64)), a second pass over
+// n2.  With |k| <= 15 the inputs with n1 in 2..5 are zero (the first pass drops
+// them) and the outputs with k2 in 2..5 are never needed (never computed).
+//   rows (x transforms): lane r < nbz takes box row r;
+//   columns (z transforms): lane x takes grid column x.
+// The plane's rows pass through the wave's own LDS slice R[nbz][65] between
+// the phases (in-order LDS within a wave: wave fences, no block barrier).
+// ---------------------------------------------------------------------------
+constexpr double COS64[15] = {  // cos(2 pi j / 64), j = 1 .. 15
+    0.9951847266721969,
+    0.9807852804032304,
+    0.9569403357322088,
+    0.9238795325112867,
+    0.881921264348355,
+    0.8314696123025452,
+    0.773010453362737,
+    0.7071067811865476,
+    0.6343932841636455,
+    0.5555702330196023,
+    0.4713967368259978,
+    0.38268343236508984,
+    0.29028467725446233,
+    0.19509032201612833,
+    0.09801714032956077};
+
+// cos and sin of 2 pi j / 64 (compile-time j), exact at the multiples of pi/2
+__host__ __device__ constexpr double cos64(int j) {
+  j &= 63;
+  const int q = j >> 4, r = j & 15;  // quadrant, offset
+  const double c = r == 0 ? 1.0 : COS64[r - 1];   // cos of the offset
+  const double s = r == 0 ? 0.0 : COS64[15 - r];  // its sin = cos(16 - r)
+  return q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+}
+__host__ __device__ constexpr double sin64(int j) { return cos64(j - 16); }
+
+// v * exp(DIR 2 pi i j / 64), j compile-time
+template <int DIR, int J, class T>
+__device__ __forceinline__ T tw64(T v) {
+  using R = typename CT<T>::R;
+  constexpr int j = J & 63;
+  if constexpr (j == 0) return v;
+  else if constexpr (j == 16) return mul_i<DIR>(v);
+  else if constexpr (j == 32) return CT<T>::mk(-v.x, -v.y);
+  else if constexpr (j == 48) return mul_i<-DIR>(v);
+  else {
+    constexpr double c = cos64(j), sn = DIR * sin64(j);
+    return CT<T>::mk((R)c * v.x - (R)sn * v.y, (R)c * v.y + (R)sn * v.x);
+  }
+}
+
+// Length-8 DFT whose inputs 2..5 are zero (only v[0], v[1], v[6], v[7] read).
+template <int DIR, class T>
+__device__ __forceinline__ void dft8_z2345(T *v) {
+  using R = typename CT<T>::R;
+  const R h = (R)SQ1_2;
+  // the two length-4 DFTs of (v0, 0, 0, v6) and (v1, 0, 0, v7)
+  const T e0 = cadd(v[0], v[6]), e2 = csub(v[0], v[6]);
+  const T e1 = csub(v[0], mul_i<DIR>(v[6])), e3 = cadd(v[0], mul_i<DIR>(v[6]));
+  const T o0 = cadd(v[1], v[7]), o2 = csub(v[1], v[7]);
+  const T o1 = csub(v[1], mul_i<DIR>(v[7])), o3 = cadd(v[1], mul_i<DIR>(v[7]));
+  const T t1 = CT<T>::mk(h * (o1.x - DIR * o1.y), h * (o1.y + DIR * o1.x));
+  const T t2 = mul_i<DIR>(o2);
+  const T t3 = CT<T>::mk(h * (-o3.x - DIR * o3.y), h * (-o3.y + DIR * o3.x));
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+
+template <int DIR, int N2, int K1, class T>
+__device__ __forceinline__ void tw_row(T (&y)[8][8]) {
+  if constexpr (K1 < 8) {
+    y[N2][K1] = tw64<DIR, N2 * K1>(y[N2][K1]);
+    tw_row<DIR, N2, K1 + 1>(y);
+  }
+}
+template <int DIR, int N2, class T>
+__device__ __forceinline__ void tw_all(T (&y)[8][8]) {
+  if constexpr (N2 < 8) {
+    tw_row<DIR, N2, 1>(y);
+    tw_all<DIR, N2 + 1>(y);
+  }
+}
+
+// In-register 64-point DFT, natural order in and out: v_k = sum_n v_n w^(n k).
+// INZ: inputs with n / 8 in 2..5 are zero; the outputs with k / 8 in 2..5 are
+// left unset when the caller never reads them (dead code).
+template <int DIR, bool INZ, class T>
+__device__ __forceinline__ void fft64_reg(T (&v)[64]) {
+  T y[8][8];  // y[n2][k1]
+#pragma unroll
+  for (int n2 = 0; n2 < 8; ++n2) {
+    T u[8];
+#pragma unroll
+    for (int n1 = 0; n1 < 8; ++n1) u[n1] = v[8 * n1 + n2];
+    if constexpr (INZ) dft8_z2345<DIR>(u);
+    else dft8<DIR>(u);
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) y[n2][k1] = u[k1];
+    __builtin_amdgcn_sched_barrier(0);  // one group at a time (register pressure)
+  }
+  tw_all<DIR, 1>(y);
+#pragma unroll
+  for (int k1 = 0; k1 < 8; ++k1) {
+    T u[8];
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) u[n2] = y[n2][k1];
+    dft8<DIR>(u);
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) v[k1 + 8 * k2] = u[k2];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// frequency index of position n of a 64-point transform, and whether n can be
+// inside a box of half-width <= 15 (compile-time)
+__host__ __device__ constexpr int freq64(int n) { return n <= 31 ? n : n - 64; }
+__host__ __device__ constexpr bool box64(int n) { return (n >> 3) < 2 || (n >> 3) > 5; }
+
+// LDS bytes of one plane's Theta V in k_rb_xzr (64 x 64 values at pitch 9 per x;
+// the layout the x/z kernels read is [((y 8 + k2) 64 + x) 8 + k1], z = k1 + 8 k2)
+template <class T>
+__host__ __device__ constexpr size_t xzr_wbytes() {
+  return ((size_t)8 * 64 * 9 * sizeof(typename CT<T>::R) + 15) / 16 * 16;
+}
+
+template <int NW, class T>
+__global__ __launch_bounds__(NW * 64) void k_rb_xzr(const Grid g, const FftKArgs ka, int ncols,
+                                                   const typename CT<T>::R *__restrict__ thp) {
+  using RT = typename CT<T>::R;
+  constexpr int RP = 65;  // LDS row pitch (odd)
+  extern __shared__ double2 sm_raw[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = blockIdx.y, kk = blockIdx.z;
+  const int y = blockIdx.x * NW + wave;
+  const int n2 = g.n2, bx = g.bx, nbx = g.nbx, bz = g.bz, nbz = g.nbz;
+  if (y >= n2) return;  // the whole wave; no block barrier in this kernel
+  // per wave: Theta V of the plane, Wl[(k2 64 + x) 9 + k1] (pitch 9 per x: no
+  // bank conflicts), then the rows R[nbz][RP]
+  RT *Wl = reinterpret_cast<RT *>(reinterpret_cast<char *>(sm_raw) +
+                                  (size_t)wave * (xzr_wbytes<T>() + (size_t)nbz * RP * sizeof(T)));
+  T *R = reinterpret_cast<T *>(reinterpret_cast<char *>(Wl) + xzr_wbytes<T>());
+  {  // Theta V of the plane: 4096 contiguous values, coalesced, into Wl
+    const RT *src = thp + (long long)y * 4096;
+#pragma unroll 16
+    for (int it = 0; it < 64; ++it) {
+      const int e = it * 64 + lane;
+      Wl[(e >> 3) * 9 + (e & 7)] = src[e];
+    }
+  }
+  const long long csz = (long long)nbz * n2 * nbx, rs = (long long)n2 * nbx;
+  const T *in = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)y * nbx;
+  T *out = reinterpret_cast<T *>(ka.slab_out[kk]) + (long long)col * csz + (long long)y * nbx;
+  const T zero = CT<T>::mk(0, 0);
+  T v[64];
+
+  // phase 1: inverse x transform of box row `lane`
+  if (lane < nbz) {
+    const T *row = in + (long long)lane * rs;
+#pragma unroll
+    for (int n = 0; n < 64; ++n) {
+      if (!box64(n)) {
+        v[n] = zero;
+      } else {
+        const int kx = freq64(n);
+        const int e = kx + bx < 0 ? 0 : (kx + bx > nbx - 1 ? nbx - 1 : kx + bx);
+        const T t = row[e];
+        v[n] = (kx >= -bx && kx <= bx) ? t : zero;
+      }
+    }
+    fft64_reg<1, true>(v);
+#pragma unroll
+    for (int k = 0; k < 64; ++k) R[lane * RP + k] = v[k];
+  }
+  wave_fence();
+
+  // phase 2: z column `lane`: inverse, times Theta V, forward (box outputs only).
+  // The inverse's second pass for a fixed k1 yields z = k1 + 8 k2 (k2 = 0..7),
+  // exactly the values the forward's first pass takes for n1 = k1, so the
+  // product with Theta V runs group by group (eight of its values live at once).
+  {
+    const int x = lane;
+#pragma unroll
+    for (int n = 0; n < 64; ++n) {
+      if (!box64(n)) {
+        v[n] = zero;
+      } else {
+        const int kz = freq64(n);
+        const int r = kz + bz < 0 ? 0 : (kz + bz > nbz - 1 ? nbz - 1 : kz + bz);
+        const T t = R[r * RP + x];
+        v[n] = (kz >= -bz && kz <= bz) ? t : zero;
+      }
+    }
+    T yq[8][8];  // inverse first pass: yq[n2][k1]
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) {
+      T u[8];
+#pragma unroll
+      for (int n1 = 0; n1 < 8; ++n1) u[n1] = v[8 * n1 + n2];
+      dft8_z2345<1>(u);
+#pragma unroll
+      for (int k1 = 0; k1 < 8; ++k1) yq[n2][k1] = u[k1];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    tw_all<1, 1>(yq);
+    T f[8][8];  // forward first pass output f[n1 = k1][m2]
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+      RT wc[8];
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) wc[k2] = Wl[(k2 * 64 + x) * 9 + k1];
+      T t[8];
+#pragma unroll
+      for (int n2 = 0; n2 < 8; ++n2) t[n2] = yq[n2][k1];
+      dft8<1>(t);  // t[k2]: the inverse at z = k1 + 8 k2
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) t[k2] = cscale(t[k2], wc[k2]);
+      dft8<-1>(t);  // over n2 = k2 for n1 = k1: t[m2]
+#pragma unroll
+      for (int m2 = 0; m2 < 8; ++m2) f[k1][m2] = t[m2];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    tw_all<-1, 1>(f);  // w^(-n1 m2)
+#pragma unroll
+    for (int m2 = 0; m2 < 8; ++m2) {
+      T u[8];
+#pragma unroll
+      for (int n1 = 0; n1 < 8; ++n1) u[n1] = f[n1][m2];
+      dft8<-1>(u);  // u[m1]: output m = 8 m1 + m2
+#pragma unroll
+      for (int m1 = 0; m1 < 8; ++m1) {
+        const int m = 8 * m1 + m2;
+        if (!box64(m)) continue;
+        const int kz = freq64(m);
+        if (kz >= -bz && kz <= bz) R[(kz + bz) * RP + x] = u[m1];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  wave_fence();
+
+  // phase 3: forward x transform of box row `lane`, box columns out
+  if (lane < nbz) {
+#pragma unroll
+    for (int n = 0; n < 64; ++n) v[n] = R[lane * RP + n];
+    fft64_reg<-1, false>(v);
+    T *orow = out + (long long)lane * rs;
+#pragma unroll
+    for (int m = 0; m < 64; ++m) {
+      if (!box64(m)) continue;
+      const int kx = freq64(m);
+      if (kx >= -bx && kx <= bx) orow[kx + bx] = v[m];
+    }
+  }
+}
+
 // One axis pass of the W synthesis with the axis matrix given by its Dirichlet
 // table: M[j'][j] = tab[(c1 j' - c2 j) mod L] (c1 = N/g, c2 = N'/g, L = N N'/g,
 // g = gcd(N, N')), so that the block stages L values instead of N' N.
@@ -1163,7 +1428,12 @@ size_t rb_xz_lds(const Grid &g) {
 
 // Launch shapes of k_rb_xz4 (waves per block, z columns per wave), the
 // candidates of the tuner: 0 = (4, LZ), 1 = (2, LZ), 2 = (4, LZ / 2), LZ as rb_lz.
-constexpr int RB_VARIANTS = 3;
+constexpr int RB_VARIANTS = 3;  // launch shapes of k_rb_xz4; shape RB_VARIANTS is k_rb_xzr
+// planes (waves) per block of k_rb_xzr: its LDS (Theta V and rows per plane) within 160 KB.
+// Only the complex64 instance is launched: 64 complex128 values per lane would
+// not fit the 256 architectural VGPRs.
+template <class T>
+constexpr int xzr_nw() { return sizeof(T) == 16 ? 2 : 4; }
 constexpr int rb_nw_of(int v) { return v == 1 ? 2 : 4; }
 template <int N, int F1>
 constexpr int rb_lz_of(int v) {
@@ -1214,6 +1484,7 @@ void each_plane_kernel(F &&f) {
   reg_xz4<72, 8, float2>(f);
   reg_xz4<64, 8, float2>(f);
   reg_xz4<16, 4, float2>(f);
+  f((const void *)k_rb_xzr<xzr_nw<float2>(), float2>);
   f((const void *)k_inv_plane<0, 0>);
   f((const void *)k_fwd_plane<0, 0>);
 #define LTD_PL(a, b)                            \
@@ -1396,14 +1667,29 @@ hipError_t fft_rb_cache(const Grid &g, const FftKArgs &ka, int nk, int ncols, hi
   return hipGetLastError();
 }
 
-int fft_rb_variants() { return RB_VARIANTS; }
+int fft_rb_variants(const Grid &g, bool fp32) {
+  return (fp32 && g.n1 == 64 && g.n3 == 64 && g.bx <= 15 && g.bz <= 15) ? RB_VARIANTS + 1 : RB_VARIANTS;
+}
+
+namespace {
+template <class T>
+void launch_xzr(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s) {
+  constexpr int NW = xzr_nw<T>();
+  const dim3 grid((g.n2 + NW - 1) / NW, ncols, nk), block(64 * NW);
+  const size_t lds = (size_t)NW * (xzr_wbytes<T>() + (size_t)g.nbz * 65 * sizeof(T));
+  hipLaunchKernelGGL((k_rb_xzr<NW, T>), grid, block, lds, s, g, ka, ncols,
+                     static_cast<const typename CT<T>::R *>(thv));
+}
+}  // namespace
 
 hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s,
                        int part, bool fp32, int variant) {
   set_attrs();
   const dim3 block(FFT_NT);
-  if (variant < 0 || variant >= RB_VARIANTS) return hipErrorInvalidValue;
-  if (part == 0 && rb_fast(g)) {
+  if (variant < 0 || variant >= fft_rb_variants(g, fp32)) return hipErrorInvalidValue;
+  if (part == 0 && variant == RB_VARIANTS) {  // register-resident: complex64 on 64-point grids
+    launch_xzr<float2>(g, ka, nk, ncols, thv, s);
+  } else if (part == 0 && rb_fast(g)) {
 #define LTD_XZ4P(n, f1)                                                  \
   do {                                                                   \
     if (fp32) launch_xz4<n, f1, float2>(g, ka, nk, ncols, thv, s, variant);  \

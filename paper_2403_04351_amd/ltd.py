@@ -161,10 +161,11 @@ class Ltd:
     def autotune(self):
         """Times the rebuild's launch shapes and projection split targets on the
         bound subspaces and keeps the fastest; returns the choice and the timings."""
-        choice = (C.c_int * 2)()
+        choice = (C.c_int * 3)()
         times = (C.c_double * 16)()
         check(self.lib.ltd_autotune(self.handle, choice, times, self.stream()), "ltd_autotune")
-        return dict(xz_shape=choice[0], projection_blocks=choice[1], times_us=list(times[:7]))
+        return dict(xz_shape=choice[0], projection_blocks=choice[1], n_shapes=choice[2],
+                    times_us=list(times[:choice[2] + 4]))
 
     def set_tuning(self, xz_shape, projection_blocks):
         """Sets the rebuild's launch shape and the projection split target."""

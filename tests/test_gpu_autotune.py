@@ -1,10 +1,13 @@
 """Tuned launch shapes of the per-step rebuild (batched k-points: tiles chosen
 by a tuner).
 
-* Every launch shape of the x/z transform kernel computes the same arithmetic in
-  the same order, so the propagated states are bit-identical across shapes, in
-  FP64 and in the FP32 residual mode, on the tiny system (16^3 transforms) and
-  on the molecule (72^3 grid rebuilt on 64^3).
+* The three launch shapes of the two-factor x/z kernel compute the same
+  arithmetic in the same order, so the propagated states are bit-identical
+  across them, in FP64 and in the FP32 residual mode, on the tiny system (16^3
+  transforms) and on the molecule (72^3 grid rebuilt on 64^3).
+* The register-resident kernel (FP32 residual, 64-point rebuild grid) takes
+  another summation order: its states agree with the two-factor kernel's to
+  FP32 rounding and with the oracle to the mixed-precision bound.
 * The tuner returns a valid choice, and the steps after it (its projection
   split only reorders a sum) match the oracle to the FP64 bound.
 """
@@ -67,10 +70,21 @@ def test_launch_shapes_bit_identical_and_tuned_steps_match_oracle(cfg, precision
     for v in (1, 2):
         assert np.array_equal(shapes[v][0], shapes[0][0]), f"launch shape {v} differs"
         assert np.array_equal(shapes[v][1], shapes[0][1])
+    n_shapes = 4 if (precision == "LTD_FP32_RESID" and cfg == 1) else 3
+    if n_shapes == 4:
+        lt.set_tuning(3, 512)
+        th3, j3 = run()
+        d = rel_max(th3, shapes[0][0])
+        print(f"[tune cfg{cfg} {precision}] register kernel vs two-factor: theta {d:.2e}", flush=True)
+        assert d < 1e-6
+    else:
+        with pytest.raises(Exception):
+            lt.set_tuning(3, 512)
     tuned = lt.autotune()
     print(f"[tune cfg{cfg} {precision}] choice {tuned}", flush=True)
-    assert 0 <= tuned["xz_shape"] < 3 and tuned["projection_blocks"] in (256, 512, 1024, 2048)
-    assert all(t > 0 for t in tuned["times_us"])
+    assert tuned["n_shapes"] == n_shapes
+    assert 0 <= tuned["xz_shape"] < n_shapes and tuned["projection_blocks"] in (256, 512, 1024, 2048)
+    assert len(tuned["times_us"]) == n_shapes + 4 and all(t > 0 for t in tuned["times_us"])
     th, j = run()
 
     v_ref = ss.rebuild_v_sub(sys, 0, phi)
