@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -39,7 +40,8 @@ WORKLOADS = {
        "FFT grid 64^3, N_aux=80, N_states=20 per k, dt=0.2, all k in one launch per stage",
 }
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFS = 78.6
+FP64_PEAK_TFS = 78.6   # dense FP64 MFMA, and FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_PEAK_TFS = 157.3  # FP32 vector (packed); the kernels here issue unpacked FP32
 STAGES = ["potential", "xz_planes", "y_lines", "mt_blocks", "v_projection", "subspace_step", "map_back"]
 
 
@@ -56,7 +58,7 @@ def parse():
     p.add_argument("--potential", choices=["series", "static"], default="series",
                    help="rebuild from a per-step potential series (default) or from one potential")
     p.add_argument("--profile-steps", type=int, default=20)
-    p.add_argument("--cpu-steps", type=int, default=6)
+    p.add_argument("--cpu-steps", type=int, default=50)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run 5 plain device-to-device copies of MIB MiB (counter calibration)")
@@ -84,9 +86,24 @@ def stage_bytes(sysd, n, nbx, nbz, rgrid, es=16):
     }
 
 
-def traffic_from_profiles(kernel_file, stage, precision):
+def stage_flops(sysd, n, nbx, nbz, rgrid):
+    """Algorithmic floating-point operations of the transform stages (5 L log2 L
+    per complex transform of length L, 2 per complex-by-real product), summed
+    over the k-points.  x/z planes: per column and rebuild plane y', inverse and
+    forward x transforms of the nbz box rows, and per grid column x the inverse
+    z transform, the product with Theta V and the forward z transform."""
+    n1, n2, n3 = rgrid
+    nk = len(sysd.kpts)
+    f = lambda L: 5.0 * L * math.log2(L)
+    xz = n * n2 * (2 * nbz * f(n1) + n1 * (2 * f(n3) + 2 * n3)) * nk
+    y = n * nbz * nbx * f(n2) * nk
+    return {"xz_planes": xz, "y_lines": y}
+
+
+def traffic_from_profiles(kernel_file, stage, precision, config):
     """HBM traffic of the dominant kernel from committed rocprofv3 counter runs,
-    valid only for the same stage and precision while the kernel source is unchanged."""
+    valid only for the same workload, stage and precision while the kernel source
+    is unchanged."""
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
     if not os.path.exists(path):
         return None
@@ -96,6 +113,8 @@ def traffic_from_profiles(kernel_file, stage, precision):
         if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
             return None
         if rec.get("stage") != stage or rec.get("precision", "fp64") != precision:
+            return None
+        if rec.get("config") != config:
             return None
         return rec.get("bytes_per_launch")
     except Exception:
@@ -269,9 +288,21 @@ def main():
     dom_us = hbm_stages[dom]
     achieved = sb[dom] / (dom_us * 1e-6) / 1e9
     kernel_file = "fft.hip" if dom in ("potential", "xz_planes", "y_lines") else "api.hip"
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_from_profiles(kernel_file, dom, args.precision),
-                    bytes_per_launch=sb[dom], avg_launch_us=dom_us)
+    traffic = traffic_from_profiles(kernel_file, dom, args.precision, args.config)
+    fl = stage_flops(sysd, sysd.n_aux, nbx, nbz, rgrid).get(dom)
+    alu_peak = FP64_PEAK_TFS if args.precision == "fp64" else FP32_PEAK_TFS
+    # the binding roofline: the resource whose peak needs the longer time for the stage's work
+    if fl is not None and fl / (alu_peak * 1e12) > sb[dom] / (HBM_PEAK_GBS * 1e9):
+        tf = fl / (dom_us * 1e-6) / 1e12
+        roofline = dict(bound="alu", kernel=dom, achieved=round(tf, 2), peak=alu_peak, unit="TFLOP/s",
+                        frac=round(tf / alu_peak, 4), traffic=traffic, flops_per_launch=fl,
+                        bytes_per_launch=sb[dom], avg_launch_us=dom_us,
+                        hbm=dict(achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                                 frac=round(achieved / HBM_PEAK_GBS, 4)))
+    else:
+        roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, bytes_per_launch=sb[dom],
+                        avg_launch_us=dom_us)
 
     # H-apply MFMA rate: the muffin-tin GEMMs of one apply at n = N_aux
     apms, _, _ = lt.profile_apply(0, phi)
