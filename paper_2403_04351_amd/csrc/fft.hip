@@ -754,6 +754,22 @@ __device__ __forceinline__ void twiddle_powers(T *v, T w) {
   }
 }
 
+// LDS layout of k_rb_xz4.  On 64-point lines (8 x 8) the exchange slots of
+// value (i, j) of a line's 8 x 8 block are i 8 + (j ^ i) (XOR swizzle), the
+// rows have pitch 66 (complex128) or 68 (complex64) and the two rows a 16-lane
+// group touches are r and r + 4, and the z scratch lines are 72 apart: every
+// access of the kernel then hits distinct LDS banks (16-lane groups of 16-byte
+// accesses).  Other lengths keep odd pitches.
+template <int NX, int X1, int NZ, int Z1>
+constexpr bool xz4_swz() { return NX == 64 && X1 == 8 && NZ == 64 && Z1 == 8; }
+template <int NX, int X1, int NZ, int Z1, class T>
+constexpr int xz4_rx() { return xz4_swz<NX, X1, NZ, Z1>() ? (sizeof(T) == 16 ? 66 : 68) : rb_pitch(NX); }
+template <int NX, int X1, int NZ, int Z1>
+constexpr int xz4_ls() { return xz4_swz<NX, X1, NZ, Z1>() ? 72 : Two<NZ, Z1, NZ / Z1>::LS; }
+// exchange slot of (i, j) in a block of rows of length `pitch` (swizzled or plain)
+template <bool SWZ>
+__device__ __forceinline__ int xslot(int i, int j, int pitch) { return SWZ ? i * 8 + (j ^ i) : i * pitch + j; }
+
 // Same transforms with NW waves per block: an x row exchanges in place through
 // its own RX slots (value (k1, n2) at slot k1 F2 + n2, odd stride across lanes);
 // the z columns exchange through a per-wave scratch of LZ lines.
@@ -765,26 +781,30 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
   using TX = Two<NX, X1, X2>;
   using TZ = Two<NZ, Z1, Z2>;
   static_assert(LZ <= TZ::LPW, "z lines per wave");
-  constexpr int RX = rb_pitch(NX);
+  constexpr bool SWZ = xz4_swz<NX, X1, NZ, Z1>();
+  constexpr int RX = xz4_rx<NX, X1, NZ, Z1, T>();
+  constexpr int LS = xz4_ls<NX, X1, NZ, Z1>();
   extern __shared__ double2 sm_raw[];
   T *sm = reinterpret_cast<T *>(sm_raw);
   const int col = blockIdx.x, y = blockIdx.y, kk = blockIdx.z;
   const int n2 = g.n2, bx = g.bx, nbx = g.nbx, bz = g.bz, nbz = g.nbz;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T *R = sm;
-  T *scr = sm + nbz * RX + wave * (LZ * TZ::LS);
+  T *scr = sm + nbz * RX + wave * (LZ * LS);
   const long long csz = (long long)nbz * n2 * nbx;
   const long long rs = (long long)n2 * nbx;  // kz stride of the box arrays
   const T *in = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)y * nbx;
   T *out = reinterpret_cast<T *>(ka.slab_out[kk]) + (long long)col * csz + (long long)y * nbx;
   const int lx = lane / TX::G, rx = lane - lx * TX::G;
   const int lz = lane / TZ::G, rz = lane - lz * TZ::G;
+  // row of line lx within a wave's group of LPW rows (SWZ: a 16-lane group takes rows r, r + 4)
+  const int lxr = SWZ ? ((lx >> 1) | ((lx & 1) << 2)) : lx;
 
   // phase 1: inverse x transforms of the box rows, in place in R
   {
     const T w = CT<T>::from(cconj(g.tw1[rx < NX ? rx : 0]));
     for (int r0 = wave * TX::LPW; r0 < nbz; r0 += NW * TX::LPW) {
-      const int r = r0 + lx;
+      const int r = r0 + lxr;
       const bool on = lx < TX::LPW && r < nbz;
       T *row = R + r * RX;
       if (on && rx < X2) {
@@ -798,13 +818,13 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         dft_reg<X1, 1>(v);
         twiddle_powers<X1>(v, w);
 #pragma unroll
-        for (int k1 = 0; k1 < X1; ++k1) row[k1 * X2 + rx] = v[k1];
+        for (int k1 = 0; k1 < X1; ++k1) row[xslot<SWZ>(k1, rx, X2)] = v[k1];
       }
       wave_fence();
       if (on && rx < X1) {
         T u[X2];
 #pragma unroll
-        for (int q = 0; q < X2; ++q) u[q] = row[rx * X2 + q];
+        for (int q = 0; q < X2; ++q) u[q] = row[xslot<SWZ>(rx, q, X2)];
         dft_reg<X2, 1>(u);
         wave_fence();
 #pragma unroll
@@ -821,7 +841,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
     for (int x0 = wave * LZ; x0 < NX; x0 += NW * LZ) {
       const int x = x0 + lz;
       const bool on = lz < LZ && x < NX;
-      T *sl = scr + lz * TZ::LS;
+      T *sl = scr + lz * LS;
       if (on && rz < Z2) {
         T v[Z1];
 #pragma unroll
@@ -833,7 +853,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         dft_reg<Z1, 1>(v);
         twiddle_powers<Z1>(v, w);
 #pragma unroll
-        for (int k1 = 0; k1 < Z1; ++k1) sl[rz * TZ::P + k1] = v[k1];
+        for (int k1 = 0; k1 < Z1; ++k1) sl[xslot<SWZ>(rz, k1, TZ::P)] = v[k1];
       }
       wave_fence();
       if (on && rz < Z1) {
@@ -842,7 +862,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         for (int k2 = 0; k2 < Z2; ++k2) t[k2] = thp[(((long long)y * Z2 + k2) * NX + x) * Z1 + rz];
         T u[Z2];
 #pragma unroll
-        for (int q = 0; q < Z2; ++q) u[q] = sl[q * TZ::P + rz];
+        for (int q = 0; q < Z2; ++q) u[q] = sl[xslot<SWZ>(q, rz, TZ::P)];
         dft_reg<Z2, 1>(u);
 #pragma unroll
         for (int k2 = 0; k2 < Z2; ++k2) u[k2] = cscale(u[k2], t[k2]);
@@ -850,13 +870,13 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         twiddle_powers<Z2>(u, wc);
         wave_fence();
 #pragma unroll
-        for (int d = 0; d < Z2; ++d) sl[rz * TZ::P + d] = u[d];
+        for (int d = 0; d < Z2; ++d) sl[xslot<SWZ>(rz, d, TZ::P)] = u[d];
       }
       wave_fence();
       if (on && rz < Z2) {
         T v[Z1];
 #pragma unroll
-        for (int a = 0; a < Z1; ++a) v[a] = sl[a * TZ::P + rz];
+        for (int a = 0; a < Z1; ++a) v[a] = sl[xslot<SWZ>(a, rz, TZ::P)];
         dft_reg<Z1, -1>(v);
 #pragma unroll
         for (int c = 0; c < Z1; ++c) {
@@ -873,7 +893,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
   {
     const T wc = CT<T>::from(g.tw1[rx < NX ? rx : 0]);
     for (int r0 = wave * TX::LPW; r0 < nbz; r0 += NW * TX::LPW) {
-      const int r = r0 + lx;
+      const int r = r0 + lxr;
       const bool on = lx < TX::LPW && r < nbz;
       T *row = R + r * RX;
       if (on && rx < X1) {
@@ -884,13 +904,13 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         twiddle_powers<X2>(u, wc);
         wave_fence();
 #pragma unroll
-        for (int d = 0; d < X2; ++d) row[rx * X2 + d] = u[d];
+        for (int d = 0; d < X2; ++d) row[xslot<SWZ>(rx, d, X2)] = u[d];
       }
       wave_fence();
       if (on && rx < X2) {
         T v[X1];
 #pragma unroll
-        for (int a = 0; a < X1; ++a) v[a] = row[a * X2 + rx];
+        for (int a = 0; a < X1; ++a) v[a] = row[xslot<SWZ>(a, rx, X2)];
         dft_reg<X1, -1>(v);
 #pragma unroll
         for (int c = 0; c < X1; ++c) {
@@ -1452,12 +1472,12 @@ template <int N, int F1, class T>
 void launch_xz4(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s, int v) {
   using TZ = Two<N, F1, N / F1>;
   const auto *th = static_cast<const typename CT<T>::R *>(thv);
-  const size_t fixed = (size_t)g.nbz * rb_pitch(N);
+  const size_t fixed = (size_t)g.nbz * xz4_rx<N, F1, N, F1, T>();
   const dim3 grid(ncols, g.n2, nk);
 #define LTD_V(V)                                                                                                \
   do {                                                                                                          \
     constexpr int NW = rb_nw_of(V), LZ = rb_lz_of<N, F1>(V);                                                    \
-    const size_t lds = (fixed + (size_t)NW * LZ * TZ::LS) * sizeof(T);                                          \
+    const size_t lds = (fixed + (size_t)NW * LZ * xz4_ls<N, F1, N, F1>()) * sizeof(T);                           \
     hipLaunchKernelGGL((k_rb_xz4<N, F1, N / F1, N, F1, N / F1, NW, LZ, T>), grid, dim3(NW * 64), lds, s, g, ka, \
                        ncols, th);                                                                              \
   } while (0)
