@@ -82,6 +82,29 @@ __device__ inline void dft8(T *v) {
   v[7] = csub(e3, t3);
 }
 
+// Length-8 DFT whose inputs 2..5 are zero (only v[0], v[1], v[6], v[7] read).
+template <int DIR, class T>
+__device__ __forceinline__ void dft8_z2345(T *v) {
+  using R = typename CT<T>::R;
+  const R h = (R)SQ1_2;
+  // the two length-4 DFTs of (v0, 0, 0, v6) and (v1, 0, 0, v7)
+  const T e0 = cadd(v[0], v[6]), e2 = csub(v[0], v[6]);
+  const T e1 = csub(v[0], mul_i<DIR>(v[6])), e3 = cadd(v[0], mul_i<DIR>(v[6]));
+  const T o0 = cadd(v[1], v[7]), o2 = csub(v[1], v[7]);
+  const T o1 = csub(v[1], mul_i<DIR>(v[7])), o3 = cadd(v[1], mul_i<DIR>(v[7]));
+  const T t1 = CT<T>::mk(h * (o1.x - DIR * o1.y), h * (o1.y + DIR * o1.x));
+  const T t2 = mul_i<DIR>(o2);
+  const T t3 = CT<T>::mk(h * (-o3.x - DIR * o3.y), h * (-o3.y + DIR * o3.x));
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+
 template <int DIR, class T>
 __device__ inline void dft3(T *v) {
   using R = typename CT<T>::R;
@@ -811,11 +834,16 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         T v[X1];
 #pragma unroll
         for (int n1 = 0; n1 < X1; ++n1) {
+          if (SWZ && n1 >= 2 && n1 <= 5) {  // |freq| >= 16 > b: zero (dropped by dft8_z2345)
+            v[n1] = CT<T>::mk(0, 0);
+            continue;
+          }
           const int n = X2 * n1 + rx;
           const int kx = n <= bx ? n : n - NX;
           v[n1] = (n <= bx || n >= NX - bx) ? in[r * rs + kx + bx] : CT<T>::mk(0, 0);
         }
-        dft_reg<X1, 1>(v);
+        if constexpr (SWZ) dft8_z2345<1>(v);
+        else dft_reg<X1, 1>(v);
         twiddle_powers<X1>(v, w);
 #pragma unroll
         for (int k1 = 0; k1 < X1; ++k1) row[xslot<SWZ>(k1, rx, X2)] = v[k1];
@@ -842,24 +870,31 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
       const int x = x0 + lz;
       const bool on = lz < LZ && x < NX;
       T *sl = scr + lz * LS;
+      // Theta V of this column (used after the inverse): loads issued first
+      RT t[Z2];
+#pragma unroll
+      for (int k2 = 0; k2 < Z2; ++k2)
+        t[k2] = thp[(((long long)y * Z2 + k2) * NX + (x < NX ? x : NX - 1)) * Z1 + (rz < Z1 ? rz : 0)];
       if (on && rz < Z2) {
         T v[Z1];
 #pragma unroll
         for (int n1 = 0; n1 < Z1; ++n1) {
+          if (SWZ && n1 >= 2 && n1 <= 5) {
+            v[n1] = CT<T>::mk(0, 0);
+            continue;
+          }
           const int n = Z2 * n1 + rz;
           const int row = n <= bz ? n + bz : n - NZ + bz;
           v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : CT<T>::mk(0, 0);
         }
-        dft_reg<Z1, 1>(v);
+        if constexpr (SWZ) dft8_z2345<1>(v);
+        else dft_reg<Z1, 1>(v);
         twiddle_powers<Z1>(v, w);
 #pragma unroll
         for (int k1 = 0; k1 < Z1; ++k1) sl[xslot<SWZ>(rz, k1, TZ::P)] = v[k1];
       }
       wave_fence();
       if (on && rz < Z1) {
-        RT t[Z2];
-#pragma unroll
-        for (int k2 = 0; k2 < Z2; ++k2) t[k2] = thp[(((long long)y * Z2 + k2) * NX + x) * Z1 + rz];
         T u[Z2];
 #pragma unroll
         for (int q = 0; q < Z2; ++q) u[q] = sl[xslot<SWZ>(q, rz, TZ::P)];
@@ -880,6 +915,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         dft_reg<Z1, -1>(v);
 #pragma unroll
         for (int c = 0; c < Z1; ++c) {
+          if (SWZ && c >= 2 && c <= 5) continue;  // |freq| >= 16 > b: never needed
           const int m = Z2 * c + rz;
           if (m <= bz || m >= NZ - bz) R[(m <= bz ? m + bz : m - NZ + bz) * RX + x] = v[c];
         }
@@ -914,6 +950,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         dft_reg<X1, -1>(v);
 #pragma unroll
         for (int c = 0; c < X1; ++c) {
+          if (SWZ && c >= 2 && c <= 5) continue;
           const int m = X2 * c + rx;
           if (m <= bx || m >= NX - bx) out[r * rs + (m <= bx ? m : m - NX) + bx] = v[c];
         }
@@ -976,29 +1013,6 @@ __device__ __forceinline__ T tw64(T v) {
     constexpr double c = cos64(j), sn = DIR * sin64(j);
     return CT<T>::mk((R)c * v.x - (R)sn * v.y, (R)c * v.y + (R)sn * v.x);
   }
-}
-
-// Length-8 DFT whose inputs 2..5 are zero (only v[0], v[1], v[6], v[7] read).
-template <int DIR, class T>
-__device__ __forceinline__ void dft8_z2345(T *v) {
-  using R = typename CT<T>::R;
-  const R h = (R)SQ1_2;
-  // the two length-4 DFTs of (v0, 0, 0, v6) and (v1, 0, 0, v7)
-  const T e0 = cadd(v[0], v[6]), e2 = csub(v[0], v[6]);
-  const T e1 = csub(v[0], mul_i<DIR>(v[6])), e3 = cadd(v[0], mul_i<DIR>(v[6]));
-  const T o0 = cadd(v[1], v[7]), o2 = csub(v[1], v[7]);
-  const T o1 = csub(v[1], mul_i<DIR>(v[7])), o3 = cadd(v[1], mul_i<DIR>(v[7]));
-  const T t1 = CT<T>::mk(h * (o1.x - DIR * o1.y), h * (o1.y + DIR * o1.x));
-  const T t2 = mul_i<DIR>(o2);
-  const T t3 = CT<T>::mk(h * (-o3.x - DIR * o3.y), h * (-o3.y + DIR * o3.x));
-  v[0] = cadd(e0, o0);
-  v[4] = csub(e0, o0);
-  v[1] = cadd(e1, t1);
-  v[5] = csub(e1, t1);
-  v[2] = cadd(e2, t2);
-  v[6] = csub(e2, t2);
-  v[3] = cadd(e3, t3);
-  v[7] = csub(e3, t3);
 }
 
 template <int DIR, int N2, int K1, class T>
@@ -1185,6 +1199,61 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xzr(const Grid g, const FftKArgs
       const int kx = freq64(m);
       if (kx >= -bx && kx <= bx) orow[kx + bx] = v[m];
     }
+  }
+}
+
+// y transforms of the rebuild step for N2' = 64 and nbx <= 32: one block per
+// (kz, column), one line per box x (4 waves x 8 lines x 8 lanes), each line the
+// two-factor forward transform of k_rb_xz4's phase 3 in place in its LDS row
+// (pitch 66, rows r and r + 4 in a 16-lane group, XOR-swizzled exchange); then
+// the sphere read-out as in k_rb_y.
+template <class T>
+__global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka, int ncols) {
+  constexpr int N = 64, BP = 66;
+  extern __shared__ double2 sm_raw[];
+  T *bxc = reinterpret_cast<T *>(sm_raw);
+  const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
+  const int nbx = g.nbx, bx = g.bx;
+  const KSphere &sp = ka.sph[kk];
+  const FwdOut &fo = ka.out[kk];
+  const long long csz = (long long)g.nbz * N * nbx;
+  const T *src = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)pz * N * nbx;
+  stage8<T>(
+      N * nbx, [&](int i) { return src[i]; }, [&](int i, T x) { bxc[(i % nbx) * BP + i / nbx] = x; });
+  __syncthreads();
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = lane >> 3, rx = lane & 7;
+    const int line = wave * 8 + ((lx >> 1) | ((lx & 1) << 2));
+    if (line < nbx) {
+      T *row = bxc + line * BP;
+      const T wc = CT<T>::from(g.tw2[rx]);
+      T u[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) u[b] = row[rx + 8 * b];
+      dft8<-1>(u);
+      twiddle_powers<8>(u, wc);
+      wave_fence();
+#pragma unroll
+      for (int d = 0; d < 8; ++d) row[xslot<true>(rx, d, 8)] = u[d];
+      wave_fence();
+      T v[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) v[a] = row[xslot<true>(a, rx, 8)];
+      dft8<-1>(v);
+      wave_fence();
+#pragma unroll
+      for (int c = 0; c < 8; ++c) row[8 * c + rx] = v[c];
+    }
+  }
+  __syncthreads();
+  const double inv_n = 1.0 / ((double)g.n1 * N * g.n3);
+  const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
+  for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+    const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+    const int yy = xy / g.d1, x = xy - yy * g.d1;
+    const int yr = yy <= g.by ? yy : yy - g.d2 + N;
+    fo.o0[gi + (long long)col * fo.ld0] = cscale(to_d2(bxc[box_of(x, g.d1, bx) * BP + yr]), inv_n);
   }
 }
 
@@ -1741,7 +1810,11 @@ hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, con
     if (fp32) hipLaunchKernelGGL((k_rb_y<a, float2>), grid, block, lds, s, g, ka, ncols); \
     else hipLaunchKernelGGL((k_rb_y<a, double2>), grid, block, lds, s, g, ka, ncols);     \
   } while (0)
-    if (g.n2 == 16) LTD_RY(16);
+    if (g.n2 == 64 && g.nbx <= 32) {
+      const size_t lds64 = (size_t)g.nbx * 66 * (fp32 ? sizeof(float2) : sizeof(double2));
+      if (fp32) hipLaunchKernelGGL(k_rb_y64<float2>, grid, dim3(256), lds64, s, g, ka, ncols);
+      else hipLaunchKernelGGL(k_rb_y64<double2>, grid, dim3(256), lds64, s, g, ka, ncols);
+    } else if (g.n2 == 16) LTD_RY(16);
     else if (g.n2 == 64) LTD_RY(64);
     else if (g.n2 == 72) LTD_RY(72);
     else if (g.n2 == 96) LTD_RY(96);

@@ -410,11 +410,14 @@ __device__ void finalize_step(const StepCtx &c, int step) {
   *c.step_rw = step + 1;
 }
 
+// Threads per state block of the forward step (512 measured no faster).
+constexpr int STEP_NT = 256;
+
 // HL / PL: H~(mid) / P~ staged in LDS (compile-time, so that their reads are
 // LDS reads rather than generic ones).  The block that finishes last sums the
 // partials of every state (finalize_step).
 template <bool HL, bool PL>
-__global__ __launch_bounds__(256) void k_step(const StepCtx c) {
+__global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
   extern __shared__ double2 sm[];
   const int j = blockIdx.x, k = blockIdx.y;
   const SubDev &S = c.sub[k];
@@ -811,7 +814,8 @@ hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s
 size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint, bool p_in_lds) {
   const size_t vecs = adjoint ? 11 : 6;
   const size_t mats = (h_in_lds ? (size_t)n * n : 0) + ((!adjoint && p_in_lds) ? (size_t)n * n : 0);
-  return (mats + vecs * n + 256) * sizeof(double2) + 256 * sizeof(double);
+  const size_t nt = adjoint ? 256 : STEP_NT;  // one reduction slot per thread
+  return (mats + vecs * n + nt) * sizeof(double2) + 256 * sizeof(double);
 }
 
 hipError_t launch_conj_transpose(const double2 *a, double2 *out, int n, hipStream_t s) {
@@ -841,11 +845,11 @@ hipError_t launch_step(const StepCtx &c, hipStream_t s) {
   if (e0 != hipSuccess) return e0;
   const size_t lds = step_lds_bytes(c.n_aux, c.h_in_lds, false, c.p_in_lds);
   if (c.h_in_lds && c.p_in_lds)
-    hipLaunchKernelGGL((k_step<true, true>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c);
+    hipLaunchKernelGGL((k_step<true, true>), dim3(c.n_states, c.n_k), dim3(STEP_NT), lds, s, c);
   else if (c.h_in_lds)
-    hipLaunchKernelGGL((k_step<true, false>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c);
+    hipLaunchKernelGGL((k_step<true, false>), dim3(c.n_states, c.n_k), dim3(STEP_NT), lds, s, c);
   else
-    hipLaunchKernelGGL((k_step<false, false>), dim3(c.n_states, c.n_k), dim3(256), lds, s, c);
+    hipLaunchKernelGGL((k_step<false, false>), dim3(c.n_states, c.n_k), dim3(STEP_NT), lds, s, c);
   return hipGetLastError();
 }
 
