@@ -71,6 +71,7 @@ struct ZProb {
   double2 alpha, beta;
   // planner-filled
   int tiles_m, tiles_n, ksplit, kchunk;  // kchunk: K per split, multiple of the K tile
+  int bm;                                // output tile rows (64 or 32), the same for a whole launch
   int tile_begin;                        // first logical tile of this problem
   int rtile_begin;                       // first output tile (reduction pass)
   long long part_off;                    // offset (tiles) into the split-K partial buffer

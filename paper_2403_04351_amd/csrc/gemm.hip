@@ -5,8 +5,9 @@
 // and an optional split of the K dimension whose partial tiles are summed in a
 // fixed order by a second pass (deterministic, no atomics).
 //
-// Work decomposition: 64x64 output tiles, 256 threads = 4 wavefronts in a 2x2
-// arrangement, each wavefront owning a 32x32 block = 2x2 MFMA blocks of 16x16.
+// Work decomposition: MB x 64 output tiles (MB = 64 or 32, chosen per launch by
+// the planner), 256 threads = 4 wavefronts in a 2x2 arrangement, each
+// wavefront owning an (MB/2) x 32 block of 16x16 MFMA blocks.
 // A complex multiply-add is three real v_mfma_f64_16x16x4_f64 (the Gauss form
 // below).  Operand tiles (64 x 16 complex)
 // are staged through LDS as separate real and imaginary planes, double
@@ -23,10 +24,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256, LP = 2;  // LP: LDS row padding (doubles)
+// split-K partial tiles keep a BM x BN stride whatever the tile height
 
-struct Frag {
-  double2 v[4];
+template <int Q>
+struct FragN {
+  double2 v[Q];
 };
+using Frag = FragN<4>;
 
 __device__ inline int xcd_logical(int b, int g) {
   const int q = g / 8, rem = g % 8, x = b % 8, r = b / 8;
@@ -50,24 +54,27 @@ struct Ops {
 // Operand loads at clamped (in-bounds) indices, zeroed by value outside the
 // problem: no branch around a load, so the loads of a tile are all in flight
 // together.
-template <int OPA>
-__device__ inline void load_a(const Ops &o, int m0, int k0, int t, Frag &f) {
+// A tile MB x BK: QA = MB / 16 values per thread
+template <int OPA, int MB>
+__device__ inline void load_a(const Ops &o, int m0, int k0, int t, FragN<MB / 16> &f) {
+  constexpr int QA = MB / 16;
   if (OPA == OP_N) {  // A is m x k: tile column kk is contiguous in i
-    const int kk = t >> 4, i = (t & 15) * 4;
+    const int kk = t >> 4, i = (t & 15) * QA;
     const int kg = k0 + kk;
     const int kc = kg < o.kend ? kg : o.kend - 1;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QA; ++q) {
       const int ig = m0 + i + q;
       const double2 v = ldg(o.A + (long long)(ig < o.m ? ig : o.m - 1) + (long long)kc * o.lda);
       f.v[q] = (ig < o.m && kg < o.kend) ? v : make_double2(0.0, 0.0);
     }
   } else {  // A is k x m, op = conj-transpose: tile row i is contiguous in kk
-    const int i = t >> 2, kk = (t & 3) * 4;
+    constexpr int TPR = NT / MB;  // threads per tile row
+    const int i = t / TPR, kk = (t % TPR) * QA;
     const int ig = m0 + i;
     const int ic = ig < o.m ? ig : o.m - 1;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QA; ++q) {
       const int kg = k0 + kk + q;
       const double2 v = ldg(o.A + (long long)(kg < o.kend ? kg : o.kend - 1) + (long long)ic * o.lda);
       f.v[q] = (ig < o.m && kg < o.kend) ? v : make_double2(0.0, 0.0);
@@ -102,20 +109,22 @@ __device__ inline void load_b(const Ops &o, int n0, int k0, int t, Frag &f) {
   }
 }
 
-template <int OPA>
-__device__ inline void store_a(double (*As)[BK][BM + LP], int t, const Frag &f) {
+template <int OPA, int MB>
+__device__ inline void store_a(double (*As)[BK][MB + LP], int t, const FragN<MB / 16> &f) {
+  constexpr int QA = MB / 16;
   const double sg = (OPA == OP_C) ? -1.0 : 1.0;
   if (OPA == OP_N) {
-    const int kk = t >> 4, i = (t & 15) * 4;
+    const int kk = t >> 4, i = (t & 15) * QA;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QA; ++q) {
       As[0][kk][i + q] = f.v[q].x;
       As[1][kk][i + q] = f.v[q].y;
     }
   } else {
-    const int i = t >> 2, kk = (t & 3) * 4;
+    constexpr int TPR = NT / MB;
+    const int i = t / TPR, kk = (t % TPR) * QA;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QA; ++q) {
       As[0][kk + q][i] = f.v[q].x;
       As[1][kk + q][i] = sg * f.v[q].y;
     }
@@ -148,10 +157,11 @@ __device__ inline void store_b(double (*Bs)[BK][BN + LP], int t, const Frag &f) 
 // as three MFMA accumulators summed over K, so a complex multiply-add costs
 // three real MFMAs instead of four; the sums ar + ai, br + bi are formed after
 // the LDS reads.
-template <int OPA, int OPB, bool TABLE>
+template <int OPA, int OPB, bool TABLE, int MB>
 __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZProb *__restrict__ table,
                                                    int nprob, double2 *__restrict__ partials, int n_limit) {
-  __shared__ double As[2][2][BK][BM + LP];
+  constexpr int AW = MB / 32;  // 16-row MFMA blocks per wavefront
+  __shared__ double As[2][2][BK][MB + LP];
   __shared__ double Bs[2][2][BK][BN + LP];
 
   const ZProb *probs = TABLE ? table : batch.p;
@@ -168,7 +178,7 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
   const int bi = t % P.batch;
   const int ks = t / P.batch;
 
-  const int m0 = tm * BM, n0 = tn * BN;
+  const int m0 = tm * MB, n0 = tn * BN;
   Ops o;
   o.nlim = (n_limit > 0 && n_limit < P.n) ? n_limit : P.n;
   if (n0 >= o.nlim) return;  // whole block: columns beyond the limit
@@ -187,9 +197,9 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
-  d4 t1[2][2], t2[2][2], t3[2][2];
+  d4 t1[AW][2], t2[AW][2], t3[AW][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < AW; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       t1[a][b] = d4{0.0, 0.0, 0.0, 0.0};
@@ -197,11 +207,12 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
       t3[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
-  Frag fa, fb;
+  FragN<MB / 16> fa;
+  Frag fb;
   if (nkt > 0) {
-    load_a<OPA>(o, m0, kbeg, tid, fa);
+    load_a<OPA, MB>(o, m0, kbeg, tid, fa);
     load_b<OPB>(o, n0, kbeg, tid, fb);
-    store_a<OPA>(As[0], tid, fa);
+    store_a<OPA, MB>(As[0], tid, fa);
     store_b<OPB>(Bs[0], tid, fb);
   }
   __syncthreads();
@@ -210,16 +221,16 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
     const int cur = kt & 1;
     // next tile's loads (clamped: the last iteration reloads the last tile, unused)
     const int k0 = kbeg + (kt + 1 < nkt ? kt + 1 : kt) * BK;
-    load_a<OPA>(o, m0, k0, tid, fa);
+    load_a<OPA, MB>(o, m0, k0, tid, fa);
     load_b<OPB>(o, n0, k0, tid, fb);
     __builtin_amdgcn_sched_barrier(0);  // the loads issue before the MFMAs of this tile
 #pragma unroll
     for (int kq = 0; kq < BK; kq += 4) {
       const int kk = kq + (lane >> 4);
-      double ar[2], ai[2], as[2], br[2], bi2[2], bs[2];
+      double ar[AW], ai[AW], as[AW], br[2], bi2[2], bs[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int i = wm * 32 + a * 16 + (lane & 15);
+      for (int a = 0; a < AW; ++a) {
+        const int i = wm * (MB / 2) + a * 16 + (lane & 15);
         ar[a] = As[cur][0][kk][i];
         ai[a] = As[cur][1][kk][i];
         as[a] = ar[a] + ai[a];
@@ -232,20 +243,20 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
         bs[b] = br[b] + bi2[b];
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < AW; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], t1[a][b], 0, 0, 0);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < AW; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi2[b], t2[a][b], 0, 0, 0);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < AW; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[a], bs[b], t3[a][b], 0, 0, 0);
     }
     if (kt + 1 < nkt) {
-      store_a<OPA>(As[cur ^ 1], tid, fa);
+      store_a<OPA, MB>(As[cur ^ 1], tid, fa);
       store_b<OPB>(Bs[cur ^ 1], tid, fb);
     }
     __syncthreads();
@@ -260,12 +271,12 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
     double2 *C = P.C + (long long)bi * P.sC;
     const bool rd = (P.beta.x != 0.0 || P.beta.y != 0.0);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < AW; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = m0 + wm * 32 + a * 16 + 4 * r + (lane >> 4);
+          const int i = m0 + wm * (MB / 2) + a * 16 + 4 * r + (lane >> 4);
           const int j = n0 + wn * 32 + b * 16 + (lane & 15);
           if (i < P.m && j < o.nlim) {
             double2 v = cmul(P.alpha, acc_of(a, b, r));
@@ -278,14 +289,14 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
     const long long tile_lin = ((long long)bi * P.tiles_n + tn) * P.tiles_m + tm;
     double2 *dst = partials + (P.part_off + tile_lin * P.ksplit + ks) * (long long)(BM * BN);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < AW; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int il = wm * 32 + a * 16 + 4 * r + (lane >> 4);
+          const int il = wm * (MB / 2) + a * 16 + 4 * r + (lane >> 4);
           const int jl = wn * 32 + b * 16 + (lane & 15);
-          dst[jl * BM + il] = acc_of(a, b, r);
+          dst[jl * MB + il] = acc_of(a, b, r);
         }
   }
 }
@@ -315,8 +326,10 @@ __global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZP
   const int bi = tl / (P.tiles_m * P.tiles_n);
   const int el = threadIdx.x % RED_E, grp = threadIdx.x / RED_E;
   const int e = sub * RED_E + el;
-  const int il = e % BM, jl = e / BM;
-  const int i = tm * BM + il, j = tn * BN + jl;
+  const int mb = P.bm;
+  if (e >= mb * BN) return;  // the whole block: a tile of mb < BM rows
+  const int il = e % mb, jl = e / mb;
+  const int i = tm * mb + il, j = tn * BN + jl;
   const int nlim = (n_limit > 0 && n_limit < P.n) ? n_limit : P.n;
   const bool live = (i < P.m && j < nlim);
   double2 s = make_double2(0.0, 0.0);
@@ -352,8 +365,13 @@ hipError_t launch_impl(int opa, int opb, const ZBatch &b, const ZProb *table, co
                        int total_tiles, double2 *partials, int n_limit, hipStream_t s) {
   if (total_tiles <= 0) return hipSuccess;
   dim3 grid(total_tiles), block(NT);
-#define LTD_ZG(OA, OB) \
-  hipLaunchKernelGGL((zgemm_kernel<OA, OB, TABLE>), grid, block, 0, s, b, table, nprob, partials, n_limit)
+#define LTD_ZG(OA, OB)                                                                                         \
+  do {                                                                                                         \
+    if (host[0].bm == 32)                                                                                      \
+      hipLaunchKernelGGL((zgemm_kernel<OA, OB, TABLE, 32>), grid, block, 0, s, b, table, nprob, partials, n_limit); \
+    else                                                                                                       \
+      hipLaunchKernelGGL((zgemm_kernel<OA, OB, TABLE, 64>), grid, block, 0, s, b, table, nprob, partials, n_limit); \
+  } while (0)
   if (opa == OP_N && opb == OP_N) LTD_ZG(OP_N, OP_N);
   else if (opa == OP_C && opb == OP_N) LTD_ZG(OP_C, OP_N);
   else if (opa == OP_N && opb == OP_C) LTD_ZG(OP_N, OP_C);
@@ -375,15 +393,16 @@ hipError_t launch_impl(int opa, int opb, const ZBatch &b, const ZProb *table, co
 
 }  // namespace
 
-size_t gemm_plan(ZProb *probs, int nprob, int *total_tiles, int target_blocks, long long max_part_tiles) {
-  // Output tiles of every problem; the K split is chosen for the launch as a
-  // whole: the problems whose tiles alone leave the GPU short of target_blocks
-  // split their K dimension by a common factor (at most K-tiles / per of each),
-  // within the partial-tile budget.
+namespace {
+// Plans the launch with output tiles of bm rows (see gemm_plan); returns the
+// per-CU load estimate: blocks per CU x tile rows x K tiles per block.
+long long plan_bm(ZProb *probs, int nprob, int bm, int target_blocks, long long max_part_tiles, int *total_tiles,
+                  long long *part_tiles) {
   long long base_all = 0, base_split = 0;
   for (int i = 0; i < nprob; ++i) {
     ZProb &P = probs[i];
-    P.tiles_m = (P.m + BM - 1) / BM;
+    P.bm = bm;
+    P.tiles_m = (P.m + bm - 1) / bm;
     P.tiles_n = (P.n + BN - 1) / BN;
     if (P.batch < 1) P.batch = 1;
     base_all += (long long)P.tiles_m * P.tiles_n * P.batch;
@@ -403,7 +422,7 @@ size_t gemm_plan(ZProb *probs, int nprob, int *total_tiles, int target_blocks, l
       if (ks_common > cap) ks_common = (int)(cap > 1 ? cap : 1);
     }
   }
-  int tb = 0, rb = 0;
+  int tb = 0, rb = 0, kt_max = 0;
   long long part = 0;
   for (int i = 0; i < nprob; ++i) {
     ZProb &P = probs[i];
@@ -424,8 +443,34 @@ size_t gemm_plan(ZProb *probs, int nprob, int *total_tiles, int target_blocks, l
     tb += base * P.ksplit;
     rb += base;
     if (P.ksplit > 1) part += (long long)base * P.ksplit;
+    if (base > 0 && kt_per > kt_max) kt_max = kt_per;
   }
   *total_tiles = tb;
+  *part_tiles = part;
+  constexpr int CUS = 256;
+  return (long long)((tb + CUS - 1) / CUS) * bm * (kt_max > 0 ? kt_max : 1);
+}
+}  // namespace
+
+size_t gemm_plan(ZProb *probs, int nprob, int *total_tiles, int target_blocks, long long max_part_tiles) {
+  // Output tiles of every problem; the K split is chosen for the launch as a
+  // whole: the problems whose tiles alone leave the GPU short of target_blocks
+  // split their K dimension by a common factor (at most K-tiles / per of each),
+  // within the partial-tile budget.  The tile height (64 or 32 rows) is the one
+  // with the lower per-CU load (ties: 64); 32-row tiles balance launches whose
+  // 64-row tile count falls just past a multiple of the CU count, and waste less
+  // on heights just past a multiple of 64.
+  int t32 = 0, t64 = 0;
+  long long p32 = 0, p64 = 0;
+  const long long l32 = plan_bm(probs, nprob, 32, target_blocks, max_part_tiles, &t32, &p32);
+  const long long l64 = plan_bm(probs, nprob, 64, target_blocks, max_part_tiles, &t64, &p64);
+  long long part = p64;
+  *total_tiles = t64;
+  if (l32 < l64) {
+    plan_bm(probs, nprob, 32, target_blocks, max_part_tiles, &t32, &p32);
+    part = p32;
+    *total_tiles = t32;
+  }
   return (size_t)part * BM * BN * sizeof(double2);
 }
 
