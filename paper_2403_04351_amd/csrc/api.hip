@@ -88,6 +88,10 @@ struct ltd_system {
   // side stream of the rebuild: the muffin-tin branch runs beside the FFT chain
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // pipelined propagation: the exponential of step n on `side2` beside the
+  // rebuild of step n + 1 (ev_p0: step start, ev_asm: H~(mid) assembled, ev_pj: step done)
+  hipStream_t side2 = nullptr;
+  hipEvent_t ev_p0 = nullptr, ev_asm = nullptr, ev_pj = nullptr;
   size_t o_rtw1 = 0, o_rtw2 = 0, o_rtw3 = 0, o_M1 = 0, o_M2 = 0, o_M3 = 0, o_syn1 = 0, o_syn2 = 0;
   size_t o_F1 = 0, o_F2 = 0, o_F3 = 0;  // MFMA fragments of the synthesis axis matrices
   int chunk = 0;        // columns per apply pass
@@ -113,6 +117,7 @@ struct ltd_system {
   hipGraph_t graph = nullptr;
   ltd_step_args gargs{};
   bool gvalid = false;
+  bool gpipe = false;  // the captured step is the pipelined one
 
   template <class T>
   T *at(size_t off) const {
@@ -619,10 +624,17 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
 // Step stages (profiling tags): 0 Theta V(t), 1 x/z planes, 2 y lines, 3 muffin-tin
 // blocks (K2), 4 projection of V~ (GEMM), 5 subspace step and observables, 6 map-back.
 // Rebuild V~(t) of every k for the potential of this step (v_r_t, h_t).
+// V~_step = Phi~_ext^H Y_ext of every bound k (one split-K GEMM table).
+ltd_status project_v(ltd_system *sys, hipStream_t s) {
+  LTD_HIP(gemm_launch_table(OP_C, OP_N, sys->at<ZProb>(sys->o_vstep_tab), sys->vstep_tab.data(),
+                            (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_partials), 0, s));
+  return LTD_OK;
+}
+
 // host_step >= 0: the step index is known on the host (adjoint); otherwise the
 // series are indexed by the device step counter.
 ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Prof *pf = nullptr,
-                     int host_step = -1) {
+                     int host_step = -1, bool with_proj = true) {
   const Grid g = rgrid_of(sys);
   const int n = sys->n_aux;
   const void *hx = k2_source(sys, a);
@@ -685,8 +697,7 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
   if (fork) LTD_HIP(hipStreamWaitEvent(s, sys->ev_join, 0));
   else LTD_TRY(run_k2(sys, sys->k2_step, n, s));
   LTD_MARK(pf, 3);
-  LTD_HIP(gemm_launch_table(OP_C, OP_N, sys->at<ZProb>(sys->o_vstep_tab), sys->vstep_tab.data(),
-                            (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_partials), 0, s));
+  if (with_proj) LTD_TRY(project_v(sys, s));
   LTD_MARK(pf, 4);
   return LTD_OK;
 }
@@ -718,6 +729,30 @@ ltd_status check_step_args(ltd_system *sys, const ltd_step_args *a) {
   if (a->v_stride < 0 || a->h_stride < 0) return LTD_EINVAL;
   if (a->v_stride && a->v_stride < sys->ngrid) return LTD_ESHAPE;
   if (a->h_stride && a->h_stride < sys->blk_elems) return LTD_ESHAPE;
+  return LTD_OK;
+}
+
+// Pipelined steps (REBUILD): each replayed step rebuilds V~ of the next step
+// (the lookahead index rs[0], clamped to the call's last step) on `s` while the
+// exponential of the current step runs on side2; the projection that overwrites
+// V~ waits until the current step has assembled H~(mid) from it.
+ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
+  int *rs = sys->at<int>(sys->o_status) + 12;
+  ltd_step_args an = *a;
+  an.step = rs;
+  const StepCtx c = step_ctx(sys, a);
+  LTD_HIP(launch_lookahead(a->step, rs, s));
+  LTD_HIP(hipEventRecord(sys->ev_p0, s));
+  LTD_HIP(hipStreamWaitEvent(sys->side2, sys->ev_p0, 0));
+  LTD_HIP(launch_assemble(c, sys->side2));
+  LTD_HIP(hipEventRecord(sys->ev_asm, sys->side2));
+  LTD_HIP(launch_step_only(c, sys->side2));
+  LTD_HIP(hipEventRecord(sys->ev_pj, sys->side2));
+  LTD_TRY(rebuild_v(sys, &an, s, nullptr, -1, false));
+  LTD_HIP(hipStreamWaitEvent(s, sys->ev_asm, 0));
+  LTD_TRY(project_v(sys, s));
+  LTD_HIP(hipStreamWaitEvent(s, sys->ev_pj, 0));
+  LTD_TRY(map_back(sys, a, s));
   return LTD_OK;
 }
 
@@ -924,7 +959,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_thv = ar.take(sys->ngrid * sizeof(double));
   sys->o_thv_rb = ar.take(sys->ngrid * sizeof(double));
   sys->o_thv_step = ar.take(sys->ngrid * sizeof(double));
-  sys->o_status = ar.take(64);
+  sys->o_status = ar.take(64);  // [0..1] status, [8] step-kernel block counter, [12..13] lookahead
   sys->o_part = ar.take((size_t)4 * sys->n_k * sys->n_states * sizeof(double));
   sys->o_partials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
   const long long slab_f = (long long)g.nbz * g.n1 * g.n2 * sys->chunk;
@@ -1008,6 +1043,10 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
     LTD_HIP(hipStreamCreateWithFlags(&sys->side, hipStreamNonBlocking));
     LTD_HIP(hipEventCreateWithFlags(&sys->ev_fork, hipEventDisableTiming));
     LTD_HIP(hipEventCreateWithFlags(&sys->ev_join, hipEventDisableTiming));
+    LTD_HIP(hipStreamCreateWithFlags(&sys->side2, hipStreamNonBlocking));
+    LTD_HIP(hipEventCreateWithFlags(&sys->ev_p0, hipEventDisableTiming));
+    LTD_HIP(hipEventCreateWithFlags(&sys->ev_asm, hipEventDisableTiming));
+    LTD_HIP(hipEventCreateWithFlags(&sys->ev_pj, hipEventDisableTiming));
   }
   // twiddles exp(-2 pi i m / L)
   auto tw = [&](int L, size_t off) -> ltd_status {
@@ -1093,6 +1132,10 @@ ltd_status ltd_destroy(ltd_system *sys) {
   if (sys->side) (void)hipStreamDestroy(sys->side);
   if (sys->ev_fork) (void)hipEventDestroy(sys->ev_fork);
   if (sys->ev_join) (void)hipEventDestroy(sys->ev_join);
+  if (sys->side2) (void)hipStreamDestroy(sys->side2);
+  if (sys->ev_p0) (void)hipEventDestroy(sys->ev_p0);
+  if (sys->ev_asm) (void)hipEventDestroy(sys->ev_asm);
+  if (sys->ev_pj) (void)hipEventDestroy(sys->ev_pj);
   delete sys;
   return LTD_OK;
 }
@@ -1380,7 +1423,15 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
     sys->k2_step_h = k2_source(sys, a);
     LTD_TRY(build_step_tables(sys));
   }
-  const bool same = sys->gvalid && std::memcmp(&sys->gargs, a, sizeof(ltd_step_args)) == 0;
+  const bool pipe = a->mode == LTD_STEP_REBUILD && sys->side2 != nullptr;
+  if (pipe) {  // V~ of the first step, and the lookahead bounds of this call
+    int *rs = sys->at<int>(sys->o_status) + 12;
+    LTD_HIP(launch_lookahead_init(a->step, n_steps, rs, s));
+    ltd_step_args a0 = *a;
+    a0.step = rs;
+    LTD_TRY(rebuild_v(sys, &a0, s));
+  }
+  const bool same = sys->gvalid && sys->gpipe == pipe && std::memcmp(&sys->gargs, a, sizeof(ltd_step_args)) == 0;
   if (!same) {
     if (sys->gexec) {
       (void)hipGraphExecDestroy(sys->gexec);
@@ -1392,7 +1443,7 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
     }
     if (!sys->cap_stream) LTD_HIP(hipStreamCreateWithFlags(&sys->cap_stream, hipStreamNonBlocking));
     LTD_HIP(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeThreadLocal));
-    const ltd_status st = step_once(sys, a, sys->cap_stream);
+    const ltd_status st = pipe ? pipelined_step(sys, a, sys->cap_stream) : step_once(sys, a, sys->cap_stream);
     hipGraph_t gr = nullptr;
     const hipError_t ec = hipStreamEndCapture(sys->cap_stream, &gr);
     if (st != LTD_OK) {
@@ -1403,6 +1454,7 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
     sys->graph = gr;
     LTD_HIP(hipGraphInstantiate(&sys->gexec, gr, nullptr, nullptr, 0));
     sys->gargs = *a;
+    sys->gpipe = pipe;
     sys->gvalid = true;
   }
   for (int i = 0; i < n_steps; ++i) LTD_HIP(hipGraphLaunch(sys->gexec, s));

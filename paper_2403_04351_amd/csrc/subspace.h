@@ -78,6 +78,14 @@ size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint, bool p_in_lds = false)
 hipError_t launch_conj_transpose(const double2 *a, double2 *out, int n, hipStream_t s);
 void subspace_init_attrs();  // LDS limits of the step kernels (call outside graph capture)
 hipError_t launch_step(const StepCtx &c, hipStream_t s);
+// The two halves of launch_step: H~(mid) of the step (k_assemble), then the
+// exponential, observables and step counter (k_step).
+hipError_t launch_assemble(const StepCtx &c, hipStream_t s);
+hipError_t launch_step_only(const StepCtx &c, hipStream_t s);
+// rs[0] = *step, rs[1] = *step + n_steps - 1 (lookahead bounds of one propagate call)
+hipError_t launch_lookahead_init(const int *step, int n_steps, int *rs, hipStream_t s);
+// rs[0] = min(*step + 1, rs[1]): the step whose V~ the pipelined rebuild computes
+hipError_t launch_lookahead(const int *step, int *rs, hipStream_t s);
 int assemble_blocks(int n);
 hipError_t launch_adjoint(const StepCtx &c, const AdjCtx &a, hipStream_t s);
 hipError_t launch_knot_samples(const double *q, int nk, double t_end, double dt, int ns, double *a_t,

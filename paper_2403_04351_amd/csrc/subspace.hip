@@ -838,11 +838,19 @@ void subspace_init_attrs() {
   g_step_attr = true;
 }
 
-hipError_t launch_step(const StepCtx &c, hipStream_t s) {
-  subspace_init_attrs();
+hipError_t launch_assemble(const StepCtx &c, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble, dim3(assemble_blocks(c.n_aux), c.n_k), dim3(256), 0, s, c);
-  hipError_t e0 = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const StepCtx &c, hipStream_t s) {
+  const hipError_t e0 = launch_assemble(c, s);
   if (e0 != hipSuccess) return e0;
+  return launch_step_only(c, s);
+}
+
+hipError_t launch_step_only(const StepCtx &c, hipStream_t s) {
+  subspace_init_attrs();
   const size_t lds = step_lds_bytes(c.n_aux, c.h_in_lds, false, c.p_in_lds);
   if (c.h_in_lds && c.p_in_lds)
     hipLaunchKernelGGL((k_step<true, true>), dim3(c.n_states, c.n_k), dim3(STEP_NT), lds, s, c);
@@ -850,6 +858,23 @@ hipError_t launch_step(const StepCtx &c, hipStream_t s) {
     hipLaunchKernelGGL((k_step<true, false>), dim3(c.n_states, c.n_k), dim3(STEP_NT), lds, s, c);
   else
     hipLaunchKernelGGL((k_step<false, false>), dim3(c.n_states, c.n_k), dim3(STEP_NT), lds, s, c);
+  return hipGetLastError();
+}
+
+__global__ void k_lookahead_init(const int *step, int n_steps, int *rs) {
+  rs[0] = *step;
+  rs[1] = *step + n_steps - 1;
+}
+
+__global__ void k_lookahead(const int *step, int *rs) { rs[0] = min(*step + 1, rs[1]); }
+
+hipError_t launch_lookahead_init(const int *step, int n_steps, int *rs, hipStream_t s) {
+  hipLaunchKernelGGL(k_lookahead_init, dim3(1), dim3(1), 0, s, step, n_steps, rs);
+  return hipGetLastError();
+}
+
+hipError_t launch_lookahead(const int *step, int *rs, hipStream_t s) {
+  hipLaunchKernelGGL(k_lookahead, dim3(1), dim3(1), 0, s, step, rs);
   return hipGetLastError();
 }
 

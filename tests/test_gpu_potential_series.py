@@ -130,3 +130,43 @@ def test_adjoint_with_potential_series_matches_oracle():
     assert abs(loss.item() - g["loss"]) < 1e-10 * abs(g["loss"])
     assert rel_max(g_mid.cpu().numpy(), g["mid"]) < 1e-9
     assert rel_max(grad.cpu().numpy(), gq) < 1e-9
+
+
+@pytest.mark.parametrize("grid", [None, (64, 64, 64)], ids=["grid16", "grid64_rebuilt_on_16"])
+def test_pipelined_replay_equals_stepwise_with_series(grid):
+    """ltd_propagate rebuilds V~ of step n + 1 beside the exponential of step n
+    (lookahead index from the device counter, clamped to the call's last step);
+    the arithmetic is that of the stepwise calls, so the results are bit-identical:
+    one call of n steps, two calls of n1 + n2 steps, and n single steps."""
+    sys, phi, sub, lt, ltd, torch = _setup(grid)
+    n, n1 = 24, 9
+    a_t, a_mid = pulse_samples(sys, n)
+    s_n = np.sin(0.4 * np.arange(n))
+    pot, _ = _series(sys, phi, lt, torch, s_n)
+    th0 = pr.initial_theta(sys.n_aux, sys.n_states)
+    dev = lt.device
+
+    def fresh():
+        theta = torch.from_numpy(np.ascontiguousarray(th0.T)[None]).to(dev)
+        return lt.make_step_args(ltd.LTD_STEP_REBUILD, sys.dt, torch.from_numpy(a_t).to(dev),
+                                 torch.from_numpy(a_mid).to(dev), theta, n, **pot)
+
+    runs = {}
+    st = fresh()
+    lt.run(st, n)
+    runs["one call"] = st
+    st = fresh()
+    lt.run(st, n1)
+    lt.run(st, n - n1)
+    runs["two calls"] = st
+    st = fresh()
+    for _ in range(n):
+        lt.step(st)
+    runs["stepwise"] = st
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+    ref = runs["stepwise"]
+    for name in ("one call", "two calls"):
+        for key in ("j", "e", "dmu", "theta"):
+            assert np.array_equal(runs[name][key].cpu().numpy(), ref[key].cpu().numpy()), (name, key)
+    assert int(runs["two calls"]["step"].item()) == n
