@@ -18,6 +18,7 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr long long PART_TILES = 2048;  // split-K partial budget (64x64 complex tiles)
+constexpr int GRAPH_STEPS = 8;          // steps captured in the multi-step graph
 
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -113,8 +114,10 @@ struct ltd_system {
   std::vector<SubDev> sd;
   double cheb_dt = NAN;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec = nullptr;  // one step
   hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec_m = nullptr;  // GRAPH_STEPS steps (one replay boundary per GRAPH_STEPS steps)
+  hipGraph_t graph_m = nullptr;
   ltd_step_args gargs{};
   bool gvalid = false;
   bool gpipe = false;  // the captured step is the pipelined one
@@ -732,6 +735,15 @@ ltd_status check_step_args(ltd_system *sys, const ltd_step_args *a) {
   return LTD_OK;
 }
 
+void drop_graphs(ltd_system *sys) {
+  if (sys->gexec) (void)hipGraphExecDestroy(sys->gexec);
+  if (sys->graph) (void)hipGraphDestroy(sys->graph);
+  if (sys->gexec_m) (void)hipGraphExecDestroy(sys->gexec_m);
+  if (sys->graph_m) (void)hipGraphDestroy(sys->graph_m);
+  sys->gexec = sys->gexec_m = nullptr;
+  sys->graph = sys->graph_m = nullptr;
+}
+
 // Pipelined steps (REBUILD): each replayed step rebuilds V~ of the next step
 // (the lookahead index rs[0], clamped to the call's last step) on `s` while the
 // exponential of the current step runs on side2; the projection that overwrites
@@ -1126,8 +1138,7 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
 
 ltd_status ltd_destroy(ltd_system *sys) {
   if (!sys) return LTD_EINVAL;
-  if (sys->gexec) (void)hipGraphExecDestroy(sys->gexec);
-  if (sys->graph) (void)hipGraphDestroy(sys->graph);
+  drop_graphs(sys);
   if (sys->cap_stream) (void)hipStreamDestroy(sys->cap_stream);
   if (sys->side) (void)hipStreamDestroy(sys->side);
   if (sys->ev_fork) (void)hipEventDestroy(sys->ev_fork);
@@ -1433,17 +1444,19 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
   }
   const bool same = sys->gvalid && sys->gpipe == pipe && std::memcmp(&sys->gargs, a, sizeof(ltd_step_args)) == 0;
   if (!same) {
-    if (sys->gexec) {
-      (void)hipGraphExecDestroy(sys->gexec);
-      sys->gexec = nullptr;
-    }
-    if (sys->graph) {
-      (void)hipGraphDestroy(sys->graph);
-      sys->graph = nullptr;
-    }
+    drop_graphs(sys);
+    sys->gargs = *a;
+    sys->gpipe = pipe;
+    sys->gvalid = true;
+  }
+  // k steps in one capture; replayed graphs of GRAPH_STEPS steps, then single steps
+  const auto ensure = [&](int k, hipGraph_t *g, hipGraphExec_t *x) -> ltd_status {
+    if (*x) return LTD_OK;
     if (!sys->cap_stream) LTD_HIP(hipStreamCreateWithFlags(&sys->cap_stream, hipStreamNonBlocking));
     LTD_HIP(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeThreadLocal));
-    const ltd_status st = pipe ? pipelined_step(sys, a, sys->cap_stream) : step_once(sys, a, sys->cap_stream);
+    ltd_status st = LTD_OK;
+    for (int i = 0; i < k && st == LTD_OK; ++i)
+      st = pipe ? pipelined_step(sys, a, sys->cap_stream) : step_once(sys, a, sys->cap_stream);
     hipGraph_t gr = nullptr;
     const hipError_t ec = hipStreamEndCapture(sys->cap_stream, &gr);
     if (st != LTD_OK) {
@@ -1451,13 +1464,15 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
       return st;
     }
     if (ec != hipSuccess) return LTD_EHIP;
-    sys->graph = gr;
-    LTD_HIP(hipGraphInstantiate(&sys->gexec, gr, nullptr, nullptr, 0));
-    sys->gargs = *a;
-    sys->gpipe = pipe;
-    sys->gvalid = true;
-  }
-  for (int i = 0; i < n_steps; ++i) LTD_HIP(hipGraphLaunch(sys->gexec, s));
+    *g = gr;
+    LTD_HIP(hipGraphInstantiate(x, gr, nullptr, nullptr, 0));
+    return LTD_OK;
+  };
+  const int nm = n_steps / GRAPH_STEPS, n1 = n_steps % GRAPH_STEPS;
+  if (nm > 0) LTD_TRY(ensure(GRAPH_STEPS, &sys->graph_m, &sys->gexec_m));
+  if (n1 > 0) LTD_TRY(ensure(1, &sys->graph, &sys->gexec));
+  for (int i = 0; i < nm; ++i) LTD_HIP(hipGraphLaunch(sys->gexec_m, s));
+  for (int i = 0; i < n1; ++i) LTD_HIP(hipGraphLaunch(sys->gexec, s));
   return LTD_OK;
 }
 
