@@ -744,26 +744,34 @@ void drop_graphs(ltd_system *sys) {
   sys->graph = sys->graph_m = nullptr;
 }
 
-// Pipelined steps (REBUILD): each replayed step rebuilds V~ of the next step
-// (the lookahead index rs[0], clamped to the call's last step) on `s` while the
-// exponential of the current step runs on side2; the projection that overwrites
-// V~ waits until the current step has assembled H~(mid) from it.
-ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s) {
+// Pipelined steps (REBUILD): each step rebuilds V~ of the next step on `s`
+// while the exponential of the current step runs on side2.  The rebuild's step
+// index rs[0] is its own counter (set at the start of a propagate call, then
+// advanced by one per step and clamped to the call's last step), so the rebuild
+// chain never waits for the exponential; side2 waits for the V~ it assembles
+// (ev_p0), and the projection that overwrites V~ waits until it was assembled
+// (ev_asm).  `join`: the last step of a capture joins side2 back into s.
+// map_back is a no-op without C.
+ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s, bool join) {
   int *rs = sys->at<int>(sys->o_status) + 12;
   ltd_step_args an = *a;
   an.step = rs;
   const StepCtx c = step_ctx(sys, a);
-  LTD_HIP(launch_lookahead(a->step, rs, s));
   LTD_HIP(hipEventRecord(sys->ev_p0, s));
   LTD_HIP(hipStreamWaitEvent(sys->side2, sys->ev_p0, 0));
   LTD_HIP(launch_assemble(c, sys->side2));
   LTD_HIP(hipEventRecord(sys->ev_asm, sys->side2));
   LTD_HIP(launch_step_only(c, sys->side2));
-  LTD_HIP(hipEventRecord(sys->ev_pj, sys->side2));
+  LTD_HIP(launch_lookahead(rs, s));
   LTD_TRY(rebuild_v(sys, &an, s, nullptr, -1, false));
   LTD_HIP(hipStreamWaitEvent(s, sys->ev_asm, 0));
   LTD_TRY(project_v(sys, s));
-  LTD_HIP(hipStreamWaitEvent(s, sys->ev_pj, 0));
+  // the map-back GEMM shares the split-K partials with the rebuild's GEMMs: it
+  // runs on s, after the step (a join every step when C is requested)
+  if (join || a->c_out) {
+    LTD_HIP(hipEventRecord(sys->ev_pj, sys->side2));
+    LTD_HIP(hipStreamWaitEvent(s, sys->ev_pj, 0));
+  }
   LTD_TRY(map_back(sys, a, s));
   return LTD_OK;
 }
@@ -1456,7 +1464,7 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
     LTD_HIP(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeThreadLocal));
     ltd_status st = LTD_OK;
     for (int i = 0; i < k && st == LTD_OK; ++i)
-      st = pipe ? pipelined_step(sys, a, sys->cap_stream) : step_once(sys, a, sys->cap_stream);
+      st = pipe ? pipelined_step(sys, a, sys->cap_stream, i == k - 1) : step_once(sys, a, sys->cap_stream);
     hipGraph_t gr = nullptr;
     const hipError_t ec = hipStreamEndCapture(sys->cap_stream, &gr);
     if (st != LTD_OK) {

@@ -84,8 +84,8 @@ hipError_t launch_assemble(const StepCtx &c, hipStream_t s);
 hipError_t launch_step_only(const StepCtx &c, hipStream_t s);
 // rs[0] = *step, rs[1] = *step + n_steps - 1 (lookahead bounds of one propagate call)
 hipError_t launch_lookahead_init(const int *step, int n_steps, int *rs, hipStream_t s);
-// rs[0] = min(*step + 1, rs[1]): the step whose V~ the pipelined rebuild computes
-hipError_t launch_lookahead(const int *step, int *rs, hipStream_t s);
+// rs[0] = min(rs[0] + 1, rs[1]): the step whose V~ the pipelined rebuild computes
+hipError_t launch_lookahead(int *rs, hipStream_t s);
 int assemble_blocks(int n);
 hipError_t launch_adjoint(const StepCtx &c, const AdjCtx &a, hipStream_t s);
 hipError_t launch_knot_samples(const double *q, int nk, double t_end, double dt, int ns, double *a_t,

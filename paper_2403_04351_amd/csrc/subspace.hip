@@ -866,15 +866,15 @@ __global__ void k_lookahead_init(const int *step, int n_steps, int *rs) {
   rs[1] = *step + n_steps - 1;
 }
 
-__global__ void k_lookahead(const int *step, int *rs) { rs[0] = min(*step + 1, rs[1]); }
+__global__ void k_lookahead(int *rs) { rs[0] = min(rs[0] + 1, rs[1]); }
 
 hipError_t launch_lookahead_init(const int *step, int n_steps, int *rs, hipStream_t s) {
   hipLaunchKernelGGL(k_lookahead_init, dim3(1), dim3(1), 0, s, step, n_steps, rs);
   return hipGetLastError();
 }
 
-hipError_t launch_lookahead(const int *step, int *rs, hipStream_t s) {
-  hipLaunchKernelGGL(k_lookahead, dim3(1), dim3(1), 0, s, step, rs);
+hipError_t launch_lookahead(int *rs, hipStream_t s) {
+  hipLaunchKernelGGL(k_lookahead, dim3(1), dim3(1), 0, s, rs);
   return hipGetLastError();
 }
 

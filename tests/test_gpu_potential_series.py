@@ -137,7 +137,8 @@ def test_pipelined_replay_equals_stepwise_with_series(grid):
     """ltd_propagate rebuilds V~ of step n + 1 beside the exponential of step n
     (lookahead index from the device counter, clamped to the call's last step);
     the arithmetic is that of the stepwise calls, so the results are bit-identical:
-    one call of n steps, two calls of n1 + n2 steps, and n single steps."""
+    one call of n steps, two calls of n1 + n2 steps, and n single steps (the
+    series, the states and the mapped-back coefficients C)."""
     sys, phi, sub, lt, ltd, torch = _setup(grid)
     n, n1 = 24, 9
     a_t, a_mid = pulse_samples(sys, n)
@@ -148,8 +149,9 @@ def test_pipelined_replay_equals_stepwise_with_series(grid):
 
     def fresh():
         theta = torch.from_numpy(np.ascontiguousarray(th0.T)[None]).to(dev)
+        cout = torch.zeros((sys.n_states, sys.n_basis(0)), dtype=torch.complex128, device=dev)
         return lt.make_step_args(ltd.LTD_STEP_REBUILD, sys.dt, torch.from_numpy(a_t).to(dev),
-                                 torch.from_numpy(a_mid).to(dev), theta, n, **pot)
+                                 torch.from_numpy(a_mid).to(dev), theta, n, c_out=cout, **pot)
 
     runs = {}
     st = fresh()
@@ -167,6 +169,6 @@ def test_pipelined_replay_equals_stepwise_with_series(grid):
     assert lt.sync_status() == 0
     ref = runs["stepwise"]
     for name in ("one call", "two calls"):
-        for key in ("j", "e", "dmu", "theta"):
+        for key in ("j", "e", "dmu", "theta", "c_out"):
             assert np.array_equal(runs[name][key].cpu().numpy(), ref[key].cpu().numpy()), (name, key)
     assert int(runs["two calls"]["step"].item()) == n
