@@ -345,6 +345,7 @@ def main():
         "h_apply": h_apply,
         "subspace": dict(eps_min=emin, eps_max=emax, dt_cr=dtcr),
         "dmu_final": float(st["dmu"][args.warmup + args.steps].item()),
+        "state_drift": lt.state_drift(theta),
     }
     if args.precision == "fp32" and series and nk == 1:
         out["mixed_error"] = mixed_error(sysd, st, args.warmup + args.steps)

@@ -168,6 +168,16 @@ ltd_status ltd_autotune(ltd_system *sys, int *choice, double *times_us, void *st
  * those ranges.  Invalidates a captured step graph. */
 ltd_status ltd_set_tuning(ltd_system *sys, const int *choice);
 
+/* S-orthonormality of the propagated states (mixed precision: S-reorthonormalisation
+ * with the drift reported): for every k, G = theta^H S_sub theta (n_states x
+ * n_states); *drift (host) = max over k and entries of |G - I|.  With
+ * reorthonormalize != 0 the states are replaced by Loewdin's symmetric
+ * orthonormalisation theta G^{-1/2} (G = V diag(w) V^H by the device Jacobi
+ * solver; the S-orthonormal set closest to theta, spanning the same space).
+ * theta (device): n_k x n_states x n_aux as in ltd_step_args, in/out.  Every
+ * k-point must be bound.  Synchronises `stream`. */
+ltd_status ltd_state_drift(ltd_system *sys, void *theta, int reorthonormalize, double *drift, void *stream);
+
 /* Host read-out of the FFT lengths of the per-step rebuild (lengths[3], host):
  * the smallest supported lengths >= 4 b_i + 1 (b_i the largest |g_i| of the
  * G+k sets) and <= the grid's, so that every difference of two G-box

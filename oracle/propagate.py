@@ -109,3 +109,20 @@ def speedup_per_au(t_ref: float, dtcr_ref: float, t_new: float, dtcr_new: float)
     """Overall speedup over a fixed simulated time window (Sec. 3.1): the ratio
     of wall time per simulated a.u., (t_ref/dtcr_ref) / (t_new/dtcr_new)."""
     return (t_ref / dtcr_ref) / (t_new / dtcr_new)
+
+
+def state_gram(theta: np.ndarray, s_sub: np.ndarray) -> np.ndarray:
+    """G = theta^H S_sub theta, the overlap of the propagated states in the
+    subspace metric (the exact propagator keeps G = I: Sec. 2.2, the states stay
+    S-orthonormal)."""
+    return theta.conj().T @ s_sub @ theta
+
+
+def lowdin(theta: np.ndarray, s_sub: np.ndarray) -> np.ndarray:
+    """Loewdin's symmetric orthonormalisation in the S_sub metric, theta G^{-1/2}
+    with G = theta^H S_sub theta: the S-orthonormal set spanning the same space
+    that is closest to theta (the reorthonormalisation of the mixed-precision
+    extension; not in the paper)."""
+    g = state_gram(theta, s_sub)
+    w, v = np.linalg.eigh(0.5 * (g + g.conj().T))
+    return theta @ ((v / np.sqrt(w)) @ v.conj().T)

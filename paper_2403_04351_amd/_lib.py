@@ -31,7 +31,7 @@ EXPORTED = [
     "ltd_apply_HS", "ltd_project_subspace", "ltd_ritz_basis", "ltd_subspace_info",
     "ltd_propagate_step", "ltd_propagate", "ltd_propagate_step_adjoint", "ltd_knot_samples",
     "ltd_knot_gradient", "ltd_chebyshev_coefficients", "ltd_profile_steps", "ltd_profile_apply",
-    "ltd_rebuild_grid", "ltd_autotune", "ltd_set_tuning",
+    "ltd_rebuild_grid", "ltd_autotune", "ltd_set_tuning", "ltd_state_drift",
 ]
 LTD_PROFILE_STAGES = 8
 
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH):
     lib.ltd_rebuild_grid.argtypes = [vp, C.POINTER(ip)]
     lib.ltd_autotune.argtypes = [vp, C.POINTER(ip), dp, vp]
     lib.ltd_set_tuning.argtypes = [vp, C.POINTER(ip)]
+    lib.ltd_state_drift.argtypes = [vp, vp, ip, dp, vp]
     lib.ltd_propagate_step.argtypes = [vp, C.POINTER(StepArgs), vp]
     lib.ltd_propagate.argtypes = [vp, C.POINTER(StepArgs), ip, vp]
     lib.ltd_propagate_step_adjoint.argtypes = [vp, C.POINTER(AdjointArgs), vp]

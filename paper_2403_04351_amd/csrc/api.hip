@@ -1406,6 +1406,49 @@ ltd_status ltd_set_tuning(ltd_system *sys, const int *choice) {
   return LTD_OK;
 }
 
+ltd_status ltd_state_drift(ltd_system *sys, void *theta, int reorthonormalize, double *drift, void *stream) {
+  if (!sys || !theta || !drift) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  for (int k = 0; k < sys->n_k; ++k)
+    if (!sys->kh[k].bound) return LTD_ESTATE;
+  if (!aligned16(theta)) return LTD_EALIGN;
+  hipStream_t s = S(stream);
+  const int n = sys->n_aux, ns = sys->n_states;
+  const long long n2 = (long long)n * n;
+  double2 *X = sys->at<double2>(sys->o_tmp3);  // n x ns: S theta, then theta G^{-1/2}
+  double2 *G = X + n2;                          // ns x ns: theta^H S theta
+  double2 *B = G + n2;                          // ns x ns: V diag(w^{-1/2}), then G^{-1/2}
+  double2 *A = sys->at<double2>(sys->o_eigA), *V = sys->at<double2>(sys->o_eigV);
+  double *w = sys->at<double>(sys->o_eigw);
+  std::vector<double2> gh((size_t)ns * ns);
+  double worst = 0.0;
+  for (int k = 0; k < sys->n_k; ++k) {
+    const KHost &kh = sys->kh[k];
+    double2 *th = reinterpret_cast<double2 *>(theta) + (long long)k * n * ns;
+    const double2 *ssub = sys->at<double2>(kh.o_subs) + 3 * n2;
+    LTD_TRY(gemm1(sys, OP_N, OP_N, zp(n, ns, n, ssub, n, th, n, X, n), s));
+    LTD_TRY(gemm1(sys, OP_C, OP_N, zp(ns, ns, n, th, n, X, n, G, ns), s));
+    LTD_HIP(hipMemcpyAsync(gh.data(), G, gh.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    LTD_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < ns; ++j)
+      for (int i = 0; i < ns; ++i) {
+        const double2 g = gh[(size_t)i + (size_t)j * ns];
+        worst = std::max(worst, std::hypot(g.x - (i == j ? 1.0 : 0.0), g.y));
+      }
+    if (reorthonormalize) {  // Loewdin: theta <- theta G^{-1/2}, G = V diag(w) V^H
+      LTD_HIP(hipMemcpyAsync(A, G, (size_t)ns * ns * sizeof(double2), hipMemcpyDeviceToDevice, s));
+      LTD_HIP(launch_jacobi(A, V, w, ns, s));
+      LTD_HIP(launch_scale_cols(B, V, w, ns, s));
+      LTD_TRY(gemm1(sys, OP_N, OP_C, zp(ns, ns, ns, B, ns, V, ns, G, ns), s));
+      LTD_TRY(gemm1(sys, OP_N, OP_N, zp(n, ns, ns, th, n, G, ns, X, n), s));
+      LTD_HIP(hipMemcpyAsync(th, X, (size_t)n * ns * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    }
+  }
+  LTD_HIP(hipStreamSynchronize(s));
+  *drift = worst;
+  return LTD_OK;
+}
+
 ltd_status ltd_rebuild_grid(const ltd_system *sys, int *lengths) {
   if (!sys || !lengths) return LTD_EINVAL;
   lengths[0] = sys->rgrid.n1;

@@ -878,6 +878,17 @@ hipError_t launch_lookahead(int *rs, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_scale_cols(double2 *out, const double2 *V, const double *w, int n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (long long)n * n) out[e] = cscale(V[e], 1.0 / sqrt(w[e / n]));
+}
+
+hipError_t launch_scale_cols(double2 *out, const double2 *V, const double *w, int n, hipStream_t s) {
+  const long long tot = (long long)n * n;
+  hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, out, V, w, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_adjoint(const StepCtx &c, const AdjCtx &a, hipStream_t s) {
   subspace_init_attrs();
   const size_t lds = step_lds_bytes(c.n_aux, c.h_in_lds, true);

@@ -167,6 +167,14 @@ class Ltd:
         return dict(xz_shape=choice[0], projection_blocks=choice[1], n_shapes=choice[2],
                     times_us=list(times[:choice[2] + 4]))
 
+    def state_drift(self, theta, reorthonormalize=False):
+        """max |theta^H S_sub theta - I| over the k-points; with reorthonormalize the
+        states are replaced (in place) by their Loewdin orthonormalisation."""
+        d = C.c_double()
+        check(self.lib.ltd_state_drift(self.handle, _ptr(theta), 1 if reorthonormalize else 0, C.byref(d),
+                                       self.stream()), "ltd_state_drift")
+        return d.value
+
     def set_tuning(self, xz_shape, projection_blocks):
         """Sets the rebuild's launch shape and the projection split target."""
         choice = (C.c_int * 2)(xz_shape, projection_blocks)
@@ -205,8 +213,23 @@ class Ltd:
         check(self.lib.ltd_propagate(self.handle, C.byref(st["args"]), n_steps, self.stream()), "ltd_propagate")
 
     def propagate(self, mode, dt, a_t, a_mid, theta, n_steps, graph=True, c_out=None, v_r_t=None, h_t=None,
-                  v_stride=0, h_stride=0):
+                  v_stride=0, h_stride=0, reorth_every=None):
+        """n_steps steps; reorth_every = K: after every K steps the states are
+        reorthonormalised (Loewdin) and the drift before it is kept in st["drift"]."""
         st = self.make_step_args(mode, dt, a_t, a_mid, theta, n_steps, c_out, v_r_t, h_t, v_stride, h_stride)
+        if reorth_every:
+            st["drift"] = []
+            done = 0
+            while done < n_steps:
+                k = min(int(reorth_every), n_steps - done)
+                if graph:
+                    self.run(st, k)
+                else:
+                    for _ in range(k):
+                        self.step(st)
+                done += k
+                st["drift"].append(self.state_drift(theta, reorthonormalize=done < n_steps))
+            return st
         if graph:
             self.run(st, n_steps)
         else:

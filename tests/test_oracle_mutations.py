@@ -75,3 +75,30 @@ def test_wrong_current_sign_is_caught(monkeypatch):
     de = (e(0.75) - e(0.65)) / 0.1
     j = pr.current(th, sub, 0.7, sys.occ, sys.omega, sys.c_light)
     assert abs(j - (-(sys.c_light / sys.omega) * de)) > 1e-3 * abs(j)
+
+
+@pytest.mark.parametrize("power", [-1.0, 0.5, -0.25])
+def test_wrong_lowdin_power_is_caught(power):
+    """theta G^p with p != -1/2 fails the S-orthonormality pin."""
+    from tests.test_oracle_propagate import _perturbed
+
+    sys = make_system(0)
+    phi, eps = ss.ground_state(sys, 0)
+    th, _, s = _perturbed((sys, phi, eps, ss.project(sys, 0, phi)))
+    g = pr.state_gram(th, s)
+    w, v = np.linalg.eigh(0.5 * (g + g.conj().T))
+    q = th @ ((v * w**power) @ v.conj().T)
+    assert np.abs(pr.state_gram(q, s) - np.eye(q.shape[1])).max() > 1e-6
+
+
+def test_unconjugated_lowdin_gram_is_caught():
+    """G = theta^T S theta (conjugate dropped) fails the same pin."""
+    from tests.test_oracle_propagate import _perturbed
+
+    sys = make_system(0)
+    phi, eps = ss.ground_state(sys, 0)
+    th, _, s = _perturbed((sys, phi, eps, ss.project(sys, 0, phi)))
+    g = th.T @ s @ th
+    w, v = np.linalg.eig(g)
+    q = th @ (v @ np.diag(1.0 / np.sqrt(w)) @ np.linalg.inv(v))
+    assert np.abs(pr.state_gram(q, s) - np.eye(q.shape[1])).max() > 1e-6

@@ -183,3 +183,49 @@ def test_co_per_step_speedups_from_paper():
     t_conv, t_mm, t_fft = float(r4[2]), float(r4[3]), float(r4[4])
     assert round(pr.speedup_per_au(t_conv, 1.0, t_mm, 1.0)) == 98
     assert round(pr.speedup_per_au(t_conv, 1.0, t_fft, 1.0)) == 123
+
+
+def _perturbed(setup0, eps=0.05, seed=7):
+    sys, phi, _, sub = setup0
+    rng = np.random.default_rng(seed)
+    th0 = pr.initial_theta(sys.n_aux, sys.n_states)
+    # S-orthonormal start: the Ritz vectors' coefficients, orthonormalised by the exact Cholesky route
+    l = np.linalg.cholesky(sub["S"])
+    th0 = scipy.linalg.solve_triangular(l.conj().T, th0, lower=False)
+    noise = rng.standard_normal(th0.shape) + 1j * rng.standard_normal(th0.shape)
+    return th0 + eps * noise, th0, sub["S"]
+
+
+def test_lowdin_is_s_orthonormal_same_span_and_idempotent(setup0):
+    th, th0, s = _perturbed(setup0)
+    assert np.abs(pr.state_gram(th0, s) - np.eye(th0.shape[1])).max() < 1e-13
+    q = pr.lowdin(th, s)
+    assert np.abs(pr.state_gram(q, s) - np.eye(q.shape[1])).max() < 1e-13
+    # q lies in the column space of theta: least-squares coefficients reproduce it
+    c, *_ = np.linalg.lstsq(th, q, rcond=None)
+    assert np.abs(th @ c - q).max() < 1e-12 * np.abs(q).max()
+    # an S-orthonormal input is left unchanged; a second application changes nothing
+    assert np.abs(pr.lowdin(th0, s) - th0).max() < 1e-13
+    assert np.abs(pr.lowdin(q, s) - q).max() < 1e-13
+
+
+def test_lowdin_is_the_closest_s_orthonormal_set(setup0):
+    """Loewdin's set minimises sum_j ||q_j - theta_j||_S over S-orthonormal sets
+    spanning theta's space: Gram-Schmidt and rotations of Loewdin's set are farther."""
+    th, _, s = _perturbed(setup0, eps=0.2)
+    q = pr.lowdin(th, s)
+
+    def dist(x):
+        d = x - th
+        return float(np.real(np.trace(d.conj().T @ s @ d)))
+
+    # Gram-Schmidt in the S metric: theta R^{-1} with G = R^H R
+    r = np.linalg.cholesky(pr.state_gram(th, s)).conj().T
+    gs = scipy.linalg.solve_triangular(r.T, th.T, lower=True).T
+    assert np.abs(pr.state_gram(gs, s) - np.eye(gs.shape[1])).max() < 1e-12
+    assert dist(q) < dist(gs)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        a = rng.standard_normal((q.shape[1],) * 2) + 1j * rng.standard_normal((q.shape[1],) * 2)
+        u = scipy.linalg.expm(1e-2 * (a - a.conj().T))  # unitary near I
+        assert dist(q) < dist(q @ u)
