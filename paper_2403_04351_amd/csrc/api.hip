@@ -1227,6 +1227,9 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
     ka.slab_out[0] = sys->at<double2>(kh.o_cache);
     LTD_HIP(fft_rb_cache(rgrid_of(sys), ka, 1, n, s, resid32(sys)));
   }
+  // the G rows of Phi~_ext in the order the rebuild writes Y (the sphere tables'
+  // plane order, so that its writes are contiguous); the projection sums over G
+  LTD_HIP(launch_gather_rows(pe, kh.k_ext, pt, sys->nb_max, sys->at<int>(kh.o_ptsg), kh.n_g, n, s));
   // outputs in the Phi basis
   if (h0_sub) LTD_HIP(launch_axpby(reinterpret_cast<double2 *>(h0_sub), subs, subs + n2, 1.0, 1.0, n2, s));
   if (s_sub)

@@ -192,7 +192,7 @@ void fft_init_attrs();  // LDS limits of the FFT kernels (call outside graph cap
 // (fft_rb_slab_values per column); fft_rb_cache builds it from sphere
 // coefficients (ka.in -> ka.slab_out); fft_rb_step part 0 maps slab_in -> slab_out
 // through the x/z transforms and the Theta V product, part 1 reads slab_in out to
-// the sphere (ka.out[k].o0).
+// the sphere (ka.out[k].o0, row i = sphere-table point i, i.e. G index pts_g[i]).
 size_t fft_rb_slab_values(const Grid &g);
 // fp32: the cache and step slabs hold float2 (the FP32 residual); thv is then
 // float, else double; Y is written in FP64 either way.

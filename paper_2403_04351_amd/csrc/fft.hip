@@ -602,7 +602,8 @@ __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKAr
 //     transforms of the x columns, product with Theta V, forward z and x
 //     transforms, box read-out -> d[kz][y][kx];
 //   k_rb_y (per kz plane): forward y transforms of the box columns and the
-//     sphere read-out,
+//     sphere read-out, row i of Y holding sphere-table point i (plane order,
+//     contiguous writes; the projection takes Phi~'s G rows in that order),
 // so a column moves 3 box arrays (nbz*N2*nbx values) through HBM per step.
 // ---------------------------------------------------------------------------
 
@@ -724,10 +725,10 @@ __global__ __launch_bounds__(FFT_NT) void k_rb_y(const Grid g, const FftKArgs ka
   const double inv_n = 1.0 / ((double)n1 * n2 * g.n3);
   const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
   for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
-    const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+    const int xy = sp.pts_xy[i];
     const int yy = xy / g.d1, x = xy - yy * g.d1;
     const int yr = yy <= g.by ? yy : yy - g.d2 + n2;
-    fo.o0[gi + (long long)col * fo.ld0] = cscale(to_d2(bxc[box_of(x, g.d1, bx) * bp + yr]), inv_n);
+    fo.o0[i + (long long)col * fo.ld0] = cscale(to_d2(bxc[box_of(x, g.d1, bx) * bp + yr]), inv_n);
   }
 }
 
@@ -1250,10 +1251,10 @@ __global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka,
   const double inv_n = 1.0 / ((double)g.n1 * N * g.n3);
   const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
   for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
-    const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+    const int xy = sp.pts_xy[i];
     const int yy = xy / g.d1, x = xy - yy * g.d1;
     const int yr = yy <= g.by ? yy : yy - g.d2 + N;
-    fo.o0[gi + (long long)col * fo.ld0] = cscale(to_d2(bxc[box_of(x, g.d1, bx) * BP + yr]), inv_n);
+    fo.o0[i + (long long)col * fo.ld0] = cscale(to_d2(bxc[box_of(x, g.d1, bx) * BP + yr]), inv_n);
   }
 }
 

@@ -74,6 +74,9 @@ hipError_t launch_thv(double *out, const double *th, const double *v, long long 
 hipError_t launch_cholesky(const double2 *S, double2 *L, int n, int *status, int *fail, hipStream_t s);
 hipError_t launch_trtri(const double2 *L, double2 *Li, int n, hipStream_t s);
 hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s);
+// dst[i + c ldd] = src[idx[i] + c lds], i < rows, c < cols (row gather)
+hipError_t launch_gather_rows(double2 *dst, int ldd, const double2 *src, int lds, const int *idx, int rows, int cols,
+                              hipStream_t s);
 // out[:, j] = V[:, j] / sqrt(w[j]) (n x n, ld n)
 hipError_t launch_scale_cols(double2 *out, const double2 *V, const double *w, int n, hipStream_t s);
 size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint, bool p_in_lds = false);

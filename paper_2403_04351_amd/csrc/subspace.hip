@@ -878,6 +878,23 @@ hipError_t launch_lookahead(int *rs, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_gather_rows(double2 *dst, int ldd, const double2 *src, int lds, const int *idx, int rows,
+                              int cols) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)rows * cols) return;
+  const int i = (int)(e % rows), c = (int)(e / rows);
+  dst[i + (long long)c * ldd] = src[idx[i] + (long long)c * lds];
+}
+
+hipError_t launch_gather_rows(double2 *dst, int ldd, const double2 *src, int lds, const int *idx, int rows, int cols,
+                              hipStream_t s) {
+  const long long tot = (long long)rows * cols;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, dst, ldd, src, lds, idx,
+                     rows, cols);
+  return hipGetLastError();
+}
+
 __global__ void k_scale_cols(double2 *out, const double2 *V, const double *w, int n) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < (long long)n * n) out[e] = cscale(V[e], 1.0 / sqrt(w[e / n]));
