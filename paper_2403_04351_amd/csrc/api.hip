@@ -93,6 +93,10 @@ struct ltd_system {
   // rebuild of step n + 1 (ev_p0: step start, ev_asm: H~(mid) assembled, ev_pj: step done)
   hipStream_t side2 = nullptr;
   hipEvent_t ev_p0 = nullptr, ev_asm = nullptr, ev_pj = nullptr;
+  // and Theta V of step n + 1 synthesised on `side3` once the x/z transforms of
+  // step n have read it (ev_xz), ready before those of step n + 1 (ev_syn)
+  hipStream_t side3 = nullptr;
+  hipEvent_t ev_xz = nullptr, ev_syn = nullptr;
   size_t o_rtw1 = 0, o_rtw2 = 0, o_rtw3 = 0, o_M1 = 0, o_M2 = 0, o_M3 = 0, o_syn1 = 0, o_syn2 = 0;
   size_t o_F1 = 0, o_F2 = 0, o_F3 = 0;  // MFMA fragments of the synthesis axis matrices
   int chunk = 0;        // columns per apply pass
@@ -637,7 +641,7 @@ ltd_status project_v(ltd_system *sys, hipStream_t s) {
 // host_step >= 0: the step index is known on the host (adjoint); otherwise the
 // series are indexed by the device step counter.
 ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Prof *pf = nullptr,
-                     int host_step = -1, bool with_proj = true) {
+                     int host_step = -1) {
   const Grid g = rgrid_of(sys);
   const int n = sys->n_aux;
   const void *hx = k2_source(sys, a);
@@ -700,8 +704,71 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
   if (fork) LTD_HIP(hipStreamWaitEvent(s, sys->ev_join, 0));
   else LTD_TRY(run_k2(sys, sys->k2_step, n, s));
   LTD_MARK(pf, 3);
-  if (with_proj) LTD_TRY(project_v(sys, s));
+  LTD_TRY(project_v(sys, s));
   LTD_MARK(pf, 4);
+  return LTD_OK;
+}
+
+// Rebuild of V~ within a pipelined step (no projection).  Theta V of the step
+// is already in o_thv_step when the call hands in a potential (synthesised on
+// side3 beside the previous step's read-out and projection; wait_syn makes s
+// wait for it when that synthesis was issued in the same capture).  The
+// muffin-tin branch advances its own step index rk on the side stream before it
+// reads the blocks of the step, and once the x/z transforms have read Theta V
+// the synthesis of the next step's starts on side3 (its own step index rv).
+ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s, bool wait_syn) {
+  const Grid g = rgrid_of(sys);
+  const int n = sys->n_aux;
+  int *rk = sys->at<int>(sys->o_status) + 12, *rv = rk + 2;
+  const void *hx = k2_source(sys, a);
+  if (hx != sys->k2_step_h) {
+    sys->k2_step_h = hx;
+    LTD_TRY(build_step_tables(sys));
+  }
+  const bool r32 = resid32(sys);
+  LTD_HIP(hipEventRecord(sys->ev_fork, s));
+  LTD_HIP(hipStreamWaitEvent(sys->side, sys->ev_fork, 0));
+  LTD_HIP(launch_lookahead(rk, sys->side));
+  if (a->h_t && (a->h_stride || r32))
+    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), reinterpret_cast<const double2 *>(a->h_t),
+                             sys->blk_elems, a->h_stride ? rk : nullptr, a->h_stride, 0, r32 ? sys->h : nullptr,
+                             sys->side));
+  else if (r32)
+    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), sys->h, sys->blk_elems, nullptr, 0, 0, sys->h,
+                             sys->side));
+  LTD_TRY(run_k2(sys, sys->k2_step, n, sys->side));
+  LTD_HIP(hipEventRecord(sys->ev_join, sys->side));
+  const void *thv = r32 ? static_cast<const void *>(sys->at<float>(sys->o_zero32))
+                        : static_cast<const void *>(sys->at<double>(sys->o_thv_rb));
+  if (a->v_r_t) {
+    thv = sys->at<double>(sys->o_thv_step);
+    if (wait_syn) LTD_HIP(hipStreamWaitEvent(s, sys->ev_syn, 0));
+  }
+  const long long slab = (long long)fft_rb_slab_values(g) * n;
+  for (int k0 = 0; k0 < sys->n_k; k0 += FFT_MAXK) {
+    const int nk = std::min(FFT_MAXK, sys->n_k - k0);
+    FftKArgs ka{};
+    for (int i = 0; i < nk; ++i) {
+      const KHost &kh = sys->kh[k0 + i];
+      ka.sph[i] = sphere_of(sys, k0 + i);
+      ka.slab_in[i] = sys->at<double2>(kh.o_cache);
+      ka.slab_out[i] = reinterpret_cast<double2 *>(sys->ws + sys->o_stepslab + (size_t)i * slab * rb_elem(sys));
+      ka.out[i].o0 = sys->at<double2>(kh.o_yext);
+      ka.out[i].ld0 = kh.k_ext;
+    }
+    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0, r32, sys->rb_variant));
+    if (a->v_r_t && k0 + FFT_MAXK >= sys->n_k) {  // Theta V read: the next step's synthesis
+      LTD_HIP(hipEventRecord(sys->ev_xz, s));
+      LTD_HIP(hipStreamWaitEvent(sys->side3, sys->ev_xz, 0));
+      LTD_HIP(launch_lookahead(rv, sys->side3));
+      LTD_TRY(rebuild_potential(sys, a->v_r_t, a->v_stride ? rv : nullptr, a->v_stride,
+                                sys->at<double>(sys->o_thv_step), r32, sys->side3));
+      LTD_HIP(hipEventRecord(sys->ev_syn, sys->side3));
+    }
+    for (int i = 0; i < nk; ++i) ka.slab_in[i] = ka.slab_out[i];
+    LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1, r32, 0));
+  }
+  LTD_HIP(hipStreamWaitEvent(s, sys->ev_join, 0));
   return LTD_OK;
 }
 
@@ -746,24 +813,21 @@ void drop_graphs(ltd_system *sys) {
 
 // Pipelined steps (REBUILD): each step rebuilds V~ of the next step on `s`
 // while the exponential of the current step runs on side2.  The rebuild's step
-// index rs[0] is its own counter (set at the start of a propagate call, then
+// indices are counters of their own (set at the start of a propagate call, then
 // advanced by one per step and clamped to the call's last step), so the rebuild
 // chain never waits for the exponential; side2 waits for the V~ it assembles
 // (ev_p0), and the projection that overwrites V~ waits until it was assembled
-// (ev_asm).  `join`: the last step of a capture joins side2 back into s.
-// map_back is a no-op without C.
-ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s, bool join) {
-  int *rs = sys->at<int>(sys->o_status) + 12;
-  ltd_step_args an = *a;
-  an.step = rs;
+// (ev_asm).  `first`: the first step of a capture (Theta V of its rebuild was
+// made before the capture); `join`: the last step joins side2 and side3 back
+// into s.  map_back is a no-op without C.
+ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s, bool first, bool join) {
   const StepCtx c = step_ctx(sys, a);
   LTD_HIP(hipEventRecord(sys->ev_p0, s));
   LTD_HIP(hipStreamWaitEvent(sys->side2, sys->ev_p0, 0));
   LTD_HIP(launch_assemble(c, sys->side2));
   LTD_HIP(hipEventRecord(sys->ev_asm, sys->side2));
   LTD_HIP(launch_step_only(c, sys->side2));
-  LTD_HIP(launch_lookahead(rs, s));
-  LTD_TRY(rebuild_v(sys, &an, s, nullptr, -1, false));
+  LTD_TRY(rebuild_v_pipe(sys, a, s, !first));
   LTD_HIP(hipStreamWaitEvent(s, sys->ev_asm, 0));
   LTD_TRY(project_v(sys, s));
   // the map-back GEMM shares the split-K partials with the rebuild's GEMMs: it
@@ -772,6 +836,7 @@ ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s
     LTD_HIP(hipEventRecord(sys->ev_pj, sys->side2));
     LTD_HIP(hipStreamWaitEvent(s, sys->ev_pj, 0));
   }
+  if (join && a->v_r_t) LTD_HIP(hipStreamWaitEvent(s, sys->ev_syn, 0));
   LTD_TRY(map_back(sys, a, s));
   return LTD_OK;
 }
@@ -979,7 +1044,9 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_thv = ar.take(sys->ngrid * sizeof(double));
   sys->o_thv_rb = ar.take(sys->ngrid * sizeof(double));
   sys->o_thv_step = ar.take(sys->ngrid * sizeof(double));
-  sys->o_status = ar.take(64);  // [0..1] status, [8] step-kernel block counter, [12..13] lookahead
+  // [0..1] status, [8] step-kernel block counter, [12..13] and [14..15] step index
+  // and last step of the pipelined rebuild (muffin-tin branch, potential synthesis)
+  sys->o_status = ar.take(64);
   sys->o_part = ar.take((size_t)4 * sys->n_k * sys->n_states * sizeof(double));
   sys->o_partials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
   const long long slab_f = (long long)g.nbz * g.n1 * g.n2 * sys->chunk;
@@ -1067,6 +1134,9 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
     LTD_HIP(hipEventCreateWithFlags(&sys->ev_p0, hipEventDisableTiming));
     LTD_HIP(hipEventCreateWithFlags(&sys->ev_asm, hipEventDisableTiming));
     LTD_HIP(hipEventCreateWithFlags(&sys->ev_pj, hipEventDisableTiming));
+    LTD_HIP(hipStreamCreateWithFlags(&sys->side3, hipStreamNonBlocking));
+    LTD_HIP(hipEventCreateWithFlags(&sys->ev_xz, hipEventDisableTiming));
+    LTD_HIP(hipEventCreateWithFlags(&sys->ev_syn, hipEventDisableTiming));
   }
   // twiddles exp(-2 pi i m / L)
   auto tw = [&](int L, size_t off) -> ltd_status {
@@ -1155,6 +1225,9 @@ ltd_status ltd_destroy(ltd_system *sys) {
   if (sys->ev_p0) (void)hipEventDestroy(sys->ev_p0);
   if (sys->ev_asm) (void)hipEventDestroy(sys->ev_asm);
   if (sys->ev_pj) (void)hipEventDestroy(sys->ev_pj);
+  if (sys->side3) (void)hipStreamDestroy(sys->side3);
+  if (sys->ev_xz) (void)hipEventDestroy(sys->ev_xz);
+  if (sys->ev_syn) (void)hipEventDestroy(sys->ev_syn);
   delete sys;
   return LTD_OK;
 }
@@ -1489,12 +1562,17 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
     LTD_TRY(build_step_tables(sys));
   }
   const bool pipe = a->mode == LTD_STEP_REBUILD && sys->side2 != nullptr;
-  if (pipe) {  // V~ of the first step, and the lookahead bounds of this call
+  if (pipe) {  // V~ of the first step, Theta V of the second, the step-index bounds of this call
     int *rs = sys->at<int>(sys->o_status) + 12;
     LTD_HIP(launch_lookahead_init(a->step, n_steps, rs, s));
     ltd_step_args a0 = *a;
     a0.step = rs;
     LTD_TRY(rebuild_v(sys, &a0, s));
+    if (a->v_r_t) {
+      LTD_HIP(launch_lookahead(rs + 2, s));
+      LTD_TRY(rebuild_potential(sys, a->v_r_t, a->v_stride ? rs + 2 : nullptr, a->v_stride,
+                                sys->at<double>(sys->o_thv_step), resid32(sys), s));
+    }
   }
   const bool same = sys->gvalid && sys->gpipe == pipe && std::memcmp(&sys->gargs, a, sizeof(ltd_step_args)) == 0;
   if (!same) {
@@ -1510,7 +1588,7 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
     LTD_HIP(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeThreadLocal));
     ltd_status st = LTD_OK;
     for (int i = 0; i < k && st == LTD_OK; ++i)
-      st = pipe ? pipelined_step(sys, a, sys->cap_stream, i == k - 1) : step_once(sys, a, sys->cap_stream);
+      st = pipe ? pipelined_step(sys, a, sys->cap_stream, i == 0, i == k - 1) : step_once(sys, a, sys->cap_stream);
     hipGraph_t gr = nullptr;
     const hipError_t ec = hipStreamEndCapture(sys->cap_stream, &gr);
     if (st != LTD_OK) {

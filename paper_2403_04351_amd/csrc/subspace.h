@@ -87,7 +87,8 @@ hipError_t launch_step(const StepCtx &c, hipStream_t s);
 // exponential, observables and step counter (k_step).
 hipError_t launch_assemble(const StepCtx &c, hipStream_t s);
 hipError_t launch_step_only(const StepCtx &c, hipStream_t s);
-// rs[0] = *step, rs[1] = *step + n_steps - 1 (lookahead bounds of one propagate call)
+// rs[0] = rs[2] = *step, rs[1] = rs[3] = *step + n_steps - 1 (two step-index counters
+// of one propagate call, each with its last step)
 hipError_t launch_lookahead_init(const int *step, int n_steps, int *rs, hipStream_t s);
 // rs[0] = min(rs[0] + 1, rs[1]): the step whose V~ the pipelined rebuild computes
 hipError_t launch_lookahead(int *rs, hipStream_t s);

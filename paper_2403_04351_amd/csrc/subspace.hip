@@ -862,8 +862,8 @@ hipError_t launch_step_only(const StepCtx &c, hipStream_t s) {
 }
 
 __global__ void k_lookahead_init(const int *step, int n_steps, int *rs) {
-  rs[0] = *step;
-  rs[1] = *step + n_steps - 1;
+  rs[0] = rs[2] = *step;
+  rs[1] = rs[3] = *step + n_steps - 1;
 }
 
 __global__ void k_lookahead(int *rs) { rs[0] = min(rs[0] + 1, rs[1]); }
