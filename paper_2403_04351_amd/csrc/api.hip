@@ -18,7 +18,9 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr long long PART_TILES = 2048;  // split-K partial budget (64x64 complex tiles)
-constexpr int GRAPH_STEPS = 8;          // steps captured in the multi-step graph
+// steps captured per graph: a call replays the largest that fit, then the smaller ones
+constexpr int GRAPH_TIERS = 3;
+constexpr int GRAPH_STEPS[GRAPH_TIERS] = {32, 8, 1};
 
 size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -118,10 +120,8 @@ struct ltd_system {
   std::vector<SubDev> sd;
   double cheb_dt = NAN;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec = nullptr;  // one step
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec_m = nullptr;  // GRAPH_STEPS steps (one replay boundary per GRAPH_STEPS steps)
-  hipGraph_t graph_m = nullptr;
+  hipGraphExec_t gexec[GRAPH_TIERS] = {};  // GRAPH_STEPS[t] steps per replay
+  hipGraph_t graph[GRAPH_TIERS] = {};
   ltd_step_args gargs{};
   bool gvalid = false;
   bool gpipe = false;  // the captured step is the pipelined one
@@ -803,12 +803,12 @@ ltd_status check_step_args(ltd_system *sys, const ltd_step_args *a) {
 }
 
 void drop_graphs(ltd_system *sys) {
-  if (sys->gexec) (void)hipGraphExecDestroy(sys->gexec);
-  if (sys->graph) (void)hipGraphDestroy(sys->graph);
-  if (sys->gexec_m) (void)hipGraphExecDestroy(sys->gexec_m);
-  if (sys->graph_m) (void)hipGraphDestroy(sys->graph_m);
-  sys->gexec = sys->gexec_m = nullptr;
-  sys->graph = sys->graph_m = nullptr;
+  for (int t = 0; t < GRAPH_TIERS; ++t) {
+    if (sys->gexec[t]) (void)hipGraphExecDestroy(sys->gexec[t]);
+    if (sys->graph[t]) (void)hipGraphDestroy(sys->graph[t]);
+    sys->gexec[t] = nullptr;
+    sys->graph[t] = nullptr;
+  }
 }
 
 // Pipelined steps (REBUILD): each step rebuilds V~ of the next step on `s`
@@ -1581,7 +1581,7 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
     sys->gpipe = pipe;
     sys->gvalid = true;
   }
-  // k steps in one capture; replayed graphs of GRAPH_STEPS steps, then single steps
+  // k steps in one capture (a replay boundary per k steps)
   const auto ensure = [&](int k, hipGraph_t *g, hipGraphExec_t *x) -> ltd_status {
     if (*x) return LTD_OK;
     if (!sys->cap_stream) LTD_HIP(hipStreamCreateWithFlags(&sys->cap_stream, hipStreamNonBlocking));
@@ -1600,11 +1600,14 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
     LTD_HIP(hipGraphInstantiate(x, gr, nullptr, nullptr, 0));
     return LTD_OK;
   };
-  const int nm = n_steps / GRAPH_STEPS, n1 = n_steps % GRAPH_STEPS;
-  if (nm > 0) LTD_TRY(ensure(GRAPH_STEPS, &sys->graph_m, &sys->gexec_m));
-  if (n1 > 0) LTD_TRY(ensure(1, &sys->graph, &sys->gexec));
-  for (int i = 0; i < nm; ++i) LTD_HIP(hipGraphLaunch(sys->gexec_m, s));
-  for (int i = 0; i < n1; ++i) LTD_HIP(hipGraphLaunch(sys->gexec, s));
+  int left = n_steps;
+  for (int t = 0; t < GRAPH_TIERS; ++t) {
+    const int reps = left / GRAPH_STEPS[t];
+    if (reps == 0) continue;
+    LTD_TRY(ensure(GRAPH_STEPS[t], &sys->graph[t], &sys->gexec[t]));
+    for (int i = 0; i < reps; ++i) LTD_HIP(hipGraphLaunch(sys->gexec[t], s));
+    left -= reps * GRAPH_STEPS[t];
+  }
   return LTD_OK;
 }
 

@@ -778,6 +778,14 @@ __device__ __forceinline__ void twiddle_powers(T *v, T w) {
   }
 }
 
+// v[j] *= t[j] (DIR = -1) or conj(t[j]) (DIR = +1), j = 1 .. R-1: the twiddles of
+// one lane from its table of exp(-2 pi i role j / N)
+template <int R, int DIR, class T>
+__device__ __forceinline__ void twiddle_tab(T *v, const T *t) {
+#pragma unroll
+  for (int j = 1; j < R; ++j) v[j] = cmul(v[j], DIR < 0 ? t[j] : cconj(t[j]));
+}
+
 // LDS layout of k_rb_xz4.  On 64-point lines (8 x 8) the exchange slots of
 // value (i, j) of a line's 8 x 8 block are i 8 + (j ^ i) (XOR swizzle), the
 // rows have pitch 66 (complex128) or 68 (complex64) and the two rows a 16-lane
@@ -823,6 +831,13 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
   const int lz = lane / TZ::G, rz = lane - lz * TZ::G;
   // row of line lx within a wave's group of LPW rows (SWZ: a 16-lane group takes rows r, r + 4)
   const int lxr = SWZ ? ((lx >> 1) | ((lx & 1) << 2)) : lx;
+  // SWZ (x and z 8 x 8, rx == rz): this lane's twiddles exp(-2 pi i rx j / 64), j < 8,
+  // shared by the four two-factor passes
+  T twt[8];
+  if constexpr (SWZ) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) twt[j] = CT<T>::from(g.tw1[(rx * j) & 63]);
+  }
 
   // phase 1: inverse x transforms of the box rows, in place in R
   {
@@ -843,9 +858,13 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
           const int kx = n <= bx ? n : n - NX;
           v[n1] = (n <= bx || n >= NX - bx) ? in[r * rs + kx + bx] : CT<T>::mk(0, 0);
         }
-        if constexpr (SWZ) dft8_z2345<1>(v);
-        else dft_reg<X1, 1>(v);
-        twiddle_powers<X1>(v, w);
+        if constexpr (SWZ) {
+          dft8_z2345<1>(v);
+          twiddle_tab<X1, 1>(v, twt);
+        } else {
+          dft_reg<X1, 1>(v);
+          twiddle_powers<X1>(v, w);
+        }
 #pragma unroll
         for (int k1 = 0; k1 < X1; ++k1) row[xslot<SWZ>(k1, rx, X2)] = v[k1];
       }
@@ -888,9 +907,13 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
           const int row = n <= bz ? n + bz : n - NZ + bz;
           v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : CT<T>::mk(0, 0);
         }
-        if constexpr (SWZ) dft8_z2345<1>(v);
-        else dft_reg<Z1, 1>(v);
-        twiddle_powers<Z1>(v, w);
+        if constexpr (SWZ) {
+          dft8_z2345<1>(v);
+          twiddle_tab<Z1, 1>(v, twt);
+        } else {
+          dft_reg<Z1, 1>(v);
+          twiddle_powers<Z1>(v, w);
+        }
 #pragma unroll
         for (int k1 = 0; k1 < Z1; ++k1) sl[xslot<SWZ>(rz, k1, TZ::P)] = v[k1];
       }
@@ -903,7 +926,8 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
 #pragma unroll
         for (int k2 = 0; k2 < Z2; ++k2) u[k2] = cscale(u[k2], t[k2]);
         dft_reg<Z2, -1>(u);
-        twiddle_powers<Z2>(u, wc);
+        if constexpr (SWZ) twiddle_tab<Z2, -1>(u, twt);
+        else twiddle_powers<Z2>(u, wc);
         wave_fence();
 #pragma unroll
         for (int d = 0; d < Z2; ++d) sl[xslot<SWZ>(rz, d, TZ::P)] = u[d];
@@ -938,7 +962,8 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
 #pragma unroll
         for (int b = 0; b < X2; ++b) u[b] = row[rx + X1 * b];
         dft_reg<X2, -1>(u);
-        twiddle_powers<X2>(u, wc);
+        if constexpr (SWZ) twiddle_tab<X2, -1>(u, twt);
+        else twiddle_powers<X2>(u, wc);
         wave_fence();
 #pragma unroll
         for (int d = 0; d < X2; ++d) row[xslot<SWZ>(rx, d, X2)] = u[d];

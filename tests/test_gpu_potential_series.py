@@ -133,14 +133,17 @@ def test_adjoint_with_potential_series_matches_oracle():
 
 
 @pytest.mark.parametrize("grid", [None, (64, 64, 64)], ids=["grid16", "grid64_rebuilt_on_16"])
-def test_pipelined_replay_equals_stepwise_with_series(grid):
-    """ltd_propagate rebuilds V~ of step n + 1 beside the exponential of step n
-    (lookahead index from the device counter, clamped to the call's last step);
-    the arithmetic is that of the stepwise calls, so the results are bit-identical:
-    one call of n steps, two calls of n1 + n2 steps, and n single steps (the
-    series, the states and the mapped-back coefficients C)."""
+@pytest.mark.parametrize("with_c", [True, False])
+def test_pipelined_replay_equals_stepwise_with_series(grid, with_c):
+    """ltd_propagate rebuilds V~ of step n + 1 beside the exponential of step n,
+    and synthesises Theta V of step n + 2 beside the read-out of step n + 1
+    (step indices from device counters, clamped to the call's last step); the
+    arithmetic is that of the stepwise calls, so the results are bit-identical:
+    one call of n steps (graphs of 32, 8 and 1 steps), two calls of n1 + n2
+    steps, and n single steps (the series, the states and, with_c, the
+    mapped-back coefficients C, which join the streams every step)."""
     sys, phi, sub, lt, ltd, torch = _setup(grid)
-    n, n1 = 24, 9
+    n, n1 = 45, 9
     a_t, a_mid = pulse_samples(sys, n)
     s_n = np.sin(0.4 * np.arange(n))
     pot, _ = _series(sys, phi, lt, torch, s_n)
@@ -149,7 +152,7 @@ def test_pipelined_replay_equals_stepwise_with_series(grid):
 
     def fresh():
         theta = torch.from_numpy(np.ascontiguousarray(th0.T)[None]).to(dev)
-        cout = torch.zeros((sys.n_states, sys.n_basis(0)), dtype=torch.complex128, device=dev)
+        cout = torch.zeros((sys.n_states, sys.n_basis(0)), dtype=torch.complex128, device=dev) if with_c else None
         return lt.make_step_args(ltd.LTD_STEP_REBUILD, sys.dt, torch.from_numpy(a_t).to(dev),
                                  torch.from_numpy(a_mid).to(dev), theta, n, c_out=cout, **pot)
 
@@ -169,6 +172,6 @@ def test_pipelined_replay_equals_stepwise_with_series(grid):
     assert lt.sync_status() == 0
     ref = runs["stepwise"]
     for name in ("one call", "two calls"):
-        for key in ("j", "e", "dmu", "theta", "c_out"):
+        for key in ("j", "e", "dmu", "theta") + (("c_out",) if with_c else ()):
             assert np.array_equal(runs[name][key].cpu().numpy(), ref[key].cpu().numpy()), (name, key)
     assert int(runs["two calls"]["step"].item()) == n
