@@ -801,6 +801,37 @@ constexpr int xz4_ls() { return xz4_swz<NX, X1, NZ, Z1>() ? 72 : Two<NZ, Z1, NZ 
 // exchange slot of (i, j) in a block of rows of length `pitch` (swizzled or plain)
 template <bool SWZ>
 __device__ __forceinline__ int xslot(int i, int j, int pitch) { return SWZ ? i * 8 + (j ^ i) : i * pitch + j; }
+// complex128 on the swizzled 8 x 8 layout: the z lines exchange their real and
+// imaginary parts one after the other through a scratch of doubles (lines 72
+// doubles apart, again distinct banks for every 32-lane group of 8-byte
+// accesses), half the LDS of a complex scratch: three blocks fit a CU
+template <int NX, int X1, int NZ, int Z1, class T>
+constexpr bool xz4_split() { return xz4_swz<NX, X1, NZ, Z1>() && sizeof(T) == 16; }
+// LDS bytes of k_rb_xz4 (rows, then NW x LZ z-line scratch)
+template <int NX, int X1, int NZ, int Z1, class T>
+constexpr size_t xz4_lds(int nbz, int nw, int lz) {
+  return (size_t)nbz * xz4_rx<NX, X1, NZ, Z1, T>() * sizeof(T) +
+         (size_t)nw * lz * xz4_ls<NX, X1, NZ, Z1>() * (xz4_split<NX, X1, NZ, Z1, T>() ? sizeof(double) : sizeof(T));
+}
+
+// 8 x 8 transpose of one z line through its scratch sd (doubles, slot xslot<true>):
+// lane r holds in[k] = value (r, k) and receives out[q] = value (q, r); the real
+// parts pass first, then the imaginary parts through the same slots (LDS
+// operations of one wave complete in order, so no wait is needed between them)
+__device__ __forceinline__ void xch8_split(double *sd, int r, const double2 (&in)[8], double2 (&out)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sd[xslot<true>(r, k, 8)] = in[k].x;
+  wave_fence();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) out[q].x = sd[xslot<true>(q, r, 8)];
+  wave_fence();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sd[xslot<true>(r, k, 8)] = in[k].y;
+  wave_fence();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) out[q].y = sd[xslot<true>(q, r, 8)];
+  wave_fence();
+}
 
 // Same transforms with NW waves per block: an x row exchanges in place through
 // its own RX slots (value (k1, n2) at slot k1 F2 + n2, odd stride across lanes);
@@ -816,13 +847,15 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
   constexpr bool SWZ = xz4_swz<NX, X1, NZ, Z1>();
   constexpr int RX = xz4_rx<NX, X1, NZ, Z1, T>();
   constexpr int LS = xz4_ls<NX, X1, NZ, Z1>();
+  constexpr bool SPLIT = xz4_split<NX, X1, NZ, Z1, T>();
   extern __shared__ double2 sm_raw[];
   T *sm = reinterpret_cast<T *>(sm_raw);
   const int col = blockIdx.x, y = blockIdx.y, kk = blockIdx.z;
   const int n2 = g.n2, bx = g.bx, nbx = g.nbx, bz = g.bz, nbz = g.nbz;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T *R = sm;
-  T *scr = sm + nbz * RX + wave * (LZ * LS);
+  T *scr = sm + nbz * RX + wave * (LZ * LS);  // complex scratch (!SPLIT)
+  double *scd = reinterpret_cast<double *>(sm + nbz * RX) + wave * (LZ * LS);  // SPLIT
   const long long csz = (long long)nbz * n2 * nbx;
   const long long rs = (long long)n2 * nbx;  // kz stride of the box arrays
   const T *in = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)y * nbx;
@@ -895,6 +928,40 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
 #pragma unroll
       for (int k2 = 0; k2 < Z2; ++k2)
         t[k2] = thp[(((long long)y * Z2 + k2) * NX + (x < NX ? x : NX - 1)) * Z1 + (rz < Z1 ? rz : 0)];
+      if constexpr (SPLIT) {  // 8 x 8, complex128: the same transforms, split exchanges
+        if (on) {
+          double2 v[8], u[8];
+#pragma unroll
+          for (int n1 = 0; n1 < 8; ++n1) {
+            if (n1 >= 2 && n1 <= 5) {
+              v[n1] = make_double2(0.0, 0.0);
+              continue;
+            }
+            const int n = 8 * n1 + rz;
+            const int row = n <= bz ? n + bz : n - NZ + bz;
+            v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : make_double2(0.0, 0.0);
+          }
+          dft8_z2345<1>(v);
+          twiddle_tab<8, 1>(v, twt);
+          double *sd = scd + lz * LS;
+          xch8_split(sd, rz, v, u);
+          dft_reg<8, 1>(u);
+#pragma unroll
+          for (int k2 = 0; k2 < 8; ++k2) u[k2] = cscale(u[k2], t[k2]);
+          dft_reg<8, -1>(u);
+          twiddle_tab<8, -1>(u, twt);
+          xch8_split(sd, rz, u, v);
+          dft_reg<8, -1>(v);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            if (c >= 2 && c <= 5) continue;
+            const int m = 8 * c + rz;
+            if (m <= bz || m >= NZ - bz) R[(m <= bz ? m + bz : m - NZ + bz) * RX + x] = v[c];
+          }
+        }
+        wave_fence();
+        continue;
+      }
       if (on && rz < Z2) {
         T v[Z1];
 #pragma unroll
@@ -1567,12 +1634,11 @@ template <int N, int F1, class T>
 void launch_xz4(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s, int v) {
   using TZ = Two<N, F1, N / F1>;
   const auto *th = static_cast<const typename CT<T>::R *>(thv);
-  const size_t fixed = (size_t)g.nbz * xz4_rx<N, F1, N, F1, T>();
   const dim3 grid(ncols, g.n2, nk);
 #define LTD_V(V)                                                                                                \
   do {                                                                                                          \
     constexpr int NW = rb_nw_of(V), LZ = rb_lz_of<N, F1>(V);                                                    \
-    const size_t lds = (fixed + (size_t)NW * LZ * xz4_ls<N, F1, N, F1>()) * sizeof(T);                           \
+    const size_t lds = xz4_lds<N, F1, N, F1, T>(g.nbz, NW, LZ);                                                   \
     hipLaunchKernelGGL((k_rb_xz4<N, F1, N / F1, N, F1, N / F1, NW, LZ, T>), grid, dim3(NW * 64), lds, s, g, ka, \
                        ncols, th);                                                                              \
   } while (0)
