@@ -108,6 +108,7 @@ struct ltd_system {
   char *ws = nullptr;
   size_t ws_need = 0, ws_bound = 0;
   size_t o_tw1, o_tw2, o_tw3, o_thv, o_thv_rb, o_thv_step, o_status, o_part, o_partials;
+  size_t o_vpartials;  // split-K partials of the V~ projection (its own: reduced on another stream)
   size_t o_slab_in, o_slab_out, o_W, o_Y, o_heff, o_tvps, o_proj, o_tmp3, o_eigA, o_eigV, o_eigw;
   size_t o_stepslab, o_subdev, o_theta_sc, o_k6, o_hstep, o_zero32;
   K2Table k2_hs, k2_tvps, k2_step;
@@ -632,9 +633,12 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
 // blocks (K2), 4 projection of V~ (GEMM), 5 subspace step and observables, 6 map-back.
 // Rebuild V~(t) of every k for the potential of this step (v_r_t, h_t).
 // V~_step = Phi~_ext^H Y_ext of every bound k (one split-K GEMM table).
-ltd_status project_v(ltd_system *sys, hipStream_t s) {
+// parts: 1 the product (partials), 2 their reduction into V~, 3 both; the
+// reduction only reads the partials, so repeating it gives the same V~.
+ltd_status project_v(ltd_system *sys, hipStream_t s, int parts = 3) {
   LTD_HIP(gemm_launch_table(OP_C, OP_N, sys->at<ZProb>(sys->o_vstep_tab), sys->vstep_tab.data(),
-                            (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_partials), 0, s));
+                            (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_vpartials), 0, s,
+                            parts));
   return LTD_OK;
 }
 
@@ -817,19 +821,24 @@ void drop_graphs(ltd_system *sys) {
 // advanced by one per step and clamped to the call's last step), so the rebuild
 // chain never waits for the exponential; side2 waits for the V~ it assembles
 // (ev_p0), and the projection that overwrites V~ waits until it was assembled
-// (ev_asm).  `first`: the first step of a capture (Theta V of its rebuild was
-// made before the capture); `join`: the last step joins side2 and side3 back
-// into s.  map_back is a no-op without C.
+// (ev_asm).  The projection's split-K reduction into V~ runs on side2 at the
+// start of the next step, before the assembly that reads V~ (the partials of
+// the last product of a call are reduced once more after its graphs; the
+// first step of a call reduces the prologue's partials a second time, which
+// gives the same V~).  `first`: the first step of a capture (Theta V of its
+// rebuild was made before the capture); `join`: the last step joins side2 and
+// side3 back into s.  map_back is a no-op without C.
 ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s, bool first, bool join) {
   const StepCtx c = step_ctx(sys, a);
   LTD_HIP(hipEventRecord(sys->ev_p0, s));
   LTD_HIP(hipStreamWaitEvent(sys->side2, sys->ev_p0, 0));
+  LTD_TRY(project_v(sys, sys->side2, 2));
   LTD_HIP(launch_assemble(c, sys->side2));
   LTD_HIP(hipEventRecord(sys->ev_asm, sys->side2));
   LTD_HIP(launch_step_only(c, sys->side2));
   LTD_TRY(rebuild_v_pipe(sys, a, s, !first));
   LTD_HIP(hipStreamWaitEvent(s, sys->ev_asm, 0));
-  LTD_TRY(project_v(sys, s));
+  LTD_TRY(project_v(sys, s, 1));
   // the map-back GEMM shares the split-K partials with the rebuild's GEMMs: it
   // runs on s, after the step (a join every step when C is requested)
   if (join || a->c_out) {
@@ -1049,6 +1058,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_status = ar.take(64);
   sys->o_part = ar.take((size_t)4 * sys->n_k * sys->n_states * sizeof(double));
   sys->o_partials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
+  sys->o_vpartials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
   const long long slab_f = (long long)g.nbz * g.n1 * g.n2 * sys->chunk;
   sys->o_slab_in = ar.take(4 * slab_f * sizeof(double2));
   sys->o_slab_out = ar.take(5 * slab_f * sizeof(double2));
@@ -1448,9 +1458,7 @@ ltd_status ltd_autotune(ltd_system *sys, int *choice, double *times_us, void *st
     if (st != LTD_OK) break;
     double us = 0.0;
     st = timed([&]() -> ltd_status {
-      LTD_HIP(gemm_launch_table(OP_C, OP_N, sys->at<ZProb>(sys->o_vstep_tab), sys->vstep_tab.data(),
-                                (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_partials), 0,
-                                s));
+      LTD_TRY(project_v(sys, s));
       return LTD_OK;
     }, &us);
     if (times_us) times_us[ti++] = us;
@@ -1608,6 +1616,7 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
     for (int i = 0; i < reps; ++i) LTD_HIP(hipGraphLaunch(sys->gexec[t], s));
     left -= reps * GRAPH_STEPS[t];
   }
+  if (pipe) LTD_TRY(project_v(sys, s, 2));  // V~ of the step after the call's last
   return LTD_OK;
 }
 

@@ -95,8 +95,9 @@ hipError_t gemm_launch(int opa, int opb, const ZBatch &b, double2 *partials, hip
 // Launches a planned batch whose problem table lives in device memory (any size);
 // `host` is the same table on the host (for the reduction pass).
 // n_limit > 0 caps every problem's column count (tiles beyond it exit at once).
+// parts: 1 the product kernel, 2 the split-K reduction (when K is split), 3 both.
 hipError_t gemm_launch_table(int opa, int opb, const ZProb *dev_table, const ZProb *host, int nprob,
-                             int total_tiles, double2 *partials, int n_limit, hipStream_t s);
+                             int total_tiles, double2 *partials, int n_limit, hipStream_t s, int parts = 3);
 
 // ----------------------------------------------------------------------------
 // Interstitial FFT pipeline.

@@ -362,9 +362,9 @@ __global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZP
 
 template <bool TABLE>
 hipError_t launch_impl(int opa, int opb, const ZBatch &b, const ZProb *table, const ZProb *host, int nprob,
-                       int total_tiles, double2 *partials, int n_limit, hipStream_t s) {
+                       int total_tiles, double2 *partials, int n_limit, hipStream_t s, int parts = 3) {
   if (total_tiles <= 0) return hipSuccess;
-  dim3 grid(total_tiles), block(NT);
+  const dim3 grid(total_tiles), block(NT);
 #define LTD_ZG(OA, OB)                                                                                         \
   do {                                                                                                         \
     if (host[0].bm == 32)                                                                                      \
@@ -372,13 +372,16 @@ hipError_t launch_impl(int opa, int opb, const ZBatch &b, const ZProb *table, co
     else                                                                                                       \
       hipLaunchKernelGGL((zgemm_kernel<OA, OB, TABLE, 64>), grid, block, 0, s, b, table, nprob, partials, n_limit); \
   } while (0)
-  if (opa == OP_N && opb == OP_N) LTD_ZG(OP_N, OP_N);
-  else if (opa == OP_C && opb == OP_N) LTD_ZG(OP_C, OP_N);
-  else if (opa == OP_N && opb == OP_C) LTD_ZG(OP_N, OP_C);
-  else LTD_ZG(OP_C, OP_C);
+  if (parts & 1) {
+    if (opa == OP_N && opb == OP_N) LTD_ZG(OP_N, OP_N);
+    else if (opa == OP_C && opb == OP_N) LTD_ZG(OP_C, OP_N);
+    else if (opa == OP_N && opb == OP_C) LTD_ZG(OP_N, OP_C);
+    else LTD_ZG(OP_C, OP_C);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
 #undef LTD_ZG
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (!(parts & 2)) return hipSuccess;
   bool split = false;
   int rtiles = 0;
   for (int i = 0; i < nprob; ++i) {
@@ -479,9 +482,9 @@ hipError_t gemm_launch(int opa, int opb, const ZBatch &b, double2 *partials, hip
 }
 
 hipError_t gemm_launch_table(int opa, int opb, const ZProb *dev_table, const ZProb *host, int nprob,
-                             int total_tiles, double2 *partials, int n_limit, hipStream_t s) {
+                             int total_tiles, double2 *partials, int n_limit, hipStream_t s, int parts) {
   static const ZBatch empty{};
-  return launch_impl<true>(opa, opb, empty, dev_table, host, nprob, total_tiles, partials, n_limit, s);
+  return launch_impl<true>(opa, opb, empty, dev_table, host, nprob, total_tiles, partials, n_limit, s, parts);
 }
 
 }  // namespace ltd
