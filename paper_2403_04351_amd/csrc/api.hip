@@ -312,10 +312,11 @@ void build_k2(const ltd_system *sys, const std::vector<const double2 *> &xs, con
   }
 }
 
+// target: the planner's block target (K is split below it; 0: never split)
 ltd_status upload_k2(ltd_system *sys, std::vector<ZProb> &p1, std::vector<ZProb> &p2, K2Table &t, size_t off1,
-                     size_t off2, size_t cap) {
+                     size_t off2, size_t cap, int target = 512) {
   int tt = 0;
-  gemm_plan(p1.data(), (int)p1.size(), &tt, 512, PART_TILES);
+  gemm_plan(p1.data(), (int)p1.size(), &tt, target, PART_TILES);
   t.tiles1 = tt;
   tt = 0;
   if (!p2.empty()) gemm_plan(p2.data(), (int)p2.size(), &tt, 512, PART_TILES);
@@ -592,7 +593,10 @@ ltd_status build_step_tables(ltd_system *sys) {
     pv.push_back(zp(n, n, kh.k_ext, ph, kh.k_ext, ye, kh.k_ext, sys->at<double2>(kh.o_vstep), n));
   }
   const size_t cap = (size_t)4 * sys->n_atoms * sys->n_k * sizeof(ZProb) + 1024;
-  LTD_TRY(upload_k2(sys, p1, p2, sys->k2_step, sys->o_k2_st1, sys->o_k2_st2, cap));
+  // the rebuild's block products run beside the x/z transforms: unsplit, on few
+  // CUs, with no reduction pass (a K split to fill the GPU took CUs from the
+  // transforms and cost 7 us per pipelined step)
+  LTD_TRY(upload_k2(sys, p1, p2, sys->k2_step, sys->o_k2_st1, sys->o_k2_st2, cap, 0));
   int tt = 0;
   gemm_plan(pv.data(), (int)pv.size(), &tt, sys->vproj_target, PART_TILES);
   sys->vstep_tab = pv;
