@@ -260,7 +260,9 @@ ltd_status ltd_propagate_step_adjoint(ltd_system *sys, const ltd_adjoint_args *a
  *
  * ltd_profile_steps: n_steps calls of ltd_propagate_step (advancing the step
  * counter); stage_ms[i] is the mean per step of stage i: 0 Theta V(t) on the
- * grid, 1 x/z transforms and Theta V product per y plane, 2 y transforms and
+ * grid, 1 x/z transforms and Theta V product per y plane (the mean of four
+ * back-to-back launches of that kernel, which rewrite the same output, so the
+ * figure is its launch duration without the latency after the event), 2 y transforms and
  * sphere read-out, 3 muffin-tin block products, 4 projection of V~ (Phi~^H Y), 5 subspace
  * exponential and observables, 6 map-back.
  *

@@ -238,7 +238,8 @@ class Ltd:
         return st
 
     def profile_steps(self, st, n_steps: int):
-        """Mean per-step duration (ms) of each stage over n_steps eager steps."""
+        """Mean per-step duration (ms) of each stage over n_steps eager steps (the
+        x/z stage: the mean of four back-to-back launches of its kernel)."""
         buf = (C.c_double * _lib.LTD_PROFILE_STAGES)()
         check(self.lib.ltd_profile_steps(self.handle, C.byref(st["args"]), n_steps, buf, self.stream()),
               "ltd_profile_steps")
