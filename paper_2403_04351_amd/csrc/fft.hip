@@ -1295,48 +1295,64 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xzr(const Grid g, const FftKArgs
   }
 }
 
-// y transforms of the rebuild step for N2' = 64 and nbx <= 32: one block per
-// (kz, column), one line per box x (4 waves x 8 lines x 8 lanes), each line the
-// two-factor forward transform of k_rb_xz4's phase 3 in place in its LDS row
-// (pitch 66, rows r and r + 4 in a 16-lane group, XOR-swizzled exchange); then
-// the sphere read-out as in k_rb_y.
+// The same 8 x 8 transpose for complex64 lines, through a float2 scratch (the
+// same slots: 8-byte accesses as in xch8_split).
+__device__ __forceinline__ void xch8_split(float2 *sd, int r, const float2 (&in)[8], float2 (&out)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sd[xslot<true>(r, k, 8)] = in[k];
+  wave_fence();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) out[q] = sd[xslot<true>(q, r, 8)];
+  wave_fence();
+}
+
+// y transforms of the rebuild step for N2' = 64, nbx <= 32 and by <= 15: one
+// block per (kz, column), one line per box x (4 waves x 8 lines x 8 lanes).
+// Each lane loads the values y = rx + 8 b of its line straight from the slab
+// (eight 128-byte runs per load across a wave), runs the two-factor forward
+// transform of k_rb_xz4's phase 3 with the exchange through a per-line scratch
+// (lines 72 eight-byte slots apart; complex128 passes its real and imaginary
+// parts in turn), and keeps the outputs with |ky| <= by in a box [x][ky] that
+// takes the scratch's place; then the sphere read-out.  18 KB of LDS per block.
+constexpr int Y64_LS = 72;
+constexpr size_t y64_lds_bytes() { return (size_t)32 * Y64_LS * 8; }
 template <class T>
 __global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka, int ncols) {
-  constexpr int N = 64, BP = 66;
+  constexpr int N = 64;
+  using XT = typename std::conditional<sizeof(T) == 16, double, float2>::type;  // scratch slot type
   extern __shared__ double2 sm_raw[];
-  T *bxc = reinterpret_cast<T *>(sm_raw);
+  XT *scr = reinterpret_cast<XT *>(sm_raw);
+  T *box = reinterpret_cast<T *>(sm_raw);  // after the transforms: [x][ky + by], pitch nby
   const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
-  const int nbx = g.nbx, bx = g.bx;
+  const int nbx = g.nbx, bx = g.bx, by = g.by, nby = g.nby;
   const KSphere &sp = ka.sph[kk];
   const FwdOut &fo = ka.out[kk];
   const long long csz = (long long)g.nbz * N * nbx;
   const T *src = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)pz * N * nbx;
-  stage8<T>(
-      N * nbx, [&](int i) { return src[i]; }, [&](int i, T x) { bxc[(i % nbx) * BP + i / nbx] = x; });
-  __syncthreads();
-  {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lx = lane >> 3, rx = lane & 7;
-    const int line = wave * 8 + ((lx >> 1) | ((lx & 1) << 2));
-    if (line < nbx) {
-      T *row = bxc + line * BP;
-      const T wc = CT<T>::from(g.tw2[rx]);
-      T u[8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lx = lane >> 3, rx = lane & 7;
+  const int line = wave * 8 + lx;
+  T v[8];
+  if (line < nbx) {
+    T twt[8];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) u[b] = row[rx + 8 * b];
-      dft8<-1>(u);
-      twiddle_powers<8>(u, wc);
-      wave_fence();
+    for (int j = 0; j < 8; ++j) twt[j] = CT<T>::from(g.tw2[(rx * j) & 63]);
+    T u[8];
 #pragma unroll
-      for (int d = 0; d < 8; ++d) row[xslot<true>(rx, d, 8)] = u[d];
-      wave_fence();
-      T v[8];
+    for (int b = 0; b < 8; ++b) u[b] = src[(rx + 8 * b) * nbx + line];
+    dft8<-1>(u);
+    twiddle_tab<8, -1>(u, twt);
+    xch8_split(scr + line * Y64_LS, rx, u, v);
+    dft8<-1>(v);
+  }
+  __syncthreads();  // every line has left the scratch
+  if (line < nbx) {
 #pragma unroll
-      for (int a = 0; a < 8; ++a) v[a] = row[xslot<true>(a, rx, 8)];
-      dft8<-1>(v);
-      wave_fence();
-#pragma unroll
-      for (int c = 0; c < 8; ++c) row[8 * c + rx] = v[c];
+    for (int c = 0; c < 8; ++c) {
+      if (c >= 2 && c <= 5) continue;  // |ky| >= 16 > by
+      const int m = 8 * c + rx;
+      const int ky = m < 32 ? m : m - N;
+      if (ky >= -by && ky <= by) box[line * nby + ky + by] = v[c];
     }
   }
   __syncthreads();
@@ -1345,8 +1361,8 @@ __global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka,
   for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
     const int xy = sp.pts_xy[i];
     const int yy = xy / g.d1, x = xy - yy * g.d1;
-    const int yr = yy <= g.by ? yy : yy - g.d2 + N;
-    fo.o0[i + (long long)col * fo.ld0] = cscale(to_d2(bxc[box_of(x, g.d1, bx) * BP + yr]), inv_n);
+    const int ky = yy <= by ? yy : yy - g.d2;
+    fo.o0[i + (long long)col * fo.ld0] = cscale(to_d2(box[box_of(x, g.d1, bx) * nby + ky + by]), inv_n);
   }
 }
 
@@ -1712,7 +1728,12 @@ size_t fft_rb_slab_values(const Grid &g) { return (size_t)g.nbz * g.n2 * g.nbx; 
 
 // Two-factor splits of the x and z lengths with a register path (0 if none).
 int rb_split(int n) { return n == 72 ? 8 : n == 64 ? 8 : n == 16 ? 4 : 0; }
-bool rb_fast(const Grid &g) { return rb_split(g.n1) > 0 && rb_split(g.n3) > 0; }
+// the register x/z kernel; on 64-point axes it drops the inputs and outputs with
+// |frequency| >= 16, so the box there must have b <= 15 (which 64 >= 4 b + 1 gives)
+bool rb_fast(const Grid &g) {
+  const auto ok = [](int n, int b) { return rb_split(n) > 0 && (n != 64 || b <= 15); };
+  return ok(g.n1, g.bx) && ok(g.n3, g.bz);
+}
 
 
 bool fft_rb_fast(const Grid &g) { return rb_fast(g); }
@@ -1902,8 +1923,8 @@ hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, con
     if (fp32) hipLaunchKernelGGL((k_rb_y<a, float2>), grid, block, lds, s, g, ka, ncols); \
     else hipLaunchKernelGGL((k_rb_y<a, double2>), grid, block, lds, s, g, ka, ncols);     \
   } while (0)
-    if (g.n2 == 64 && g.nbx <= 32) {
-      const size_t lds64 = (size_t)g.nbx * 66 * (fp32 ? sizeof(float2) : sizeof(double2));
+    if (g.n2 == 64 && g.nbx <= 32 && g.by <= 15) {
+      const size_t lds64 = y64_lds_bytes();
       if (fp32) hipLaunchKernelGGL(k_rb_y64<float2>, grid, dim3(256), lds64, s, g, ka, ncols);
       else hipLaunchKernelGGL(k_rb_y64<double2>, grid, dim3(256), lds64, s, g, ka, ncols);
     } else if (g.n2 == 16) LTD_RY(16);

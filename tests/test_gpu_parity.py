@@ -276,3 +276,36 @@ def test_singular_overlap_is_reported(cfg0, torch):
     with pytest.raises(_lib.LtdError) as ei:
         lt2.project_subspace(0, ltd.colmajor(phi, lt2.device))
     assert ei.value.code == _lib.LTD_ENOTSPD
+
+
+def test_rebuild_on_64_grid_with_box_past_15(torch):
+    """A 64-point grid whose G box reaches |g| = 16 (N < 4 b + 1, so the rebuild
+    runs on the grid itself): the register x/z kernel, which drops |frequency|
+    >= 16 on 64-point axes, must not be taken.  With the static potential the
+    rebuilt V~ is the reference V~ of the projection (another route through the
+    full-grid H apply), so REBUILD and AFFINE propagate alike."""
+    from paper_2403_04351_amd import ltd
+
+    sys = make_system(0, grid=(64, 64, 64), n_g=20000, n_aux=8, n_states=2)
+    assert np.abs(sys.kpts[0].g_int).max() == 16
+    lt = ltd.Ltd(sys, max_cols=8)
+    assert tuple(lt.rebuild_grid()) == (64, 64, 64)
+    rng = np.random.default_rng(64016)
+    nb = sys.n_basis(0)
+    phi = rng.standard_normal((nb, 8)) + 1j * rng.standard_normal((nb, 8))
+    lt.project_subspace(0, ltd.colmajor(phi, lt.device))
+    n_steps = 6
+    a_t, a_mid = pulse_samples(sys, n_steps)
+    th0 = pr.initial_theta(sys.n_aux, sys.n_states)
+    runs = {}
+    for name, mode in (("affine", ltd.LTD_STEP_AFFINE), ("rebuild", ltd.LTD_STEP_REBUILD)):
+        theta = torch.from_numpy(np.ascontiguousarray(th0.T)[None]).to(lt.device)
+        runs[name] = lt.propagate(mode, sys.dt, torch.from_numpy(a_t).to(lt.device),
+                                  torch.from_numpy(a_mid).to(lt.device), theta, n_steps)
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+    a, b = runs["affine"], runs["rebuild"]
+    print(f"64-grid b=16: J {rel_max(b['j'].cpu().numpy(), a['j'].cpu().numpy()):.2e} "
+          f"theta {rel_max(b['theta'].cpu().numpy(), a['theta'].cpu().numpy()):.2e}", flush=True)
+    assert rel_max(b["j"].cpu().numpy(), a["j"].cpu().numpy()) < 1e-12
+    assert rel_max(b["theta"].cpu().numpy(), a["theta"].cpu().numpy()) < 1e-12
