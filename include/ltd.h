@@ -148,8 +148,8 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
  * form the auxiliary basis (Sec. 2.2, Eq. (11)).  Synchronises `stream`. */
 ltd_status ltd_ritz_basis(ltd_system *sys, int k, void *x, int ldx, double *eps, void *stream);
 
-/* Tuner of the per-step rebuild's launch shapes (batched k-points: tiles from
- * an autotuner, the survey's extension 2): times, on the bound subspaces, every
+/* Tuner of the per-step rebuild's launch shapes (batched k-points, with the
+ * tiles chosen by a tuner rather than fixed): times, on the bound subspaces, every
  * launch shape of the x/z transform kernel (three shapes of the two-factor
  * kernel, whose results do not depend on the shape, and for the FP32 residual
  * on a 64-point rebuild grid a fourth, register-resident kernel: the same
