@@ -225,10 +225,15 @@ typedef struct {
  * written too.  Every k-point needs a bound subspace. */
 ltd_status ltd_propagate_step(ltd_system *sys, const ltd_step_args *args, void *stream);
 
-/* n_steps calls of ltd_propagate_step, recorded once into a hipGraph and
- * replayed (the device step counter selects the pulse samples and, with
- * nonzero strides, the potential of the step).  REBUILD re-reads v_r_t / h_t
- * every step. */
+/* n_steps calls of ltd_propagate_step, recorded once into hipGraphs of 32, 8
+ * and 1 steps and replayed, the largest that fit first (the device step
+ * counter selects the pulse samples and, with nonzero strides, the potential
+ * of the step).  REBUILD re-reads v_r_t / h_t every step and is pipelined: the
+ * rebuild of V_sub for step n + 1 runs beside the exponential of step n on
+ * library-owned streams that join `stream` before the call's work ends, with
+ * their own step indices clamped to the call's last step.  The results are
+ * bit-identical to n_steps calls of ltd_propagate_step.  The graphs are kept
+ * and replayed again while the arguments stay the same. */
 ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *args, int n_steps, void *stream);
 
 typedef struct {
