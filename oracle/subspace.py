@@ -64,11 +64,18 @@ def rebuild_v_sub(sys, ik: int, phi: np.ndarray, vr=None, h=None, r_cache=None) 
     return herm(v)
 
 
-def ritz(sys, ik: int, x: np.ndarray, route: str = "fft"):
-    """Rayleigh-Ritz of (H0, S) over span(X): Phi = X W with (X^H H0 X) W =
-    (X^H S X) W diag(eps), W^H (X^H S X) W = I, eps ascending."""
+def ritz_rotation(sys, ik: int, x: np.ndarray, route: str = "fft"):
+    """The rotation W and Ritz values eps of the Rayleigh-Ritz problem of
+    (H0, S) over span(X): (X^H H0 X) W = (X^H S X) W diag(eps),
+    W^H (X^H S X) W = I, eps ascending."""
     sub = project(sys, ik, x, route)
     eps, w = scipy.linalg.eigh(sub["H0"], sub["S"])
+    return w, eps
+
+
+def ritz(sys, ik: int, x: np.ndarray, route: str = "fft"):
+    """Rayleigh-Ritz vectors Phi = X W of (H0, S) over span(X) (``ritz_rotation``)."""
+    w, eps = ritz_rotation(sys, ik, x, route)
     return x @ w, eps
 
 

@@ -16,4 +16,5 @@ from .lapw_inputs import (  # noqa: F401
     pulse_samples,
     hat_weights,
     td_potential,
+    potential_scale,
 )

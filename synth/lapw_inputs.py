@@ -409,3 +409,10 @@ def td_potential(sys: System, eps_v: float = 1e-2, seed: int = 7):
     w /= np.abs(w).max()
     blocks = [_random_hermitian(rng, at.size) for at in sys.atoms]
     return eps_v, w, blocks
+
+
+def potential_scale(n_total: int) -> np.ndarray:
+    """s_n = sin(0.05 n), n = 0..n_total-1: the scale of the perturbation in the
+    potential handed in for step n, V_n = V + eps_v s_n W and h_n = h + eps_v s_n w
+    (the per-step potential series of the benchmark and its parity tests)."""
+    return np.sin(0.05 * np.arange(n_total))

@@ -63,8 +63,9 @@ def test_stationary_states_acquire_phase_only(setup0):
     assert np.abs(out["theta"] - expect).max() < 1e-11
     assert np.abs(out["E"] - out["E"][0]).max() < 1e-12
     assert np.abs(out["J"] - out["J"][0]).max() < 1e-15
-    # delta mu = Omega int J_ind dt (Eq. (4)): bounded by Omega t max |J_ind|
-    assert np.abs(out["dmu"]).max() <= sys.omega * t * np.abs(out["J"] - out["J"][0]).max()
+    # no induced current, so no dipole change (Eq. (4)): delta mu stays at the rounding
+    # level of what the static current would integrate to over the run
+    assert np.abs(out["dmu"]).max() < 1e-12 * sys.omega * t * np.abs(out["J"]).max()
 
 
 def test_norm_and_energy_conservation_static(setup0):
