@@ -52,9 +52,10 @@ enum {
   LTD_ESTATE = -4,      /* call out of order (no workspace / no subspace bound) */
   LTD_EWORKSPACE = -5,  /* bound workspace smaller than ltd_create asked for */
   LTD_EUNSUPPORTED = -6,/* grid length or mode this build does not handle */
+  LTD_ESTEP = -7,       /* time step above the critical time step of the explicit propagator */
   LTD_EHIP = 1,         /* a HIP runtime call failed */
   LTD_ENOTSPD = 2,      /* device: S_sub Cholesky met a pivot <= 0 */
-  LTD_ENONFINITE = 3,   /* device: non-finite current or energy */
+  LTD_ENONFINITE = 3,   /* device: non-finite current, energy or step Hamiltonian */
   LTD_ESPECTRUM = 4     /* device: subspace spectrum left the propagator's interval */
 };
 
@@ -119,7 +120,8 @@ ltd_status ltd_sync_status(ltd_system *sys, void *stream);
  * matching coefficients and per-atom blocks (Eq. (19); App. A, Eqs.
  * (A.4)-(A.6)), the interstitial part by FFT convolution with the step
  * function (Sec. 2.3, second route; App. A, Eq. (A.7)).  a_vec (host) holds
- * A(t) = (A_x, A_y, A_z); only A_z enters (the momentum block is z only).
+ * A(t) = (A_x, A_y, A_z); only A_z can enter (the system carries the z
+ * momentum block only): a nonzero A_x or A_y returns LTD_EUNSUPPORTED.
  * C, HC, SC: N_basis(k) x n, leading dimensions >= N_basis(k); outputs must
  * not overlap C or each other.  n <= max_cols. */
 ltd_status ltd_apply_HS(ltd_system *sys, int k, const double a_vec[3], const void *C, int ldc,
@@ -210,6 +212,15 @@ typedef struct {
                              v_r_t: step n reads v_r_t + n v_stride (0: one potential) */
   long long h_stride;     /* REBUILD: complex elements between the blocks of consecutive steps
                              in h_t: step n reads h_t + n h_stride (0: one set of blocks) */
+  int taylor_order;       /* 0: exponential midpoint rule (Chebyshev series to double precision);
+                             1..8: explicit step, the Taylor series of exp(-i dt (H~ - c0)) truncated
+                             after that many terms (c0 the centre of the bound spectrum), allowed
+                             only for |dt| <= 0.2 / (eps_max - eps_min) of every k-point (Sec. 3.1,
+                             Eq. (20)); a larger step returns LTD_ESTEP */
+  double *nexc_out;       /* optional [n_steps+1]: excited electrons at t_n,
+                             f sum_k w_k sum_j (|theta_j|_S^2 - sum_{i < N_states} |<phi_i|S|psi_j>|^2),
+                             the states' weight outside the first N_states auxiliary functions
+                             (Secs. 3.2-3.3); NULL skips */
 } ltd_step_args;
 
 /* One time step n -> n+1 for every k-point (Sec. 2.2, Eqs. (12)-(13); Sec. 2.3
@@ -235,6 +246,13 @@ ltd_status ltd_propagate_step(ltd_system *sys, const ltd_step_args *args, void *
  * bit-identical to n_steps calls of ltd_propagate_step.  The graphs are kept
  * and replayed again while the arguments stay the same. */
 ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *args, int n_steps, void *stream);
+
+/* Captures and instantiates the graphs that a call of ltd_propagate with the
+ * same arguments and n_steps replays, without running any step: a caller that
+ * times ltd_propagate calls this first so that the capture is outside its timed
+ * region (ltd_propagate itself captures on first use).  Enqueues nothing on
+ * `stream`. */
+ltd_status ltd_propagate_prepare(ltd_system *sys, const ltd_step_args *args, int n_steps, void *stream);
 
 typedef struct {
   const ltd_step_args *fwd; /* the step description (mode, dt, pulse, potential);
@@ -291,6 +309,30 @@ ltd_status ltd_knot_samples(const double *knots, int n_knots, double t_end, doub
  * sum_n dl_da_mid[n] phi_k(t_n + dt/2), phi_k the hat functions. */
 ltd_status ltd_knot_gradient(const double *dl_da_t, const double *dl_da_mid, int n_steps,
                              double dt, int n_knots, double t_end, double *dl_dq, void *stream);
+
+/* Vector potential samples of the paper's excitations along z:
+ * a_t[n] = A(n dt), n = 0..n_steps, a_mid[n] = A((n + 1/2) dt), n < n_steps.
+ * kind / params (host, 4 doubles):
+ *   LTD_PULSE_SIN2: (A0, w, t0, T_p): A0 cos(w t) sin^2[pi (t - t0)/T_p] for
+ *     t0 <= t <= t0 + T_p, 0 outside (the laser of Sec. 3.2);
+ *   LTD_PULSE_KICK: (E0, c, -, -): an impulsive field E0 delta(t - 0+), i.e.
+ *     A = -c E0 for t > 0 and 0 at t = 0 (the kick of Sec. 3.1);
+ *   LTD_PULSE_GAUSS_SIN: (A0, w, t0, width): A0 sin(w t) exp(-((t - t0)/width)^2).
+ * Non-finite parameters, T_p, width or c <= 0 return LTD_EINVAL. */
+enum { LTD_PULSE_GAUSS_SIN = 0, LTD_PULSE_SIN2 = 1, LTD_PULSE_KICK = 2 };
+ltd_status ltd_pulse_samples(int kind, const double *params, double dt, int n_steps, double *a_t, double *a_mid,
+                             void *stream);
+
+/* Dynamical polarizability alpha_zz(w) = (i Omega / w) J(w) / E(w) (Sec. 2,
+ * Eq. (5)) from the current series j[0..n_steps] (J at t_n = n dt, as written by
+ * the propagation; J_ind = J - J(0)) and the potential samples a_t[0..n_steps]:
+ *   J(w) = dt sum_n w_n J_ind(t_n) exp((i w - gamma) t_n), trapezoid weights,
+ *   E(w) = -(1/c) sum_n (A(t_{n+1}) - A(t_n)) exp((i w - gamma) t_{n+1/2}),
+ * the field E = -(1/c) dA/dt of the sampled A; gamma >= 0 damps the tail.
+ * w: [n_w] nonzero frequencies (a.u.); alpha: [n_w] complex128 out.  One
+ * workgroup per frequency, fixed-order sums. */
+ltd_status ltd_polarizability(const double *j, const double *a_t, int n_steps, double dt, double omega_cell,
+                              double c_light, const double *w, int n_w, double gamma, void *alpha, void *stream);
 
 /* Coefficients of the Chebyshev series exp(-i tau x) = sum_k c_k T_k(x) on
  * [-1, 1]: c_k = (2 - delta_k0) (-i)^k J_k(tau) (host; Bessel functions by

@@ -15,6 +15,7 @@ LTD_EALIGN = -3
 LTD_ESTATE = -4
 LTD_EWORKSPACE = -5
 LTD_EUNSUPPORTED = -6
+LTD_ESTEP = -7
 LTD_EHIP = 1
 LTD_ENOTSPD = 2
 LTD_ENONFINITE = 3
@@ -23,15 +24,19 @@ LTD_ESPECTRUM = 4
 LTD_FP64 = 0
 LTD_FP32_RESID = 1
 LTD_BF16X3_RESID = 2
+LTD_PULSE_GAUSS_SIN = 0
+LTD_PULSE_SIN2 = 1
+LTD_PULSE_KICK = 2
 LTD_STEP_REBUILD = 0
 LTD_STEP_AFFINE = 1
 
 EXPORTED = [
     "ltd_create", "ltd_bind_workspace", "ltd_destroy", "ltd_status_string", "ltd_sync_status",
     "ltd_apply_HS", "ltd_project_subspace", "ltd_ritz_basis", "ltd_subspace_info",
-    "ltd_propagate_step", "ltd_propagate", "ltd_propagate_step_adjoint", "ltd_knot_samples",
+    "ltd_propagate_step", "ltd_propagate", "ltd_propagate_prepare", "ltd_propagate_step_adjoint", "ltd_knot_samples",
     "ltd_knot_gradient", "ltd_chebyshev_coefficients", "ltd_profile_steps", "ltd_profile_apply",
     "ltd_rebuild_grid", "ltd_autotune", "ltd_set_tuning", "ltd_state_drift",
+    "ltd_pulse_samples", "ltd_polarizability",
 ]
 LTD_PROFILE_STAGES = 8
 
@@ -78,6 +83,8 @@ class StepArgs(C.Structure):
         ("dmu_out", C.c_void_p),
         ("v_stride", C.c_longlong),
         ("h_stride", C.c_longlong),
+        ("taylor_order", C.c_int),
+        ("nexc_out", C.c_void_p),
     ]
 
 
@@ -123,9 +130,12 @@ def load(path: str = LIB_PATH):
     lib.ltd_state_drift.argtypes = [vp, vp, ip, dp, vp]
     lib.ltd_propagate_step.argtypes = [vp, C.POINTER(StepArgs), vp]
     lib.ltd_propagate.argtypes = [vp, C.POINTER(StepArgs), ip, vp]
+    lib.ltd_propagate_prepare.argtypes = [vp, C.POINTER(StepArgs), ip, vp]
     lib.ltd_propagate_step_adjoint.argtypes = [vp, C.POINTER(AdjointArgs), vp]
     lib.ltd_knot_samples.argtypes = [vp, ip, C.c_double, C.c_double, ip, vp, vp, vp]
     lib.ltd_knot_gradient.argtypes = [vp, vp, ip, C.c_double, ip, C.c_double, vp, vp]
+    lib.ltd_pulse_samples.argtypes = [ip, dp, C.c_double, ip, vp, vp, vp]
+    lib.ltd_polarizability.argtypes = [vp, vp, ip, C.c_double, C.c_double, C.c_double, vp, ip, C.c_double, vp, vp]
     lib.ltd_chebyshev_coefficients.argtypes = [C.c_double, ip, dp, C.POINTER(ip)]
     lib.ltd_profile_steps.argtypes = [vp, C.POINTER(StepArgs), ip, dp, vp]
     lib.ltd_profile_apply.argtypes = [vp, ip, vp, ip, ip, vp, vp, ip, dp, vp]

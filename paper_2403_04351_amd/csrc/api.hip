@@ -56,6 +56,7 @@ struct KHost {
   size_t o_tilde;          // Tt, Vt_ref, Pt (3 n^2), then H0t (n^2)
   size_t o_L, o_Linv, o_LH, o_LinvH, o_vstep, o_work, o_hm, o_dev;
   size_t o_phit, o_yext, o_cache;
+  size_t o_phit32 = 0, o_yext32 = 0;  // FP32 residual: complex64 Phi~_ext (atom-contiguous MT rows) and Y_ext
   // bound subspace
   bool bound = false;
   const double2 *phi = nullptr;
@@ -118,6 +119,14 @@ struct ltd_system {
   std::vector<ZProb> vstep_tab;
   int vstep_tiles = 0;
   size_t o_vstep_tab;
+  // FP32 residual: the block products (complex64 blocks h(t) - h, FP32 matrix
+  // cores) and the projection on complex64 operands; MT rows permuted so that
+  // each atom's channels and local orbitals are contiguous (mtperm: FP64 row of
+  // each FP32 row, relative to N_G)
+  std::vector<ZProb> k7_32, vstep32;
+  int k7_32_tiles = 0, vstep32_tiles = 0;
+  size_t o_k7_32 = 0, o_vstep32 = 0, o_hstep32 = 0, o_mtperm = 0;
+  std::vector<int> mt_row32;  // first FP32 MT row of each atom
   const void *k2_step_h = nullptr;  // blocks the step table points at
   // subspace / step state
   std::vector<SubDev> sd;
@@ -270,15 +279,22 @@ ZProb zp(int m, int n, int k, const double2 *A, int lda, const double2 *B, int l
   return p;
 }
 
-ltd_status gemm(ltd_system *sys, int opa, int opb, std::vector<ZProb> probs, hipStream_t s) {
+// problems held by value, GEMM_MAXP per launch; K split within part_tiles partial
+// tiles (64 x 64 complex) of the buffer part
+ltd_status gemm_buf(int opa, int opb, const std::vector<ZProb> &probs, double2 *part, long long part_tiles,
+                    hipStream_t s) {
   for (size_t i0 = 0; i0 < probs.size(); i0 += GEMM_MAXP) {
     ZBatch b{};
     b.nprob = (int)std::min<size_t>(GEMM_MAXP, probs.size() - i0);
     for (int i = 0; i < b.nprob; ++i) b.p[i] = probs[i0 + i];
-    gemm_plan(b.p, b.nprob, &b.total_tiles, 512, PART_TILES);
-    LTD_HIP(gemm_launch(opa, opb, b, sys->at<double2>(sys->o_partials), s));
+    gemm_plan(b.p, b.nprob, &b.total_tiles, 512, part_tiles);
+    LTD_HIP(gemm_launch(opa, opb, b, part, s));
   }
   return LTD_OK;
+}
+
+ltd_status gemm(ltd_system *sys, int opa, int opb, std::vector<ZProb> probs, hipStream_t s) {
+  return gemm_buf(opa, opb, probs, sys->at<double2>(sys->o_partials), PART_TILES, s);
 }
 
 ltd_status gemm1(ltd_system *sys, int opa, int opb, const ZProb &p, hipStream_t s) {
@@ -417,8 +433,33 @@ const void *k2_source(const ltd_system *sys, const ltd_step_args *a) {
 // ---------------------------------------------------------------------------
 // Apply stages (profiling tags): 0 inverse planes, 1 z lines, 2 forward planes,
 // 3 A C (K1), 4 block-diagonal muffin-tin products (K2), 5 A^H Y (K3) and LO rows.
+// Scratch of one apply pass: FFT slabs (4 input and 5 output fields), the
+// muffin-tin vectors W and products Y (blocks ystride apart), the effective
+// blocks h + (A/c) p_z + (A^2/2c^2) o, and the GEMMs' split-K partials.
+// k2_tables: the block products come from the tables uploaded at bind, which
+// point at the workspace's W and Y; otherwise they are passed by value.
+struct ApplyBufs {
+  double2 *slab_in, *slab_out, *W, *Y, *heff, *part;
+  long long ystride, part_tiles;
+  bool k2_tables;
+};
+
+ApplyBufs workspace_bufs(const ltd_system *sys) {
+  ApplyBufs b{};
+  b.slab_in = sys->at<double2>(sys->o_slab_in);
+  b.slab_out = sys->at<double2>(sys->o_slab_out);
+  b.W = sys->at<double2>(sys->o_W);
+  b.Y = sys->at<double2>(sys->o_Y);
+  b.heff = sys->at<double2>(sys->o_heff);
+  b.part = sys->at<double2>(sys->o_partials);
+  b.ystride = (long long)sys->n_loc * sys->chunk;
+  b.part_tiles = PART_TILES;
+  b.k2_tables = true;
+  return b;
+}
+
 ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const double2 *C, int ldc, int cols,
-                       double2 *const out[4], const int ldo[4], hipStream_t s, Prof *pf = nullptr) {
+                       double2 *const out[4], const int ldo[4], hipStream_t s, Prof *pf, const ApplyBufs &bf) {
   if (cols <= 0) return LTD_OK;
   const KHost &kh = sys->kh[k];
   const Grid g = grid_of(sys);
@@ -428,14 +469,14 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   ka.sph[0] = sphere_of(sys, k);
   ka.in[0].c = C;
   ka.in[0].ldc = ldc;
-  ka.slab_out[0] = sys->at<double2>(sys->o_slab_in);
+  ka.slab_out[0] = bf.slab_in;
   LTD_HIP(fft_inverse_planes(g, ka, 1, cols, 4, s));
   LTD_MARK(pf, 0);
-  ka.slab_in[0] = sys->at<double2>(sys->o_slab_in);
-  ka.slab_out[0] = sys->at<double2>(sys->o_slab_out);
+  ka.slab_in[0] = bf.slab_in;
+  ka.slab_out[0] = bf.slab_out;
   LTD_HIP(fft_lines(g, ka, 1, cols, FFT_MODE_HS, sys->at<double>(sys->o_thv), s));
   LTD_MARK(pf, 1);
-  ka.slab_in[0] = sys->at<double2>(sys->o_slab_out);
+  ka.slab_in[0] = bf.slab_out;
   FwdOut fo{};
   fo.o0 = out[0];
   fo.o1 = out[1];
@@ -451,42 +492,50 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   LTD_HIP(fft_forward_planes(g, ka, 1, cols, mode, al, be, s));
   LTD_MARK(pf, 2);
   // muffin-tin chain: W = [A C_G; C_LO]
-  double2 *W = sys->at<double2>(sys->o_W);
-  double2 *Y = sys->at<double2>(sys->o_Y);
-  const int nl = sys->n_loc, chunk = sys->chunk;
+  double2 *W = bf.W;
+  double2 *Y = bf.Y;
+  const int nl = sys->n_loc;
+  const long long yst = bf.ystride;
   const double2 *Ak = sys->amat + kh.amat_off;
-  LTD_TRY(gemm1(sys, OP_N, OP_N, zp(sys->n_a, cols, kh.n_g, Ak, sys->n_a, C, ldc, W, nl), s));
+  LTD_TRY(gemm_buf(OP_N, OP_N, {zp(sys->n_a, cols, kh.n_g, Ak, sys->n_a, C, ldc, W, nl)}, bf.part, bf.part_tiles, s));
   if (sys->n_lo_tot > 0) LTD_HIP(launch_copy_rows(W + sys->n_a, nl, C + kh.n_g, ldc, sys->n_lo_tot, cols, false, s));
   LTD_MARK(pf, 3);
   const double2 one = make_double2(1.0, 0.0);
   std::vector<ZProb> k3;
   if (mode == FFT_MODE_HS) {
-    LTD_HIP(launch_heff(sys->at<double2>(sys->o_heff), sys->h, sys->pz, sys->o, al, be, sys->blk_elems, s));
-    LTD_TRY(run_k2(sys, sys->k2_hs, cols, s));
+    LTD_HIP(launch_heff(bf.heff, sys->h, sys->pz, sys->o, al, be, sys->blk_elems, s));
+    if (bf.k2_tables) {
+      LTD_TRY(run_k2(sys, sys->k2_hs, cols, s));
+    } else {
+      std::vector<ZProb> p1, p2;
+      build_k2(sys, {bf.heff, sys->o}, W, nl, {Y, Y + yst}, nl, cols, p1, p2);
+      LTD_TRY(gemm_buf(OP_N, OP_N, p1, bf.part, bf.part_tiles, s));
+    }
     LTD_MARK(pf, 4);
-    // Y layout: [Y_heff | Y_o], each n_loc x chunk
+    // Y layout: [Y_heff | Y_o], each n_loc x (ystride / n_loc)
     for (int x = 0; x < 2; ++x) {
-      double2 *Yx = Y + (long long)x * nl * chunk;
+      double2 *Yx = Y + (long long)x * yst;
       k3.push_back(zp(kh.n_g, cols, sys->n_a, Ak, sys->n_a, Yx, nl, out[x], ldo[x], one, one));
     }
-    LTD_TRY(gemm(sys, OP_C, OP_N, k3, s));
+    LTD_TRY(gemm_buf(OP_C, OP_N, k3, bf.part, bf.part_tiles, s));
     for (int x = 0; x < 2; ++x)
       if (sys->n_lo_tot > 0)
-        LTD_HIP(launch_copy_rows(out[x] + kh.n_g, ldo[x], Y + (long long)x * nl * chunk + sys->n_a, nl,
+        LTD_HIP(launch_copy_rows(out[x] + kh.n_g, ldo[x], Y + (long long)x * yst + sys->n_a, nl,
                                  sys->n_lo_tot, cols, false, s));
   } else {
+    if (!bf.k2_tables) return LTD_EUNSUPPORTED;  // the four-operator apply runs on the workspace only
     LTD_TRY(run_k2(sys, sys->k2_tvps, cols, s));
     LTD_MARK(pf, 4);
     // Y layout: [Y_h | Y_p | Y_o] -> V, P, S
     for (int x = 0; x < 3; ++x) {
-      double2 *Yx = Y + (long long)x * nl * chunk;
+      double2 *Yx = Y + (long long)x * yst;
       k3.push_back(zp(kh.n_g, cols, sys->n_a, Ak, sys->n_a, Yx, nl, out[x + 1], ldo[x + 1], one, one));
     }
     LTD_TRY(gemm(sys, OP_C, OP_N, k3, s));
     if (sys->n_lo_tot > 0) {
       LTD_HIP(launch_copy_rows(out[0] + kh.n_g, ldo[0], nullptr, 0, sys->n_lo_tot, cols, true, s));
       for (int x = 0; x < 3; ++x)
-        LTD_HIP(launch_copy_rows(out[x + 1] + kh.n_g, ldo[x + 1], Y + (long long)x * nl * chunk + sys->n_a, nl,
+        LTD_HIP(launch_copy_rows(out[x + 1] + kh.n_g, ldo[x + 1], Y + (long long)x * yst + sys->n_a, nl,
                                  sys->n_lo_tot, cols, false, s));
     }
   }
@@ -500,7 +549,8 @@ ltd_status apply_cols(ltd_system *sys, int k, int mode, double a_z, const double
     const int cols = std::min(sys->chunk, n - j0);
     double2 *o[4];
     for (int i = 0; i < 4; ++i) o[i] = out[i] ? out[i] + (long long)j0 * ldo[i] : nullptr;
-    LTD_TRY(apply_chunk(sys, k, mode, a_z, C + (long long)j0 * ldc, ldc, cols, o, ldo, s));
+    LTD_TRY(apply_chunk(sys, k, mode, a_z, C + (long long)j0 * ldc, ldc, cols, o, ldo, s, nullptr,
+                        workspace_bufs(sys)));
   }
   return LTD_OK;
 }
@@ -604,6 +654,33 @@ ltd_status build_step_tables(ltd_system *sys) {
   sys->vstep_tab = pv;
   sys->vstep_tiles = tt;
   LTD_HIP(hipMemcpy(sys->ws + sys->o_vstep_tab, pv.data(), pv.size() * sizeof(ZProb), hipMemcpyHostToDevice));
+  if (resid32(sys)) {  // the same two products on complex64 operands (ZProb pointers hold float2 data)
+    std::vector<ZProb> p7, p6;
+    const auto d2 = [](const void *p) { return reinterpret_cast<const double2 *>(p); };
+    const float2 *dh = sys->at<float2>(sys->o_hstep32);
+    for (int k = 0; k < sys->n_k; ++k) {
+      KHost &kh = sys->kh[k];
+      if (!kh.bound) continue;
+      float2 *ph = sys->at<float2>(kh.o_phit32), *ye = sys->at<float2>(kh.o_yext32);
+      for (int a = 0; a < sys->n_atoms; ++a) {
+        const int sa = sys->n_mt[a] + sys->n_lo[a], r = kh.n_g + sys->mt_row32[a];
+        p7.push_back(zp(sa, n, sa, d2(dh + sys->s_off[a]), sa, d2(ph + r), kh.k_ext,
+                        reinterpret_cast<double2 *>(ye + r), kh.k_ext));
+      }
+      p6.push_back(zp(n, n, kh.k_ext, d2(ph), kh.k_ext, d2(ye), kh.k_ext, sys->at<double2>(kh.o_vstep), n));
+    }
+    int t7 = 0, t6 = 0;
+    gemm_plan(p7.data(), (int)p7.size(), &t7, 0, PART_TILES);  // unsplit: written in complex64 directly
+    gemm_plan(p6.data(), (int)p6.size(), &t6, sys->vproj_target, PART_TILES);
+    if (p7.size() * sizeof(ZProb) > (size_t)4 * sys->n_atoms * sys->n_k * sizeof(ZProb) + 1024) return LTD_EUNSUPPORTED;
+    sys->k7_32 = p7;
+    sys->k7_32_tiles = t7;
+    sys->vstep32 = p6;
+    sys->vstep32_tiles = t6;
+    if (!p7.empty())
+      LTD_HIP(hipMemcpy(sys->ws + sys->o_k7_32, p7.data(), p7.size() * sizeof(ZProb), hipMemcpyHostToDevice));
+    LTD_HIP(hipMemcpy(sys->ws + sys->o_vstep32, p6.data(), p6.size() * sizeof(ZProb), hipMemcpyHostToDevice));
+  }
   return LTD_OK;
 }
 
@@ -627,6 +704,8 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
   c.dt = a->dt;
   c.theta = reinterpret_cast<double2 *>(a->theta);
   c.part = sys->at<double>(sys->o_part);
+  c.taylor = a->taylor_order;
+  c.nexc_out = a->nexc_out;
   c.status = sys->at<int>(sys->o_status);
   c.done = sys->at<int>(sys->o_status) + 8;  // zeroed at bind, reset by the step kernel's last block
   c.j_out = a->j_out;
@@ -642,10 +721,36 @@ StepCtx step_ctx(ltd_system *sys, const ltd_step_args *a) {
 // parts: 1 the product (partials), 2 their reduction into V~, 3 both; the
 // reduction only reads the partials, so repeating it gives the same V~.
 ltd_status project_v(ltd_system *sys, hipStream_t s, int parts = 3) {
+  if (resid32(sys)) {  // complex64 operands, FP32 matrix cores, FP64 sums across K tiles
+    LTD_HIP(cgemm32_launch_table(OP_C, sys->at<ZProb>(sys->o_vstep32), sys->vstep32.data(), (int)sys->vstep32.size(),
+                                 sys->vstep32_tiles, sys->at<double2>(sys->o_vpartials), s, parts, false));
+    return LTD_OK;
+  }
   LTD_HIP(gemm_launch_table(OP_C, OP_N, sys->at<ZProb>(sys->o_vstep_tab), sys->vstep_tab.data(),
                             (int)sys->vstep_tab.size(), sys->vstep_tiles, sys->at<double2>(sys->o_vpartials), 0, s,
                             parts));
   return LTD_OK;
+}
+
+// The step's muffin-tin blocks (the difference h(t) - h for the FP32 residual,
+// in complex64) into the copy buffer the block products read, then the products.
+// step: the device index of the step in a series (NULL: host_off or one set).
+ltd_status step_blocks(ltd_system *sys, const ltd_step_args *a, const int *step, long long host_off, int n,
+                       hipStream_t s) {
+  if (resid32(sys)) {
+    const double2 *src = a->h_t ? reinterpret_cast<const double2 *>(a->h_t) : sys->h;
+    const bool series = a->h_t && a->h_stride;
+    LTD_HIP(launch_copy_step32(sys->at<float2>(sys->o_hstep32), src, sys->blk_elems, series ? step : nullptr,
+                               series ? a->h_stride : 0, series ? host_off : 0, sys->h, s));
+    if (!sys->k7_32.empty())
+      LTD_HIP(cgemm32_launch_table(OP_N, sys->at<ZProb>(sys->o_k7_32), sys->k7_32.data(), (int)sys->k7_32.size(),
+                                   sys->k7_32_tiles, sys->at<double2>(sys->o_partials), s, 3, true));
+    return LTD_OK;
+  }
+  if (a->h_t && a->h_stride)
+    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), reinterpret_cast<const double2 *>(a->h_t),
+                             sys->blk_elems, step, a->h_stride, host_off, nullptr, s));
+  return run_k2(sys, sys->k2_step, n, s);
 }
 
 // host_step >= 0: the step index is known on the host (adjoint); otherwise the
@@ -669,14 +774,10 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
     sb = sys->side;
   }
   const bool r32 = resid32(sys);
-  if (a->h_t && (a->h_stride || r32))
-    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), reinterpret_cast<const double2 *>(a->h_t),
-                             sys->blk_elems, host_step >= 0 || !a->h_stride ? nullptr : a->step, a->h_stride,
-                             host_step >= 0 ? (long long)host_step * a->h_stride : 0, r32 ? sys->h : nullptr, sb));
-  else if (r32)  // the reference blocks: a zero difference (h - h)
-    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), sys->h, sys->blk_elems, nullptr, 0, 0, sys->h, sb));
+  const int *hstep = host_step >= 0 ? nullptr : a->step;
+  const long long hoff = host_step >= 0 ? (long long)host_step * a->h_stride : 0;
   if (fork) {
-    LTD_TRY(run_k2(sys, sys->k2_step, n, sb));
+    LTD_TRY(step_blocks(sys, a, hstep, hoff, n, sb));
     LTD_HIP(hipEventRecord(sys->ev_join, sb));
   }
   const void *thv = r32 ? static_cast<const void *>(sys->at<float>(sys->o_zero32))
@@ -702,6 +803,7 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
       ka.slab_in[i] = sys->at<double2>(kh.o_cache);
       ka.slab_out[i] = reinterpret_cast<double2 *>(sys->ws + sys->o_stepslab + (size_t)i * slab * rb_elem(sys));
       ka.out[i].o0 = sys->at<double2>(kh.o_yext);
+      ka.out[i].o0f = r32 ? sys->at<float2>(kh.o_yext32) : nullptr;
       ka.out[i].ld0 = kh.k_ext;
     }
     // x/z transforms and the Theta V product per y plane, then y transforms per kz plane;
@@ -715,7 +817,7 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
     LTD_MARK(pf, 2);
   }
   if (fork) LTD_HIP(hipStreamWaitEvent(s, sys->ev_join, 0));
-  else LTD_TRY(run_k2(sys, sys->k2_step, n, s));
+  else LTD_TRY(step_blocks(sys, a, hstep, hoff, n, s));
   LTD_MARK(pf, 3);
   LTD_TRY(project_v(sys, s));
   LTD_MARK(pf, 4);
@@ -748,14 +850,7 @@ ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s
   LTD_HIP(hipEventRecord(sys->ev_fork, s));
   LTD_HIP(hipStreamWaitEvent(sys->side, sys->ev_fork, 0));
   LTD_HIP(launch_lookahead(rk, sys->side));
-  if (a->h_t && (a->h_stride || r32))
-    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), reinterpret_cast<const double2 *>(a->h_t),
-                             sys->blk_elems, a->h_stride ? rk : nullptr, a->h_stride, 0, r32 ? sys->h : nullptr,
-                             sys->side));
-  else if (r32)
-    LTD_HIP(launch_copy_step(sys->at<double2>(sys->o_hstep), sys->h, sys->blk_elems, nullptr, 0, 0, sys->h,
-                             sys->side));
-  LTD_TRY(run_k2(sys, sys->k2_step, n, sys->side));
+  LTD_TRY(step_blocks(sys, a, rk, 0, n, sys->side));
   LTD_HIP(hipEventRecord(sys->ev_join, sys->side));
   const void *thv = r32 ? static_cast<const void *>(sys->at<float>(sys->o_zero32))
                         : static_cast<const void *>(sys->at<double>(sys->o_thv_rb));
@@ -773,6 +868,7 @@ ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s
       ka.slab_in[i] = sys->at<double2>(kh.o_cache);
       ka.slab_out[i] = reinterpret_cast<double2 *>(sys->ws + sys->o_stepslab + (size_t)i * slab * rb_elem(sys));
       ka.out[i].o0 = sys->at<double2>(kh.o_yext);
+      ka.out[i].o0f = r32 ? sys->at<float2>(kh.o_yext32) : nullptr;
       ka.out[i].ld0 = kh.k_ext;
     }
     LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0, r32, sys->rb_variant));
@@ -830,6 +926,10 @@ ltd_status check_step_args(ltd_system *sys, const ltd_step_args *a) {
   if (a->v_stride < 0 || a->h_stride < 0) return LTD_EINVAL;
   if (a->v_stride && a->v_stride < sys->ngrid) return LTD_ESHAPE;
   if (a->h_stride && a->h_stride < sys->blk_elems) return LTD_ESHAPE;
+  if (a->taylor_order < 0 || a->taylor_order > TAYLOR_MAX) return LTD_EINVAL;
+  if (a->taylor_order > 0)  // the explicit step diverges beyond the critical time step (Eq. (20))
+    for (int k = 0; k < sys->n_k; ++k)
+      if (std::fabs(a->dt) > 0.2 / (sys->kh[k].lam_max - sys->kh[k].lam_min)) return LTD_ESTEP;
   return LTD_OK;
 }
 
@@ -884,6 +984,56 @@ ltd_status step_once(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
   return LTD_OK;
 }
 
+// k steps in one capture (a replay boundary per k steps); the graph is kept
+ltd_status capture_steps(ltd_system *sys, const ltd_step_args *a, int k, bool pipe, hipGraph_t *g,
+                         hipGraphExec_t *x) {
+  if (*x) return LTD_OK;
+  if (!sys->cap_stream) LTD_HIP(hipStreamCreateWithFlags(&sys->cap_stream, hipStreamNonBlocking));
+  LTD_HIP(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeThreadLocal));
+  ltd_status st = LTD_OK;
+  for (int i = 0; i < k && st == LTD_OK; ++i)
+    st = pipe ? pipelined_step(sys, a, sys->cap_stream, i == 0, i == k - 1) : step_once(sys, a, sys->cap_stream);
+  hipGraph_t gr = nullptr;
+  const hipError_t ec = hipStreamEndCapture(sys->cap_stream, &gr);
+  if (st != LTD_OK) {
+    if (gr) (void)hipGraphDestroy(gr);
+    return st;
+  }
+  if (ec != hipSuccess) return LTD_EHIP;
+  *g = gr;
+  LTD_HIP(hipGraphInstantiate(x, gr, nullptr, nullptr, 0));
+  return LTD_OK;
+}
+
+// The graphs of every tier a call of n_steps with these arguments replays
+// (captured now if they are not kept from an earlier call with the same ones).
+ltd_status ensure_graphs(ltd_system *sys, const ltd_step_args *a, int n_steps, bool pipe) {
+  const bool same = sys->gvalid && sys->gpipe == pipe && std::memcmp(&sys->gargs, a, sizeof(ltd_step_args)) == 0;
+  if (!same) {
+    drop_graphs(sys);
+    sys->gargs = *a;
+    sys->gpipe = pipe;
+    sys->gvalid = true;
+  }
+  int left = n_steps;
+  for (int t = 0; t < GRAPH_TIERS; ++t) {
+    const int reps = left / GRAPH_STEPS[t];
+    if (reps == 0) continue;
+    LTD_TRY(capture_steps(sys, a, GRAPH_STEPS[t], pipe, &sys->graph[t], &sys->gexec[t]));
+    left -= reps * GRAPH_STEPS[t];
+  }
+  return LTD_OK;
+}
+
+// the step tables a rebuild reads must be current before a capture
+ltd_status refresh_step_tables(ltd_system *sys, const ltd_step_args *a) {
+  if (a->mode == LTD_STEP_REBUILD && k2_source(sys, a) != sys->k2_step_h) {
+    sys->k2_step_h = k2_source(sys, a);
+    LTD_TRY(build_step_tables(sys));
+  }
+  return LTD_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -904,6 +1054,7 @@ const char *ltd_status_string(ltd_status st) {
     case LTD_ENOTSPD: return "subspace overlap not positive definite";
     case LTD_ENONFINITE: return "non-finite current or energy";
     case LTD_ESPECTRUM: return "subspace spectrum left the propagator interval";
+    case LTD_ESTEP: return "time step above the critical time step of the explicit propagator";
     default: return "unknown status";
   }
 }
@@ -1081,7 +1232,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   // [0..1] status, [8] step-kernel block counter, [12..13] and [14..15] step index
   // and last step of the pipelined rebuild (muffin-tin branch, potential synthesis)
   sys->o_status = ar.take(64);
-  sys->o_part = ar.take((size_t)4 * sys->n_k * sys->n_states * sizeof(double));
+  sys->o_part = ar.take((size_t)PART_STRIDE * sys->n_k * sys->n_states * sizeof(double));
   sys->o_partials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
   sys->o_vpartials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
   const long long slab_f = (long long)g.nbz * g.n1 * g.n2 * sys->chunk;
@@ -1125,6 +1276,17 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_k2_st1 = ar.take(k2cap_step);
   sys->o_k2_st2 = ar.take(k2cap_step);
   sys->o_vstep_tab = ar.take(sys->n_k * sizeof(ZProb) + 256);
+  if (resid32(sys)) {
+    sys->o_k7_32 = ar.take(k2cap_step);
+    sys->o_vstep32 = ar.take(sys->n_k * sizeof(ZProb) + 256);
+    sys->o_hstep32 = ar.take((size_t)std::max<long long>(1, sys->blk_elems) * sizeof(float2));
+    sys->o_mtperm = ar.take((size_t)std::max(1, sys->n_loc) * sizeof(int));
+    int r = 0;
+    for (int a = 0; a < sys->n_atoms; ++a) {
+      sys->mt_row32.push_back(r);
+      r += sys->n_mt[a] + sys->n_lo[a];
+    }
+  }
   for (int k = 0; k < sys->n_k; ++k) {
     KHost &kh = sys->kh[k];
     kh.o_gk = ar.take((size_t)3 * kh.n_g * sizeof(double));
@@ -1144,6 +1306,10 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     kh.o_phit = ar.take((size_t)kh.k_ext * n * sizeof(double2));
     kh.o_yext = ar.take((size_t)kh.k_ext * n * sizeof(double2));
     kh.o_cache = ar.take(fft_rb_slab_values(sys->rgrid) * n * rb_elem(sys));
+    if (resid32(sys)) {
+      kh.o_phit32 = ar.take((size_t)kh.k_ext * n * sizeof(float2));
+      kh.o_yext32 = ar.take((size_t)kh.k_ext * n * sizeof(float2));
+    }
   }
   sys->ws_need = ar.off;
   sys->sd.assign(sys->n_k, SubDev{});
@@ -1222,6 +1388,14 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
   }
   std::vector<int> zero(16, 0);
   LTD_HIP(hipMemcpy(sys->ws + sys->o_status, zero.data(), 16 * sizeof(int), hipMemcpyHostToDevice));
+  if (resid32(sys) && sys->n_loc > 0) {
+    std::vector<int> perm;
+    for (int a = 0; a < sys->n_atoms; ++a) {
+      for (int i = 0; i < sys->n_mt[a]; ++i) perm.push_back(sys->a_off[a] + i);
+      for (int q = 0; q < sys->n_lo[a]; ++q) perm.push_back(sys->n_a + sys->l_off[a] + q);
+    }
+    LTD_HIP(hipMemcpy(sys->ws + sys->o_mtperm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
   LTD_HIP(launch_thv(sys->at<double>(sys->o_thv), sys->theta, sys->v_r, sys->ngrid, s));
   LTD_TRY(rebuild_potential(sys, sys->v_r, nullptr, 0, sys->at<double>(sys->o_thv_rb), false, s));
   if (resid32(sys)) LTD_HIP(hipMemsetAsync(sys->ws + sys->o_zero32, 0, sys->ngrid * sizeof(float), s));
@@ -1285,6 +1459,8 @@ ltd_status ltd_apply_HS(ltd_system *sys, int k, const double a_vec[3], const voi
   if (n == 0) return LTD_OK;
   if (!C || !HC || !SC) return LTD_EINVAL;
   if (!std::isfinite(a_vec[0]) || !std::isfinite(a_vec[1]) || !std::isfinite(a_vec[2])) return LTD_EINVAL;
+  // only the z momentum block is part of the system: a transverse A cannot be applied
+  if (a_vec[0] != 0.0 || a_vec[1] != 0.0) return LTD_EUNSUPPORTED;
   const int nb = sys->kh[k].n_basis;
   if (ldc < nb || ldhc < nb || ldsc < nb) return LTD_ESHAPE;
   if (!aligned16(C) || !aligned16(HC) || !aligned16(SC)) return LTD_EALIGN;
@@ -1338,6 +1514,9 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
   // the G rows of Phi~_ext in the order the rebuild writes Y (the sphere tables'
   // plane order, so that its writes are contiguous); the projection sums over G
   LTD_HIP(launch_gather_rows(pe, kh.k_ext, pt, sys->nb_max, sys->at<int>(kh.o_ptsg), kh.n_g, n, s));
+  if (resid32(sys))  // complex64 Phi~_ext of the FP32 residual projection (atom-contiguous MT rows)
+    LTD_HIP(launch_rows_to_c64(sys->at<float2>(kh.o_phit32), kh.k_ext, pe, kh.k_ext, kh.n_g,
+                               sys->at<int>(sys->o_mtperm), sys->n_loc, n, s));
   // outputs in the Phi basis
   if (h0_sub) LTD_HIP(launch_axpby(reinterpret_cast<double2 *>(h0_sub), subs, subs + n2, 1.0, 1.0, n2, s));
   if (s_sub)
@@ -1589,11 +1768,7 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
   if (n_steps == 0) return LTD_OK;
   LTD_TRY(prepare_dt(sys, a->dt));
   hipStream_t s = S(stream);
-  // tables that a rebuild step would refresh on the host must be current before capture
-  if (a->mode == LTD_STEP_REBUILD && k2_source(sys, a) != sys->k2_step_h) {
-    sys->k2_step_h = k2_source(sys, a);
-    LTD_TRY(build_step_tables(sys));
-  }
+  LTD_TRY(refresh_step_tables(sys, a));
   const bool pipe = a->mode == LTD_STEP_REBUILD && sys->side2 != nullptr;
   if (pipe) {  // V~ of the first step, Theta V of the second, the step-index bounds of this call
     int *rs = sys->at<int>(sys->o_status) + 12;
@@ -1607,37 +1782,11 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
                                 sys->at<double>(sys->o_thv_step), resid32(sys), s));
     }
   }
-  const bool same = sys->gvalid && sys->gpipe == pipe && std::memcmp(&sys->gargs, a, sizeof(ltd_step_args)) == 0;
-  if (!same) {
-    drop_graphs(sys);
-    sys->gargs = *a;
-    sys->gpipe = pipe;
-    sys->gvalid = true;
-  }
-  // k steps in one capture (a replay boundary per k steps)
-  const auto ensure = [&](int k, hipGraph_t *g, hipGraphExec_t *x) -> ltd_status {
-    if (*x) return LTD_OK;
-    if (!sys->cap_stream) LTD_HIP(hipStreamCreateWithFlags(&sys->cap_stream, hipStreamNonBlocking));
-    LTD_HIP(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeThreadLocal));
-    ltd_status st = LTD_OK;
-    for (int i = 0; i < k && st == LTD_OK; ++i)
-      st = pipe ? pipelined_step(sys, a, sys->cap_stream, i == 0, i == k - 1) : step_once(sys, a, sys->cap_stream);
-    hipGraph_t gr = nullptr;
-    const hipError_t ec = hipStreamEndCapture(sys->cap_stream, &gr);
-    if (st != LTD_OK) {
-      if (gr) (void)hipGraphDestroy(gr);
-      return st;
-    }
-    if (ec != hipSuccess) return LTD_EHIP;
-    *g = gr;
-    LTD_HIP(hipGraphInstantiate(x, gr, nullptr, nullptr, 0));
-    return LTD_OK;
-  };
+  LTD_TRY(ensure_graphs(sys, a, n_steps, pipe));
   int left = n_steps;
   for (int t = 0; t < GRAPH_TIERS; ++t) {
     const int reps = left / GRAPH_STEPS[t];
     if (reps == 0) continue;
-    LTD_TRY(ensure(GRAPH_STEPS[t], &sys->graph[t], &sys->gexec[t]));
     for (int i = 0; i < reps; ++i) LTD_HIP(hipGraphLaunch(sys->gexec[t], s));
     left -= reps * GRAPH_STEPS[t];
   }
@@ -1645,10 +1794,21 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
   return LTD_OK;
 }
 
+ltd_status ltd_propagate_prepare(ltd_system *sys, const ltd_step_args *a, int n_steps, void *stream) {
+  (void)stream;
+  LTD_TRY(check_step_args(sys, a));
+  if (n_steps < 0) return LTD_ESHAPE;
+  if (n_steps == 0) return LTD_OK;
+  LTD_TRY(prepare_dt(sys, a->dt));
+  LTD_TRY(refresh_step_tables(sys, a));
+  return ensure_graphs(sys, a, n_steps, a->mode == LTD_STEP_REBUILD && sys->side2 != nullptr);
+}
+
 ltd_status ltd_propagate_step_adjoint(ltd_system *sys, const ltd_adjoint_args *aa, void *stream) {
   if (!aa) return LTD_EINVAL;
   const ltd_step_args *a = aa->fwd;
   LTD_TRY(check_step_args(sys, a));
+  if (a->taylor_order != 0) return LTD_EUNSUPPORTED;  // the adjoint differentiates the exponential
   if (!aa->mu_out || (!aa->terminal && (!aa->mu_next || !aa->dl_da_mid)) || !aa->dl_da_t) return LTD_EINVAL;
   if (aa->n_steps < 1 || aa->n < 0 || aa->n > aa->n_steps || (!aa->terminal && aa->n == aa->n_steps))
     return LTD_ESHAPE;
@@ -1705,7 +1865,8 @@ ltd_status ltd_profile_apply(ltd_system *sys, int k, const void *C, int ldc, int
     double2 *o[4] = {outs[0] + (long long)j0 * ldo, outs[1] + (long long)j0 * ldo, nullptr, nullptr};
     Prof pf;
     LTD_TRY(pf.begin(s));
-    LTD_TRY(apply_chunk(sys, k, FFT_MODE_HS, 0.0, c + (long long)j0 * ldc, ldc, cols, o, lo, s, &pf));
+    LTD_TRY(apply_chunk(sys, k, FFT_MODE_HS, 0.0, c + (long long)j0 * ldc, ldc, cols, o, lo, s, &pf,
+                        workspace_bufs(sys)));
     LTD_TRY(pf.collect(stage_ms, LTD_PROFILE_STAGES));
   }
   return LTD_OK;

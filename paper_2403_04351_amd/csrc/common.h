@@ -99,6 +99,14 @@ hipError_t gemm_launch(int opa, int opb, const ZBatch &b, double2 *partials, hip
 hipError_t gemm_launch_table(int opa, int opb, const ZProb *dev_table, const ZProb *host, int nprob,
                              int total_tiles, double2 *partials, int n_limit, hipStream_t s, int parts = 3);
 
+// The same GEMMs on complex64 operands (ZProb pointers holding float2 data) with
+// FP32 matrix cores, FP32 sums per K tile of 16 and FP64 sums across tiles and
+// splits, op(B) = B.  Planned by gemm_plan like the FP64 ones.  C in complex128,
+// or (out32, unsplit problems only) in complex64.
+hipError_t cgemm32_launch(int opa, const ZBatch &b, double2 *partials, hipStream_t s, bool out32 = false);
+hipError_t cgemm32_launch_table(int opa, const ZProb *dev_table, const ZProb *host, int nprob, int total_tiles,
+                                double2 *partials, hipStream_t s, int parts = 3, bool out32 = false);
+
 // ----------------------------------------------------------------------------
 // Interstitial FFT pipeline.
 // ----------------------------------------------------------------------------
@@ -156,6 +164,7 @@ enum FftMode { FFT_MODE_V = 0, FFT_MODE_HS = 1, FFT_MODE_TVPS = 2 };
 // Output descriptor of the forward plane pass (one per k).
 struct FwdOut {
   double2 *o0;  // MODE_V: Y;  MODE_HS: HC;  MODE_TVPS: T
+  float2 *o0f;  // rebuild read-out: when set, Y goes here in complex64 instead of to o0
   double2 *o1;  // MODE_HS: SC;  MODE_TVPS: V
   double2 *o2;  // MODE_TVPS: P
   double2 *o3;  // MODE_TVPS: S

@@ -187,10 +187,44 @@ __device__ inline void dft9(T *v) {
   }
 }
 
+// Length 12 as 3 x 4: input q = 4 q1 + q2, output p = p1 + 3 p2:
+//   y[p1 + 3 p2] = sum_q2 w4^(p2 q2) w12^(p1 q2) sum_q1 w3^(p1 q1) v[4 q1 + q2].
+template <int DIR, class T>
+__device__ inline void dft12(T *v) {
+  using R = typename CT<T>::R;
+  T a[4][3];
+#pragma unroll
+  for (int q2 = 0; q2 < 4; ++q2) {
+    T t[3] = {v[q2], v[4 + q2], v[8 + q2]};
+    dft3<DIR>(t);
+    a[q2][0] = t[0];
+    a[q2][1] = t[1];
+    a[q2][2] = t[2];
+  }
+  // w12^e, e = p1 q2: 1 = (sqrt3/2, 1/2), 2 = (1/2, sqrt3/2), 3 = i, 4 = (-1/2, sqrt3/2), 6 = -1
+  // (imaginary parts times DIR)
+  a[1][1] = cmul(a[1][1], CT<T>::mk((R)SQ3_2, (R)(DIR * 0.5)));
+  a[2][1] = cmul(a[2][1], CT<T>::mk((R)0.5, (R)(DIR * SQ3_2)));
+  a[3][1] = mul_i<DIR>(a[3][1]);
+  a[1][2] = cmul(a[1][2], CT<T>::mk((R)0.5, (R)(DIR * SQ3_2)));
+  a[2][2] = cmul(a[2][2], CT<T>::mk((R)-0.5, (R)(DIR * SQ3_2)));
+  a[3][2] = CT<T>::mk(-a[3][2].x, -a[3][2].y);
+#pragma unroll
+  for (int p1 = 0; p1 < 3; ++p1) {
+    T t0 = a[0][p1], t1 = a[1][p1], t2 = a[2][p1], t3 = a[3][p1];
+    dft4<DIR>(t0, t1, t2, t3);
+    v[p1] = t0;
+    v[p1 + 3] = t1;
+    v[p1 + 6] = t2;
+    v[p1 + 9] = t3;
+  }
+}
+
 // In-register DFT of the lengths the two-factor transforms use.
 template <int R, int DIR, class T>
 __device__ __forceinline__ void dft_reg(T *v) {
   if constexpr (R == 9) dft9<DIR>(v);
+  else if constexpr (R == 12) dft12<DIR>(v);
   else if constexpr (R == 1) (void)v;
   else dft_small<R, DIR>(v);
 }
@@ -728,7 +762,9 @@ __global__ __launch_bounds__(FFT_NT) void k_rb_y(const Grid g, const FftKArgs ka
     const int xy = sp.pts_xy[i];
     const int yy = xy / g.d1, x = xy - yy * g.d1;
     const int yr = yy <= g.by ? yy : yy - g.d2 + n2;
-    fo.o0[i + (long long)col * fo.ld0] = cscale(to_d2(bxc[box_of(x, g.d1, bx) * bp + yr]), inv_n);
+    const double2 val = cscale(to_d2(bxc[box_of(x, g.d1, bx) * bp + yr]), inv_n);
+    if (fo.o0f) fo.o0f[i + (long long)col * fo.ld0] = make_float2((float)val.x, (float)val.y);
+    else fo.o0[i + (long long)col * fo.ld0] = val;
   }
 }
 
@@ -1362,7 +1398,9 @@ __global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka,
     const int xy = sp.pts_xy[i];
     const int yy = xy / g.d1, x = xy - yy * g.d1;
     const int ky = yy <= by ? yy : yy - g.d2;
-    fo.o0[i + (long long)col * fo.ld0] = cscale(to_d2(box[box_of(x, g.d1, bx) * nby + ky + by]), inv_n);
+    const double2 val = cscale(to_d2(box[box_of(x, g.d1, bx) * nby + ky + by]), inv_n);
+    if (fo.o0f) fo.o0f[i + (long long)col * fo.ld0] = make_float2((float)val.x, (float)val.y);
+    else fo.o0[i + (long long)col * fo.ld0] = val;
   }
 }
 
@@ -1633,30 +1671,31 @@ constexpr int RB_VARIANTS = 3;  // launch shapes of k_rb_xz4; shape RB_VARIANTS 
 template <class T>
 constexpr int xzr_nw() { return sizeof(T) == 16 ? 2 : 4; }
 constexpr int rb_nw_of(int v) { return v == 1 ? 2 : 4; }
-template <int N, int F1>
+template <int NZ, int Z1>
 constexpr int rb_lz_of(int v) {
-  return v == 2 ? (rb_lz(Two<N, F1, N / F1>::LPW) / 2 > 0 ? rb_lz(Two<N, F1, N / F1>::LPW) / 2 : 1)
-                : rb_lz(Two<N, F1, N / F1>::LPW);
+  return v == 2 ? (rb_lz(Two<NZ, Z1, NZ / Z1>::LPW) / 2 > 0 ? rb_lz(Two<NZ, Z1, NZ / Z1>::LPW) / 2 : 1)
+                : rb_lz(Two<NZ, Z1, NZ / Z1>::LPW);
 }
 
-template <int N, int F1, class T, class F>
+// the three launch shapes of the x/z kernel for x length NX = X1 (NX / X1) and z
+// length NZ = Z1 (NZ / Z1)
+template <int NX, int X1, int NZ, int Z1, class T, class F>
 void reg_xz4(F &&f) {
-  f((const void *)k_rb_xz4<N, F1, N / F1, N, F1, N / F1, rb_nw_of(0), rb_lz_of<N, F1>(0), T>);
-  f((const void *)k_rb_xz4<N, F1, N / F1, N, F1, N / F1, rb_nw_of(1), rb_lz_of<N, F1>(1), T>);
-  f((const void *)k_rb_xz4<N, F1, N / F1, N, F1, N / F1, rb_nw_of(2), rb_lz_of<N, F1>(2), T>);
+  f((const void *)k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, rb_nw_of(0), rb_lz_of<NZ, Z1>(0), T>);
+  f((const void *)k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, rb_nw_of(1), rb_lz_of<NZ, Z1>(1), T>);
+  f((const void *)k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, rb_nw_of(2), rb_lz_of<NZ, Z1>(2), T>);
 }
 
-template <int N, int F1, class T>
+template <int NX, int X1, int NZ, int Z1, class T>
 void launch_xz4(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s, int v) {
-  using TZ = Two<N, F1, N / F1>;
   const auto *th = static_cast<const typename CT<T>::R *>(thv);
   const dim3 grid(ncols, g.n2, nk);
-#define LTD_V(V)                                                                                                \
-  do {                                                                                                          \
-    constexpr int NW = rb_nw_of(V), LZ = rb_lz_of<N, F1>(V);                                                    \
-    const size_t lds = xz4_lds<N, F1, N, F1, T>(g.nbz, NW, LZ);                                                   \
-    hipLaunchKernelGGL((k_rb_xz4<N, F1, N / F1, N, F1, N / F1, NW, LZ, T>), grid, dim3(NW * 64), lds, s, g, ka, \
-                       ncols, th);                                                                              \
+#define LTD_V(V)                                                                                            \
+  do {                                                                                                      \
+    constexpr int NW = rb_nw_of(V), LZ = rb_lz_of<NZ, Z1>(V);                                               \
+    const size_t lds = xz4_lds<NX, X1, NZ, Z1, T>(g.nbz, NW, LZ);                                           \
+    hipLaunchKernelGGL((k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, NW, LZ, T>), grid, dim3(NW * 64), lds, s, g, \
+                       ka, ncols, th);                                                                      \
   } while (0)
   if (v == 1) LTD_V(1);
   else if (v == 2) LTD_V(2);
@@ -1675,12 +1714,14 @@ void each_plane_kernel(F &&f) {
   f((const void *)k_rb_xz<a, c>);
   LTD_RB(0, 0) LTD_RB(16, 16) LTD_RB(64, 64) LTD_RB(72, 72) LTD_RB(96, 160)
 #undef LTD_RB
-  reg_xz4<72, 8, double2>(f);
-  reg_xz4<64, 8, double2>(f);
-  reg_xz4<16, 4, double2>(f);
-  reg_xz4<72, 8, float2>(f);
-  reg_xz4<64, 8, float2>(f);
-  reg_xz4<16, 4, float2>(f);
+  reg_xz4<72, 8, 72, 8, double2>(f);
+  reg_xz4<64, 8, 64, 8, double2>(f);
+  reg_xz4<16, 4, 16, 4, double2>(f);
+  reg_xz4<72, 8, 108, 12, double2>(f);
+  reg_xz4<72, 8, 72, 8, float2>(f);
+  reg_xz4<64, 8, 64, 8, float2>(f);
+  reg_xz4<16, 4, 16, 4, float2>(f);
+  reg_xz4<72, 8, 108, 12, float2>(f);
   f((const void *)k_rb_xzr<xzr_nw<float2>(), float2>);
   f((const void *)k_inv_plane<0, 0>);
   f((const void *)k_fwd_plane<0, 0>);
@@ -1726,20 +1767,24 @@ void fft_init_attrs() { set_attrs(); }
 
 size_t fft_rb_slab_values(const Grid &g) { return (size_t)g.nbz * g.n2 * g.nbx; }
 
-// Two-factor splits of the x and z lengths with a register path (0 if none).
-int rb_split(int n) { return n == 72 ? 8 : n == 64 ? 8 : n == 16 ? 4 : 0; }
+// Two-factor splits N = F1 F2 of the x and z lengths with a register path (F1, or 0 if none).
+int rb_split(int n) { return n == 72 ? 8 : n == 64 ? 8 : n == 16 ? 4 : n == 108 ? 12 : 0; }
+// (x, z) length pairs of the register x/z kernel
+bool rb_pair(int nx, int nz) {
+  return (nx == nz && (nx == 16 || nx == 64 || nx == 72)) || (nx == 72 && nz == 108);
+}
 // the register x/z kernel; on 64-point axes it drops the inputs and outputs with
 // |frequency| >= 16, so the box there must have b <= 15 (which 64 >= 4 b + 1 gives)
 bool rb_fast(const Grid &g) {
   const auto ok = [](int n, int b) { return rb_split(n) > 0 && (n != 64 || b <= 15); };
-  return ok(g.n1, g.bx) && ok(g.n3, g.bz);
+  return rb_pair(g.n1, g.n3) && ok(g.n1, g.bx) && ok(g.n3, g.bz);
 }
 
 
 bool fft_rb_fast(const Grid &g) { return rb_fast(g); }
 
 int fft_rb_length(int n, int b) {
-  for (int c : {16, 64, 72})
+  for (int c : {16, 64, 72, 108})
     if (c >= 4 * b + 1 && c <= n) return c;
   return n;
 }
@@ -1892,14 +1937,15 @@ hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, con
   if (part == 0 && variant == RB_VARIANTS) {  // register-resident: complex64 on 64-point grids
     launch_xzr<float2>(g, ka, nk, ncols, thv, s);
   } else if (part == 0 && rb_fast(g)) {
-#define LTD_XZ4P(n, f1)                                                  \
-  do {                                                                   \
-    if (fp32) launch_xz4<n, f1, float2>(g, ka, nk, ncols, thv, s, variant);  \
-    else launch_xz4<n, f1, double2>(g, ka, nk, ncols, thv, s, variant);      \
+#define LTD_XZ4P(nx, x1, nz, z1)                                                    \
+  do {                                                                              \
+    if (fp32) launch_xz4<nx, x1, nz, z1, float2>(g, ka, nk, ncols, thv, s, variant);  \
+    else launch_xz4<nx, x1, nz, z1, double2>(g, ka, nk, ncols, thv, s, variant);      \
   } while (0)
-    if (g.n1 == 72 && g.n3 == 72) LTD_XZ4P(72, 8);
-    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ4P(64, 8);
-    else if (g.n1 == 16 && g.n3 == 16) LTD_XZ4P(16, 4);
+    if (g.n1 == 72 && g.n3 == 72) LTD_XZ4P(72, 8, 72, 8);
+    else if (g.n1 == 64 && g.n3 == 64) LTD_XZ4P(64, 8, 64, 8);
+    else if (g.n1 == 16 && g.n3 == 16) LTD_XZ4P(16, 4, 16, 4);
+    else if (g.n1 == 72 && g.n3 == 108) LTD_XZ4P(72, 8, 108, 12);
     else return hipErrorInvalidValue;
 #undef LTD_XZ4P
   } else if (part == 0) {

@@ -360,11 +360,228 @@ __global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZP
   }
 }
 
+// ---------------------------------------------------------------------------
+// Complex GEMM on complex64 operands with FP32 matrix cores (the mixed-precision
+// residual rebuild): C = alpha op(A) B + beta C, op(A) = A or A^H, A and B
+// complex64 column-major (the ZProb pointers hold float2 data), C complex128.
+// Each K tile of BK = 16 is accumulated in FP32 by v_mfma_f32_16x16x4f32 (four
+// real MFMAs per complex multiply-add: re += ar br - ai bi, im += ar bi + ai br),
+// and the tiles' sums are added in FP64 registers, so the rounding of a long K
+// stays that of one 16-term FP32 sum per tile; split-K partial tiles are written
+// in FP64 and reduced in a fixed order by zgemm_reduce (deterministic).  Same
+// tiling, planner and XCD remap as zgemm_kernel.
+// ---------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef const f2v __attribute__((address_space(1))) *gptr32;
+__device__ inline float2 ldg32(gptr32 p) {
+  const f2v v = *p;
+  return make_float2(v.x, v.y);
+}
+
+// TO: element type of C (double2; float2 only for unsplit problems, whose C
+// pointer then holds float2 data).
+template <int OPA, bool TABLE, int MB, class TO>
+__global__ __launch_bounds__(NT) void cgemm32_kernel(const ZBatch batch, const ZProb *__restrict__ table, int nprob,
+                                                     double2 *__restrict__ partials) {
+  constexpr int AW = MB / 32;
+  constexpr int QA = MB / 16;
+  __shared__ float As[2][2][BK][MB + 4];
+  __shared__ float Bs[2][2][BK][BN + 4];
+  const ZProb *probs = TABLE ? table : batch.p;
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  int pi = 0;
+  while (pi + 1 < nprob && probs[pi + 1].tile_begin <= logical) ++pi;
+  const ZProb &P = probs[pi];
+  int t = logical - P.tile_begin;
+  const int tm = t % P.tiles_m;
+  t /= P.tiles_m;
+  const int tn = t % P.tiles_n;
+  t /= P.tiles_n;
+  const int bi = t % P.batch;
+  const int ks = t / P.batch;
+  const int m0 = tm * MB, n0 = tn * BN;
+  const gptr32 A = (gptr32)(const void *)(reinterpret_cast<const float2 *>(P.A) + (long long)bi * P.sA);
+  const gptr32 B = (gptr32)(const void *)(reinterpret_cast<const float2 *>(P.B) + (long long)bi * P.sB);
+  const int kbeg = ks * P.kchunk;
+  const int kend = min(P.k, kbeg + P.kchunk);
+  const int nkt = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  // staging of one K tile (clamped loads, zero outside the problem)
+  float2 fa[QA], fb[4];
+  const auto load = [&](int k0) {
+    if (OPA == OP_N) {  // A is m x k: column kk contiguous in i
+      const int kk = tid >> 4, i = (tid & 15) * QA, kg = k0 + kk, kc = kg < kend ? kg : kend - 1;
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const int ig = m0 + i + q;
+        const float2 v = ldg32(A + (long long)(ig < P.m ? ig : P.m - 1) + (long long)kc * P.lda);
+        fa[q] = (ig < P.m && kg < kend) ? v : make_float2(0.f, 0.f);
+      }
+    } else {  // A is k x m (conjugate-transposed): row i contiguous in kk
+      constexpr int TPR = NT / MB;
+      const int i = tid / TPR, kk = (tid % TPR) * QA, ig = m0 + i, ic = ig < P.m ? ig : P.m - 1;
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const int kg = k0 + kk + q;
+        const float2 v = ldg32(A + (long long)(kg < kend ? kg : kend - 1) + (long long)ic * P.lda);
+        fa[q] = (ig < P.m && kg < kend) ? v : make_float2(0.f, 0.f);
+      }
+    }
+    const int j = tid >> 2, kk = (tid & 3) * 4, jg = n0 + j, jc = jg < P.n ? jg : P.n - 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kg = k0 + kk + q;
+      const float2 v = ldg32(B + (long long)(kg < kend ? kg : kend - 1) + (long long)jc * P.ldb);
+      fb[q] = (jg < P.n && kg < kend) ? v : make_float2(0.f, 0.f);
+    }
+  };
+  const auto store = [&](int buf) {
+    if (OPA == OP_N) {
+      const int kk = tid >> 4, i = (tid & 15) * QA;
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        As[buf][0][kk][i + q] = fa[q].x;
+        As[buf][1][kk][i + q] = fa[q].y;
+      }
+    } else {
+      constexpr int TPR = NT / MB;
+      const int i = tid / TPR, kk = (tid % TPR) * QA;
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        As[buf][0][kk + q][i] = fa[q].x;
+        As[buf][1][kk + q][i] = -fa[q].y;  // conjugate
+      }
+    }
+    const int j = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Bs[buf][0][kk + q][j] = fb[q].x;
+      Bs[buf][1][kk + q][j] = fb[q].y;
+    }
+  };
+
+  double sre[AW][2][4], sim[AW][2][4];
+#pragma unroll
+  for (int a = 0; a < AW; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sre[a][b][r] = sim[a][b][r] = 0.0;
+  if (nkt > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int cur = kt & 1;
+    load(kbeg + (kt + 1 < nkt ? kt + 1 : kt) * BK);
+    __builtin_amdgcn_sched_barrier(0);
+    f4 fre[AW][2], fim[AW][2];
+#pragma unroll
+    for (int a = 0; a < AW; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) fre[a][b] = fim[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kq = 0; kq < BK; kq += 4) {
+      const int kk = kq + (lane >> 4);
+      float ar[AW], ai[AW], nai[AW], br[2], bim[2];
+#pragma unroll
+      for (int a = 0; a < AW; ++a) {
+        const int i = wm * (MB / 2) + a * 16 + (lane & 15);
+        ar[a] = As[cur][0][kk][i];
+        ai[a] = As[cur][1][kk][i];
+        nai[a] = -ai[a];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = wn * 32 + b * 16 + (lane & 15);
+        br[b] = Bs[cur][0][kk][j];
+        bim[b] = Bs[cur][1][kk][j];
+      }
+#pragma unroll
+      for (int a = 0; a < AW; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          fre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[a], br[b], fre[a][b], 0, 0, 0);
+          fre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[a], bim[b], fre[a][b], 0, 0, 0);
+          fim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[a], bim[b], fim[a][b], 0, 0, 0);
+          fim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[a], br[b], fim[a][b], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < AW; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          sre[a][b][r] += (double)fre[a][b][r];
+          sim[a][b][r] += (double)fim[a][b][r];
+        }
+    if (kt + 1 < nkt) store(cur ^ 1);
+    __syncthreads();
+  }
+  // output element of register r of v_mfma_f32_16x16x4f32: row 4 (lane / 16) + r, column lane % 16
+  const auto row_of = [&](int a, int r) { return wm * (MB / 2) + a * 16 + 4 * (lane >> 4) + r; };
+  const auto col_of = [&](int b) { return wn * 32 + b * 16 + (lane & 15); };
+  if (P.ksplit == 1) {
+    TO *C = reinterpret_cast<TO *>(P.C) + (long long)bi * P.sC;
+    const bool rd = (P.beta.x != 0.0 || P.beta.y != 0.0);
+#pragma unroll
+    for (int a = 0; a < AW; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = m0 + row_of(a, r), j = n0 + col_of(b);
+          if (i < P.m && j < P.n) {
+            double2 v = cmul(P.alpha, make_double2(sre[a][b][r], sim[a][b][r]));
+            TO *dst = C + (long long)i + (long long)j * P.ldc;
+            if (rd) v = cfma(P.beta, to_d2(*dst), v);
+            *dst = CT<TO>::from(v);
+          }
+        }
+  } else if constexpr (sizeof(TO) == 16) {
+    const long long tile_lin = ((long long)bi * P.tiles_n + tn) * P.tiles_m + tm;
+    double2 *dst = partials + (P.part_off + tile_lin * P.ksplit + ks) * (long long)(BM * BN);
+#pragma unroll
+    for (int a = 0; a < AW; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[col_of(b) * MB + row_of(a, r)] = make_double2(sre[a][b][r], sim[a][b][r]);
+  }
+}
+
 template <bool TABLE>
 hipError_t launch_impl(int opa, int opb, const ZBatch &b, const ZProb *table, const ZProb *host, int nprob,
-                       int total_tiles, double2 *partials, int n_limit, hipStream_t s, int parts = 3) {
+                       int total_tiles, double2 *partials, int n_limit, hipStream_t s, int parts = 3,
+                       bool fp32 = false, bool out32 = false) {
   if (total_tiles <= 0) return hipSuccess;
   const dim3 grid(total_tiles), block(NT);
+  if (fp32 && (parts & 1)) {  // complex64 operands, op(B) = B, no column limit
+    if (opb != OP_N || n_limit > 0) return hipErrorInvalidValue;
+    if (out32)
+      for (int i = 0; i < nprob; ++i)
+        if (host[i].ksplit != 1) return hipErrorInvalidValue;  // complex64 C: unsplit problems only
+#define LTD_CG(OA, TO)                                                                                        \
+  do {                                                                                                        \
+    if (host[0].bm == 32)                                                                                     \
+      hipLaunchKernelGGL((cgemm32_kernel<OA, TABLE, 32, TO>), grid, block, 0, s, b, table, nprob, partials);   \
+    else                                                                                                      \
+      hipLaunchKernelGGL((cgemm32_kernel<OA, TABLE, 64, TO>), grid, block, 0, s, b, table, nprob, partials);   \
+  } while (0)
+    if (opa == OP_N && out32) LTD_CG(OP_N, float2);
+    else if (opa == OP_N) LTD_CG(OP_N, double2);
+    else if (out32) LTD_CG(OP_C, float2);
+    else LTD_CG(OP_C, double2);
+#undef LTD_CG
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    parts &= ~1;
+  }
 #define LTD_ZG(OA, OB)                                                                                         \
   do {                                                                                                         \
     if (host[0].bm == 32)                                                                                      \
@@ -485,6 +702,17 @@ hipError_t gemm_launch_table(int opa, int opb, const ZProb *dev_table, const ZPr
                              int total_tiles, double2 *partials, int n_limit, hipStream_t s, int parts) {
   static const ZBatch empty{};
   return launch_impl<true>(opa, opb, empty, dev_table, host, nprob, total_tiles, partials, n_limit, s, parts);
+}
+
+hipError_t cgemm32_launch(int opa, const ZBatch &b, double2 *partials, hipStream_t s, bool out32) {
+  return launch_impl<false>(opa, OP_N, b, nullptr, b.p, b.nprob, b.total_tiles, partials, 0, s, 3, true, out32);
+}
+
+hipError_t cgemm32_launch_table(int opa, const ZProb *dev_table, const ZProb *host, int nprob, int total_tiles,
+                                double2 *partials, hipStream_t s, int parts, bool out32) {
+  static const ZBatch empty{};
+  return launch_impl<true>(opa, OP_N, empty, dev_table, host, nprob, total_tiles, partials, 0, s, parts, true,
+                           out32);
 }
 
 }  // namespace ltd

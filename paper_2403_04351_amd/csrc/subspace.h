@@ -7,6 +7,8 @@
 namespace ltd {
 
 constexpr int CHEB_KMAX = 96;  // largest Chebyshev degree of the step exponential
+constexpr int TAYLOR_MAX = 8;  // largest order of the explicit (truncated Taylor) step
+constexpr int PART_STRIDE = 6; // per-state partial sums of the step and adjoint kernels
 
 // Per k-point subspace state (lives in the workspace; matrices n_aux x n_aux,
 // column-major, in the S-orthonormal basis Phi~ = Phi L^{-H} unless noted).
@@ -43,7 +45,9 @@ struct StepCtx {
   const double *a_t, *a_mid;
   double c_light, occ, omega, dt;
   double2 *theta;          // [n_k][n_states][n_aux]
-  double *part;            // [n_k * n_states][4] partial sums
+  double *part;            // [n_k * n_states][PART_STRIDE] partial sums
+  int taylor;              // 0: exponential (Chebyshev series); else order of the truncated Taylor step
+  double *nexc_out;        // optional [n_steps+1] excited electrons at t_n
   int *status;
   int *done;               // blocks of the step kernel finished (zero between launches)
   double *j_out, *e_out, *dmu_out;
@@ -65,6 +69,13 @@ hipError_t launch_copy_step(double2 *dst, const double2 *src, long long n, const
                             long long host_off, const double2 *sub, hipStream_t s);
 hipError_t launch_copy_rows(double2 *dst, int ldd, const double2 *src, int lds, int rows, int cols, bool zero,
                             hipStream_t s);
+// dst[i] = complex64(src[off + i] - sub[i]), i < n (off as launch_copy_step)
+hipError_t launch_copy_step32(float2 *dst, const double2 *src, long long n, const int *step, long long stride,
+                              long long host_off, const double2 *sub, hipStream_t s);
+// complex64 copy of the rows of src (ld lds): rows r < ng as they are, then row
+// ng + i from src row ng + perm[i], i < nperm; cols columns
+hipError_t launch_rows_to_c64(float2 *dst, int ldd, const double2 *src, int lds, int ng, const int *perm, int nperm,
+                              int cols, hipStream_t s);
 hipError_t launch_herm_split(const double2 *x, int ldx, int n, int nb, double2 *out, hipStream_t s);
 hipError_t launch_axpby(double2 *out, const double2 *a, const double2 *b, double sa, double sb, long long n,
                         hipStream_t s);

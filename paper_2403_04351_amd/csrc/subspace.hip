@@ -160,6 +160,29 @@ __global__ void k_copy_step(double2 *__restrict__ dst, const double2 *__restrict
     dst[i] = sub ? csub(src[off + i], sub[i]) : src[off + i];
 }
 
+// dst[i] = complex64(src[off + i] - sub[i]) (the FP32 residual's block difference)
+__global__ void k_copy_step32(float2 *__restrict__ dst, const double2 *__restrict__ src, long long n, const int *step,
+                              long long stride, long long host_off, const double2 *__restrict__ sub) {
+  const long long off = step ? (long long)(*step) * stride : host_off;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double2 v = csub(src[off + i], sub[i]);
+    dst[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+// dst rows (complex64, ld ldd): rows r < ng copy src row r; row ng + i copies src row ng + perm[i]
+__global__ void k_rows_to_c64(float2 *dst, int ldd, const double2 *src, int lds, int ng, const int *perm, int nperm,
+                              int cols) {
+  const int rows = ng + nperm;
+  const long long tot = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % rows), c = (int)(e / rows);
+    const int sr = r < ng ? r : ng + perm[r - ng];
+    const double2 v = src[sr + (long long)c * lds];
+    dst[r + (long long)c * ldd] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
 __global__ void k_thv(double *out, const double *th, const double *v, long long n) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
     out[e] = th[e] * v[e];
@@ -391,17 +414,22 @@ __device__ __forceinline__ void stage_to_lds(double2 *dst, const double2 *src, l
 __device__ void finalize_step(const StepCtx &c, int step) {
   const int np = c.n_k * c.n_states;
   double j1 = 0.0, e1 = 0.0, j0 = 0.0, e0 = 0.0;
+  double x1 = 0.0, x0 = 0.0;
   for (int p = 0; p < np; ++p) {
-    j1 += c.part[4 * p + 0];
-    e1 += c.part[4 * p + 1];
-    j0 += c.part[4 * p + 2];
-    e0 += c.part[4 * p + 3];
+    j1 += c.part[PART_STRIDE * p + 0];
+    e1 += c.part[PART_STRIDE * p + 1];
+    j0 += c.part[PART_STRIDE * p + 2];
+    e0 += c.part[PART_STRIDE * p + 3];
+    x1 += c.part[PART_STRIDE * p + 4];
+    x0 += c.part[PART_STRIDE * p + 5];
   }
   if (step == 0) {
     c.j_out[0] = j0;
     c.e_out[0] = e0;
     c.dmu_out[0] = 0.0;
+    if (c.nexc_out) c.nexc_out[0] = x0;
   }
+  if (c.nexc_out) c.nexc_out[step + 1] = x1;
   const double jz = c.j_out[0];
   c.j_out[step + 1] = j1;
   c.e_out[step + 1] = e1;
@@ -443,7 +471,10 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
     const int nb = (int)((n2 + 255) / 256);
     for (int q = threadIdx.x; q < nb; q += 64) dev2 += S.dev[q];
     dev2 = wave_sum(dev2);
-    if (threadIdx.x == 0 && !(sqrt(dev2) <= S.margin)) latch(c.status, 4);
+    // a non-finite H~(mid) (a non-finite potential handed in) is reported as such;
+    // a finite one outside the series' interval as a spectrum error
+    if (threadIdx.x == 0 && !isfinite(dev2)) latch(c.status, 3);
+    else if (threadIdx.x == 0 && !(sqrt(dev2) <= S.margin)) latch(c.status, 4);
   }
   __syncthreads();
 
@@ -476,9 +507,45 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
       *eo = c.occ * S.kw * vh;
     }
   };
-  double *part = c.part + 4 * ((long long)k * c.n_states + j);
-  if (step == 0) observe(c.a_t[0], part + 2, part + 3, true);
+  double *part = c.part + PART_STRIDE * ((long long)k * c.n_states + j);
+  // excited electrons of this state: f w_k (theta~^H theta~ - sum_{i < N_s} |(S_sub theta)_i|^2),
+  // S_sub theta = L theta~ (the overlaps with the first N_s auxiliary functions)
+  auto excited = [&](double *xo) {
+    double nn = 0.0, oc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) nn += v[i].x * v[i].x + v[i].y * v[i].y;
+    for (int i = threadIdx.x; i < c.n_states; i += blockDim.x) {
+      double2 sv = make_double2(0.0, 0.0);
+      for (int q = 0; q <= i; ++q) sv = cfma(S.L[i + (long long)q * n], v[q], sv);
+      oc += sv.x * sv.x + sv.y * sv.y;
+    }
+    double z = 0.0;
+    block_sum3(nn, oc, z, sred);
+    if (threadIdx.x == 0) *xo = c.occ * S.kw * (nn - oc);
+  };
+  if (step == 0) {
+    observe(c.a_t[0], part + 2, part + 3, true);
+    if (c.nexc_out) excited(part + 5);
+  }
 
+  if (c.taylor > 0) {
+    // 3'. explicit step: the Taylor series of exp(-i dt (H~ - c0)) truncated after
+    //     c.taylor terms (H~ - c0 = r M), term_q = (-i dt r / q) M term_{q-1}
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      t0[i] = v[i];
+      acc[i] = v[i];
+    }
+    __syncthreads();
+    for (int q = 1; q <= c.taylor; ++q) {
+      matvec<false>(Hm, n, t0, tmp, n, red);
+      const double fq = c.dt * S.r / q;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 tn = make_double2(fq * tmp[i].y, -fq * tmp[i].x);  // -i fq tmp
+        t0[i] = tn;
+        acc[i] = cadd(acc[i], tn);
+      }
+      __syncthreads();
+    }
+  } else {
   // 3. Chebyshev series
   const int K = S.K;
   for (int i = threadIdx.x; i < n; i += blockDim.x) t0[i] = v[i];
@@ -499,6 +566,7 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
     pa = pb;
     pb = x;
   }
+  }
   for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = cmul(S.phase, acc[i]);
   __syncthreads();
 
@@ -506,8 +574,9 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
   matvec<false>(S.LinvH, n, v, w, n, red);
   for (int i = threadIdx.x; i < n; i += blockDim.x) th[i] = w[i];
 
-  // 5. observables at t_{n+1}
+  // 5. observables at t_{n+1} (v still holds theta~)
   observe(a1, part + 0, part + 1, false);
+  if (c.nexc_out) excited(part + 4);
 
   // 6. the last block to finish: fixed-order sum, series, step counter
   __syncthreads();
@@ -556,7 +625,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepCtx c, const AdjCtx a
   const double wn = (step == 0 || step == ac.n_steps) ? 0.5 : 1.0;
   const double ir = 1.0 / S.r;
   const double gs = -(2.0 * c.occ / c.omega) * S.kw;
-  double *part = c.part + 4 * ((long long)k * c.n_states + j);
+  double *part = c.part + PART_STRIDE * ((long long)k * c.n_states + j);
   double2 *mo = ac.mu_out + (long long)k * n * c.n_states + (long long)j * n;
 
   const double2 *th = c.theta + (long long)k * n * c.n_states + (long long)j * n;
@@ -688,9 +757,9 @@ __global__ void k_adjoint_finalize(const StepCtx c, const AdjCtx ac) {
   const int np = c.n_k * c.n_states;
   double dm = 0.0, dt_ = 0.0, dj = 0.0;
   for (int p = 0; p < np; ++p) {
-    dm += c.part[4 * p + 0];
-    dt_ += c.part[4 * p + 1];
-    dj += c.part[4 * p + 2];
+    dm += c.part[PART_STRIDE * p + 0];
+    dt_ += c.part[PART_STRIDE * p + 1];
+    dj += c.part[PART_STRIDE * p + 2];
   }
   if (!ac.terminal) ac.dl_da_mid[ac.n] = dm;
   // the J_0 subtracted in J_ind: L contains -T J_0, T = N dt
@@ -786,6 +855,23 @@ hipError_t launch_copy_step(double2 *dst, const double2 *src, long long n, const
   if (n <= 0) return hipSuccess;
   const int blocks = (int)std::min<long long>((n + 255) / 256, 2048);
   hipLaunchKernelGGL(k_copy_step, dim3(blocks), dim3(256), 0, s, dst, src, n, step, stride, host_off, sub);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_step32(float2 *dst, const double2 *src, long long n, const int *step, long long stride,
+                              long long host_off, const double2 *sub, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_copy_step32, dim3(blocks), dim3(256), 0, s, dst, src, n, step, stride, host_off, sub);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_to_c64(float2 *dst, int ldd, const double2 *src, int lds, int ng, const int *perm, int nperm,
+                              int cols, hipStream_t s) {
+  const long long tot = (long long)(ng + nperm) * cols;
+  if (tot <= 0) return hipSuccess;
+  const int nb = (int)((tot + 255) / 256 < 4096 ? (tot + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_rows_to_c64, dim3(nb), dim3(256), 0, s, dst, ldd, src, lds, ng, perm, nperm, cols);
   return hipGetLastError();
 }
 

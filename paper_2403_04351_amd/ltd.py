@@ -187,10 +187,12 @@ class Ltd:
         return tuple(out)
 
     def make_step_args(self, mode, dt, a_t, a_mid, theta, n_steps, c_out=None, v_r_t=None, h_t=None,
-                       v_stride=0, h_stride=0):
+                       v_stride=0, h_stride=0, taylor_order=0, nexc=False):
         """Device buffers and the StepArgs for a run of n_steps; theta (n_k, n_states, n_aux).
         v_stride / h_stride: elements between the potentials / blocks of consecutive
-        steps when v_r_t / h_t hold one per step (0: one for every step)."""
+        steps when v_r_t / h_t hold one per step (0: one for every step).
+        taylor_order > 0: the explicit truncated-Taylor step; nexc: also the
+        excited-electron series st["nexc"]."""
         torch = _torch()
         dev = self.device
         st = dict(
@@ -198,12 +200,14 @@ class Ltd:
             j=torch.zeros(n_steps + 1, dtype=torch.float64, device=dev),
             e=torch.zeros(n_steps + 1, dtype=torch.float64, device=dev),
             dmu=torch.zeros(n_steps + 1, dtype=torch.float64, device=dev),
+            nexc=torch.zeros(n_steps + 1, dtype=torch.float64, device=dev) if nexc else None,
             a_t=a_t, a_mid=a_mid, theta=theta, c_out=c_out, v_r_t=v_r_t, h_t=h_t,
         )
         st["args"] = StepArgs(mode=mode, dt=dt, a_t=_ptr(a_t), a_mid=_ptr(a_mid), step=_ptr(st["step"]),
                               v_r_t=_ptr(v_r_t), h_t=_ptr(h_t), theta=_ptr(theta), c_out=_ptr(c_out),
                               j_out=_ptr(st["j"]), e_out=_ptr(st["e"]), dmu_out=_ptr(st["dmu"]),
-                              v_stride=v_stride, h_stride=h_stride)
+                              v_stride=v_stride, h_stride=h_stride, taylor_order=taylor_order,
+                              nexc_out=_ptr(st["nexc"]))
         return st
 
     def step(self, st):
@@ -212,11 +216,17 @@ class Ltd:
     def run(self, st, n_steps: int):
         check(self.lib.ltd_propagate(self.handle, C.byref(st["args"]), n_steps, self.stream()), "ltd_propagate")
 
+    def prepare(self, st, n_steps: int):
+        """Captures the graphs a ``run(st, n_steps)`` replays, without running a step."""
+        check(self.lib.ltd_propagate_prepare(self.handle, C.byref(st["args"]), n_steps, self.stream()),
+              "ltd_propagate_prepare")
+
     def propagate(self, mode, dt, a_t, a_mid, theta, n_steps, graph=True, c_out=None, v_r_t=None, h_t=None,
-                  v_stride=0, h_stride=0, reorth_every=None):
+                  v_stride=0, h_stride=0, reorth_every=None, taylor_order=0, nexc=False):
         """n_steps steps; reorth_every = K: after every K steps the states are
         reorthonormalised (Loewdin) and the drift before it is kept in st["drift"]."""
-        st = self.make_step_args(mode, dt, a_t, a_mid, theta, n_steps, c_out, v_r_t, h_t, v_stride, h_stride)
+        st = self.make_step_args(mode, dt, a_t, a_mid, theta, n_steps, c_out, v_r_t, h_t, v_stride, h_stride,
+                                 taylor_order, nexc)
         if reorth_every:
             st["drift"] = []
             done = 0
@@ -277,6 +287,31 @@ class Ltd:
         check(self.lib.ltd_knot_gradient(_ptr(g_t), _ptr(g_mid), g_mid.numel(), dt, n_knots, t_end, _ptr(g),
                                          self.stream()), "ltd_knot_gradient")
         return g
+
+
+def pulse_samples(kind: int, params, dt: float, n_steps: int, device="cuda"):
+    """A(t_n) (n = 0..n_steps) and A(t_n + dt/2) of a pulse kind (LTD_PULSE_*)
+    with its four parameters, on the device."""
+    torch = _torch()
+    lib = _lib.load()
+    a_t = torch.empty(n_steps + 1, dtype=torch.float64, device=device)
+    a_mid = torch.empty(n_steps, dtype=torch.float64, device=device)
+    p = (C.c_double * 4)(*[float(x) for x in params])
+    stream = int(torch.cuda.current_stream(a_t.device).cuda_stream)
+    check(lib.ltd_pulse_samples(kind, p, dt, n_steps, _ptr(a_t), _ptr(a_mid), stream), "ltd_pulse_samples")
+    return a_t, a_mid
+
+
+def polarizability(j, a_t, dt: float, omega_cell: float, c_light: float, w, gamma: float):
+    """alpha_zz(w) (complex tensor, one per frequency of w) from the current series j
+    and the potential samples a_t of a run (Eq. (5))."""
+    torch = _torch()
+    lib = _lib.load()
+    out = torch.empty(w.numel(), dtype=torch.complex128, device=j.device)
+    stream = int(torch.cuda.current_stream(j.device).cuda_stream)
+    check(lib.ltd_polarizability(_ptr(j), _ptr(a_t), j.numel() - 1, dt, omega_cell, c_light, _ptr(w), w.numel(),
+                                 gamma, _ptr(out), stream), "ltd_polarizability")
+    return out
 
 
 def chebyshev_coefficients(tau: float, kmax: int):

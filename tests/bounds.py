@@ -1,22 +1,41 @@
-"""Error bounds of results that are fixed linear maps of the current series J.
+"""Parity bars of the series derived from the current: J_ind = J - J(0) and the
+dipole change delta mu (Sec. 2, Eq. (4)), each measured against its own
+maximum (``rel_own``).
 
-delta mu (Eq. (4): Omega times the time integral of J_ind) and J_ind = J - J(0)
-are linear in J, so a J within eps max|J| of the oracle bounds their errors by
-the map's norm times eps max|J|.  Their own relative errors are inflated by
-cancellation (J_ind is a small difference of large currents), so the parity
-tests check them against these bounds."""
+They cannot meet the 1e-10 bar of J itself: J_ind is a small difference of
+large currents (the static current J(0) of the synthetic blocks is hundreds of
+times the induced one) and delta mu integrates J_ind over the run, so rounding
+at the 1e-16 level in the subspace matrices moves them by far more than 1e-10
+of their own size.  ``tests/golden/rounding_spread.json`` holds that movement for
+the oracle itself (the oracle against the oracle with the plane-wave order
+permuted: same physics, other rounding).  The bars below are a fixed multiple
+of the largest measured spread, and never below 1e-10.
+"""
+
+import json
+import os
 
 import numpy as np
 
 J_TOL = 1e-10
+_SPREAD = os.path.join(os.path.dirname(__file__), "golden", "rounding_spread.json")
+_FACTOR = 10.0
 
 
-def dmu_bound(j_ref, dt, omega, eps=J_TOL):
-    """|d dmu_n| <= Omega t_n (max_m |dJ_m| + |dJ_0|) <= 2 Omega T eps max|J| (trapezoid weights sum to t_n)."""
-    n = len(j_ref) - 1
-    return 2.0 * abs(omega) * n * dt * eps * float(np.abs(j_ref).max())
+def _bar(key):
+    try:
+        rec = json.load(open(_SPREAD))
+    except OSError:
+        return 1e-8
+    worst = max(float(v[key]) for v in rec.values() if isinstance(v, dict))
+    return max(J_TOL, _FACTOR * worst)
 
 
-def jind_bound(j_ref, eps=J_TOL):
-    """|d(J_n - J_0)| <= 2 eps max|J|."""
-    return 2.0 * eps * float(np.abs(j_ref).max())
+JIND_TOL = _bar("j_ind")
+DMU_TOL = _bar("dmu")
+
+
+def rel_own(x, ref):
+    """max |x - ref| / max |ref|: the error of a series against its own maximum."""
+    x, ref = np.asarray(x), np.asarray(ref)
+    return float(np.abs(x - ref).max() / np.abs(ref).max())

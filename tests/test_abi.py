@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings(lib):
-    for code in (0, -1, -2, -3, -4, -5, -6, 1, 2, 3, 4):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1, 2, 3, 4):
         assert lib.ltd_status_string(code).decode()
     assert lib.ltd_status_string(0).decode() == "ok"
 
@@ -145,3 +145,21 @@ def test_calls_before_binding_are_rejected(lib, sys0):
     assert lib.ltd_bind_workspace(h, None, wsb.value, None) == _lib.LTD_EINVAL
     assert lib.ltd_subspace_info(h, 0, None, None, None) == _lib.LTD_ESTATE
     assert lib.ltd_destroy(h) == 0
+
+
+def test_pulse_and_spectrum_argument_checks(lib):
+    """Host-side rejections of the pulse and polarizability entry points (nothing
+    is launched: the pointers are never dereferenced)."""
+    fake = C.c_void_p(0x1000)
+    prm = (C.c_double * 4)(1.0, 0.3, 0.0, 10.0)
+    assert lib.ltd_pulse_samples(7, prm, 0.1, 10, fake, fake, None) == _lib.LTD_EINVAL
+    assert lib.ltd_pulse_samples(_lib.LTD_PULSE_SIN2, None, 0.1, 10, fake, fake, None) == _lib.LTD_EINVAL
+    assert lib.ltd_pulse_samples(_lib.LTD_PULSE_SIN2, prm, 0.1, 0, fake, fake, None) == _lib.LTD_ESHAPE
+    bad = (C.c_double * 4)(1.0, 0.3, 0.0, -1.0)
+    assert lib.ltd_pulse_samples(_lib.LTD_PULSE_SIN2, bad, 0.1, 10, fake, fake, None) == _lib.LTD_EINVAL
+    nan = (C.c_double * 4)(float("nan"), 0.3, 0.0, 1.0)
+    assert lib.ltd_pulse_samples(_lib.LTD_PULSE_GAUSS_SIN, nan, 0.1, 10, fake, fake, None) == _lib.LTD_EINVAL
+    assert lib.ltd_polarizability(fake, fake, 10, 0.1, 1.0, 137.0, fake, 0, 0.0, fake, None) == _lib.LTD_ESHAPE
+    assert lib.ltd_polarizability(fake, fake, 10, 0.1, 1.0, 137.0, fake, 5, -1.0, fake, None) == _lib.LTD_EINVAL
+    assert lib.ltd_polarizability(fake, fake, 10, 0.1, 1.0, 137.0, fake, 5, 0.0, C.c_void_p(0x1008),
+                                  None) == _lib.LTD_EALIGN

@@ -18,7 +18,7 @@ import pytest
 
 from oracle import propagate as pr
 from oracle import subspace as ss
-from tests.bounds import dmu_bound
+from tests.bounds import DMU_TOL, JIND_TOL, rel_own
 from synth import make_system, pulse_samples, td_potential
 
 pytestmark = pytest.mark.gpu
@@ -94,7 +94,10 @@ def test_batched_propagation_matches_oracle(w3):
     assert rel_max(gj, j) < TOL
     assert rel_max(ge, e) < TOL
     assert worst < TOL
-    assert np.abs(gd - dmu).max() < dmu_bound(j, sys.dt, sys.omega)
+    print(f"batched 16 k: J_ind {rel_own(gj - gj[0], j - j[0]):.2e} (bar {JIND_TOL:.1e}) "
+          f"dmu {rel_own(gd, dmu):.2e} (bar {DMU_TOL:.1e})", flush=True)
+    assert rel_own(gj - gj[0], j - j[0]) < JIND_TOL
+    assert rel_own(gd, dmu) < DMU_TOL
 
 
 def test_batched_rebuild_with_new_potential(w3):

@@ -21,7 +21,7 @@ import pytest
 
 from oracle import propagate as pr
 from oracle import subspace as ss
-from tests.bounds import dmu_bound
+from tests.bounds import DMU_TOL, JIND_TOL
 from synth import make_system, pulse_samples, td_potential
 
 pytestmark = pytest.mark.gpu
@@ -130,5 +130,5 @@ def test_fp32_residual_full_size_1000_steps():
               f"dmu {errs[prec][2]:.2e} theta {errs[prec][3]:.2e}", flush=True)
         del lt
     assert errs["LTD_FP64"][0] < 1e-10 and errs["LTD_FP64"][3] < 1e-10
-    assert errs["LTD_FP64"][4] < dmu_bound(ref["J"], sys.dt, sys.omega)
+    assert errs["LTD_FP64"][1] < JIND_TOL and errs["LTD_FP64"][2] < DMU_TOL
     assert max(errs["LTD_FP32_RESID"][:3]) < MIXED_TOL

@@ -12,7 +12,7 @@ from oracle import adjoint as ad
 from oracle import operators as op
 from oracle import propagate as pr
 from oracle import subspace as ss
-from tests.bounds import dmu_bound, jind_bound
+from tests.bounds import DMU_TOL, JIND_TOL, rel_own
 from synth import make_system, pulse_samples
 from synth.lapw_inputs import knot_times, knot_values
 
@@ -170,11 +170,13 @@ def test_propagation_matches_oracle(cfg0, mode):
           f"dmu {rel_max(dmu, ref['dmu']):.2e} theta {rel_max(th, ref['theta']):.2e}", flush=True)
     assert rel_max(j, ref["J"]) < TOL
     assert rel_max(e, ref["E"]) < TOL
-    assert np.abs(dmu - ref["dmu"]).max() < dmu_bound(ref["J"], sys.dt, sys.omega)
     assert rel_max(th, ref["theta"]) < TOL
-    # the induced current itself (J - J0) relative to its own size
+    # the induced current (J - J0) and the dipole change, each against its own maximum
     ji, jr = j - j[0], ref["J"] - ref["J"][0]
-    assert np.abs(ji - jr).max() < jind_bound(ref["J"])
+    print(f"{mode}: J_ind {rel_own(ji, jr):.2e} (bar {JIND_TOL:.1e}) dmu {rel_own(dmu, ref['dmu']):.2e} "
+          f"(bar {DMU_TOL:.1e})", flush=True)
+    assert rel_own(ji, jr) < JIND_TOL
+    assert rel_own(dmu, ref["dmu"]) < DMU_TOL
 
 
 def test_graph_replay_equals_stepwise(cfg0):
