@@ -127,6 +127,24 @@ ltd_status ltd_sync_status(ltd_system *sys, void *stream);
 ltd_status ltd_apply_HS(ltd_system *sys, int k, const double a_vec[3], const void *C, int ldc,
                         int n, void *HC, int ldhc, void *SC, int ldsc, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same HC = H(t) C,
+ * SC = S C as ltd_apply_HS (same arguments, same kernels), with every scratch
+ * buffer of the apply (FFT slabs, muffin-tin vectors and products, effective
+ * blocks, GEMM partial sums) taken from a fixed array of
+ * LTD_STATIC_SCRATCH_BYTES in the library, one per device, held until the
+ * process ends, instead of the bound workspace.  Nothing is allocated or freed.
+ * Columns are processed in passes that fit the array; when not even one column
+ * fits (an FFT slab of 9 x nbz x N1 x N2 complex values per column plus the
+ * blocks) the call returns LTD_EUNSUPPORTED and enqueues nothing.  The system
+ * must be bound (its read-only tables stay in the workspace).  Every call on a
+ * device shares that device's array: calls that overlap on one device (several
+ * streams or host threads) race and must be serialised by the caller.  n has no
+ * max_cols limit. */
+#define LTD_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+ltd_status ltd_apply_HS_static(ltd_system *sys, int k, const double a_vec[3], const void *C, int ldc,
+                               int n, void *HC, int ldhc, void *SC, int ldsc, void *stream);
+
 /* Binds the auxiliary basis Phi (N_basis(k) x n_aux, ld ldphi; caller-owned,
  * must stay valid and unchanged while the system propagates k) and prepares
  * the subspace (Sec. 2.2, Eq. (14); Sec. 2.3, Eqs. (15)-(16)): applies T, V,

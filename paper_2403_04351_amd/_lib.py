@@ -32,7 +32,7 @@ LTD_STEP_AFFINE = 1
 
 EXPORTED = [
     "ltd_create", "ltd_bind_workspace", "ltd_destroy", "ltd_status_string", "ltd_sync_status",
-    "ltd_apply_HS", "ltd_project_subspace", "ltd_ritz_basis", "ltd_subspace_info",
+    "ltd_apply_HS", "ltd_apply_HS_static", "ltd_project_subspace", "ltd_ritz_basis", "ltd_subspace_info",
     "ltd_propagate_step", "ltd_propagate", "ltd_propagate_prepare", "ltd_propagate_step_adjoint", "ltd_knot_samples",
     "ltd_knot_gradient", "ltd_chebyshev_coefficients", "ltd_profile_steps", "ltd_profile_apply",
     "ltd_rebuild_grid", "ltd_autotune", "ltd_set_tuning", "ltd_state_drift",
@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH):
     lib.ltd_status_string.restype = C.c_char_p
     lib.ltd_sync_status.argtypes = [vp, vp]
     lib.ltd_apply_HS.argtypes = [vp, ip, dp, vp, ip, ip, vp, ip, vp, ip, vp]
+    lib.ltd_apply_HS_static.argtypes = [vp, ip, dp, vp, ip, ip, vp, ip, vp, ip, vp]
     lib.ltd_project_subspace.argtypes = [vp, ip, vp, ip, ip, vp, vp, vp, ip, ip, vp, vp]
     lib.ltd_ritz_basis.argtypes = [vp, ip, vp, ip, vp, vp]
     lib.ltd_subspace_info.argtypes = [vp, ip, dp, dp, dp]

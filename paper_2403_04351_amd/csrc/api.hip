@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -541,6 +542,60 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   }
   LTD_MARK(pf, 5);
   return LTD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free apply: the scratch of ltd_apply_HS_static is this array (one
+// copy per device, held until the process ends), never the bound workspace.
+// Host code uses only the device address hipGetSymbolAddress returns for it,
+// looked up once per device (at bind, else at the entry point's first call).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[LTD_STATIC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+constexpr long long STATIC_PART_TILES = 64;  // split-K partial tiles within the scratch (4 MiB)
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// the device address of `scratch` on the current device (NULL on failure)
+char *static_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Columns per pass of an apply whose scratch is the static array (0: not even one
+// column fits), and the buffers of such a pass laid out from `base`.
+int static_cols(const ltd_system *sys, int n) {
+  const long long slab_col = (long long)sys->grid.nbz * sys->n1 * sys->n2;
+  const size_t fixed = up((size_t)std::max<long long>(1, sys->blk_elems) * sizeof(double2)) +
+                       up((size_t)STATIC_PART_TILES * 64 * 64 * sizeof(double2));
+  // per column: 4 + 5 slab fields, W and two Y blocks, plus alignment slack of four arrays
+  const size_t per_col = (size_t)(9 * slab_col + 3LL * sys->n_loc) * sizeof(double2);
+  if (fixed + 4 * ALIGN + per_col > LTD_STATIC_SCRATCH_BYTES) return 0;
+  const size_t c = (LTD_STATIC_SCRATCH_BYTES - fixed - 4 * ALIGN) / per_col;
+  return (int)std::min<size_t>(c, (size_t)n);
+}
+
+ApplyBufs static_bufs(const ltd_system *sys, char *base, int cols) {
+  const long long slab_f = (long long)sys->grid.nbz * sys->n1 * sys->n2 * cols;
+  Arena ar;
+  ApplyBufs b{};
+  b.slab_in = reinterpret_cast<double2 *>(base + ar.take((size_t)4 * slab_f * sizeof(double2)));
+  b.slab_out = reinterpret_cast<double2 *>(base + ar.take((size_t)5 * slab_f * sizeof(double2)));
+  b.W = reinterpret_cast<double2 *>(base + ar.take((size_t)sys->n_loc * cols * sizeof(double2)));
+  b.Y = reinterpret_cast<double2 *>(base + ar.take((size_t)2 * sys->n_loc * cols * sizeof(double2)));
+  b.heff = reinterpret_cast<double2 *>(base + ar.take((size_t)std::max<long long>(1, sys->blk_elems) * sizeof(double2)));
+  b.part = reinterpret_cast<double2 *>(base + ar.take((size_t)STATIC_PART_TILES * 64 * 64 * sizeof(double2)));
+  b.ystride = (long long)sys->n_loc * cols;
+  b.part_tiles = STATIC_PART_TILES;
+  b.k2_tables = false;
+  return b;
 }
 
 ltd_status apply_cols(ltd_system *sys, int k, int mode, double a_z, const double2 *C, int ldc, int n,
@@ -1327,6 +1382,7 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
   hipStream_t s = S(stream);
   fft_init_attrs();
   subspace_init_attrs();
+  if (!static_scratch()) return LTD_EHIP;  // the allocation-free apply's array on this device
   if (!sys->side) {
     LTD_HIP(hipStreamCreateWithFlags(&sys->side, hipStreamNonBlocking));
     LTD_HIP(hipEventCreateWithFlags(&sys->ev_fork, hipEventDisableTiming));
@@ -1468,6 +1524,36 @@ ltd_status ltd_apply_HS(ltd_system *sys, int k, const double a_vec[3], const voi
   double2 *outs[4] = {reinterpret_cast<double2 *>(HC), reinterpret_cast<double2 *>(SC), nullptr, nullptr};
   const int ldo[4] = {ldhc, ldsc, 0, 0};
   return apply_cols(sys, k, FFT_MODE_HS, a_vec[2], reinterpret_cast<const double2 *>(C), ldc, n, outs, ldo, S(stream));
+}
+
+ltd_status ltd_apply_HS_static(ltd_system *sys, int k, const double a_vec[3], const void *C, int ldc, int n,
+                               void *HC, int ldhc, void *SC, int ldsc, void *stream) {
+  if (!sys || !a_vec) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  if (k < 0 || k >= sys->n_k || n < 0) return LTD_ESHAPE;
+  if (n == 0) return LTD_OK;
+  if (!C || !HC || !SC) return LTD_EINVAL;
+  if (!std::isfinite(a_vec[0]) || !std::isfinite(a_vec[1]) || !std::isfinite(a_vec[2])) return LTD_EINVAL;
+  if (a_vec[0] != 0.0 || a_vec[1] != 0.0) return LTD_EUNSUPPORTED;
+  const int nb = sys->kh[k].n_basis;
+  if (ldc < nb || ldhc < nb || ldsc < nb) return LTD_ESHAPE;
+  if (!aligned16(C) || !aligned16(HC) || !aligned16(SC)) return LTD_EALIGN;
+  if (HC == C || SC == C || HC == SC) return LTD_EINVAL;
+  const int cmax = static_cols(sys, n);
+  if (cmax < 1) return LTD_EUNSUPPORTED;  // one column's scratch exceeds LTD_STATIC_SCRATCH_BYTES
+  char *base = static_scratch();
+  if (!base) return LTD_EHIP;
+  hipStream_t s = S(stream);
+  const double2 *c = reinterpret_cast<const double2 *>(C);
+  double2 *hc = reinterpret_cast<double2 *>(HC), *sc = reinterpret_cast<double2 *>(SC);
+  const int ldo[4] = {ldhc, ldsc, 0, 0};
+  for (int j0 = 0; j0 < n; j0 += cmax) {
+    const int cols = std::min(cmax, n - j0);
+    double2 *o[4] = {hc + (long long)j0 * ldhc, sc + (long long)j0 * ldsc, nullptr, nullptr};
+    LTD_TRY(apply_chunk(sys, k, FFT_MODE_HS, a_vec[2], c + (long long)j0 * ldc, ldc, cols, o, ldo, s, nullptr,
+                        static_bufs(sys, base, cols)));
+  }
+  return LTD_OK;
 }
 
 ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldphi, int n_aux, void *h0_sub,
