@@ -90,7 +90,14 @@ typedef struct {
   int n_aux;               /* auxiliary-subspace dimension N_aux (all k) */
   int n_states;            /* propagated states N_states <= n_aux (all k) */
   int max_cols;            /* most columns ever passed to ltd_apply_HS */
+  int interstitial_route;  /* LTD_ROUTE_FFT (0): the interstitial plane-wave blocks applied by FFT
+                              convolution with the step function (Sec. 2.3, second route);
+                              LTD_ROUTE_MM (1): as dense N_G x N_G matrices of Fourier coefficients
+                              at G - G' applied by GEMM (Sec. 2.3, first route; App. A, Eq. (A.7)):
+                              five N_G^2 complex128 matrices per k-point in the workspace, FP64 only */
 } ltd_system_desc;
+
+enum { LTD_ROUTE_FFT = 0, LTD_ROUTE_MM = 1 };
 
 /* Validates the description, copies its host arrays and plans every kernel;
  * returns in *workspace_bytes the device workspace the caller must bind.
@@ -239,6 +246,12 @@ typedef struct {
                              f sum_k w_k sum_j (|theta_j|_S^2 - sum_{i < N_states} |<phi_i|S|psi_j>|^2),
                              the states' weight outside the first N_states auxiliary functions
                              (Secs. 3.2-3.3); NULL skips */
+  void *theta_hist;       /* optional: before step n the states theta_n are copied to slot
+                             n mod hist_len of this buffer (hist_len slots of n_k x n_states x
+                             n_aux complex128, the layout of theta): the recomputed segment of a
+                             checkpointed backward pass, recorded inside the replayed graph;
+                             NULL skips */
+  int hist_len;           /* slots of theta_hist (>= 1 when it is set) */
 } ltd_step_args;
 
 /* One time step n -> n+1 for every k-point (Sec. 2.2, Eqs. (12)-(13); Sec. 2.3
@@ -284,6 +297,11 @@ typedef struct {
   double *dl_da_mid;        /* [N]   entry n: dL/dA(t_n + dt/2) */
   double *dl_da_t;          /* [N+1] entry n: explicit dL/dA(t_n) */
 } ltd_adjoint_args;
+
+/* The loss of the pulse-gradient workload, L = dt sum_n w_n (J_n - J_0) =
+ * delta mu(T) / Omega (Eq. (4), trapezoid weights): *loss = dmu[n_steps] / Omega
+ * on the device, dmu the dipole series a propagation of n_steps wrote. */
+ltd_status ltd_pulse_loss(ltd_system *sys, const double *dmu, int n_steps, double *loss, void *stream);
 
 /* One step of the discrete adjoint of ltd_propagate_step for the loss
  * L = dt sum_n w_n (J_n - J_0) (trapezoid weights; L = delta mu(T)/Omega by

@@ -27,6 +27,8 @@ LTD_BF16X3_RESID = 2
 LTD_PULSE_GAUSS_SIN = 0
 LTD_PULSE_SIN2 = 1
 LTD_PULSE_KICK = 2
+LTD_ROUTE_FFT = 0
+LTD_ROUTE_MM = 1
 LTD_STEP_REBUILD = 0
 LTD_STEP_AFFINE = 1
 
@@ -36,7 +38,7 @@ EXPORTED = [
     "ltd_propagate_step", "ltd_propagate", "ltd_propagate_prepare", "ltd_propagate_step_adjoint", "ltd_knot_samples",
     "ltd_knot_gradient", "ltd_chebyshev_coefficients", "ltd_profile_steps", "ltd_profile_apply",
     "ltd_rebuild_grid", "ltd_autotune", "ltd_set_tuning", "ltd_state_drift",
-    "ltd_pulse_samples", "ltd_polarizability",
+    "ltd_pulse_samples", "ltd_polarizability", "ltd_pulse_loss",
 ]
 LTD_PROFILE_STAGES = 8
 
@@ -64,6 +66,7 @@ class SystemDesc(C.Structure):
         ("n_aux", C.c_int),
         ("n_states", C.c_int),
         ("max_cols", C.c_int),
+        ("interstitial_route", C.c_int),
     ]
 
 
@@ -85,6 +88,8 @@ class StepArgs(C.Structure):
         ("h_stride", C.c_longlong),
         ("taylor_order", C.c_int),
         ("nexc_out", C.c_void_p),
+        ("theta_hist", C.c_void_p),
+        ("hist_len", C.c_int),
     ]
 
 
@@ -135,6 +140,7 @@ def load(path: str = LIB_PATH):
     lib.ltd_propagate_step_adjoint.argtypes = [vp, C.POINTER(AdjointArgs), vp]
     lib.ltd_knot_samples.argtypes = [vp, ip, C.c_double, C.c_double, ip, vp, vp, vp]
     lib.ltd_knot_gradient.argtypes = [vp, vp, ip, C.c_double, ip, C.c_double, vp, vp]
+    lib.ltd_pulse_loss.argtypes = [vp, vp, ip, vp, vp]
     lib.ltd_pulse_samples.argtypes = [ip, dp, C.c_double, ip, vp, vp, vp]
     lib.ltd_polarizability.argtypes = [vp, vp, ip, C.c_double, C.c_double, C.c_double, vp, ip, C.c_double, vp, vp]
     lib.ltd_chebyshev_coefficients.argtypes = [C.c_double, ip, dp, C.POINTER(ip)]

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libltd.so")
-SOURCES = ["gemm.hip", "fft.hip", "subspace.hip", "api.hip", "observables.hip"]
+SOURCES = ["gemm.hip", "fft.hip", "mm.hip", "subspace.hip", "api.hip", "observables.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -58,6 +58,10 @@ struct KHost {
   size_t o_L, o_Linv, o_LH, o_LinvH, o_vstep, o_work, o_hm, o_dev;
   size_t o_phit, o_yext, o_cache;
   size_t o_phit32 = 0, o_yext32 = 0;  // FP32 residual: complex64 Phi~_ext (atom-contiguous MT rows) and Y_ext
+  // matrix-matrix route: G triples on the device and the dense interstitial
+  // blocks T, V (reference potential), P_z, S (natural G order) and V of the step
+  // (sphere-table order, the row order of Phi~_ext)
+  size_t o_gint = 0, o_mmT = 0, o_mmV = 0, o_mmP = 0, o_mmS = 0, o_mmVt = 0;
   // bound subspace
   bool bound = false;
   const double2 *phi = nullptr;
@@ -84,6 +88,8 @@ struct ltd_system {
   double omega = 0, c_light = 0, occ = 0;
   std::vector<double> kw;
   int n_aux = 0, n_states = 0, max_cols = 0, precision = 0;
+  int route = LTD_ROUTE_FFT;  // interstitial route
+  size_t o_box_t = 0, o_box_v = 0, o_box_step = 0, o_box_scr = 0;  // MM: Fourier coefficient boxes
   int nb_max = 0;
   // grid plan; rgrid: the grid of the per-step rebuild (same box, lengths
   // >= 4 b + 1), with W synthesised from Theta V when it is smaller
@@ -445,6 +451,40 @@ struct ApplyBufs {
   bool k2_tables;
 };
 
+ltd_status apply_mt(ltd_system *sys, int k, int mode, double al, double be, const double2 *C, int ldc, int cols,
+                    double2 *const out[4], const int ldo[4], hipStream_t s, Prof *pf, const ApplyBufs &bf);
+
+// Interstitial part of an apply by the dense blocks: HS mode H(A) C = T C + V C +
+// (A/c) P C + (A^2/2c^2) S C and S C; TVPS mode T C, V C, P C, S C (plane-wave
+// rows of out, overwritten).  Problems that add into one output run in
+// successive launches.
+ltd_status apply_mm(ltd_system *sys, int k, int mode, double al, double be, const double2 *C, int ldc, int cols,
+                    double2 *const out[4], const int ldo[4], const ApplyBufs &bf, hipStream_t s) {
+  const KHost &kh = sys->kh[k];
+  const int ng = kh.n_g;
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  const auto blk = [&](size_t off) { return sys->at<double2>(off); };
+  if (mode == FFT_MODE_TVPS) {
+    const size_t m[4] = {kh.o_mmT, kh.o_mmV, kh.o_mmP, kh.o_mmS};
+    std::vector<ZProb> p;
+    for (int x = 0; x < 4; ++x) p.push_back(zp(ng, cols, ng, blk(m[x]), ng, C, ldc, out[x], ldo[x]));
+    return gemm_buf(OP_N, OP_N, p, bf.part, bf.part_tiles, s);
+  }
+  LTD_TRY(gemm_buf(OP_N, OP_N, {zp(ng, cols, ng, blk(kh.o_mmT), ng, C, ldc, out[0], ldo[0]),
+                                zp(ng, cols, ng, blk(kh.o_mmS), ng, C, ldc, out[1], ldo[1])},
+                   bf.part, bf.part_tiles, s));
+  LTD_TRY(gemm_buf(OP_N, OP_N, {zp(ng, cols, ng, blk(kh.o_mmV), ng, C, ldc, out[0], ldo[0], one, one)}, bf.part,
+                   bf.part_tiles, s));
+  if (al != 0.0)
+    LTD_TRY(gemm_buf(OP_N, OP_N, {zp(ng, cols, ng, blk(kh.o_mmP), ng, C, ldc, out[0], ldo[0], make_double2(al, 0.0),
+                                     one)}, bf.part, bf.part_tiles, s));
+  if (be != 0.0)
+    LTD_TRY(gemm_buf(OP_N, OP_N, {zp(ng, cols, ng, blk(kh.o_mmS), ng, C, ldc, out[0], ldo[0], make_double2(be, 0.0),
+                                     one)}, bf.part, bf.part_tiles, s));
+  (void)zero;
+  return LTD_OK;
+}
+
 ApplyBufs workspace_bufs(const ltd_system *sys) {
   ApplyBufs b{};
   b.slab_in = sys->at<double2>(sys->o_slab_in);
@@ -465,6 +505,11 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   const KHost &kh = sys->kh[k];
   const Grid g = grid_of(sys);
   const double al = a_z / sys->c_light, be = a_z * a_z / (2.0 * sys->c_light * sys->c_light);
+  if (sys->route == LTD_ROUTE_MM) {  // interstitial by the dense blocks (first route)
+    LTD_TRY(apply_mm(sys, k, mode, al, be, C, ldc, cols, out, ldo, bf, s));
+    LTD_MARK(pf, 2);
+    return apply_mt(sys, k, mode, al, be, C, ldc, cols, out, ldo, s, pf, bf);
+  }
   // interstitial
   FftKArgs ka{};
   ka.sph[0] = sphere_of(sys, k);
@@ -492,6 +537,14 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   ka.out[0] = fo;
   LTD_HIP(fft_forward_planes(g, ka, 1, cols, mode, al, be, s));
   LTD_MARK(pf, 2);
+  return apply_mt(sys, k, mode, al, be, C, ldc, cols, out, ldo, s, pf, bf);
+}
+
+// Muffin-tin and local-orbital part of an apply (accumulated into out, whose
+// plane-wave rows hold the interstitial part).
+ltd_status apply_mt(ltd_system *sys, int k, int mode, double al, double be, const double2 *C, int ldc, int cols,
+                    double2 *const out[4], const int ldo[4], hipStream_t s, Prof *pf, const ApplyBufs &bf) {
+  const KHost &kh = sys->kh[k];
   // muffin-tin chain: W = [A C_G; C_LO]
   double2 *W = bf.W;
   double2 *Y = bf.Y;
@@ -808,6 +861,32 @@ ltd_status step_blocks(ltd_system *sys, const ltd_step_args *a, const int *step,
   return run_k2(sys, sys->k2_step, n, s);
 }
 
+// Matrix-matrix route of the step's interstitial rows of Y_ext: the Fourier
+// coefficients of Theta V(t) in the box of G differences, the dense block
+// (Theta V(t))~(g - g') in the sphere-table order of Phi~_ext's rows, and
+// Y_G = V^I(t) Phi~_G (GEMM), for every k-point.
+ltd_status rebuild_v_mm(ltd_system *sys, const double *v, const int *step, long long stride, hipStream_t s,
+                        Prof *pf) {
+  const Grid g = grid_of(sys);
+  const int n = sys->n_aux;
+  double2 *box = sys->at<double2>(sys->o_box_step);
+  LTD_HIP(mm_box_coefficients(g, sys->theta, v, step, stride, sys->at<double2>(sys->o_box_scr), box, s));
+  LTD_MARK(pf, 0);
+  std::vector<ZProb> py;
+  for (int k = 0; k < sys->n_k; ++k) {
+    const KHost &kh = sys->kh[k];
+    double2 *vt = sys->at<double2>(kh.o_mmVt);
+    LTD_HIP(mm_dense(2, g, sys->at<int>(kh.o_gint), sys->at<double>(kh.o_gk), sys->at<int>(kh.o_ptsg), kh.n_g,
+                     nullptr, box, vt, kh.n_g, s));
+    py.push_back(zp(kh.n_g, n, kh.n_g, vt, kh.n_g, sys->at<double2>(kh.o_phit), kh.k_ext,
+                    sys->at<double2>(kh.o_yext), kh.k_ext));
+  }
+  LTD_MARK(pf, 1);
+  LTD_TRY(gemm(sys, OP_N, OP_N, py, s));
+  LTD_MARK(pf, 2);
+  return LTD_OK;
+}
+
 // host_step >= 0: the step index is known on the host (adjoint); otherwise the
 // series are indexed by the device step counter.
 ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Prof *pf = nullptr,
@@ -835,6 +914,15 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
     LTD_TRY(step_blocks(sys, a, hstep, hoff, n, sb));
     LTD_HIP(hipEventRecord(sys->ev_join, sb));
   }
+  if (sys->route == LTD_ROUTE_MM) {  // interstitial V_sub(t) by the dense block of the step's potential
+    const double *v = a->v_r_t ? a->v_r_t : sys->v_r;
+    const int *dstep = nullptr;
+    if (a->v_r_t && a->v_stride) {
+      if (host_step >= 0) v += (long long)host_step * a->v_stride;
+      else dstep = a->step;
+    }
+    LTD_TRY(rebuild_v_mm(sys, v, dstep, a->v_stride, s, pf));
+  } else {
   const void *thv = r32 ? static_cast<const void *>(sys->at<float>(sys->o_zero32))
                         : static_cast<const void *>(sys->at<double>(sys->o_thv_rb));
   if (a->v_r_t) {
@@ -870,6 +958,7 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
     for (int i = 0; i < nk; ++i) ka.slab_in[i] = ka.slab_out[i];
     LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1, r32, 0));
     LTD_MARK(pf, 2);
+  }
   }
   if (fork) LTD_HIP(hipStreamWaitEvent(s, sys->ev_join, 0));
   else LTD_TRY(step_blocks(sys, a, hstep, hoff, n, s));
@@ -931,6 +1020,8 @@ ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s
       LTD_HIP(hipStreamWaitEvent(sys->side2, sys->ev_p0, 0));
       LTD_TRY(project_v(sys, sys->side2, 2));
       LTD_HIP(launch_assemble(exp_ctx, sys->side2));
+      if (a->theta_hist)  // the states before the step, for a checkpointed backward pass
+        LTD_HIP(launch_record_theta(exp_ctx, reinterpret_cast<double2 *>(a->theta_hist), a->hist_len, sys->side2));
       LTD_HIP(hipEventRecord(sys->ev_asm, sys->side2));
       LTD_HIP(launch_step_only(exp_ctx, sys->side2));
     }
@@ -982,6 +1073,7 @@ ltd_status check_step_args(ltd_system *sys, const ltd_step_args *a) {
   if (a->v_stride && a->v_stride < sys->ngrid) return LTD_ESHAPE;
   if (a->h_stride && a->h_stride < sys->blk_elems) return LTD_ESHAPE;
   if (a->taylor_order < 0 || a->taylor_order > TAYLOR_MAX) return LTD_EINVAL;
+  if (a->theta_hist && (a->hist_len < 1 || !aligned16(a->theta_hist))) return a->hist_len < 1 ? LTD_ESHAPE : LTD_EALIGN;
   if (a->taylor_order > 0)  // the explicit step diverges beyond the critical time step (Eq. (20))
     for (int k = 0; k < sys->n_k; ++k)
       if (std::fabs(a->dt) > 0.2 / (sys->kh[k].lam_max - sys->kh[k].lam_min)) return LTD_ESTEP;
@@ -1032,6 +1124,8 @@ ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s
 
 ltd_status step_once(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Prof *pf = nullptr) {
   if (a->mode == LTD_STEP_REBUILD) LTD_TRY(rebuild_v(sys, a, s, pf));
+  if (a->theta_hist)
+    LTD_HIP(launch_record_theta(step_ctx(sys, a), reinterpret_cast<double2 *>(a->theta_hist), a->hist_len, s));
   LTD_HIP(launch_step(step_ctx(sys, a), s));
   LTD_MARK(pf, 5);
   LTD_TRY(map_back(sys, a, s));
@@ -1127,6 +1221,8 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   if (!aligned16(d->amat) || (d->n_atoms > 0 && (!aligned16(d->h) || !aligned16(d->o) || !aligned16(d->pz))))
     return LTD_EALIGN;
   if (d->n_aux > 320) return LTD_EUNSUPPORTED;
+  if (d->interstitial_route != LTD_ROUTE_FFT && d->interstitial_route != LTD_ROUTE_MM) return LTD_EINVAL;
+  if (d->interstitial_route == LTD_ROUTE_MM && precision != LTD_FP64) return LTD_EUNSUPPORTED;
   auto *sys = new ltd_system();
   sys->n_k = d->n_k;
   sys->n1 = d->grid[0];
@@ -1176,6 +1272,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->n_states = d->n_states;
   sys->max_cols = d->max_cols;
   sys->precision = precision;
+  sys->route = d->interstitial_route;
   // G sets, box, sphere tables
   long long gtot = 0;
   int bx = 0, by = 0, bz = 0;
@@ -1290,7 +1387,8 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_part = ar.take((size_t)PART_STRIDE * sys->n_k * sys->n_states * sizeof(double));
   sys->o_partials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
   sys->o_vpartials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
-  const long long slab_f = (long long)g.nbz * g.n1 * g.n2 * sys->chunk;
+  const bool mm = sys->route == LTD_ROUTE_MM;
+  const long long slab_f = mm ? 0 : (long long)g.nbz * g.n1 * g.n2 * sys->chunk;
   sys->o_slab_in = ar.take(4 * slab_f * sizeof(double2));
   sys->o_slab_out = ar.take(5 * slab_f * sizeof(double2));
   sys->o_W = ar.take((size_t)sys->n_loc * sys->chunk * sizeof(double2));
@@ -1304,7 +1402,13 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_eigV = ar.take((size_t)n2 * sizeof(double2));
   sys->o_eigw = ar.take((size_t)n * sizeof(double));
   sys->o_k6 = ar.take((size_t)sys->nb_max * n * sizeof(double2));
-  sys->o_stepslab = ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * fft_rb_slab_values(sys->rgrid) * n * rb_elem(sys));
+  sys->o_stepslab = mm ? 0 : ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * fft_rb_slab_values(sys->rgrid) * n * rb_elem(sys));
+  if (mm) {
+    sys->o_box_t = ar.take(mm_box_values(g) * sizeof(double2));
+    sys->o_box_v = ar.take(mm_box_values(g) * sizeof(double2));
+    sys->o_box_step = ar.take(mm_box_values(g) * sizeof(double2));
+    sys->o_box_scr = ar.take(mm_box_scratch(g) * sizeof(double2));
+  }
   sys->o_zero32 = resid32(sys) ? ar.take((size_t)sys->ngrid * sizeof(float)) : 0;
   if (sys->rb_synth) {
     const Grid &r = sys->rgrid;
@@ -1360,7 +1464,16 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     kh.o_work = sys->h_in_lds ? 0 : ar.take((size_t)sys->n_states * n2 * sizeof(double2));
     kh.o_phit = ar.take((size_t)kh.k_ext * n * sizeof(double2));
     kh.o_yext = ar.take((size_t)kh.k_ext * n * sizeof(double2));
-    kh.o_cache = ar.take(fft_rb_slab_values(sys->rgrid) * n * rb_elem(sys));
+    kh.o_cache = mm ? 0 : ar.take(fft_rb_slab_values(sys->rgrid) * n * rb_elem(sys));
+    if (mm) {
+      const size_t m2 = (size_t)kh.n_g * kh.n_g * sizeof(double2);
+      kh.o_gint = ar.take((size_t)3 * kh.n_g * sizeof(int));
+      kh.o_mmT = ar.take(m2);
+      kh.o_mmV = ar.take(m2);
+      kh.o_mmP = ar.take(m2);
+      kh.o_mmS = ar.take(m2);
+      kh.o_mmVt = ar.take(m2);
+    }
     if (resid32(sys)) {
       kh.o_phit32 = ar.take((size_t)kh.k_ext * n * sizeof(float2));
       kh.o_yext32 = ar.take((size_t)kh.k_ext * n * sizeof(float2));
@@ -1453,7 +1566,24 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
     LTD_HIP(hipMemcpy(sys->ws + sys->o_mtperm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
   }
   LTD_HIP(launch_thv(sys->at<double>(sys->o_thv), sys->theta, sys->v_r, sys->ngrid, s));
-  LTD_TRY(rebuild_potential(sys, sys->v_r, nullptr, 0, sys->at<double>(sys->o_thv_rb), false, s));
+  if (sys->route == LTD_ROUTE_FFT) {
+    LTD_TRY(rebuild_potential(sys, sys->v_r, nullptr, 0, sys->at<double>(sys->o_thv_rb), false, s));
+  } else {  // the dense interstitial blocks of every k-point (natural G order)
+    const Grid g = grid_of(sys);
+    double2 *bt = sys->at<double2>(sys->o_box_t), *bv = sys->at<double2>(sys->o_box_v);
+    LTD_HIP(mm_box_coefficients(g, sys->theta, nullptr, nullptr, 0, sys->at<double2>(sys->o_box_scr), bt, s));
+    LTD_HIP(mm_box_coefficients(g, sys->theta, sys->v_r, nullptr, 0, sys->at<double2>(sys->o_box_scr), bv, s));
+    for (int k = 0; k < sys->n_k; ++k) {
+      KHost &kh = sys->kh[k];
+      LTD_HIP(hipMemcpy(sys->ws + kh.o_gint, &sys->g_int[3 * kh.g_off], 3 * kh.n_g * sizeof(int),
+                        hipMemcpyHostToDevice));
+      const int *gi = sys->at<int>(kh.o_gint);
+      const double *gkd = sys->at<double>(kh.o_gk);
+      const size_t outs[4] = {kh.o_mmS, kh.o_mmT, kh.o_mmV, kh.o_mmP};
+      for (int w = 0; w < 4; ++w)
+        LTD_HIP(mm_dense(w, g, gi, gkd, nullptr, kh.n_g, bt, bv, sys->at<double2>(outs[w]), kh.n_g, s));
+    }
+  }
   if (resid32(sys)) LTD_HIP(hipMemsetAsync(sys->ws + sys->o_zero32, 0, sys->ngrid * sizeof(float), s));
   // K2 tables of the apply chunk
   double2 *W = sys->at<double2>(sys->o_W), *Y = sys->at<double2>(sys->o_Y);
@@ -1589,7 +1719,7 @@ ltd_status ltd_project_subspace(ltd_system *sys, int k, const void *phi, int ldp
   if (sys->n_lo_tot > 0)
     LTD_HIP(launch_copy_rows(pe + kh.n_g + sys->n_a, kh.k_ext, pt + kh.n_g, sys->nb_max, sys->n_lo_tot, n, false, s));
   // cached plane-wave part of Phi~, transformed along y only (box in x and z)
-  {
+  if (sys->route == LTD_ROUTE_FFT) {
     FftKArgs ka{};
     ka.sph[0] = sphere_of(sys, k);
     ka.in[0].c = pe;
@@ -1729,7 +1859,8 @@ ltd_status ltd_autotune(ltd_system *sys, int *choice, double *times_us, void *st
                         : static_cast<const void *>(sys->at<double>(sys->o_thv_rb));
   int best_v = 0;
   double best_t = 1e300;
-  for (int v = 0; v < fft_rb_variants(g, r32) && st == LTD_OK; ++v) {
+  const int n_shapes = sys->route == LTD_ROUTE_FFT ? fft_rb_variants(g, r32) : 0;
+  for (int v = 0; v < n_shapes && st == LTD_OK; ++v) {
     double us = 0.0;
     st = timed([&]() -> ltd_status {
       LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0, r32, v));
@@ -1763,7 +1894,7 @@ ltd_status ltd_autotune(ltd_system *sys, int *choice, double *times_us, void *st
   sys->gvalid = false;  // a captured step graph holds the previous shapes
   choice[0] = best_v;
   choice[1] = best_g;
-  choice[2] = fft_rb_variants(g, r32);
+  choice[2] = n_shapes;
   return LTD_OK;
 }
 
@@ -1855,7 +1986,7 @@ ltd_status ltd_propagate(ltd_system *sys, const ltd_step_args *a, int n_steps, v
   LTD_TRY(prepare_dt(sys, a->dt));
   hipStream_t s = S(stream);
   LTD_TRY(refresh_step_tables(sys, a));
-  const bool pipe = a->mode == LTD_STEP_REBUILD && sys->side2 != nullptr;
+  const bool pipe = a->mode == LTD_STEP_REBUILD && sys->side2 != nullptr && sys->route == LTD_ROUTE_FFT;
   if (pipe) {  // V~ of the first step, Theta V of the second, the step-index bounds of this call
     int *rs = sys->at<int>(sys->o_status) + 12;
     LTD_HIP(launch_lookahead_init(a->step, n_steps, rs, s));
@@ -1887,7 +2018,15 @@ ltd_status ltd_propagate_prepare(ltd_system *sys, const ltd_step_args *a, int n_
   if (n_steps == 0) return LTD_OK;
   LTD_TRY(prepare_dt(sys, a->dt));
   LTD_TRY(refresh_step_tables(sys, a));
-  return ensure_graphs(sys, a, n_steps, a->mode == LTD_STEP_REBUILD && sys->side2 != nullptr);
+  return ensure_graphs(sys, a, n_steps,
+                       a->mode == LTD_STEP_REBUILD && sys->side2 != nullptr && sys->route == LTD_ROUTE_FFT);
+}
+
+ltd_status ltd_pulse_loss(ltd_system *sys, const double *dmu, int n_steps, double *loss, void *stream) {
+  if (!sys || !dmu || !loss) return LTD_EINVAL;
+  if (n_steps < 0) return LTD_ESHAPE;
+  LTD_HIP(launch_pulse_loss(dmu, n_steps, sys->omega, loss, S(stream)));
+  return LTD_OK;
 }
 
 ltd_status ltd_propagate_step_adjoint(ltd_system *sys, const ltd_adjoint_args *aa, void *stream) {

@@ -245,4 +245,21 @@ hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th
                         double *t2, void *out, const double *sub, bool fp32, hipStream_t s);
 size_t fft_line_lds_bytes(const Grid &g);
 
+// ----------------------------------------------------------------------------
+// Interstitial matrix-matrix route (dense plane-wave blocks).
+// ----------------------------------------------------------------------------
+// Fourier coefficients f~(q) = (1/N) sum_j f_j exp(-2 pi i q.j/N) of f = th v (th
+// alone when v is NULL; v read at v + (*step) stride when step is set) in the box
+// |q_d| <= 2 b_d, layout [qz][qy][qx] (mm_box_values complex); scratch:
+// mm_box_scratch complex values; twiddles g.tw1..3.
+size_t mm_box_values(const Grid &g);
+size_t mm_box_scratch(const Grid &g);
+hipError_t mm_box_coefficients(const Grid &g, const double *th, const double *v, const int *step, long long stride,
+                               double2 *scratch, double2 *out, hipStream_t s);
+// Dense ng x ng block (ld) of operator `which` (0 S, 1 T, 2 V, 3 P_z) at the G
+// vectors gint/gk (k-point's natural order), rows and columns in the order idx
+// (NULL: natural); ft = Theta~ box, fv = (Theta V)~ box.
+hipError_t mm_dense(int which, const Grid &g, const int *gint, const double *gk, const int *idx, int ng,
+                    const double2 *ft, const double2 *fv, double2 *out, long long ld, hipStream_t s);
+
 }  // namespace ltd

@@ -841,8 +841,11 @@ __device__ __forceinline__ int xslot(int i, int j, int pitch) { return SWZ ? i *
 // imaginary parts one after the other through a scratch of doubles (lines 72
 // doubles apart, again distinct banks for every 32-lane group of 8-byte
 // accesses), half the LDS of a complex scratch: three blocks fit a CU
+// Every complex128 instance exchanges its z lines this way (the 8 x 8 layout
+// through xch8_split, the others through xch_split): half the LDS of a complex
+// scratch, so that two blocks of the 72 x 108 kernel (8 waves) share a CU.
 template <int NX, int X1, int NZ, int Z1, class T>
-constexpr bool xz4_split() { return xz4_swz<NX, X1, NZ, Z1>() && sizeof(T) == 16; }
+constexpr bool xz4_split() { return sizeof(T) == 16; }
 // LDS bytes of k_rb_xz4 (rows, then NW x LZ z-line scratch)
 template <int NX, int X1, int NZ, int Z1, class T>
 constexpr size_t xz4_lds(int nbz, int nw, int lz) {
@@ -869,6 +872,31 @@ __device__ __forceinline__ void xch8_split(double *sd, int r, const double2 (&in
   wave_fence();
 }
 
+// Exchange of one z line of a two-factor transform through a scratch of doubles
+// sd (slots i P + j): lanes with `put` write vin[k] to slot (r, k), k < RI,
+// lanes with `get` read vout[q] = slot (q, r), q < RO; the real parts pass
+// first, then the imaginary parts (LDS operations of one wave complete in order).
+template <int RI, int RO>
+__device__ __forceinline__ void xch_split(double *sd, int r, int P, bool put, bool get, const double2 (&vin)[RI],
+                                          double2 (&vout)[RO]) {
+  if (put)
+#pragma unroll
+    for (int k = 0; k < RI; ++k) sd[r * P + k] = vin[k].x;
+  wave_fence();
+  if (get)
+#pragma unroll
+    for (int q = 0; q < RO; ++q) vout[q].x = sd[q * P + r];
+  wave_fence();
+  if (put)
+#pragma unroll
+    for (int k = 0; k < RI; ++k) sd[r * P + k] = vin[k].y;
+  wave_fence();
+  if (get)
+#pragma unroll
+    for (int q = 0; q < RO; ++q) vout[q].y = sd[q * P + r];
+  wave_fence();
+}
+
 // Same transforms with NW waves per block: an x row exchanges in place through
 // its own RX slots (value (k1, n2) at slot k1 F2 + n2, odd stride across lanes);
 // the z columns exchange through a per-wave scratch of LZ lines.
@@ -883,7 +911,8 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
   constexpr bool SWZ = xz4_swz<NX, X1, NZ, Z1>();
   constexpr int RX = xz4_rx<NX, X1, NZ, Z1, T>();
   constexpr int LS = xz4_ls<NX, X1, NZ, Z1>();
-  constexpr bool SPLIT = xz4_split<NX, X1, NZ, Z1, T>();
+  constexpr bool SPLIT = SWZ && sizeof(T) == 16;   // the 8 x 8 split exchange
+  constexpr bool SPLITG = !SWZ && sizeof(T) == 16;  // the general split exchange
   extern __shared__ double2 sm_raw[];
   T *sm = reinterpret_cast<T *>(sm_raw);
   const int col = blockIdx.x, y = blockIdx.y, kk = blockIdx.z;
@@ -992,6 +1021,39 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
           for (int c = 0; c < 8; ++c) {
             if (c >= 2 && c <= 5) continue;
             const int m = 8 * c + rz;
+            if (m <= bz || m >= NZ - bz) R[(m <= bz ? m + bz : m - NZ + bz) * RX + x] = v[c];
+          }
+        }
+        wave_fence();
+        continue;
+      }
+      if constexpr (SPLITG) {  // complex128, general lengths: split exchanges through doubles
+        double *sd = scd + lz * LS;
+        double2 v[Z1], u[Z2];
+        if (on && rz < Z2) {
+#pragma unroll
+          for (int n1 = 0; n1 < Z1; ++n1) {
+            const int n = Z2 * n1 + rz;
+            const int row = n <= bz ? n + bz : n - NZ + bz;
+            v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : make_double2(0.0, 0.0);
+          }
+          dft_reg<Z1, 1>(v);
+          twiddle_powers<Z1>(v, w);
+        }
+        xch_split<Z1, Z2>(sd, rz, TZ::P, on && rz < Z2, on && rz < Z1, v, u);
+        if (on && rz < Z1) {
+          dft_reg<Z2, 1>(u);
+#pragma unroll
+          for (int k2 = 0; k2 < Z2; ++k2) u[k2] = cscale(u[k2], t[k2]);
+          dft_reg<Z2, -1>(u);
+          twiddle_powers<Z2>(u, wc);
+        }
+        xch_split<Z2, Z1>(sd, rz, TZ::P, on && rz < Z1, on && rz < Z2, u, v);
+        if (on && rz < Z2) {
+          dft_reg<Z1, -1>(v);
+#pragma unroll
+          for (int c = 0; c < Z1; ++c) {
+            const int m = Z2 * c + rz;
             if (m <= bz || m >= NZ - bz) R[(m <= bz ? m + bz : m - NZ + bz) * RX + x] = v[c];
           }
         }
@@ -1673,6 +1735,9 @@ constexpr int xzr_nw() { return sizeof(T) == 16 ? 2 : 4; }
 constexpr int rb_nw_of(int v) { return v == 1 ? 2 : 4; }
 template <int NZ, int Z1>
 constexpr int rb_lz_of(int v) {
+  // 108-point z lines (12 lanes, five to a wave): four per wave in the first
+  // shape keep a complex128 block within half the LDS of a CU (two blocks per CU)
+  if (NZ == 108 && v == 0) return 4;
   return v == 2 ? (rb_lz(Two<NZ, Z1, NZ / Z1>::LPW) / 2 > 0 ? rb_lz(Two<NZ, Z1, NZ / Z1>::LPW) / 2 : 1)
                 : rb_lz(Two<NZ, Z1, NZ / Z1>::LPW);
 }

@@ -104,6 +104,10 @@ hipError_t launch_lookahead_init(const int *step, int n_steps, int *rs, hipStrea
 // rs[0] = min(rs[0] + 1, rs[1]): the step whose V~ the pipelined rebuild computes
 hipError_t launch_lookahead(int *rs, hipStream_t s);
 int assemble_blocks(int n);
+// hist + (*step mod hist_len) n_k n_states n_aux <- theta (the states before the step)
+hipError_t launch_record_theta(const StepCtx &c, double2 *hist, int hist_len, hipStream_t s);
+// *loss = dmu[n] / omega
+hipError_t launch_pulse_loss(const double *dmu, int n, double omega, double *loss, hipStream_t s);
 hipError_t launch_adjoint(const StepCtx &c, const AdjCtx &a, hipStream_t s);
 hipError_t launch_knot_samples(const double *q, int nk, double t_end, double dt, int ns, double *a_t,
                                double *a_mid, hipStream_t s);

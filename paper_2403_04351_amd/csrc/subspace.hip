@@ -63,6 +63,68 @@ __device__ void matvec(const double2 *A, int lda, const double2 *v, double2 *y, 
   }
 }
 
+// Block-wide y = A v for A in global memory (n x n, column-major, ld lda), v and
+// y in LDS: lane l of wave w accumulates rows l + 64 r (r < RPL) over the
+// columns k = w, w + NW, ... (NW waves), four columns per iteration so that
+// 4 RPL independent loads are in flight; the waves' partial sums meet in red
+// (NW n values) and are added in wave order.  Row indices are clamped so that
+// every load is in bounds and branch-free.
+template <int RPL>
+__device__ void matvec_wide(const double2 *__restrict__ A, int lda, const double2 *v, double2 *y, int n,
+                            double2 *red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double2 acc[RPL];
+  int row[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    acc[r] = make_double2(0.0, 0.0);
+    const int i = lane + 64 * r;
+    row[r] = i < n ? i : n - 1;
+  }
+  int k = w;
+  for (; k + 3 * nw < n; k += 4 * nw) {
+    double2 a[4][RPL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) a[u][r] = A[(long long)row[r] + (long long)(k + u * nw) * lda];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double2 vk = v[k + u * nw];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[r] = cfma(a[u][r], vk, acc[r]);
+    }
+  }
+  for (; k < n; k += nw) {
+    const double2 vk = v[k];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) acc[r] = cfma(A[(long long)row[r] + (long long)k * lda], vk, acc[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lane + 64 * r;
+    if (i < n) red[(long long)w * n + i] = acc[r];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double2 t = red[i];
+    for (int q = 1; q < nw; ++q) t = cadd(t, red[(long long)q * n + i]);
+    y[i] = t;
+  }
+  __syncthreads();
+}
+
+// matvec_wide for n <= 320 (rows per lane ceil(n / 64))
+__device__ void matvec_g(const double2 *__restrict__ A, int lda, const double2 *v, double2 *y, int n, double2 *red) {
+  switch ((n + 63) / 64) {
+    case 1: matvec_wide<1>(A, lda, v, y, n, red); break;
+    case 2: matvec_wide<2>(A, lda, v, y, n, red); break;
+    case 3: matvec_wide<3>(A, lda, v, y, n, red); break;
+    case 4: matvec_wide<4>(A, lda, v, y, n, red); break;
+    default: matvec_wide<5>(A, lda, v, y, n, red); break;
+  }
+}
+
 // Block-wide sum of one double per thread (fixed order); result valid in all threads.
 __device__ double block_sum(double x, double *sred) {
   const int t = threadIdx.x;
@@ -258,6 +320,14 @@ __global__ __launch_bounds__(1024) void k_jacobi(double2 *A, double2 *V, double 
     }
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // keep A exactly Hermitian (the two triangles are updated by different
+    // rounded operations): the lower triangle from the upper, real diagonal
+    for (long long e = t; e < (long long)n * n; e += nt) {
+      const int i = (int)(e % n), j = (int)(e / n);
+      if (i > j) A[e] = cconj(A[j + (long long)i * n]);
+      else if (i == j) A[e].y = 0.0;
+    }
+    __syncthreads();
     double off = 0.0, tot = 0.0;
     for (long long e = t; e < (long long)n * n; e += nt) {
       const int i = (int)(e % n), j = (int)(e / n);
@@ -267,7 +337,9 @@ __global__ __launch_bounds__(1024) void k_jacobi(double2 *A, double2 *V, double 
     }
     off = block_sum(off, sred);
     tot = block_sum(tot, sred);
-    if (off <= 1e-30 * tot || off == 0.0) break;
+    // ||offdiag||_F <= 1e-14 ||A||_F bounds every eigenvalue's error by that
+    // (Weyl); the rounding floor of the off-diagonal sum lies near 1e-30 ||A||_F^2
+    if (off <= 1e-28 * tot || off == 0.0) break;
     for (int round = 0; round < m - 1; ++round) {
       for (int s = t; s < half; s += nt) {
         // circle method: position 0 fixed, others rotate
@@ -441,6 +513,12 @@ __device__ void finalize_step(const StepCtx &c, int step) {
 // Threads per state block of the forward step (512 measured no faster).
 constexpr int STEP_NT = 256;
 
+// reduction slots (double2) of the forward step kernel: one per thread, or the
+// NW n partial sums of the wide products when H~ is not LDS-resident
+__host__ __device__ inline int step_red_slots(int n, bool h_in_lds, int nt) {
+  return h_in_lds ? nt : (nt / 64 * n > nt ? nt / 64 * n : nt);
+}
+
 // HL / PL: H~(mid) / P~ staged in LDS (compile-time, so that their reads are
 // LDS reads rather than generic ones).  The block that finishes last sums the
 // partials of every state (finalize_step).
@@ -458,7 +536,13 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
   const double2 *P = pl ? Pl : S.pt;
   double2 *v = vec, *t0 = vec + n, *t1 = vec + 2 * n, *acc = vec + 3 * n, *tmp = vec + 4 * n, *w = vec + 5 * n;
   double2 *red = vec + 6 * n;
-  double *sred = reinterpret_cast<double *>(red + blockDim.x);
+  double *sred = reinterpret_cast<double *>(red + step_red_slots(n, HL, blockDim.x));
+  // products with matrices in global memory: the wide form when the subspace
+  // Hamiltonian does not fit in LDS (large n); the LDS-resident ones as they are
+  const auto mvg = [&](const double2 *A, const double2 *x, double2 *y) {
+    if constexpr (!HL) matvec_g(A, n, x, y, n, red);
+    else matvec<false>(A, n, x, y, n, red);
+  };
   const int step = *c.step;
   const double am = c.a_mid[step], a1 = c.a_t[step + 1];
   const double cl = c.c_light;
@@ -482,15 +566,18 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
   double2 *th = c.theta + (long long)k * n * c.n_states + (long long)j * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) tmp[i] = th[i];
   __syncthreads();
-  matvec<false>(S.LH, n, tmp, v, n, red);
+  mvg(S.LH, tmp, v);
 
   // observables of theta~ in v at A = a (H~(a) v built from M v):
   //   J = -(f/Omega) w_k Re(v^H P~ v + (a/c) v^H v),  E = f w_k Re v^H H~(a) v
   // ref = false: H~(a) v from the step's M = (H~(mid) - c0)/r;
   // ref = true:  H~(a) v from H~0 (the reference potential, the only one known at t_0)
   auto observe = [&](double a, double *jo, double *eo, bool ref) {
-    matvec<false>(ref ? S.h0t : Hm, n, v, t0, n, red);  // t0 = M v  or  H~0 v
-    matvec<false>(P, n, v, t1, n, red);                  // t1 = P~ v
+    if (ref) mvg(S.h0t, v, t0);  // t0 = H~0 v
+    else if constexpr (HL) matvec<false>(Hm, n, v, t0, n, red);  // t0 = M v
+    else mvg(Hm, v, t0);
+    if constexpr (PL) matvec<false>(P, n, v, t1, n, red);  // t1 = P~ v
+    else mvg(P, v, t1);
     double vv = 0.0, vp = 0.0, vm = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       vv += v[i].x * v[i].x + v[i].y * v[i].y;
@@ -536,7 +623,8 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
     }
     __syncthreads();
     for (int q = 1; q <= c.taylor; ++q) {
-      matvec<false>(Hm, n, t0, tmp, n, red);
+      if constexpr (HL) matvec<false>(Hm, n, t0, tmp, n, red);
+      else mvg(Hm, t0, tmp);
       const double fq = c.dt * S.r / q;
       for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const double2 tn = make_double2(fq * tmp[i].y, -fq * tmp[i].x);  // -i fq tmp
@@ -549,12 +637,14 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
   // 3. Chebyshev series
   const int K = S.K;
   for (int i = threadIdx.x; i < n; i += blockDim.x) t0[i] = v[i];
-  matvec<false>(Hm, n, v, t1, n, red);
+  if constexpr (HL) matvec<false>(Hm, n, v, t1, n, red);
+  else mvg(Hm, v, t1);
   for (int i = threadIdx.x; i < n; i += blockDim.x) acc[i] = cadd(cmul(S.coef[0], t0[i]), cmul(S.coef[1], t1[i]));
   __syncthreads();
   double2 *pa = t0, *pb = t1;  // T_{k-2}, T_{k-1}
   for (int q = 2; q <= K; ++q) {
-    matvec<false>(Hm, n, pb, tmp, n, red);
+    if constexpr (HL) matvec<false>(Hm, n, pb, tmp, n, red);
+    else mvg(Hm, pb, tmp);
     const double2 cq = S.coef[q];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       const double2 tn = make_double2(2.0 * tmp[i].x - pa[i].x, 2.0 * tmp[i].y - pa[i].y);
@@ -571,7 +661,7 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
   __syncthreads();
 
   // 4. theta = L^{-H} theta~
-  matvec<false>(S.LinvH, n, v, w, n, red);
+  mvg(S.LinvH, v, w);
   for (int i = threadIdx.x; i < n; i += blockDim.x) th[i] = w[i];
 
   // 5. observables at t_{n+1} (v still holds theta~)
@@ -900,7 +990,8 @@ hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s
 size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint, bool p_in_lds) {
   const size_t vecs = adjoint ? 11 : 6;
   const size_t mats = (h_in_lds ? (size_t)n * n : 0) + ((!adjoint && p_in_lds) ? (size_t)n * n : 0);
-  const size_t nt = adjoint ? 256 : STEP_NT;  // one reduction slot per thread
+  // reduction slots: one per thread, or the wave partials of the wide products
+  const size_t nt = adjoint ? 256 : step_red_slots(n, h_in_lds, STEP_NT);
   return (mats + vecs * n + nt) * sizeof(double2) + 256 * sizeof(double);
 }
 
@@ -926,6 +1017,29 @@ void subspace_init_attrs() {
 
 hipError_t launch_assemble(const StepCtx &c, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble, dim3(assemble_blocks(c.n_aux), c.n_k), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
+
+__global__ void k_record_theta(const double2 *__restrict__ th, double2 *__restrict__ hist, const int *step,
+                               int hist_len, long long len) {
+  const long long off = (long long)((*step) % hist_len) * len;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len; i += (long long)gridDim.x * blockDim.x)
+    hist[off + i] = th[i];
+}
+
+hipError_t launch_record_theta(const StepCtx &c, double2 *hist, int hist_len, hipStream_t s) {
+  const long long len = (long long)c.n_k * c.n_states * c.n_aux;
+  const int blocks = (int)std::min<long long>((len + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_record_theta, dim3(blocks), dim3(256), 0, s, c.theta, hist, c.step, hist_len, len);
+  return hipGetLastError();
+}
+
+__global__ void k_pulse_loss(const double *dmu, int n, double omega, double *loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *loss = dmu[n] / omega;
+}
+
+hipError_t launch_pulse_loss(const double *dmu, int n, double omega, double *loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_pulse_loss, dim3(1), dim3(64), 0, s, dmu, n, omega, loss);
   return hipGetLastError();
 }
 

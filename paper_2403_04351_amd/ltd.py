@@ -44,7 +44,7 @@ def _ptr(x) -> int:
 class Ltd:
     """One ltd system bound to a device workspace."""
 
-    def __init__(self, sys, device="cuda", max_cols=None, precision=_lib.LTD_FP64):
+    def __init__(self, sys, device="cuda", max_cols=None, precision=_lib.LTD_FP64, route=_lib.LTD_ROUTE_FFT):
         torch = _torch()
         self.lib = _lib.load()
         self.sysdef = sys
@@ -86,7 +86,7 @@ class Ltd:
             n_lo=ip(self._n_lo), amat=_ptr(self.amat), h=_ptr(self.h), o=_ptr(self.o), pz=_ptr(self.pz),
             omega=sys.omega, c_light=sys.c_light, occ=sys.occ,
             k_weight=self._kw.ctypes.data_as(C.POINTER(C.c_double)), n_aux=sys.n_aux,
-            n_states=sys.n_states, max_cols=self.max_cols)
+            n_states=sys.n_states, max_cols=self.max_cols, interstitial_route=route)
         wsb = C.c_size_t(0)
         handle = C.c_void_p(0)
         check(self.lib.ltd_create(C.byref(self._desc), precision, C.byref(wsb), C.byref(handle)), "ltd_create")
@@ -187,12 +187,13 @@ class Ltd:
         return tuple(out)
 
     def make_step_args(self, mode, dt, a_t, a_mid, theta, n_steps, c_out=None, v_r_t=None, h_t=None,
-                       v_stride=0, h_stride=0, taylor_order=0, nexc=False):
+                       v_stride=0, h_stride=0, taylor_order=0, nexc=False, theta_hist=None):
         """Device buffers and the StepArgs for a run of n_steps; theta (n_k, n_states, n_aux).
         v_stride / h_stride: elements between the potentials / blocks of consecutive
         steps when v_r_t / h_t hold one per step (0: one for every step).
         taylor_order > 0: the explicit truncated-Taylor step; nexc: also the
-        excited-electron series st["nexc"]."""
+        excited-electron series st["nexc"]; theta_hist (hist_len, n_k, n_states,
+        n_aux): the states before each step are recorded in slot step mod hist_len."""
         torch = _torch()
         dev = self.device
         st = dict(
@@ -207,7 +208,9 @@ class Ltd:
                               v_r_t=_ptr(v_r_t), h_t=_ptr(h_t), theta=_ptr(theta), c_out=_ptr(c_out),
                               j_out=_ptr(st["j"]), e_out=_ptr(st["e"]), dmu_out=_ptr(st["dmu"]),
                               v_stride=v_stride, h_stride=h_stride, taylor_order=taylor_order,
-                              nexc_out=_ptr(st["nexc"]))
+                              nexc_out=_ptr(st["nexc"]), theta_hist=_ptr(theta_hist),
+                              hist_len=0 if theta_hist is None else theta_hist.shape[0])
+        st["theta_hist"] = theta_hist
         return st
 
     def step(self, st):
@@ -265,6 +268,14 @@ class Ltd:
         check(self.lib.ltd_profile_apply(self.handle, k, _ptr(c), nb, n, _ptr(hc), _ptr(sc), nb, buf,
                                          self.stream()), "ltd_profile_apply")
         return list(buf), hc, sc
+
+    def pulse_loss(self, st, n_steps: int):
+        """L = delta mu(T) / Omega of a run of n_steps (a device scalar)."""
+        torch = _torch()
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        check(self.lib.ltd_pulse_loss(self.handle, _ptr(st["dmu"]), n_steps, _ptr(loss), self.stream()),
+              "ltd_pulse_loss")
+        return loss
 
     def adjoint_step(self, st, n, n_steps, mu_next, mu_out, dl_da_mid, dl_da_t, terminal=False):
         a = AdjointArgs(fwd=C.pointer(st["args"]), n=n, terminal=1 if terminal else 0, n_steps=n_steps,
@@ -344,10 +355,7 @@ def pulse_forward(lt: Ltd, mode, dt, q, t_end, n_steps, theta0, checkpoint=50, p
         lt.run(st, m) if m > 1 else lt.step(st)
         done += m
         ckpt[done] = theta.clone()
-    w = torch.ones(n_steps + 1, dtype=torch.float64, device=lt.device)
-    w[0] = w[-1] = 0.5
-    j = st["j"]
-    loss = dt * torch.sum(w * (j - j[0]))
+    loss = lt.pulse_loss(st, n_steps)
     return loss, dict(st=st, ckpt=ckpt, a_t=a_t, a_mid=a_mid, checkpoint=checkpoint, pot=pot)
 
 
@@ -366,18 +374,19 @@ def pulse_backward(lt: Ltd, mode, dt, q, t_end, n_steps, fw):
     sa = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], th_n, n_steps, **pot)
     lt.adjoint_step(sa, n_steps, n_steps, None, mu, None, g_t, terminal=True)
     seg_starts = sorted(s for s in fw["ckpt"] if s < n_steps)
+    # each segment is recomputed from its checkpoint by one replayed call that
+    # records the states before every step (slot n mod ck)
+    theta = torch.empty_like(fw["ckpt"][0])
+    hist = torch.empty((ck,) + tuple(theta.shape), dtype=theta.dtype, device=dev)
+    rec = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], theta, n_steps, theta_hist=hist, **pot)
+    slots = [lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], hist[i], n_steps, **pot) for i in range(ck)]
     for s0 in reversed(seg_starts):
         s1 = min(s0 + ck, n_steps)
-        theta = fw["ckpt"][s0].clone()
-        rec = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], theta, n_steps, **pot)
+        theta.copy_(fw["ckpt"][s0])
         rec["step"].fill_(s0)
-        thetas = []
-        for _ in range(s0, s1):
-            thetas.append(theta.clone())
-            lt.step(rec)
+        lt.run(rec, s1 - s0) if s1 - s0 > 1 else lt.step(rec)
         for n in range(s1 - 1, s0 - 1, -1):
-            sa = lt.make_step_args(mode, dt, fw["a_t"], fw["a_mid"], thetas[n - s0], n_steps, **pot)
-            lt.adjoint_step(sa, n, n_steps, mu, mu, g_mid, g_t)
+            lt.adjoint_step(slots[n % ck], n, n_steps, mu, mu, g_mid, g_t)
     return lt.knot_gradient(g_t, g_mid, dt, q.numel(), t_end), g_t, g_mid
 
 

@@ -7,6 +7,8 @@ steps of dt = 0.1, checkpoints every 50 steps.
   forward loss on every one of the 64 knots (128 forward runs of 2000 steps).
 """
 
+import time
+
 import numpy as np
 import pytest
 
@@ -61,11 +63,15 @@ def test_adjoint_matches_oracle_at_scale(w4, mode):
     lt, ltd, torch, sys = w4["lt"], w4["ltd"], w4["torch"], w4["sys"]
     m = ltd.LTD_STEP_AFFINE if mode == "affine" else ltd.LTD_STEP_REBUILD
     qd = torch.from_numpy(w4["q"]).to(lt.device)
+    tf = time.perf_counter()
     loss, fw = ltd.pulse_forward(lt, m, sys.dt, qd, w4["t_end"], sys.n_steps, w4["th0"], checkpoint=50)
     torch.cuda.synchronize()
-    print(f"[{mode}] forward done", flush=True)
+    tb = time.perf_counter()
     grad, g_t, g_mid = ltd.pulse_backward(lt, m, sys.dt, qd, w4["t_end"], sys.n_steps, fw)
     torch.cuda.synchronize()
+    te = time.perf_counter()
+    print(f"[{mode}] forward {1e3 * (tb - tf):.1f} ms, checkpointed backward {1e3 * (te - tb):.1f} ms "
+          f"({sys.n_steps} steps, segments of 50 recomputed by replayed calls)", flush=True)
     assert lt.sync_status() == 0
     g = w4["g"]
     j = fw["st"]["j"].cpu().numpy()

@@ -132,3 +132,53 @@ def test_batched_rebuild_with_new_potential(w3):
           flush=True)
     assert abs(gj[1] - j1) < TOL * abs(j1)
     assert worst < TOL
+
+
+@pytest.mark.parametrize("precision", ["LTD_FP64", "LTD_FP32_RESID"])
+def test_batched_potential_series(w3, precision):
+    """60 graph-replayed REBUILD steps of all 16 k-points with a potential handed in
+    per step, in FP64 and with the FP32 residual rebuild, against the FP64 oracle
+    (per k: V_sub(t) = V_sub,ref + s_n D_k, D_k the oracle's rebuild of the
+    perturbation alone; the weighted sum over k)."""
+    from paper_2403_04351_amd import _lib
+    from synth import potential_scale
+
+    sys, ltd, torch, subs, phis = w3["sys"], w3["ltd"], w3["torch"], w3["subs"], w3["phis"]
+    n = 60
+    eps_v, wfield, wblk = td_potential(sys)
+    s_n = potential_scale(n)
+    if "d" not in w3:
+        w3["d"] = [ss.rebuild_v_sub(sys, k, phis[k], vr=eps_v * wfield, h=[eps_v * b for b in wblk])
+                   for k in range(len(sys.kpts))]
+    a_t, a_mid = pulse_samples(sys, n)
+    th0, _ = _theta0(sys, torch, "cpu")
+    j = np.zeros(n + 1)
+    for k, kp in enumerate(sys.kpts):
+        ref = pr.propagate(subs[k], th0, a_t, a_mid, sys.dt, sys.occ, sys.omega, sys.c_light,
+                           v_sub_fn=lambda q, k=k: subs[k]["V"] + s_n[q] * w3["d"][k])
+        j += kp.weight * ref["J"]
+    dmu = pr.dipole_change(j, sys.dt, sys.omega)
+    lt = w3["lt"] if precision == "LTD_FP64" else ltd.Ltd(sys, max_cols=sys.n_aux,
+                                                           precision=getattr(_lib, precision))
+    for k in range(len(sys.kpts)):
+        lt.project_subspace(k, ltd.colmajor(phis[k], lt.device))
+    dev = lt.device
+    sd = torch.from_numpy(s_n).to(dev)[:, None]
+    v0 = torch.from_numpy(np.ascontiguousarray(sys.vr.ravel())).to(dev)
+    w0 = torch.from_numpy(np.ascontiguousarray(wfield.ravel())).to(dev)
+    wb = torch.from_numpy(np.concatenate([np.ascontiguousarray(x.T).ravel() for x in wblk])).to(dev)
+    vs = (v0[None, :] + eps_v * sd * w0[None, :]).contiguous()
+    hs = (lt.h[None, :] + eps_v * sd * wb[None, :]).contiguous()
+    _, theta = _theta0(sys, torch, dev)
+    st = lt.propagate(ltd.LTD_STEP_REBUILD, sys.dt, torch.from_numpy(a_t).to(dev), torch.from_numpy(a_mid).to(dev),
+                      theta, n, v_r_t=vs, h_t=hs, v_stride=vs.shape[1], h_stride=hs.shape[1])
+    torch.cuda.synchronize()
+    assert lt.sync_status() == 0
+    gj, gd = st["j"].cpu().numpy(), st["dmu"].cpu().numpy()
+    ej, ei, ed = rel_max(gj, j), rel_own(gj - gj[0], j - j[0]), rel_own(gd, dmu)
+    print(f"batched 16 k, potential series, {precision}: J {ej:.2e} J_ind {ei:.2e} dmu {ed:.2e}", flush=True)
+    if precision == "LTD_FP64":
+        assert ej < TOL and ei < JIND_TOL and ed < DMU_TOL
+    else:
+        assert ej < 1e-6 and ei < 1e-6 and ed < 1e-6
+        lt.close()
