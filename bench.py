@@ -64,6 +64,13 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=None,
                    help="time steps of the CPU oracle sample (default: 50, 2 for the heterostructure)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--compare-full", action="store_true",
+                   help="also time the conventional full-basis propagation of the same states at the full "
+                        "basis' critical step and report seconds per simulated atomic unit of both")
+    p.add_argument("--full-steps", type=int, default=3, help="timed full-basis steps (--compare-full)")
+    p.add_argument("--sweep-ng", type=str, default=None, metavar="N1,N2,...",
+                   help="only run the N_G sweep: per-step rebuild time of the FFT and the dense-block "
+                        "interstitial routes at N_aux = 255 on the molecule system with N_G plane waves")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run 5 plain device-to-device copies of MIB MiB (counter calibration)")
     return p.parse_args()
@@ -112,15 +119,14 @@ def traffic_from_profiles(kernel_file, stage, precision, config):
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path))
+        recs = json.load(open(path))
         src = open(os.path.join(ROOT, "paper_2403_04351_amd", "csrc", kernel_file), "rb").read()
-        if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
-            return None
-        if rec.get("stage") != stage or rec.get("precision", "fp64") != precision:
-            return None
-        if rec.get("config") != config:
-            return None
-        return rec.get("bytes_per_launch")
+        sha = hashlib.sha256(src).hexdigest()
+        for rec in recs if isinstance(recs, list) else [recs]:
+            if (rec.get("source_sha256") == sha and rec.get("stage") == stage
+                    and rec.get("precision", "fp64") == precision and rec.get("config") == config):
+                return rec.get("bytes_per_launch")
+        return None
     except Exception:
         return None
 
@@ -221,6 +227,97 @@ def cpu_baseline(sysd, n_steps, mode, series, ks):
                        f"of {kdesc} of the same workload, setup excluded; {t:.2f} s")
 
 
+def compare_full(args, torch, lt, sysd, phi, emin, sub_ms_per_step):
+    """Seconds per simulated atomic unit of time: the subspace propagation (its
+    dt) against the conventional one in the full basis (Sec. 2.1, Eq. (10)) at the
+    full basis' critical step 0.2 / (eps_max - eps_min) (Sec. 3.1, Eq. (20)),
+    explicit order-4 Taylor steps with conjugate-gradient solves of S."""
+    dev = phi.device
+    nb = sysd.n_basis(0)
+    rng = np.random.default_rng(91)
+    x0 = torch.from_numpy(rng.standard_normal(nb) + 1j * rng.standard_normal(nb)).to(dev)
+    t0 = time.perf_counter()
+    eps_max = lt.full_spectrum(0, x0, iters=30, cg_tol=1e-8)
+    t_spec = time.perf_counter() - t0
+    dt_full = 0.2 / (eps_max - emin)
+    c0 = 0.5 * (eps_max + emin)
+    c = phi[: sysd.n_states].clone()
+    a_mid = np.full(args.full_steps + 1, 0.005)
+    cg_tol = 1e-10
+    lt.propagate_full(0, c, dt_full, 4, c0, a_mid[:1], cg_max_iter=5000, cg_tol=cg_tol)  # warm-up step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, its = lt.propagate_full(0, c, dt_full, 4, c0, a_mid[1:], cg_max_iter=5000, cg_tol=cg_tol)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.full_steps
+    sub_s_au = sub_ms_per_step * 1e-3 / sysd.dt
+    full_s_au = t_step / dt_full
+    return dict(states=sysd.n_states, dt_cr_full=dt_full, eps_max_power_iteration=eps_max, eps_min_ritz=emin,
+                power_iteration_s=round(t_spec, 3), order=4, cg_tol=cg_tol, cg_iters_max=its, cg_resid_max=res,
+                steps_timed=args.full_steps, s_per_step=t_step, s_per_au=full_s_au,
+                subspace_dt=sysd.dt, subspace_s_per_au=sub_s_au, speedup=full_s_au / sub_s_au)
+
+
+def sweep_ng(args, torch, ltd, _lib, dev):
+    """Per-step rebuild time of the two interstitial routes as N_G grows (the
+    paper's basis-size study, Sec. 3.2): FFT (flat in N_G) against dense N_G x N_G
+    blocks (N_G^2 storage and work), N_aux = 255, the molecule system's cell,
+    atoms and 72^3 grid, a potential handed in per step."""
+    from synth import make_system, pulse_samples, td_potential
+
+    rows = []
+    for ng in [int(x) for x in args.sweep_ng.split(",")]:
+        sysd = make_system(1, n_g=ng, n_aux=255, n_states=5)
+        n_steps = 20
+        a_t, a_mid = pulse_samples(sysd, 5 + n_steps)
+        eps, wfield, wblk = td_potential(sysd)
+        for route, rname in ((_lib.LTD_ROUTE_FFT, "fft"), (_lib.LTD_ROUTE_MM, "mm")):
+            t0 = time.perf_counter()
+            lt = ltd.Ltd(sysd, device=dev, route=route)
+            phi = ltd.colmajor(sysd.kpts[0].start, dev)
+            lt.ritz_basis(0, phi)
+            lt.project_subspace(0, phi)
+            if route == _lib.LTD_ROUTE_FFT:
+                lt.autotune()
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            sd = torch.from_numpy(potential_series(sysd, 5 + n_steps)).to(dev)[:, None]
+            v0 = torch.from_numpy(np.ascontiguousarray(sysd.vr.ravel())).to(dev)
+            w0 = torch.from_numpy(np.ascontiguousarray(wfield.ravel())).to(dev)
+            wb = torch.from_numpy(np.concatenate([np.ascontiguousarray(x.T).ravel() for x in wblk])).to(dev)
+            vs = (v0[None, :] + eps * sd * w0[None, :]).contiguous()
+            hs = (lt.h[None, :] + eps * sd * wb[None, :]).contiguous()
+            th0 = np.zeros((1, sysd.n_states, sysd.n_aux), dtype=np.complex128)
+            for j in range(sysd.n_states):
+                th0[0, j, j] = 1.0
+            st = lt.make_step_args(ltd.LTD_STEP_REBUILD, sysd.dt, torch.from_numpy(a_t).to(dev),
+                                   torch.from_numpy(a_mid).to(dev), torch.from_numpy(th0).to(dev), 5 + n_steps,
+                                   v_r_t=vs, h_t=hs, v_stride=vs.shape[1], h_stride=hs.shape[1])
+            lt.run(st, 5)
+            lt.prepare(st, n_steps)
+            torch.cuda.synchronize()
+            s = torch.cuda.current_stream(dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            lt.run(st, n_steps)
+            e1.record(s)
+            torch.cuda.synchronize()
+            if lt.sync_status() != 0:
+                print(f"device status {lt.sync_status()} (N_G {ng}, {rname})", file=sys.stderr)
+                return 1
+            ms = e0.elapsed_time(e1) / n_steps
+            rows.append(dict(n_g=ng, n_basis=sysd.n_basis(0), route=rname, ms_per_step=round(ms, 4),
+                             setup_s=round(t_setup, 2), j_last=float(st["j"][5 + n_steps].item())))
+            print(f"[sweep] N_G {ng} {rname}: {ms:.3f} ms/step, setup {t_setup:.1f} s", file=sys.stderr, flush=True)
+            lt.close()
+            del lt, st, vs, hs, phi
+            torch.cuda.empty_cache()
+    print(json.dumps({"sweep": "per-step rebuild time vs N_G, FFT and dense-block interstitial routes",
+                      "n_aux": 255, "n_states": 5, "grid": [72, 72, 72], "steps_timed": 20, "rows": rows}),
+          flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -241,13 +338,14 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes, "reads_plus_writes_per_copy": 2 * nbytes}))
         return 0
-    from paper_2403_04351_amd import ltd
+    from paper_2403_04351_amd import _lib, ltd
     from synth import make_system, pulse_samples
 
     dev = torch.device("cuda:0")
+    if args.sweep_ng:
+        return sweep_ng(args, torch, ltd, _lib, dev)
     sysd = make_system(args.config)
     nk = len(sysd.kpts)
-    from paper_2403_04351_amd import _lib
 
     prec = _lib.LTD_FP64 if args.precision == "fp64" else _lib.LTD_FP32_RESID
     lt = ltd.Ltd(sysd, device=dev, precision=prec)
@@ -379,6 +477,8 @@ def main():
         out["dipole_error"] = dipole_error_stored(st, args.warmup + args.steps)
     elif series and nk == 1 and not args.no_cpu_baseline:
         out["dipole_error"] = dipole_error_oracle(sysd, st, args.warmup + args.steps)
+    if args.compare_full and nk == 1:
+        out["conventional"] = compare_full(args, torch, lt, sysd, phi, emin, ms / args.steps)
     if not args.no_cpu_baseline:
         ks = [0] if nk == 1 else [0, 1]
         cpu_steps = args.cpu_steps if args.cpu_steps is not None else (3 if nk > 1 else 2 if args.config == 2 else 50)

@@ -54,6 +54,7 @@ enum {
   LTD_EUNSUPPORTED = -6,/* grid length or mode this build does not handle */
   LTD_ESTEP = -7,       /* time step above the critical time step of the explicit propagator */
   LTD_EHIP = 1,         /* a HIP runtime call failed */
+  LTD_ECAPTURE = 5,     /* graph capture: a stream forked from the capture stream was not joined back */
   LTD_ENOTSPD = 2,      /* device: S_sub Cholesky met a pivot <= 0 */
   LTD_ENONFINITE = 3,   /* device: non-finite current, energy or step Hamiltonian */
   LTD_ESPECTRUM = 4     /* device: subspace spectrum left the propagator's interval */
@@ -151,6 +152,39 @@ ltd_status ltd_apply_HS(ltd_system *sys, int k, const double a_vec[3], const voi
 #define LTD_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
 ltd_status ltd_apply_HS_static(ltd_system *sys, int k, const double a_vec[3], const void *C, int ldc,
                                int n, void *HC, int ldhc, void *SC, int ldsc, void *stream);
+
+/* Conventional propagation in the full LAPW+LO basis, the reference the
+ * auxiliary subspace is measured against (Sec. 2.1, Eq. (10); Sec. 3.1): the n
+ * columns of C (N_basis(k) x n, ld ldc, in/out) are advanced n_steps explicit
+ * steps of S dC/dt = -i H(t) C, each the exponential of -i dt S^{-1} H(t_n +
+ * dt/2) truncated after `order` Taylor terms about c0 times the exact phase
+ * exp(-i dt c0).  Every term applies H by ltd_apply_HS and solves with S by
+ * conjugate gradients (one system per column; S is Hermitian positive
+ * definite), stopping when every column's relative residual is below cg_tol
+ * (checked every 8 iterations) or after cg_max_iter iterations.  The explicit
+ * step diverges beyond dt_cr = 0.2 / (eps_max - eps_min) of the full (H0, S)
+ * (Sec. 3.1, Eq. (20)); the caller chooses dt (ltd_full_spectrum estimates
+ * eps_max).  Host-driven launches (not graph-captured); synchronises `stream`. */
+typedef struct {
+  double dt;
+  int order;               /* Taylor terms, 1..8 */
+  double c0;               /* expansion centre (Ha), e.g. (eps_max + eps_min) / 2 */
+  const double *a_mid;     /* (host) [n_steps] A_z(t_n + dt/2) */
+  int cg_max_iter;         /* >= 1 */
+  double cg_tol;           /* > 0 */
+  double *cg_resid;        /* (host, optional) out: largest final relative residual of any solve */
+  int *cg_iters;           /* (host, optional) out: most iterations any solve used */
+} ltd_full_args;
+ltd_status ltd_propagate_full(ltd_system *sys, int k, void *C, int ldc, int n, const ltd_full_args *args,
+                              int n_steps, void *stream);
+
+/* Largest eigenvalue of the full (H0, S) of k-point k by power iteration on
+ * S^{-1} H0 from the start vector x0 (N_basis(k) complex128, device; the
+ * caller's seeded draw): `iters` iterations, each one H apply and one CG solve
+ * (cg_max_iter, cg_tol as above); *eps_max (host) is the last Rayleigh quotient
+ * x^H H0 x / x^H S x.  Synchronises `stream`. */
+ltd_status ltd_full_spectrum(ltd_system *sys, int k, const void *x0, int iters, int cg_max_iter, double cg_tol,
+                             double *eps_max, void *stream);
 
 /* Binds the auxiliary basis Phi (N_basis(k) x n_aux, ld ldphi; caller-owned,
  * must stay valid and unchanged while the system propagates k) and prepares

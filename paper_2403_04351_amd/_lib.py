@@ -6,7 +6,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libltd.so")
+# LTD_LIBRARY: another build of the same library (e.g. the host-sanitized one)
+LIB_PATH = os.environ.get("LTD_LIBRARY") or os.path.join(HERE, "libltd.so")
 
 LTD_OK = 0
 LTD_EINVAL = -1
@@ -20,6 +21,7 @@ LTD_EHIP = 1
 LTD_ENOTSPD = 2
 LTD_ENONFINITE = 3
 LTD_ESPECTRUM = 4
+LTD_ECAPTURE = 5
 
 LTD_FP64 = 0
 LTD_FP32_RESID = 1
@@ -38,7 +40,7 @@ EXPORTED = [
     "ltd_propagate_step", "ltd_propagate", "ltd_propagate_prepare", "ltd_propagate_step_adjoint", "ltd_knot_samples",
     "ltd_knot_gradient", "ltd_chebyshev_coefficients", "ltd_profile_steps", "ltd_profile_apply",
     "ltd_rebuild_grid", "ltd_autotune", "ltd_set_tuning", "ltd_state_drift",
-    "ltd_pulse_samples", "ltd_polarizability", "ltd_pulse_loss",
+    "ltd_pulse_samples", "ltd_polarizability", "ltd_pulse_loss", "ltd_propagate_full", "ltd_full_spectrum",
 ]
 LTD_PROFILE_STAGES = 8
 
@@ -93,6 +95,19 @@ class StepArgs(C.Structure):
     ]
 
 
+class FullArgs(C.Structure):
+    _fields_ = [
+        ("dt", C.c_double),
+        ("order", C.c_int),
+        ("c0", C.c_double),
+        ("a_mid", C.POINTER(C.c_double)),
+        ("cg_max_iter", C.c_int),
+        ("cg_tol", C.c_double),
+        ("cg_resid", C.POINTER(C.c_double)),
+        ("cg_iters", C.POINTER(C.c_int)),
+    ]
+
+
 class AdjointArgs(C.Structure):
     _fields_ = [
         ("fwd", C.POINTER(StepArgs)),
@@ -141,6 +156,8 @@ def load(path: str = LIB_PATH):
     lib.ltd_knot_samples.argtypes = [vp, ip, C.c_double, C.c_double, ip, vp, vp, vp]
     lib.ltd_knot_gradient.argtypes = [vp, vp, ip, C.c_double, ip, C.c_double, vp, vp]
     lib.ltd_pulse_loss.argtypes = [vp, vp, ip, vp, vp]
+    lib.ltd_propagate_full.argtypes = [vp, ip, vp, ip, ip, C.POINTER(FullArgs), ip, vp]
+    lib.ltd_full_spectrum.argtypes = [vp, ip, vp, ip, ip, C.c_double, dp, vp]
     lib.ltd_pulse_samples.argtypes = [ip, dp, C.c_double, ip, vp, vp, vp]
     lib.ltd_polarizability.argtypes = [vp, vp, ip, C.c_double, C.c_double, C.c_double, vp, ip, C.c_double, vp, vp]
     lib.ltd_chebyshev_coefficients.argtypes = [C.c_double, ip, dp, C.POINTER(ip)]

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <unordered_set>
 #include <vector>
 
 #include "common.h"
@@ -133,6 +134,7 @@ struct ltd_system {
   std::vector<ZProb> k7_32, vstep32;
   int k7_32_tiles = 0, vstep32_tiles = 0;
   size_t o_k7_32 = 0, o_vstep32 = 0, o_hstep32 = 0, o_mtperm = 0;
+  size_t o_full = 0, o_fscal = 0;  // full-basis propagation: eight N_basis x cols blocks, CG scalars
   std::vector<int> mt_row32;  // first FP32 MT row of each atom
   const void *k2_step_h = nullptr;  // blocks the step table points at
   // subspace / step state
@@ -663,6 +665,99 @@ ltd_status apply_cols(ltd_system *sys, int k, int mode, double a_z, const double
   return LTD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Full-basis propagation helpers: S applied alone (the interstitial step
+// function by the FFT V pass with Theta as the multiplier, or the dense block;
+// the muffin-tin overlap blocks through the matching coefficients) and block
+// conjugate gradients for S Y = B, one system per column.
+// ---------------------------------------------------------------------------
+double2 *full_blk(ltd_system *sys, int i) {
+  const int fc = std::min(1024, std::max(sys->max_cols, sys->n_states));
+  return sys->at<double2>(sys->o_full) + (size_t)i * sys->nb_max * fc;
+}
+
+ltd_status apply_s(ltd_system *sys, int k, const double2 *X, int ldx, int n, double2 *SX, int ld, hipStream_t s) {
+  const KHost &kh = sys->kh[k];
+  const int nl = sys->n_loc;
+  const double2 one = make_double2(1.0, 0.0);
+  const ApplyBufs bf = workspace_bufs(sys);
+  for (int j0 = 0; j0 < n; j0 += sys->chunk) {
+    const int cols = std::min(sys->chunk, n - j0);
+    const double2 *x = X + (long long)j0 * ldx;
+    double2 *out = SX + (long long)j0 * ld;
+    if (sys->route == LTD_ROUTE_MM) {
+      LTD_TRY(gemm1(sys, OP_N, OP_N, zp(kh.n_g, cols, kh.n_g, sys->at<double2>(kh.o_mmS), kh.n_g, x, ldx, out, ld),
+                    s));
+    } else {
+      const Grid g = grid_of(sys);
+      FftKArgs ka{};
+      ka.sph[0] = sphere_of(sys, k);
+      ka.in[0].c = x;
+      ka.in[0].ldc = ldx;
+      ka.slab_out[0] = bf.slab_in;
+      LTD_HIP(fft_inverse_planes(g, ka, 1, cols, 1, s));
+      ka.slab_in[0] = bf.slab_in;
+      ka.slab_out[0] = bf.slab_out;
+      LTD_HIP(fft_lines(g, ka, 1, cols, FFT_MODE_V, sys->theta, s));
+      ka.slab_in[0] = bf.slab_out;
+      FwdOut fo{};
+      fo.o0 = out;
+      fo.ld0 = ld;
+      ka.out[0] = fo;
+      LTD_HIP(fft_forward_planes(g, ka, 1, cols, FFT_MODE_V, 0.0, 0.0, s));
+    }
+    const double2 *Ak = sys->amat + kh.amat_off;
+    LTD_TRY(gemm1(sys, OP_N, OP_N, zp(sys->n_a, cols, kh.n_g, Ak, sys->n_a, x, ldx, bf.W, nl), s));
+    if (sys->n_lo_tot > 0) LTD_HIP(launch_copy_rows(bf.W + sys->n_a, nl, x + kh.n_g, ldx, sys->n_lo_tot, cols, false, s));
+    std::vector<ZProb> p1, p2;
+    build_k2(sys, {sys->o}, bf.W, nl, {bf.Y}, nl, cols, p1, p2);
+    LTD_TRY(gemm(sys, OP_N, OP_N, p1, s));
+    LTD_TRY(gemm1(sys, OP_C, OP_N, zp(kh.n_g, cols, sys->n_a, Ak, sys->n_a, bf.Y, nl, out, ld, one, one), s));
+    if (sys->n_lo_tot > 0)
+      LTD_HIP(launch_copy_rows(out + kh.n_g, ld, bf.Y + sys->n_a, nl, sys->n_lo_tot, cols, false, s));
+  }
+  return LTD_OK;
+}
+
+// Y = S^{-1} B (n columns of N_basis rows, ld nb_max) by conjugate gradients from
+// Y = 0; convergence (every column's ||r|| <= tol ||b||) checked every 8 iterations.
+ltd_status cg_solve(ltd_system *sys, int k, const double2 *B, int n, double2 *Y, int max_iter, double tol,
+                    double *resid, int *iters, hipStream_t s) {
+  const int nb = sys->kh[k].n_basis, ld = sys->nb_max;
+  double2 *r = full_blk(sys, 5), *p = full_blk(sys, 6), *q = full_blk(sys, 7);
+  double2 *sc = sys->at<double2>(sys->o_fscal);
+  const int fc = std::min(1024, std::max(sys->max_cols, sys->n_states));
+  double2 *rr = sc, *pq = sc + fc, *rrn = sc + 2 * fc, *b2 = sc + 3 * fc;
+  LTD_HIP(launch_copy_rows(Y, ld, nullptr, 0, nb, n, true, s));
+  LTD_HIP(launch_copy_rows(r, ld, B, ld, nb, n, false, s));
+  LTD_HIP(launch_copy_rows(p, ld, B, ld, nb, n, false, s));
+  LTD_HIP(launch_col_dots(r, r, nb, n, ld, rr, s));
+  LTD_HIP(launch_col_dots(r, r, nb, n, ld, b2, s));
+  std::vector<double2> hr(n), hb(n);
+  double worst = 0.0;
+  int it = 0;
+  for (; it < max_iter;) {
+    LTD_TRY(apply_s(sys, 0 <= k ? k : 0, p, ld, n, q, ld, s));
+    LTD_HIP(launch_col_dots(p, q, nb, n, ld, pq, s));
+    LTD_HIP(launch_cg_step(Y, r, p, q, rr, pq, nb, n, ld, s));
+    LTD_HIP(launch_col_dots(r, r, nb, n, ld, rrn, s));
+    ++it;
+    if (it % 8 == 0 || it == max_iter) {
+      LTD_HIP(hipMemcpyAsync(hr.data(), rrn, n * sizeof(double2), hipMemcpyDeviceToHost, s));
+      LTD_HIP(hipMemcpyAsync(hb.data(), b2, n * sizeof(double2), hipMemcpyDeviceToHost, s));
+      LTD_HIP(hipStreamSynchronize(s));
+      worst = 0.0;
+      for (int j = 0; j < n; ++j) worst = std::max(worst, hb[j].x > 0.0 ? std::sqrt(hr[j].x / hb[j].x) : 0.0);
+      if (!std::isfinite(worst)) return LTD_ENONFINITE;
+      if (worst <= tol) break;
+    }
+    LTD_HIP(launch_cg_dir(p, r, rr, rrn, nb, n, ld, s));
+  }
+  *resid = worst;
+  *iters = it;
+  return LTD_OK;
+}
+
 ltd_status read_status(ltd_system *sys, hipStream_t s, int *st) {
   LTD_HIP(hipStreamSynchronize(s));
   LTD_HIP(hipMemcpy(st, sys->ws + sys->o_status, sizeof(int), hipMemcpyDeviceToHost));
@@ -1133,6 +1228,45 @@ ltd_status step_once(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
   return LTD_OK;
 }
 
+// Fork/join ledger of a capture, taken before it ends: every side stream that
+// joined the capture (it waited on an event of the capture stream's chain) must
+// have its last captured work among the ancestors of the capture stream's
+// current tail, i.e. joined back; otherwise LTD_ECAPTURE (the capture code left
+// work dangling, which the runtime would report, or mishandle, at the end).
+ltd_status check_joined(ltd_system *sys) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  unsigned long long id0 = 0;
+  const hipGraphNode_t *d0 = nullptr;
+  size_t n0 = 0;
+  LTD_HIP(hipStreamGetCaptureInfo_v2(sys->cap_stream, &cs, &id0, nullptr, &d0, &n0));
+  if (cs != hipStreamCaptureStatusActive) return LTD_ECAPTURE;
+  std::unordered_set<hipGraphNode_t> anc;
+  std::vector<hipGraphNode_t> todo(d0, d0 + n0), deps;
+  while (!todo.empty()) {
+    const hipGraphNode_t node = todo.back();
+    todo.pop_back();
+    if (!anc.insert(node).second) continue;
+    size_t nd = 0;
+    LTD_HIP(hipGraphNodeGetDependencies(node, nullptr, &nd));
+    if (nd == 0) continue;
+    deps.assign(nd, nullptr);
+    LTD_HIP(hipGraphNodeGetDependencies(node, deps.data(), &nd));
+    todo.insert(todo.end(), deps.begin(), deps.begin() + nd);
+  }
+  for (hipStream_t x : {sys->side, sys->side2, sys->side3}) {
+    if (!x) continue;
+    hipStreamCaptureStatus xs = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    const hipGraphNode_t *d = nullptr;
+    size_t nd = 0;
+    LTD_HIP(hipStreamGetCaptureInfo_v2(x, &xs, &id, nullptr, &d, &nd));
+    if (xs != hipStreamCaptureStatusActive || id != id0) continue;  // not forked in this capture
+    for (size_t i = 0; i < nd; ++i)
+      if (!anc.count(d[i])) return LTD_ECAPTURE;
+  }
+  return LTD_OK;
+}
+
 // k steps in one capture (a replay boundary per k steps); the graph is kept
 ltd_status capture_steps(ltd_system *sys, const ltd_step_args *a, int k, bool pipe, hipGraph_t *g,
                          hipGraphExec_t *x) {
@@ -1142,6 +1276,7 @@ ltd_status capture_steps(ltd_system *sys, const ltd_step_args *a, int k, bool pi
   ltd_status st = LTD_OK;
   for (int i = 0; i < k && st == LTD_OK; ++i)
     st = pipe ? pipelined_step(sys, a, sys->cap_stream, i == 0, i == k - 1) : step_once(sys, a, sys->cap_stream);
+  if (st == LTD_OK) st = check_joined(sys);
   hipGraph_t gr = nullptr;
   const hipError_t ec = hipStreamEndCapture(sys->cap_stream, &gr);
   if (st != LTD_OK) {
@@ -1204,6 +1339,7 @@ const char *ltd_status_string(ltd_status st) {
     case LTD_ENONFINITE: return "non-finite current or energy";
     case LTD_ESPECTRUM: return "subspace spectrum left the propagator interval";
     case LTD_ESTEP: return "time step above the critical time step of the explicit propagator";
+    case LTD_ECAPTURE: return "graph capture: a forked stream was not joined back";
     default: return "unknown status";
   }
 }
@@ -1425,6 +1561,11 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     sys->o_syn2 = ar.take((size_t)g.n3 * r.n2 * r.n1 * sizeof(double));
   }
   sys->o_subdev = ar.take(sys->n_k * sizeof(SubDev));
+  {
+    const int fc = std::min(1024, std::max(sys->max_cols, sys->n_states));
+    sys->o_full = ar.take((size_t)8 * sys->nb_max * fc * sizeof(double2));
+    sys->o_fscal = ar.take((size_t)4 * fc * sizeof(double2));
+  }
   sys->o_hstep = ar.take((size_t)std::max<long long>(1, sys->blk_elems) * sizeof(double2));
   const size_t k2cap_apply = (size_t)4 * sys->n_atoms * 3 * sizeof(ZProb) + 1024;
   sys->o_k2_hs1 = ar.take(k2cap_apply);
@@ -1654,6 +1795,91 @@ ltd_status ltd_apply_HS(ltd_system *sys, int k, const double a_vec[3], const voi
   double2 *outs[4] = {reinterpret_cast<double2 *>(HC), reinterpret_cast<double2 *>(SC), nullptr, nullptr};
   const int ldo[4] = {ldhc, ldsc, 0, 0};
   return apply_cols(sys, k, FFT_MODE_HS, a_vec[2], reinterpret_cast<const double2 *>(C), ldc, n, outs, ldo, S(stream));
+}
+
+ltd_status ltd_propagate_full(ltd_system *sys, int k, void *C, int ldc, int n, const ltd_full_args *fa, int n_steps,
+                              void *stream) {
+  if (!sys || !C || !fa || !fa->a_mid) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  if (k < 0 || k >= sys->n_k || n < 1 || n > std::min(1024, std::max(sys->max_cols, sys->n_states)) || n_steps < 0)
+    return LTD_ESHAPE;
+  const int nb = sys->kh[k].n_basis;
+  if (ldc < nb) return LTD_ESHAPE;
+  if (!aligned16(C)) return LTD_EALIGN;
+  if (fa->order < 1 || fa->order > TAYLOR_MAX || !std::isfinite(fa->dt) || fa->dt == 0.0 || !std::isfinite(fa->c0) ||
+      fa->cg_max_iter < 1 || !(fa->cg_tol > 0.0))
+    return LTD_EINVAL;
+  for (int i = 0; i < n_steps; ++i)
+    if (!std::isfinite(fa->a_mid[i])) return LTD_EINVAL;
+  hipStream_t s = S(stream);
+  double2 *x = reinterpret_cast<double2 *>(C);
+  double2 *term = full_blk(sys, 0), *acc = full_blk(sys, 1), *ht = full_blk(sys, 2), *st = full_blk(sys, 3);
+  double2 *y = full_blk(sys, 4);
+  double worst = 0.0;
+  int most = 0;
+  const int ld = sys->nb_max;
+  for (int step = 0; step < n_steps; ++step) {
+    const double a = fa->a_mid[step];
+    LTD_HIP(launch_copy_rows(term, ld, x, ldc, nb, n, false, s));
+    LTD_HIP(launch_copy_rows(acc, ld, x, ldc, nb, n, false, s));
+    for (int q = 1; q <= fa->order; ++q) {
+      double2 *outs[4] = {ht, st, nullptr, nullptr};
+      const int ldo[4] = {ld, ld, 0, 0};
+      LTD_TRY(apply_cols(sys, k, FFT_MODE_HS, a, term, ld, n, outs, ldo, s));
+      double res = 0.0;
+      int it = 0;
+      LTD_TRY(cg_solve(sys, k, ht, n, y, fa->cg_max_iter, fa->cg_tol, &res, &it, s));
+      worst = std::max(worst, res);
+      most = std::max(most, it);
+      // term <- (-i dt / q) (S^{-1} H term - c0 term), acc += term
+      LTD_HIP(launch_taylor_term(term, y, term, make_double2(0.0, -fa->dt / q), fa->c0, acc, nb, n, ld, s));
+    }
+    LTD_HIP(launch_copy_rows(x, ldc, acc, ld, nb, n, false, s));
+    LTD_HIP(launch_scale_block(x, make_double2(std::cos(fa->dt * fa->c0), -std::sin(fa->dt * fa->c0)), nb, n, ldc,
+                               s));
+  }
+  LTD_HIP(hipStreamSynchronize(s));
+  if (fa->cg_resid) *fa->cg_resid = worst;
+  if (fa->cg_iters) *fa->cg_iters = most;
+  return LTD_OK;
+}
+
+ltd_status ltd_full_spectrum(ltd_system *sys, int k, const void *x0, int iters, int cg_max_iter, double cg_tol,
+                             double *eps_max, void *stream) {
+  if (!sys || !x0 || !eps_max) return LTD_EINVAL;
+  if (!sys->ws) return LTD_ESTATE;
+  if (k < 0 || k >= sys->n_k || iters < 1 || cg_max_iter < 1 || !(cg_tol > 0.0)) return LTD_ESHAPE;
+  if (!aligned16(x0)) return LTD_EALIGN;
+  hipStream_t s = S(stream);
+  const int nb = sys->kh[k].n_basis, ld = sys->nb_max;
+  double2 *x = full_blk(sys, 0), *hx = full_blk(sys, 1), *sx = full_blk(sys, 2), *y = full_blk(sys, 3);
+  double2 *sc = sys->at<double2>(sys->o_fscal);
+  LTD_HIP(launch_copy_rows(x, ld, reinterpret_cast<const double2 *>(x0), nb, nb, 1, false, s));
+  double lam = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    double2 *outs[4] = {hx, sx, nullptr, nullptr};
+    const int ldo[4] = {ld, ld, 0, 0};
+    LTD_TRY(apply_cols(sys, k, FFT_MODE_HS, 0.0, x, ld, 1, outs, ldo, s));
+    LTD_HIP(launch_col_dots(x, hx, nb, 1, ld, sc, s));
+    LTD_HIP(launch_col_dots(x, sx, nb, 1, ld, sc + 1, s));
+    double2 h2[2];
+    LTD_HIP(hipMemcpyAsync(h2, sc, sizeof(h2), hipMemcpyDeviceToHost, s));
+    LTD_HIP(hipStreamSynchronize(s));
+    lam = h2[0].x / h2[1].x;
+    double res = 0.0;
+    int used = 0;
+    LTD_TRY(cg_solve(sys, k, hx, 1, y, cg_max_iter, cg_tol, &res, &used, s));
+    // x <- y / |y|
+    LTD_HIP(launch_col_dots(y, y, nb, 1, ld, sc, s));
+    double2 nn;
+    LTD_HIP(hipMemcpyAsync(&nn, sc, sizeof(nn), hipMemcpyDeviceToHost, s));
+    LTD_HIP(hipStreamSynchronize(s));
+    if (!(nn.x > 0.0) || !std::isfinite(nn.x)) return LTD_ENONFINITE;
+    LTD_HIP(launch_copy_rows(x, ld, y, ld, nb, 1, false, s));
+    LTD_HIP(launch_scale_block(x, make_double2(1.0 / std::sqrt(nn.x), 0.0), nb, 1, ld, s));
+  }
+  *eps_max = lam;
+  return LTD_OK;
 }
 
 ltd_status ltd_apply_HS_static(ltd_system *sys, int k, const double a_vec[3], const void *C, int ldc, int n,

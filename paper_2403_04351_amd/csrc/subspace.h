@@ -106,6 +106,22 @@ hipError_t launch_lookahead(int *rs, hipStream_t s);
 int assemble_blocks(int n);
 // hist + (*step mod hist_len) n_k n_states n_aux <- theta (the states before the step)
 hipError_t launch_record_theta(const StepCtx &c, double2 *hist, int hist_len, hipStream_t s);
+// Block conjugate gradients of the full-basis propagation, one column per
+// system (columns of N rows, ld ld): out[j] = sum_i conj(a_ij) b_ij (fixed order,
+// one workgroup per column)
+hipError_t launch_col_dots(const double2 *a, const double2 *b, int rows, int cols, int ld, double2 *out,
+                           hipStream_t s);
+// alpha_j = rr_j / Re pq_j; x_j += alpha_j p_j; r_j -= alpha_j q_j
+hipError_t launch_cg_step(double2 *x, double2 *r, const double2 *p, const double2 *q, const double2 *rr,
+                          const double2 *pq, int rows, int cols, int ld, hipStream_t s);
+// beta_j = rrn_j / rr_j; p_j = r_j + beta_j p_j; rr_j = rrn_j
+hipError_t launch_cg_dir(double2 *p, const double2 *r, double2 *rr, const double2 *rrn, int rows, int cols, int ld,
+                         hipStream_t s);
+// y = f (x - c0 z) (f complex), and acc += y when acc is set
+hipError_t launch_taylor_term(double2 *y, const double2 *x, const double2 *z, double2 f, double c0, double2 *acc,
+                              int rows, int cols, int ld, hipStream_t s);
+// y = f y
+hipError_t launch_scale_block(double2 *y, double2 f, int rows, int cols, int ld, hipStream_t s);
 // *loss = dmu[n] / omega
 hipError_t launch_pulse_loss(const double *dmu, int n, double omega, double *loss, hipStream_t s);
 hipError_t launch_adjoint(const StepCtx &c, const AdjCtx &a, hipStream_t s);

@@ -1043,6 +1043,108 @@ hipError_t launch_pulse_loss(const double *dmu, int n, double omega, double *los
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_col_dots(const double2 *a, const double2 *b, int rows, int ld,
+                                                 double2 *out) {
+  __shared__ double2 red[256];
+  const int c = blockIdx.x;
+  const double2 *ac = a + (long long)c * ld, *bc = b + (long long)c * ld;
+  double2 s = make_double2(0.0, 0.0);
+  for (int i = threadIdx.x; i < rows; i += 256) s = cadd(s, cmulc(ac[i], bc[i]));
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
+hipError_t launch_col_dots(const double2 *a, const double2 *b, int rows, int cols, int ld, double2 *out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_col_dots, dim3(cols), dim3(256), 0, s, a, b, rows, ld, out);
+  return hipGetLastError();
+}
+
+__global__ void k_cg_step(double2 *x, double2 *r, const double2 *p, const double2 *q, const double2 *rr,
+                          const double2 *pq, int rows, int cols, int ld) {
+  const long long tot = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows), c = (int)(e / rows);
+    const double den = pq[c].x;
+    const double al = den != 0.0 ? rr[c].x / den : 0.0;
+    const long long o = (long long)i + (long long)c * ld;
+    x[o] = cadd(x[o], cscale(p[o], al));
+    r[o] = csub(r[o], cscale(q[o], al));
+  }
+}
+
+hipError_t launch_cg_step(double2 *x, double2 *r, const double2 *p, const double2 *q, const double2 *rr,
+                          const double2 *pq, int rows, int cols, int ld, hipStream_t s) {
+  const long long tot = (long long)rows * cols;
+  const int nb = (int)std::min<long long>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_cg_step, dim3(nb), dim3(256), 0, s, x, r, p, q, rr, pq, rows, cols, ld);
+  return hipGetLastError();
+}
+
+__global__ void k_cg_dir(double2 *p, const double2 *r, double2 *rr, const double2 *rrn, int rows, int cols, int ld) {
+  const long long tot = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows), c = (int)(e / rows);
+    const double be = rr[c].x != 0.0 ? rrn[c].x / rr[c].x : 0.0;
+    const long long o = (long long)i + (long long)c * ld;
+    p[o] = cadd(r[o], cscale(p[o], be));
+  }
+}
+
+__global__ void k_copy_scalars(double2 *dst, const double2 *src, int n) {
+  if (threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+hipError_t launch_cg_dir(double2 *p, const double2 *r, double2 *rr, const double2 *rrn, int rows, int cols, int ld,
+                         hipStream_t s) {
+  const long long tot = (long long)rows * cols;
+  const int nb = (int)std::min<long long>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(256), 0, s, p, r, rr, rrn, rows, cols, ld);
+  hipLaunchKernelGGL(k_copy_scalars, dim3(1), dim3(1024), 0, s, rr, rrn, cols);
+  return hipGetLastError();
+}
+
+__global__ void k_taylor_term(double2 *y, const double2 *x, const double2 *z, double2 f, double c0, double2 *acc,
+                              int rows, int cols, int ld) {
+  const long long tot = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows), c = (int)(e / rows);
+    const long long o = (long long)i + (long long)c * ld;
+    const double2 v = cmul(f, csub(x[o], cscale(z[o], c0)));
+    y[o] = v;
+    if (acc) acc[o] = cadd(acc[o], v);
+  }
+}
+
+hipError_t launch_taylor_term(double2 *y, const double2 *x, const double2 *z, double2 f, double c0, double2 *acc,
+                              int rows, int cols, int ld, hipStream_t s) {
+  const long long tot = (long long)rows * cols;
+  const int nb = (int)std::min<long long>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_taylor_term, dim3(nb), dim3(256), 0, s, y, x, z, f, c0, acc, rows, cols, ld);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_block(double2 *y, double2 f, int rows, int cols, int ld) {
+  const long long tot = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows), c = (int)(e / rows);
+    const long long o = (long long)i + (long long)c * ld;
+    y[o] = cmul(f, y[o]);
+  }
+}
+
+hipError_t launch_scale_block(double2 *y, double2 f, int rows, int cols, int ld, hipStream_t s) {
+  const long long tot = (long long)rows * cols;
+  const int nb = (int)std::min<long long>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_scale_block, dim3(nb), dim3(256), 0, s, y, f, rows, cols, ld);
+  return hipGetLastError();
+}
+
 hipError_t launch_step(const StepCtx &c, hipStream_t s) {
   const hipError_t e0 = launch_assemble(c, s);
   if (e0 != hipSuccess) return e0;

@@ -152,6 +152,26 @@ class Ltd:
               "ltd_ritz_basis")
         return eps
 
+    def propagate_full(self, k: int, c, dt: float, order: int, c0: float, a_mid, cg_max_iter: int = 500,
+                       cg_tol: float = 1e-13):
+        """Advances c (tensor (n, N_basis), in place) len(a_mid) explicit steps in the
+        full basis; returns (largest CG residual, most CG iterations)."""
+        a = np.ascontiguousarray(np.asarray(a_mid, dtype=np.float64))
+        res, its = C.c_double(), C.c_int()
+        fa = _lib.FullArgs(dt=dt, order=order, c0=c0, a_mid=a.ctypes.data_as(C.POINTER(C.c_double)),
+                           cg_max_iter=cg_max_iter, cg_tol=cg_tol, cg_resid=C.pointer(res), cg_iters=C.pointer(its))
+        n, nb = c.shape
+        check(self.lib.ltd_propagate_full(self.handle, k, _ptr(c), nb, n, C.byref(fa), len(a), self.stream()),
+              "ltd_propagate_full")
+        return res.value, its.value
+
+    def full_spectrum(self, k: int, x0, iters: int = 60, cg_max_iter: int = 500, cg_tol: float = 1e-12):
+        """Largest eigenvalue of the full (H0, S) by power iteration from x0 (tensor (N_basis,))."""
+        e = C.c_double()
+        check(self.lib.ltd_full_spectrum(self.handle, k, _ptr(x0), iters, cg_max_iter, cg_tol, C.byref(e),
+                                         self.stream()), "ltd_full_spectrum")
+        return e.value
+
     def subspace_info(self, k: int):
         a, b, d = C.c_double(), C.c_double(), C.c_double()
         check(self.lib.ltd_subspace_info(self.handle, k, C.byref(a), C.byref(b), C.byref(d)), "ltd_subspace_info")

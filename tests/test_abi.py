@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings(lib):
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1, 2, 3, 4):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, 1, 2, 3, 4, 5):
         assert lib.ltd_status_string(code).decode()
     assert lib.ltd_status_string(0).decode() == "ok"
 
@@ -144,6 +144,16 @@ def test_calls_before_binding_are_rejected(lib, sys0):
     assert lib.ltd_bind_workspace(h, 0x1000, 16, None) == _lib.LTD_EWORKSPACE
     assert lib.ltd_bind_workspace(h, None, wsb.value, None) == _lib.LTD_EINVAL
     assert lib.ltd_subspace_info(h, 0, None, None, None) == _lib.LTD_ESTATE
+    am = (C.c_double * 1)(0.1)
+    res, its = C.c_double(), C.c_int()
+    fa = _lib.FullArgs(dt=0.01, order=4, c0=0.0, a_mid=am, cg_max_iter=10, cg_tol=1e-12, cg_resid=C.pointer(res),
+                       cg_iters=C.pointer(its))
+    assert lib.ltd_propagate_full(h, 0, 4096, 208, 1, C.byref(fa), 1, None) == _lib.LTD_ESTATE
+    assert lib.ltd_propagate_full(h, 0, None, 208, 1, C.byref(fa), 1, None) == _lib.LTD_EINVAL
+    assert lib.ltd_propagate_full(h, 0, 4096, 208, 1, None, 1, None) == _lib.LTD_EINVAL
+    e = C.c_double()
+    assert lib.ltd_full_spectrum(h, 0, 4096, 10, 10, 1e-12, C.byref(e), None) == _lib.LTD_ESTATE
+    assert lib.ltd_full_spectrum(h, 0, None, 10, 10, 1e-12, C.byref(e), None) == _lib.LTD_EINVAL
     assert lib.ltd_destroy(h) == 0
 
 

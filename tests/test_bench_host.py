@@ -35,7 +35,9 @@ def test_stage_work_of_the_molecule_workload(molecule):
 
 def test_traffic_counters_apply_only_to_their_own_source_and_workload():
     path = os.path.join(ROOT, "profiles", "traffic_counters.json")
-    rec = json.load(open(path))
+    recs = json.load(open(path))
+    assert isinstance(recs, list) and recs
+    rec = recs[0]
     cur = bench.traffic_from_profiles("fft.hip", rec["stage"], rec["precision"], rec["config"])
     import hashlib
 
