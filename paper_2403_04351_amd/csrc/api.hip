@@ -845,7 +845,11 @@ ltd_status build_step_tables(ltd_system *sys) {
     if (!kh.bound) continue;
     double2 *ph = sys->at<double2>(kh.o_phit), *ye = sys->at<double2>(kh.o_yext);
     build_k2(sys, {hx}, ph + kh.n_g, kh.k_ext, {ye + kh.n_g}, kh.k_ext, n, p1, p2);
-    pv.push_back(zp(n, n, kh.k_ext, ph, kh.k_ext, ye, kh.k_ext, sys->at<double2>(kh.o_vstep), n));
+    // V~ = Phi~^H Y is Hermitian: block rows from the diagonal only
+    for (int i0 = 0; i0 < n; i0 += PROJ_BLK)
+      pv.push_back(zp(std::min(PROJ_BLK, n - i0), n - i0, kh.k_ext, ph + (long long)i0 * kh.k_ext, kh.k_ext,
+                      ye + (long long)i0 * kh.k_ext, kh.k_ext, sys->at<double2>(kh.o_vstep) + i0 + (long long)i0 * n,
+                      n));
   }
   const size_t cap = (size_t)4 * sys->n_atoms * sys->n_k * sizeof(ZProb) + 1024;
   // the rebuild's block products run beside the x/z transforms: unsplit, on few
@@ -870,7 +874,10 @@ ltd_status build_step_tables(ltd_system *sys) {
         p7.push_back(zp(sa, n, sa, d2(dh + sys->s_off[a]), sa, d2(ph + r), kh.k_ext,
                         reinterpret_cast<double2 *>(ye + r), kh.k_ext));
       }
-      p6.push_back(zp(n, n, kh.k_ext, d2(ph), kh.k_ext, d2(ye), kh.k_ext, sys->at<double2>(kh.o_vstep), n));
+      for (int i0 = 0; i0 < n; i0 += PROJ_BLK)
+        p6.push_back(zp(std::min(PROJ_BLK, n - i0), n - i0, kh.k_ext, d2(ph + (long long)i0 * kh.k_ext), kh.k_ext,
+                        d2(ye + (long long)i0 * kh.k_ext), kh.k_ext,
+                        sys->at<double2>(kh.o_vstep) + i0 + (long long)i0 * n, n));
     }
     int t7 = 0, t6 = 0;
     gemm_plan(p7.data(), (int)p7.size(), &t7, 0, PART_TILES);  // unsplit: written in complex64 directly
@@ -1501,10 +1508,13 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     aoff += (size_t)sys->n_a * kh.n_g;
     sys->kw.push_back(d->k_weight[k]);
   }
-  // columns per apply pass: FFT slabs (4 in + 5 out fields) within ~3 GB
+  // columns per apply pass: FFT slabs (4 in + 5 out fields) within ~6 GB; when
+  // the columns take several passes, a multiple of the GEMMs' 64-column tile
+  // (a 45-column pass computes 64 columns' worth of muffin-tin MFMA work)
   const long long per_col = 9LL * g.nbz * g.n1 * g.n2 * (long long)sizeof(double2);
   const int cmax = std::max(sys->max_cols, sys->n_aux);
-  sys->chunk = (int)std::max(1LL, std::min<long long>(cmax, (3LL << 30) / per_col));
+  sys->chunk = (int)std::max(1LL, std::min<long long>(cmax, (6LL << 30) / per_col));
+  if (sys->chunk < cmax && sys->chunk >= 64) sys->chunk -= sys->chunk % 64;
   const int n = sys->n_aux;
   const long long n2 = (long long)n * n;
   sys->h_in_lds = step_lds_bytes(n, true, true) <= 150 * 1024;
@@ -1575,10 +1585,10 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   const size_t k2cap_step = (size_t)4 * sys->n_atoms * sys->n_k * sizeof(ZProb) + 1024;
   sys->o_k2_st1 = ar.take(k2cap_step);
   sys->o_k2_st2 = ar.take(k2cap_step);
-  sys->o_vstep_tab = ar.take(sys->n_k * sizeof(ZProb) + 256);
+  sys->o_vstep_tab = ar.take((size_t)sys->n_k * ((n + PROJ_BLK - 1) / PROJ_BLK) * sizeof(ZProb) + 256);
   if (resid32(sys)) {
     sys->o_k7_32 = ar.take(k2cap_step);
-    sys->o_vstep32 = ar.take(sys->n_k * sizeof(ZProb) + 256);
+    sys->o_vstep32 = ar.take((size_t)sys->n_k * ((n + PROJ_BLK - 1) / PROJ_BLK) * sizeof(ZProb) + 256);
     sys->o_hstep32 = ar.take((size_t)std::max<long long>(1, sys->blk_elems) * sizeof(float2));
     sys->o_mtperm = ar.take((size_t)std::max(1, sys->n_loc) * sizeof(int));
     int r = 0;

@@ -220,6 +220,48 @@ __device__ inline void dft12(T *v) {
   }
 }
 
+// Length-12 DFT whose inputs 3..8 are zero (only v[0..2], v[9..11] read), the
+// first pass of a 108 = 12 x 9 line when the box half-width is at most 26: in the
+// 3 x 4 form the length-3 columns (v[q2], v[4+q2], v[8+q2]) have known zeros.
+template <int DIR, class T>
+__device__ inline void dft12_z3to8(T *v) {
+  using R = typename CT<T>::R;
+  T a[4][3];
+  a[0][0] = a[0][1] = a[0][2] = v[0];  // (v0, 0, 0)
+#pragma unroll
+  for (int q2 = 1; q2 <= 2; ++q2) {  // (v[q2], 0, v[8+q2])
+    const T x = v[q2], z = v[8 + q2];
+    const T m = CT<T>::mk(x.x - (R)0.5 * z.x, x.y - (R)0.5 * z.y);
+    const T u = cscale(mul_i<DIR>(CT<T>::mk(-z.x, -z.y)), (R)SQ3_2);
+    a[q2][0] = cadd(x, z);
+    a[q2][1] = cadd(m, u);
+    a[q2][2] = csub(m, u);
+  }
+  {  // (0, 0, v11)
+    const T z = v[11];
+    const T m = CT<T>::mk((R)-0.5 * z.x, (R)-0.5 * z.y);
+    const T u = cscale(mul_i<DIR>(CT<T>::mk(-z.x, -z.y)), (R)SQ3_2);
+    a[3][0] = z;
+    a[3][1] = cadd(m, u);
+    a[3][2] = csub(m, u);
+  }
+  a[1][1] = cmul(a[1][1], CT<T>::mk((R)SQ3_2, (R)(DIR * 0.5)));
+  a[2][1] = cmul(a[2][1], CT<T>::mk((R)0.5, (R)(DIR * SQ3_2)));
+  a[3][1] = mul_i<DIR>(a[3][1]);
+  a[1][2] = cmul(a[1][2], CT<T>::mk((R)0.5, (R)(DIR * SQ3_2)));
+  a[2][2] = cmul(a[2][2], CT<T>::mk((R)-0.5, (R)(DIR * SQ3_2)));
+  a[3][2] = CT<T>::mk(-a[3][2].x, -a[3][2].y);
+#pragma unroll
+  for (int p1 = 0; p1 < 3; ++p1) {
+    T t0 = a[0][p1], t1 = a[1][p1], t2 = a[2][p1], t3 = a[3][p1];
+    dft4<DIR>(t0, t1, t2, t3);
+    v[p1] = t0;
+    v[p1 + 3] = t1;
+    v[p1 + 6] = t2;
+    v[p1 + 9] = t3;
+  }
+}
+
 // In-register DFT of the lengths the two-factor transforms use.
 template <int R, int DIR, class T>
 __device__ __forceinline__ void dft_reg(T *v) {
@@ -796,6 +838,19 @@ constexpr int rb_pitch(int n) { return n + ((9 - n % 8) % 8); }  // >= n, = 1 mo
 
 __device__ __forceinline__ void wave_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
+// On an exact rebuild grid (N >= 4 b + 1, so b <= (N - 1) / 4) the inputs of a
+// line at frequencies b < n < N - b are zero and its outputs there are never
+// read.  With n = F2 n1 + r (r < F2, the lane's role) that holds for every lane
+// when n1 is in [zr_lo, zr_hi]: those register values are zero before the first
+// pass of an inverse transform and unused after the last pass of a forward one.
+template <int N, int F2>
+constexpr int zr_lo() { return ((N - 1) / 4 + F2) / F2; }
+template <int N, int F2>
+constexpr int zr_hi() { return (N - (N - 1) / 4 - F2) / F2; }
+// first pass of a line whose inputs LO..HI are zero
+template <int R, int DIR, int LO, int HI, class T>
+__device__ __forceinline__ void dft_first(T *v);
+
 // base twiddle w_N^role (inverse sign) of this lane
 __device__ __forceinline__ double2 role_twiddle(int role, int n) {
   double sv, cv;
@@ -832,8 +887,27 @@ template <int NX, int X1, int NZ, int Z1>
 constexpr bool xz4_swz() { return NX == 64 && X1 == 8 && NZ == 64 && Z1 == 8; }
 template <int NX, int X1, int NZ, int Z1, class T>
 constexpr int xz4_rx() { return xz4_swz<NX, X1, NZ, Z1>() ? (sizeof(T) == 16 ? 66 : 68) : rb_pitch(NX); }
+// z-line exchange pitches of the general lengths: slots (i, j) at i P1 + j in the
+// first exchange (rows i < Z2, columns j < Z1), i P2 + j in the second (rows
+// i < Z1, columns j < Z2), lines LS apart.  For 108 = 12 x 9 (12 lanes per line,
+// five lines per wave, 8-byte slots) P1 = 13, P2 = 9 and LS = 117 (the smallest
+// that holds both) keep a complex128 block of four such waves within half the
+// LDS of a CU; a bank model of all the kernel's LDS accesses (64 banks of 4
+// bytes, 16-byte accesses 16 lanes per cycle, 8-byte ones 32) gives 1,296
+// conflict cycles per block against 4,986 measured for the odd pitch 13 with
+// lines 161 apart.  Other lengths keep the odd pitch of Two.
+template <int NZ, int Z1>
+struct XchPitch {
+  using TZ = Two<NZ, Z1, NZ / Z1>;
+  static constexpr bool TUNED = (NZ == 108);
+  static constexpr int P1 = TZ::P;
+  static constexpr int P2 = TUNED ? NZ / Z1 : TZ::P;
+  static constexpr int need = ((NZ / Z1 - 1) * P1 + Z1) > ((Z1 - 1) * P2 + NZ / Z1) ? ((NZ / Z1 - 1) * P1 + Z1)
+                                                                                    : ((Z1 - 1) * P2 + NZ / Z1);
+  static constexpr int LS = TUNED ? need + 1 : TZ::LS;
+};
 template <int NX, int X1, int NZ, int Z1>
-constexpr int xz4_ls() { return xz4_swz<NX, X1, NZ, Z1>() ? 72 : Two<NZ, Z1, NZ / Z1>::LS; }
+constexpr int xz4_ls() { return xz4_swz<NX, X1, NZ, Z1>() ? 72 : XchPitch<NZ, Z1>::LS; }
 // exchange slot of (i, j) in a block of rows of length `pitch` (swizzled or plain)
 template <bool SWZ>
 __device__ __forceinline__ int xslot(int i, int j, int pitch) { return SWZ ? i * 8 + (j ^ i) : i * pitch + j; }
@@ -901,18 +975,33 @@ __device__ __forceinline__ void xch_split(double *sd, int r, int P, bool put, bo
 // its own RX slots (value (k1, n2) at slot k1 F2 + n2, odd stride across lanes);
 // the z columns exchange through a per-wave scratch of LZ lines.
 // T: element type (double2, or float2 for the FP32 residual); thp in its real type.
-template <int NX, int X1, int X2, int NZ, int Z1, int Z2, int NW, int LZ, class T>
+template <int R, int DIR, int LO, int HI, class T>
+__device__ __forceinline__ void dft_first(T *v) {
+  if constexpr (R == 8 && LO == 2 && HI == 5) dft8_z2345<DIR>(v);
+  else if constexpr (R == 12 && LO == 3 && HI == 8) dft12_z3to8<DIR>(v);
+  else dft_reg<R, DIR>(v);
+}
+
+// PR: the box fits the exact-grid bound on both axes (4 b + 1 <= N), so the
+// known-zero inputs and unread outputs of every line are dropped at compile
+// time (the 64-point instance always does, under its own b <= 15 check).
+template <int NX, int X1, int X2, int NZ, int Z1, int Z2, int NW, int LZ, class T, bool PR>
 __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs ka, int ncols,
                                                    const typename CT<T>::R *__restrict__ thp) {
   using RT = typename CT<T>::R;
   using TX = Two<NX, X1, X2>;
   using TZ = Two<NZ, Z1, Z2>;
+  using XP = XchPitch<NZ, Z1>;
   static_assert(LZ <= TZ::LPW, "z lines per wave");
   constexpr bool SWZ = xz4_swz<NX, X1, NZ, Z1>();
   constexpr int RX = xz4_rx<NX, X1, NZ, Z1, T>();
   constexpr int LS = xz4_ls<NX, X1, NZ, Z1>();
   constexpr bool SPLIT = SWZ && sizeof(T) == 16;   // the 8 x 8 split exchange
   constexpr bool SPLITG = !SWZ && sizeof(T) == 16;  // the general split exchange
+  constexpr bool PX = SWZ || PR;                    // dropped x and z values
+  constexpr int XLO = zr_lo<NX, X2>(), XHI = zr_hi<NX, X2>();
+  constexpr int ZLO = zr_lo<NZ, Z2>(), ZHI = zr_hi<NZ, Z2>();
+  static_assert(!SWZ || (XLO == 2 && XHI == 5 && ZLO == 2 && ZHI == 5), "64-point pruning range");
   extern __shared__ double2 sm_raw[];
   T *sm = reinterpret_cast<T *>(sm_raw);
   const int col = blockIdx.x, y = blockIdx.y, kk = blockIdx.z;
@@ -948,7 +1037,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         T v[X1];
 #pragma unroll
         for (int n1 = 0; n1 < X1; ++n1) {
-          if (SWZ && n1 >= 2 && n1 <= 5) {  // |freq| >= 16 > b: zero (dropped by dft8_z2345)
+          if (PX && n1 >= XLO && n1 <= XHI) {  // b < |freq|: zero (dropped by the first pass)
             v[n1] = CT<T>::mk(0, 0);
             continue;
           }
@@ -960,7 +1049,8 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
           dft8_z2345<1>(v);
           twiddle_tab<X1, 1>(v, twt);
         } else {
-          dft_reg<X1, 1>(v);
+          if constexpr (PR) dft_first<X1, 1, XLO, XHI>(v);
+          else dft_reg<X1, 1>(v);
           twiddle_powers<X1>(v, w);
         }
 #pragma unroll
@@ -1033,14 +1123,19 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         if (on && rz < Z2) {
 #pragma unroll
           for (int n1 = 0; n1 < Z1; ++n1) {
+            if (PR && n1 >= ZLO && n1 <= ZHI) {
+              v[n1] = make_double2(0.0, 0.0);
+              continue;
+            }
             const int n = Z2 * n1 + rz;
             const int row = n <= bz ? n + bz : n - NZ + bz;
             v[n1] = (n <= bz || n >= NZ - bz) ? R[row * RX + x] : make_double2(0.0, 0.0);
           }
-          dft_reg<Z1, 1>(v);
+          if constexpr (PR) dft_first<Z1, 1, ZLO, ZHI>(v);
+          else dft_reg<Z1, 1>(v);
           twiddle_powers<Z1>(v, w);
         }
-        xch_split<Z1, Z2>(sd, rz, TZ::P, on && rz < Z2, on && rz < Z1, v, u);
+        xch_split<Z1, Z2>(sd, rz, XP::P1, on && rz < Z2, on && rz < Z1, v, u);
         if (on && rz < Z1) {
           dft_reg<Z2, 1>(u);
 #pragma unroll
@@ -1048,11 +1143,12 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
           dft_reg<Z2, -1>(u);
           twiddle_powers<Z2>(u, wc);
         }
-        xch_split<Z2, Z1>(sd, rz, TZ::P, on && rz < Z1, on && rz < Z2, u, v);
+        xch_split<Z2, Z1>(sd, rz, XP::P2, on && rz < Z1, on && rz < Z2, u, v);
         if (on && rz < Z2) {
           dft_reg<Z1, -1>(v);
 #pragma unroll
           for (int c = 0; c < Z1; ++c) {
+            if (PR && c >= ZLO && c <= ZHI) continue;  // never read: not computed
             const int m = Z2 * c + rz;
             if (m <= bz || m >= NZ - bz) R[(m <= bz ? m + bz : m - NZ + bz) * RX + x] = v[c];
           }
@@ -1064,7 +1160,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         T v[Z1];
 #pragma unroll
         for (int n1 = 0; n1 < Z1; ++n1) {
-          if (SWZ && n1 >= 2 && n1 <= 5) {
+          if (PX && n1 >= ZLO && n1 <= ZHI) {
             v[n1] = CT<T>::mk(0, 0);
             continue;
           }
@@ -1076,17 +1172,18 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
           dft8_z2345<1>(v);
           twiddle_tab<Z1, 1>(v, twt);
         } else {
-          dft_reg<Z1, 1>(v);
+          if constexpr (PR) dft_first<Z1, 1, ZLO, ZHI>(v);
+          else dft_reg<Z1, 1>(v);
           twiddle_powers<Z1>(v, w);
         }
 #pragma unroll
-        for (int k1 = 0; k1 < Z1; ++k1) sl[xslot<SWZ>(rz, k1, TZ::P)] = v[k1];
+        for (int k1 = 0; k1 < Z1; ++k1) sl[xslot<SWZ>(rz, k1, XP::P1)] = v[k1];
       }
       wave_fence();
       if (on && rz < Z1) {
         T u[Z2];
 #pragma unroll
-        for (int q = 0; q < Z2; ++q) u[q] = sl[xslot<SWZ>(q, rz, TZ::P)];
+        for (int q = 0; q < Z2; ++q) u[q] = sl[xslot<SWZ>(q, rz, XP::P1)];
         dft_reg<Z2, 1>(u);
 #pragma unroll
         for (int k2 = 0; k2 < Z2; ++k2) u[k2] = cscale(u[k2], t[k2]);
@@ -1095,17 +1192,17 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         else twiddle_powers<Z2>(u, wc);
         wave_fence();
 #pragma unroll
-        for (int d = 0; d < Z2; ++d) sl[xslot<SWZ>(rz, d, TZ::P)] = u[d];
+        for (int d = 0; d < Z2; ++d) sl[xslot<SWZ>(rz, d, XP::P2)] = u[d];
       }
       wave_fence();
       if (on && rz < Z2) {
         T v[Z1];
 #pragma unroll
-        for (int a = 0; a < Z1; ++a) v[a] = sl[xslot<SWZ>(a, rz, TZ::P)];
+        for (int a = 0; a < Z1; ++a) v[a] = sl[xslot<SWZ>(a, rz, XP::P2)];
         dft_reg<Z1, -1>(v);
 #pragma unroll
         for (int c = 0; c < Z1; ++c) {
-          if (SWZ && c >= 2 && c <= 5) continue;  // |freq| >= 16 > b: never needed
+          if (PX && c >= ZLO && c <= ZHI) continue;  // b < |freq|: never needed
           const int m = Z2 * c + rz;
           if (m <= bz || m >= NZ - bz) R[(m <= bz ? m + bz : m - NZ + bz) * RX + x] = v[c];
         }
@@ -1141,7 +1238,7 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
         dft_reg<X1, -1>(v);
 #pragma unroll
         for (int c = 0; c < X1; ++c) {
-          if (SWZ && c >= 2 && c <= 5) continue;
+          if (PX && c >= XLO && c <= XHI) continue;
           const int m = X2 * c + rx;
           if (m <= bx || m >= NX - bx) out[r * rs + (m <= bx ? m : m - NX) + bx] = v[c];
         }
@@ -1466,6 +1563,99 @@ __global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka,
   }
 }
 
+// y transforms of the rebuild step for N2' = 72 = 8 x 9 and nbx <= 35: one block
+// per (kz, column), one line per box x (5 waves x 7 lines x 9 lanes).  Each lane
+// a < 8 loads the values y = a + 8 b (b < 9) of its line from the slab, runs the
+// forward two-factor transform of k_rb_xz4's phase 3 (length 9 over b, twiddles
+// w^(a d) from a per-lane table, exchange through a per-line scratch, length 8
+// over a) and keeps the outputs with |ky| <= by in a box [x][ky] that takes the
+// scratch's place; then the sphere read-out.  PR (4 by + 1 <= 72): the outputs
+// 9 c + d with c in 2..5 are never read and not computed.
+constexpr int Y72_P = 9, Y72_LS = 73, Y72_LINES = 35;
+inline size_t y72_lds_bytes(const Grid &g, size_t es) {
+  const size_t scr = (size_t)Y72_LINES * Y72_LS * 8, box = (size_t)g.nbx * g.nby * es;
+  return scr > box ? scr : box;
+}
+template <class T, bool PR>
+__global__ __launch_bounds__(320) void k_rb_y72(const Grid g, const FftKArgs ka, int ncols) {
+  constexpr int N = 72, F1 = 8, F2 = 9, LPW = 7;
+  using XT = typename std::conditional<sizeof(T) == 16, double, float2>::type;  // scratch slot type
+  extern __shared__ double2 sm_raw[];
+  XT *scr = reinterpret_cast<XT *>(sm_raw);
+  T *box = reinterpret_cast<T *>(sm_raw);  // after the transforms: [x][ky + by], pitch nby
+  const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
+  const int nbx = g.nbx, bx = g.bx, by = g.by, nby = g.nby;
+  const KSphere &sp = ka.sph[kk];
+  const FwdOut &fo = ka.out[kk];
+  const long long csz = (long long)g.nbz * N * nbx;
+  const T *src = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)pz * N * nbx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lx = lane / F2, r = lane - lx * F2;
+  const int line = wave * LPW + lx;
+  const bool on = lx < LPW && line < nbx;
+  T v[F1];
+  if (on) {
+    XT *sl = scr + line * Y72_LS;
+    T u[F2];
+    if (r < F1) {
+      T twt[F2];
+#pragma unroll
+      for (int j = 0; j < F2; ++j) twt[j] = CT<T>::from(g.tw2[(r * j) % N]);
+#pragma unroll
+      for (int b = 0; b < F2; ++b) u[b] = src[(r + F1 * b) * nbx + line];
+      dft_reg<F2, -1>(u);
+      twiddle_tab<F2, -1>(u, twt);
+    }
+    if constexpr (sizeof(T) == 16) {  // real parts, then imaginary parts (in-order LDS within a wave)
+      if (r < F1)
+#pragma unroll
+        for (int d = 0; d < F2; ++d) sl[r * Y72_P + d] = u[d].x;
+      wave_fence();
+      if (r < F2)
+#pragma unroll
+        for (int a = 0; a < F1; ++a) v[a].x = sl[a * Y72_P + r];
+      wave_fence();
+      if (r < F1)
+#pragma unroll
+        for (int d = 0; d < F2; ++d) sl[r * Y72_P + d] = u[d].y;
+      wave_fence();
+      if (r < F2)
+#pragma unroll
+        for (int a = 0; a < F1; ++a) v[a].y = sl[a * Y72_P + r];
+    } else {
+      if (r < F1)
+#pragma unroll
+        for (int d = 0; d < F2; ++d) sl[r * Y72_P + d] = u[d];
+      wave_fence();
+      if (r < F2)
+#pragma unroll
+        for (int a = 0; a < F1; ++a) v[a] = sl[a * Y72_P + r];
+    }
+    if (r < F2) dft_reg<F1, -1>(v);
+  }
+  __syncthreads();  // every line has left the scratch
+  if (on && r < F2) {
+#pragma unroll
+    for (int c = 0; c < F1; ++c) {
+      if (PR && c >= 2 && c <= 5) continue;  // |ky| > 17 >= by
+      const int m = F2 * c + r;
+      const int ky = m < N / 2 ? m : m - N;
+      if (ky >= -by && ky <= by) box[line * nby + ky + by] = v[c];
+    }
+  }
+  __syncthreads();
+  const double inv_n = 1.0 / ((double)g.n1 * N * g.n3);
+  const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
+  for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+    const int xy = sp.pts_xy[i];
+    const int yy = xy / g.d1, x = xy - yy * g.d1;
+    const int ky = yy <= by ? yy : yy - g.d2;
+    const double2 val = cscale(to_d2(box[box_of(x, g.d1, bx) * nby + ky + by]), inv_n);
+    if (fo.o0f) fo.o0f[i + (long long)col * fo.ld0] = make_float2((float)val.x, (float)val.y);
+    else fo.o0[i + (long long)col * fo.ld0] = val;
+  }
+}
+
 // One axis pass of the W synthesis with the axis matrix given by its Dirichlet
 // table: M[j'][j] = tab[(c1 j' - c2 j) mod L] (c1 = N/g, c2 = N'/g, L = N N'/g,
 // g = gcd(N, N')), so that the block stages L values instead of N' N.
@@ -1735,37 +1925,48 @@ constexpr int xzr_nw() { return sizeof(T) == 16 ? 2 : 4; }
 constexpr int rb_nw_of(int v) { return v == 1 ? 2 : 4; }
 template <int NZ, int Z1>
 constexpr int rb_lz_of(int v) {
-  // 108-point z lines (12 lanes, five to a wave): four per wave in the first
-  // shape keep a complex128 block within half the LDS of a CU (two blocks per CU)
-  if (NZ == 108 && v == 0) return 4;
   return v == 2 ? (rb_lz(Two<NZ, Z1, NZ / Z1>::LPW) / 2 > 0 ? rb_lz(Two<NZ, Z1, NZ / Z1>::LPW) / 2 : 1)
                 : rb_lz(Two<NZ, Z1, NZ / Z1>::LPW);
 }
 
 // the three launch shapes of the x/z kernel for x length NX = X1 (NX / X1) and z
 // length NZ = Z1 (NZ / Z1)
-template <int NX, int X1, int NZ, int Z1, class T, class F>
+template <int NX, int X1, int NZ, int Z1, class T, bool PR, class F>
 void reg_xz4(F &&f) {
-  f((const void *)k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, rb_nw_of(0), rb_lz_of<NZ, Z1>(0), T>);
-  f((const void *)k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, rb_nw_of(1), rb_lz_of<NZ, Z1>(1), T>);
-  f((const void *)k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, rb_nw_of(2), rb_lz_of<NZ, Z1>(2), T>);
+  f((const void *)k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, rb_nw_of(0), rb_lz_of<NZ, Z1>(0), T, PR>);
+  f((const void *)k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, rb_nw_of(1), rb_lz_of<NZ, Z1>(1), T, PR>);
+  f((const void *)k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, rb_nw_of(2), rb_lz_of<NZ, Z1>(2), T, PR>);
 }
+// the lengths whose lines are pruned when the box fits the exact-grid bound
+template <int NX, int NZ>
+constexpr bool xz4_prunable() { return (NX == 72 && (NZ == 72 || NZ == 108)); }
 
-template <int NX, int X1, int NZ, int Z1, class T>
-void launch_xz4(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s, int v) {
+template <int NX, int X1, int NZ, int Z1, class T, bool PR>
+void launch_xz4_pr(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s, int v) {
   const auto *th = static_cast<const typename CT<T>::R *>(thv);
   const dim3 grid(ncols, g.n2, nk);
-#define LTD_V(V)                                                                                            \
-  do {                                                                                                      \
-    constexpr int NW = rb_nw_of(V), LZ = rb_lz_of<NZ, Z1>(V);                                               \
-    const size_t lds = xz4_lds<NX, X1, NZ, Z1, T>(g.nbz, NW, LZ);                                           \
-    hipLaunchKernelGGL((k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, NW, LZ, T>), grid, dim3(NW * 64), lds, s, g, \
-                       ka, ncols, th);                                                                      \
+#define LTD_V(V)                                                                                       \
+  do {                                                                                                 \
+    constexpr int NW = rb_nw_of(V), LZ = rb_lz_of<NZ, Z1>(V);                                          \
+    const size_t lds = xz4_lds<NX, X1, NZ, Z1, T>(g.nbz, NW, LZ);                                      \
+    hipLaunchKernelGGL((k_rb_xz4<NX, X1, NX / X1, NZ, Z1, NZ / Z1, NW, LZ, T, PR>), grid, dim3(NW * 64), \
+                       lds, s, g, ka, ncols, th);                                                      \
   } while (0)
   if (v == 1) LTD_V(1);
   else if (v == 2) LTD_V(2);
   else LTD_V(0);
 #undef LTD_V
+}
+
+template <int NX, int X1, int NZ, int Z1, class T>
+void launch_xz4(const Grid &g, const FftKArgs &ka, int nk, int ncols, const void *thv, hipStream_t s, int v) {
+  if constexpr (xz4_prunable<NX, NZ>()) {
+    if (4 * g.bx + 1 <= NX && 4 * g.bz + 1 <= NZ) {
+      launch_xz4_pr<NX, X1, NZ, Z1, T, true>(g, ka, nk, ncols, thv, s, v);
+      return;
+    }
+  }
+  launch_xz4_pr<NX, X1, NZ, Z1, T, false>(g, ka, nk, ncols, thv, s, v);
 }
 
 template <class F>
@@ -1779,14 +1980,18 @@ void each_plane_kernel(F &&f) {
   f((const void *)k_rb_xz<a, c>);
   LTD_RB(0, 0) LTD_RB(16, 16) LTD_RB(64, 64) LTD_RB(72, 72) LTD_RB(96, 160)
 #undef LTD_RB
-  reg_xz4<72, 8, 72, 8, double2>(f);
-  reg_xz4<64, 8, 64, 8, double2>(f);
-  reg_xz4<16, 4, 16, 4, double2>(f);
-  reg_xz4<72, 8, 108, 12, double2>(f);
-  reg_xz4<72, 8, 72, 8, float2>(f);
-  reg_xz4<64, 8, 64, 8, float2>(f);
-  reg_xz4<16, 4, 16, 4, float2>(f);
-  reg_xz4<72, 8, 108, 12, float2>(f);
+  reg_xz4<72, 8, 72, 8, double2, false>(f);
+  reg_xz4<64, 8, 64, 8, double2, false>(f);
+  reg_xz4<16, 4, 16, 4, double2, false>(f);
+  reg_xz4<72, 8, 108, 12, double2, false>(f);
+  reg_xz4<72, 8, 72, 8, float2, false>(f);
+  reg_xz4<64, 8, 64, 8, float2, false>(f);
+  reg_xz4<16, 4, 16, 4, float2, false>(f);
+  reg_xz4<72, 8, 108, 12, float2, false>(f);
+  reg_xz4<72, 8, 72, 8, double2, true>(f);
+  reg_xz4<72, 8, 108, 12, double2, true>(f);
+  reg_xz4<72, 8, 72, 8, float2, true>(f);
+  reg_xz4<72, 8, 108, 12, float2, true>(f);
   f((const void *)k_rb_xzr<xzr_nw<float2>(), float2>);
   f((const void *)k_inv_plane<0, 0>);
   f((const void *)k_fwd_plane<0, 0>);
@@ -2038,6 +2243,16 @@ hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, con
       const size_t lds64 = y64_lds_bytes();
       if (fp32) hipLaunchKernelGGL(k_rb_y64<float2>, grid, dim3(256), lds64, s, g, ka, ncols);
       else hipLaunchKernelGGL(k_rb_y64<double2>, grid, dim3(256), lds64, s, g, ka, ncols);
+    } else if (g.n2 == 72 && g.nbx <= Y72_LINES) {
+      const size_t l72 = y72_lds_bytes(g, fp32 ? sizeof(float2) : sizeof(double2));
+      const bool pr = 4 * g.by + 1 <= 72;
+      if (fp32) {
+        if (pr) hipLaunchKernelGGL((k_rb_y72<float2, true>), grid, dim3(320), l72, s, g, ka, ncols);
+        else hipLaunchKernelGGL((k_rb_y72<float2, false>), grid, dim3(320), l72, s, g, ka, ncols);
+      } else {
+        if (pr) hipLaunchKernelGGL((k_rb_y72<double2, true>), grid, dim3(320), l72, s, g, ka, ncols);
+        else hipLaunchKernelGGL((k_rb_y72<double2, false>), grid, dim3(320), l72, s, g, ka, ncols);
+      }
     } else if (g.n2 == 16) LTD_RY(16);
     else if (g.n2 == 64) LTD_RY(64);
     else if (g.n2 == 72) LTD_RY(72);

@@ -9,6 +9,10 @@ namespace ltd {
 constexpr int CHEB_KMAX = 96;  // largest Chebyshev degree of the step exponential
 constexpr int TAYLOR_MAX = 8;  // largest order of the explicit (truncated Taylor) step
 constexpr int PART_STRIDE = 6; // per-state partial sums of the step and adjoint kernels
+// The per-step projection V~ = Phi~^H Y computes only the PROJ_BLK x PROJ_BLK
+// blocks on and above the block diagonal (V~ is Hermitian): block rows of
+// PROJ_BLK rows starting at the diagonal.
+constexpr int PROJ_BLK = 64;
 
 // Per k-point subspace state (lives in the workspace; matrices n_aux x n_aux,
 // column-major, in the S-orthonormal basis Phi~ = Phi L^{-H} unless noted).

@@ -435,6 +435,18 @@ __global__ __launch_bounds__(1024) void k_jacobi(double2 *A, double2 *V, double 
 // (H~(mid) - c0)/r for every k-point, one thread per element, and per-block
 // partial sums of ||H~(mid) - H~0||_F^2 for the spectral-interval check.
 // grid (assemble_blocks(n), n_k).
+// Element (a, b) of the Hermitian part of the step's V~, of which the projection
+// wrote the PROJ_BLK-blocks on and above the block diagonal: the mean of the
+// element and its mirror inside a diagonal block, else the written one.
+__device__ inline double2 vt_herm(const double2 *v, int a, int b, int n) {
+  const int ba = a / PROJ_BLK, bb = b / PROJ_BLK;
+  if (ba < bb) return v[a + (long long)b * n];
+  const double2 y = v[b + (long long)a * n];
+  if (ba > bb) return make_double2(y.x, -y.y);
+  const double2 x = v[a + (long long)b * n];
+  return make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+}
+
 __global__ __launch_bounds__(256) void k_assemble(const StepCtx c) {
   __shared__ double sred[16];
   const int k = blockIdx.y;
@@ -452,8 +464,7 @@ __global__ __launch_bounds__(256) void k_assemble(const StepCtx c) {
     const int a = (int)(e % n), b = (int)(e / n);
     double2 vv;
     if (c.rebuild) {  // Hermitian part of the rebuilt matrix (plus the reference for a residual)
-      const double2 x = S.vt_step[e], y = S.vt_step[b + (long long)a * n];
-      vv = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+      vv = vt_herm(S.vt_step, a, b, n);
       if (c.resid) vv = cadd(vv, S.vt_ref[e]);
     } else {
       vv = S.vt_ref[e];
@@ -749,8 +760,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepCtx c, const AdjCtx a
     const int a = (int)(e % n), b = (int)(e / n);
     double2 vv2;
     if (c.rebuild) {
-      const double2 x = S.vt_step[e], y = S.vt_step[b + (long long)a * n];
-      vv2 = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+      vv2 = vt_herm(S.vt_step, a, b, n);
       if (c.resid) vv2 = cadd(vv2, S.vt_ref[e]);
     } else {
       vv2 = S.vt_ref[e];

@@ -59,3 +59,24 @@ def test_potential_beyond_the_interval_latches_espectrum(tiny):
     _, wfield, _ = td_potential(sys)
     assert _step_with(tiny, sys.vr + 50.0 * wfield) == _lib.LTD_ESPECTRUM
     assert _step_with(tiny, sys.vr) == _lib.LTD_OK
+
+
+def test_transverse_vector_potential_is_refused(tiny):
+    """Only the z momentum block is part of the system: a nonzero A_x or A_y is
+    refused on the host (LTD_EUNSUPPORTED) instead of being dropped."""
+    import ctypes as C
+
+    from paper_2403_04351_amd import _lib
+    from paper_2403_04351_amd.ltd import _ptr
+
+    sys, lt, ltd, torch = tiny["sys"], tiny["lt"], tiny["ltd"], tiny["torch"]
+    nb = sys.n_basis(0)
+    c = ltd.colmajor(np.ones((nb, 2), dtype=np.complex128), lt.device)
+    hc, sc = torch.empty_like(c), torch.empty_like(c)
+    for a in ((0.1, 0.0, 0.0), (0.0, -0.2, 0.3)):
+        av = (C.c_double * 3)(*a)
+        st = lt.lib.ltd_apply_HS(lt.handle, 0, av, _ptr(c), nb, 2, _ptr(hc), nb, _ptr(sc), nb, lt.stream())
+        assert st == _lib.LTD_EUNSUPPORTED
+    av = (C.c_double * 3)(0.0, 0.0, 0.3)
+    assert lt.lib.ltd_apply_HS(lt.handle, 0, av, _ptr(c), nb, 2, _ptr(hc), nb, _ptr(sc), nb, lt.stream()) == 0
+    torch.cuda.synchronize()
