@@ -412,6 +412,9 @@ def main():
     hbm_stages = {k: v for k, v in prof.items() if k in sb}
     dom = max(hbm_stages, key=hbm_stages.get)
     dom_us = hbm_stages[dom]
+    affine_only = dom_us <= 0.0  # AFFINE: no rebuild stage ran; the step is the exponential
+    if affine_only:
+        dom_us = 1.0
     achieved = sb[dom] / (dom_us * 1e-6) / 1e9
     kernel_file = "fft.hip" if dom in ("potential", "xz_planes", "y_lines") else "api.hip"
     traffic = traffic_from_profiles(kernel_file, dom, args.precision, args.config)
@@ -430,6 +433,8 @@ def main():
                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, bytes_per_launch=sb[dom],
                         avg_launch_us=dom_us)
 
+    if affine_only:
+        roofline = None
     # H-apply MFMA rate: the muffin-tin GEMMs of one apply at n = N_aux
     apms, _, _ = lt.profile_apply(0, phi)
     n = sysd.n_aux

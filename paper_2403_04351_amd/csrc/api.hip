@@ -51,7 +51,8 @@ struct KHost {
   int n_g, n_basis, k_ext;
   size_t g_off;            // first G of this k in the concatenated arrays
   size_t amat_off;         // element offset of A_k
-  std::vector<int> plane_ptr, pts_g, pts_xy;
+  std::vector<int> plane_ptr, pts_g, pts_xy, pts_xy_a;
+  size_t o_ptsxy_a = 0;
   // workspace offsets
   size_t o_gk, o_pptr, o_ptsg, o_ptsxy;
   size_t o_subs;           // Tsub, Vsub, Psub, Ssub (4 n^2, Phi basis)
@@ -97,6 +98,12 @@ struct ltd_system {
   Grid grid{};
   Grid rgrid{};
   bool rb_synth = false;
+  // the FFT-route apply on the rebuild grid (exact: the products it forms need
+  // Theta~ and (Theta V)~ only at differences of two box frequencies), with
+  // Theta and Theta V synthesised there in grid order and sphere tables in its
+  // coordinates
+  bool ap_red = false;
+  size_t o_th_ap = 0, o_thv_ap = 0, o_ones = 0;
   int rb_variant = 0;      // launch shape of the x/z rebuild kernel (tuned)
   int vproj_target = 512;  // block target of the projection GEMM's K split (tuned)
   // side stream of the rebuild: the muffin-tin branch runs beside the FFT chain
@@ -383,6 +390,13 @@ KSphere sphere_of(const ltd_system *sys, int k) {
   return sp;
 }
 
+// grid, sphere tables and Theta V of the apply's interstitial passes
+KSphere sphere_ap(const ltd_system *sys, int k) {
+  KSphere sp = sphere_of(sys, k);
+  if (sys->ap_red) sp.pts_xy = sys->at<int>(sys->kh[k].o_ptsxy_a);
+  return sp;
+}
+
 // bytes per value of the rebuild cache and step slabs (complex64 for the FP32 residual)
 size_t rb_elem(const ltd_system *sys) {
   return sys->precision == LTD_FP32_RESID ? sizeof(float2) : sizeof(double2);
@@ -409,6 +423,16 @@ Grid rgrid_of(const ltd_system *sys) {
 }
 
 bool resid32(const ltd_system *sys) { return sys->precision == LTD_FP32_RESID; }
+
+Grid agrid_of(const ltd_system *sys) {
+  if (!sys->ap_red) return grid_of(sys);
+  Grid g = rgrid_of(sys);
+  g.theta = sys->at<double>(sys->o_th_ap);
+  return g;
+}
+const double *athv_of(const ltd_system *sys) {
+  return sys->at<double>(sys->ap_red ? sys->o_thv_ap : sys->o_thv);
+}
 
 // Theta v in the layout of the rebuild step (W on the rebuild grid when it is
 // smaller); v read at v + (*step) * stride when step is not NULL.  resid: the
@@ -505,7 +529,7 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
                        double2 *const out[4], const int ldo[4], hipStream_t s, Prof *pf, const ApplyBufs &bf) {
   if (cols <= 0) return LTD_OK;
   const KHost &kh = sys->kh[k];
-  const Grid g = grid_of(sys);
+  const Grid g = agrid_of(sys);
   const double al = a_z / sys->c_light, be = a_z * a_z / (2.0 * sys->c_light * sys->c_light);
   if (sys->route == LTD_ROUTE_MM) {  // interstitial by the dense blocks (first route)
     LTD_TRY(apply_mm(sys, k, mode, al, be, C, ldc, cols, out, ldo, bf, s));
@@ -514,7 +538,7 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   }
   // interstitial
   FftKArgs ka{};
-  ka.sph[0] = sphere_of(sys, k);
+  ka.sph[0] = sphere_ap(sys, k);
   ka.in[0].c = C;
   ka.in[0].ldc = ldc;
   ka.slab_out[0] = bf.slab_in;
@@ -522,7 +546,7 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   LTD_MARK(pf, 0);
   ka.slab_in[0] = bf.slab_in;
   ka.slab_out[0] = bf.slab_out;
-  LTD_HIP(fft_lines(g, ka, 1, cols, FFT_MODE_HS, sys->at<double>(sys->o_thv), s));
+  LTD_HIP(fft_lines(g, ka, 1, cols, FFT_MODE_HS, athv_of(sys), s));
   LTD_MARK(pf, 1);
   ka.slab_in[0] = bf.slab_out;
   FwdOut fo{};
@@ -627,7 +651,8 @@ char *static_scratch() {
 // Columns per pass of an apply whose scratch is the static array (0: not even one
 // column fits), and the buffers of such a pass laid out from `base`.
 int static_cols(const ltd_system *sys, int n) {
-  const long long slab_col = (long long)sys->grid.nbz * sys->n1 * sys->n2;
+  const Grid &ag = sys->ap_red ? sys->rgrid : sys->grid;
+  const long long slab_col = (long long)ag.nbz * ag.n1 * ag.n2;
   const size_t fixed = up((size_t)std::max<long long>(1, sys->blk_elems) * sizeof(double2)) +
                        up((size_t)STATIC_PART_TILES * 64 * 64 * sizeof(double2));
   // per column: 4 + 5 slab fields, W and two Y blocks, plus alignment slack of four arrays
@@ -638,7 +663,8 @@ int static_cols(const ltd_system *sys, int n) {
 }
 
 ApplyBufs static_bufs(const ltd_system *sys, char *base, int cols) {
-  const long long slab_f = (long long)sys->grid.nbz * sys->n1 * sys->n2 * cols;
+  const Grid &ag = sys->ap_red ? sys->rgrid : sys->grid;
+  const long long slab_f = (long long)ag.nbz * ag.n1 * ag.n2 * cols;
   Arena ar;
   ApplyBufs b{};
   b.slab_in = reinterpret_cast<double2 *>(base + ar.take((size_t)4 * slab_f * sizeof(double2)));
@@ -689,16 +715,16 @@ ltd_status apply_s(ltd_system *sys, int k, const double2 *X, int ldx, int n, dou
       LTD_TRY(gemm1(sys, OP_N, OP_N, zp(kh.n_g, cols, kh.n_g, sys->at<double2>(kh.o_mmS), kh.n_g, x, ldx, out, ld),
                     s));
     } else {
-      const Grid g = grid_of(sys);
+      const Grid g = agrid_of(sys);
       FftKArgs ka{};
-      ka.sph[0] = sphere_of(sys, k);
+      ka.sph[0] = sphere_ap(sys, k);
       ka.in[0].c = x;
       ka.in[0].ldc = ldx;
       ka.slab_out[0] = bf.slab_in;
       LTD_HIP(fft_inverse_planes(g, ka, 1, cols, 1, s));
       ka.slab_in[0] = bf.slab_in;
       ka.slab_out[0] = bf.slab_out;
-      LTD_HIP(fft_lines(g, ka, 1, cols, FFT_MODE_V, sys->theta, s));
+      LTD_HIP(fft_lines(g, ka, 1, cols, FFT_MODE_V, g.theta, s));
       ka.slab_in[0] = bf.slab_out;
       FwdOut fo{};
       fo.o0 = out;
@@ -1125,7 +1151,7 @@ ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s
       if (a->theta_hist)  // the states before the step, for a checkpointed backward pass
         LTD_HIP(launch_record_theta(exp_ctx, reinterpret_cast<double2 *>(a->theta_hist), a->hist_len, sys->side2));
       LTD_HIP(hipEventRecord(sys->ev_asm, sys->side2));
-      LTD_HIP(launch_step_only(exp_ctx, sys->side2));
+      LTD_HIP(launch_step_only(exp_ctx, sys->side2, true));
     }
     if (a->v_r_t && k0 + FFT_MAXK >= sys->n_k) {  // Theta V read: the next step's synthesis
       LTD_HIP(hipEventRecord(sys->ev_xz, s));
@@ -1463,6 +1489,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
       delete sys;
       return LTD_EUNSUPPORTED;
     }
+    sys->ap_red = sys->rb_synth && sys->route == LTD_ROUTE_FFT;
   }
   if (fft_plane_lds_bytes(g) > 160 * 1024 || fft_line_lds_bytes(g) > 160 * 1024) {
     delete sys;
@@ -1500,6 +1527,11 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
         const int x = (gi[0] % g.n1 + g.n1) % g.n1, y = (gi[1] % g.n2 + g.n2) % g.n2;
         kh.pts_g.push_back(i);
         kh.pts_xy.push_back(y * g.n1 + x);
+        if (sys->ap_red) {
+          const int rn1 = sys->rgrid.n1, rn2 = sys->rgrid.n2;
+          const int xa = (gi[0] % rn1 + rn1) % rn1, ya = (gi[1] % rn2 + rn2) % rn2;
+          kh.pts_xy_a.push_back(ya * rn1 + xa);
+        }
       }
       kh.plane_ptr.push_back((int)kh.pts_g.size());
     }
@@ -1511,7 +1543,8 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   // columns per apply pass: FFT slabs (4 in + 5 out fields) within ~6 GB; when
   // the columns take several passes, a multiple of the GEMMs' 64-column tile
   // (a 45-column pass computes 64 columns' worth of muffin-tin MFMA work)
-  const long long per_col = 9LL * g.nbz * g.n1 * g.n2 * (long long)sizeof(double2);
+  const Grid &ag = sys->ap_red ? sys->rgrid : g;  // grid of the apply's FFT passes
+  const long long per_col = 9LL * ag.nbz * ag.n1 * ag.n2 * (long long)sizeof(double2);
   const int cmax = std::max(sys->max_cols, sys->n_aux);
   sys->chunk = (int)std::max(1LL, std::min<long long>(cmax, (6LL << 30) / per_col));
   if (sys->chunk < cmax && sys->chunk >= 64) sys->chunk -= sys->chunk % 64;
@@ -1527,6 +1560,12 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_thv = ar.take(sys->ngrid * sizeof(double));
   sys->o_thv_rb = ar.take(sys->ngrid * sizeof(double));
   sys->o_thv_step = ar.take(sys->ngrid * sizeof(double));
+  if (sys->ap_red) {
+    const size_t rn = (size_t)sys->rgrid.n1 * sys->rgrid.n2 * sys->rgrid.n3;
+    sys->o_th_ap = ar.take(rn * sizeof(double));
+    sys->o_thv_ap = ar.take(rn * sizeof(double));
+    sys->o_ones = ar.take(sys->ngrid * sizeof(double));
+  }
   // [0..1] status, [8] step-kernel block counter, [12..13] and [14..15] step index
   // and last step of the pipelined rebuild (muffin-tin branch, potential synthesis)
   sys->o_status = ar.take(64);
@@ -1534,7 +1573,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_partials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
   sys->o_vpartials = ar.take((size_t)PART_TILES * 64 * 64 * sizeof(double2));
   const bool mm = sys->route == LTD_ROUTE_MM;
-  const long long slab_f = mm ? 0 : (long long)g.nbz * g.n1 * g.n2 * sys->chunk;
+  const long long slab_f = mm ? 0 : (long long)ag.nbz * ag.n1 * ag.n2 * sys->chunk;
   sys->o_slab_in = ar.take(4 * slab_f * sizeof(double2));
   sys->o_slab_out = ar.take(5 * slab_f * sizeof(double2));
   sys->o_W = ar.take((size_t)sys->n_loc * sys->chunk * sizeof(double2));
@@ -1603,6 +1642,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     kh.o_pptr = ar.take((size_t)(g.nbz + 1) * sizeof(int));
     kh.o_ptsg = ar.take((size_t)kh.n_g * sizeof(int));
     kh.o_ptsxy = ar.take((size_t)kh.n_g * sizeof(int));
+    if (sys->ap_red) kh.o_ptsxy_a = ar.take((size_t)kh.n_g * sizeof(int));
     kh.o_subs = ar.take((size_t)4 * n2 * sizeof(double2));
     kh.o_tilde = ar.take((size_t)4 * n2 * sizeof(double2));
     kh.o_L = ar.take((size_t)n2 * sizeof(double2));
@@ -1704,6 +1744,8 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
     LTD_HIP(hipMemcpy(sys->ws + kh.o_pptr, kh.plane_ptr.data(), kh.plane_ptr.size() * sizeof(int), hipMemcpyHostToDevice));
     LTD_HIP(hipMemcpy(sys->ws + kh.o_ptsg, kh.pts_g.data(), kh.n_g * sizeof(int), hipMemcpyHostToDevice));
     LTD_HIP(hipMemcpy(sys->ws + kh.o_ptsxy, kh.pts_xy.data(), kh.n_g * sizeof(int), hipMemcpyHostToDevice));
+    if (sys->ap_red)
+      LTD_HIP(hipMemcpy(sys->ws + kh.o_ptsxy_a, kh.pts_xy_a.data(), kh.n_g * sizeof(int), hipMemcpyHostToDevice));
     kh.bound = false;
   }
   std::vector<int> zero(16, 0);
@@ -1719,6 +1761,20 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
   LTD_HIP(launch_thv(sys->at<double>(sys->o_thv), sys->theta, sys->v_r, sys->ngrid, s));
   if (sys->route == LTD_ROUTE_FFT) {
     LTD_TRY(rebuild_potential(sys, sys->v_r, nullptr, 0, sys->at<double>(sys->o_thv_rb), false, s));
+    if (sys->ap_red) {  // Theta and Theta V of the bound potential on the apply grid, grid order
+      const std::vector<double> ones(sys->ngrid, 1.0);
+      LTD_HIP(hipMemcpy(sys->ws + sys->o_ones, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
+      const auto syn = [&](const double *v, size_t off) -> ltd_status {
+        LTD_HIP(fft_rb_synth(rgrid_of(sys), sys->n1, sys->n2, sys->n3, sys->theta, v, nullptr, 0,
+                             sys->at<double>(sys->o_M1), sys->at<double>(sys->o_M2), sys->at<double>(sys->o_M3),
+                             sys->at<double>(sys->o_F1), sys->at<double>(sys->o_F2), sys->at<double>(sys->o_F3),
+                             sys->at<double>(sys->o_syn1), sys->at<double>(sys->o_syn2), sys->at<double>(off),
+                             nullptr, false, s, true));
+        return LTD_OK;
+      };
+      LTD_TRY(syn(sys->at<double>(sys->o_ones), sys->o_th_ap));
+      LTD_TRY(syn(sys->v_r, sys->o_thv_ap));
+    }
   } else {  // the dense interstitial blocks of every k-point (natural G order)
     const Grid g = grid_of(sys);
     double2 *bt = sys->at<double2>(sys->o_box_t), *bv = sys->at<double2>(sys->o_box_v);

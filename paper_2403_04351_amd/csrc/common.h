@@ -238,11 +238,12 @@ int fft_rb_frag_len(int n, int np);
 void fft_rb_frag(int n, int np, const double *tab, double *mf);
 // mf_d: the fragments of M_d (device), used where n_d is 16, 64, 72 or 96; the
 // tables otherwise.  sub != NULL: out = W - sub (same layout); fp32: out is
-// float, else double.
+// float, else double.  plain: out in grid order [z'][y'][x'] instead of the
+// order of the x/z rebuild kernel.
 hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th, const double *v,
                         const int *step, long long stride, const double *tab1, const double *tab2,
                         const double *tab3, const double *mf1, const double *mf2, const double *mf3, double *t1,
-                        double *t2, void *out, const double *sub, bool fp32, hipStream_t s);
+                        double *t2, void *out, const double *sub, bool fp32, hipStream_t s, bool plain = false);
 size_t fft_line_lds_bytes(const Grid &g);
 
 // ----------------------------------------------------------------------------

@@ -2003,7 +2003,7 @@ void each_plane_kernel(F &&f) {
 #define LTD_LK(a)                               \
   f((const void *)k_lines<a, true>);            \
   f((const void *)k_lines<a, false>);
-  LTD_LK(0) LTD_LK(16) LTD_LK(64) LTD_LK(72) LTD_LK(160)
+  LTD_LK(0) LTD_LK(16) LTD_LK(64) LTD_LK(72) LTD_LK(108) LTD_LK(160)
 #undef LTD_LK
 }
 
@@ -2105,7 +2105,7 @@ bool syn_mfma(int N, dim3 grid, hipStream_t s, const double *in, const double *t
 hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th, const double *v,
                         const int *step, long long stride, const double *tab1, const double *tab2,
                         const double *tab3, const double *mf1, const double *mf2, const double *mf3, double *t1,
-                        double *t2, void *out, const double *sub, bool fp32, hipStream_t s) {
+                        double *t2, void *out, const double *sub, bool fp32, hipStream_t s, bool plain) {
   static bool attr = false;
   if (!attr) {
     for (const void *k : {(const void *)k_syn_pass<32, true, double>, (const void *)k_syn_pass<16, false, double>,
@@ -2137,17 +2137,18 @@ hipError_t fft_rb_synth(const Grid &gr, int n1, int n2, int n3, const double *th
     pass(k_syn_pass<16, false, double>, 16, t1, nullptr, nullptr, t2, nullptr, tab2, n2, gr.n2, n3, gr.n1, 0);
   // z: [n3][n2' n1'] -> the k_rb_xz4 order (minus sub, in FP32 for the residual)
   const long long pz = (long long)gr.n2 * gr.n1;
+  const int pn = plain ? 0 : gr.n1;  // 0: grid order
   if (fp32) {
     if (!syn_mfma<false, false, float>(n3, grid_of(gr.n3, pz), s, t2, nullptr, nullptr, 0, static_cast<float *>(out),
-                                       sub, mf3, rb(gr.n3), 1, (int)pz, gr.n3, gr.n1, z1, z2))
+                                       sub, mf3, rb(gr.n3), 1, (int)pz, gr.n3, pn, z1, z2))
       pass(k_syn_pass<16, false, float>, 16, t2, nullptr, nullptr, static_cast<float *>(out), sub, tab3, n3, gr.n3, 1,
-           gr.n2 * gr.n1, gr.n1);
+           gr.n2 * gr.n1, pn);
   } else {
     if (!syn_mfma<false, false, double>(n3, grid_of(gr.n3, pz), s, t2, nullptr, nullptr, 0,
-                                        static_cast<double *>(out), sub, mf3, rb(gr.n3), 1, (int)pz, gr.n3, gr.n1, z1,
+                                        static_cast<double *>(out), sub, mf3, rb(gr.n3), 1, (int)pz, gr.n3, pn, z1,
                                         z2))
       pass(k_syn_pass<16, false, double>, 16, t2, nullptr, nullptr, static_cast<double *>(out), sub, tab3, n3, gr.n3,
-           1, gr.n2 * gr.n1, gr.n1);
+           1, gr.n2 * gr.n1, pn);
   }
   return hipGetLastError();
 }
@@ -2298,6 +2299,8 @@ hipError_t fft_lines(const Grid &g, const FftKArgs &ka, int nk, int ncols, int m
     LTD_LN(64);
   } else if (g.n3 == 72) {
     LTD_LN(72);
+  } else if (g.n3 == 108) {
+    LTD_LN(108);
   } else if (g.n3 == 160) {
     LTD_LN(160);
   } else {

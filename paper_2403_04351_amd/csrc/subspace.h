@@ -101,7 +101,9 @@ hipError_t launch_step(const StepCtx &c, hipStream_t s);
 // The two halves of launch_step: H~(mid) of the step (k_assemble), then the
 // exponential, observables and step counter (k_step).
 hipError_t launch_assemble(const StepCtx &c, hipStream_t s);
-hipError_t launch_step_only(const StepCtx &c, hipStream_t s);
+// beside: the launch runs beside other kernels (the pipelined rebuild), which
+// prefers fewer, longer blocks for the large-subspace form
+hipError_t launch_step_only(const StepCtx &c, hipStream_t s, bool beside = false);
 // rs[0] = rs[2] = *step, rs[1] = rs[3] = *step + n_steps - 1 (two step-index counters
 // of one propagate call, each with its last step)
 hipError_t launch_lookahead_init(const int *step, int n_steps, int *rs, hipStream_t s);

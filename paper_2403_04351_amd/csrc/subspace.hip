@@ -523,6 +523,9 @@ __device__ void finalize_step(const StepCtx &c, int step) {
 
 // Threads per state block of the forward step (512 measured no faster).
 constexpr int STEP_NT = 256;
+// the row-per-thread step: the largest n (six vectors per state in LDS, one
+// thread per row, at most 1024 threads)
+constexpr int STEP_MULTI_MAXN = 768;
 
 // reduction slots (double2) of the forward step kernel: one per thread, or the
 // NW n partial sums of the wide products when H~ is not LDS-resident
@@ -680,6 +683,174 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
   if (c.nexc_out) excited(part + 4);
 
   // 6. the last block to finish: fixed-order sum, series, step counter
+  __syncthreads();
+  int *last = reinterpret_cast<int *>(sred);
+  if (threadIdx.x == 0) {
+    __threadfence();
+    *last = atomicAdd(c.done, 1) == (int)(gridDim.x * gridDim.y) - 1;
+  }
+  __syncthreads();
+  if (!*last || threadIdx.x != 0) return;
+  __threadfence();
+  finalize_step(c, step);
+  *c.done = 0;
+}
+
+// ---------------------------------------------------------------------------
+// The same step for NS states per block (blockIdx.x covers states NS x, ...,
+// NS x + NS - 1), for subspaces whose matrices stay in global memory: one block
+// thread per matrix row (blockDim = 64 ceil(n / 64)), each product Y_s = A X_s
+// reads A once for all NS states (row i of every product in thread i, columns
+// in order, no cross-wave reduction).  Per state the arithmetic is that of
+// k_step<false, false> except the summation order inside the products.
+// ---------------------------------------------------------------------------
+template <int NS, int UN>
+__device__ void matvec_rows(const double2 *__restrict__ A, int lda, const double2 *X, double2 *Y, int n) {
+  const int i = threadIdx.x;
+  if (i < n) {
+    double2 acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = make_double2(0.0, 0.0);
+    const double2 *a = A + i;
+    int k = 0;
+    for (; k + UN <= n; k += UN) {
+      double2 av[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) av[u] = a[(long long)(k + u) * lda];
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = cfma(av[u], X[s * n + k + u], acc[s]);
+    }
+    for (; k < n; ++k) {
+      const double2 av = a[(long long)k * lda];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[s] = cfma(av, X[s * n + k], acc[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Y[s * n + i] = acc[s];
+  }
+  __syncthreads();
+}
+
+template <int NS, int UN>
+__global__ __launch_bounds__(1024) void k_step_multi(const StepCtx c) {
+  extern __shared__ double2 sm[];
+  const int k = blockIdx.y;
+  const int j0 = blockIdx.x * NS;
+  const int ns = (c.n_states - j0) < NS ? (c.n_states - j0) : NS;  // states of this block
+  const SubDev &S = c.sub[k];
+  const int n = c.n_aux;
+  const int bd = blockDim.x;
+  double2 *v = sm, *t0 = sm + NS * n, *t1 = sm + 2 * NS * n, *acc = sm + 3 * NS * n, *tmp = sm + 4 * NS * n;
+  double2 *w = sm + 5 * NS * n;
+  double *sred = reinterpret_cast<double *>(sm + 6 * NS * n);
+  const auto mv = [&](const double2 *A, const double2 *x, double2 *y) { matvec_rows<NS, UN>(A, n, x, y, n); };
+  const int step = *c.step;
+  const double am = c.a_mid[step], a1 = c.a_t[step + 1];
+  const double cl = c.c_light;
+  const double2 *Hm = S.hm;
+
+  if (blockIdx.x == 0 && threadIdx.x < 64) {  // spectral check (one wave, fixed-order sum)
+    double dev2 = 0.0;
+    const long long n2 = (long long)n * n;
+    const int nb = (int)((n2 + 255) / 256);
+    for (int q = threadIdx.x; q < nb; q += 64) dev2 += S.dev[q];
+    dev2 = wave_sum(dev2);
+    if (threadIdx.x == 0 && !isfinite(dev2)) latch(c.status, 3);
+    else if (threadIdx.x == 0 && !(sqrt(dev2) <= S.margin)) latch(c.status, 4);
+  }
+
+  // theta~ = L^H theta (states past n_states: zero vectors, results discarded)
+  double2 *th0 = c.theta + (long long)k * n * c.n_states + (long long)j0 * n;
+  for (int e = threadIdx.x; e < NS * n; e += bd) tmp[e] = (e / n < ns) ? th0[e] : make_double2(0.0, 0.0);
+  __syncthreads();
+  mv(S.LH, tmp, v);
+
+  auto observe = [&](double a, int slot_j, int slot_e, bool ref) {
+    mv(ref ? S.h0t : Hm, v, t0);
+    mv(S.pt, v, t1);
+    for (int s = 0; s < ns; ++s) {
+      double vv = 0.0, vp = 0.0, vm = 0.0;
+      for (int i = threadIdx.x; i < n; i += bd) {
+        const double2 x = v[s * n + i], p = t1[s * n + i], m = t0[s * n + i];
+        vv += x.x * x.x + x.y * x.y;
+        vp += x.x * p.x + x.y * p.y;
+        vm += x.x * m.x + x.y * m.y;
+      }
+      block_sum3(vv, vp, vm, sred);
+      const double vh = ref ? vm + (a / cl) * vp + (a * a / (2.0 * cl * cl)) * vv
+                            : S.r * vm + S.c0 * vv + ((a - am) / cl) * vp + ((a * a - am * am) / (2.0 * cl * cl)) * vv;
+      if (threadIdx.x == 0) {
+        double *part = c.part + PART_STRIDE * ((long long)k * c.n_states + j0 + s);
+        part[slot_j] = -(c.occ / c.omega) * S.kw * (vp + (a / cl) * vv);
+        part[slot_e] = c.occ * S.kw * vh;
+      }
+    }
+  };
+  auto excited = [&](int slot) {
+    for (int s = 0; s < ns; ++s) {
+      double nn = 0.0, oc = 0.0;
+      for (int i = threadIdx.x; i < n; i += bd) nn += v[s * n + i].x * v[s * n + i].x + v[s * n + i].y * v[s * n + i].y;
+      for (int i = threadIdx.x; i < c.n_states; i += bd) {
+        double2 sv = make_double2(0.0, 0.0);
+        for (int q = 0; q <= i; ++q) sv = cfma(S.L[i + (long long)q * n], v[s * n + q], sv);
+        oc += sv.x * sv.x + sv.y * sv.y;
+      }
+      double z = 0.0;
+      block_sum3(nn, oc, z, sred);
+      if (threadIdx.x == 0) c.part[PART_STRIDE * ((long long)k * c.n_states + j0 + s) + slot] = c.occ * S.kw * (nn - oc);
+    }
+  };
+  if (step == 0) {
+    observe(c.a_t[0], 2, 3, true);
+    if (c.nexc_out) excited(5);
+  }
+
+  if (c.taylor > 0) {
+    for (int e = threadIdx.x; e < NS * n; e += bd) {
+      t0[e] = v[e];
+      acc[e] = v[e];
+    }
+    __syncthreads();
+    for (int q = 1; q <= c.taylor; ++q) {
+      mv(Hm, t0, tmp);
+      const double fq = c.dt * S.r / q;
+      for (int e = threadIdx.x; e < NS * n; e += bd) {
+        const double2 tn = make_double2(fq * tmp[e].y, -fq * tmp[e].x);
+        t0[e] = tn;
+        acc[e] = cadd(acc[e], tn);
+      }
+      __syncthreads();
+    }
+  } else {
+    const int K = S.K;
+    for (int e = threadIdx.x; e < NS * n; e += bd) t0[e] = v[e];
+    mv(Hm, v, t1);
+    for (int e = threadIdx.x; e < NS * n; e += bd) acc[e] = cadd(cmul(S.coef[0], t0[e]), cmul(S.coef[1], t1[e]));
+    __syncthreads();
+    double2 *pa = t0, *pb = t1;
+    for (int q = 2; q <= K; ++q) {
+      mv(Hm, pb, tmp);
+      const double2 cq = S.coef[q];
+      for (int e = threadIdx.x; e < NS * n; e += bd) {
+        const double2 tn = make_double2(2.0 * tmp[e].x - pa[e].x, 2.0 * tmp[e].y - pa[e].y);
+        pa[e] = tn;
+        acc[e] = cfma(cq, tn, acc[e]);
+      }
+      __syncthreads();
+      double2 *x = pa;
+      pa = pb;
+      pb = x;
+    }
+  }
+  for (int e = threadIdx.x; e < NS * n; e += bd) v[e] = cmul(S.phase, acc[e]);
+  __syncthreads();
+  mv(S.LinvH, v, w);
+  for (int e = threadIdx.x; e < ns * n; e += bd) th0[e] = w[e];
+  observe(a1, 0, 1, false);
+  if (c.nexc_out) excited(4);
+
   __syncthreads();
   int *last = reinterpret_cast<int *>(sred);
   if (threadIdx.x == 0) {
@@ -997,6 +1168,8 @@ hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s
   return hipGetLastError();
 }
 
+size_t step_multi_lds_bytes(int n, int ns) { return ((size_t)6 * ns * n) * sizeof(double2) + 3 * 16 * sizeof(double) + 64; }
+
 size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint, bool p_in_lds) {
   const size_t vecs = adjoint ? 11 : 6;
   const size_t mats = (h_in_lds ? (size_t)n * n : 0) + ((!adjoint && p_in_lds) ? (size_t)n * n : 0);
@@ -1019,7 +1192,9 @@ int assemble_blocks(int n) { return (int)(((long long)n * n + 255) / 256); }
 void subspace_init_attrs() {
   if (g_step_attr) return;
   for (const void *k : {(const void *)k_step<true, true>, (const void *)k_step<true, false>,
-                        (const void *)k_step<false, false>, (const void *)k_adjoint<true>,
+                        (const void *)k_step<false, false>, (const void *)k_step_multi<1, 16>,
+                        (const void *)k_step_multi<2, 8>,
+                        (const void *)k_adjoint<true>,
                         (const void *)k_adjoint<false>})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   g_step_attr = true;
@@ -1161,8 +1336,24 @@ hipError_t launch_step(const StepCtx &c, hipStream_t s) {
   return launch_step_only(c, s);
 }
 
-hipError_t launch_step_only(const StepCtx &c, hipStream_t s) {
+hipError_t launch_step_only(const StepCtx &c, hipStream_t s, bool beside) {
   subspace_init_attrs();
+  // matrices in global memory: one thread per row.  Alone (stepwise, AFFINE)
+  // one state per block with 16 column loads in flight per thread (the
+  // shortest step); beside the rebuild of the next step two states per block
+  // (half the blocks, so that the x/z transforms keep more CUs; measured on the
+  // heterostructure: exponential 267 / 318 us, pipelined step 1.281 / 1.265 ms,
+  // against 513 us and 1.349 ms for the column-split product)
+  if (!c.h_in_lds && c.n_aux <= STEP_MULTI_MAXN) {
+    const int nt = 64 * ((c.n_aux + 63) / 64);
+#define LTD_SM(NS, UN)                                                                          \
+  hipLaunchKernelGGL((k_step_multi<NS, UN>), dim3((c.n_states + NS - 1) / NS, c.n_k), dim3(nt), \
+                     step_multi_lds_bytes(c.n_aux, NS), s, c)
+    if (beside) LTD_SM(2, 8);
+    else LTD_SM(1, 16);
+#undef LTD_SM
+    return hipGetLastError();
+  }
   const size_t lds = step_lds_bytes(c.n_aux, c.h_in_lds, false, c.p_in_lds);
   if (c.h_in_lds && c.p_in_lds)
     hipLaunchKernelGGL((k_step<true, true>), dim3(c.n_states, c.n_k), dim3(STEP_NT), lds, s, c);

@@ -82,13 +82,14 @@ def test_static_apply_more_columns_than_one_pass():
 
 
 def test_static_apply_rejects_oversized_column():
-    """One column of a 192^3 grid's FFT slabs exceeds the array: rejected on the
-    host with LTD_EUNSUPPORTED, nothing enqueued; the ordinary apply still runs."""
+    """One column of a 120^3 grid's FFT slabs exceeds the array (the G box reaches
+    |g| = 27, so no smaller exact grid exists for the apply): rejected on the host
+    with LTD_EUNSUPPORTED, nothing enqueued; the ordinary apply still runs."""
     import torch
 
     from paper_2403_04351_amd import _lib, ltd
 
-    sys = make_system(0, grid=(192, 192, 192), n_g=2000, with_start=False)
+    sys = make_system(0, grid=(120, 120, 120), n_g=90000, with_start=False)
     lt = ltd.Ltd(sys, max_cols=2)
     nb = sys.n_basis(0)
     c = torch.ones((1, nb), dtype=torch.complex128, device=lt.device)
