@@ -1249,6 +1249,106 @@ __global__ __launch_bounds__(NW * 64) void k_rb_xz4(const Grid g, const FftKArgs
 }
 
 // ---------------------------------------------------------------------------
+// Line pass of the apply along z with the two-factor register transforms of the
+// rebuild (NZ = Z1 x Z2, the box within the exact-grid bound 4 bz + 1 <= NZ): a
+// wave takes LZ lines at consecutive (x, y) positions, TZ::G lanes each.  Per
+// input field: the inverse line transform (known-zero inputs dropped), the
+// products with Theta (and Theta V) held in registers, the forward transforms
+// (unread outputs not computed) and the box values out, with the z lines
+// exchanged through a per-wave scratch of doubles (real parts, then imaginary
+// parts).  Fields as k_lines: MODE_V psi -> m psi (m = thv); otherwise psi,
+// pi_x, pi_y, pi_z -> Theta psi, Theta V psi, Theta pi_x psi, Theta pi_y psi,
+// Theta pi_z psi.  Four waves per block.
+// ---------------------------------------------------------------------------
+template <int NZ, int Z1, bool VMODE>
+__global__ __launch_bounds__(256) void k_lines_reg(const Grid g, const FftKArgs ka, int ncols,
+                                                   const double *__restrict__ thv) {
+  constexpr int Z2 = NZ / Z1;
+  using TZ = Two<NZ, Z1, Z2>;
+  using XP = XchPitch<NZ, Z1>;
+  constexpr int LZ = rb_lz(TZ::LPW);
+  constexpr int ZLO = zr_lo<NZ, Z2>(), ZHI = zr_hi<NZ, Z2>();
+  extern __shared__ double2 sm_raw[];
+  const int col = blockIdx.y, kk = blockIdx.z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lz = lane / TZ::G, rz = lane - lz * TZ::G;
+  const long long plane = (long long)g.n1 * g.n2;
+  const int bz = g.bz, nbz = g.nbz;
+  const long long pos = ((long long)blockIdx.x * 4 + wave) * LZ + lz;
+  const bool on = lz < LZ && pos < plane;
+  const long long pc = on ? pos : 0;  // clamped position (loads of idle lanes stay in bounds)
+  double *sd = reinterpret_cast<double *>(sm_raw) + (long long)(wave * LZ + (lz < LZ ? lz : 0)) * XP::LS;
+  const long long fstride = (long long)ncols * nbz * plane;
+  const double2 *in = ka.slab_in[kk] + (long long)col * nbz * plane + pc;
+  double2 *out = ka.slab_out[kk] + (long long)col * nbz * plane + pc;
+  const double2 w = cconj(g.tw3[rz < NZ ? rz : 0]), wc = cconj(w);
+  // the multipliers at z = rz + Z1 k2, the layout of a line after its inverse transform
+  double m0[Z2], m1[Z2];
+  {
+    const int r = rz < Z1 ? rz : 0;
+#pragma unroll
+    for (int k2 = 0; k2 < Z2; ++k2) {
+      const long long e = (long long)(r + Z1 * k2) * plane + pc;
+      m0[k2] = VMODE ? thv[e] : g.theta[e];
+      m1[k2] = VMODE ? 0.0 : thv[e];
+    }
+  }
+  // inverse transform of input field f into u (lanes rz < Z1)
+  auto inverse = [&](int f, double2 (&u)[Z2]) {
+    double2 v[Z1];
+    if (on && rz < Z2) {
+      const double2 *src = in + (long long)f * fstride;
+#pragma unroll
+      for (int n1 = 0; n1 < Z1; ++n1) {
+        if (n1 >= ZLO && n1 <= ZHI) {
+          v[n1] = make_double2(0.0, 0.0);
+          continue;
+        }
+        const int n = Z2 * n1 + rz;
+        const int row = n <= bz ? n + bz : n - NZ + bz;
+        v[n1] = (n <= bz || n >= NZ - bz) ? src[(long long)row * plane] : make_double2(0.0, 0.0);
+      }
+      dft_first<Z1, 1, ZLO, ZHI>(v);
+      twiddle_powers<Z1>(v, w);
+    }
+    xch_split<Z1, Z2>(sd, rz, XP::P1, on && rz < Z2, on && rz < Z1, v, u);
+    if (on && rz < Z1) dft_reg<Z2, 1>(u);
+  };
+  // forward transform of u times m into output field o
+  auto forward = [&](const double2 (&u)[Z2], const double (&m)[Z2], int o) {
+    double2 p[Z2], q[Z1];
+    if (on && rz < Z1) {
+#pragma unroll
+      for (int k2 = 0; k2 < Z2; ++k2) p[k2] = cscale(u[k2], m[k2]);
+      dft_reg<Z2, -1>(p);
+      twiddle_powers<Z2>(p, wc);
+    }
+    xch_split<Z2, Z1>(sd, rz, XP::P2, on && rz < Z1, on && rz < Z2, p, q);
+    if (on && rz < Z2) {
+      dft_reg<Z1, -1>(q);
+      double2 *dst = out + (long long)o * fstride;
+#pragma unroll
+      for (int c = 0; c < Z1; ++c) {
+        if (c >= ZLO && c <= ZHI) continue;  // b < |freq|: never read
+        const int mm = Z2 * c + rz;
+        if (mm <= bz || mm >= NZ - bz) dst[(long long)(mm <= bz ? mm + bz : mm - NZ + bz) * plane] = q[c];
+      }
+    }
+  };
+  double2 u[Z2];
+  inverse(0, u);
+  forward(u, m0, 0);
+  if constexpr (!VMODE) {
+    forward(u, m1, 1);
+#pragma unroll 1
+    for (int f = 1; f <= 3; ++f) {
+      inverse(f, u);
+      forward(u, m0, f + 1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Register-resident x/z transforms for N1' = N3' = 64 (box half-widths b <= 15,
 // which the rebuild grid guarantees: 4 b + 1 <= 64).  One wavefront per
 // (column, y') plane; each lane holds one whole 64-point transform in registers
@@ -2285,6 +2385,25 @@ hipError_t fft_lines(const Grid &g, const FftKArgs &ka, int nk, int ncols, int m
                      hipStream_t s) {
   set_attrs();
   const bool vmode = (mode == FFT_MODE_V);
+  // register line transforms where the length has a two-factor split and the
+  // box fits the exact-grid bound (64 = 8 x 8, 72 = 8 x 9, 108 = 12 x 9)
+  if (4 * g.bz + 1 <= g.n3 && (g.n3 == 64 || g.n3 == 72 || g.n3 == 108)) {
+#define LTD_LR(nz, z1)                                                                                   \
+  do {                                                                                                   \
+    using TZ = Two<nz, z1, nz / z1>;                                                                     \
+    constexpr int LZ = rb_lz(TZ::LPW);                                                                   \
+    const long long pl = (long long)g.n1 * g.n2;                                                         \
+    const dim3 gr((unsigned)((pl + 4 * LZ - 1) / (4 * LZ)), ncols, nk);                                  \
+    const size_t lds = (size_t)4 * LZ * XchPitch<nz, z1>::LS * sizeof(double);                           \
+    if (vmode) hipLaunchKernelGGL((k_lines_reg<nz, z1, true>), gr, dim3(256), lds, s, g, ka, ncols, thv); \
+    else hipLaunchKernelGGL((k_lines_reg<nz, z1, false>), gr, dim3(256), lds, s, g, ka, ncols, thv);     \
+  } while (0)
+    if (g.n3 == 64) LTD_LR(64, 8);
+    else if (g.n3 == 72) LTD_LR(72, 8);
+    else LTD_LR(108, 12);
+#undef LTD_LR
+    return hipGetLastError();
+  }
   const int t = line_tile(g, vmode);
   const long long plane_sz = (long long)g.n1 * g.n2;
   const int ntile = (int)((plane_sz + t - 1) / t);
