@@ -587,6 +587,46 @@ __global__ __launch_bounds__(FFT_NT) void k_lines(const Grid g, const FftKArgs k
 // ---------------------------------------------------------------------------
 // Forward plane pass: slab planes -> values at the sphere, combined per mode.
 // ---------------------------------------------------------------------------
+// The value of output field f at sphere point gi of column col into the mode's
+// outputs: MODE_V Y; MODE_HS S C and H C = F(Th V psi) + (A/c) F(1/2 (gz Th psi
+// + Th pi_z psi)) + (A^2 / 2 c^2) F(Th psi) + sum_i 1/2 (G+k)_i F(Th pi_i psi);
+// MODE_TVPS the blocks T, V, P, S applied separately.
+__device__ __forceinline__ void fwd_out_point(const FwdOut &fo, const KSphere &sp, int gi, int col, int f, int mode,
+                                              double2 val, double alpha_a, double beta_a) {
+  const long long c = (long long)col;
+  if (mode == FFT_MODE_V) {
+    fo.o0[gi + c * fo.ld0] = val;
+  } else if (mode == FFT_MODE_HS) {
+    double2 *hc = fo.o0 + gi + c * fo.ld0;
+    const double gz = sp.gk[3 * gi + 2];
+    if (f == 0) {
+      fo.o1[gi + c * fo.ld1] = val;                    // S C
+      *hc = cscale(val, alpha_a * 0.5 * gz + beta_a);  // (A/c) 1/2 gz F(Th psi) + (A^2/2c^2) F(Th psi)
+    } else if (f == 1) {
+      *hc = cadd(*hc, val);                            // F(Th V psi)
+    } else {
+      double w = 0.5 * sp.gk[3 * gi + (f - 2)];        // 1/2 (G+k)_i F(Th pi_i psi)
+      if (f == 4) w += 0.5 * alpha_a;                  // (A/c) 1/2 F(Th pi_z psi)
+      *hc = cadd(*hc, cscale(val, w));
+    }
+  } else {  // TVPS
+    const double gz = sp.gk[3 * gi + 2];
+    if (f == 0) {
+      fo.o3[gi + c * fo.ld3] = val;                    // S
+      fo.o2[gi + c * fo.ld2] = cscale(val, 0.5 * gz);  // P part
+    } else if (f == 1) {
+      fo.o1[gi + c * fo.ld1] = val;                    // V
+    } else {
+      const double w = 0.5 * sp.gk[3 * gi + (f - 2)];
+      double2 *t = fo.o0 + gi + c * fo.ld0;
+      *t = (f == 2) ? cscale(val, w) : cadd(*t, cscale(val, w));
+      if (f == 4) {
+        double2 *p = fo.o2 + gi + c * fo.ld2;
+        *p = cadd(*p, cscale(val, 0.5));
+      }
+    }
+  }
+}
 template <int L1, int L2>
 __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKArgs ka, int ncols, int mode,
                                                       double alpha_a, double beta_a, int ch) {
@@ -631,40 +671,7 @@ __global__ __launch_bounds__(FFT_NT) void k_fwd_plane(const Grid g, const FftKAr
     for (int i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
       const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
       const int y = xy / n1, x = xy - y * n1;
-      const double2 val = cscale(bxc[box_of(x, n1, bx) * bp + y], inv_n);
-      const long long c = (long long)col;
-      if (mode == FFT_MODE_V) {
-        fo.o0[gi + c * fo.ld0] = val;
-      } else if (mode == FFT_MODE_HS) {
-        double2 *hc = fo.o0 + gi + c * fo.ld0;
-        const double gz = sp.gk[3 * gi + 2];
-        if (f == 0) {
-          fo.o1[gi + c * fo.ld1] = val;                    // S C
-          *hc = cscale(val, alpha_a * 0.5 * gz + beta_a);  // (A/c) 1/2 gz F(Th psi) + (A^2/2c^2) F(Th psi)
-        } else if (f == 1) {
-          *hc = cadd(*hc, val);                            // F(Th V psi)
-        } else {
-          double w = 0.5 * sp.gk[3 * gi + (f - 2)];        // 1/2 (G+k)_i F(Th pi_i psi)
-          if (f == 4) w += 0.5 * alpha_a;                  // (A/c) 1/2 F(Th pi_z psi)
-          *hc = cadd(*hc, cscale(val, w));
-        }
-      } else {  // TVPS
-        const double gz = sp.gk[3 * gi + 2];
-        if (f == 0) {
-          fo.o3[gi + c * fo.ld3] = val;                    // S
-          fo.o2[gi + c * fo.ld2] = cscale(val, 0.5 * gz);  // P part
-        } else if (f == 1) {
-          fo.o1[gi + c * fo.ld1] = val;                    // V
-        } else {
-          const double w = 0.5 * sp.gk[3 * gi + (f - 2)];
-          double2 *t = fo.o0 + gi + c * fo.ld0;
-          *t = (f == 2) ? cscale(val, w) : cadd(*t, cscale(val, w));
-          if (f == 4) {
-            double2 *p = fo.o2 + gi + c * fo.ld2;
-            *p = cadd(*p, cscale(val, 0.5));
-          }
-        }
-      }
+      fwd_out_point(fo, sp, gi, col, f, mode, cscale(bxc[box_of(x, n1, bx) * bp + y], inv_n), alpha_a, beta_a);
     }
     __syncthreads();
   }
@@ -1346,6 +1353,327 @@ __global__ __launch_bounds__(256) void k_lines_reg(const Grid g, const FftKArgs 
       forward(u, m0, f + 1);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Plane passes of the apply with the two-factor register transforms, for square
+// planes N1 = N2 = N = F1 F2 (72 = 8 x 9, 64 = 8 x 8) with the box within the
+// exact-grid bound (4 b + 1 <= N on x and y).  One block (four waves) per (kz
+// plane, column), as k_inv_plane / k_fwd_plane, with the same slab layout and
+// the same sums up to rounding order.  A line takes Two<N>::G lanes (a lane of
+// role r holds the values r + F2 n1 before the first pass, r + F1 k2 after the
+// second); the box columns B[kx][y] (pitch RP = rb_pitch(N)) stay in LDS and
+// exchange in place, the x rows exchange through a per-wave scratch of doubles
+// (real parts, then imaginary parts).  Known-zero inputs (|k| > b) are dropped
+// before the first pass, outputs outside the box are never computed.  The
+// plane's sphere points are read once per block into registers (PLANE_PPT per
+// thread, two for the four outputs of MODE_TVPS; points beyond that times 256
+// go through global memory per field), and the forward pass keeps its outputs
+// there across the fields.
+// ---------------------------------------------------------------------------
+constexpr int PLANE_PPT = 3;
+template <int N>
+constexpr size_t plane_reg_lds(int nbx) {
+  using TT = Two<N, 8, N / 8>;
+  return (size_t)nbx * rb_pitch(N) * sizeof(double2) + (size_t)4 * TT::LPW * TT::LS * sizeof(double);
+}
+
+// Inverse: sphere coefficients (times 1 or (G+k)_i, fields as k_inv_plane) ->
+// box columns -> inverse y transforms in place -> per grid row y the inverse x
+// transform from the box columns, written to the slab row.
+template <int N>
+__global__ __launch_bounds__(256) void k_inv_plane_reg(const Grid g, const FftKArgs ka, int ncols, int nfields) {
+  constexpr int F1 = 8, F2 = N / F1;
+  using TT = Two<N, F1, F2>;
+  constexpr int G = TT::G, LPW = TT::LPW, RP = rb_pitch(N), P = TT::P, LS = TT::LS;
+  constexpr int LO = zr_lo<N, F2>(), HI = zr_hi<N, F2>();
+  extern __shared__ double2 sm_raw[];
+  const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
+  const int bx = g.bx, nbx = g.nbx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane / G, r = lane - li * G;
+  double2 *B = sm_raw;
+  double *sd = reinterpret_cast<double *>(B + nbx * RP) + (wave * LPW + (li < LPW ? li : 0)) * LS;
+  const KSphere &sp = ka.sph[kk];
+  const InvIn in = ka.in[kk];
+  const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
+  constexpr long long plane_sz = (long long)N * N;
+  const long long fstride = (long long)ncols * g.nbz * plane_sz;
+  double2 *out = ka.slab_out[kk] + ((long long)col * g.nbz + pz) * plane_sz;
+  // this lane's twiddles exp(-2 pi i r j / N), j < F1 (used conjugated)
+  double2 twt[F1];
+#pragma unroll
+  for (int j = 0; j < F1; ++j) twt[j] = g.tw1[(r * j) % N];
+  // this thread's sphere points: coefficient, (G+k), LDS slot (-1: none)
+  double2 pc[PLANE_PPT];
+  double pk[PLANE_PPT][3];
+  int ps[PLANE_PPT];
+#pragma unroll
+  for (int k = 0; k < PLANE_PPT; ++k) {
+    const int i = p0 + threadIdx.x + k * (int)blockDim.x;
+    ps[k] = -1;
+    if (i < p1) {
+      const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+      const int y = xy / N, x = xy - y * N;
+      ps[k] = box_of(x, N, bx) * RP + y;
+      pc[k] = in.c[(long long)gi + (long long)col * in.ldc];
+      if (nfields > 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) pk[k][d] = sp.gk[3 * gi + d];
+    }
+  }
+  for (int f = 0; f < nfields; ++f) {
+    for (int i = threadIdx.x; i < nbx * RP; i += blockDim.x) B[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PLANE_PPT; ++k)
+      if (ps[k] >= 0) B[ps[k]] = f > 0 ? cscale(pc[k], pk[k][f - 1]) : pc[k];
+    for (int i = p0 + threadIdx.x + PLANE_PPT * (int)blockDim.x; i < p1; i += blockDim.x) {
+      const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+      double2 c = in.c[(long long)gi + (long long)col * in.ldc];
+      if (f > 0) c = cscale(c, sp.gk[3 * gi + (f - 1)]);
+      const int y = xy / N, x = xy - y * N;
+      B[box_of(x, N, bx) * RP + y] = c;
+    }
+    __syncthreads();
+    // inverse y transforms of the box columns, in place
+    for (int b0 = wave * LPW; b0 < nbx; b0 += 4 * LPW) {
+      const int b = b0 + li;
+      const bool on = li < LPW && b < nbx;
+      double2 *row = B + (on ? b : 0) * RP;
+      if (on && r < F2) {  // reads and writes only the slots r + F2 j of its line
+        double2 v[F1];
+#pragma unroll
+        for (int n1 = 0; n1 < F1; ++n1) v[n1] = (n1 >= LO && n1 <= HI) ? make_double2(0.0, 0.0) : row[F2 * n1 + r];
+        dft_first<F1, 1, LO, HI>(v);
+        twiddle_tab<F1, 1>(v, twt);
+#pragma unroll
+        for (int k1 = 0; k1 < F1; ++k1) row[k1 * F2 + r] = v[k1];
+      }
+      wave_fence();
+      if (on && r < F1) {
+        double2 u[F2];
+#pragma unroll
+        for (int q = 0; q < F2; ++q) u[q] = row[r * F2 + q];
+        dft_reg<F2, 1>(u);
+        wave_fence();
+#pragma unroll
+        for (int k2 = 0; k2 < F2; ++k2) row[r + F1 * k2] = u[k2];
+      }
+      wave_fence();
+    }
+    __syncthreads();
+    // inverse x transforms of the grid rows, from the box columns to the slab
+    double2 *o = out + f * fstride;
+    for (int y0 = wave * LPW; y0 < N; y0 += 4 * LPW) {
+      const int y = y0 + li;
+      const bool on = li < LPW && y < N;
+      double2 v[F1], u[F2];
+      if (on && r < F2) {
+#pragma unroll
+        for (int n1 = 0; n1 < F1; ++n1) {
+          const int n = F2 * n1 + r;
+          if (n1 >= LO && n1 <= HI) {
+            v[n1] = make_double2(0.0, 0.0);
+            continue;
+          }
+          v[n1] = (n <= bx || n >= N - bx) ? B[(n <= bx ? n + bx : n - N + bx) * RP + y] : make_double2(0.0, 0.0);
+        }
+        dft_first<F1, 1, LO, HI>(v);
+        twiddle_tab<F1, 1>(v, twt);
+      }
+      xch_split<F1, F2>(sd, r, P, on && r < F2, on && r < F1, v, u);
+      if (on && r < F1) {
+        dft_reg<F2, 1>(u);
+#pragma unroll
+        for (int k2 = 0; k2 < F2; ++k2) o[(long long)y * N + r + F1 * k2] = u[k2];
+      }
+      wave_fence();
+    }
+    __syncthreads();  // the next field rewrites B
+  }
+}
+
+// The forward pass's outputs of one sphere point, accumulated over the fields
+// in the order of fwd_out_point (the same sums), stored after the last field.
+template <int MODE>
+struct FwdAcc {
+  double2 a0, a1, a2, a3;
+  __device__ __forceinline__ void add(int f, double2 val, const double *gk, double alpha_a, double beta_a) {
+    if constexpr (MODE == FFT_MODE_V) {
+      a0 = val;
+    } else if constexpr (MODE == FFT_MODE_HS) {
+      // weights: (A/c) 1/2 gz + A^2/2c^2 on F(Th psi), 1 on F(Th V psi), 1/2 (G+k)_i on
+      // F(Th pi_i psi), plus (A/c) 1/2 on F(Th pi_z psi); S C = F(Th psi)
+      const double gi = f == 2 ? gk[0] : f == 3 ? gk[1] : gk[2];
+      const double w = f == 0 ? alpha_a * 0.5 * gk[2] + beta_a : f == 1 ? 1.0 : 0.5 * gi + (f == 4 ? 0.5 * alpha_a : 0.0);
+      if (f == 0) a1 = val;
+      a0 = f == 0 ? cscale(val, w) : cadd(a0, cscale(val, w));
+    } else {  // TVPS: a0 T, a1 V, a2 P, a3 S
+      if (f == 0) {
+        a3 = val;
+        a2 = cscale(val, 0.5 * gk[2]);
+      } else if (f == 1) {
+        a1 = val;
+      } else {
+        const double w = 0.5 * gk[f - 2];
+        a0 = (f == 2) ? cscale(val, w) : cadd(a0, cscale(val, w));
+        if (f == 4) a2 = cadd(a2, cscale(val, 0.5));
+      }
+    }
+  }
+  __device__ __forceinline__ void store(const FwdOut &fo, int gi, int col) const {
+    const long long c = (long long)col;
+    fo.o0[gi + c * fo.ld0] = a0;
+    if constexpr (MODE != FFT_MODE_V) fo.o1[gi + c * fo.ld1] = a1;
+    if constexpr (MODE == FFT_MODE_TVPS) {
+      fo.o2[gi + c * fo.ld2] = a2;
+      fo.o3[gi + c * fo.ld3] = a3;
+    }
+  }
+};
+
+// Forward: per output field, the forward x transforms of the slab rows (only
+// the box outputs kept, into the box columns; each pass's rows loaded during
+// the previous pass), then the forward y transforms of the box columns in place
+// (only |ky| <= by kept), then the field's term of each sphere point's outputs.
+template <int N, int MODE>
+__global__ __launch_bounds__(256, 2) void k_fwd_plane_reg(const Grid g, const FftKArgs ka, int ncols, double alpha_a,
+                                                       double beta_a) {
+  constexpr int F1 = 8, F2 = N / F1;
+  using TT = Two<N, F1, F2>;
+  constexpr int G = TT::G, LPW = TT::LPW, RP = rb_pitch(N), LS = TT::LS;
+  constexpr int LO = zr_lo<N, F2>(), HI = zr_hi<N, F2>();
+  constexpr int P2 = F2;  // exchange slots a P2 + d, a < F1, d < F2
+  static_assert((F1 - 1) * P2 + F2 <= LS, "exchange scratch");
+  constexpr int NF = MODE == FFT_MODE_V ? 1 : 5;
+  constexpr int NP = (N + 4 * LPW - 1) / (4 * LPW);  // row passes per field
+  extern __shared__ double2 sm_raw[];
+  const int pz = blockIdx.x, col = blockIdx.y, kk = blockIdx.z;
+  const int bx = g.bx, by = g.by, nbx = g.nbx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane / G, r = lane - li * G;
+  double2 *B = sm_raw;
+  double *sd = reinterpret_cast<double *>(B + nbx * RP) + (wave * LPW + (li < LPW ? li : 0)) * LS;
+  const KSphere &sp = ka.sph[kk];
+  const FwdOut &fo = ka.out[kk];
+  const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
+  constexpr long long plane_sz = (long long)N * N;
+  const long long fstride = (long long)ncols * g.nbz * plane_sz;
+  const double2 *src0 = ka.slab_in[kk] + ((long long)col * g.nbz + pz) * plane_sz;
+  const double inv_n = 1.0 / ((double)N * N * g.n3);
+  // this lane's twiddles exp(-2 pi i r j / N), j < F2
+  double2 twt[F2];
+#pragma unroll
+  for (int j = 0; j < F2; ++j) twt[j] = g.tw1[(r * j) % N];
+  // this thread's sphere points: G index, LDS slot of its box value (-1: none), (G+k)
+  constexpr int PPT = MODE == FFT_MODE_TVPS ? 2 : PLANE_PPT;
+  int pg[PPT], ps[PPT];
+  double pk[PPT][3];
+  FwdAcc<MODE> acc[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int i = p0 + threadIdx.x + k * (int)blockDim.x;
+    ps[k] = -1;
+    pg[k] = 0;
+    if (i < p1) {
+      const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+      const int y = xy / N, x = xy - y * N;
+      pg[k] = gi;
+      ps[k] = box_of(x, N, bx) * RP + (y <= by ? y : y - N) + by;
+      if constexpr (MODE != FFT_MODE_V)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) pk[k][d] = sp.gk[3 * gi + d];
+    }
+  }
+  // rows of pass p of field f into u (lanes r < F1: x = r + F1 q)
+  auto load_rows = [&](int f, int p, double2 (&u)[F2]) {
+    const int y = wave * LPW + li + p * 4 * LPW;
+    if (li < LPW && y < N && r < F1) {
+      const double2 *src = src0 + f * fstride + (long long)y * N + r;
+#pragma unroll
+      for (int q = 0; q < F2; ++q) u[q] = src[F1 * q];
+    }
+  };
+  double2 nxt[F2];
+  load_rows(0, 0, nxt);
+#pragma unroll 1
+  for (int f = 0; f < NF; ++f) {
+    // forward x transforms of the grid rows, box outputs into B[kx + bx][y]
+#pragma unroll 1
+    for (int p = 0; p < NP; ++p) {
+      const int y = wave * LPW + li + p * 4 * LPW;
+      const bool on = li < LPW && y < N;
+      double2 u[F2], v[F1];
+#pragma unroll
+      for (int q = 0; q < F2; ++q) u[q] = nxt[q];
+      if (p + 1 < NP) load_rows(f, p + 1, nxt);
+      else if (f + 1 < NF) load_rows(f + 1, 0, nxt);
+      if (on && r < F1) {
+        dft_reg<F2, -1>(u);
+        twiddle_tab<F2, -1>(u, twt);
+      }
+      xch_split<F2, F1>(sd, r, P2, on && r < F1, on && r < F2, u, v);
+      if (on && r < F2) {
+        dft_reg<F1, -1>(v);
+#pragma unroll
+        for (int c = 0; c < F1; ++c) {
+          if (c >= LO && c <= HI) continue;  // |kx| > bx: never read
+          const int m = F2 * c + r;
+          if (m <= bx || m >= N - bx) B[(m <= bx ? m + bx : m - N + bx) * RP + y] = v[c];
+        }
+      }
+      wave_fence();
+    }
+    __syncthreads();
+    // forward y transforms of the box columns in place; |ky| <= by kept at B[b][ky + by]
+    for (int b0 = wave * LPW; b0 < nbx; b0 += 4 * LPW) {
+      const int b = b0 + li;
+      const bool on = li < LPW && b < nbx;
+      double2 *row = B + (on ? b : 0) * RP;
+      if (on && r < F1) {
+        double2 u[F2];
+#pragma unroll
+        for (int q = 0; q < F2; ++q) u[q] = row[r + F1 * q];
+        dft_reg<F2, -1>(u);
+        twiddle_tab<F2, -1>(u, twt);
+        wave_fence();
+#pragma unroll
+        for (int d = 0; d < F2; ++d) row[r * F2 + d] = u[d];
+      }
+      wave_fence();
+      double2 v[F1];
+      if (on && r < F2) {
+#pragma unroll
+        for (int a = 0; a < F1; ++a) v[a] = row[a * F2 + r];
+        dft_reg<F1, -1>(v);
+      }
+      wave_fence();
+      if (on && r < F2) {
+#pragma unroll
+        for (int c = 0; c < F1; ++c) {
+          if (c >= LO && c <= HI) continue;  // |ky| > by: never read
+          const int m = F2 * c + r;
+          if (m <= by || m >= N - by) row[m <= by ? m + by : m - N + by] = v[c];
+        }
+      }
+      wave_fence();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+      if (ps[k] >= 0) acc[k].add(f, cscale(B[ps[k]], inv_n), pk[k], alpha_a, beta_a);
+    for (int i = p0 + threadIdx.x + PPT * (int)blockDim.x; i < p1; i += blockDim.x) {
+      const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+      const int y = xy / N, x = xy - y * N;
+      const int ky = y <= by ? y : y - N;
+      fwd_out_point(fo, sp, gi, col, f, MODE, cscale(B[box_of(x, N, bx) * RP + ky + by], inv_n), alpha_a, beta_a);
+    }
+    __syncthreads();  // the next field rewrites B
+  }
+#pragma unroll
+  for (int k = 0; k < PPT; ++k)
+    if (ps[k] >= 0) acc[k].store(fo, pg[k], col);
 }
 
 // ---------------------------------------------------------------------------
@@ -2095,6 +2423,14 @@ void each_plane_kernel(F &&f) {
   f((const void *)k_rb_xzr<xzr_nw<float2>(), float2>);
   f((const void *)k_inv_plane<0, 0>);
   f((const void *)k_fwd_plane<0, 0>);
+  f((const void *)k_inv_plane_reg<72>);
+  f((const void *)k_inv_plane_reg<64>);
+#define LTD_FR(a)                                          \
+  f((const void *)k_fwd_plane_reg<a, FFT_MODE_V>);         \
+  f((const void *)k_fwd_plane_reg<a, FFT_MODE_HS>);        \
+  f((const void *)k_fwd_plane_reg<a, FFT_MODE_TVPS>);
+  LTD_FR(72) LTD_FR(64)
+#undef LTD_FR
 #define LTD_PL(a, b)                            \
   f((const void *)k_inv_plane<a, b>);           \
   f((const void *)k_fwd_plane<a, b>);
@@ -2367,9 +2703,21 @@ hipError_t fft_rb_step(const Grid &g, const FftKArgs &ka, int nk, int ncols, con
 size_t fft_plane_lds_bytes(const Grid &g) { return plane_lds(g); }
 size_t fft_line_lds_bytes(const Grid &g) { return line_lds(g, line_tile(g, false), false); }
 
+// the register plane passes: square 72- or 64-point planes, box within the exact-grid bound
+bool plane_reg_ok(const Grid &g) {
+  return g.n1 == g.n2 && (g.n1 == 72 || g.n1 == 64) && 4 * g.bx + 1 <= g.n1 && 4 * g.by + 1 <= g.n2;
+}
+
 hipError_t fft_inverse_planes(const Grid &g, const FftKArgs &ka, int nk, int ncols, int nfields, hipStream_t s) {
   set_attrs();
   const dim3 grid(g.nbz, ncols, nk), block(FFT_NT);
+  if (plane_reg_ok(g)) {
+    if (g.n1 == 72)
+      hipLaunchKernelGGL(k_inv_plane_reg<72>, grid, dim3(256), plane_reg_lds<72>(g.nbx), s, g, ka, ncols, nfields);
+    else
+      hipLaunchKernelGGL(k_inv_plane_reg<64>, grid, dim3(256), plane_reg_lds<64>(g.nbx), s, g, ka, ncols, nfields);
+    return hipGetLastError();
+  }
   const size_t lds = plane_lds(g);
 #define LTD_INV(a, b) hipLaunchKernelGGL((k_inv_plane<a, b>), grid, block, lds, s, g, ka, ncols, nfields, plane_ch(g))
   if (g.n1 == 16 && g.n2 == 16) LTD_INV(16, 16);
@@ -2433,6 +2781,21 @@ hipError_t fft_forward_planes(const Grid &g, const FftKArgs &ka, int nk, int nco
                               double beta_a, hipStream_t s) {
   set_attrs();
   const dim3 grid(g.nbz, ncols, nk), block(FFT_NT);
+  if (plane_reg_ok(g)) {
+#define LTD_FR(a, m) \
+  hipLaunchKernelGGL((k_fwd_plane_reg<a, m>), grid, dim3(256), plane_reg_lds<a>(g.nbx), s, g, ka, ncols, alpha_a, beta_a)
+#define LTD_FRM(a)                                   \
+  do {                                               \
+    if (mode == FFT_MODE_V) LTD_FR(a, FFT_MODE_V);   \
+    else if (mode == FFT_MODE_HS) LTD_FR(a, FFT_MODE_HS); \
+    else LTD_FR(a, FFT_MODE_TVPS);                   \
+  } while (0)
+    if (g.n1 == 72) LTD_FRM(72);
+    else LTD_FRM(64);
+#undef LTD_FRM
+#undef LTD_FR
+    return hipGetLastError();
+  }
   const size_t lds = plane_lds(g);
 #define LTD_FW(a, b) \
   hipLaunchKernelGGL((k_fwd_plane<a, b>), grid, block, lds, s, g, ka, ncols, mode, alpha_a, beta_a, plane_ch(g))

@@ -3,6 +3,8 @@
 register x/z kernel's 72 x 72 instance with the known-zero inputs and unread
 outputs of every line dropped at compile time (valid while 4 b + 1 <= 72), in
 FP64 and in the complex64 residual form, against the oracle's per-step rebuild.
+The apply on the same grid (the register plane passes, pruned the same way, and
+the register z lines) on ragged column counts against the oracle's apply.
 
 Bars: FP64 1e-10 relative (element maxima against the largest reference
 element); FP32 residual 1e-6.
@@ -11,6 +13,7 @@ element); FP32 residual 1e-6.
 import numpy as np
 import pytest
 
+from oracle import operators as op
 from oracle import propagate as pr
 from oracle import subspace as ss
 from synth import make_system, potential_scale, pulse_samples, td_potential
@@ -73,4 +76,25 @@ def test_pruned_72_rebuild_matches_oracle(box, precision):
     print(f"72^3 rebuild, |g| <= {b.max()}, {precision}: J {ej:.2e} theta {et:.2e}", flush=True)
     bar = 1e-10 if precision == "LTD_FP64" else 1e-6
     assert ej < bar and et < bar
+    lt.close()
+
+
+@pytest.mark.parametrize("n", [1, 9, 29])
+def test_apply_on_72_planes(box, n):
+    import torch
+
+    from paper_2403_04351_amd import ltd
+
+    sys = box["sys"]
+    lt = ltd.Ltd(sys, max_cols=32)
+    assert tuple(lt.rebuild_grid()) == (72, 72, 72)
+    rng = np.random.default_rng(70 + n)
+    c = rng.standard_normal((sys.n_basis(0), n)) + 1j * rng.standard_normal((sys.n_basis(0), n))
+    hc, sc = lt.apply_hs(0, ltd.colmajor(c, lt.device), 0.0029)
+    torch.cuda.synchronize()
+    hr, sr = op.apply_hs(sys, 0, c, 0.0029)
+    eh, es = rel_max(ltd.to_numpy(hc), hr), rel_max(ltd.to_numpy(sc), sr)
+    b = np.abs(sys.kpts[0].g_int).max(0)
+    print(f"72^3 apply, |g| <= {b.max()}, n = {n}: H {eh:.2e} S {es:.2e}", flush=True)
+    assert eh < 1e-10 and es < 1e-10
     lt.close()
