@@ -127,7 +127,7 @@ struct ltd_system {
   size_t ws_need = 0, ws_bound = 0;
   size_t o_tw1, o_tw2, o_tw3, o_thv, o_thv_rb, o_thv_step, o_status, o_part, o_partials;
   size_t o_vpartials;  // split-K partials of the V~ projection (its own: reduced on another stream)
-  size_t o_slab_in, o_slab_out, o_W, o_Y, o_heff, o_tvps, o_proj, o_tmp3, o_eigA, o_eigV, o_eigw;
+  size_t o_slab_in, o_slab_out, o_W, o_Y, o_heff, o_tvps, o_proj, o_tmp3, o_eigA, o_eigV, o_eigw, o_eigwork;
   size_t o_stepslab, o_subdev, o_theta_sc, o_k6, o_hstep, o_zero32;
   K2Table k2_hs, k2_tvps, k2_step;
   size_t o_k2_hs1, o_k2_hs2, o_k2_tv1, o_k2_tv2, o_k2_st1, o_k2_st2;
@@ -830,7 +830,7 @@ ltd_status eig_bounds(ltd_system *sys, int k, hipStream_t s, double *lmin, doubl
   double2 *A = sys->at<double2>(sys->o_eigA);
   double *w = sys->at<double>(sys->o_eigw);
   LTD_HIP(hipMemcpyAsync(A, sys->at<double2>(kh.o_tilde) + 3 * n2, n2 * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  LTD_HIP(launch_jacobi(A, nullptr, w, n, s));
+  LTD_HIP(launch_jacobi(A, nullptr, w, n, s, sys->ws + sys->o_eigwork));
   std::vector<double> hw(n);
   LTD_HIP(hipStreamSynchronize(s));
   LTD_HIP(hipMemcpy(hw.data(), w, n * sizeof(double), hipMemcpyDeviceToHost));
@@ -1586,6 +1586,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_eigA = ar.take((size_t)n2 * sizeof(double2));
   sys->o_eigV = ar.take((size_t)n2 * sizeof(double2));
   sys->o_eigw = ar.take((size_t)n * sizeof(double));
+  sys->o_eigwork = ar.take(jacobi_work_bytes(n));
   sys->o_k6 = ar.take((size_t)sys->nb_max * n * sizeof(double2));
   sys->o_stepslab = mm ? 0 : ar.take((size_t)std::min(sys->n_k, FFT_MAXK) * fft_rb_slab_values(sys->rgrid) * n * rb_elem(sys));
   if (mm) {
@@ -2099,7 +2100,7 @@ ltd_status ltd_ritz_basis(ltd_system *sys, int k, void *x, int ldx, double *eps,
   double2 *A = sys->at<double2>(sys->o_eigA), *V = sys->at<double2>(sys->o_eigV);
   double *w = sys->at<double>(sys->o_eigw);
   LTD_HIP(hipMemcpyAsync(A, sys->at<double2>(kh.o_tilde) + 3 * n2, n2 * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  LTD_HIP(launch_jacobi(A, V, w, n, s));
+  LTD_HIP(launch_jacobi(A, V, w, n, s, sys->ws + sys->o_eigwork));
   // X <- X L^{-H} W
   double2 *t = sys->at<double2>(sys->o_k6);
   LTD_TRY(gemm1(sys, OP_N, OP_C, zp(kh.n_basis, n, n, X, ldx, sys->at<double2>(kh.o_Linv), n, t, sys->nb_max), s));
@@ -2234,7 +2235,7 @@ ltd_status ltd_state_drift(ltd_system *sys, void *theta, int reorthonormalize, d
       }
     if (reorthonormalize) {  // Loewdin: theta <- theta G^{-1/2}, G = V diag(w) V^H
       LTD_HIP(hipMemcpyAsync(A, G, (size_t)ns * ns * sizeof(double2), hipMemcpyDeviceToDevice, s));
-      LTD_HIP(launch_jacobi(A, V, w, ns, s));
+      LTD_HIP(launch_jacobi(A, V, w, ns, s, sys->ws + sys->o_eigwork));
       LTD_HIP(launch_scale_cols(B, V, w, ns, s));
       LTD_TRY(gemm1(sys, OP_N, OP_C, zp(ns, ns, ns, B, ns, V, ns, G, ns), s));
       LTD_TRY(gemm1(sys, OP_N, OP_N, zp(n, ns, ns, th, n, G, ns, X, n), s));

@@ -88,7 +88,13 @@ hipError_t launch_heff(double2 *out, const double2 *h, const double2 *p, const d
 hipError_t launch_thv(double *out, const double *th, const double *v, long long n, hipStream_t s);
 hipError_t launch_cholesky(const double2 *S, double2 *L, int n, int *status, int *fail, hipStream_t s);
 hipError_t launch_trtri(const double2 *L, double2 *Li, int n, hipStream_t s);
-hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s);
+// Hermitian eigendecomposition by cyclic Jacobi: A (n x n, destroyed) -> w
+// ascending, V (optional) the eigenvectors.  n <= JACOBI_ONE_BLOCK (or no work
+// buffer): one block, asynchronous; larger n: one launch per half round with the
+// host reading the sweep test (synchronises s), work = jacobi_work_bytes(n).
+constexpr int JACOBI_ONE_BLOCK = 128, JACOBI_MAXN = 1024;
+size_t jacobi_work_bytes(int n);
+hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s, void *work = nullptr);
 // dst[i + c ldd] = src[idx[i] + c lds], i < rows, c < cols (row gather)
 hipError_t launch_gather_rows(double2 *dst, int ldd, const double2 *src, int lds, const int *idx, int rows, int cols,
                               hipStream_t s);

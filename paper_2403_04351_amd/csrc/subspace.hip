@@ -429,6 +429,132 @@ __global__ __launch_bounds__(1024) void k_jacobi(double2 *A, double2 *V, double 
   }
 }
 
+// The same cyclic Jacobi for larger n, one launch per half round: every pair
+// (p, q) of a round gets a block, which computes its rotation from the current
+// A (the elements of its own two columns) and applies it to columns p, q of A
+// and V (k_jac_cols); the row updates follow in a second launch (k_jac_rows).
+// The rotations, their order and their arithmetic are those of k_jacobi; the
+// sweep test (k_jac_check: symmetrise, then off(A) <= 1e-28 ||A||^2) is read
+// by the host between sweeps.  JacRot: c, s and the phase e of each pair.
+struct JacRot {
+  double c, sn;
+  double2 e;
+  int p, q;
+};
+
+__device__ inline int jac_player(int pos, int round, int m) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (m - 1); }
+
+__global__ __launch_bounds__(256) void k_jac_init(double2 *V, int n) {
+  const long long tot = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    V[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_jac_check(double2 *A, int n, int *done) {
+  __shared__ double sred[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (long long e = t; e < (long long)n * n; e += nt) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    if (i > j) A[e] = cconj(A[j + (long long)i * n]);
+    else if (i == j) A[e].y = 0.0;
+  }
+  __syncthreads();
+  double off = 0.0, tot = 0.0;
+  for (long long e = t; e < (long long)n * n; e += nt) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    const double a2 = A[e].x * A[e].x + A[e].y * A[e].y;
+    tot += a2;
+    if (i != j) off += a2;
+  }
+  off = block_sum(off, sred);
+  tot = block_sum(tot, sred);
+  if (t == 0) *done = (off <= 1e-28 * tot || off == 0.0) ? 1 : 0;
+}
+
+// grid (m / 2): block s takes pair s of the round
+__global__ __launch_bounds__(256) void k_jac_cols(double2 *A, double2 *V, int n, int round, JacRot *rot) {
+  __shared__ JacRot r;
+  const int m = (n + 1) & ~1, s = blockIdx.x;
+  if (threadIdx.x == 0) {
+    int p = jac_player(s, round, m), q = jac_player(m - 1 - s, round, m);
+    if (p > q) {
+      const int x = p;
+      p = q;
+      q = x;
+    }
+    double c = 1.0, sn = 0.0;
+    double2 e = make_double2(1.0, 0.0);
+    if (q < n) {
+      const double2 apq = A[p + (long long)q * n];
+      const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+      const double app = A[p + (long long)p * n].x, aqq = A[q + (long long)q * n].x;
+      if (mag > 0.0) {
+        e = make_double2(apq.x / mag, apq.y / mag);
+        const double zeta = (aqq - app) / (2.0 * mag);
+        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        c = 1.0 / sqrt(1.0 + tt * tt);
+        sn = tt * c;
+      }
+    }
+    r = JacRot{c, sn, e, p, q};
+    rot[s] = r;
+  }
+  __syncthreads();
+  if (r.q >= n || r.sn == 0.0) return;
+  const double2 ec = cconj(r.e);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double2 *ap = A + i + (long long)r.p * n, *aq = A + i + (long long)r.q * n;
+    const double2 x = *ap, y = cmul(ec, *aq);
+    *ap = make_double2(r.c * x.x - r.sn * y.x, r.c * x.y - r.sn * y.y);
+    *aq = make_double2(r.sn * x.x + r.c * y.x, r.sn * x.y + r.c * y.y);
+    if (V) {
+      double2 *vp = V + i + (long long)r.p * n, *vq = V + i + (long long)r.q * n;
+      const double2 vx = *vp, vy = cmul(ec, *vq);
+      *vp = make_double2(r.c * vx.x - r.sn * vy.x, r.c * vx.y - r.sn * vy.y);
+      *vq = make_double2(r.sn * vx.x + r.c * vy.x, r.sn * vx.y + r.c * vy.y);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_jac_rows(double2 *A, int n, const JacRot *rot) {
+  const JacRot r = rot[blockIdx.x];
+  if (r.q >= n || r.sn == 0.0) return;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double2 *ap = A + r.p + (long long)j * n, *aq = A + r.q + (long long)j * n;
+    const double2 x = *ap, y = cmul(r.e, *aq);
+    *ap = make_double2(r.c * x.x - r.sn * y.x, r.c * x.y - r.sn * y.y);
+    *aq = make_double2(r.sn * x.x + r.c * y.x, r.sn * x.y + r.c * y.y);
+  }
+}
+
+// eigenvalues ascending (ties by index) into w, the columns of V in that order
+__global__ __launch_bounds__(1024) void k_jac_sort(double2 *A, double2 *V, double *w, int n) {
+  __shared__ int perm[JACOBI_MAXN];
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int i = t; i < n; i += nt) {
+    const double di = A[i + (long long)i * n].x;
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double dj = A[j + (long long)j * n].x;
+      rank += (dj < di) || (dj == di && j < i);
+    }
+    perm[rank] = i;
+  }
+  __syncthreads();
+  for (int r = t; r < n; r += nt) w[r] = A[perm[r] + (long long)perm[r] * n].x;
+  if (V) {
+    __syncthreads();
+    for (long long e = t; e < (long long)n * n; e += nt) A[e] = V[e];
+    __syncthreads();
+    for (long long e = t; e < (long long)n * n; e += nt) {
+      const int i = (int)(e % n), r = (int)(e / n);
+      V[e] = A[i + (long long)perm[r] * n];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Per-step propagation of one state (blockIdx.x) of one k-point (blockIdx.y).
 // ---------------------------------------------------------------------------
@@ -1163,8 +1289,31 @@ hipError_t launch_trtri(const double2 *L, double2 *Li, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, A, V, w, n, 40);
+size_t jacobi_work_bytes(int n) { return (size_t)((n + 1) / 2) * sizeof(JacRot) + 256; }
+
+hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s, void *work) {
+  if (n <= JACOBI_ONE_BLOCK || !work) {
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, A, V, w, n, 40);
+    return hipGetLastError();
+  }
+  if (n > JACOBI_MAXN) return hipErrorInvalidValue;
+  const int m = (n + 1) & ~1;
+  int *done = static_cast<int *>(work);
+  JacRot *rot = reinterpret_cast<JacRot *>(static_cast<char *>(work) + 256);
+  if (V) hipLaunchKernelGGL(k_jac_init, dim3(std::min(1024, (n * n + 255) / 256)), dim3(256), 0, s, V, n);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    hipLaunchKernelGGL(k_jac_check, dim3(1), dim3(1024), 0, s, A, n, done);
+    int hd = 0;
+    hipError_t e = hipMemcpyAsync(&hd, done, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (hd) break;
+    for (int round = 0; round < m - 1; ++round) {
+      hipLaunchKernelGGL(k_jac_cols, dim3(m / 2), dim3(256), 0, s, A, V, n, round, rot);
+      hipLaunchKernelGGL(k_jac_rows, dim3(m / 2), dim3(256), 0, s, A, n, rot);
+    }
+  }
+  hipLaunchKernelGGL(k_jac_sort, dim3(1), dim3(1024), 0, s, A, V, w, n);
   return hipGetLastError();
 }
 
