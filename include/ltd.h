@@ -95,10 +95,14 @@ typedef struct {
                               convolution with the step function (Sec. 2.3, second route);
                               LTD_ROUTE_MM (1): as dense N_G x N_G matrices of Fourier coefficients
                               at G - G' applied by GEMM (Sec. 2.3, first route; App. A, Eq. (A.7)):
-                              five N_G^2 complex128 matrices per k-point in the workspace, FP64 only */
+                              five N_G^2 complex128 matrices per k-point in the workspace, FP64 only;
+                              LTD_ROUTE_FFT_PLANES (2): the FFT route with the apply's transforms as
+                              whole-plane x-y passes and z lines on every grid (LTD_ROUTE_FFT takes
+                              box arrays and the rebuild's x/z and y kernels where the grid has
+                              them); the same sums up to rounding order */
 } ltd_system_desc;
 
-enum { LTD_ROUTE_FFT = 0, LTD_ROUTE_MM = 1 };
+enum { LTD_ROUTE_FFT = 0, LTD_ROUTE_MM = 1, LTD_ROUTE_FFT_PLANES = 2 };
 
 /* Validates the description, copies its host arrays and plans every kernel;
  * returns in *workspace_bytes the device workspace the caller must bind.

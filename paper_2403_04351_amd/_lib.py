@@ -31,6 +31,7 @@ LTD_PULSE_SIN2 = 1
 LTD_PULSE_KICK = 2
 LTD_ROUTE_FFT = 0
 LTD_ROUTE_MM = 1
+LTD_ROUTE_FFT_PLANES = 2
 LTD_STEP_REBUILD = 0
 LTD_STEP_AFFINE = 1
 

@@ -104,6 +104,11 @@ struct ltd_system {
   // coordinates
   bool ap_red = false;
   size_t o_th_ap = 0, o_thv_ap = 0, o_ones = 0;
+  // the apply's box route (register x/z and y kernels of the rebuild on the apply
+  // grid): Theta and Theta V of the bound potential in the x/z kernel's layout
+  bool ap_box = false;
+  bool planes_only = false;  // LTD_ROUTE_FFT_PLANES: never the box route
+  size_t o_th_x = 0, o_thv_x = 0;
   int rb_variant = 0;      // launch shape of the x/z rebuild kernel (tuned)
   int vproj_target = 512;  // block target of the projection GEMM's K split (tuned)
   // side stream of the rebuild: the muffin-tin branch runs beside the FFT chain
@@ -525,6 +530,74 @@ ApplyBufs workspace_bufs(const ltd_system *sys) {
   return b;
 }
 
+// Interstitial part of an apply by the box route: the y images of the input
+// fields (psi, and pi_x, pi_y, pi_z unless MODE_V), the rebuild's x/z kernel
+// once per (input field, multiplier) pass with the fields as pseudo k-points
+// (psi Theta, pi_i Theta into fields 0, 2, 3, 4; psi Theta V into field 1), its
+// y kernel (sphere order, into slab_in: the y images are read by then) and the
+// mode's combination.  The slabs hold box arrays (nbz x N2 x nbx per column and
+// field) instead of whole planes.
+ltd_status apply_box(ltd_system *sys, int k, int mode, double al, double be, const double2 *C, int ldc, int cols,
+                     double2 *const out[4], const int ldo[4], const ApplyBufs &bf, hipStream_t s) {
+  const Grid g = agrid_of(sys);
+  const KSphere sp = sphere_ap(sys, k);
+  const long long bsz = (long long)g.nbz * g.n2 * g.nbx * cols;  // one field's box slab
+  const bool vm = mode == FFT_MODE_V;
+  // the five sphere-order fields reuse slab_in (four plane fields per column)
+  if (5LL * sp.n_g > 4LL * g.nbz * g.n1 * g.n2) return LTD_EUNSUPPORTED;
+  FftKArgs ka{};
+  ka.sph[0] = sp;
+  ka.in[0].c = C;
+  ka.in[0].ldc = ldc;
+  ka.slab_out[0] = bf.slab_in;
+  LTD_HIP(fft_ap_inverse_y(g, ka, cols, vm ? 1 : 4, s));
+  const double *th = sys->at<double>(sys->o_th_x);
+  const double *thv = sys->at<double>(sys->ap_red ? sys->o_thv_x : sys->o_thv_rb);
+  const int np = vm ? 1 : 4, fout[4] = {0, 2, 3, 4};
+  FftKArgs kx{};
+  for (int i = 0; i < np; ++i) {
+    kx.sph[i] = sp;
+    kx.slab_in[i] = bf.slab_in + i * bsz;
+    kx.slab_out[i] = bf.slab_out + fout[i] * bsz;
+  }
+  LTD_HIP(fft_rb_step(g, kx, np, cols, th, s, 0, false, 0));
+  if (!vm) {
+    FftKArgs kv{};
+    kv.sph[0] = sp;
+    kv.slab_in[0] = bf.slab_in;
+    kv.slab_out[0] = bf.slab_out + bsz;
+    LTD_HIP(fft_rb_step(g, kv, 1, cols, thv, s, 0, false, 0));
+  }
+  const int nf = vm ? 1 : 5;
+  double2 *ys = bf.slab_in;
+  // the y kernel decodes the sphere positions on the grid of the sphere tables
+  // (g.d1, g.d2), as in the rebuild; the sphere order is the same
+  const KSphere spy = sphere_of(sys, k);
+  FftKArgs ky{};
+  for (int f = 0; f < nf; ++f) {
+    ky.sph[f] = spy;
+    ky.slab_in[f] = bf.slab_out + f * bsz;
+    ky.out[f].o0 = ys + (long long)f * sp.n_g * cols;
+    ky.out[f].ld0 = sp.n_g;
+  }
+  LTD_HIP(fft_rb_step(g, ky, nf, cols, th, s, 1, false, 0));
+  FwdOut fo{};
+  fo.o0 = out[0];
+  fo.ld0 = ldo[0];
+  if (!vm) {
+    fo.o1 = out[1];
+    fo.ld1 = ldo[1];
+  }
+  if (mode == FFT_MODE_TVPS) {
+    fo.o2 = out[2];
+    fo.o3 = out[3];
+    fo.ld2 = ldo[2];
+    fo.ld3 = ldo[3];
+  }
+  LTD_HIP(fft_ap_combine(fo, sp, ys, cols, mode, al, be, s));
+  return LTD_OK;
+}
+
 ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const double2 *C, int ldc, int cols,
                        double2 *const out[4], const int ldo[4], hipStream_t s, Prof *pf, const ApplyBufs &bf) {
   if (cols <= 0) return LTD_OK;
@@ -533,6 +606,13 @@ ltd_status apply_chunk(ltd_system *sys, int k, int mode, double a_z, const doubl
   const double al = a_z / sys->c_light, be = a_z * a_z / (2.0 * sys->c_light * sys->c_light);
   if (sys->route == LTD_ROUTE_MM) {  // interstitial by the dense blocks (first route)
     LTD_TRY(apply_mm(sys, k, mode, al, be, C, ldc, cols, out, ldo, bf, s));
+    LTD_MARK(pf, 2);
+    return apply_mt(sys, k, mode, al, be, C, ldc, cols, out, ldo, s, pf, bf);
+  }
+  if (sys->ap_box) {
+    LTD_TRY(apply_box(sys, k, mode, al, be, C, ldc, cols, out, ldo, bf, s));
+    LTD_MARK(pf, 0);
+    LTD_MARK(pf, 1);
     LTD_MARK(pf, 2);
     return apply_mt(sys, k, mode, al, be, C, ldc, cols, out, ldo, s, pf, bf);
   }
@@ -714,6 +794,10 @@ ltd_status apply_s(ltd_system *sys, int k, const double2 *X, int ldx, int n, dou
     if (sys->route == LTD_ROUTE_MM) {
       LTD_TRY(gemm1(sys, OP_N, OP_N, zp(kh.n_g, cols, kh.n_g, sys->at<double2>(kh.o_mmS), kh.n_g, x, ldx, out, ld),
                     s));
+    } else if (sys->ap_box) {
+      double2 *o[4] = {out, nullptr, nullptr, nullptr};
+      const int lo[4] = {ld, 0, 0, 0};
+      LTD_TRY(apply_box(sys, k, FFT_MODE_V, 0.0, 0.0, x, ldx, cols, o, lo, bf, s));
     } else {
       const Grid g = agrid_of(sys);
       FftKArgs ka{};
@@ -1390,7 +1474,9 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   if (!aligned16(d->amat) || (d->n_atoms > 0 && (!aligned16(d->h) || !aligned16(d->o) || !aligned16(d->pz))))
     return LTD_EALIGN;
   if (d->n_aux > 320) return LTD_EUNSUPPORTED;
-  if (d->interstitial_route != LTD_ROUTE_FFT && d->interstitial_route != LTD_ROUTE_MM) return LTD_EINVAL;
+  if (d->interstitial_route != LTD_ROUTE_FFT && d->interstitial_route != LTD_ROUTE_MM &&
+      d->interstitial_route != LTD_ROUTE_FFT_PLANES)
+    return LTD_EINVAL;
   if (d->interstitial_route == LTD_ROUTE_MM && precision != LTD_FP64) return LTD_EUNSUPPORTED;
   auto *sys = new ltd_system();
   sys->n_k = d->n_k;
@@ -1441,7 +1527,8 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->n_states = d->n_states;
   sys->max_cols = d->max_cols;
   sys->precision = precision;
-  sys->route = d->interstitial_route;
+  sys->route = d->interstitial_route == LTD_ROUTE_MM ? LTD_ROUTE_MM : LTD_ROUTE_FFT;
+  sys->planes_only = d->interstitial_route == LTD_ROUTE_FFT_PLANES;
   // G sets, box, sphere tables
   long long gtot = 0;
   int bx = 0, by = 0, bz = 0;
@@ -1544,6 +1631,13 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   // the columns take several passes, a multiple of the GEMMs' 64-column tile
   // (a 45-column pass computes 64 columns' worth of muffin-tin MFMA work)
   const Grid &ag = sys->ap_red ? sys->rgrid : g;  // grid of the apply's FFT passes
+  // the box route runs where the apply grid has the register plane and x/z kernels
+  // (on the rebuild grid, or the grid itself when it is the rebuild grid); its
+  // slabs hold box arrays: 4 y images (or the 5 sphere-order fields) in, 5 out
+  // (the passes keep the plane route's width: one pass of 300 heterostructure
+  // columns made the muffin-tin GEMMs slower, 3.55 -> 4.33 ms, and the step too)
+  sys->ap_box = sys->route == LTD_ROUTE_FFT && !sys->planes_only && (sys->ap_red || !sys->rb_synth) &&
+                fft_ap_box_ok(ag);
   const long long per_col = 9LL * ag.nbz * ag.n1 * ag.n2 * (long long)sizeof(double2);
   const int cmax = std::max(sys->max_cols, sys->n_aux);
   sys->chunk = (int)std::max(1LL, std::min<long long>(cmax, (6LL << 30) / per_col));
@@ -1564,7 +1658,12 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     const size_t rn = (size_t)sys->rgrid.n1 * sys->rgrid.n2 * sys->rgrid.n3;
     sys->o_th_ap = ar.take(rn * sizeof(double));
     sys->o_thv_ap = ar.take(rn * sizeof(double));
-    sys->o_ones = ar.take(sys->ngrid * sizeof(double));
+  }
+  if (sys->ap_red || sys->ap_box) sys->o_ones = ar.take(sys->ngrid * sizeof(double));
+  if (sys->ap_box) {
+    const size_t rn = (size_t)ag.n1 * ag.n2 * ag.n3;
+    sys->o_th_x = ar.take(rn * sizeof(double));
+    sys->o_thv_x = sys->ap_red ? ar.take(rn * sizeof(double)) : 0;  // else the rebuild's Theta V
   }
   // [0..1] status, [8] step-kernel block counter, [12..13] and [14..15] step index
   // and last step of the pipelined rebuild (muffin-tin branch, potential synthesis)
@@ -1762,19 +1861,28 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
   LTD_HIP(launch_thv(sys->at<double>(sys->o_thv), sys->theta, sys->v_r, sys->ngrid, s));
   if (sys->route == LTD_ROUTE_FFT) {
     LTD_TRY(rebuild_potential(sys, sys->v_r, nullptr, 0, sys->at<double>(sys->o_thv_rb), false, s));
-    if (sys->ap_red) {  // Theta and Theta V of the bound potential on the apply grid, grid order
+    if (sys->ap_red || sys->ap_box) {
       const std::vector<double> ones(sys->ngrid, 1.0);
       LTD_HIP(hipMemcpy(sys->ws + sys->o_ones, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
-      const auto syn = [&](const double *v, size_t off) -> ltd_status {
+    }
+    if (sys->ap_red) {  // Theta and Theta V of the bound potential on the apply grid, grid order
+      const auto syn = [&](const double *v, size_t off, bool plain) -> ltd_status {
         LTD_HIP(fft_rb_synth(rgrid_of(sys), sys->n1, sys->n2, sys->n3, sys->theta, v, nullptr, 0,
                              sys->at<double>(sys->o_M1), sys->at<double>(sys->o_M2), sys->at<double>(sys->o_M3),
                              sys->at<double>(sys->o_F1), sys->at<double>(sys->o_F2), sys->at<double>(sys->o_F3),
                              sys->at<double>(sys->o_syn1), sys->at<double>(sys->o_syn2), sys->at<double>(off),
-                             nullptr, false, s, true));
+                             nullptr, false, s, plain));
         return LTD_OK;
       };
-      LTD_TRY(syn(sys->at<double>(sys->o_ones), sys->o_th_ap));
-      LTD_TRY(syn(sys->v_r, sys->o_thv_ap));
+      LTD_TRY(syn(sys->at<double>(sys->o_ones), sys->o_th_ap, true));
+      LTD_TRY(syn(sys->v_r, sys->o_thv_ap, true));
+      if (sys->ap_box) {  // the same two in the x/z kernel's layout
+        LTD_TRY(syn(sys->at<double>(sys->o_ones), sys->o_th_x, false));
+        LTD_TRY(syn(sys->v_r, sys->o_thv_x, false));
+      }
+    } else if (sys->ap_box) {  // Theta alone in the x/z layout on the grid itself
+      LTD_HIP(fft_rb_thv(grid_of(sys), sys->theta, sys->at<double>(sys->o_ones), nullptr, 0,
+                         sys->at<double>(sys->o_th_x), nullptr, false, s));
     }
   } else {  // the dense interstitial blocks of every k-point (natural G order)
     const Grid g = grid_of(sys);

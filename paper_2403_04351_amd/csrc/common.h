@@ -188,6 +188,16 @@ struct FftKArgs {
 };
 
 // slab layout per k: [field][col][pz][y][x]; field stride = ncols * nbz * N1 * N2.
+// Box route of the apply (square 72- or 64-point planes with the register x/z
+// kernel, box within the exact-grid bound): fft_ap_inverse_y writes the y images
+// of nfields input fields (ka.sph[0], ka.in[0] -> ka.slab_out[0], field stride
+// ncols * nbz * N2 * nbx); the rebuild's x/z kernel (fft_rb_step part 0, one
+// pseudo k-point per field pass) and y kernel (part 1, sphere order) follow;
+// fft_ap_combine forms the mode's outputs from the five (MODE_V: one) fields.
+bool fft_ap_box_ok(const Grid &g);
+hipError_t fft_ap_inverse_y(const Grid &g, const FftKArgs &ka, int ncols, int nfields, hipStream_t s);
+hipError_t fft_ap_combine(const FwdOut &fo, const KSphere &sp, const double2 *ys, int ncols, int mode, double alpha_a,
+                          double beta_a, hipStream_t s);
 hipError_t fft_inverse_planes(const Grid &g, const FftKArgs &ka, int nk, int ncols, int nfields,
                               hipStream_t s);
 hipError_t fft_lines(const Grid &g, const FftKArgs &ka, int nk, int ncols, int mode,

@@ -1494,6 +1494,97 @@ __global__ __launch_bounds__(256) void k_inv_plane_reg(const Grid g, const FftKA
   }
 }
 
+// Inverse y transforms of the apply's box route: per (kz plane, column) the
+// sphere coefficients of each input field (times 1 or (G+k)_i) into the box
+// columns B[kx][y], their inverse y transforms in place (as k_inv_plane_reg),
+// and the y image of the plane out: c[f][col][kz][y][kx] (the layout the x/z
+// kernel reads, fstride values per field).  grid (nbz, ncols).
+template <int N>
+__global__ __launch_bounds__(256) void k_ap_inv_y(const Grid g, const FftKArgs ka, int ncols, int nfields) {
+  constexpr int F1 = 8, F2 = N / F1;
+  using TT = Two<N, F1, F2>;
+  constexpr int G = TT::G, LPW = TT::LPW, RP = rb_pitch(N);
+  constexpr int LO = zr_lo<N, F2>(), HI = zr_hi<N, F2>();
+  extern __shared__ double2 sm_raw[];
+  const int pz = blockIdx.x, col = blockIdx.y;
+  const int bx = g.bx, nbx = g.nbx, nbz = g.nbz;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane / G, r = lane - li * G;
+  double2 *B = sm_raw;
+  const KSphere &sp = ka.sph[0];
+  const InvIn in = ka.in[0];
+  const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
+  const long long fstride = (long long)ncols * nbz * N * nbx;
+  double2 *out = ka.slab_out[0] + ((long long)col * nbz + pz) * N * nbx;
+  double2 twt[F1];
+#pragma unroll
+  for (int j = 0; j < F1; ++j) twt[j] = g.tw2[(r * j) % N];
+  double2 pc[PLANE_PPT];
+  double pk[PLANE_PPT][3];
+  int ps[PLANE_PPT];
+#pragma unroll
+  for (int k = 0; k < PLANE_PPT; ++k) {
+    const int i = p0 + threadIdx.x + k * (int)blockDim.x;
+    ps[k] = -1;
+    if (i < p1) {
+      const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+      const int y = xy / g.n1, x = xy - y * g.n1;
+      ps[k] = box_of(x, g.n1, bx) * RP + y;
+      pc[k] = in.c[(long long)gi + (long long)col * in.ldc];
+      if (nfields > 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) pk[k][d] = sp.gk[3 * gi + d];
+    }
+  }
+  for (int f = 0; f < nfields; ++f) {
+    for (int i = threadIdx.x; i < nbx * RP; i += blockDim.x) B[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PLANE_PPT; ++k)
+      if (ps[k] >= 0) B[ps[k]] = f > 0 ? cscale(pc[k], pk[k][f - 1]) : pc[k];
+    for (int i = p0 + threadIdx.x + PLANE_PPT * (int)blockDim.x; i < p1; i += blockDim.x) {
+      const int gi = sp.pts_g[i], xy = sp.pts_xy[i];
+      double2 c = in.c[(long long)gi + (long long)col * in.ldc];
+      if (f > 0) c = cscale(c, sp.gk[3 * gi + (f - 1)]);
+      const int y = xy / g.n1, x = xy - y * g.n1;
+      B[box_of(x, g.n1, bx) * RP + y] = c;
+    }
+    __syncthreads();
+    for (int b0 = wave * LPW; b0 < nbx; b0 += 4 * LPW) {
+      const int b = b0 + li;
+      const bool on = li < LPW && b < nbx;
+      double2 *row = B + (on ? b : 0) * RP;
+      if (on && r < F2) {  // reads and writes only the slots r + F2 j of its line
+        double2 v[F1];
+#pragma unroll
+        for (int n1 = 0; n1 < F1; ++n1) v[n1] = (n1 >= LO && n1 <= HI) ? make_double2(0.0, 0.0) : row[F2 * n1 + r];
+        dft_first<F1, 1, LO, HI>(v);
+        twiddle_tab<F1, 1>(v, twt);
+#pragma unroll
+        for (int k1 = 0; k1 < F1; ++k1) row[k1 * F2 + r] = v[k1];
+      }
+      wave_fence();
+      if (on && r < F1) {
+        double2 u[F2];
+#pragma unroll
+        for (int q = 0; q < F2; ++q) u[q] = row[r * F2 + q];
+        dft_reg<F2, 1>(u);
+        wave_fence();
+#pragma unroll
+        for (int k2 = 0; k2 < F2; ++k2) row[r + F1 * k2] = u[k2];
+      }
+      wave_fence();
+    }
+    __syncthreads();
+    double2 *o = out + f * fstride;
+    for (int i = threadIdx.x; i < N * nbx; i += blockDim.x) {
+      const int y = i / nbx, b = i - y * nbx;
+      o[i] = B[b * RP + y];
+    }
+    __syncthreads();  // the next field rewrites B
+  }
+}
+
 // The forward pass's outputs of one sphere point, accumulated over the fields
 // in the order of fwd_out_point (the same sums), stored after the last field.
 template <int MODE>
@@ -1532,6 +1623,32 @@ struct FwdAcc {
     }
   }
 };
+
+// The apply's outputs at the sphere points from the five forward-transformed
+// fields in sphere-table order (ys[f]: n_g x ncols, ld n_g, already scaled by
+// 1/N): the sums of FwdAcc in registers, one store per output.  MODE_V: one field.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_ap_combine(const FwdOut fo, const KSphere sp, const double2 *ys, int ncols,
+                                                    double alpha_a, double beta_a) {
+  constexpr int NF = MODE == FFT_MODE_V ? 1 : 5;
+  const int ng = sp.n_g;
+  const long long fs = (long long)ng * ncols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < fs; e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % ng), c = (int)(e / ng);
+    const int gi = sp.pts_g[i];
+    double gk[3] = {0.0, 0.0, 0.0};
+    if constexpr (MODE != FFT_MODE_V)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gk[d] = sp.gk[3 * gi + d];
+    double2 y[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) y[f] = ys[f * fs + e];
+    FwdAcc<MODE> acc;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc.add(f, y[f], gk, alpha_a, beta_a);
+    acc.store(fo, gi, c);
+  }
+}
 
 // Forward: per output field, the forward x transforms of the slab rows (only
 // the box outputs kept, into the box columns; each pass's rows loaded during
@@ -2704,6 +2821,33 @@ size_t fft_plane_lds_bytes(const Grid &g) { return plane_lds(g); }
 size_t fft_line_lds_bytes(const Grid &g) { return line_lds(g, line_tile(g, false), false); }
 
 // the register plane passes: square 72- or 64-point planes, box within the exact-grid bound
+bool plane_reg_ok(const Grid &g);
+
+bool fft_ap_box_ok(const Grid &g) { return plane_reg_ok(g) && rb_fast(g); }
+
+hipError_t fft_ap_inverse_y(const Grid &g, const FftKArgs &ka, int ncols, int nfields, hipStream_t s) {
+  set_attrs();
+  if (!fft_ap_box_ok(g)) return hipErrorInvalidValue;
+  const dim3 grid(g.nbz, ncols, 1);
+  const size_t lds = (size_t)g.nbx * rb_pitch(g.n2) * sizeof(double2);
+  if (g.n2 == 72) hipLaunchKernelGGL(k_ap_inv_y<72>, grid, dim3(256), lds, s, g, ka, ncols, nfields);
+  else hipLaunchKernelGGL(k_ap_inv_y<64>, grid, dim3(256), lds, s, g, ka, ncols, nfields);
+  return hipGetLastError();
+}
+
+hipError_t fft_ap_combine(const FwdOut &fo, const KSphere &sp, const double2 *ys, int ncols, int mode, double alpha_a,
+                          double beta_a, hipStream_t s) {
+  const long long tot = (long long)sp.n_g * ncols;
+  const int nb = (int)std::min<long long>((tot + 255) / 256, 16384);
+  if (mode == FFT_MODE_V)
+    hipLaunchKernelGGL(k_ap_combine<FFT_MODE_V>, dim3(nb), dim3(256), 0, s, fo, sp, ys, ncols, alpha_a, beta_a);
+  else if (mode == FFT_MODE_HS)
+    hipLaunchKernelGGL(k_ap_combine<FFT_MODE_HS>, dim3(nb), dim3(256), 0, s, fo, sp, ys, ncols, alpha_a, beta_a);
+  else
+    hipLaunchKernelGGL(k_ap_combine<FFT_MODE_TVPS>, dim3(nb), dim3(256), 0, s, fo, sp, ys, ncols, alpha_a, beta_a);
+  return hipGetLastError();
+}
+
 bool plane_reg_ok(const Grid &g) {
   return g.n1 == g.n2 && (g.n1 == 72 || g.n1 == 64) && 4 * g.bx + 1 <= g.n1 && 4 * g.by + 1 <= g.n2;
 }

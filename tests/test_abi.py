@@ -121,6 +121,8 @@ def test_create_rejects_bad_arguments(lib, sys0):
     assert create(lib, Desc(sys0, grid=(C.c_int * 3)(16, 16, 7)))[0] == _lib.LTD_EUNSUPPORTED
     assert create(lib, Desc(sys0, n_aux=400, n_states=4))[0] == _lib.LTD_EUNSUPPORTED
     assert create(lib, Desc(sys0), precision=7)[0] == _lib.LTD_EUNSUPPORTED
+    assert create(lib, Desc(sys0, interstitial_route=3))[0] == _lib.LTD_EINVAL
+    assert create(lib, Desc(sys0, interstitial_route=_lib.LTD_ROUTE_FFT_PLANES))[0] == 0
 
 
 def test_create_rejects_non_injective_g_set(lib, sys0):
