@@ -8,7 +8,7 @@ projected and nothing is propagated here.
 
 from .lapw_inputs import (  # noqa: F401
     C_LIGHT,
-    CONFIGS,
+    WORKLOADS,
     Atom,
     KPoint,
     System,

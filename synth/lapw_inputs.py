@@ -139,7 +139,7 @@ def _diatomic(cell, lmax, n_lo, rmt=1.0, bond=2.13):
             dict(pos=c + d, rmt=rmt, lmax=lmax, n_lo=n_lo)]
 
 
-CONFIGS = {
+WORKLOADS = {
     # Tiny plain FP64 reference.
     0: dict(cell=(10.0, 10.0, 10.0), grid=(16, 16, 16), n_g=200,
             atoms=("diatomic", 3, 4), kgrid=None, n_aux=16, n_states=4,
@@ -275,7 +275,7 @@ def make_system(cfg: int, seed: Optional[int] = None, with_start: bool = True, *
     scaled variants with the same recipe; ``n_k`` keeps only the first n_k
     k-points.
     """
-    p = dict(CONFIGS[cfg])
+    p = dict(WORKLOADS[cfg])
     n_k_keep = over.pop("n_k", None)
     p.update(over)
     rng = np.random.default_rng(_SEED_BASE + cfg if seed is None else seed)
