@@ -51,8 +51,8 @@ struct KHost {
   int n_g, n_basis, k_ext;
   size_t g_off;            // first G of this k in the concatenated arrays
   size_t amat_off;         // element offset of A_k
-  std::vector<int> plane_ptr, pts_g, pts_xy, pts_xy_a;
-  size_t o_ptsxy_a = 0;
+  std::vector<int> plane_ptr, pts_g, pts_xy, pts_xy_a, plane_x;
+  size_t o_ptsxy_a = 0, o_pxr = 0;
   // workspace offsets
   size_t o_gk, o_pptr, o_ptsg, o_ptsxy;
   size_t o_subs;           // Tsub, Vsub, Psub, Ssub (4 n^2, Phi basis)
@@ -391,6 +391,7 @@ KSphere sphere_of(const ltd_system *sys, int k) {
   sp.plane_ptr = sys->at<int>(h.o_pptr);
   sp.pts_g = sys->at<int>(h.o_ptsg);
   sp.pts_xy = sys->at<int>(h.o_ptsxy);
+  sp.plane_x = sys->at<int>(h.o_pxr);
   sp.n_g = h.n_g;
   return sp;
 }
@@ -1609,6 +1610,13 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     }
     kh.plane_ptr.push_back(0);
     for (int p = 0; p < g.nbz; ++p) {
+      int xlo = g.nbx, xhi = 0;  // box-x lines of the plane's points
+      for (int i : byplane[p]) {
+        xlo = std::min(xlo, sys->g_int[3 * (goff + i)] + g.bx);
+        xhi = std::max(xhi, sys->g_int[3 * (goff + i)] + g.bx + 1);
+      }
+      kh.plane_x.push_back(xlo < xhi ? xlo : 0);
+      kh.plane_x.push_back(xlo < xhi ? xhi : 0);
       for (int i : byplane[p]) {
         const int *gi = &sys->g_int[3 * (goff + i)];
         const int x = (gi[0] % g.n1 + g.n1) % g.n1, y = (gi[1] % g.n2 + g.n2) % g.n2;
@@ -1740,6 +1748,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
     KHost &kh = sys->kh[k];
     kh.o_gk = ar.take((size_t)3 * kh.n_g * sizeof(double));
     kh.o_pptr = ar.take((size_t)(g.nbz + 1) * sizeof(int));
+    kh.o_pxr = ar.take((size_t)2 * g.nbz * sizeof(int));
     kh.o_ptsg = ar.take((size_t)kh.n_g * sizeof(int));
     kh.o_ptsxy = ar.take((size_t)kh.n_g * sizeof(int));
     if (sys->ap_red) kh.o_ptsxy_a = ar.take((size_t)kh.n_g * sizeof(int));
@@ -1842,6 +1851,7 @@ ltd_status ltd_bind_workspace(ltd_system *sys, void *ws, size_t bytes, void *str
     KHost &kh = sys->kh[k];
     LTD_HIP(hipMemcpy(sys->ws + kh.o_gk, &sys->gk[3 * kh.g_off], 3 * kh.n_g * sizeof(double), hipMemcpyHostToDevice));
     LTD_HIP(hipMemcpy(sys->ws + kh.o_pptr, kh.plane_ptr.data(), kh.plane_ptr.size() * sizeof(int), hipMemcpyHostToDevice));
+    LTD_HIP(hipMemcpy(sys->ws + kh.o_pxr, kh.plane_x.data(), kh.plane_x.size() * sizeof(int), hipMemcpyHostToDevice));
     LTD_HIP(hipMemcpy(sys->ws + kh.o_ptsg, kh.pts_g.data(), kh.n_g * sizeof(int), hipMemcpyHostToDevice));
     LTD_HIP(hipMemcpy(sys->ws + kh.o_ptsxy, kh.pts_xy.data(), kh.n_g * sizeof(int), hipMemcpyHostToDevice));
     if (sys->ap_red)

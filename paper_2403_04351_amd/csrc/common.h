@@ -75,6 +75,10 @@ struct ZProb {
   int tile_begin;                        // first logical tile of this problem
   int rtile_begin;                       // first output tile (reduction pass)
   long long part_off;                    // offset (tiles) into the split-K partial buffer
+  // launch-wide (the same in every problem): the output tiles of the launch when
+  // its logical tiles run K-chunk-major (every problem split by the same factor:
+  // the tiles of one K chunk of all problems are adjacent), else 0
+  int kmajor;
 };
 
 constexpr int GEMM_MAXP = 8;  // problems passed by value in one launch
@@ -156,6 +160,7 @@ struct KSphere {
   const int *plane_ptr;   // [nbz+1] CSR over kz planes
   const int *pts_g;       // [n_g] G index, sorted by plane
   const int *pts_xy;      // [n_g] position y*N1 + x of the point in its plane
+  const int *plane_x;     // [2 nbz] box-x range [lo, hi) of each plane's points (lo = hi: none)
   int n_g;
 };
 

@@ -2047,7 +2047,9 @@ __device__ __forceinline__ void xch8_split(float2 *sd, int r, const float2 (&in)
 }
 
 // y transforms of the rebuild step for N2' = 64, nbx <= 32 and by <= 15: one
-// block per (kz, column), one line per box x (4 waves x 8 lines x 8 lanes).
+// block per (kz, column), one line per box x (4 waves x 8 lines x 8 lanes) from
+// the first to the last x with a sphere point in the plane (the slab lines
+// outside that range are never read out: about a fifth of them on a sphere).
 // Each lane loads the values y = rx + 8 b of its line straight from the slab
 // (eight 128-byte runs per load across a wave), runs the two-factor forward
 // transform of k_rb_xz4's phase 3 with the exchange through a per-line scratch
@@ -2071,7 +2073,9 @@ __global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka,
   const T *src = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)pz * N * nbx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane >> 3, rx = lane & 7;
-  const int line = wave * 8 + lx;
+  // lines from the first box x with a sphere point in the plane to the last
+  const int line = sp.plane_x[2 * pz] + wave * 8 + lx;
+  const bool on = line < sp.plane_x[2 * pz + 1];
   // complex64: this thread's sphere points of the plane, read before the transforms
   constexpr int PP = sizeof(T) == 8 ? PLANE_PPT : 0;
   const int p0 = sp.plane_ptr[pz], p1 = sp.plane_ptr[pz + 1];
@@ -2082,7 +2086,7 @@ __global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka,
     pxy[k] = i < p1 ? sp.pts_xy[i] : 0;
   }
   T v[8];
-  if (line < nbx) {
+  if (on) {
     T twt[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) twt[j] = CT<T>::from(g.tw2[(rx * j) & 63]);
@@ -2095,7 +2099,7 @@ __global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka,
     dft8<-1>(v);
   }
   __syncthreads();  // every line has left the scratch
-  if (line < nbx) {
+  if (on) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       if (c >= 2 && c <= 5) continue;  // |ky| >= 16 > by
@@ -2122,7 +2126,8 @@ __global__ __launch_bounds__(256) void k_rb_y64(const Grid g, const FftKArgs ka,
 }
 
 // y transforms of the rebuild step for N2' = 72 = 8 x 9 and nbx <= 35: one block
-// per (kz, column), one line per box x (5 waves x 7 lines x 9 lanes).  Each lane
+// per (kz, column), one line per box x (5 waves x 7 lines x 9 lanes) from the
+// first to the last x with a sphere point in the plane.  Each lane
 // a < 8 loads the values y = a + 8 b (b < 9) of its line from the slab, runs the
 // forward two-factor transform of k_rb_xz4's phase 3 (length 9 over b, twiddles
 // w^(a d) from a per-lane table, exchange through a per-line scratch, length 8
@@ -2149,8 +2154,9 @@ __global__ __launch_bounds__(320) void k_rb_y72(const Grid g, const FftKArgs ka,
   const T *src = reinterpret_cast<const T *>(ka.slab_in[kk]) + (long long)col * csz + (long long)pz * N * nbx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane / F2, r = lane - lx * F2;
-  const int line = wave * LPW + lx;
-  const bool on = lx < LPW && line < nbx;
+  // lines from the first box x with a sphere point in the plane to the last
+  const int line = sp.plane_x[2 * pz] + wave * LPW + lx;
+  const bool on = lx < LPW && line < sp.plane_x[2 * pz + 1];
   // complex64: this thread's sphere points of the plane, read before the
   // transforms (complex128: read at the read-out; the registers would cost a
   // wave per SIMD, measured 164 -> 182 us)

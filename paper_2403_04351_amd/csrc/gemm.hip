@@ -37,6 +37,39 @@ __device__ inline int xcd_logical(int b, int g) {
   return (x < rem) ? x * (q + 1) + r : rem * (q + 1) + (x - rem) * q + r;
 }
 
+// Problem and tile of a logical tile.  Problem-major order: the tiles of each
+// problem are contiguous (tile rows fastest, then tile columns, batch entries,
+// K chunks).  K-major order (kmajor > 0, every problem split by the same factor):
+// logical = ks * kmajor + the output tile's index over all problems, so the
+// problems' tiles of one K chunk are adjacent and land on one XCD, where they
+// share the operand panels of that chunk in L2 (the blocks of a Hermitian
+// block-row product read the same columns of both operands).
+struct TileAt {
+  int pi, tm, tn, bi, ks;
+};
+__device__ inline TileAt tile_at(const ZProb *probs, int nprob, int logical) {
+  TileAt r{};
+  const int kmt = probs[0].kmajor;
+  int t;
+  if (kmt > 0) {
+    const int q = logical % kmt;
+    r.ks = logical / kmt;
+    while (r.pi + 1 < nprob && probs[r.pi + 1].rtile_begin <= q) ++r.pi;
+    t = q - probs[r.pi].rtile_begin;
+  } else {
+    while (r.pi + 1 < nprob && probs[r.pi + 1].tile_begin <= logical) ++r.pi;
+    t = logical - probs[r.pi].tile_begin;
+  }
+  const ZProb &P = probs[r.pi];
+  r.tm = t % P.tiles_m;
+  t /= P.tiles_m;
+  r.tn = t % P.tiles_n;
+  t /= P.tiles_n;
+  r.bi = t % P.batch;
+  if (kmt == 0) r.ks = t / P.batch;
+  return r;
+}
+
 // Global-memory operand pointer (address space 1: global loads, not flat ones).
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef const d2v __attribute__((address_space(1))) *gptr;
@@ -165,18 +198,9 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
   __shared__ double Bs[2][2][BK][BN + LP];
 
   const ZProb *probs = TABLE ? table : batch.p;
-  const int logical = xcd_logical(blockIdx.x, gridDim.x);
-  int pi = 0;
-  while (pi + 1 < nprob && probs[pi + 1].tile_begin <= logical) ++pi;
-  const ZProb &P = probs[pi];
-
-  int t = logical - P.tile_begin;
-  const int tm = t % P.tiles_m;
-  t /= P.tiles_m;
-  const int tn = t % P.tiles_n;
-  t /= P.tiles_n;
-  const int bi = t % P.batch;
-  const int ks = t / P.batch;
+  const TileAt at = tile_at(probs, nprob, xcd_logical(blockIdx.x, gridDim.x));
+  const ZProb &P = probs[at.pi];
+  const int tm = at.tm, tn = at.tn, bi = at.bi, ks = at.ks;
 
   const int m0 = tm * MB, n0 = tn * BN;
   Ops o;
@@ -389,17 +413,9 @@ __global__ __launch_bounds__(NT) void cgemm32_kernel(const ZBatch batch, const Z
   __shared__ float As[2][2][BK][MB + 4];
   __shared__ float Bs[2][2][BK][BN + 4];
   const ZProb *probs = TABLE ? table : batch.p;
-  const int logical = xcd_logical(blockIdx.x, gridDim.x);
-  int pi = 0;
-  while (pi + 1 < nprob && probs[pi + 1].tile_begin <= logical) ++pi;
-  const ZProb &P = probs[pi];
-  int t = logical - P.tile_begin;
-  const int tm = t % P.tiles_m;
-  t /= P.tiles_m;
-  const int tn = t % P.tiles_n;
-  t /= P.tiles_n;
-  const int bi = t % P.batch;
-  const int ks = t / P.batch;
+  const TileAt at = tile_at(probs, nprob, xcd_logical(blockIdx.x, gridDim.x));
+  const ZProb &P = probs[at.pi];
+  const int tm = at.tm, tn = at.tn, bi = at.bi, ks = at.ks;
   const int m0 = tm * MB, n0 = tn * BN;
   const gptr32 A = (gptr32)(const void *)(reinterpret_cast<const float2 *>(P.A) + (long long)bi * P.sA);
   const gptr32 B = (gptr32)(const void *)(reinterpret_cast<const float2 *>(P.B) + (long long)bi * P.sB);
@@ -665,6 +681,16 @@ long long plan_bm(ZProb *probs, int nprob, int bm, int target_blocks, long long 
     if (P.ksplit > 1) part += (long long)base * P.ksplit;
     if (base > 0 && kt_per > kt_max) kt_max = kt_per;
   }
+  // K-major order when every problem with tiles is split by the same factor
+  int ks_all = 0;
+  for (int i = 0; i < nprob && ks_all >= 0; ++i) {
+    const ZProb &P = probs[i];
+    if (P.tiles_m * P.tiles_n * P.batch == 0) continue;
+    if (ks_all == 0) ks_all = P.ksplit;
+    else if (P.ksplit != ks_all) ks_all = -1;
+  }
+  const int kmajor = (ks_all > 1 && (long long)rb * ks_all == tb) ? rb : 0;
+  for (int i = 0; i < nprob; ++i) probs[i].kmajor = kmajor;
   *total_tiles = tb;
   *part_tiles = part;
   constexpr int CUS = 256;
