@@ -828,7 +828,9 @@ __global__ __launch_bounds__(STEP_NT) void k_step(const StepCtx c) {
 // thread per matrix row (blockDim = 64 ceil(n / 64)), each product Y_s = A X_s
 // reads A once for all NS states (row i of every product in thread i, columns
 // in order, no cross-wave reduction).  Per state the arithmetic is that of
-// k_step<false, false> except the summation order inside the products.
+// k_step<false, false> except the summation order inside the products.  The
+// stepwise REBUILD step and the step beside the rebuild of the next one use
+// this form, so that the two give the same bits.
 // ---------------------------------------------------------------------------
 template <int NS, int UN>
 __device__ void matvec_rows(const double2 *__restrict__ A, int lda, const double2 *X, double2 *Y, int n) {
@@ -859,7 +861,60 @@ __device__ void matvec_rows(const double2 *__restrict__ A, int lda, const double
   __syncthreads();
 }
 
-template <int NS, int UN>
+// The products of the AFFINE step, where the exponential is the whole step:
+// P threads per row (blockDim = P x 64 ceil(n / 64), parts are whole waves),
+// part p summing the columns of its contiguous range in order with UN loads in
+// flight (the range's last, partial batch too: loads at clamped indices, the
+// products predicated), the parts added in the order p = 0, 1, ... through red.
+// Each thread's chain of dependent loads is P times shorter than in matvec_rows.
+template <int NS, int UN, int P>
+__device__ void matvec_split(const double2 *__restrict__ A, int lda, const double2 *X, double2 *Y, int n,
+                             double2 *red) {
+  const int nr = blockDim.x / P;
+  const int i = threadIdx.x % nr, p = threadIdx.x / nr;
+  const int chunk = ((n + P - 1) / P + UN - 1) / UN * UN;  // columns per part
+  const int kb = p * chunk, ke = min(n, kb + chunk);
+  double2 acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = make_double2(0.0, 0.0);
+  if (i < n) {
+    const double2 *a = A + i;
+    int k = kb;
+    for (; k + UN <= ke; k += UN) {
+      double2 av[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) av[u] = a[(long long)(k + u) * lda];
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = cfma(av[u], X[s * n + k + u], acc[s]);
+    }
+    if (k < ke) {
+      double2 av[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) av[u] = a[(long long)min(k + u, ke - 1) * lda];
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+        if (k + u < ke)
+#pragma unroll
+          for (int s = 0; s < NS; ++s) acc[s] = cfma(av[u], X[s * n + k + u], acc[s]);
+    }
+    if (p > 0)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) red[((p - 1) * NS + s) * n + i] = acc[s];
+  }
+  __syncthreads();
+  if (p == 0 && i < n)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double2 y = acc[s];
+      for (int q = 1; q < P; ++q) y = cadd(y, red[((q - 1) * NS + s) * n + i]);
+      Y[s * n + i] = y;
+    }
+  __syncthreads();
+}
+
+template <int NS, int UN, int P>
 __global__ __launch_bounds__(1024) void k_step_multi(const StepCtx c) {
   extern __shared__ double2 sm[];
   const int k = blockIdx.y;
@@ -870,8 +925,12 @@ __global__ __launch_bounds__(1024) void k_step_multi(const StepCtx c) {
   const int bd = blockDim.x;
   double2 *v = sm, *t0 = sm + NS * n, *t1 = sm + 2 * NS * n, *acc = sm + 3 * NS * n, *tmp = sm + 4 * NS * n;
   double2 *w = sm + 5 * NS * n;
-  double *sred = reinterpret_cast<double *>(sm + 6 * NS * n);
-  const auto mv = [&](const double2 *A, const double2 *x, double2 *y) { matvec_rows<NS, UN>(A, n, x, y, n); };
+  double2 *red = sm + 6 * NS * n;  // partial sums of parts 1 .. P-1
+  double *sred = reinterpret_cast<double *>(sm + (5 + P) * NS * n);
+  const auto mv = [&](const double2 *A, const double2 *x, double2 *y) {
+    if constexpr (P == 1) matvec_rows<NS, UN>(A, n, x, y, n);
+    else matvec_split<NS, UN, P>(A, n, x, y, n, red);
+  };
   const int step = *c.step;
   const double am = c.a_mid[step], a1 = c.a_t[step + 1];
   const double cl = c.c_light;
@@ -1317,7 +1376,9 @@ hipError_t launch_jacobi(double2 *A, double2 *V, double *w, int n, hipStream_t s
   return hipGetLastError();
 }
 
-size_t step_multi_lds_bytes(int n, int ns) { return ((size_t)6 * ns * n) * sizeof(double2) + 3 * 16 * sizeof(double) + 64; }
+size_t step_multi_lds_bytes(int n, int ns, int parts) {
+  return ((size_t)(5 + parts) * ns * n) * sizeof(double2) + 3 * 16 * sizeof(double) + 64;
+}
 
 size_t step_lds_bytes(int n, bool h_in_lds, bool adjoint, bool p_in_lds) {
   const size_t vecs = adjoint ? 11 : 6;
@@ -1341,8 +1402,9 @@ int assemble_blocks(int n) { return (int)(((long long)n * n + 255) / 256); }
 void subspace_init_attrs() {
   if (g_step_attr) return;
   for (const void *k : {(const void *)k_step<true, true>, (const void *)k_step<true, false>,
-                        (const void *)k_step<false, false>, (const void *)k_step_multi<1, 16>,
-                        (const void *)k_step_multi<2, 8>,
+                        (const void *)k_step<false, false>, (const void *)k_step_multi<1, 16, 1>,
+                        (const void *)k_step_multi<1, 12, 2>, (const void *)k_step_multi<1, 12, 3>,
+                        (const void *)k_step_multi<2, 8, 1>,
                         (const void *)k_adjoint<true>,
                         (const void *)k_adjoint<false>})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -1495,11 +1557,13 @@ hipError_t launch_step_only(const StepCtx &c, hipStream_t s, bool beside) {
   // against 513 us and 1.349 ms for the column-split product)
   if (!c.h_in_lds && c.n_aux <= STEP_MULTI_MAXN) {
     const int nt = 64 * ((c.n_aux + 63) / 64);
-#define LTD_SM(NS, UN)                                                                          \
-  hipLaunchKernelGGL((k_step_multi<NS, UN>), dim3((c.n_states + NS - 1) / NS, c.n_k), dim3(nt), \
-                     step_multi_lds_bytes(c.n_aux, NS), s, c)
-    if (beside) LTD_SM(2, 8);
-    else LTD_SM(1, 16);
+#define LTD_SM(NS, UN, P)                                                                              \
+  hipLaunchKernelGGL((k_step_multi<NS, UN, P>), dim3((c.n_states + NS - 1) / NS, c.n_k), dim3(P * nt), \
+                     step_multi_lds_bytes(c.n_aux, NS, P), s, c)
+    if (beside) LTD_SM(2, 8, 1);
+    else if (c.rebuild || 2 * nt > 1024) LTD_SM(1, 16, 1);
+    else if (3 * nt > 1024) LTD_SM(1, 12, 2);
+    else LTD_SM(1, 12, 3);
 #undef LTD_SM
     return hipGetLastError();
   }
