@@ -2338,12 +2338,13 @@ __global__ __launch_bounds__(256) void k_syn_pass(const double *__restrict__ in,
 //    RB waves takes 16 rows, staged through LDS; the data rows are the A
 //    operand and M^T the B operand, D[p][j'] = sum_j F[p][j] M[j'][j], so the 16
 //    lanes of an output register write 16 consecutive j';
-//  otherwise (I a multiple of 16, a block of 16 consecutive i within one o): M
-//    is the A operand and the data the B operand, D[j'][p] = sum_j M[j'][j] F[j][p],
-//    read and written 16 consecutive i at a time.
+//  otherwise (a block of 16 consecutive positions p = o I + i, which may cross
+//    from one o to the next when I is not a multiple of 16): M is the A operand
+//    and the data the B operand, D[j'][p] = sum_j M[j'][j] F[j][p], each lane
+//    reading and writing at its own position.
 // Output element of accumulator register r: row 4 r + lane / 16, column lane % 16.
 template <int KS, bool ROWS, bool TH, class TO>
-__global__ __launch_bounds__(256) void k_syn_mfma(const double *__restrict__ in, const double *__restrict__ th,
+__global__ __launch_bounds__(512) void k_syn_mfma(const double *__restrict__ in, const double *__restrict__ th,
                                                   const int *step, long long stride, TO *__restrict__ out,
                                                   const double *__restrict__ sub, const double *__restrict__ mf,
                                                   int RB, int O, int N, int I, int Np, int perm_n1, int perm_z1,
@@ -2382,13 +2383,14 @@ __global__ __launch_bounds__(256) void k_syn_mfma(const double *__restrict__ in,
       fb[s] = mf[(s * RB + a) * 64 + lane];
     }
   } else {
-    const long long task = (long long)blockIdx.x * 4 + wave;
+    const long long task = (long long)blockIdx.x * (blockDim.x >> 6) + wave;
     const long long ntile = (P + 15) / 16;
     if (task >= ntile * RB) return;  // the whole wave (task is uniform across it)
     a = (int)(task % RB);
     p0 = (task / RB) * 16;
-    const long long o = p0 / I;
-    const long long i = p0 - o * I + lr;
+    const long long pl = p0 + lr < P ? p0 + lr : P - 1;  // this lane's position (clamped)
+    const long long o = pl / I;
+    const long long i = pl - o * I;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const long long src = (o * N + 4 * s + lk) * I + i;
@@ -2412,9 +2414,10 @@ __global__ __launch_bounds__(256) void k_syn_mfma(const double *__restrict__ in,
       if (p < P && jp < Np) out[p * Np + jp] = (TO)v;
     } else {
       const int jp = 16 * a + 4 * r + lk;
-      const long long o = p0 / I;
-      const long long i = p0 - o * I + lr;
-      if (jp >= Np) continue;
+      const long long p = p0 + lr;
+      const long long o = p / I;
+      const long long i = p - o * I;
+      if (jp >= Np || p >= P) continue;
       if (perm_n1 > 0) {
         const long long y = i / perm_n1, x = i - y * perm_n1;
         const long long oi = ((y * perm_z2 + jp / perm_z1) * perm_n1 + x) * perm_z1 + jp % perm_z1;
@@ -2668,21 +2671,23 @@ void fft_rb_frag(int n, int np, const double *tab, double *mf) {
 }
 
 namespace {
-// MFMA pass for N in {16, 64, 72, 96} (and I a multiple of 16 unless ROWS);
-// false when the shape has no instantiation
+// MFMA pass for N in {16, 64, 72, 96, 160} (ROWS: at most eight 16-row blocks of
+// j', one wave each); false when the shape has no instantiation
 template <bool ROWS, bool TH, class TO>
 bool syn_mfma(int N, dim3 grid, hipStream_t s, const double *in, const double *th, const int *step, long long stride,
               TO *out, const double *sub, const double *mf, int RB, int O, int I, int Np, int pn1, int z1, int z2) {
-  if (ROWS ? (I != 1 || RB > 4) : I % 16 != 0) return false;
+  if (ROWS && (I != 1 || RB > 8)) return false;
   if (ROWS) grid = dim3((unsigned)(((long long)O + 15) / 16));
+  const dim3 block(ROWS ? 64 * RB : 256);
 #define LTD_SM(KS) \
-  hipLaunchKernelGGL((k_syn_mfma<KS, ROWS, TH, TO>), grid, dim3(256), 0, s, in, th, step, stride, out, sub, mf, RB, O, \
-                     N, I, Np, pn1, z1, z2)
+  hipLaunchKernelGGL((k_syn_mfma<KS, ROWS, TH, TO>), grid, block, 0, s, in, th, step, stride, out, sub, mf, RB, O, N, \
+                     I, Np, pn1, z1, z2)
   switch (N) {
     case 16: LTD_SM(4); return true;
     case 64: LTD_SM(16); return true;
     case 72: LTD_SM(18); return true;
     case 96: LTD_SM(24); return true;
+    case 160: LTD_SM(40); return true;
     default: return false;
   }
 #undef LTD_SM
