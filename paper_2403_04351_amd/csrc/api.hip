@@ -118,8 +118,9 @@ struct ltd_system {
   // rebuild of step n + 1 (ev_p0: step start, ev_asm: H~(mid) assembled, ev_pj: step done)
   hipStream_t side2 = nullptr;
   hipEvent_t ev_p0 = nullptr, ev_asm = nullptr, ev_pj = nullptr;
-  // and Theta V of step n + 1 synthesised on `side3` once the x/z transforms of
-  // step n have read it (ev_xz), ready before those of step n + 1 (ev_syn)
+  // and Theta V of step n + 1 synthesised on `side3` into the buffer step n does
+  // not read, beside its x/z transforms (or, when both are the same buffer, once
+  // they have read it: ev_xz), done before its y transforms (ev_syn)
   hipStream_t side3 = nullptr;
   hipEvent_t ev_xz = nullptr, ev_syn = nullptr;
   size_t o_rtw1 = 0, o_rtw2 = 0, o_rtw3 = 0, o_M1 = 0, o_M2 = 0, o_M3 = 0, o_syn1 = 0, o_syn2 = 0;
@@ -131,6 +132,7 @@ struct ltd_system {
   char *ws = nullptr;
   size_t ws_need = 0, ws_bound = 0;
   size_t o_tw1, o_tw2, o_tw3, o_thv, o_thv_rb, o_thv_step, o_status, o_part, o_partials;
+  size_t o_thv_step2 = 0;  // second Theta V buffer of the pipelined rebuild (steps of odd index in a graph)
   size_t o_vpartials;  // split-K partials of the V~ projection (its own: reduced on another stream)
   size_t o_slab_in, o_slab_out, o_W, o_Y, o_heff, o_tvps, o_proj, o_tmp3, o_eigA, o_eigV, o_eigw, o_eigwork;
   size_t o_stepslab, o_subdev, o_theta_sc, o_k6, o_hstep, o_zero32;
@@ -1186,14 +1188,18 @@ ltd_status rebuild_v(ltd_system *sys, const ltd_step_args *a, hipStream_t s, Pro
 // side2 (the reduction of the previous product's partials into V~ once s has
 // passed ev_p0, the assembly of H~(mid), recorded as ev_asm, and the
 // exponential of exp_ctx); the y transforms wait for ev_asm, so the product
-// that rewrites the partials comes after the assembly.  Theta V of the step is
-// already in o_thv_step when the call hands in a potential (synthesised on
-// side3 beside the previous step's read-out and projection; wait_syn makes s
-// wait for it when that synthesis was issued in the same capture).  The
-// muffin-tin branch advances its own step index rk on the side stream before it
-// reads the blocks of the step, and once the x/z transforms have read Theta V
-// the synthesis of the next step's starts on side3 (its own step index rv).
-ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s, bool wait_syn,
+// that rewrites the partials comes after the assembly.  The muffin-tin branch
+// advances its own step index rk on the side stream before it reads the blocks
+// of the step.  When the call hands in a potential, Theta V alternates between
+// two buffers: step i of a capture of kc steps reads buffer i mod 2, which holds
+// it already, and the synthesis of the next step's (its own step index rv, on
+// side3) writes the other one, beside the x/z transforms, and joins s with the
+// muffin-tin rows and the assembly before the y transforms, so that the next
+// x/z launch waits on no other stream.  The last step of a capture writes
+// buffer 0, where the next capture (or the prologue of ltd_propagate) starts;
+// when that step reads buffer 0 itself (kc odd) the synthesis waits for its x/z
+// transforms and the capture's end joins it.
+ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s, int i_cap, int kc,
                           const StepCtx &exp_ctx) {
   const Grid g = rgrid_of(sys);
   const int n = sys->n_aux;
@@ -1211,10 +1217,11 @@ ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s
   LTD_HIP(hipEventRecord(sys->ev_join, sys->side));
   const void *thv = r32 ? static_cast<const void *>(sys->at<float>(sys->o_zero32))
                         : static_cast<const void *>(sys->at<double>(sys->o_thv_rb));
-  if (a->v_r_t) {
-    thv = sys->at<double>(sys->o_thv_step);
-    if (wait_syn) LTD_HIP(hipStreamWaitEvent(s, sys->ev_syn, 0));
-  }
+  double *const tbuf[2] = {sys->at<double>(sys->o_thv_step), sys->at<double>(sys->o_thv_step2)};
+  const bool last = i_cap == kc - 1;
+  double *const tnext = last ? tbuf[0] : tbuf[(i_cap + 1) & 1];
+  const bool early = a->v_r_t && tnext != tbuf[i_cap & 1];  // the next Theta V beside the x/z transforms
+  if (a->v_r_t) thv = tbuf[i_cap & 1];
   const long long slab = (long long)fft_rb_slab_values(g) * n;
   for (int k0 = 0; k0 < sys->n_k; k0 += FFT_MAXK) {
     const int nk = std::min(FFT_MAXK, sys->n_k - k0);
@@ -1237,13 +1244,18 @@ ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s
         LTD_HIP(launch_record_theta(exp_ctx, reinterpret_cast<double2 *>(a->theta_hist), a->hist_len, sys->side2));
       LTD_HIP(hipEventRecord(sys->ev_asm, sys->side2));
       LTD_HIP(launch_step_only(exp_ctx, sys->side2, true));
+      if (early) {  // after ev_fork: the x/z launch of step i - 1 has read tnext
+        LTD_HIP(hipStreamWaitEvent(sys->side3, sys->ev_fork, 0));
+        LTD_HIP(launch_lookahead(rv, sys->side3));
+        LTD_TRY(rebuild_potential(sys, a->v_r_t, a->v_stride ? rv : nullptr, a->v_stride, tnext, r32, sys->side3));
+        LTD_HIP(hipEventRecord(sys->ev_syn, sys->side3));
+      }
     }
-    if (a->v_r_t && k0 + FFT_MAXK >= sys->n_k) {  // Theta V read: the next step's synthesis
+    if (a->v_r_t && !early && k0 + FFT_MAXK >= sys->n_k) {  // Theta V read: the next step's synthesis
       LTD_HIP(hipEventRecord(sys->ev_xz, s));
       LTD_HIP(hipStreamWaitEvent(sys->side3, sys->ev_xz, 0));
       LTD_HIP(launch_lookahead(rv, sys->side3));
-      LTD_TRY(rebuild_potential(sys, a->v_r_t, a->v_stride ? rv : nullptr, a->v_stride,
-                                sys->at<double>(sys->o_thv_step), r32, sys->side3));
+      LTD_TRY(rebuild_potential(sys, a->v_r_t, a->v_stride ? rv : nullptr, a->v_stride, tnext, r32, sys->side3));
       LTD_HIP(hipEventRecord(sys->ev_syn, sys->side3));
     }
     for (int i = 0; i < nk; ++i) ka.slab_in[i] = ka.slab_out[i];
@@ -1253,6 +1265,7 @@ ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s
     // 14 us per step less in the replayed graph)
     LTD_HIP(hipStreamWaitEvent(s, sys->ev_join, 0));
     LTD_HIP(hipStreamWaitEvent(s, sys->ev_asm, 0));
+    if (early) LTD_HIP(hipStreamWaitEvent(s, sys->ev_syn, 0));
     LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 1, r32, 0));
   }
   return LTD_OK;
@@ -1315,14 +1328,15 @@ void drop_graphs(ltd_system *sys) {
 // gives the same V~).  `first`: the first step of a capture (Theta V of its
 // rebuild was made before the capture); `join`: the last step joins side2 and
 // side3 back into s.  map_back is a no-op without C.
-ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s, bool first, bool join) {
+ltd_status pipelined_step(ltd_system *sys, const ltd_step_args *a, hipStream_t s, int i_cap, int kc) {
+  const bool join = i_cap == kc - 1;
   const StepCtx c = step_ctx(sys, a);
   // side2's work (reduction, assembly, exponential) depends on s only up to
   // here (ev_p0); it is captured after the first x/z launch, which leaves the
   // graph's dependencies as they are but puts the x/z kernel first in its
   // launch order (measured: 2.7 us per step less)
   LTD_HIP(hipEventRecord(sys->ev_p0, s));
-  LTD_TRY(rebuild_v_pipe(sys, a, s, !first, c));
+  LTD_TRY(rebuild_v_pipe(sys, a, s, i_cap, kc, c));
   LTD_TRY(project_v(sys, s, 1));
   // the map-back GEMM shares the split-K partials with the rebuild's GEMMs: it
   // runs on s, after the step (a join every step when C is requested)
@@ -1393,7 +1407,7 @@ ltd_status capture_steps(ltd_system *sys, const ltd_step_args *a, int k, bool pi
   LTD_HIP(hipStreamBeginCapture(sys->cap_stream, hipStreamCaptureModeThreadLocal));
   ltd_status st = LTD_OK;
   for (int i = 0; i < k && st == LTD_OK; ++i)
-    st = pipe ? pipelined_step(sys, a, sys->cap_stream, i == 0, i == k - 1) : step_once(sys, a, sys->cap_stream);
+    st = pipe ? pipelined_step(sys, a, sys->cap_stream, i, k) : step_once(sys, a, sys->cap_stream);
   if (st == LTD_OK) st = check_joined(sys);
   hipGraph_t gr = nullptr;
   const hipError_t ec = hipStreamEndCapture(sys->cap_stream, &gr);
@@ -1662,6 +1676,7 @@ ltd_status ltd_create(const ltd_system_desc *d, int precision, size_t *ws_bytes,
   sys->o_thv = ar.take(sys->ngrid * sizeof(double));
   sys->o_thv_rb = ar.take(sys->ngrid * sizeof(double));
   sys->o_thv_step = ar.take(sys->ngrid * sizeof(double));
+  sys->o_thv_step2 = ar.take(sys->ngrid * sizeof(double));
   if (sys->ap_red) {
     const size_t rn = (size_t)sys->rgrid.n1 * sys->rgrid.n2 * sys->rgrid.n3;
     sys->o_th_ap = ar.take(rn * sizeof(double));
