@@ -1403,7 +1403,7 @@ void subspace_init_attrs() {
   if (g_step_attr) return;
   for (const void *k : {(const void *)k_step<true, true>, (const void *)k_step<true, false>,
                         (const void *)k_step<false, false>, (const void *)k_step_multi<1, 16, 1>,
-                        (const void *)k_step_multi<1, 12, 2>, (const void *)k_step_multi<1, 12, 3>,
+                        (const void *)k_step_multi<1, 12, 3>,
                         (const void *)k_step_multi<2, 8, 1>,
                         (const void *)k_adjoint<true>,
                         (const void *)k_adjoint<false>})
@@ -1561,9 +1561,8 @@ hipError_t launch_step_only(const StepCtx &c, hipStream_t s, bool beside) {
   hipLaunchKernelGGL((k_step_multi<NS, UN, P>), dim3((c.n_states + NS - 1) / NS, c.n_k), dim3(P * nt), \
                      step_multi_lds_bytes(c.n_aux, NS, P), s, c)
     if (beside) LTD_SM(2, 8, 1);
-    else if (c.rebuild || 2 * nt > 1024) LTD_SM(1, 16, 1);
-    else if (3 * nt > 1024) LTD_SM(1, 12, 2);
-    else LTD_SM(1, 12, 3);
+    else if (c.rebuild || 3 * nt > 1024) LTD_SM(1, 16, 1);
+    else LTD_SM(1, 12, 3);  // AFFINE: three parts of each row (n <= 320 at creation: 960 threads at most)
 #undef LTD_SM
     return hipGetLastError();
   }
