@@ -326,18 +326,17 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(const ZBatch batch, const ZPr
 }
 
 // Sums the split-K partials of every output tile in a fixed order, then
-// C = alpha * sum + beta * C.  A block covers RED_E output elements of one
-// tile; its 256 threads are RED_E elements x RED_G groups, group g summing
-// splits g, g + RED_G, g + 2 RED_G, ... in order (eight loads in flight per
-// thread), then the RED_G group sums are added in order.
-constexpr int RED_E = 8, RED_G = 32;
+// C = alpha * sum + beta * C.  One thread per output element: a block covers
+// RED_T consecutive elements of one tile (RED_T x 16 bytes read per split, one
+// run), each thread adding splits 0, 1, ..., ksplit - 1 in order with eight
+// loads in flight.
+constexpr int RED_T = 256;
 
 template <bool TABLE>
-__global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZProb *__restrict__ table,
-                                                    int nprob, const double2 *__restrict__ partials, int n_limit) {
-  __shared__ double2 part[RED_G][RED_E];
+__global__ __launch_bounds__(RED_T) void zgemm_reduce(const ZBatch batch, const ZProb *__restrict__ table,
+                                                      int nprob, const double2 *__restrict__ partials, int n_limit) {
   const ZProb *probs = TABLE ? table : batch.p;
-  const int per_tile = (BM * BN) / RED_E;  // blocks per tile
+  const int per_tile = (BM * BN) / RED_T;  // blocks per tile
   const int rt = blockIdx.x / per_tile;
   const int sub = blockIdx.x % per_tile;
   int pi = 0;
@@ -348,40 +347,28 @@ __global__ __launch_bounds__(256) void zgemm_reduce(const ZBatch batch, const ZP
   const int tm = tl % P.tiles_m;
   const int tn = (tl / P.tiles_m) % P.tiles_n;
   const int bi = tl / (P.tiles_m * P.tiles_n);
-  const int el = threadIdx.x % RED_E, grp = threadIdx.x / RED_E;
-  const int e = sub * RED_E + el;
+  const int e = sub * RED_T + threadIdx.x;
   const int mb = P.bm;
-  if (e >= mb * BN) return;  // the whole block: a tile of mb < BM rows
+  if (e >= mb * BN) return;  // past a tile of mb < BM rows
   const int il = e % mb, jl = e / mb;
   const int i = tm * mb + il, j = tn * BN + jl;
   const int nlim = (n_limit > 0 && n_limit < P.n) ? n_limit : P.n;
-  const bool live = (i < P.m && j < nlim);
-  double2 s = make_double2(0.0, 0.0);
-  if (live) {
-    const double2 *src = partials + (P.part_off + (long long)tl * P.ksplit) * (long long)(BM * BN) + e;
-    const int ks = P.ksplit;
-    for (int q0 = grp; q0 < ks; q0 += 8 * RED_G) {
-      double2 v[8];
+  if (i >= P.m || j >= nlim) return;
+  const double2 *src = partials + (P.part_off + (long long)tl * P.ksplit) * (long long)(BM * BN) + e;
+  const int ks = P.ksplit;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int q0 = 0; q0 < ks; q0 += 8) {
+    double2 v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int q = q0 + u * RED_G;
-        v[u] = src[(long long)(q < ks ? q : ks - 1) * BM * BN];
-      }
+    for (int u = 0; u < 8; ++u) v[u] = src[(long long)(q0 + u < ks ? q0 + u : ks - 1) * BM * BN];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (q0 + u * RED_G < ks) s = cadd(s, v[u]);
-    }
+    for (int u = 0; u < 8; ++u)
+      if (q0 + u < ks) acc = cadd(acc, v[u]);
   }
-  part[grp][el] = s;
-  __syncthreads();
-  if (grp == 0 && live) {
-    double2 acc = part[0][el];
-    for (int g2 = 1; g2 < RED_G; ++g2) acc = cadd(acc, part[g2][el]);
-    double2 *C = P.C + (long long)bi * P.sC + (long long)i + (long long)j * P.ldc;
-    double2 v = cmul(P.alpha, acc);
-    if (P.beta.x != 0.0 || P.beta.y != 0.0) v = cfma(P.beta, *C, v);
-    *C = v;
-  }
+  double2 *C = P.C + (long long)bi * P.sC + (long long)i + (long long)j * P.ldc;
+  double2 v = cmul(P.alpha, acc);
+  if (P.beta.x != 0.0 || P.beta.y != 0.0) v = cfma(P.beta, *C, v);
+  *C = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -622,7 +609,7 @@ hipError_t launch_impl(int opa, int opb, const ZBatch &b, const ZProb *table, co
     rtiles = host[i].rtile_begin + host[i].tiles_m * host[i].tiles_n * host[i].batch;
   }
   if (!split) return hipSuccess;
-  hipLaunchKernelGGL((zgemm_reduce<TABLE>), dim3(rtiles * ((BM * BN) / RED_E)), dim3(256), 0, s, b, table, nprob,
+  hipLaunchKernelGGL((zgemm_reduce<TABLE>), dim3(rtiles * ((BM * BN) / RED_T)), dim3(RED_T), 0, s, b, table, nprob,
                      partials, n_limit);
   return hipGetLastError();
 }
