@@ -1210,11 +1210,10 @@ ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s
     LTD_TRY(build_step_tables(sys));
   }
   const bool r32 = resid32(sys);
+  // the side streams' work of the step depends on s only up to here; it is
+  // captured after the first x/z launch, so that the x/z kernel is the first
+  // node its predecessor releases
   LTD_HIP(hipEventRecord(sys->ev_fork, s));
-  LTD_HIP(hipStreamWaitEvent(sys->side, sys->ev_fork, 0));
-  LTD_HIP(launch_lookahead(rk, sys->side));
-  LTD_TRY(step_blocks(sys, a, rk, 0, n, sys->side));
-  LTD_HIP(hipEventRecord(sys->ev_join, sys->side));
   const void *thv = r32 ? static_cast<const void *>(sys->at<float>(sys->o_zero32))
                         : static_cast<const void *>(sys->at<double>(sys->o_thv_rb));
   double *const tbuf[2] = {sys->at<double>(sys->o_thv_step), sys->at<double>(sys->o_thv_step2)};
@@ -1236,7 +1235,11 @@ ltd_status rebuild_v_pipe(ltd_system *sys, const ltd_step_args *a, hipStream_t s
       ka.out[i].ld0 = kh.k_ext;
     }
     LTD_HIP(fft_rb_step(g, ka, nk, n, thv, s, 0, r32, sys->rb_variant));
-    if (k0 == 0) {  // the exponential of the current step on side2 (see pipelined_step)
+    if (k0 == 0) {  // the muffin-tin rows on side, the exponential of the current step on side2
+      LTD_HIP(hipStreamWaitEvent(sys->side, sys->ev_fork, 0));
+      LTD_HIP(launch_lookahead(rk, sys->side));
+      LTD_TRY(step_blocks(sys, a, rk, 0, n, sys->side));
+      LTD_HIP(hipEventRecord(sys->ev_join, sys->side));
       LTD_HIP(hipStreamWaitEvent(sys->side2, sys->ev_p0, 0));
       LTD_TRY(project_v(sys, sys->side2, 2));
       LTD_HIP(launch_assemble(exp_ctx, sys->side2));
